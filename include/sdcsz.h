@@ -1,0 +1,184 @@
+/*
+ * sdcsz.h -- C ABI of the MI355X (gfx950) SDC-resilient error-bounded lossy
+ * compressor: independent-block compression and decompression of FP32/FP64
+ * fields with ABFT protection, after "SDC Resilient Error-bounded Lossy
+ * Compressor" (arXiv 2010.03144).
+ *
+ * Conventions shared by every entry point
+ *  - Pointers named d_* are device pointers (HIP device memory of the current
+ *    device); h_* and plain structs are host memory.  `stream` is a
+ *    hipStream_t passed as void* (NULL = the legacy default stream).
+ *  - The caller owns every buffer.  The library allocates no device memory
+ *    and frees nothing: each call takes a caller-provided device workspace of
+ *    at least the size the matching *_workspace_size() reports.
+ *  - All device work is queued on `stream`.  Calls that return host results
+ *    (sizes, reports) synchronise that stream before returning.
+ *  - Errors are negative return codes (SDCSZ_E*); nothing throws or aborts
+ *    across the ABI.  sdcsz_strerror() names them.
+ */
+#ifndef SDCSZ_H
+#define SDCSZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SDCSZ_OK 0
+#define SDCSZ_EINVAL (-1)  /* bad dims/block/eb/fault plan/size argument          */
+#define SDCSZ_ENOSPC (-2)  /* output or workspace too small (required size set)    */
+#define SDCSZ_EFORMAT (-3) /* not a stream of this format, or inconsistent sections */
+#define SDCSZ_ESDC (-4)    /* uncorrectable silent data corruption (Algorithm 2,
+                              "SDC in compression"), or a code with no codeword   */
+#define SDCSZ_EHIP (-5)    /* HIP runtime error                                     */
+
+enum { SDCSZ_F32 = 0, SDCSZ_F64 = 1 };
+/* error-bound mode: absolute, or relative to the value range of the finite
+ * values (Sec. 6.1, "value-range based error bound") */
+enum { SDCSZ_ABS = 0, SDCSZ_REL = 1 };
+/* predictor choice per block: sampled selection (Algorithm 1, second loop), or
+ * forced */
+enum { SDCSZ_PRED_AUTO = 0, SDCSZ_PRED_LORENZO = 1, SDCSZ_PRED_REGRESSION = 2 };
+
+/* Fault-injection targets (evaluation mode A, Sec. 6.1; decompression errors,
+ * Sec. 5.3).  A plan is plain data applied at fixed program points. */
+enum {
+  SDCSZ_T_INPUT = 0,     /* input word, after the block's input checksums     */
+  SDCSZ_T_COEF = 1,      /* regression-coefficient word, after its checksums  */
+  SDCSZ_T_CODE = 2,      /* quantization code at rest, before encoding        */
+  SDCSZ_T_RECON = 3,     /* decompressed word, before its checksum            */
+  SDCSZ_T_DUP_PRED = 4,  /* first copy of the duplicated prediction           */
+  SDCSZ_T_DUP_RECON = 5, /* first copy of the duplicated reconstruction       */
+  SDCSZ_N_TARGETS = 6
+};
+
+typedef struct {
+  uint32_t target; /* SDCSZ_T_*                                                 */
+  uint32_t bit;    /* bit to flip: < 32 for word targets (CODE: taken mod 16),
+                      < 32 * words-per-value for DUP_* targets                  */
+  uint64_t block;  /* linear block id (C order over the block grid)             */
+  uint64_t word;   /* INPUT/RECON: 32-bit word in the block (FP64: 2 per value,
+                      low half first); COEF: word of the 4 coefficients;
+                      CODE/DUP_*: point index (C order inside the block)        */
+} sdcsz_fault;
+
+typedef struct {
+  uint32_t dtype;     /* SDCSZ_F32 / SDCSZ_F64                                  */
+  uint32_t ndim;      /* 1..3                                                   */
+  uint64_t dims[3];   /* first ndim entries, C order (dims[0] slowest)          */
+  uint32_t block[3];  /* block edge per used axis (Sec. 5.1; 6x6x6 in SZ)       */
+  uint32_t eb_mode;   /* SDCSZ_ABS / SDCSZ_REL                                  */
+  uint32_t predictor; /* SDCSZ_PRED_*                                           */
+  double eb;          /* error bound: finite and > 0                            */
+  uint32_t abft;      /* 1: checksums + instruction duplication (ftrsz); 0: not */
+  uint32_t n_faults;  /* entries in `faults` (compression uses INPUT, COEF, CODE,
+                         DUP_PRED, DUP_RECON; other targets are ignored)        */
+  const sdcsz_fault *faults; /* host array, NULL when n_faults == 0             */
+} sdcsz_params;
+
+typedef struct {
+  uint64_t n_blocks;
+  uint64_t injected[SDCSZ_N_TARGETS];
+  uint64_t detected[SDCSZ_N_TARGETS];
+  uint64_t corrected[SDCSZ_N_TARGETS];
+  uint64_t uncorrectable[SDCSZ_N_TARGETS];
+  uint64_t n_outliers;    /* values stored verbatim                          */
+  uint64_t n_regression;  /* blocks predicted by regression                  */
+  uint64_t payload_words; /* 32-bit words of Huffman payload                 */
+  uint64_t stream_size;   /* bytes of the compressed stream                  */
+  double eb_abs;          /* absolute bound actually enforced                */
+} sdcsz_report;
+
+/* Upper bound of the stream size for these parameters (0 if invalid). */
+uint64_t sdcsz_max_compressed_size(const sdcsz_params *p);
+
+/* Device workspace that sdcsz_compress needs for these parameters (0 if
+ * invalid).  Dominated by the per-point code and outlier staging areas. */
+uint64_t sdcsz_compress_workspace_size(const sdcsz_params *p);
+
+/*
+ * Compress a field: Algorithm 1 (fault tolerant compression) without its final
+ * lossless stage.  Per independent block (Sec. 5.1): regression coefficients
+ * and input/coefficient checksums (Sec. 3.2, integer words per Sec. 5.4);
+ * sampled predictor selection; detection and correction of the input and the
+ * coefficients; duplicated prediction and reconstruction; linear-scaling
+ * quantization with outliers kept verbatim and the double check of the bound;
+ * code checksums and the decompressed-data checksum sum_dc.  Then one
+ * Huffman code over all codes, detection/correction of the codes and
+ * per-block encoding.
+ *   d_in      device, dims[0]*dims[1]*dims[2] values of dtype, C order; read only
+ *   d_out     device, out_cap bytes; receives the stream
+ *   h_out_size host; receives the stream size (also on SDCSZ_ENOSPC: the
+ *             required size)
+ *   h_rep     host, may be NULL; fault counters and stream statistics
+ *   d_ws      device workspace of ws_size >= sdcsz_compress_workspace_size(p)
+ * Returns SDCSZ_OK, SDCSZ_EINVAL, SDCSZ_ENOSPC, SDCSZ_ESDC (an uncorrectable
+ * corruption, or a code without codeword when ABFT is off), SDCSZ_EHIP.
+ * Synchronises `stream`.
+ */
+int sdcsz_compress(const void *d_in, const sdcsz_params *p, void *d_out, uint64_t out_cap,
+                   uint64_t *h_out_size, sdcsz_report *h_rep, void *d_ws, uint64_t ws_size,
+                   void *stream);
+
+/*
+ * Read the parameters recorded in a stream's header (the stream may stay in
+ * device memory).  Fills *h_p (faults = NULL), *h_n_blocks and *h_eb_abs
+ * (either may be NULL).  Returns SDCSZ_OK or SDCSZ_EFORMAT.  Synchronises.
+ */
+int sdcsz_stream_info(const void *d_stream, uint64_t stream_size, sdcsz_params *h_p,
+                      uint64_t *h_n_blocks, double *h_eb_abs, void *stream);
+
+/* Device workspace that sdcsz_decompress / sdcsz_verify / region decoding
+ * need for a stream with these parameters (0 if invalid). */
+uint64_t sdcsz_decompress_workspace_size(const sdcsz_params *p);
+
+/*
+ * Decompress a stream: Algorithm 2.  Every block is decoded and
+ * reconstructed with the arithmetic of compression; with ABFT its checksum is
+ * compared with sum_dc and a mismatch re-executes the block from the
+ * compressed bytes (random-access decompression); a second mismatch marks the
+ * block uncorrectable, the other blocks still finish, and SDCSZ_ESDC is
+ * returned.  RECON entries of the fault plan strike the decompressed words
+ * before the checksum.
+ *   d_stream  device, stream_size bytes
+ *   d_out     device, out_cap >= n_values * sizeof(dtype) bytes, C order
+ *   h_faults  host, n_faults entries (only SDCSZ_T_RECON is used), may be NULL
+ * Returns SDCSZ_OK, SDCSZ_EINVAL, SDCSZ_ENOSPC, SDCSZ_EFORMAT, SDCSZ_ESDC,
+ * SDCSZ_EHIP.  Synchronises `stream`.
+ */
+int sdcsz_decompress(const void *d_stream, uint64_t stream_size, void *d_out, uint64_t out_cap,
+                     const sdcsz_fault *h_faults, uint32_t n_faults, sdcsz_report *h_rep,
+                     void *d_ws, uint64_t ws_size, void *stream);
+
+/*
+ * Stand-alone check of a decompressed buffer held by the caller (the checksum
+ * half of Algorithm 2): each block's checksum is compared with sum_dc; a
+ * mismatching block is decoded again from the stream and written over the
+ * caller's copy.  The stream must carry ABFT checksums (else SDCSZ_EINVAL).
+ *   d_data    device, data_size bytes, repaired in place
+ * RECON entries of the plan strike d_data's words before the check.
+ */
+int sdcsz_verify(const void *d_stream, uint64_t stream_size, void *d_data, uint64_t data_size,
+                 const sdcsz_fault *h_faults, uint32_t n_faults, sdcsz_report *h_rep, void *d_ws,
+                 uint64_t ws_size, void *stream);
+
+/*
+ * Random-access decompression of the box [lo, hi) (Sec. 5.1): only the blocks
+ * that intersect the box are decoded (checked and re-executed as in
+ * sdcsz_decompress); the box is written to d_out in C order.
+ *   h_lo, h_hi host arrays of ndim entries, lo < hi <= dims
+ *   d_out      device, out_cap >= prod(hi - lo) * sizeof(dtype)
+ */
+int sdcsz_decompress_region(const void *d_stream, uint64_t stream_size, const uint64_t *h_lo,
+                            const uint64_t *h_hi, void *d_out, uint64_t out_cap,
+                            sdcsz_report *h_rep, void *d_ws, uint64_t ws_size, void *stream);
+
+/* Human-readable name of a return code. */
+const char *sdcsz_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

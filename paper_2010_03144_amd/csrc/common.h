@@ -1,0 +1,118 @@
+// common.h -- definitions shared by the library's kernels and its host code.
+//
+// Stream format, block geometry and the per-call device work areas of the
+// SDC-resilient independent-block compressor (arXiv 2010.03144).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sdcsz.h"
+
+namespace sdcsz {
+
+constexpr uint32_t kRadius = 32768;  // code of a zero residual; 0 marks an outlier
+constexpr uint32_t kMaxLen = 24;     // longest Huffman codeword
+constexpr uint64_t kHeader = 192;    // fixed stream header bytes
+constexpr uint32_t kMaxBlockPts = 8192;
+constexpr uint32_t kMaxPatches = 8;  // fault-plan entries per block and call
+
+// Counter slots (u64) in the device report area.
+enum {
+  C_INJ = 0,
+  C_DET = 6,
+  C_COR = 12,
+  C_UNC = 18,
+  C_MISSING = 24,  // a code without codeword was met while encoding
+  C_N = 32
+};
+
+// Block grid of a field normalised to three axes (leading axes of extent 1).
+struct Geo {
+  uint64_t d[3];
+  uint32_t b[3];
+  uint32_t nb[3];
+  uint32_t rem[3];  // extent of the last block along each axis
+  uint32_t ndim;    // dimensionality of the block as configured (1..3)
+  uint32_t bpts;    // points of a full block
+  uint64_t n_blocks;
+  uint64_t n_values;
+};
+
+// Error-bound constants, written on the device by the constants kernel.
+struct EbDev {
+  double eb_abs;
+  double q, inv, inv_e;    // 2eb, 1/(2eb), 1/eb
+  float qf, invf, inv_ef;  // the same rounded to FP32
+  uint32_t pad;
+};
+
+// Regression constants per partial-block pattern (bit a set: axis a partial).
+template <typename T> struct RegTab {
+  T K[8][3];     // 12 / (n (n_a^2 - 1)), 0 when n_a == 1
+  T inv_pts[8];  // 1 / n
+  T c[8][3];     // (n_a - 1) / 2
+};
+
+// Fault plan on the device: entries sorted by block, one bit per block.
+struct PlanDev {
+  const sdcsz_fault *f;
+  uint32_t n;
+  const uint32_t *bits;
+};
+
+// Per-call device areas of compression (inside the caller's workspace).
+struct CompWork {
+  uint16_t *codes;     // bpts per block, C order inside the block
+  void *vals;          // bpts values per block: outliers, packed in order
+  void *recon;         // bpts values per block (generic kernels only)
+  uint32_t *meta;      // per block: n_outliers << 1 | is_regression
+  uint32_t *words;     // per block: payload words
+  void *coef;          // 4 values per block
+  uint64_t *sum_dc;    // per block
+  uint64_t *sum_q;     // per block
+  uint64_t *isum_q;    // per block
+  uint32_t *hist;      // 65536
+  uint32_t *enc;       // 65536: codeword << 8 | length
+  unsigned long long *cnt;  // C_N counters
+  uint64_t *off_pay;   // n_blocks + 1
+  uint32_t *off_out;   // n_blocks + 1
+  uint32_t *off_coef;  // n_blocks + 1
+  uint64_t *scan_part; // 3 per scan chunk
+  void *range_part;    // 2 doubles + flag per range work-group
+  EbDev *eb;
+};
+
+// Decoder tables built from the stream's codebook (canonical code).
+struct DecTab {
+  uint32_t first[kMaxLen + 2];
+  uint32_t count[kMaxLen + 2];
+  uint32_t start[kMaxLen + 2];
+  uint32_t min_len, max_len;
+};
+
+struct DecWork {
+  uint16_t *symbols;   // 65536: symbols ordered by (length, symbol)
+  DecTab *tab;
+  void *recon;         // bpts values per block (generic kernels only)
+  uint64_t *off_pay;   // n_blocks + 1
+  uint32_t *off_out;
+  uint32_t *off_coef;
+  uint64_t *scan_part;
+  unsigned long long *cnt;
+};
+
+// Stream header fields (byte offsets inside the 192-byte header).
+struct Header {
+  uint32_t dtype, ndim;
+  uint64_t d[3];
+  uint32_t b[3];
+  uint32_t eb_mode;
+  double eb, eb_abs;
+  uint32_t abft, n_sym;
+  uint64_t n_blocks, n_outliers, n_regression, payload_words;
+  uint64_t off_codebook, off_table, off_coef, off_sumdc, off_outliers, off_payload, total;
+  uint32_t predictor;
+};
+
+}  // namespace sdcsz

@@ -1,0 +1,810 @@
+// host.cpp -- C ABI, parameter validation, workspace layout, Huffman codebook
+// construction, stream header handling and kernel orchestration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "kern.h"
+
+using namespace sdcsz;
+
+namespace {
+
+#define HIPCHK(x)                          \
+  do {                                     \
+    if ((x) != hipSuccess) return SDCSZ_EHIP; \
+  } while (0)
+
+uint64_t a256(uint64_t v) { return (v + 255) & ~255ull; }
+uint64_t a8(uint64_t v) { return (v + 7) & ~7ull; }
+uint32_t vbytes(uint32_t dtype) { return dtype == SDCSZ_F32 ? 4u : 8u; }
+
+// ---------------------------------------------------------------------------
+// geometry and validation
+// ---------------------------------------------------------------------------
+bool geometry(uint32_t ndim, const uint64_t *dims, const uint32_t *block, Geo *g) {
+  if (ndim < 1 || ndim > 3) return false;
+  std::memset(g, 0, sizeof(*g));
+  for (int a = 0; a < 3; a++) {
+    g->d[a] = 1;
+    g->b[a] = 1;
+  }
+  const uint32_t off = 3 - ndim;
+  for (uint32_t a = 0; a < ndim; a++) {
+    if (block[a] < 1 || block[a] > 4096) return false;
+    g->d[off + a] = dims[a];
+    g->b[off + a] = block[a];
+  }
+  uint64_t bp = (uint64_t)g->b[0] * g->b[1] * g->b[2];
+  if (bp > kMaxBlockPts) return false;
+  g->bpts = (uint32_t)bp;
+  g->ndim = ndim;
+  g->n_values = g->d[0] * g->d[1] * g->d[2];
+  if (g->n_values >= (1ull << 32)) return false;
+  uint64_t nb = 1;
+  for (int a = 0; a < 3; a++) {
+    uint64_t n = (g->d[a] + g->b[a] - 1) / g->b[a];
+    g->nb[a] = (uint32_t)n;
+    g->rem[a] = n ? (uint32_t)(g->d[a] - (n - 1) * g->b[a]) : 0;
+    nb *= n;
+  }
+  g->n_blocks = nb;
+  return true;
+}
+
+uint64_t block_pts(const Geo &g, uint64_t blk) {
+  uint64_t t = blk;
+  uint64_t c2 = t % g.nb[2];
+  t /= g.nb[2];
+  uint64_t c1 = t % g.nb[1], c0 = t / g.nb[1];
+  uint64_t c[3] = {c0, c1, c2}, pts = 1;
+  for (int a = 0; a < 3; a++) pts *= (c[a] + 1 == g.nb[a]) ? g.rem[a] : g.b[a];
+  return pts;
+}
+
+// fault entries of the targets a call uses; EINVAL on out-of-range entries
+int check_plan(const Geo &g, uint32_t dtype, const sdcsz_fault *f, uint32_t n, bool decomp,
+               std::vector<sdcsz_fault> &out) {
+  out.clear();
+  if (n && !f) return SDCSZ_EINVAL;
+  const uint32_t per = dtype == SDCSZ_F32 ? 1 : 2;
+  for (uint32_t t = 0; t < n; t++) {
+    const sdcsz_fault &e = f[t];
+    if (e.target >= SDCSZ_N_TARGETS || e.block >= g.n_blocks) return SDCSZ_EINVAL;
+    const uint64_t pts = block_pts(g, e.block);
+    switch (e.target) {
+      case SDCSZ_T_INPUT:
+      case SDCSZ_T_RECON:
+        if (e.word >= pts * per || e.bit >= 32) return SDCSZ_EINVAL;
+        break;
+      case SDCSZ_T_COEF:
+        if (e.word >= 4ull * per || e.bit >= 32) return SDCSZ_EINVAL;
+        break;
+      case SDCSZ_T_CODE:
+        if (e.word >= pts || e.bit >= 32) return SDCSZ_EINVAL;
+        break;
+      default:
+        if (e.word >= pts || e.bit >= 32 * per) return SDCSZ_EINVAL;
+        break;
+    }
+    if ((e.target == SDCSZ_T_RECON) == decomp) out.push_back(e);
+  }
+  std::stable_sort(out.begin(), out.end(),
+                   [](const sdcsz_fault &a, const sdcsz_fault &b) { return a.block < b.block; });
+  // the kernels keep at most kMaxPatches plan entries per block
+  for (size_t i = 0, run = 0; i < out.size(); i++) {
+    run = (i > 0 && out[i].block == out[i - 1].block) ? run + 1 : 1;
+    if (run > kMaxPatches) return SDCSZ_EINVAL;
+  }
+  return SDCSZ_OK;
+}
+
+int check_params(const sdcsz_params *p, Geo *g) {
+  if (!p || p->dtype > 1 || p->eb_mode > 1 || p->predictor > 2 || p->abft > 1) return SDCSZ_EINVAL;
+  if (!(p->eb > 0) || !std::isfinite(p->eb)) return SDCSZ_EINVAL;
+  if (!geometry(p->ndim, p->dims, p->block, g)) return SDCSZ_EINVAL;
+  return SDCSZ_OK;
+}
+
+template <typename T> RegTab<T> reg_table(const Geo &g) {
+  RegTab<T> rt;
+  for (uint32_t pat = 0; pat < 8; pat++) {
+    uint64_t n[3], pts = 1;
+    for (int a = 0; a < 3; a++) {
+      n[a] = (pat >> a) & 1 ? g.rem[a] : g.b[a];
+      pts *= n[a];
+    }
+    for (int a = 0; a < 3; a++) {
+      rt.c[pat][a] = (T)(0.5 * (double)(n[a] - 1));
+      rt.K[pat][a] = n[a] > 1 ? (T)(12.0 / ((double)pts * ((double)n[a] * (double)n[a] - 1.0))) : (T)0;
+    }
+    rt.inv_pts[pat] = pts ? (T)(1.0 / (double)pts) : (T)0;
+  }
+  return rt;
+}
+
+// ---------------------------------------------------------------------------
+// workspace layouts
+// ---------------------------------------------------------------------------
+struct CompLayout {
+  uint64_t cnt, eb, range, hist, enc, codes, vals, recon, meta, words, coef, sum_dc, sum_q, isum_q;
+  uint64_t off_pay, off_out, off_coef, scan, plan, bits, total;
+};
+
+CompLayout comp_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
+  CompLayout L;
+  const uint64_t nb = g.n_blocks, vb = vbytes(dtype), slots = nb * g.bpts;
+  const uint64_t chunks = (nb + kScanChunk - 1) / kScanChunk + 1;
+  uint64_t at = 0;
+  auto take = [&](uint64_t bytes) {
+    uint64_t o = at;
+    at = a256(at + bytes);
+    return o;
+  };
+  L.cnt = take(8 * C_N);
+  L.eb = take(sizeof(EbDev));
+  L.range = take(16ull * kRangeBlocks);
+  L.hist = take(4 * 65536);
+  L.enc = take(4 * 65536);
+  L.codes = take(2 * slots);
+  L.vals = take(vb * slots);
+  L.recon = take(vb * slots);
+  L.meta = take(4 * nb);
+  L.words = take(4 * nb);
+  L.coef = take(4 * vb * nb);
+  L.sum_dc = take(8 * nb);
+  L.sum_q = take(8 * nb);
+  L.isum_q = take(8 * nb);
+  L.off_pay = take(8 * (nb + 1));
+  L.off_out = take(4 * (nb + 1));
+  L.off_coef = take(4 * (nb + 1));
+  L.scan = take(24 * chunks);
+  L.plan = take(sizeof(sdcsz_fault) * (uint64_t)std::max<uint32_t>(nfaults, 1));
+  L.bits = take(4 * (nb / 32 + 1));
+  L.total = at;
+  return L;
+}
+
+struct DecLayout {
+  uint64_t cnt, symbols, tab, recon, off_pay, off_out, off_coef, scan, plan, bits, total;
+};
+
+DecLayout dec_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
+  DecLayout L;
+  const uint64_t nb = g.n_blocks, vb = vbytes(dtype), slots = nb * g.bpts;
+  const uint64_t chunks = (nb + kScanChunk - 1) / kScanChunk + 1;
+  uint64_t at = 0;
+  auto take = [&](uint64_t bytes) {
+    uint64_t o = at;
+    at = a256(at + bytes);
+    return o;
+  };
+  L.cnt = take(8 * C_N);
+  L.symbols = take(2 * 65536);
+  L.tab = take(sizeof(DecTab));
+  L.recon = take(vb * slots);
+  L.off_pay = take(8 * (nb + 1));
+  L.off_out = take(4 * (nb + 1));
+  L.off_coef = take(4 * (nb + 1));
+  L.scan = take(24 * chunks);
+  L.plan = take(sizeof(sdcsz_fault) * (uint64_t)std::max<uint32_t>(nfaults, 1));
+  L.bits = take(4 * (nb / 32 + 1));
+  L.total = at;
+  return L;
+}
+
+// ---------------------------------------------------------------------------
+// Huffman code: symbols with a non-zero count ordered by (count, symbol),
+// merged with two queues (ties go to the leaf queue); one symbol -> length 1;
+// deeper than 24 bits -> halve every count (minimum 1) and rebuild.
+// ---------------------------------------------------------------------------
+void tree_lengths(const std::vector<uint64_t> &cnt, std::vector<uint8_t> &len) {
+  len.assign(65536, 0);
+  std::vector<uint32_t> sym;
+  sym.reserve(1024);
+  for (uint32_t s = 0; s < 65536; s++)
+    if (cnt[s]) sym.push_back(s);
+  const size_t S = sym.size();
+  if (S == 0) return;
+  if (S == 1) {
+    len[sym[0]] = 1;
+    return;
+  }
+  std::sort(sym.begin(), sym.end(), [&](uint32_t a, uint32_t b) {
+    return cnt[a] != cnt[b] ? cnt[a] < cnt[b] : a < b;
+  });
+  // nodes 0..S-1 leaves (in sorted order), S.. internal in creation order
+  std::vector<uint64_t> wgt(2 * S - 1);
+  std::vector<uint32_t> up(2 * S - 1, 0);
+  for (size_t i = 0; i < S; i++) wgt[i] = cnt[sym[i]];
+  size_t li = 0, ii = S, top = S;
+  for (size_t m = 0; m + 1 < S; m++) {
+    size_t pick[2];
+    for (int r = 0; r < 2; r++) {
+      bool leaf = li < S && (ii >= top || wgt[li] <= wgt[ii]);
+      pick[r] = leaf ? li++ : ii++;
+    }
+    wgt[top] = wgt[pick[0]] + wgt[pick[1]];
+    up[pick[0]] = up[pick[1]] = (uint32_t)top;
+    top++;
+  }
+  // depth of node v = depth(parent) + 1; parents have larger indices
+  std::vector<uint32_t> dep(2 * S - 1, 0);
+  for (size_t v = 2 * S - 1; v-- > 0;)
+    if (v != 2 * S - 2) dep[v] = dep[up[v]] + 1;
+  for (size_t i = 0; i < S; i++) len[sym[i]] = (uint8_t)std::min<uint32_t>(dep[i], 255);
+}
+
+void code_lengths(const uint32_t *hist, std::vector<uint8_t> &len) {
+  std::vector<uint64_t> cnt(hist, hist + 65536);
+  for (;;) {
+    tree_lengths(cnt, len);
+    if (*std::max_element(len.begin(), len.end()) <= kMaxLen) return;
+    for (auto &c : cnt)
+      if (c) c = std::max<uint64_t>(1, c >> 1);
+  }
+}
+
+// Canonical codes by length counts (codes of one length are consecutive in
+// symbol order; the first code of length l is (first(l-1) + count(l-1)) << 1).
+struct Canon {
+  uint32_t bl_count[kMaxLen + 2] = {0};
+  uint32_t first[kMaxLen + 2] = {0};
+  uint32_t start[kMaxLen + 2] = {0};
+};
+
+Canon canonical(const std::vector<uint8_t> &len, std::vector<uint32_t> *codes, std::vector<uint16_t> *order) {
+  Canon C;
+  for (uint32_t s = 0; s < 65536; s++)
+    if (len[s]) C.bl_count[len[s]]++;
+  uint32_t code = 0, acc = 0;
+  for (uint32_t l = 1; l <= kMaxLen; l++) {
+    code = (code + C.bl_count[l - 1]) << 1;
+    C.first[l] = code;
+    C.start[l] = acc;
+    acc += C.bl_count[l];
+  }
+  C.first[1] = 0;
+  if (codes) {
+    codes->assign(65536, 0);
+    std::vector<uint32_t> next(C.first, C.first + kMaxLen + 2);
+    for (uint32_t s = 0; s < 65536; s++)
+      if (len[s]) (*codes)[s] = next[len[s]]++;
+  }
+  if (order) {
+    order->assign(65536, 0);
+    std::vector<uint32_t> pos(C.start, C.start + kMaxLen + 2);
+    for (uint32_t s = 0; s < 65536; s++)
+      if (len[s]) (*order)[pos[len[s]]++] = (uint16_t)s;
+  }
+  return C;
+}
+
+// ---------------------------------------------------------------------------
+// header
+// ---------------------------------------------------------------------------
+const uint8_t kMagic[8] = {'S', 'D', 'C', 'S', 'Z', 0, 'v', '1'};
+
+void section_offsets(Header &h) {
+  const uint64_t vb = vbytes(h.dtype);
+  h.off_codebook = kHeader;
+  h.off_table = a8(h.off_codebook + 4ull * h.n_sym);
+  h.off_coef = h.off_table + 8ull * h.n_blocks;
+  h.off_sumdc = a8(h.off_coef + 4ull * vb * h.n_regression);
+  h.off_outliers = h.off_sumdc + (h.abft ? 8ull * h.n_blocks : 0);
+  h.off_payload = a8(h.off_outliers + vb * h.n_outliers);
+  h.total = a8(h.off_payload + 4ull * h.payload_words);
+}
+
+template <typename V> void put(uint8_t *b, uint64_t off, V v) { std::memcpy(b + off, &v, sizeof(V)); }
+template <typename V> V get(const uint8_t *b, uint64_t off) {
+  V v;
+  std::memcpy(&v, b + off, sizeof(V));
+  return v;
+}
+
+void pack_header(const Header &h, uint8_t *o) {
+  std::memset(o, 0, kHeader);
+  std::memcpy(o, kMagic, 8);
+  put<uint32_t>(o, 8, h.dtype);
+  put<uint32_t>(o, 12, h.ndim);
+  for (int a = 0; a < 3; a++) put<uint64_t>(o, 16 + 8 * a, h.d[a]);
+  for (int a = 0; a < 3; a++) put<uint32_t>(o, 40 + 4 * a, h.b[a]);
+  put<uint32_t>(o, 52, h.eb_mode);
+  put<double>(o, 56, h.eb);
+  put<double>(o, 64, h.eb_abs);
+  put<uint32_t>(o, 72, h.abft);
+  put<uint32_t>(o, 76, h.n_sym);
+  put<uint64_t>(o, 80, h.n_blocks);
+  put<uint64_t>(o, 88, h.n_outliers);
+  put<uint64_t>(o, 96, h.n_regression);
+  put<uint64_t>(o, 104, h.payload_words);
+  put<uint64_t>(o, 112, h.off_codebook);
+  put<uint64_t>(o, 120, h.off_table);
+  put<uint64_t>(o, 128, h.off_coef);
+  put<uint64_t>(o, 136, h.off_sumdc);
+  put<uint64_t>(o, 144, h.off_outliers);
+  put<uint64_t>(o, 152, h.off_payload);
+  put<uint64_t>(o, 160, h.total);
+  put<uint32_t>(o, 168, h.predictor);
+}
+
+// parse + validate the header (and its geometry) from host bytes
+int unpack_header(const uint8_t *o, uint64_t avail, uint64_t stream_size, Header &h, Geo &g) {
+  if (avail < kHeader || stream_size < kHeader || std::memcmp(o, kMagic, 8) != 0) return SDCSZ_EFORMAT;
+  h.dtype = get<uint32_t>(o, 8);
+  h.ndim = get<uint32_t>(o, 12);
+  for (int a = 0; a < 3; a++) h.d[a] = get<uint64_t>(o, 16 + 8 * a);
+  for (int a = 0; a < 3; a++) h.b[a] = get<uint32_t>(o, 40 + 4 * a);
+  h.eb_mode = get<uint32_t>(o, 52);
+  h.eb = get<double>(o, 56);
+  h.eb_abs = get<double>(o, 64);
+  h.abft = get<uint32_t>(o, 72);
+  h.n_sym = get<uint32_t>(o, 76);
+  h.n_blocks = get<uint64_t>(o, 80);
+  h.n_outliers = get<uint64_t>(o, 88);
+  h.n_regression = get<uint64_t>(o, 96);
+  h.payload_words = get<uint64_t>(o, 104);
+  h.predictor = get<uint32_t>(o, 168);
+  if (h.dtype > 1 || h.abft > 1 || h.n_sym > 65536 || h.ndim < 1 || h.ndim > 3) return SDCSZ_EFORMAT;
+  Header chk = h;
+  section_offsets(chk);
+  if (chk.off_table != get<uint64_t>(o, 120) || chk.off_coef != get<uint64_t>(o, 128) ||
+      chk.off_sumdc != get<uint64_t>(o, 136) || chk.off_outliers != get<uint64_t>(o, 144) ||
+      chk.off_payload != get<uint64_t>(o, 152) || chk.total != get<uint64_t>(o, 160) ||
+      get<uint64_t>(o, 112) != kHeader)
+    return SDCSZ_EFORMAT;
+  h = chk;
+  if (h.total > stream_size) return SDCSZ_EFORMAT;
+  uint64_t dims[3];
+  uint32_t blk[3];
+  for (uint32_t a = 0; a < 3 - h.ndim; a++)
+    if (h.d[a] != 1 || h.b[a] != 1) return SDCSZ_EFORMAT;
+  for (uint32_t a = 0; a < h.ndim; a++) {
+    dims[a] = h.d[3 - h.ndim + a];
+    blk[a] = h.b[3 - h.ndim + a];
+  }
+  if (!geometry(h.ndim, dims, blk, &g) || g.n_blocks != h.n_blocks) return SDCSZ_EFORMAT;
+  if (h.n_outliers > g.n_values || h.n_regression > g.n_blocks) return SDCSZ_EFORMAT;
+  return SDCSZ_OK;
+}
+
+void fill_report(sdcsz_report *r, const unsigned long long *cnt, uint64_t nb) {
+  std::memset(r, 0, sizeof(*r));
+  r->n_blocks = nb;
+  for (int t = 0; t < SDCSZ_N_TARGETS; t++) {
+    r->injected[t] = cnt[C_INJ + t];
+    r->detected[t] = cnt[C_DET + t];
+    r->corrected[t] = cnt[C_COR + t];
+    r->uncorrectable[t] = cnt[C_UNC + t];
+  }
+}
+
+uint32_t grid_for(uint64_t n, uint32_t per) { return (uint32_t)std::max<uint64_t>(1, (n + per - 1) / per); }
+
+// upload a sorted plan and its per-block bitmap
+int upload_plan(const std::vector<sdcsz_fault> &pl, uint64_t nb, uint8_t *ws, uint64_t off_plan,
+                uint64_t off_bits, std::vector<uint32_t> &bits_host, hipStream_t st, PlanDev *pd) {
+  pd->n = (uint32_t)pl.size();
+  pd->f = (const sdcsz_fault *)(ws + off_plan);
+  pd->bits = (const uint32_t *)(ws + off_bits);
+  if (pl.empty()) return SDCSZ_OK;
+  bits_host.assign(nb / 32 + 1, 0);
+  for (auto &f : pl) bits_host[f.block >> 5] |= 1u << (f.block & 31);
+  HIPCHK(hipMemcpyAsync(ws + off_plan, pl.data(), pl.size() * sizeof(sdcsz_fault), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ws + off_bits, bits_host.data(), bits_host.size() * 4, hipMemcpyHostToDevice, st));
+  return SDCSZ_OK;
+}
+
+int launch_scan(ScanSrc src, uint64_t n, uint64_t *part, uint64_t *off_pay, uint32_t *off_out,
+                uint32_t *off_coef, hipStream_t st) {
+  if (n == 0) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, (unsigned long long *)off_pay, 1);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, off_out, 1);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, off_coef, 1);
+    return hipGetLastError() == hipSuccess ? SDCSZ_OK : SDCSZ_EHIP;
+  }
+  uint32_t chunks = (uint32_t)((n + kScanChunk - 1) / kScanChunk);
+  hipLaunchKernelGGL(k_scan1, dim3(chunks), dim3(kScanThreads), 0, st, src, n, part);
+  hipLaunchKernelGGL(k_scan2, dim3(1), dim3(kScanThreads), 0, st, part, chunks);
+  hipLaunchKernelGGL(k_scan3, dim3(chunks), dim3(kScanThreads), 0, st, src, n, part, off_pay, off_out, off_coef);
+  return hipGetLastError() == hipSuccess ? SDCSZ_OK : SDCSZ_EHIP;
+}
+
+// ---------------------------------------------------------------------------
+// compression
+// ---------------------------------------------------------------------------
+template <typename T>
+int compress_t(const void *d_in, const sdcsz_params *p, const Geo &g, uint8_t *d_out, uint64_t out_cap,
+               uint64_t *h_out_size, sdcsz_report *h_rep, uint8_t *ws, uint64_t ws_size, hipStream_t st) {
+  std::vector<sdcsz_fault> plan;
+  int rc = check_plan(g, p->dtype, p->faults, p->n_faults, false, plan);
+  if (rc) return rc;
+  const CompLayout L = comp_layout(g, p->dtype, p->n_faults);
+  if (!ws || ws_size < L.total) return SDCSZ_ENOSPC;
+  CompWork w;
+  w.codes = (uint16_t *)(ws + L.codes);
+  w.vals = ws + L.vals;
+  w.recon = ws + L.recon;
+  w.meta = (uint32_t *)(ws + L.meta);
+  w.words = (uint32_t *)(ws + L.words);
+  w.coef = ws + L.coef;
+  w.sum_dc = (uint64_t *)(ws + L.sum_dc);
+  w.sum_q = (uint64_t *)(ws + L.sum_q);
+  w.isum_q = (uint64_t *)(ws + L.isum_q);
+  w.hist = (uint32_t *)(ws + L.hist);
+  w.enc = (uint32_t *)(ws + L.enc);
+  w.cnt = (unsigned long long *)(ws + L.cnt);
+  w.off_pay = (uint64_t *)(ws + L.off_pay);
+  w.off_out = (uint32_t *)(ws + L.off_out);
+  w.off_coef = (uint32_t *)(ws + L.off_coef);
+  w.scan_part = (uint64_t *)(ws + L.scan);
+  w.range_part = ws + L.range;
+  w.eb = (EbDev *)(ws + L.eb);
+
+  std::vector<uint32_t> bits_host;
+  PlanDev pd;
+  rc = upload_plan(plan, g.n_blocks, ws, L.plan, L.bits, bits_host, st, &pd);
+  if (rc) return rc;
+
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, w.cnt, (uint64_t)C_N);
+  hipLaunchKernelGGL(k_zero_u32, dim3(256), dim3(256), 0, st, w.hist, (uint64_t)65536);
+  uint32_t nparts = 0;
+  if (p->eb_mode == SDCSZ_REL && g.n_values) {
+    nparts = (uint32_t)std::min<uint64_t>(kRangeBlocks, grid_for(g.n_values, kRangeThreads * 8));
+    hipLaunchKernelGGL(k_range<T>, dim3(nparts), dim3(kRangeThreads), 0, st, (const T *)d_in, g.n_values,
+                       (double *)w.range_part);
+  }
+  hipLaunchKernelGGL(k_consts, dim3(1), dim3(64), 0, st, (const double *)w.range_part, nparts, p->eb_mode,
+                     p->eb, w.eb);
+  HIPCHK(hipGetLastError());
+
+  if (g.n_blocks) {
+    const RegTab<T> rt = reg_table<T>(g);
+    hipLaunchKernelGGL(k_compress_generic<T>, dim3(grid_for(g.n_blocks, 64)), dim3(64), 0, st,
+                       (const T *)d_in, g, rt, pd, w, p->abft, p->predictor);
+    HIPCHK(hipGetLastError());
+    bool any_code = false;
+    for (auto &f : plan) any_code |= f.target == SDCSZ_T_CODE;
+    if (any_code) hipLaunchKernelGGL(k_code_faults, dim3(1), dim3(64), 0, st, pd, g, w.codes, w.cnt);
+  }
+
+  // Huffman code over the whole field's codes (host)
+  std::vector<uint32_t> hist(65536);
+  HIPCHK(hipMemcpyAsync(hist.data(), w.hist, 4 * 65536, hipMemcpyDeviceToHost, st));
+  EbDev ebh;
+  HIPCHK(hipMemcpyAsync(&ebh, w.eb, sizeof(EbDev), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<uint8_t> len;
+  code_lengths(hist.data(), len);
+  std::vector<uint32_t> codes;
+  canonical(len, &codes, nullptr);
+  std::vector<uint32_t> enc(65536);
+  uint32_t n_sym = 0;
+  for (uint32_t s = 0; s < 65536; s++) {
+    enc[s] = (codes[s] << 8) | len[s];
+    n_sym += len[s] ? 1 : 0;
+  }
+  HIPCHK(hipMemcpyAsync(w.enc, enc.data(), 4 * 65536, hipMemcpyHostToDevice, st));
+
+  if (g.n_blocks) {
+    hipLaunchKernelGGL(k_codes_check, dim3(grid_for(g.n_blocks, 256)), dim3(256), 0, st, g, w, p->abft);
+    ScanSrc src{w.words, w.meta, 1};
+    rc = launch_scan(src, g.n_blocks, w.scan_part, w.off_pay, w.off_out, w.off_coef, st);
+    if (rc) return rc;
+  }
+  uint64_t tot_pay = 0;
+  uint32_t tot_out = 0, tot_coef = 0;
+  unsigned long long cnt[C_N];
+  if (g.n_blocks) {
+    HIPCHK(hipMemcpyAsync(&tot_pay, w.off_pay + g.n_blocks, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&tot_out, w.off_out + g.n_blocks, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&tot_coef, w.off_coef + g.n_blocks, 4, hipMemcpyDeviceToHost, st));
+  }
+  HIPCHK(hipMemcpyAsync(cnt, w.cnt, sizeof(cnt), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+
+  sdcsz_report rep;
+  fill_report(&rep, cnt, g.n_blocks);
+  rep.eb_abs = ebh.eb_abs;
+  bool unc = cnt[C_UNC + SDCSZ_T_INPUT] || cnt[C_UNC + SDCSZ_T_COEF] || cnt[C_UNC + SDCSZ_T_CODE] ||
+             cnt[C_MISSING];
+  if (unc) {
+    *h_out_size = 0;
+    if (h_rep) *h_rep = rep;
+    return SDCSZ_ESDC;
+  }
+
+  Header h;
+  std::memset(&h, 0, sizeof(h));
+  h.dtype = p->dtype;
+  h.ndim = p->ndim;
+  for (int a = 0; a < 3; a++) {
+    h.d[a] = g.d[a];
+    h.b[a] = g.b[a];
+  }
+  h.eb_mode = p->eb_mode;
+  h.eb = p->eb;
+  h.eb_abs = ebh.eb_abs;
+  h.abft = p->abft;
+  h.n_sym = n_sym;
+  h.n_blocks = g.n_blocks;
+  h.n_outliers = tot_out;
+  h.n_regression = tot_coef;
+  h.payload_words = tot_pay;
+  h.predictor = p->predictor;
+  section_offsets(h);
+  rep.n_outliers = h.n_outliers;
+  rep.n_regression = h.n_regression;
+  rep.payload_words = h.payload_words;
+  rep.stream_size = h.total;
+  *h_out_size = h.total;
+  if (h_rep) *h_rep = rep;
+  if (h.total > out_cap || !d_out) return SDCSZ_ENOSPC;
+
+  // header + codebook (with its padding) from the host; zero the tail pads
+  std::vector<uint8_t> head(h.off_table, 0);
+  pack_header(h, head.data());
+  for (uint32_t s = 0, t = 0; s < 65536; s++)
+    if (len[s]) put<uint32_t>(head.data(), kHeader + 4ull * t++, (s << 8) | len[s]);
+  HIPCHK(hipMemcpyAsync(d_out, head.data(), head.size(), hipMemcpyHostToDevice, st));
+  if (h.off_payload > h.off_outliers)
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t *)(d_out + h.off_payload - 8), 2);
+  if (h.total > h.off_payload)
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t *)(d_out + h.total - 8), 2);
+  if (g.n_blocks) hipLaunchKernelGGL(k_encode<T>, dim3(grid_for(g.n_blocks, 256)), dim3(256), 0, st, g, w, d_out, h);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  return SDCSZ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// decompression / verification / region
+// ---------------------------------------------------------------------------
+struct Opened {
+  Header h;
+  Geo g;
+  std::vector<uint8_t> head;  // header + codebook bytes (host copy)
+};
+
+int open_stream(const void *d_stream, uint64_t size, hipStream_t st, Opened &o) {
+  if (!d_stream) return SDCSZ_EINVAL;
+  uint64_t avail = std::min<uint64_t>(size, kHeader + 4ull * 65536);
+  o.head.assign(avail, 0);
+  HIPCHK(hipMemcpyAsync(o.head.data(), d_stream, avail, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return unpack_header(o.head.data(), avail, size, o.h, o.g);
+}
+
+template <typename T>
+int decode_t(const uint8_t *d_s, Opened &o, T *d_out, uint32_t mode, const Region &reg,
+             const sdcsz_fault *faults, uint32_t n_faults, sdcsz_report *h_rep, uint8_t *ws, uint64_t ws_size,
+             hipStream_t st) {
+  const Header &h = o.h;
+  const Geo &g = o.g;
+  std::vector<sdcsz_fault> plan;
+  int rc = check_plan(g, h.dtype, faults, n_faults, true, plan);
+  if (rc) return rc;
+  const DecLayout L = dec_layout(g, h.dtype, n_faults);
+  if (!ws || ws_size < L.total) return SDCSZ_ENOSPC;
+  // decoder tables from the codebook section
+  std::vector<uint8_t> len(65536, 0);
+  for (uint32_t t = 0; t < h.n_sym; t++) {
+    uint32_t e = get<uint32_t>(o.head.data(), kHeader + 4ull * t);
+    uint32_t s = e >> 8, l = e & 0xFF;
+    if (s > 65535 || l == 0 || l > kMaxLen || len[s]) return SDCSZ_EFORMAT;
+    len[s] = (uint8_t)l;
+  }
+  std::vector<uint16_t> order;
+  Canon C = canonical(len, nullptr, &order);
+  DecTab tab;
+  std::memset(&tab, 0, sizeof(tab));
+  tab.min_len = kMaxLen + 1;
+  tab.max_len = 0;
+  for (uint32_t l = 1; l <= kMaxLen; l++) {
+    tab.first[l] = C.first[l];
+    tab.count[l] = C.bl_count[l];
+    tab.start[l] = C.start[l];
+    if (C.bl_count[l]) {
+      tab.min_len = std::min(tab.min_len, l);
+      tab.max_len = std::max(tab.max_len, l);
+    }
+  }
+  if (tab.max_len == 0) tab.min_len = 1;
+  DecWork w;
+  w.cnt = (unsigned long long *)(ws + L.cnt);
+  w.symbols = (uint16_t *)(ws + L.symbols);
+  w.tab = (DecTab *)(ws + L.tab);
+  w.recon = ws + L.recon;
+  w.off_pay = (uint64_t *)(ws + L.off_pay);
+  w.off_out = (uint32_t *)(ws + L.off_out);
+  w.off_coef = (uint32_t *)(ws + L.off_coef);
+  w.scan_part = (uint64_t *)(ws + L.scan);
+  HIPCHK(hipMemcpyAsync(w.symbols, order.data(), 2 * 65536, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(w.tab, &tab, sizeof(tab), hipMemcpyHostToDevice, st));
+  std::vector<uint32_t> bits_host;
+  PlanDev pd;
+  rc = upload_plan(plan, g.n_blocks, ws, L.plan, L.bits, bits_host, st, &pd);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, w.cnt, (uint64_t)C_N);
+  const uint32_t *table = (const uint32_t *)(d_s + h.off_table);
+  ScanSrc src{table, table + 1, 2};
+  rc = launch_scan(src, g.n_blocks, w.scan_part, w.off_pay, w.off_out, w.off_coef, st);
+  if (rc) return rc;
+  uint64_t tot_pay = 0;
+  uint32_t tot_out = 0, tot_coef = 0;
+  HIPCHK(hipMemcpyAsync(&tot_pay, w.off_pay + g.n_blocks, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&tot_out, w.off_out + g.n_blocks, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&tot_coef, w.off_coef + g.n_blocks, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (tot_pay != h.payload_words || tot_out != h.n_outliers || tot_coef != h.n_regression) return SDCSZ_EFORMAT;
+  if (g.n_blocks) {
+    hipLaunchKernelGGL(k_decode_generic<T>, dim3(grid_for(g.n_blocks, 64)), dim3(64), 0, st, d_s, h, g, w, pd,
+                       d_out, mode, reg);
+    HIPCHK(hipGetLastError());
+  }
+  unsigned long long cnt[C_N];
+  HIPCHK(hipMemcpyAsync(cnt, w.cnt, sizeof(cnt), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  sdcsz_report rep;
+  fill_report(&rep, cnt, g.n_blocks);
+  rep.eb_abs = h.eb_abs;
+  rep.n_outliers = h.n_outliers;
+  rep.n_regression = h.n_regression;
+  rep.payload_words = h.payload_words;
+  rep.stream_size = h.total;
+  if (h_rep) *h_rep = rep;
+  return cnt[C_UNC + SDCSZ_T_RECON] ? SDCSZ_ESDC : SDCSZ_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *sdcsz_strerror(int code) {
+  switch (code) {
+    case SDCSZ_OK: return "ok";
+    case SDCSZ_EINVAL: return "invalid argument";
+    case SDCSZ_ENOSPC: return "output or workspace too small";
+    case SDCSZ_EFORMAT: return "not a valid sdcsz stream";
+    case SDCSZ_ESDC: return "uncorrectable silent data corruption";
+    case SDCSZ_EHIP: return "HIP runtime error";
+    default: return "unknown error";
+  }
+}
+
+uint64_t sdcsz_max_compressed_size(const sdcsz_params *p) {
+  Geo g;
+  if (check_params(p, &g)) return 0;
+  Header h;
+  std::memset(&h, 0, sizeof(h));
+  h.dtype = p->dtype;
+  h.abft = 1;
+  h.n_sym = 65536;
+  h.n_blocks = g.n_blocks;
+  h.n_regression = g.n_blocks;
+  h.n_outliers = g.n_values;
+  h.payload_words = (g.n_values * kMaxLen + 31) / 32 + g.n_blocks;
+  section_offsets(h);
+  return h.total;
+}
+
+uint64_t sdcsz_compress_workspace_size(const sdcsz_params *p) {
+  Geo g;
+  if (check_params(p, &g)) return 0;
+  return comp_layout(g, p->dtype, p->n_faults).total;
+}
+
+int sdcsz_compress(const void *d_in, const sdcsz_params *p, void *d_out, uint64_t out_cap, uint64_t *h_out_size,
+                   sdcsz_report *h_rep, void *d_ws, uint64_t ws_size, void *stream) {
+  Geo g;
+  int rc = check_params(p, &g);
+  if (rc) return rc;
+  if (!h_out_size || (g.n_values && !d_in)) return SDCSZ_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  if (p->dtype == SDCSZ_F32)
+    return compress_t<float>(d_in, p, g, (uint8_t *)d_out, out_cap, h_out_size, h_rep, (uint8_t *)d_ws, ws_size, st);
+  return compress_t<double>(d_in, p, g, (uint8_t *)d_out, out_cap, h_out_size, h_rep, (uint8_t *)d_ws, ws_size, st);
+}
+
+int sdcsz_stream_info(const void *d_stream, uint64_t stream_size, sdcsz_params *h_p, uint64_t *h_n_blocks,
+                      double *h_eb_abs, void *stream) {
+  Opened o;
+  int rc = open_stream(d_stream, stream_size, (hipStream_t)stream, o);
+  if (rc) return rc;
+  if (h_p) {
+    std::memset(h_p, 0, sizeof(*h_p));
+    h_p->dtype = o.h.dtype;
+    h_p->ndim = o.h.ndim;
+    for (uint32_t a = 0; a < o.h.ndim; a++) {
+      h_p->dims[a] = o.h.d[3 - o.h.ndim + a];
+      h_p->block[a] = o.h.b[3 - o.h.ndim + a];
+    }
+    h_p->eb_mode = o.h.eb_mode;
+    h_p->predictor = o.h.predictor;
+    h_p->eb = o.h.eb;
+    h_p->abft = o.h.abft;
+  }
+  if (h_n_blocks) *h_n_blocks = o.h.n_blocks;
+  if (h_eb_abs) *h_eb_abs = o.h.eb_abs;
+  return SDCSZ_OK;
+}
+
+uint64_t sdcsz_decompress_workspace_size(const sdcsz_params *p) {
+  Geo g;
+  if (!p || p->dtype > 1 || !geometry(p->ndim, p->dims, p->block, &g)) return 0;
+  return dec_layout(g, p->dtype, p->n_faults).total;
+}
+
+int sdcsz_decompress(const void *d_stream, uint64_t stream_size, void *d_out, uint64_t out_cap,
+                     const sdcsz_fault *h_faults, uint32_t n_faults, sdcsz_report *h_rep, void *d_ws, uint64_t ws_size,
+                     void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  Opened o;
+  int rc = open_stream(d_stream, stream_size, st, o);
+  if (rc) return rc;
+  if (out_cap < o.g.n_values * vbytes(o.h.dtype) || (o.g.n_values && !d_out)) return SDCSZ_ENOSPC;
+  Region reg{};
+  if (o.h.dtype == SDCSZ_F32)
+    return decode_t<float>((const uint8_t *)d_stream, o, (float *)d_out, 0, reg, h_faults, n_faults, h_rep,
+                           (uint8_t *)d_ws, ws_size, st);
+  return decode_t<double>((const uint8_t *)d_stream, o, (double *)d_out, 0, reg, h_faults, n_faults, h_rep,
+                          (uint8_t *)d_ws, ws_size, st);
+}
+
+int sdcsz_verify(const void *d_stream, uint64_t stream_size, void *d_data, uint64_t data_size,
+                 const sdcsz_fault *h_faults, uint32_t n_faults, sdcsz_report *h_rep, void *d_ws, uint64_t ws_size,
+                 void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  Opened o;
+  int rc = open_stream(d_stream, stream_size, st, o);
+  if (rc) return rc;
+  if (!o.h.abft) return SDCSZ_EINVAL;
+  if (data_size < o.g.n_values * vbytes(o.h.dtype) || (o.g.n_values && !d_data)) return SDCSZ_ENOSPC;
+  Region reg{};
+  if (o.h.dtype == SDCSZ_F32)
+    return decode_t<float>((const uint8_t *)d_stream, o, (float *)d_data, 1, reg, h_faults, n_faults, h_rep,
+                           (uint8_t *)d_ws, ws_size, st);
+  return decode_t<double>((const uint8_t *)d_stream, o, (double *)d_data, 1, reg, h_faults, n_faults, h_rep,
+                          (uint8_t *)d_ws, ws_size, st);
+}
+
+int sdcsz_decompress_region(const void *d_stream, uint64_t stream_size, const uint64_t *h_lo, const uint64_t *h_hi,
+                            void *d_out, uint64_t out_cap, sdcsz_report *h_rep, void *d_ws, uint64_t ws_size,
+                            void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  Opened o;
+  int rc = open_stream(d_stream, stream_size, st, o);
+  if (rc) return rc;
+  if (!h_lo || !h_hi) return SDCSZ_EINVAL;
+  Region reg;
+  uint64_t cnt = 1;
+  const uint32_t off = 3 - o.h.ndim;
+  for (int a = 0; a < 3; a++) {
+    reg.lo[a] = 0;
+    reg.hi[a] = 1;
+  }
+  for (uint32_t a = 0; a < o.h.ndim; a++) {
+    reg.lo[off + a] = h_lo[a];
+    reg.hi[off + a] = h_hi[a];
+  }
+  for (int a = 0; a < 3; a++) {
+    if (reg.lo[a] >= reg.hi[a] || reg.hi[a] > o.g.d[a]) return SDCSZ_EINVAL;
+    cnt *= reg.hi[a] - reg.lo[a];
+  }
+  if (out_cap < cnt * vbytes(o.h.dtype) || !d_out) return SDCSZ_ENOSPC;
+  if (o.h.dtype == SDCSZ_F32)
+    return decode_t<float>((const uint8_t *)d_stream, o, (float *)d_out, 2, reg, nullptr, 0, h_rep, (uint8_t *)d_ws,
+                           ws_size, st);
+  return decode_t<double>((const uint8_t *)d_stream, o, (double *)d_out, 2, reg, nullptr, 0, h_rep, (uint8_t *)d_ws,
+                          ws_size, st);
+}
+
+}  // extern "C"

@@ -1,0 +1,45 @@
+// kern.h -- kernel declarations (definitions in kern_*.hip).
+#pragma once
+
+#include "common.h"
+
+namespace sdcsz {
+
+struct Region {
+  uint64_t lo[3], hi[3];
+};
+
+// streams of counts scanned per block: payload words, outliers, regression
+struct ScanSrc {
+  const uint32_t *words;
+  const uint32_t *meta;
+  uint32_t stride;
+};
+
+constexpr uint32_t kScanThreads = 256;
+constexpr uint32_t kScanItems = 8;
+constexpr uint32_t kScanChunk = kScanThreads * kScanItems;
+constexpr uint32_t kRangeThreads = 256;
+constexpr uint32_t kRangeBlocks = 2048;
+
+__global__ void k_zero_u64(unsigned long long *p, uint64_t n);
+__global__ void k_zero_u32(uint32_t *p, uint64_t n);
+template <typename T> __global__ void k_range(const T *in, uint64_t n, double *part);
+__global__ void k_consts(const double *part, uint32_t nparts, uint32_t mode, double eb, EbDev *out);
+__global__ void k_code_faults(PlanDev plan, Geo g, uint16_t *codes, unsigned long long *cnt);
+__global__ void k_codes_check(Geo g, CompWork w, uint32_t abft);
+__global__ void k_scan1(ScanSrc src, uint64_t n, uint64_t *part);
+__global__ void k_scan2(uint64_t *part, uint32_t nparts);
+__global__ void k_scan3(ScanSrc src, uint64_t n, const uint64_t *part, uint64_t *off_pay,
+                        uint32_t *off_out, uint32_t *off_coef);
+template <typename T>
+__global__ void k_encode(Geo g, CompWork w, uint8_t *out, Header h);
+
+template <typename T>
+__global__ void k_compress_generic(const T *in, Geo g, RegTab<T> rt, PlanDev plan, CompWork w,
+                                   uint32_t abft, uint32_t predictor);
+template <typename T>
+__global__ void k_decode_generic(const uint8_t *s, Header h, Geo g, DecWork w, PlanDev plan,
+                                 T *out, uint32_t mode, Region reg);
+
+}  // namespace sdcsz

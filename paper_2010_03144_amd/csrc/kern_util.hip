@@ -1,0 +1,269 @@
+// kern_util.hip -- range/constant kernels, code check and sizing, scans and
+// stream assembly.
+#include "dev.h"
+#include "kern.h"
+
+namespace sdcsz {
+
+__global__ void k_zero_u64(unsigned long long *p, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+__global__ void k_zero_u32(uint32_t *p, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+// ---- value range of the finite values (value-range relative bound) ----------
+template <typename T>
+__global__ void __launch_bounds__(kRangeThreads) k_range(const T *__restrict__ in, uint64_t n, double *part) {
+  T lo = (T)INFINITY, hi = (T)-INFINITY;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    T v = in[i];
+    if (isfinite(v)) {
+      lo = v < lo ? v : lo;
+      hi = v > hi ? v : hi;
+    }
+  }
+  __shared__ double slo[kRangeThreads], shi[kRangeThreads];
+  slo[threadIdx.x] = (double)lo;
+  shi[threadIdx.x] = (double)hi;
+  __syncthreads();
+  for (uint32_t s = kRangeThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + s]);
+      shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = slo[0];
+    part[2 * blockIdx.x + 1] = shi[0];
+  }
+}
+template __global__ void k_range<float>(const float *, uint64_t, double *);
+template __global__ void k_range<double>(const double *, uint64_t, double *);
+
+// eb_abs and its derived constants, computed in double then rounded once.
+__global__ void k_consts(const double *part, uint32_t nparts, uint32_t mode, double eb, EbDev *out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double eb_abs = eb;
+  if (mode == SDCSZ_REL) {
+    double lo = INFINITY, hi = -INFINITY;
+    for (uint32_t i = 0; i < nparts; i++) {
+      lo = fmin(lo, part[2 * i]);
+      hi = fmax(hi, part[2 * i + 1]);
+    }
+    eb_abs = lo <= hi ? eb * (hi - lo) : 0.0;
+  }
+  EbDev e;
+  e.eb_abs = eb_abs;
+  e.q = 2.0 * eb_abs;
+  e.inv = 1.0 / (2.0 * eb_abs);
+  e.inv_e = 1.0 / eb_abs;
+  e.qf = (float)e.q;
+  e.invf = (float)e.inv;
+  e.inv_ef = (float)e.inv_e;
+  e.pad = 0;
+  *out = e;
+}
+
+// ---- codes at rest: fault injection, then detection/correction + sizing ----
+__global__ void k_code_faults(PlanDev plan, Geo g, uint16_t *codes, unsigned long long *cnt) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (uint32_t t = 0; t < plan.n; t++) {
+    const sdcsz_fault f = plan.f[t];
+    if (f.target != SDCSZ_T_CODE) continue;
+    codes[f.block * (uint64_t)g.bpts + f.word] ^= (uint16_t)(1u << (f.bit & 15));
+    cnt[C_INJ + SDCSZ_T_CODE]++;
+  }
+}
+
+// One thread per block: verify/correct the block's codes with sum_q/isum_q
+// (Algorithm 1, before encoding) and size its Huffman payload in words.
+__global__ void __launch_bounds__(256) k_codes_check(Geo g, CompWork w, uint32_t abft) {
+  const uint64_t blk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (blk >= g.n_blocks) return;
+  const Box b = box_of(g, blk);
+  uint16_t *codes = w.codes + blk * (uint64_t)g.bpts;
+  if (abft) {
+    uint64_t s2 = 0, i2 = 0;
+    for (uint32_t p = 0; p < b.pts; p++) {
+      s2 += codes[p];
+      i2 += (uint64_t)p * codes[p];
+    }
+    uint64_t j;
+    uint32_t v;
+    int st = locate_repair(s2, i2, w.sum_q[blk], w.isum_q[blk], b.pts, 16,
+                           [&](uint64_t jj) { return (uint32_t)codes[jj]; }, &j, &v);
+    if (st != 0) count(w.cnt, C_DET + SDCSZ_T_CODE);
+    if (st == 1) {
+      codes[j] = (uint16_t)v;
+      count(w.cnt, C_COR + SDCSZ_T_CODE);
+    }
+    if (st < 0) count(w.cnt, C_UNC + SDCSZ_T_CODE);
+  }
+  uint64_t bits = 0;
+  bool missing = false;
+  for (uint32_t p = 0; p < b.pts; p++) {
+    uint32_t len = w.enc[codes[p]] & 0xFFu;
+    missing |= len == 0;
+    bits += len;
+  }
+  if (missing) count(w.cnt, C_MISSING);
+  w.words[blk] = (uint32_t)((bits + 31) / 32);
+}
+
+// ---- scans of per-block counts ----------------------------------------------
+namespace {
+struct Tri {
+  uint64_t a;
+  uint64_t b;
+  uint64_t c;
+};
+
+__device__ inline Tri item(const ScanSrc &s, uint64_t i) {
+  uint32_t m = s.meta[i * s.stride];
+  return Tri{s.words[i * s.stride], m >> 1, m & 1u};
+}
+
+// exclusive scan of one Tri per thread across the work-group; returns the
+// exclusive prefix and sets *total.
+__device__ Tri block_exclusive(Tri v, Tri *total) {
+  __shared__ uint64_t sh[3][kScanThreads];
+  const uint32_t t = threadIdx.x;
+  sh[0][t] = v.a;
+  sh[1][t] = v.b;
+  sh[2][t] = v.c;
+  __syncthreads();
+  for (uint32_t off = 1; off < kScanThreads; off <<= 1) {
+    uint64_t a = 0, b = 0, c = 0;
+    if (t >= off) {
+      a = sh[0][t - off];
+      b = sh[1][t - off];
+      c = sh[2][t - off];
+    }
+    __syncthreads();
+    sh[0][t] += a;
+    sh[1][t] += b;
+    sh[2][t] += c;
+    __syncthreads();
+  }
+  Tri incl{sh[0][t], sh[1][t], sh[2][t]};
+  *total = Tri{sh[0][kScanThreads - 1], sh[1][kScanThreads - 1], sh[2][kScanThreads - 1]};
+  __syncthreads();
+  return Tri{incl.a - v.a, incl.b - v.b, incl.c - v.c};
+}
+}  // namespace
+
+__global__ void __launch_bounds__(kScanThreads) k_scan1(ScanSrc src, uint64_t n, uint64_t *part) {
+  const uint64_t base = (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * kScanItems;
+  Tri s{0, 0, 0};
+  for (uint32_t u = 0; u < kScanItems; u++)
+    if (base + u < n) {
+      Tri v = item(src, base + u);
+      s.a += v.a;
+      s.b += v.b;
+      s.c += v.c;
+    }
+  Tri tot;
+  block_exclusive(s, &tot);
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x] = tot.a;
+    part[3 * blockIdx.x + 1] = tot.b;
+    part[3 * blockIdx.x + 2] = tot.c;
+  }
+}
+
+// single work-group: exclusive scan of the chunk totals, in place
+__global__ void __launch_bounds__(kScanThreads) k_scan2(uint64_t *part, uint32_t nparts) {
+  Tri carry{0, 0, 0};
+  for (uint32_t base = 0; base < nparts; base += kScanThreads) {
+    uint32_t i = base + threadIdx.x;
+    Tri v{0, 0, 0};
+    if (i < nparts) v = Tri{part[3 * i], part[3 * i + 1], part[3 * i + 2]};
+    Tri tot;
+    Tri ex = block_exclusive(v, &tot);
+    if (i < nparts) {
+      part[3 * i] = carry.a + ex.a;
+      part[3 * i + 1] = carry.b + ex.b;
+      part[3 * i + 2] = carry.c + ex.c;
+    }
+    carry.a += tot.a;
+    carry.b += tot.b;
+    carry.c += tot.c;
+  }
+}
+
+__global__ void __launch_bounds__(kScanThreads)
+k_scan3(ScanSrc src, uint64_t n, const uint64_t *part, uint64_t *off_pay, uint32_t *off_out, uint32_t *off_coef) {
+  const uint64_t base = (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * kScanItems;
+  Tri loc[kScanItems];
+  Tri s{0, 0, 0};
+  for (uint32_t u = 0; u < kScanItems; u++) {
+    loc[u] = base + u < n ? item(src, base + u) : Tri{0, 0, 0};
+    s.a += loc[u].a;
+    s.b += loc[u].b;
+    s.c += loc[u].c;
+  }
+  Tri tot;
+  Tri ex = block_exclusive(s, &tot);
+  Tri run{part[3 * blockIdx.x] + ex.a, part[3 * blockIdx.x + 1] + ex.b, part[3 * blockIdx.x + 2] + ex.c};
+  for (uint32_t u = 0; u < kScanItems; u++) {
+    if (base + u < n) {
+      off_pay[base + u] = run.a;
+      off_out[base + u] = (uint32_t)run.b;
+      off_coef[base + u] = (uint32_t)run.c;
+    }
+    run.a += loc[u].a;
+    run.b += loc[u].b;
+    run.c += loc[u].c;
+    if (base + u + 1 == n) {
+      off_pay[n] = run.a;
+      off_out[n] = (uint32_t)run.b;
+      off_coef[n] = (uint32_t)run.c;
+    }
+  }
+}
+
+// ---- stream assembly: one thread per block ----------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_encode(Geo g, CompWork w, uint8_t *out, Header h) {
+  const uint64_t blk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (blk >= g.n_blocks) return;
+  const Box b = box_of(g, blk);
+  const uint16_t *codes = w.codes + blk * (uint64_t)g.bpts;
+  uint32_t *dst = (uint32_t *)(out + h.off_payload) + w.off_pay[blk];
+  uint64_t acc = 0;
+  uint32_t nacc = 0;
+  for (uint32_t p = 0; p < b.pts; p++) {
+    uint32_t e = w.enc[codes[p]];
+    uint32_t len = e & 0xFFu;
+    acc = (acc << len) | (e >> 8);
+    nacc += len;
+    if (nacc >= 32) {
+      nacc -= 32;
+      *dst++ = (uint32_t)(acc >> nacc);
+      acc &= (1ull << nacc) - 1;
+    }
+  }
+  if (nacc > 0) *dst++ = (uint32_t)(acc << (32 - nacc));
+  const uint32_t meta = w.meta[blk];
+  uint32_t *tab = (uint32_t *)(out + h.off_table) + 2 * blk;
+  tab[0] = w.words[blk];
+  tab[1] = meta;
+  const T *src = (const T *)w.vals + blk * (uint64_t)g.bpts;
+  T *od = (T *)(out + h.off_outliers) + w.off_out[blk];
+  for (uint32_t t = 0; t < (meta >> 1); t++) od[t] = src[t];
+  if (meta & 1u) {
+    const T *cf = (const T *)w.coef + 4 * blk;
+    T *cd = (T *)(out + h.off_coef) + 4ull * w.off_coef[blk];
+    for (int a = 0; a < 4; a++) cd[a] = cf[a];
+  }
+  if (h.abft) ((uint64_t *)(out + h.off_sumdc))[blk] = w.sum_dc[blk];
+}
+template __global__ void k_encode<float>(Geo, CompWork, uint8_t *, Header);
+template __global__ void k_encode<double>(Geo, CompWork, uint8_t *, Header);
+
+}  // namespace sdcsz

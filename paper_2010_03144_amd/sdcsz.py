@@ -1,0 +1,244 @@
+"""Python binding of libsdcsz.so (the C ABI declared in include/sdcsz.h).
+
+Argument marshalling only: PyTorch provides device memory and the current
+HIP stream; every step of compression and decompression runs in the
+library's HIP kernels.  Importing works without a GPU; calling needs the
+built library (paper_2010_03144_amd/libsdcsz.so) and fails loudly if it is
+missing.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsdcsz.so")
+
+OK, EINVAL, ENOSPC, EFORMAT, ESDC, EHIP = 0, -1, -2, -3, -4, -5
+TARGETS = ["input", "coef", "code", "recon", "dup_pred", "dup_recon"]
+ERRORS = {OK: "ok", EINVAL: "EINVAL", ENOSPC: "ENOSPC", EFORMAT: "EFORMAT", ESDC: "ESDC", EHIP: "EHIP"}
+FUNCTIONS = ["sdcsz_max_compressed_size", "sdcsz_compress_workspace_size", "sdcsz_compress",
+             "sdcsz_stream_info", "sdcsz_decompress_workspace_size", "sdcsz_decompress",
+             "sdcsz_verify", "sdcsz_decompress_region", "sdcsz_strerror"]
+
+
+class SdcszError(RuntimeError):
+    def __init__(self, rc, what=""):
+        super().__init__(f"{what}: {ERRORS.get(rc, rc)}")
+        self.rc = rc
+
+
+class Fault(C.Structure):
+    _fields_ = [("target", C.c_uint32), ("bit", C.c_uint32), ("block", C.c_uint64),
+                ("word", C.c_uint64)]
+
+
+class Params(C.Structure):
+    _fields_ = [("dtype", C.c_uint32), ("ndim", C.c_uint32), ("dims", C.c_uint64 * 3),
+                ("block", C.c_uint32 * 3), ("eb_mode", C.c_uint32), ("predictor", C.c_uint32),
+                ("eb", C.c_double), ("abft", C.c_uint32), ("n_faults", C.c_uint32),
+                ("faults", C.POINTER(Fault))]
+
+
+class Report(C.Structure):
+    _fields_ = [("n_blocks", C.c_uint64), ("injected", C.c_uint64 * 6),
+                ("detected", C.c_uint64 * 6), ("corrected", C.c_uint64 * 6),
+                ("uncorrectable", C.c_uint64 * 6), ("n_outliers", C.c_uint64),
+                ("n_regression", C.c_uint64), ("payload_words", C.c_uint64),
+                ("stream_size", C.c_uint64), ("eb_abs", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsdcsz.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2010_03144_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        vp = C.c_void_p
+        L.sdcsz_max_compressed_size.restype = C.c_uint64
+        L.sdcsz_max_compressed_size.argtypes = [P(Params)]
+        L.sdcsz_compress_workspace_size.restype = C.c_uint64
+        L.sdcsz_compress_workspace_size.argtypes = [P(Params)]
+        L.sdcsz_decompress_workspace_size.restype = C.c_uint64
+        L.sdcsz_decompress_workspace_size.argtypes = [P(Params)]
+        L.sdcsz_compress.argtypes = [vp, P(Params), vp, C.c_uint64, P(C.c_uint64), P(Report), vp,
+                                     C.c_uint64, vp]
+        L.sdcsz_stream_info.argtypes = [vp, C.c_uint64, P(Params), P(C.c_uint64), P(C.c_double), vp]
+        L.sdcsz_decompress.argtypes = [vp, C.c_uint64, vp, C.c_uint64, P(Fault), C.c_uint32, P(Report),
+                                       vp, C.c_uint64, vp]
+        L.sdcsz_verify.argtypes = [vp, C.c_uint64, vp, C.c_uint64, P(Fault), C.c_uint32, P(Report), vp,
+                                   C.c_uint64, vp]
+        L.sdcsz_decompress_region.argtypes = [vp, C.c_uint64, P(C.c_uint64), P(C.c_uint64), vp,
+                                              C.c_uint64, P(Report), vp, C.c_uint64, vp]
+        L.sdcsz_strerror.restype = C.c_char_p
+        L.sdcsz_strerror.argtypes = [C.c_int]
+        _lib = L
+    return _lib
+
+
+def report_dict(r):
+    d = {"n_blocks": r.n_blocks, "n_outliers": r.n_outliers, "n_regression": r.n_regression,
+         "payload_words": r.payload_words, "stream_size": r.stream_size, "eb_abs": r.eb_abs}
+    for i, t in enumerate(TARGETS):
+        d[t] = {"injected": r.injected[i], "detected": r.detected[i],
+                "corrected": r.corrected[i], "uncorrectable": r.uncorrectable[i]}
+    return d
+
+
+def _faults(faults):
+    if faults is None or len(faults) == 0:
+        return None, 0, None
+    arr = (Fault * len(faults))()
+    for i, f in enumerate(faults):
+        arr[i].target, arr[i].bit, arr[i].block, arr[i].word = (int(f[0]), int(f[1]), int(f[2]),
+                                                                int(f[3]))
+    return C.cast(arr, C.POINTER(Fault)), len(faults), arr
+
+
+def make_params(shape, is_f32, block, eb, eb_mode="rel", abft=True, predictor="auto", faults=None):
+    p = Params()
+    p.dtype = 0 if is_f32 else 1
+    p.ndim = len(shape)
+    for a, n in enumerate(shape):
+        p.dims[a] = int(n)
+        p.block[a] = int(block[a])
+    p.eb_mode = {"abs": 0, "rel": 1}[eb_mode]
+    p.predictor = {"auto": 0, "lorenzo": 1, "regression": 2}[predictor]
+    p.eb = float(eb)
+    p.abft = 1 if abft else 0
+    ptr, n, keep = _faults(faults)
+    p.n_faults = n
+    p.faults = ptr
+    p._keep = keep
+    return p
+
+
+def _stream_handle(device):
+    import torch
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Codec:
+    """Compress/decompress torch tensors on one GPU.  Workspaces are cached
+    per size (torch allocations), so repeated calls allocate nothing new."""
+
+    def __init__(self, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self._ws = {}
+
+    def workspace(self, nbytes, tag):
+        t = self._ws.get(tag)
+        if t is None or t.numel() < nbytes:
+            t = self.torch.empty(max(int(nbytes), 256), dtype=self.torch.uint8, device=self.device)
+            self._ws[tag] = t
+        return t
+
+    # ------------------------------------------------------------------ compress
+    def compress(self, x, block, eb, eb_mode="rel", abft=True, predictor="auto", faults=None,
+                 out=None):
+        """Returns (rc, stream uint8 tensor on the device, report dict)."""
+        torch = self.torch
+        L = lib()
+        assert x.is_cuda and x.is_contiguous() and x.dtype in (torch.float32, torch.float64)
+        p = make_params(tuple(x.shape), x.dtype == torch.float32, block, eb, eb_mode, abft,
+                        predictor, faults)
+        ws_n = L.sdcsz_compress_workspace_size(C.byref(p))
+        if ws_n == 0:
+            return EINVAL, None, None
+        cap = L.sdcsz_max_compressed_size(C.byref(p))
+        if out is None or out.numel() < cap:
+            out = self.workspace(cap, "stream_out")
+        ws = self.workspace(ws_n, "compress")
+        size = C.c_uint64(0)
+        rep = Report()
+        rc = L.sdcsz_compress(C.c_void_p(x.data_ptr()), C.byref(p), C.c_void_p(out.data_ptr()),
+                              out.numel(), C.byref(size), C.byref(rep), C.c_void_p(ws.data_ptr()),
+                              ws.numel(), _stream_handle(self.device))
+        stream = out[: size.value] if rc == OK else None
+        return rc, stream, report_dict(rep)
+
+    def info(self, stream):
+        L = lib()
+        p = Params()
+        nb = C.c_uint64(0)
+        eb_abs = C.c_double(0)
+        rc = L.sdcsz_stream_info(C.c_void_p(stream.data_ptr()), stream.numel(), C.byref(p),
+                                 C.byref(nb), C.byref(eb_abs), _stream_handle(self.device))
+        if rc != OK:
+            return rc, None, None
+        shape = tuple(int(p.dims[a]) for a in range(p.ndim))
+        return rc, p, shape
+
+    def _dec_ws(self, p, n_faults):
+        L = lib()
+        p.n_faults = n_faults
+        n = L.sdcsz_decompress_workspace_size(C.byref(p))
+        return self.workspace(n, "decompress")
+
+    # ---------------------------------------------------------------- decompress
+    def decompress(self, stream, faults=None, out=None):
+        """Returns (rc, tensor, report dict)."""
+        torch = self.torch
+        L = lib()
+        rc, p, shape = self.info(stream)
+        if rc != OK:
+            return rc, None, None
+        dt = torch.float32 if p.dtype == 0 else torch.float64
+        if out is None:
+            out = torch.empty(shape, dtype=dt, device=self.device)
+        fptr, nf, keep = _faults(faults)
+        ws = self._dec_ws(p, nf)
+        rep = Report()
+        rc = L.sdcsz_decompress(C.c_void_p(stream.data_ptr()), stream.numel(),
+                                C.c_void_p(out.data_ptr()), out.numel() * out.element_size(), fptr,
+                                nf, C.byref(rep), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                _stream_handle(self.device))
+        del keep
+        return rc, out, report_dict(rep)
+
+    def verify(self, stream, data, faults=None):
+        """Check `data` (repaired in place) against the stream's checksums."""
+        L = lib()
+        rc, p, shape = self.info(stream)
+        if rc != OK:
+            return rc, None
+        fptr, nf, keep = _faults(faults)
+        ws = self._dec_ws(p, nf)
+        rep = Report()
+        rc = L.sdcsz_verify(C.c_void_p(stream.data_ptr()), stream.numel(),
+                            C.c_void_p(data.data_ptr()), data.numel() * data.element_size(), fptr,
+                            nf, C.byref(rep), C.c_void_p(ws.data_ptr()), ws.numel(),
+                            _stream_handle(self.device))
+        del keep
+        return rc, report_dict(rep)
+
+    def decompress_region(self, stream, lo, hi):
+        torch = self.torch
+        L = lib()
+        rc, p, shape = self.info(stream)
+        if rc != OK:
+            return rc, None, None
+        dt = torch.float32 if p.dtype == 0 else torch.float64
+        ext = [int(h) - int(l) for l, h in zip(lo, hi)]
+        out = torch.empty([max(e, 0) for e in ext], dtype=dt, device=self.device)
+        ws = self._dec_ws(p, 0)
+        lo_a = (C.c_uint64 * 3)(*([int(v) for v in lo] + [0] * (3 - len(lo))))
+        hi_a = (C.c_uint64 * 3)(*([int(v) for v in hi] + [0] * (3 - len(hi))))
+        rep = Report()
+        rc = L.sdcsz_decompress_region(C.c_void_p(stream.data_ptr()), stream.numel(), lo_a, hi_a,
+                                       C.c_void_p(out.data_ptr()) if out.numel() else None,
+                                       out.numel() * out.element_size(), C.byref(rep),
+                                       C.c_void_p(ws.data_ptr()), ws.numel(),
+                                       _stream_handle(self.device))
+        return rc, out, report_dict(rep)
+
+
+def strerror(rc):
+    return lib().sdcsz_strerror(rc).decode()

@@ -1,0 +1,158 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Integer outputs (codes, predictor choices, Huffman streams, fault counters)
+and the reconstructed values must match bit for bit: both sides evaluate the
+same IEEE operations in the same order (no contraction, no fast math).
+"""
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_2010_03144_amd import sdcsz, synth
+from tests.gpu_util import first_difference
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def codec():
+    return sdcsz.Codec("cuda:0")
+
+
+def both(codec, x, block, eb, **kw):
+    print(f"case shape={x.shape} dtype={x.dtype} block={block} eb={eb} {kw}", flush=True)
+    rc_r, s_r, rep_r = ref.compress(x, block, eb, **kw)
+    xd = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    rc_g, s_g, rep_g = codec.compress(xd, block, eb, **kw)
+    s_g = s_g.cpu().numpy() if s_g is not None else None
+    return (rc_r, s_r, rep_r), (rc_g, s_g, rep_g)
+
+
+def same_counts(a, b):
+    for t in sdcsz.TARGETS:
+        assert a[t] == b[t], (t, a[t], b[t])
+
+
+def check_roundtrip(codec, x, block, eb, **kw):
+    (rc_r, s_r, rep_r), (rc_g, s_g, rep_g) = both(codec, x, block, eb, **kw)
+    assert rc_r == rc_g == 0, (rc_r, rc_g)
+    assert np.array_equal(s_r, s_g), first_difference(s_r, s_g)
+    same_counts(rep_r, rep_g)
+    assert rep_r["eb_abs"] == rep_g["eb_abs"]
+    rc, y_r, _ = ref.decompress(s_r)
+    rc2, y_g, rep_d = codec.decompress(torch.from_numpy(s_g).cuda())
+    assert rc == rc2 == 0
+    y_g = y_g.cpu().numpy()
+    assert np.array_equal(y_r.view(np.uint8), y_g.view(np.uint8))
+    fin = np.isfinite(x)
+    if x.size:
+        err = np.abs(x[fin].astype(np.float64) - y_g[fin].astype(np.float64))
+        assert err.size == 0 or err.max() <= rep_g["eb_abs"]
+    return s_g, rep_g
+
+
+def test_config1_bumps_64cube(codec):
+    x = synth.bumps_field((64, 64, 64), seed=1)
+    check_roundtrip(codec, x, (6, 6, 6), 1e-3)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("eb", [1e-2, 1e-4])
+@pytest.mark.parametrize("abft", [True, False])
+def test_grf_tiles_and_ragged_tail(codec, dtype, eb, abft):
+    x = synth.grf_field((50, 47, 44), seed=2, dtype=dtype)
+    check_roundtrip(codec, x, (6, 6, 6), eb, abft=abft)
+
+
+@pytest.mark.parametrize("predictor", ["lorenzo", "regression"])
+def test_forced_predictors(codec, predictor):
+    x = synth.grf_field((30, 31, 32), seed=7)
+    check_roundtrip(codec, x, (6, 6, 6), 1e-3, predictor=predictor)
+
+
+@pytest.mark.parametrize("shape,block", [((300, 257), (16, 16)), ((5000,), (64,)), ((7, 13, 5), (6, 6, 6)),
+                                         ((33, 20), (8, 5)), ((1, 1, 1), (6, 6, 6)), ((9, 9, 9), (4, 4, 4)),
+                                         ((40, 40, 40), (10, 10, 10))])
+def test_shapes(codec, shape, block):
+    x = synth.grf_field(shape, seed=4, dtype=np.float32)
+    check_roundtrip(codec, x, block, 1e-3)
+    check_roundtrip(codec, x.astype(np.float64), block, 0.05, eb_mode="abs")
+
+
+def test_special_values(codec):
+    x = synth.bumps_field((20, 20, 20), seed=3)
+    x[1, 2, 3] = np.nan
+    x[7, 7, 7] = np.inf
+    x[19, 0, 5] = -np.inf
+    x[10, 10, 10] = 1e-42  # FP32 denormal
+    check_roundtrip(codec, x, (6, 6, 6), 1e-3)
+    c = np.full((9, 8, 7), 3.25, np.float32)
+    check_roundtrip(codec, c, (6, 6, 6), 1e-3)
+
+
+def test_empty_field(codec):
+    x = np.zeros((0, 5), np.float32)
+    (rc_r, s_r, _), (rc_g, s_g, _) = both(codec, x, (16, 16), 1e-3)
+    assert rc_r == rc_g == 0 and np.array_equal(s_r, s_g)
+
+
+def test_invalid_arguments(codec):
+    x = torch.zeros((8, 8), device="cuda")
+    assert codec.compress(x, (0, 8), 1e-3)[0] == sdcsz.EINVAL
+    assert codec.compress(x, (8, 8), -1.0)[0] == sdcsz.EINVAL
+    bad = torch.zeros(256, dtype=torch.uint8, device="cuda")
+    assert codec.decompress(bad)[0] == sdcsz.EFORMAT
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_compression_fault_counts_match_oracle(codec, dtype):
+    shape, block = (48, 42, 36), (6, 6, 6)
+    x = synth.grf_field(shape, seed=3, dtype=dtype)
+    plan = synth.fault_plan(shape, block, dtype, {"input": 6, "coef": 6, "code": 6, "dup_pred": 6,
+                                                  "dup_recon": 6}, seed=31)
+    for abft in (True, False):
+        (rc_r, s_r, rep_r), (rc_g, s_g, rep_g) = both(codec, x, block, 1e-4, abft=abft, faults=plan)
+        assert rc_r == rc_g, (rc_r, rc_g)
+        same_counts(rep_r, rep_g)
+        if rc_r == 0:
+            assert np.array_equal(s_r, s_g), first_difference(s_r, s_g)
+
+
+def test_decompression_faults_and_verify(codec):
+    shape, block = (48, 42, 36), (6, 6, 6)
+    x = synth.grf_field(shape, seed=3)
+    rc, s, _ = ref.compress(x, block, 1e-4)
+    plan = synth.fault_plan(shape, block, np.float32, {"recon": 25}, seed=8)
+    rc_r, y_r, rep_r = ref.decompress(s, faults=plan)
+    sd = torch.from_numpy(s).cuda()
+    rc_g, y_g, rep_g = codec.decompress(sd, faults=plan)
+    assert rc_r == rc_g == 0
+    same_counts(rep_r, rep_g)
+    assert np.array_equal(y_r.view(np.uint32), y_g.cpu().numpy().view(np.uint32))
+    z = y_g.clone()
+    rc_v, rep_v = codec.verify(sd, z, faults=plan)
+    assert rc_v == 0 and rep_v["recon"]["corrected"] == 25
+    assert torch.equal(z, y_g)
+
+
+def test_corrupt_stream_is_reported(codec):
+    x = synth.grf_field((24, 24, 24), seed=3)
+    rc, s, _ = ref.compress(x, (6, 6, 6), 1e-4)
+    from tests.gpu_util import sections
+    bad = s.copy()
+    bad[sections(s)["payload"] + 40] ^= 0x10
+    rc_r, _, rep_r = ref.decompress(bad)
+    rc_g, _, rep_g = codec.decompress(torch.from_numpy(bad).cuda())
+    assert rc_r == rc_g == sdcsz.ESDC
+    same_counts(rep_r, rep_g)
+
+
+def test_region(codec):
+    x = synth.grf_field((30, 26, 20), seed=6)
+    rc, s, _ = ref.compress(x, (6, 6, 6), 1e-3)
+    lo, hi = (5, 3, 7), (17, 26, 13)
+    rc_r, part_r, _ = ref.decompress_region(s, lo, hi)
+    rc_g, part_g, _ = codec.decompress_region(torch.from_numpy(s).cuda(), lo, hi)
+    assert rc_r == rc_g == 0
+    assert np.array_equal(part_r.view(np.uint32), part_g.cpu().numpy().view(np.uint32))
