@@ -1,0 +1,210 @@
+"""Benchmark: compress + decompress throughput of one 512^3 FP32 field on one GPU.
+
+A step is one sdcsz_compress plus one sdcsz_decompress of the resident field
+(the whole hot path: range, per-block prediction/quantization with ABFT,
+code check, scans, Huffman encoding and stream assembly, then decoding with
+the checksum check).  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD public specification
+METRIC = "compress+decompress GB/s and %HBM roofline, ABFT on/off; p50/p99 served"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(phase, n, nb, vb, rep, abft):
+    """Bytes the method must move in one launch of a phase."""
+    n_out, n_reg, pw = rep["n_outliers"], rep["n_regression"], rep["payload_words"]
+    sums = 24 * nb if abft else 0  # sum_dc, sum_q, isum_q per block
+    if phase == "range":
+        return vb * n
+    if phase == "predict_quantize":
+        return vb * n + 2 * n + vb * n_out + nb * (4 + 4 * vb) + sums
+    if phase == "code_check":
+        return 2 * n + 4 * nb + (16 * nb if abft else 0)
+    if phase == "encode":
+        return (2 * n + 4 * pw + 2 * vb * n_out + 2 * 4 * vb * n_reg + 16 * nb
+                + (16 * nb if abft else 0))
+    if phase == "decode":
+        return 4 * pw + 8 * nb + vb * n_out + 4 * vb * n_reg + (8 * nb if abft else 0) + vb * n
+    if phase in ("scan_compress", "scan_decompress"):
+        return nb * 8 + nb * 16
+    return 0
+
+
+def source_digest():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2010_03144_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(phase, digest):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if
+    they were taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = d.get(phase)
+    if not e or e.get("source_digest") != digest:
+        return None
+    return e.get("hbm_bytes_per_launch")
+
+
+def run_steps(codec, xd, block, eb, abft, steps, sync):
+    stream = y = rep = None
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rc, stream, rep = codec.compress(xd, block, eb, abft=abft)
+        assert rc == 0, rc
+        rc, y, _ = codec.decompress(stream, out=y)
+        assert rc == 0, rc
+    sync()
+    return (time.perf_counter() - t0) / steps, stream, y, rep
+
+
+def cpu_baseline(x, block, eb):
+    """The oracle, as it is, on a bounded crop of the same field (1 core)."""
+    from oracle import ref
+    crop = np.ascontiguousarray(x[:320])  # 320 x 512 x 512 slab of the field
+    t0 = time.perf_counter()
+    rc, s, _ = ref.compress(crop, block, eb)
+    t1 = time.perf_counter()
+    rc2, y, _ = ref.decompress(s)
+    t2 = time.perf_counter()
+    assert rc == 0 and rc2 == 0
+    gbs = crop.nbytes / (t2 - t0) / 1e9
+    return {"value": round(gbs, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"320x512x512 FP32 slab of the same field, eb {eb:g} REL, ABFT on: "
+                      f"compress {t1 - t0:.2f} s + decompress {t2 - t1:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--eb", type=float, default=1e-3)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build runs the compressor on a single MI355X "
+              "and has no multi-GPU path (see DESIGN.md for how it would shard).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2010_03144_amd import sdcsz, synth
+
+    shape = (args.size,) * 3
+    block = (6, 6, 6)
+    log(f"generating {shape} FP32 field")
+    x = synth.grf_field(shape, seed=2)
+    xd = torch.from_numpy(x).cuda()
+    n, vb = x.size, 4
+    codec = sdcsz.Codec("cuda:0")
+    sync = torch.cuda.synchronize
+
+    log("warmup")
+    run_steps(codec, xd, block, args.eb, True, max(args.warmup, 1), sync)
+    sdcsz.timing_enable(True)
+    sync()
+    log(f"timed: {args.steps} steps, ABFT on")
+    t_on, stream, y, rep = run_steps(codec, xd, block, args.eb, True, args.steps, sync)
+    phases = sdcsz.timing_read()
+    sdcsz.timing_enable(False)
+    err = float((xd.double() - y.double()).abs().max())
+    assert err <= rep["eb_abs"], (err, rep["eb_abs"])
+    nb = rep["n_blocks"]
+    stream_bytes = int(stream.numel())
+
+    log("timed: ABFT off")
+    t_off, stream_off, _, rep_off = run_steps(codec, xd, block, args.eb, False, args.steps, sync)
+
+    # compress-only / decompress-only split from the phase timers
+    comp_ph = ("range", "predict_quantize", "code_faults", "code_check", "scan_compress", "encode")
+    dec_ph = ("scan_decompress", "decode")
+    ms_c = sum(phases[p][0] for p in comp_ph) / args.steps
+    ms_d = sum(phases[p][0] for p in dec_ph) / args.steps
+
+    # roofline of the dominant kernel
+    dom = max(phases, key=lambda p: phases[p][0])
+    dom_ms, dom_launches = phases[dom]
+    avg_s = dom_ms / max(dom_launches, 1) / 1e3
+    alg = algorithmic_bytes(dom, n, nb, vb, rep, True)
+    achieved = alg / avg_s / 1e9
+    digest = source_digest()
+    traffic = traffic_from_profile(dom, digest)
+
+    result = {
+        "metric": METRIC,
+        "value": round(n * vb / t_on / 1e9, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_on * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.size}^3 FP32 Gaussian random field P(k)~k^-3 with a 1% "
+                               f"tanh front, value-range-relative eb {args.eb:g}, block 6x6x6, "
+                               f"ABFT on; one compress + one decompress per step",
+                   "field_bytes": n * vb, "eb_abs": rep["eb_abs"]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "algorithmic_bytes_per_launch": int(alg),
+                     "avg_launch_ms": round(avg_s * 1e3, 4)},
+        "abft_off": {"value": round(n * vb / t_off / 1e9, 3), "ms_per_step": round(t_off * 1e3, 4),
+                     "abft_overhead": round((t_on - t_off) / t_off, 4),
+                     "stream_bytes": int(stream_off.numel())},
+        "compress_gbs": round(n * vb / (ms_c / 1e3) / 1e9, 3) if ms_c else None,
+        "decompress_gbs": round(n * vb / (ms_d / 1e3) / 1e9, 3) if ms_d else None,
+        "compression_ratio": round(n * vb / stream_bytes, 4),
+        "max_abs_err": err,
+        "phases_ms_per_step": {p: round(v[0] / args.steps, 4) for p, v in phases.items() if v[1]},
+        "source_digest": digest,
+    }
+
+    if not args.no_extras:
+        extras = {}
+        for eb in (1e-2, 1e-4):
+            for abft in (True, False):
+                t, s, _, r = run_steps(codec, xd, block, eb, abft, 2, sync)
+                extras[f"eb{eb:g}_abft{int(abft)}"] = {
+                    "gbs": round(n * vb / t / 1e9, 3), "cr": round(n * vb / int(s.numel()), 4)}
+        result["eb_sweep"] = extras
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        result["cpu_baseline"] = cpu_baseline(x, block, args.eb)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -178,6 +178,24 @@ int sdcsz_decompress_region(const void *d_stream, uint64_t stream_size, const ui
 /* Human-readable name of a return code. */
 const char *sdcsz_strerror(int code);
 
+/*
+ * Kernel-phase timing (instrumentation).  When enabled, every call records
+ * HIP events on its stream around each kernel phase and accumulates the
+ * elapsed device time per phase.  Process-wide state; not thread safe.
+ * Phases: 0 range, 1 predict+quantize (per block), 2 code faults,
+ * 3 code check+size, 4 compression scan, 5 encode+assemble,
+ * 6 decompression scan, 7 decode+check (per block).
+ */
+#define SDCSZ_N_PHASES 8
+typedef struct {
+  double ms[SDCSZ_N_PHASES];       /* accumulated device milliseconds */
+  uint64_t launches[SDCSZ_N_PHASES];
+} sdcsz_timing;
+/* on != 0 enables and clears the accumulators; 0 disables. */
+void sdcsz_timing_enable(int on);
+void sdcsz_timing_read(sdcsz_timing *h_out);
+const char *sdcsz_phase_name(int phase);
+
 #ifdef __cplusplus
 }
 #endif

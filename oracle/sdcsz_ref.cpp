@@ -219,10 +219,15 @@ T lorenzo(const T *r, const uint64_t n[3], uint32_t ndim, uint64_t i, uint64_t j
   int64_t I = (int64_t)i, J = (int64_t)j, K = (int64_t)k;
   if (ndim == 1) return at(I, J, K - 1);
   if (ndim == 2) return (at(I, J - 1, K) + at(I, J, K - 1)) - at(I, J - 1, K - 1);
+  /* inclusion-exclusion over the 7 earlier neighbours, grouped as the
+   * current neighbour c plus the difference of the two 2D face stencils
+   * u(k) = (a + b) - d and u(k-1) = (e + f) - g */
   T a = at(I - 1, J, K), b = at(I, J - 1, K), c = at(I, J, K - 1);
   T d = at(I - 1, J - 1, K), e = at(I - 1, J, K - 1), f = at(I, J - 1, K - 1);
   T g = at(I - 1, J - 1, K - 1);
-  return (((((a + b) + c) - d) - e) - f) + g;
+  T u = (a + b) - d;
+  T u_prev = (e + f) - g;
+  return c + (u - u_prev);
 }
 
 /* Sampling cost in units of the error bound, saturated (Algorithm 1, second
@@ -233,11 +238,14 @@ template <typename T> uint32_t sample_cost(T diff, T inv_e) {
   return 65536;
 }
 
-/* Sample points: the block's space diagonals (4 in 3D, 2 in 2D), every point
- * in 1D; duplicates removed. */
-void sample_points(const uint64_t n[3], uint32_t ndim, std::vector<uint64_t> &out) {
+/* Sample points: the space diagonals of the block as configured (4 in 3D,
+ * 2 in 2D; every point in 1D), keeping the points that fall inside the
+ * block's actual extents (partial blocks at the field's upper edges);
+ * duplicates removed. */
+void sample_points(const uint64_t bs[3], const uint64_t n[3], uint32_t ndim, std::vector<uint64_t> &out) {
   out.clear();
   auto push = [&](uint64_t i, uint64_t j, uint64_t k) {
+    if (i >= n[0] || j >= n[1] || k >= n[2]) return;
     uint64_t p = (i * n[1] + j) * n[2] + k;
     for (uint64_t q : out)
       if (q == p) return;
@@ -248,19 +256,19 @@ void sample_points(const uint64_t n[3], uint32_t ndim, std::vector<uint64_t> &ou
     return;
   }
   if (ndim == 2) {
-    uint64_t m = std::min(n[1], n[2]);
+    uint64_t m = std::min(bs[1], bs[2]);
     for (uint64_t t = 0; t < m; t++) {
       push(0, t, t);
-      push(0, t, n[2] - 1 - t);
+      push(0, t, bs[2] - 1 - t);
     }
     return;
   }
-  uint64_t m = std::min(n[0], std::min(n[1], n[2]));
+  uint64_t m = std::min(bs[0], std::min(bs[1], bs[2]));
   for (uint64_t t = 0; t < m; t++) {
     push(t, t, t);
-    push(t, t, n[2] - 1 - t);
-    push(t, n[1] - 1 - t, t);
-    push(n[0] - 1 - t, t, t);
+    push(t, t, bs[2] - 1 - t);
+    push(t, bs[1] - 1 - t, t);
+    push(bs[0] - 1 - t, t, t);
   }
 }
 
@@ -590,7 +598,7 @@ int compress_impl(const T *in, const ref_params *p, const Geometry &g, uint8_t *
         for (uint64_t k = 0; k < bb.n[2]; k++) xb[q++] = X[field_index(g, bb, i, j, k)];
     T c[3];
     for (int a = 0; a < 3; a++) c[a] = (T)(0.5 * (double)(bb.n[a] - 1));
-    sample_points(bb.n, nd, samples);
+    sample_points(g.b, bb.n, nd, samples);
     uint64_t e_lor = samples.size(), e_reg = 0;  /* one bound of slack per
         sample for the reconstructed (not original) neighbours Lorenzo uses */
     for (uint64_t sp : samples) {

@@ -16,6 +16,7 @@ constexpr uint32_t kMaxLen = 24;     // longest Huffman codeword
 constexpr uint64_t kHeader = 192;    // fixed stream header bytes
 constexpr uint32_t kMaxBlockPts = 8192;
 constexpr uint32_t kMaxPatches = 8;  // fault-plan entries per block and call
+constexpr uint32_t kMaxRedo = 4096;  // blocks re-run after a detected mismatch
 
 // Counter slots (u64) in the device report area.
 enum {
@@ -35,6 +36,7 @@ struct Geo {
   uint32_t rem[3];  // extent of the last block along each axis
   uint32_t ndim;    // dimensionality of the block as configured (1..3)
   uint32_t bpts;    // points of a full block
+  uint32_t groups;  // 4-code groups per block in the code staging layout
   uint64_t n_blocks;
   uint64_t n_values;
 };
@@ -44,7 +46,8 @@ struct EbDev {
   double eb_abs;
   double q, inv, inv_e;    // 2eb, 1/(2eb), 1/eb
   float qf, invf, inv_ef;  // the same rounded to FP32
-  uint32_t pad;
+  float lo, hi;            // FP32 |x - r| <= lo passes, > hi fails the bound;
+                           // in between the double comparison decides
 };
 
 // Regression constants per partial-block pattern (bit a set: axis a partial).
@@ -63,7 +66,7 @@ struct PlanDev {
 
 // Per-call device areas of compression (inside the caller's workspace).
 struct CompWork {
-  uint16_t *codes;     // bpts per block, C order inside the block
+  uint16_t *codes;     // interleaved staging layout (see code_index)
   void *vals;          // bpts values per block: outliers, packed in order
   void *recon;         // bpts values per block (generic kernels only)
   uint32_t *meta;      // per block: n_outliers << 1 | is_regression
@@ -81,6 +84,8 @@ struct CompWork {
   uint64_t *scan_part; // 3 per scan chunk
   void *range_part;    // 2 doubles + flag per range work-group
   EbDev *eb;
+  uint32_t *redo_n;    // blocks queued for a re-run
+  uint64_t *redo;      // kMaxRedo block ids
 };
 
 // Decoder tables built from the stream's codebook (canonical code).

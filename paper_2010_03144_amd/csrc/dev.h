@@ -13,6 +13,8 @@ template <> struct Wd<float> {
   __device__ static inline float join(const uint32_t *w) { return __uint_as_float(w[0]); }
   __device__ static inline uint32_t sum(float v) { return __float_as_uint(v); }
   __device__ static inline bool same(float a, float b) { return __float_as_uint(a) == __float_as_uint(b); }
+  // non-zero iff the bit patterns differ
+  __device__ static inline uint32_t diff(float a, float b) { return __float_as_uint(a) ^ __float_as_uint(b); }
   __device__ static inline float flip(float v, uint32_t bit) {
     return __uint_as_float(__float_as_uint(v) ^ (1u << (bit & 31)));
   }
@@ -31,6 +33,10 @@ template <> struct Wd<double> {
   __device__ static inline uint64_t sum(double v) {
     uint64_t u = (uint64_t)__double_as_longlong(v);
     return (u & 0xFFFFFFFFull) + (u >> 32);
+  }
+  __device__ static inline uint32_t diff(double a, double b) {
+    uint64_t x = (uint64_t)__double_as_longlong(a) ^ (uint64_t)__double_as_longlong(b);
+    return (uint32_t)x | (uint32_t)(x >> 32);
   }
   __device__ static inline bool same(double a, double b) {
     return __double_as_longlong(a) == __double_as_longlong(b);
@@ -120,6 +126,18 @@ __device__ inline int locate_repair(uint64_t s2, uint64_t i2, uint64_t s, uint64
   *jout = (uint64_t)j;
   *val = (uint32_t)rep;
   return 1;
+}
+
+// ---- code staging layout --------------------------------------------------
+// Codes of 64 consecutive blocks are interleaved in groups of 4: the 4 codes
+// q..q+3 (q a multiple of 4, q the point's index in the block padded to the
+// configured block shape) of block blk sit in one 8-byte vector, and the 64
+// blocks of a tile store their vectors for group q/4 contiguously (512 B).
+__device__ inline uint64_t code_index(uint64_t blk, uint32_t q, uint32_t groups) {
+  return (((blk >> 6) * groups + (q >> 2)) * 64 + (blk & 63)) * 4 + (q & 3);
+}
+__device__ inline uint32_t padded_index(const Geo &g, uint32_t i, uint32_t j, uint32_t k) {
+  return (i * g.b[1] + j) * g.b[2] + k;
 }
 
 __device__ inline void count(unsigned long long *cnt, int slot, unsigned long long v = 1) {

@@ -19,6 +19,54 @@ namespace {
     if ((x) != hipSuccess) return SDCSZ_EHIP; \
   } while (0)
 
+// ---------------------------------------------------------------------------
+// kernel-phase timing with HIP events on the call's stream
+// ---------------------------------------------------------------------------
+enum { PH_RANGE, PH_PREDICT, PH_CODEFAULT, PH_CHECK, PH_SCAN_C, PH_ENCODE, PH_SCAN_D, PH_DECODE };
+const char *kPhaseNames[SDCSZ_N_PHASES] = {"range",      "predict_quantize", "code_faults", "code_check",
+                                           "scan_compress", "encode",        "scan_decompress", "decode"};
+
+struct PhaseTimer {
+  bool on = false;
+  bool made = false;
+  hipEvent_t ev[SDCSZ_N_PHASES][2];
+  bool pending[SDCSZ_N_PHASES] = {};
+  double ms[SDCSZ_N_PHASES] = {};
+  uint64_t launches[SDCSZ_N_PHASES] = {};
+  void begin(int ph, hipStream_t st) {
+    if (!on) return;
+    if (!made) {
+      for (int i = 0; i < SDCSZ_N_PHASES; i++)
+        for (int j = 0; j < 2; j++)
+          if (hipEventCreate(&ev[i][j]) != hipSuccess) {
+            on = false;
+            return;
+          }
+      made = true;
+    }
+    (void)hipEventRecord(ev[ph][0], st);
+  }
+  void end(int ph, hipStream_t st) {
+    if (!on || !made) return;
+    (void)hipEventRecord(ev[ph][1], st);
+    pending[ph] = true;
+  }
+  void resolve() {
+    for (int i = 0; i < SDCSZ_N_PHASES; i++)
+      if (pending[i]) {
+        float t = 0;
+        (void)hipEventSynchronize(ev[i][1]);
+        if (hipEventElapsedTime(&t, ev[i][0], ev[i][1]) == hipSuccess) {
+          ms[i] += t;
+          launches[i]++;
+        }
+        pending[i] = false;
+      }
+  }
+};
+PhaseTimer g_timer;
+
+uint32_t grid_for(uint64_t n, uint32_t per) { return (uint32_t)std::max<uint64_t>(1, (n + per - 1) / per); }
 uint64_t a256(uint64_t v) { return (v + 255) & ~255ull; }
 uint64_t a8(uint64_t v) { return (v + 7) & ~7ull; }
 uint32_t vbytes(uint32_t dtype) { return dtype == SDCSZ_F32 ? 4u : 8u; }
@@ -42,6 +90,7 @@ bool geometry(uint32_t ndim, const uint64_t *dims, const uint32_t *block, Geo *g
   uint64_t bp = (uint64_t)g->b[0] * g->b[1] * g->b[2];
   if (bp > kMaxBlockPts) return false;
   g->bpts = (uint32_t)bp;
+  g->groups = (uint32_t)((bp + 3) / 4);
   g->ndim = ndim;
   g->n_values = g->d[0] * g->d[1] * g->d[2];
   if (g->n_values >= (1ull << 32)) return false;
@@ -132,7 +181,7 @@ template <typename T> RegTab<T> reg_table(const Geo &g) {
 // ---------------------------------------------------------------------------
 struct CompLayout {
   uint64_t cnt, eb, range, hist, enc, codes, vals, recon, meta, words, coef, sum_dc, sum_q, isum_q;
-  uint64_t off_pay, off_out, off_coef, scan, plan, bits, total;
+  uint64_t off_pay, off_out, off_coef, scan, plan, bits, redo_n, redo, plan_blocks, total;
 };
 
 CompLayout comp_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
@@ -150,7 +199,7 @@ CompLayout comp_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
   L.range = take(16ull * kRangeBlocks);
   L.hist = take(4 * 65536);
   L.enc = take(4 * 65536);
-  L.codes = take(2 * slots);
+  L.codes = take(2ull * 256 * g.groups * ((nb + 63) / 64));
   L.vals = take(vb * slots);
   L.recon = take(vb * slots);
   L.meta = take(4 * nb);
@@ -165,8 +214,49 @@ CompLayout comp_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
   L.scan = take(24 * chunks);
   L.plan = take(sizeof(sdcsz_fault) * (uint64_t)std::max<uint32_t>(nfaults, 1));
   L.bits = take(4 * (nb / 32 + 1));
+  L.redo_n = take(4);
+  L.redo = take(8ull * kMaxRedo);
+  L.plan_blocks = take(8ull * std::max<uint32_t>(nfaults, 1));
   L.total = at;
   return L;
+}
+
+// Specialised kernel for this block shape, if there is one.  Its lanes
+// address the input with 32-bit byte offsets from the wave's lowest block,
+// so it takes fields below 2 GiB.
+bool fast_shape(const Geo &g, uint32_t vb) {
+  if (!(g.ndim == 3 && g.b[0] == 6 && g.b[1] == 6 && g.b[2] == 6)) return false;
+  return g.n_values * vb < (1ull << 31);
+}
+
+template <typename T, bool ABFT>
+void launch_fast(const T *in, const Geo &g, const RegTab<T> &rt, const PlanDev &pd, const CompWork &w,
+                 uint32_t predictor, const uint64_t *plan_blocks, uint32_t n_plan_blocks, hipStream_t st) {
+  if (n_plan_blocks)
+    hipLaunchKernelGGL(k_compress_list<T>, dim3(grid_for(n_plan_blocks, 64)), dim3(64), 0, st, in, g, rt, pd, w,
+                       ABFT ? 1u : 0u, predictor, plan_blocks, n_plan_blocks);
+  bool part[3];
+  Launch full, shell;
+  std::memset(&full, 0, sizeof(full));
+  for (int a = 0; a < 3; a++) {
+    part[a] = g.rem[a] != g.b[a];
+    full.nf[a] = g.nb[a] - (part[a] ? 1 : 0);
+  }
+  shell = full;
+  full.mode = 0;
+  full.count = (uint64_t)full.nf[0] * full.nf[1] * full.nf[2];
+  shell.mode = 1;
+  shell.s2 = part[2] ? (uint64_t)g.nb[0] * g.nb[1] : 0;
+  shell.s1 = part[1] ? (uint64_t)g.nb[0] * full.nf[2] : 0;
+  const uint64_t s0 = part[0] ? (uint64_t)full.nf[1] * full.nf[2] : 0;
+  shell.count = shell.s2 + shell.s1 + s0;
+  if (full.count)
+    hipLaunchKernelGGL((k_compress_fast<T, 3, 6, 6, 6, true, ABFT>), dim3(grid_for(full.count, 256)), dim3(256), 0,
+                       st, in, g, rt, pd, w, predictor, full);
+  if (shell.count)
+    hipLaunchKernelGGL((k_compress_fast<T, 3, 6, 6, 6, false, ABFT>), dim3(grid_for(shell.count, 256)), dim3(256),
+                       0, st, in, g, rt, pd, w, predictor, shell);
+  hipLaunchKernelGGL(k_redo<T>, dim3(1), dim3(64), 0, st, in, g, rt, pd, w, ABFT ? 1u : 0u, predictor);
 }
 
 struct DecLayout {
@@ -384,7 +474,6 @@ void fill_report(sdcsz_report *r, const unsigned long long *cnt, uint64_t nb) {
   }
 }
 
-uint32_t grid_for(uint64_t n, uint32_t per) { return (uint32_t)std::max<uint64_t>(1, (n + per - 1) / per); }
 
 // upload a sorted plan and its per-block bitmap
 int upload_plan(const std::vector<sdcsz_fault> &pl, uint64_t nb, uint8_t *ws, uint64_t off_plan,
@@ -445,6 +534,8 @@ int compress_t(const void *d_in, const sdcsz_params *p, const Geo &g, uint8_t *d
   w.scan_part = (uint64_t *)(ws + L.scan);
   w.range_part = ws + L.range;
   w.eb = (EbDev *)(ws + L.eb);
+  w.redo_n = (uint32_t *)(ws + L.redo_n);
+  w.redo = (uint64_t *)(ws + L.redo);
 
   std::vector<uint32_t> bits_host;
   PlanDev pd;
@@ -454,6 +545,7 @@ int compress_t(const void *d_in, const sdcsz_params *p, const Geo &g, uint8_t *d
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, w.cnt, (uint64_t)C_N);
   hipLaunchKernelGGL(k_zero_u32, dim3(256), dim3(256), 0, st, w.hist, (uint64_t)65536);
   uint32_t nparts = 0;
+  g_timer.begin(PH_RANGE, st);
   if (p->eb_mode == SDCSZ_REL && g.n_values) {
     nparts = (uint32_t)std::min<uint64_t>(kRangeBlocks, grid_for(g.n_values, kRangeThreads * 8));
     hipLaunchKernelGGL(k_range<T>, dim3(nparts), dim3(kRangeThreads), 0, st, (const T *)d_in, g.n_values,
@@ -461,16 +553,37 @@ int compress_t(const void *d_in, const sdcsz_params *p, const Geo &g, uint8_t *d
   }
   hipLaunchKernelGGL(k_consts, dim3(1), dim3(64), 0, st, (const double *)w.range_part, nparts, p->eb_mode,
                      p->eb, w.eb);
+  g_timer.end(PH_RANGE, st);
   HIPCHK(hipGetLastError());
 
   if (g.n_blocks) {
     const RegTab<T> rt = reg_table<T>(g);
-    hipLaunchKernelGGL(k_compress_generic<T>, dim3(grid_for(g.n_blocks, 64)), dim3(64), 0, st,
-                       (const T *)d_in, g, rt, pd, w, p->abft, p->predictor);
+    g_timer.begin(PH_PREDICT, st);
+    if (fast_shape(g, sizeof(T))) {
+      // the distinct blocks the plan names run through the generic routine
+      std::vector<uint64_t> pb;
+      for (auto &f : plan)
+        if (pb.empty() || pb.back() != f.block) pb.push_back(f.block);
+      const uint64_t *d_pb = (const uint64_t *)(ws + L.plan_blocks);
+      if (!pb.empty())
+        HIPCHK(hipMemcpyAsync(ws + L.plan_blocks, pb.data(), 8 * pb.size(), hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, w.redo_n, (uint64_t)1);
+      if (p->abft) launch_fast<T, true>((const T *)d_in, g, rt, pd, w, p->predictor, d_pb, (uint32_t)pb.size(), st);
+      else launch_fast<T, false>((const T *)d_in, g, rt, pd, w, p->predictor, d_pb, (uint32_t)pb.size(), st);
+      HIPCHK(hipStreamSynchronize(st));  // keeps pb alive until its copy is done
+    } else {
+      hipLaunchKernelGGL(k_compress_generic<T>, dim3(grid_for(g.n_blocks, 64)), dim3(64), 0, st,
+                         (const T *)d_in, g, rt, pd, w, p->abft, p->predictor);
+    }
+    g_timer.end(PH_PREDICT, st);
     HIPCHK(hipGetLastError());
     bool any_code = false;
     for (auto &f : plan) any_code |= f.target == SDCSZ_T_CODE;
-    if (any_code) hipLaunchKernelGGL(k_code_faults, dim3(1), dim3(64), 0, st, pd, g, w.codes, w.cnt);
+    if (any_code) {
+      g_timer.begin(PH_CODEFAULT, st);
+      hipLaunchKernelGGL(k_code_faults, dim3(1), dim3(64), 0, st, pd, g, w.codes, w.cnt);
+      g_timer.end(PH_CODEFAULT, st);
+    }
   }
 
   // Huffman code over the whole field's codes (host)
@@ -492,9 +605,13 @@ int compress_t(const void *d_in, const sdcsz_params *p, const Geo &g, uint8_t *d
   HIPCHK(hipMemcpyAsync(w.enc, enc.data(), 4 * 65536, hipMemcpyHostToDevice, st));
 
   if (g.n_blocks) {
+    g_timer.begin(PH_CHECK, st);
     hipLaunchKernelGGL(k_codes_check, dim3(grid_for(g.n_blocks, 256)), dim3(256), 0, st, g, w, p->abft);
+    g_timer.end(PH_CHECK, st);
     ScanSrc src{w.words, w.meta, 1};
+    g_timer.begin(PH_SCAN_C, st);
     rc = launch_scan(src, g.n_blocks, w.scan_part, w.off_pay, w.off_out, w.off_coef, st);
+    g_timer.end(PH_SCAN_C, st);
     if (rc) return rc;
   }
   uint64_t tot_pay = 0;
@@ -556,9 +673,12 @@ int compress_t(const void *d_in, const sdcsz_params *p, const Geo &g, uint8_t *d
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t *)(d_out + h.off_payload - 8), 2);
   if (h.total > h.off_payload)
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t *)(d_out + h.total - 8), 2);
+  g_timer.begin(PH_ENCODE, st);
   if (g.n_blocks) hipLaunchKernelGGL(k_encode<T>, dim3(grid_for(g.n_blocks, 256)), dim3(256), 0, st, g, w, d_out, h);
+  g_timer.end(PH_ENCODE, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
+  g_timer.resolve();
   return SDCSZ_OK;
 }
 
@@ -633,7 +753,9 @@ int decode_t(const uint8_t *d_s, Opened &o, T *d_out, uint32_t mode, const Regio
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, w.cnt, (uint64_t)C_N);
   const uint32_t *table = (const uint32_t *)(d_s + h.off_table);
   ScanSrc src{table, table + 1, 2};
+  g_timer.begin(PH_SCAN_D, st);
   rc = launch_scan(src, g.n_blocks, w.scan_part, w.off_pay, w.off_out, w.off_coef, st);
+  g_timer.end(PH_SCAN_D, st);
   if (rc) return rc;
   uint64_t tot_pay = 0;
   uint32_t tot_out = 0, tot_coef = 0;
@@ -643,13 +765,16 @@ int decode_t(const uint8_t *d_s, Opened &o, T *d_out, uint32_t mode, const Regio
   HIPCHK(hipStreamSynchronize(st));
   if (tot_pay != h.payload_words || tot_out != h.n_outliers || tot_coef != h.n_regression) return SDCSZ_EFORMAT;
   if (g.n_blocks) {
+    g_timer.begin(PH_DECODE, st);
     hipLaunchKernelGGL(k_decode_generic<T>, dim3(grid_for(g.n_blocks, 64)), dim3(64), 0, st, d_s, h, g, w, pd,
                        d_out, mode, reg);
+    g_timer.end(PH_DECODE, st);
     HIPCHK(hipGetLastError());
   }
   unsigned long long cnt[C_N];
   HIPCHK(hipMemcpyAsync(cnt, w.cnt, sizeof(cnt), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  g_timer.resolve();
   sdcsz_report rep;
   fill_report(&rep, cnt, g.n_blocks);
   rep.eb_abs = h.eb_abs;
@@ -678,6 +803,27 @@ const char *sdcsz_strerror(int code) {
     case SDCSZ_EHIP: return "HIP runtime error";
     default: return "unknown error";
   }
+}
+
+void sdcsz_timing_enable(int on) {
+  for (int i = 0; i < SDCSZ_N_PHASES; i++) {
+    g_timer.ms[i] = 0;
+    g_timer.launches[i] = 0;
+    g_timer.pending[i] = false;
+  }
+  g_timer.on = on != 0;
+}
+
+void sdcsz_timing_read(sdcsz_timing *h_out) {
+  if (!h_out) return;
+  for (int i = 0; i < SDCSZ_N_PHASES; i++) {
+    h_out->ms[i] = g_timer.ms[i];
+    h_out->launches[i] = g_timer.launches[i];
+  }
+}
+
+const char *sdcsz_phase_name(int phase) {
+  return phase >= 0 && phase < SDCSZ_N_PHASES ? kPhaseNames[phase] : "unknown";
 }
 
 uint64_t sdcsz_max_compressed_size(const sdcsz_params *p) {

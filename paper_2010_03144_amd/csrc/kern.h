@@ -20,6 +20,18 @@ constexpr uint32_t kScanThreads = 256;
 constexpr uint32_t kScanItems = 8;
 constexpr uint32_t kScanChunk = kScanThreads * kScanItems;
 constexpr uint32_t kRangeThreads = 256;
+constexpr uint32_t kHistWin = 2048;  // codes counted in LDS around the radius
+
+// Work of one specialised compression launch: the sub-grid of full blocks
+// (mode 0), or the shell of partial blocks at the upper edges (mode 1: the
+// slab of blocks partial along the fastest axis, then the middle, then the
+// slowest, each excluding the earlier slabs).
+struct Launch {
+  uint32_t mode;
+  uint32_t nf[3];  // full blocks per axis
+  uint64_t s2, s1; // sizes of the first two shell slabs
+  uint64_t count;  // lanes of work
+};
 constexpr uint32_t kRangeBlocks = 2048;
 
 __global__ void k_zero_u64(unsigned long long *p, uint64_t n);
@@ -34,6 +46,16 @@ __global__ void k_scan3(ScanSrc src, uint64_t n, const uint64_t *part, uint64_t 
                         uint32_t *off_out, uint32_t *off_coef);
 template <typename T>
 __global__ void k_encode(Geo g, CompWork w, uint8_t *out, Header h);
+
+template <typename T, int ND, int B0, int B1, int B2, bool FULL, bool ABFT>
+__global__ void k_compress_fast(const T *in, Geo g, RegTab<T> rt, PlanDev plan, CompWork w, uint32_t predictor,
+                                Launch L);
+template <typename T>
+__global__ void k_compress_list(const T *in, Geo g, RegTab<T> rt, PlanDev plan, CompWork w, uint32_t abft,
+                                uint32_t predictor, const uint64_t *list, uint32_t n);
+template <typename T>
+__global__ void k_redo(const T *in, Geo g, RegTab<T> rt, PlanDev plan, CompWork w, uint32_t abft,
+                       uint32_t predictor);
 
 template <typename T>
 __global__ void k_compress_generic(const T *in, Geo g, RegTab<T> rt, PlanDev plan, CompWork w,

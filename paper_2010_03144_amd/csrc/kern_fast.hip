@@ -1,0 +1,503 @@
+// kern_fast.hip -- block-shape-specialised compression: one lane per block.
+//
+// Block edges are template parameters, so the block's values sit in
+// registers with compile-time indexing: a fully unrolled first pass (input
+// checksums, regression sums, costs at the diagonal samples) and a plane loop
+// that keeps the previous reconstructed plane in registers for the Lorenzo
+// recursion.  The input is read twice (first pass, prediction pass); the
+// prediction pass recomputes the input checksums over exactly the words it
+// predicts from, which is Algorithm 1's detection step at the point of use.
+// Blocks named in a fault plan take the generic per-block routine.  A block
+// whose checksums or duplicated computations disagree (a real corruption) is
+// queued and recomputed by k_redo after the launch.
+#include "block_generic.h"
+#include "kern.h"
+
+namespace sdcsz {
+
+namespace {
+
+constexpr uint32_t kHistLo = kRadius - kHistWin / 2;
+// reasons a block is queued for a re-run (high byte of the queue entry)
+constexpr uint64_t kWhyInput = 1, kWhyCoef = 2, kWhyPred = 4, kWhyRecon = 8;
+
+__device__ inline uint64_t map_block(const Geo &g, const Launch &L, uint64_t idx) {
+  uint64_t c0, c1, c2;
+  if (L.mode == 0) {
+    c2 = idx % L.nf[2];
+    uint64_t t = idx / L.nf[2];
+    c1 = t % L.nf[1];
+    c0 = t / L.nf[1];
+  } else if (idx < L.s2) {  // slab of blocks partial along the fastest axis
+    c2 = g.nb[2] - 1;
+    c1 = idx % g.nb[1];
+    c0 = idx / g.nb[1];
+  } else if (idx < L.s2 + L.s1) {  // partial along the middle axis
+    uint64_t t = idx - L.s2;
+    c1 = g.nb[1] - 1;
+    c2 = t % L.nf[2];
+    c0 = t / L.nf[2];
+  } else {  // partial along the slowest axis
+    uint64_t t = idx - L.s2 - L.s1;
+    c0 = g.nb[0] - 1;
+    c2 = t % L.nf[2];
+    c1 = t / L.nf[2];
+  }
+  return (c0 * g.nb[1] + c1) * g.nb[2] + c2;
+}
+
+// an opaque copy: the compiler must assume a different value, so a
+// computation on it is carried out again rather than reused
+template <typename T> __device__ inline T launder(T v) {
+  __asm__ volatile("" : "+v"(v));
+  return v;
+}
+
+// Compiler-only barrier that consumes a row's results: the row's work stays
+// before it and the next row's loads after it, so loads run one row ahead of
+// their use instead of all at once (which would hold the whole block).
+template <typename V> __device__ inline void pin(V &v) { __asm__ volatile("" : "+v"(v)); }
+template <typename... V> __device__ inline void row_fence(V &...v) {
+  (pin(v), ...);
+  __asm__ volatile("" ::: "memory");
+}
+
+// point (i,j,k) lies on a diagonal of the configured block (3D: the four
+// space diagonals; 2D: the two diagonals)
+template <int ND, int B0, int B1, int B2> constexpr bool is_sample(int i, int j, int k) {
+  if (ND == 2) {
+    constexpr int m = B1 < B2 ? B1 : B2;
+    return j < m && (k == j || k == B2 - 1 - j);
+  }
+  constexpr int m = B0 < B1 ? (B0 < B2 ? B0 : B2) : (B1 < B2 ? B1 : B2);
+  return (i < m && j == i && k == i) || (i < m && j == i && k == B2 - 1 - i) ||
+         (i < m && k == i && j == B1 - 1 - i) || (j < m && k == j && i == B0 - 1 - j);
+}
+
+// slot of a sample point among the samples in C order
+template <int ND, int B0, int B1, int B2> constexpr int sample_slot(int i0, int j0, int k0) {
+  int n = 0;
+  for (int i = 0; i < B0; i++)
+    for (int j = 0; j < B1; j++)
+      for (int k = 0; k < B2; k++) {
+        if (i == i0 && j == j0 && k == k0) return n;
+        if (is_sample<ND, B0, B1, B2>(i, j, k)) n++;
+      }
+  return n;
+}
+
+// Checksum-word accumulation: S = sum of the words, Q = sum of the running
+// sums; the paper's isum = sum_j j * w_j (0-based j) is then n_words*S - Q.
+template <typename T> struct Ck;
+template <> struct Ck<float> {
+  __device__ static inline void add(float v, uint64_t &S, uint64_t &Q) {
+    S += __float_as_uint(v);
+    Q += S;
+  }
+};
+template <> struct Ck<double> {
+  __device__ static inline void add(double v, uint64_t &S, uint64_t &Q) {
+    uint64_t u = (uint64_t)__double_as_longlong(v);
+    S += u & 0xFFFFFFFFull;
+    Q += S;
+    S += u >> 32;
+    Q += S;
+  }
+};
+
+// The double-precision check of the bound, with an FP32 shortcut taken only
+// where it provably agrees with the double comparison.
+template <typename T> struct Bound;
+template <> struct Bound<float> {
+  __device__ static inline bool ok(float x, float r, const EbDev &e) {
+    const float d = fabsf(x - r);
+    const bool fast = d <= e.lo;
+    const bool maybe = !fast && !(d > e.hi);  // NaN and the thin band around eb
+    if (__builtin_expect(__ballot(maybe) != 0, 0)) {
+      const bool exact = fabs((double)x - (double)r) <= e.eb_abs;
+      return fast || (maybe && exact);
+    }
+    return fast;
+  }
+};
+template <> struct Bound<double> {
+  __device__ static inline bool ok(double x, double r, const EbDev &e) { return fabs(x - r) <= e.eb_abs; }
+};
+
+}  // namespace
+
+template <typename T, int ND, int B0, int B1, int B2, bool FULL, bool ABFT>
+__global__ void __launch_bounds__(256)
+k_compress_fast(const T *__restrict__ in, Geo g, RegTab<T> rt, PlanDev plan, CompWork w, uint32_t predictor,
+                Launch L) {
+  constexpr int PL = B1 * B2;  // points per plane
+  static_assert(PL % 4 == 0, "a plane must fill whole 4-code groups");
+  constexpr int NS = sample_slot<ND, B0, B1, B2>(B0, 0, 0);
+  __shared__ uint32_t hist[kHistWin];
+  for (uint32_t t = threadIdx.x; t < kHistWin; t += blockDim.x) hist[t] = 0;
+  __syncthreads();
+  uint32_t hot = 0;
+
+  const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool active = idx < L.count;
+  const uint64_t blk = map_block(g, L, active ? idx : L.count - 1);
+  // wave-uniform base of the input (the wave's lowest block origin); lanes
+  // address it with 32-bit byte offsets (the host takes this kernel only for
+  // fields below 2 GiB, so every offset fits)
+  const Box bx = box_of(g, blk);
+  const uint64_t org = fidx(g, bx, 0, 0, 0);
+  uint64_t omin = org;
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)omin, off);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(omin >> 32), off);
+    const uint64_t o = ((uint64_t)hi << 32) | lo;
+    omin = o < omin ? o : omin;
+  }
+  const uint64_t org0 = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(omin >> 32)) << 32) |
+                        (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)omin);
+  const char *wbase = (const char *)(in + org0);
+  const uint32_t loff = (uint32_t)((org - org0) * sizeof(T));
+  if (active && plan_hit(plan, blk)) active = false;  // done by k_compress_list
+  if (active) {
+    const EbDev eb = *w.eb;
+    const T q = EbSel<T>::q(eb), inv = EbSel<T>::inv(eb), inv_e = EbSel<T>::inv_e(eb);
+    const uint32_t n0 = FULL ? B0 : bx.n[0], n1 = FULL ? B1 : bx.n[1], n2 = FULL ? B2 : bx.n[2];
+    const uint32_t pat = FULL ? 0 : bx.pat;
+    const T c0 = rt.c[pat][0], c1 = rt.c[pat][1], c2 = rt.c[pat][2];
+    const uint32_t PSB = (uint32_t)(g.d[1] * g.d[2] * sizeof(T)), RSB = (uint32_t)(g.d[2] * sizeof(T));
+    auto valid = [&](int i, int j, int k) -> bool {
+      return FULL || ((uint32_t)i < n0 && (uint32_t)j < n1 && (uint32_t)k < n2);
+    };
+    auto ld = [&](int i, int j, int k) -> T {
+      if (FULL) return *(const T *)(wbase + (loff + (uint32_t)i * PSB + (uint32_t)j * RSB) + k * sizeof(T));
+      const uint32_t ii = min((uint32_t)i, n0 - 1), jj = min((uint32_t)j, n1 - 1), kk = min((uint32_t)k, n2 - 1);
+      const T v = *(const T *)(wbase + (loff + ii * PSB + jj * RSB + kk * (uint32_t)sizeof(T)));
+      return valid(i, j, k) ? v : (T)0;
+    };
+    const uint64_t nwords = (uint64_t)n0 * n1 * n2 * Wd<T>::per;
+
+    // ---- first pass: input checksums, regression sums, Lorenzo costs ------
+    T x[B0][B1][B2];
+    T sx[NS > 0 ? NS : 1];
+    uint64_t S1 = 0, Q1 = 0;
+    uint32_t e_lor = 0;
+    T S0 = 0, Sa0 = 0, Sa1 = 0, Sa2 = 0;
+#pragma unroll
+    for (int k = 0; k < B2; k++) x[0][0][k] = ld(0, 0, k);
+#pragma unroll
+    for (int i = 0; i < B0; i++) {
+      T P = 0, A = 0, Bv = 0;
+      T D[B2];
+#pragma unroll
+      for (int k = 0; k < B2; k++) D[k] = 0;
+#pragma unroll
+      for (int j = 0; j < B1; j++) {
+        T R = 0;
+        // issue the next row's loads, then work on this row
+        const int jn = j + 1 < B1 ? j + 1 : 0, in_ = j + 1 < B1 ? i : i + 1;
+        if (in_ < B0) {
+#pragma unroll
+          for (int k = 0; k < B2; k++) x[in_][jn][k] = ld(in_, jn, k);
+        }
+#pragma unroll
+        for (int k = 0; k < B2; k++) {
+          if (valid(i, j, k)) {
+            if (ABFT) Ck<T>::add(x[i][j][k], S1, Q1);
+            R = R + x[i][j][k];
+            D[k] = D[k] + x[i][j][k];
+          }
+          if (is_sample<ND, B0, B1, B2>(i, j, k)) {
+            // Lorenzo on the original values (zero outside the block)
+            auto X = [&](int a, int b, int c) -> T { return (a < 0 || b < 0 || c < 0) ? (T)0 : x[a][b][c]; };
+            T pl;
+            if (ND == 2) {
+              pl = (X(i, j - 1, k) + X(i, j, k - 1)) - X(i, j - 1, k - 1);
+            } else {
+              const T u = (X(i - 1, j, k) + X(i, j - 1, k)) - X(i - 1, j - 1, k);
+              const T up = (X(i - 1, j, k - 1) + X(i, j - 1, k - 1)) - X(i - 1, j - 1, k - 1);
+              pl = X(i, j, k - 1) + (u - up);
+            }
+            sx[sample_slot<ND, B0, B1, B2>(i, j, k)] = x[i][j][k];
+            if (valid(i, j, k)) e_lor += cost<T>(x[i][j][k] - pl, inv_e) + 1u;
+          }
+        }
+        if (valid(i, j, 0)) {
+          P = P + R;
+          A = A + ((T)j - c1) * R;
+        }
+        row_fence(P, A, S1, Q1, e_lor);
+#pragma unroll
+        for (int k = 0; k < B2; k++) pin(D[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < B2; k++)
+        if (valid(i, 0, k)) Bv = Bv + ((T)k - c2) * D[k];
+      if (valid(i, 0, 0)) {
+        S0 = S0 + P;
+        Sa0 = Sa0 + ((T)i - c0) * P;
+        Sa1 = Sa1 + A;
+        Sa2 = Sa2 + Bv;
+      }
+    }
+    T beta0 = n0 > 1 ? Sa0 * rt.K[pat][0] : (T)0;
+    T beta1 = n1 > 1 ? Sa1 * rt.K[pat][1] : (T)0;
+    T beta2 = n2 > 1 ? Sa2 * rt.K[pat][2] : (T)0;
+    T mu = S0 * rt.inv_pts[pat];
+
+    bool is_reg;
+    if (predictor == SDCSZ_PRED_LORENZO) is_reg = false;
+    else if (predictor == SDCSZ_PRED_REGRESSION) is_reg = true;
+    else {
+      uint32_t e_reg = 0;
+#pragma unroll
+      for (int i = 0; i < B0; i++)
+#pragma unroll
+        for (int j = 0; j < B1; j++)
+#pragma unroll
+          for (int k = 0; k < B2; k++) {
+            if (!is_sample<ND, B0, B1, B2>(i, j, k)) continue;
+            const T pr = ((beta0 * ((T)i - c0) + beta1 * ((T)j - c1)) + beta2 * ((T)k - c2)) + mu;
+            if (valid(i, j, k)) e_reg += cost<T>(sx[sample_slot<ND, B0, B1, B2>(i, j, k)] - pr, inv_e);
+          }
+      is_reg = e_reg <= e_lor;
+    }
+
+    uint64_t why = 0;
+    if (ABFT) {  // coefficient checksums, taken again where the coefficients are used
+      uint64_t sc = 0, qc = 0, sc2 = 0, qc2 = 0;
+      Ck<T>::add(beta0, sc, qc);
+      Ck<T>::add(beta1, sc, qc);
+      Ck<T>::add(beta2, sc, qc);
+      Ck<T>::add(mu, sc, qc);
+      beta0 = launder(beta0);
+      beta1 = launder(beta1);
+      beta2 = launder(beta2);
+      mu = launder(mu);
+      Ck<T>::add(beta0, sc2, qc2);
+      Ck<T>::add(beta1, sc2, qc2);
+      Ck<T>::add(beta2, sc2, qc2);
+      Ck<T>::add(mu, sc2, qc2);
+      if (sc != sc2 || qc != qc2) why |= kWhyCoef;
+    }
+
+    // ---- prediction pass ------------------------------------------------
+    T Pw[B1][B2];  // reconstructed plane i-1, overwritten row by row with plane i
+#pragma unroll
+    for (int j = 0; j < B1; j++)
+#pragma unroll
+      for (int k = 0; k < B2; k++) Pw[j][k] = 0;
+    const T beta0d = ABFT ? launder(beta0) : beta0, beta1d = ABFT ? launder(beta1) : beta1;
+    const T beta2d = ABFT ? launder(beta2) : beta2;
+    T Bk[B2], Bk2[B2];
+#pragma unroll
+    for (int k = 0; k < B2; k++) {
+      Bk[k] = beta2 * ((T)k - c2);
+      Bk2[k] = beta2d * ((T)k - c2);
+    }
+    uint64_t S2 = 0, Q2 = 0, s_dc = 0, is_q = 0;
+    uint32_t s_q = 0, nout = 0;
+    uint32_t mis_p = 0, mis_r = 0;  // OR of bit differences between the duplicated results
+    T *outl = (T *)w.vals + blk * (uint64_t)g.bpts;
+    uint2 *cbase = (uint2 *)(w.codes + code_index(blk, 0, g.groups));  // next group is 64 vectors on
+    T xn[B2];  // the row after the current one, loaded one row ahead
+#pragma unroll
+    for (int k = 0; k < B2; k++) xn[k] = ld(0, 0, k);
+#pragma unroll 1
+    for (int i = 0; i < B0; i++) {
+      if (!FULL && (uint32_t)i >= n0) break;
+      const T A0 = beta0 * ((T)i - c0), A0d = beta0d * ((T)i - c0);
+      T Sv[B2];  // row j-1 of plane i-1
+#pragma unroll
+      for (int k = 0; k < B2; k++) Sv[k] = 0;
+      uint32_t pk0 = 0, pk1 = 0;
+#pragma unroll
+      for (int j = 0; j < B1; j++) {
+        T Aj = A0 + beta1 * ((T)j - c1), Ajd = A0d + beta1d * ((T)j - c1);
+        pin(Aj);  // keeps this row's regression predictions inside the row
+        if (ABFT) pin(Ajd);
+        T xr[B2];
+#pragma unroll
+        for (int k = 0; k < B2; k++) xr[k] = xn[k];
+        if (j + 1 < B1) {
+#pragma unroll
+          for (int k = 0; k < B2; k++) xn[k] = ld(i, j + 1, k);
+        } else if (i + 1 < B0) {
+#pragma unroll
+          for (int k = 0; k < B2; k++) xn[k] = ld(i + 1, 0, k);
+        }
+        T rowold[B2];
+        T cprev = 0, Up = 0, Up2 = 0;
+        uint32_t rs = 0, rk = 0;
+#pragma unroll
+        for (int k = 0; k < B2; k++) {
+          const bool v = valid(i, j, k);
+          const T xv = xr[k];
+          if (ABFT && v) Ck<T>::add(xv, S2, Q2);
+          const T a = Pw[j][k];
+          rowold[k] = a;
+          const T b = j > 0 ? Pw[j - 1][k] : (T)0;
+          const T d = j > 0 ? Sv[k] : (T)0;
+          T lor, U1 = 0;
+          if (ND == 2) {
+            const T f = (j > 0 && k > 0) ? Pw[j - 1][k - 1] : (T)0;
+            lor = (b + cprev) - f;
+          } else {
+            U1 = (a + b) - d;
+            lor = cprev + (U1 - Up);
+          }
+          const T reg = (Aj + Bk[k]) + mu;
+          const T pred = is_reg ? reg : lor;
+          if (ABFT) {  // pred' <- f_dup()
+            const T bl = launder(b);
+            T lor2, U2 = 0;
+            if (ND == 2) {
+              const T f = (j > 0 && k > 0) ? Pw[j - 1][k - 1] : (T)0;
+              lor2 = (bl + cprev) - f;
+            } else {
+              U2 = (a + bl) - d;
+              lor2 = cprev + (U2 - Up2);
+            }
+            const T reg2 = (Ajd + Bk2[k]) + mu;
+            mis_p |= Wd<T>::diff(pred, is_reg ? reg2 : lor2);
+            Up2 = U2;
+          }
+          const T diff = xv - pred;
+          const T t = fabs(diff) * inv + (T)0.5;
+          const bool inr = t < (T)32768;
+          const int m = (int)t;
+          const int sm = diff < (T)0 ? -m : m;
+          const T r1 = pred + (T)sm * q;
+          if (ABFT) mis_r |= Wd<T>::diff(r1, pred + (T)launder(sm) * q);  // dec_dup()
+          const bool bok = Bound<T>::ok(xv, r1, eb);
+          const bool ok = inr && bok;
+          const uint32_t code = (ok && v) ? (uint32_t)(sm + (int)kRadius) : 0u;
+          const T r_out = ok ? r1 : xv;
+          Pw[j][k] = r_out;
+          cprev = r_out;
+          Up = U1;
+          const bool is_out = v && !ok;
+          if (__builtin_expect(__ballot(is_out) != 0, 0)) {
+            if (is_out) outl[nout] = xv;
+            nout += is_out ? 1u : 0u;
+          }
+          const bool z = v && code == kRadius;
+          hot += (uint32_t)__popcll(__ballot(z));  // the same in every lane running the pass
+          if (v) {
+            if (ABFT) {
+              s_dc += Wd<T>::sum(r_out);
+              rs += code;
+              rk += (uint32_t)k * code;
+            }
+            if (!z) {
+              const uint32_t cb = code - kHistLo;
+              if (cb < kHistWin) atomicAdd(&hist[cb], 1u);
+              else atomicAdd(w.hist + code, 1u);
+            }
+          }
+          // pack the codes of 4 consecutive padded indices into 8 bytes
+          constexpr int dummy_unused = 0;
+          (void)dummy_unused;
+          const int qp = j * B2 + k;  // index inside the plane (planes fill whole groups)
+          if ((qp & 1) == 0) {
+            if ((qp & 2) == 0) pk0 = code;
+            else pk1 = code;
+          } else {
+            if ((qp & 2) == 0) pk0 |= code << 16;
+            else pk1 |= code << 16;
+          }
+          if ((qp & 3) == 3) cbase[(uint64_t)((i * PL + qp) >> 2) * 64] = make_uint2(pk0, pk1);
+        }
+        if (ABFT) {
+          const uint32_t rowbase = ((uint32_t)i * n1 + (uint32_t)j) * n2;
+          is_q += (uint64_t)rowbase * rs + rk;
+          s_q += rs;
+        }
+#pragma unroll
+        for (int k = 0; k < B2; k++) Sv[k] = rowold[k];
+        row_fence(cprev, S2, Q2, s_dc, is_q, s_q, nout, mis_p, mis_r);
+      }
+    }
+    w.meta[blk] = (nout << 1) | (is_reg ? 1u : 0u);
+    T *cf = (T *)w.coef + 4 * blk;
+    cf[0] = beta0;
+    cf[1] = beta1;
+    cf[2] = beta2;
+    cf[3] = mu;
+    if (ABFT) {
+      w.sum_dc[blk] = s_dc;
+      w.sum_q[blk] = s_q;
+      w.isum_q[blk] = is_q;
+      const uint64_t is1 = nwords * S1 - Q1, is2 = nwords * S2 - Q2;
+      if (S1 != S2 || is1 != is2) why |= kWhyInput;
+      if (mis_p) why |= kWhyPred;
+      if (mis_r) why |= kWhyRecon;
+      if (__builtin_expect(why != 0, 0)) {
+        if (why & kWhyInput) count(w.cnt, C_DET + SDCSZ_T_INPUT);
+        if (why & kWhyCoef) count(w.cnt, C_DET + SDCSZ_T_COEF);
+        if (why & kWhyPred) count(w.cnt, C_DET + SDCSZ_T_DUP_PRED);
+        if (why & kWhyRecon) count(w.cnt, C_DET + SDCSZ_T_DUP_RECON);
+        const uint32_t slot = atomicAdd(w.redo_n, 1u);
+        if (slot < kMaxRedo) w.redo[slot] = blk | (why << 56);
+      }
+    }
+  }
+  // wave total of the zero-residual bin (lanes that ran the pass agree; the
+  // others hold 0), then flush the window
+  for (int off = 32; off > 0; off >>= 1) hot = max(hot, (uint32_t)__shfl_xor((int)hot, off));
+  if ((threadIdx.x & 63) == 0 && hot) atomicAdd(&hist[kRadius - kHistLo], hot);
+  __syncthreads();
+  for (uint32_t t = threadIdx.x; t < kHistWin; t += blockDim.x)
+    if (hist[t]) atomicAdd(w.hist + kHistLo + t, hist[t]);
+}
+
+// The blocks a fault plan names, in the paper's order with the plan applied
+// (one thread per listed block).
+template <typename T>
+__global__ void __launch_bounds__(64) k_compress_list(const T *__restrict__ in, Geo g, RegTab<T> rt, PlanDev plan,
+                                                       CompWork w, uint32_t abft, uint32_t predictor,
+                                                       const uint64_t *list, uint32_t n) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) compress_block_generic<T>(in, g, rt, plan, w, abft, predictor, list[t]);
+}
+
+// Blocks whose checks disagreed in the specialised pass: take the block's
+// codes back out of the histogram and run the block again from the input
+// with the generic routine.
+template <typename T>
+__global__ void __launch_bounds__(64) k_redo(const T *__restrict__ in, Geo g, RegTab<T> rt, PlanDev plan,
+                                              CompWork w, uint32_t abft, uint32_t predictor) {
+  const uint32_t n = min(*w.redo_n, kMaxRedo);
+  for (uint32_t s = threadIdx.x; s < n; s += blockDim.x) {
+    const uint64_t e = w.redo[s];
+    const uint64_t blk = e & ((1ull << 56) - 1), why = e >> 56;
+    const Box b = box_of(g, blk);
+    for (uint32_t i = 0; i < b.n[0]; i++)
+      for (uint32_t j = 0; j < b.n[1]; j++)
+        for (uint32_t k = 0; k < b.n[2]; k++)
+          atomicSub(w.hist + w.codes[code_index(blk, padded_index(g, i, j, k), g.groups)], 1u);
+    compress_block_generic<T>(in, g, rt, plan, w, abft, predictor, blk);
+    if (why & kWhyInput) count(w.cnt, C_COR + SDCSZ_T_INPUT);
+    if (why & kWhyCoef) count(w.cnt, C_COR + SDCSZ_T_COEF);
+    if (why & kWhyPred) count(w.cnt, C_COR + SDCSZ_T_DUP_PRED);
+    if (why & kWhyRecon) count(w.cnt, C_COR + SDCSZ_T_DUP_RECON);
+  }
+}
+
+#define SDCSZ_INST_FAST(T, ND, B0, B1, B2, FULL, ABFT)                                                   \
+  template __global__ void k_compress_fast<T, ND, B0, B1, B2, FULL, ABFT>(const T *, Geo, RegTab<T>, PlanDev, \
+                                                                          CompWork, uint32_t, Launch);
+#define SDCSZ_INST_SHAPE(T, ND, B0, B1, B2)            \
+  SDCSZ_INST_FAST(T, ND, B0, B1, B2, true, true)      \
+  SDCSZ_INST_FAST(T, ND, B0, B1, B2, false, true)     \
+  SDCSZ_INST_FAST(T, ND, B0, B1, B2, true, false)     \
+  SDCSZ_INST_FAST(T, ND, B0, B1, B2, false, false)
+SDCSZ_INST_SHAPE(float, 3, 6, 6, 6)
+SDCSZ_INST_SHAPE(double, 3, 6, 6, 6)
+template __global__ void k_compress_list<float>(const float *, Geo, RegTab<float>, PlanDev, CompWork, uint32_t,
+                                                uint32_t, const uint64_t *, uint32_t);
+template __global__ void k_compress_list<double>(const double *, Geo, RegTab<double>, PlanDev, CompWork, uint32_t,
+                                                 uint32_t, const uint64_t *, uint32_t);
+template __global__ void k_redo<float>(const float *, Geo, RegTab<float>, PlanDev, CompWork, uint32_t, uint32_t);
+template __global__ void k_redo<double>(const double *, Geo, RegTab<double>, PlanDev, CompWork, uint32_t, uint32_t);
+
+}  // namespace sdcsz

@@ -65,7 +65,15 @@ __global__ void k_consts(const double *part, uint32_t nparts, uint32_t mode, dou
   e.qf = (float)e.q;
   e.invf = (float)e.inv;
   e.inv_ef = (float)e.inv_e;
-  e.pad = 0;
+  // FP32 rounding of |x - r| has relative error below 2^-24 (exact when the
+  // result is subnormal), so a margin of 1e-6 on either side of eb leaves the
+  // double comparison the only judge inside the band
+  const double dlo = eb_abs * (1.0 - 1e-6), dhi = eb_abs * (1.0 + 1e-6);
+  float lo = (float)dlo, hi = (float)dhi;
+  if ((double)lo > dlo) lo = nextafterf(lo, 0.0f);
+  if ((double)hi < dhi) hi = nextafterf(hi, INFINITY);
+  e.lo = lo;
+  e.hi = hi;
   *out = e;
 }
 
@@ -75,7 +83,10 @@ __global__ void k_code_faults(PlanDev plan, Geo g, uint16_t *codes, unsigned lon
   for (uint32_t t = 0; t < plan.n; t++) {
     const sdcsz_fault f = plan.f[t];
     if (f.target != SDCSZ_T_CODE) continue;
-    codes[f.block * (uint64_t)g.bpts + f.word] ^= (uint16_t)(1u << (f.bit & 15));
+    const Box b = box_of(g, f.block);
+    const uint32_t p = (uint32_t)f.word;
+    const uint32_t k = p % b.n[2], j = (p / b.n[2]) % b.n[1], i = p / (b.n[2] * b.n[1]);
+    codes[code_index(f.block, padded_index(g, i, j, k), g.groups)] ^= (uint16_t)(1u << (f.bit & 15));
     cnt[C_INJ + SDCSZ_T_CODE]++;
   }
 }
@@ -86,20 +97,26 @@ __global__ void __launch_bounds__(256) k_codes_check(Geo g, CompWork w, uint32_t
   const uint64_t blk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (blk >= g.n_blocks) return;
   const Box b = box_of(g, blk);
-  uint16_t *codes = w.codes + blk * (uint64_t)g.bpts;
+  uint16_t *codes = w.codes;
+  // position in the staging layout of the block's p-th point (C order)
+  auto at = [&](uint32_t p) -> uint64_t {
+    uint32_t k = p % b.n[2], j = (p / b.n[2]) % b.n[1], i = p / (b.n[2] * b.n[1]);
+    return code_index(blk, padded_index(g, i, j, k), g.groups);
+  };
   if (abft) {
     uint64_t s2 = 0, i2 = 0;
     for (uint32_t p = 0; p < b.pts; p++) {
-      s2 += codes[p];
-      i2 += (uint64_t)p * codes[p];
+      uint32_t c = codes[at(p)];
+      s2 += c;
+      i2 += (uint64_t)p * c;
     }
     uint64_t j;
     uint32_t v;
     int st = locate_repair(s2, i2, w.sum_q[blk], w.isum_q[blk], b.pts, 16,
-                           [&](uint64_t jj) { return (uint32_t)codes[jj]; }, &j, &v);
+                           [&](uint64_t jj) { return (uint32_t)codes[at((uint32_t)jj)]; }, &j, &v);
     if (st != 0) count(w.cnt, C_DET + SDCSZ_T_CODE);
     if (st == 1) {
-      codes[j] = (uint16_t)v;
+      codes[at((uint32_t)j)] = (uint16_t)v;
       count(w.cnt, C_COR + SDCSZ_T_CODE);
     }
     if (st < 0) count(w.cnt, C_UNC + SDCSZ_T_CODE);
@@ -107,7 +124,7 @@ __global__ void __launch_bounds__(256) k_codes_check(Geo g, CompWork w, uint32_t
   uint64_t bits = 0;
   bool missing = false;
   for (uint32_t p = 0; p < b.pts; p++) {
-    uint32_t len = w.enc[codes[p]] & 0xFFu;
+    uint32_t len = w.enc[codes[at(p)]] & 0xFFu;
     missing |= len == 0;
     bits += len;
   }
@@ -233,12 +250,13 @@ __global__ void __launch_bounds__(256) k_encode(Geo g, CompWork w, uint8_t *out,
   const uint64_t blk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (blk >= g.n_blocks) return;
   const Box b = box_of(g, blk);
-  const uint16_t *codes = w.codes + blk * (uint64_t)g.bpts;
   uint32_t *dst = (uint32_t *)(out + h.off_payload) + w.off_pay[blk];
   uint64_t acc = 0;
   uint32_t nacc = 0;
-  for (uint32_t p = 0; p < b.pts; p++) {
-    uint32_t e = w.enc[codes[p]];
+  for (uint32_t i = 0; i < b.n[0]; i++)
+    for (uint32_t j = 0; j < b.n[1]; j++)
+      for (uint32_t k = 0; k < b.n[2]; k++) {
+    uint32_t e = w.enc[w.codes[code_index(blk, padded_index(g, i, j, k), g.groups)]];
     uint32_t len = e & 0xFFu;
     acc = (acc << len) | (e >> 8);
     nacc += len;
@@ -247,7 +265,7 @@ __global__ void __launch_bounds__(256) k_encode(Geo g, CompWork w, uint8_t *out,
       *dst++ = (uint32_t)(acc >> nacc);
       acc &= (1ull << nacc) - 1;
     }
-  }
+      }
   if (nacc > 0) *dst++ = (uint32_t)(acc << (32 - nacc));
   const uint32_t meta = w.meta[blk];
   uint32_t *tab = (uint32_t *)(out + h.off_table) + 2 * blk;

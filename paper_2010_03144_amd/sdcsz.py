@@ -19,7 +19,9 @@ TARGETS = ["input", "coef", "code", "recon", "dup_pred", "dup_recon"]
 ERRORS = {OK: "ok", EINVAL: "EINVAL", ENOSPC: "ENOSPC", EFORMAT: "EFORMAT", ESDC: "ESDC", EHIP: "EHIP"}
 FUNCTIONS = ["sdcsz_max_compressed_size", "sdcsz_compress_workspace_size", "sdcsz_compress",
              "sdcsz_stream_info", "sdcsz_decompress_workspace_size", "sdcsz_decompress",
-             "sdcsz_verify", "sdcsz_decompress_region", "sdcsz_strerror"]
+             "sdcsz_verify", "sdcsz_decompress_region", "sdcsz_strerror", "sdcsz_timing_enable",
+             "sdcsz_timing_read", "sdcsz_phase_name"]
+N_PHASES = 8
 
 
 class SdcszError(RuntimeError):
@@ -38,6 +40,10 @@ class Params(C.Structure):
                 ("block", C.c_uint32 * 3), ("eb_mode", C.c_uint32), ("predictor", C.c_uint32),
                 ("eb", C.c_double), ("abft", C.c_uint32), ("n_faults", C.c_uint32),
                 ("faults", C.POINTER(Fault))]
+
+
+class Timing(C.Structure):
+    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_uint64 * 8)]
 
 
 class Report(C.Structure):
@@ -77,6 +83,12 @@ def lib():
                                               C.c_uint64, P(Report), vp, C.c_uint64, vp]
         L.sdcsz_strerror.restype = C.c_char_p
         L.sdcsz_strerror.argtypes = [C.c_int]
+        L.sdcsz_timing_enable.argtypes = [C.c_int]
+        L.sdcsz_timing_enable.restype = None
+        L.sdcsz_timing_read.argtypes = [P(Timing)]
+        L.sdcsz_timing_read.restype = None
+        L.sdcsz_phase_name.argtypes = [C.c_int]
+        L.sdcsz_phase_name.restype = C.c_char_p
         _lib = L
     return _lib
 
@@ -238,6 +250,18 @@ class Codec:
                                        C.c_void_p(ws.data_ptr()), ws.numel(),
                                        _stream_handle(self.device))
         return rc, out, report_dict(rep)
+
+
+def timing_enable(on=True):
+    lib().sdcsz_timing_enable(1 if on else 0)
+
+
+def timing_read():
+    """{phase name: (accumulated device ms, launches)} of the enabled period."""
+    L = lib()
+    t = Timing()
+    L.sdcsz_timing_read(C.byref(t))
+    return {L.sdcsz_phase_name(i).decode(): (t.ms[i], t.launches[i]) for i in range(N_PHASES)}
 
 
 def strerror(rc):
