@@ -105,7 +105,12 @@ struct DecWork {
   uint32_t *off_coef;
   uint64_t *scan_part;
   unsigned long long *cnt;
+  uint32_t *lut;       // 2^kLutBits entries: symbol << 8 | length (0: longer code)
+  uint32_t *redo_n;    // blocks queued for re-execution
+  uint64_t *redo;      // kMaxRedo entries: block | reason << 56
 };
+
+constexpr uint32_t kLutBits = 11;  // codeword prefix resolved by one table lookup
 
 // Stream header fields (byte offsets inside the 192-byte header).
 struct Header {

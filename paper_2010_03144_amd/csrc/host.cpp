@@ -229,38 +229,42 @@ bool fast_shape(const Geo &g, uint32_t vb) {
   return g.n_values * vb < (1ull << 31);
 }
 
+// One launch of a specialised kernel: the first work-groups take the
+// sub-grid of full blocks, the others the shell of partial blocks along the
+// upper faces.  Returns the number of work-groups of 256 lanes.
+uint32_t fast_launch(const Geo &g, Launch *L) {
+  bool part[3];
+  std::memset(L, 0, sizeof(*L));
+  for (int a = 0; a < 3; a++) {
+    part[a] = g.rem[a] != g.b[a];
+    L->nf[a] = g.nb[a] - (part[a] ? 1 : 0);
+  }
+  L->full_count = (uint64_t)L->nf[0] * L->nf[1] * L->nf[2];
+  L->s2 = part[2] ? (uint64_t)g.nb[0] * g.nb[1] : 0;
+  L->s1 = part[1] ? (uint64_t)g.nb[0] * L->nf[2] : 0;
+  const uint64_t s0 = part[0] ? (uint64_t)L->nf[1] * L->nf[2] : 0;
+  L->shell_count = L->s2 + L->s1 + s0;
+  L->full_wgs = (uint32_t)((L->full_count + 255) / 256);
+  return L->full_wgs + (uint32_t)((L->shell_count + 255) / 256);
+}
+
 template <typename T, bool ABFT>
 void launch_fast(const T *in, const Geo &g, const RegTab<T> &rt, const PlanDev &pd, const CompWork &w,
                  uint32_t predictor, const uint64_t *plan_blocks, uint32_t n_plan_blocks, hipStream_t st) {
   if (n_plan_blocks)
     hipLaunchKernelGGL(k_compress_list<T>, dim3(grid_for(n_plan_blocks, 64)), dim3(64), 0, st, in, g, rt, pd, w,
                        ABFT ? 1u : 0u, predictor, plan_blocks, n_plan_blocks);
-  bool part[3];
-  Launch full, shell;
-  std::memset(&full, 0, sizeof(full));
-  for (int a = 0; a < 3; a++) {
-    part[a] = g.rem[a] != g.b[a];
-    full.nf[a] = g.nb[a] - (part[a] ? 1 : 0);
-  }
-  shell = full;
-  full.mode = 0;
-  full.count = (uint64_t)full.nf[0] * full.nf[1] * full.nf[2];
-  shell.mode = 1;
-  shell.s2 = part[2] ? (uint64_t)g.nb[0] * g.nb[1] : 0;
-  shell.s1 = part[1] ? (uint64_t)g.nb[0] * full.nf[2] : 0;
-  const uint64_t s0 = part[0] ? (uint64_t)full.nf[1] * full.nf[2] : 0;
-  shell.count = shell.s2 + shell.s1 + s0;
-  if (full.count)
-    hipLaunchKernelGGL((k_compress_fast<T, 3, 6, 6, 6, true, ABFT>), dim3(grid_for(full.count, 256)), dim3(256), 0,
-                       st, in, g, rt, pd, w, predictor, full);
-  if (shell.count)
-    hipLaunchKernelGGL((k_compress_fast<T, 3, 6, 6, 6, false, ABFT>), dim3(grid_for(shell.count, 256)), dim3(256),
-                       0, st, in, g, rt, pd, w, predictor, shell);
+  Launch L;
+  const uint32_t wgs = fast_launch(g, &L);
+  if (wgs)
+    hipLaunchKernelGGL((k_compress_fast<T, 3, 6, 6, 6, ABFT>), dim3(wgs), dim3(256), 0, st, in, g, rt, pd, w,
+                       predictor, L);
   hipLaunchKernelGGL(k_redo<T>, dim3(1), dim3(64), 0, st, in, g, rt, pd, w, ABFT ? 1u : 0u, predictor);
 }
 
 struct DecLayout {
-  uint64_t cnt, symbols, tab, recon, off_pay, off_out, off_coef, scan, plan, bits, total;
+  uint64_t cnt, symbols, tab, recon, off_pay, off_out, off_coef, scan, plan, bits, lut, redo_n, redo, plan_blocks;
+  uint64_t total;
 };
 
 DecLayout dec_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
@@ -283,6 +287,10 @@ DecLayout dec_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
   L.scan = take(24 * chunks);
   L.plan = take(sizeof(sdcsz_fault) * (uint64_t)std::max<uint32_t>(nfaults, 1));
   L.bits = take(4 * (nb / 32 + 1));
+  L.lut = take(4ull << kLutBits);
+  L.redo_n = take(4);
+  L.redo = take(8ull * kMaxRedo);
+  L.plan_blocks = take(8ull * std::max<uint32_t>(nfaults, 1));
   L.total = at;
   return L;
 }
@@ -551,7 +559,7 @@ int compress_t(const void *d_in, const sdcsz_params *p, const Geo &g, uint8_t *d
     hipLaunchKernelGGL(k_range<T>, dim3(nparts), dim3(kRangeThreads), 0, st, (const T *)d_in, g.n_values,
                        (double *)w.range_part);
   }
-  hipLaunchKernelGGL(k_consts, dim3(1), dim3(64), 0, st, (const double *)w.range_part, nparts, p->eb_mode,
+  hipLaunchKernelGGL(k_consts, dim3(1), dim3(256), 0, st, (const double *)w.range_part, nparts, p->eb_mode,
                      p->eb, w.eb);
   g_timer.end(PH_RANGE, st);
   HIPCHK(hipGetLastError());
@@ -570,7 +578,7 @@ int compress_t(const void *d_in, const sdcsz_params *p, const Geo &g, uint8_t *d
       hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, w.redo_n, (uint64_t)1);
       if (p->abft) launch_fast<T, true>((const T *)d_in, g, rt, pd, w, p->predictor, d_pb, (uint32_t)pb.size(), st);
       else launch_fast<T, false>((const T *)d_in, g, rt, pd, w, p->predictor, d_pb, (uint32_t)pb.size(), st);
-      HIPCHK(hipStreamSynchronize(st));  // keeps pb alive until its copy is done
+      if (!pb.empty()) HIPCHK(hipStreamSynchronize(st));  // keeps pb alive until its copy is done
     } else {
       hipLaunchKernelGGL(k_compress_generic<T>, dim3(grid_for(g.n_blocks, 64)), dim3(64), 0, st,
                          (const T *)d_in, g, rt, pd, w, p->abft, p->predictor);
@@ -606,7 +614,10 @@ int compress_t(const void *d_in, const sdcsz_params *p, const Geo &g, uint8_t *d
 
   if (g.n_blocks) {
     g_timer.begin(PH_CHECK, st);
-    hipLaunchKernelGGL(k_codes_check, dim3(grid_for(g.n_blocks, 256)), dim3(256), 0, st, g, w, p->abft);
+    if (fast_shape(g, sizeof(T)))
+      hipLaunchKernelGGL((k_check_fast<6, 6, 6>), dim3(grid_for(g.n_blocks, 256)), dim3(256), 0, st, g, w, p->abft);
+    else
+      hipLaunchKernelGGL(k_codes_check, dim3(grid_for(g.n_blocks, 256)), dim3(256), 0, st, g, w, p->abft);
     g_timer.end(PH_CHECK, st);
     ScanSrc src{w.words, w.meta, 1};
     g_timer.begin(PH_SCAN_C, st);
@@ -674,7 +685,10 @@ int compress_t(const void *d_in, const sdcsz_params *p, const Geo &g, uint8_t *d
   if (h.total > h.off_payload)
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t *)(d_out + h.total - 8), 2);
   g_timer.begin(PH_ENCODE, st);
-  if (g.n_blocks) hipLaunchKernelGGL(k_encode<T>, dim3(grid_for(g.n_blocks, 256)), dim3(256), 0, st, g, w, d_out, h);
+  if (g.n_blocks && fast_shape(g, sizeof(T)))
+    hipLaunchKernelGGL((k_encode_fast<T, 6, 6, 6>), dim3(grid_for(g.n_blocks, 256)), dim3(256), 0, st, g, w, d_out, h);
+  else if (g.n_blocks)
+    hipLaunchKernelGGL(k_encode<T>, dim3(grid_for(g.n_blocks, 256)), dim3(256), 0, st, g, w, d_out, h);
   g_timer.end(PH_ENCODE, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
@@ -720,7 +734,15 @@ int decode_t(const uint8_t *d_s, Opened &o, T *d_out, uint32_t mode, const Regio
     len[s] = (uint8_t)l;
   }
   std::vector<uint16_t> order;
-  Canon C = canonical(len, nullptr, &order);
+  std::vector<uint32_t> codes;
+  Canon C = canonical(len, &codes, &order);
+  // one-lookup table for codewords of up to kLutBits bits
+  std::vector<uint32_t> lut(1u << kLutBits, 0);
+  for (uint32_t s = 0; s < 65536; s++)
+    if (len[s] && len[s] <= kLutBits) {
+      const uint32_t sh = kLutBits - len[s];
+      for (uint32_t v = codes[s] << sh; v < ((codes[s] + 1) << sh); v++) lut[v] = (s << 8) | len[s];
+    }
   DecTab tab;
   std::memset(&tab, 0, sizeof(tab));
   tab.min_len = kMaxLen + 1;
@@ -744,8 +766,12 @@ int decode_t(const uint8_t *d_s, Opened &o, T *d_out, uint32_t mode, const Regio
   w.off_out = (uint32_t *)(ws + L.off_out);
   w.off_coef = (uint32_t *)(ws + L.off_coef);
   w.scan_part = (uint64_t *)(ws + L.scan);
+  w.lut = (uint32_t *)(ws + L.lut);
+  w.redo_n = (uint32_t *)(ws + L.redo_n);
+  w.redo = (uint64_t *)(ws + L.redo);
   HIPCHK(hipMemcpyAsync(w.symbols, order.data(), 2 * 65536, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(w.tab, &tab, sizeof(tab), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(w.lut, lut.data(), 4ull << kLutBits, hipMemcpyHostToDevice, st));
   std::vector<uint32_t> bits_host;
   PlanDev pd;
   rc = upload_plan(plan, g.n_blocks, ws, L.plan, L.bits, bits_host, st, &pd);
@@ -764,7 +790,26 @@ int decode_t(const uint8_t *d_s, Opened &o, T *d_out, uint32_t mode, const Regio
   HIPCHK(hipMemcpyAsync(&tot_coef, w.off_coef + g.n_blocks, 4, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (tot_pay != h.payload_words || tot_out != h.n_outliers || tot_coef != h.n_regression) return SDCSZ_EFORMAT;
-  if (g.n_blocks) {
+  const bool fast = mode == 0 && fast_shape(g, sizeof(T));
+  std::vector<uint64_t> pb;
+  if (g.n_blocks && fast) {
+    for (auto &f : plan)
+      if (pb.empty() || pb.back() != f.block) pb.push_back(f.block);
+    const uint64_t *d_pb = (const uint64_t *)(ws + L.plan_blocks);
+    if (!pb.empty()) HIPCHK(hipMemcpyAsync(ws + L.plan_blocks, pb.data(), 8 * pb.size(), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, w.redo_n, (uint64_t)1);
+    g_timer.begin(PH_DECODE, st);
+    if (!pb.empty())
+      hipLaunchKernelGGL(k_decode_list<T>, dim3(grid_for(pb.size(), 64)), dim3(64), 0, st, d_s, h, g, w, pd, d_out,
+                         d_pb, (uint32_t)pb.size());
+    Launch FL;
+    const uint32_t wgs = fast_launch(g, &FL);
+    if (wgs)
+      hipLaunchKernelGGL((k_decode_fast<T, 3, 6, 6, 6>), dim3(wgs), dim3(256), 0, st, d_s, h, g, w, pd, d_out, FL);
+    hipLaunchKernelGGL(k_decode_redo<T>, dim3(1), dim3(64), 0, st, d_s, h, g, w, d_out);
+    g_timer.end(PH_DECODE, st);
+    HIPCHK(hipGetLastError());
+  } else if (g.n_blocks) {
     g_timer.begin(PH_DECODE, st);
     hipLaunchKernelGGL(k_decode_generic<T>, dim3(grid_for(g.n_blocks, 64)), dim3(64), 0, st, d_s, h, g, w, pd,
                        d_out, mode, reg);
@@ -772,9 +817,19 @@ int decode_t(const uint8_t *d_s, Opened &o, T *d_out, uint32_t mode, const Regio
     HIPCHK(hipGetLastError());
   }
   unsigned long long cnt[C_N];
+  uint32_t redo_n = 0;
   HIPCHK(hipMemcpyAsync(cnt, w.cnt, sizeof(cnt), hipMemcpyDeviceToHost, st));
+  if (fast) HIPCHK(hipMemcpyAsync(&redo_n, w.redo_n, 4, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   g_timer.resolve();
+  if (redo_n > kMaxRedo) {
+    // more blocks to re-execute than the queue holds: decode everything again
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, w.cnt, (uint64_t)C_N);
+    hipLaunchKernelGGL(k_decode_generic<T>, dim3(grid_for(g.n_blocks, 64)), dim3(64), 0, st, d_s, h, g, w, pd,
+                       d_out, mode, reg);
+    HIPCHK(hipMemcpyAsync(cnt, w.cnt, sizeof(cnt), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
   sdcsz_report rep;
   fill_report(&rep, cnt, g.n_blocks);
   rep.eb_abs = h.eb_abs;

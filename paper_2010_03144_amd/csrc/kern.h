@@ -22,15 +22,15 @@ constexpr uint32_t kScanChunk = kScanThreads * kScanItems;
 constexpr uint32_t kRangeThreads = 256;
 constexpr uint32_t kHistWin = 2048;  // codes counted in LDS around the radius
 
-// Work of one specialised compression launch: the sub-grid of full blocks
-// (mode 0), or the shell of partial blocks at the upper edges (mode 1: the
-// slab of blocks partial along the fastest axis, then the middle, then the
-// slowest, each excluding the earlier slabs).
+// Work of one specialised launch: work-groups [0, full_wgs) take the
+// sub-grid of full blocks, the others the shell of partial blocks at the
+// upper edges (the slab of blocks partial along the fastest axis, then the
+// middle, then the slowest, each excluding the earlier slabs).
 struct Launch {
-  uint32_t mode;
-  uint32_t nf[3];  // full blocks per axis
-  uint64_t s2, s1; // sizes of the first two shell slabs
-  uint64_t count;  // lanes of work
+  uint32_t nf[3];      // full blocks per axis
+  uint32_t full_wgs;   // work-groups of full blocks
+  uint64_t s2, s1;     // sizes of the first two shell slabs
+  uint64_t full_count, shell_count;
 };
 constexpr uint32_t kRangeBlocks = 2048;
 
@@ -47,7 +47,7 @@ __global__ void k_scan3(ScanSrc src, uint64_t n, const uint64_t *part, uint64_t 
 template <typename T>
 __global__ void k_encode(Geo g, CompWork w, uint8_t *out, Header h);
 
-template <typename T, int ND, int B0, int B1, int B2, bool FULL, bool ABFT>
+template <typename T, int ND, int B0, int B1, int B2, bool ABFT>
 __global__ void k_compress_fast(const T *in, Geo g, RegTab<T> rt, PlanDev plan, CompWork w, uint32_t predictor,
                                 Launch L);
 template <typename T>
@@ -56,6 +56,18 @@ __global__ void k_compress_list(const T *in, Geo g, RegTab<T> rt, PlanDev plan, 
 template <typename T>
 __global__ void k_redo(const T *in, Geo g, RegTab<T> rt, PlanDev plan, CompWork w, uint32_t abft,
                        uint32_t predictor);
+
+template <typename T, int ND, int B0, int B1, int B2>
+__global__ void k_decode_fast(const uint8_t *s, Header h, Geo g, DecWork w, PlanDev plan, T *out, Launch L);
+template <typename T>
+__global__ void k_decode_list(const uint8_t *s, Header h, Geo g, DecWork w, PlanDev plan, T *out,
+                              const uint64_t *list, uint32_t n);
+template <typename T>
+__global__ void k_decode_redo(const uint8_t *s, Header h, Geo g, DecWork w, T *out);
+
+template <int B0, int B1, int B2> __global__ void k_check_fast(Geo g, CompWork w, uint32_t abft);
+template <typename T, int B0, int B1, int B2>
+__global__ void k_encode_fast(Geo g, CompWork w, uint8_t *out, Header h);
 
 template <typename T>
 __global__ void k_compress_generic(const T *in, Geo g, RegTab<T> rt, PlanDev plan, CompWork w,

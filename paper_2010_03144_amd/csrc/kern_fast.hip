@@ -21,9 +21,9 @@ constexpr uint32_t kHistLo = kRadius - kHistWin / 2;
 // reasons a block is queued for a re-run (high byte of the queue entry)
 constexpr uint64_t kWhyInput = 1, kWhyCoef = 2, kWhyPred = 4, kWhyRecon = 8;
 
-__device__ inline uint64_t map_block(const Geo &g, const Launch &L, uint64_t idx) {
+__device__ inline uint64_t map_block(const Geo &g, const Launch &L, uint32_t mode, uint64_t idx) {
   uint64_t c0, c1, c2;
-  if (L.mode == 0) {
+  if (mode == 0) {
     c2 = idx % L.nf[2];
     uint64_t t = idx / L.nf[2];
     c1 = t % L.nf[1];
@@ -126,21 +126,18 @@ template <> struct Bound<double> {
 
 }  // namespace
 
+// One lane's block: full blocks (FULL) have compile-time extents, blocks of
+// the partial shell mask every point by their actual extents.
 template <typename T, int ND, int B0, int B1, int B2, bool FULL, bool ABFT>
-__global__ void __launch_bounds__(256)
-k_compress_fast(const T *__restrict__ in, Geo g, RegTab<T> rt, PlanDev plan, CompWork w, uint32_t predictor,
-                Launch L) {
+__device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const Geo &g, const RegTab<T> &rt,
+                                               const PlanDev &plan, const CompWork &w, uint32_t predictor,
+                                               const Launch &L, uint32_t *hist, uint32_t &hot, uint64_t idx,
+                                               uint64_t nlanes) {
   constexpr int PL = B1 * B2;  // points per plane
   static_assert(PL % 4 == 0, "a plane must fill whole 4-code groups");
   constexpr int NS = sample_slot<ND, B0, B1, B2>(B0, 0, 0);
-  __shared__ uint32_t hist[kHistWin];
-  for (uint32_t t = threadIdx.x; t < kHistWin; t += blockDim.x) hist[t] = 0;
-  __syncthreads();
-  uint32_t hot = 0;
-
-  const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool active = idx < L.count;
-  const uint64_t blk = map_block(g, L, active ? idx : L.count - 1);
+  bool active = idx < nlanes;
+  const uint64_t blk = map_block(g, L, FULL ? 0u : 1u, active ? idx : nlanes - 1);
   // wave-uniform base of the input (the wave's lowest block origin); lanes
   // address it with 32-bit byte offsets (the host takes this kernel only for
   // fields below 2 GiB, so every offset fits)
@@ -441,6 +438,24 @@ k_compress_fast(const T *__restrict__ in, Geo g, RegTab<T> rt, PlanDev plan, Com
       }
     }
   }
+}
+
+// Work-groups [0, L.full_wgs) take full blocks, the rest the partial shell.
+template <typename T, int ND, int B0, int B1, int B2, bool ABFT>
+__global__ void __launch_bounds__(256)
+k_compress_fast(const T *__restrict__ in, Geo g, RegTab<T> rt, PlanDev plan, CompWork w, uint32_t predictor,
+                Launch L) {
+  __shared__ uint32_t hist[kHistWin];
+  for (uint32_t t = threadIdx.x; t < kHistWin; t += blockDim.x) hist[t] = 0;
+  __syncthreads();
+  uint32_t hot = 0;
+  if (blockIdx.x < L.full_wgs)
+    compress_lanes<T, ND, B0, B1, B2, true, ABFT>(in, g, rt, plan, w, predictor, L, hist, hot,
+                                                  (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, L.full_count);
+  else
+    compress_lanes<T, ND, B0, B1, B2, false, ABFT>(in, g, rt, plan, w, predictor, L, hist, hot,
+                                                   (uint64_t)(blockIdx.x - L.full_wgs) * blockDim.x + threadIdx.x,
+                                                   L.shell_count);
   // wave total of the zero-residual bin (lanes that ran the pass agree; the
   // others hold 0), then flush the window
   for (int off = 32; off > 0; off >>= 1) hot = max(hot, (uint32_t)__shfl_xor((int)hot, off));
@@ -483,14 +498,12 @@ __global__ void __launch_bounds__(64) k_redo(const T *__restrict__ in, Geo g, Re
   }
 }
 
-#define SDCSZ_INST_FAST(T, ND, B0, B1, B2, FULL, ABFT)                                                   \
-  template __global__ void k_compress_fast<T, ND, B0, B1, B2, FULL, ABFT>(const T *, Geo, RegTab<T>, PlanDev, \
-                                                                          CompWork, uint32_t, Launch);
-#define SDCSZ_INST_SHAPE(T, ND, B0, B1, B2)            \
-  SDCSZ_INST_FAST(T, ND, B0, B1, B2, true, true)      \
-  SDCSZ_INST_FAST(T, ND, B0, B1, B2, false, true)     \
-  SDCSZ_INST_FAST(T, ND, B0, B1, B2, true, false)     \
-  SDCSZ_INST_FAST(T, ND, B0, B1, B2, false, false)
+#define SDCSZ_INST_FAST(T, ND, B0, B1, B2, ABFT)                                                          \
+  template __global__ void k_compress_fast<T, ND, B0, B1, B2, ABFT>(const T *, Geo, RegTab<T>, PlanDev, CompWork, \
+                                                                    uint32_t, Launch);
+#define SDCSZ_INST_SHAPE(T, ND, B0, B1, B2) \
+  SDCSZ_INST_FAST(T, ND, B0, B1, B2, true)  \
+  SDCSZ_INST_FAST(T, ND, B0, B1, B2, false)
 SDCSZ_INST_SHAPE(float, 3, 6, 6, 6)
 SDCSZ_INST_SHAPE(double, 3, 6, 6, 6)
 template __global__ void k_compress_list<float>(const float *, Geo, RegTab<float>, PlanDev, CompWork, uint32_t,

@@ -1,0 +1,161 @@
+// kern_fast_enc.hip -- block-shape-specialised code check and Huffman encoding.
+//
+// One lane per block over consecutive block ids, so the interleaved code
+// staging layout gives fully coalesced 8-byte-per-lane reads.  The codeword
+// table is held in LDS for the codes around the zero residual (where almost
+// all codes fall) and read from global memory outside that window.
+#include "dev.h"
+#include "kern.h"
+
+namespace sdcsz {
+
+namespace {
+
+constexpr uint32_t kEncWin = 4096;
+constexpr uint32_t kEncLo = kRadius - kEncWin / 2;
+
+__device__ inline uint32_t enc_of(uint32_t code, const uint32_t *encw, const uint32_t *enc) {
+  const uint32_t c = code - kEncLo;
+  return c < kEncWin ? encw[c] : enc[code];
+}
+
+__device__ inline void load_window(uint32_t *encw, const uint32_t *enc) {
+  for (uint32_t t = threadIdx.x; t < kEncWin; t += blockDim.x) encw[t] = enc[kEncLo + t];
+  __syncthreads();
+}
+
+template <int B0, int B1, int B2> struct BlockCodes {
+  static constexpr int NG = (B0 * B1 * B2 + 3) / 4;
+  uint32_t v[2 * NG];  // two codes per word, padded point order
+  __device__ void load(const uint16_t *codes, uint64_t blk, uint32_t groups) {
+    const uint2 *cb = (const uint2 *)(codes + code_index(blk, 0, groups));
+#pragma unroll
+    for (int gi = 0; gi < NG; gi++) {
+      const uint2 u = cb[(uint64_t)gi * 64];
+      v[2 * gi] = u.x;
+      v[2 * gi + 1] = u.y;
+    }
+  }
+  __device__ uint32_t at(int qp) const { return (v[qp >> 1] >> (16 * (qp & 1))) & 0xFFFFu; }
+};
+
+}  // namespace
+
+// Verify/correct the codes of each block with sum_q/isum_q (Algorithm 1,
+// before encoding) and size its payload in 32-bit words.
+template <int B0, int B1, int B2>
+__global__ void __launch_bounds__(256) k_check_fast(Geo g, CompWork w, uint32_t abft) {
+  __shared__ uint32_t encw[kEncWin];
+  load_window(encw, w.enc);
+  const uint64_t blk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (blk >= g.n_blocks) return;
+  const Box b = box_of(g, blk);
+  const uint32_t n1 = b.n[1], n2 = b.n[2];
+  BlockCodes<B0, B1, B2> bc;
+  bc.load(w.codes, blk, g.groups);
+  uint64_t s = 0, is = 0, bits = 0;
+  bool missing = false;
+#pragma unroll
+  for (int i = 0; i < B0; i++)
+#pragma unroll
+    for (int j = 0; j < B1; j++) {
+      const uint32_t rowbase = ((uint32_t)i * n1 + (uint32_t)j) * n2;
+      uint32_t rs = 0, rk = 0;
+#pragma unroll
+      for (int k = 0; k < B2; k++) {
+        const bool v = (uint32_t)i < b.n[0] && (uint32_t)j < n1 && (uint32_t)k < n2;
+        const uint32_t c = v ? bc.at((i * B1 + j) * B2 + k) : 0u;
+        const uint32_t len = enc_of(c, encw, w.enc) & 0xFFu;
+        if (v) {
+          rs += c;
+          rk += (uint32_t)k * c;
+          bits += len;
+          missing |= len == 0;
+        }
+      }
+      s += rs;
+      is += (uint64_t)rowbase * rs + rk;
+    }
+  if (abft && (s != w.sum_q[blk] || is != w.isum_q[blk])) {
+    // detected: locate and repair one code, then size the block again
+    auto pos = [&](uint64_t p) -> uint64_t {
+      const uint32_t k = (uint32_t)(p % n2), j = (uint32_t)((p / n2) % n1), i = (uint32_t)(p / ((uint64_t)n2 * n1));
+      return code_index(blk, padded_index(g, i, j, k), g.groups);
+    };
+    uint64_t jf;
+    uint32_t vf;
+    const int st = locate_repair(s, is, w.sum_q[blk], w.isum_q[blk], b.pts, 16,
+                                 [&](uint64_t jj) { return (uint32_t)w.codes[pos(jj)]; }, &jf, &vf);
+    count(w.cnt, C_DET + SDCSZ_T_CODE);
+    if (st == 1) {
+      w.codes[pos(jf)] = (uint16_t)vf;
+      count(w.cnt, C_COR + SDCSZ_T_CODE);
+      bits = 0;
+      missing = false;
+      for (uint32_t p = 0; p < b.pts; p++) {
+        const uint32_t len = enc_of(w.codes[pos(p)], encw, w.enc) & 0xFFu;
+        bits += len;
+        missing |= len == 0;
+      }
+    } else {
+      count(w.cnt, C_UNC + SDCSZ_T_CODE);
+    }
+  }
+  if (missing) count(w.cnt, C_MISSING);
+  w.words[blk] = (uint32_t)((bits + 31) / 32);
+}
+
+// Per-block Huffman encoding (MSB first into 32-bit words) and the block's
+// table entry, coefficients, sum_dc and outliers at their scanned offsets.
+template <typename T, int B0, int B1, int B2>
+__global__ void __launch_bounds__(256) k_encode_fast(Geo g, CompWork w, uint8_t *out, Header h) {
+  __shared__ uint32_t encw[kEncWin];
+  load_window(encw, w.enc);
+  const uint64_t blk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (blk >= g.n_blocks) return;
+  const Box b = box_of(g, blk);
+  BlockCodes<B0, B1, B2> bc;
+  bc.load(w.codes, blk, g.groups);
+  uint32_t *dst = (uint32_t *)(out + h.off_payload) + w.off_pay[blk];
+  uint64_t acc = 0;
+  uint32_t nacc = 0;
+#pragma unroll
+  for (int i = 0; i < B0; i++)
+#pragma unroll
+    for (int j = 0; j < B1; j++)
+#pragma unroll
+      for (int k = 0; k < B2; k++) {
+        const bool v = (uint32_t)i < b.n[0] && (uint32_t)j < b.n[1] && (uint32_t)k < b.n[2];
+        const uint32_t e = enc_of(v ? bc.at((i * B1 + j) * B2 + k) : kRadius, encw, w.enc);
+        const uint32_t len = v ? (e & 0xFFu) : 0u;
+        acc = (acc << len) | (e >> 8 & ((1u << len) - 1u));
+        nacc += len;
+        if (nacc >= 32) {
+          nacc -= 32;
+          *dst++ = (uint32_t)(acc >> nacc);
+          acc &= (1ull << nacc) - 1;
+        }
+      }
+  if (nacc > 0) *dst = (uint32_t)(acc << (32 - nacc));
+  const uint32_t meta = w.meta[blk];
+  uint32_t *tab = (uint32_t *)(out + h.off_table) + 2 * blk;
+  tab[0] = w.words[blk];
+  tab[1] = meta;
+  if (__builtin_expect((meta >> 1) != 0, 0)) {
+    const T *src = (const T *)w.vals + blk * (uint64_t)g.bpts;
+    T *od = (T *)(out + h.off_outliers) + w.off_out[blk];
+    for (uint32_t t = 0; t < (meta >> 1); t++) od[t] = src[t];
+  }
+  if (meta & 1u) {
+    const T *cf = (const T *)w.coef + 4 * blk;
+    T *cd = (T *)(out + h.off_coef) + 4ull * w.off_coef[blk];
+    for (int a = 0; a < 4; a++) cd[a] = cf[a];
+  }
+  if (h.abft) ((uint64_t *)(out + h.off_sumdc))[blk] = w.sum_dc[blk];
+}
+
+template __global__ void k_check_fast<6, 6, 6>(Geo, CompWork, uint32_t);
+template __global__ void k_encode_fast<float, 6, 6, 6>(Geo, CompWork, uint8_t *, Header);
+template __global__ void k_encode_fast<double, 6, 6, 6>(Geo, CompWork, uint8_t *, Header);
+
+}  // namespace sdcsz

@@ -86,11 +86,9 @@ __device__ bool decode_block_generic(const uint8_t *__restrict__ s, const Header
 // mode 1: verify the caller's `out` (decode only on mismatch); mode 2: region
 // [lo, hi) into `out` laid out over the region.
 template <typename T>
-__global__ void __launch_bounds__(64)
-k_decode_generic(const uint8_t *__restrict__ s, Header h, Geo g, DecWork w, PlanDev plan, T *out,
-                 uint32_t mode, Region reg) {
-  const uint64_t blk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (blk >= g.n_blocks) return;
+__device__ __noinline__ void decode_one(const uint8_t *__restrict__ s, const Header &h, const Geo &g,
+                                        const DecWork &w, const PlanDev &plan, T *out, uint32_t mode,
+                                        const Region &reg, uint64_t blk) {
   const Box b = box_of(g, blk);
   if (mode == 2) {
     for (int a = 0; a < 3; a++)
@@ -187,7 +185,60 @@ k_decode_generic(const uint8_t *__restrict__ s, Header h, Geo g, DecWork w, Plan
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(64)
+k_decode_generic(const uint8_t *__restrict__ s, Header h, Geo g, DecWork w, PlanDev plan, T *out, uint32_t mode,
+                 Region reg) {
+  const uint64_t blk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (blk < g.n_blocks) decode_one<T>(s, h, g, w, plan, out, mode, reg, blk);
+}
+
+// full decompression of listed blocks (the blocks a fault plan names)
+template <typename T>
+__global__ void __launch_bounds__(64)
+k_decode_list(const uint8_t *__restrict__ s, Header h, Geo g, DecWork w, PlanDev plan, T *out,
+              const uint64_t *list, uint32_t n) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  Region reg{};
+  if (t < n) decode_one<T>(s, h, g, w, plan, out, 0, reg, list[t]);
+}
+
+// Blocks the specialised decoder queued: a checksum mismatch (already counted
+// as detected) is re-executed from the compressed bytes; a block that could
+// not be decoded is decoded once more and, failing again, zeroed.
+template <typename T>
+__global__ void __launch_bounds__(64)
+k_decode_redo(const uint8_t *__restrict__ s, Header h, Geo g, DecWork w, T *out) {
+  const uint32_t n = min(*w.redo_n, kMaxRedo);
+  const DecTab tab = *w.tab;
+  const T q = (T)(2.0 * h.eb_abs);
+  const uint64_t *sumdc = (const uint64_t *)(s + h.off_sumdc);
+  for (uint32_t e = threadIdx.x; e < n; e += blockDim.x) {
+    const uint64_t blk = w.redo[e] & ((1ull << 56) - 1), why = w.redo[e] >> 56;
+    const Box b = box_of(g, blk);
+    T *rec = (T *)w.recon + blk * (uint64_t)g.bpts;
+    bool ok = decode_block_generic<T>(s, h, g, b, blk, w, tab, q, rec);
+    if (ok && h.abft) {
+      uint64_t sum = 0;
+      for (uint32_t p = 0; p < b.pts; p++) sum += Wd<T>::sum(rec[p]);
+      ok = sum == sumdc[blk];
+    }
+    if (!ok)
+      for (uint32_t p = 0; p < b.pts; p++) rec[p] = (T)0;
+    if (ok || why == 2)
+      for (uint32_t i = 0, p = 0; i < b.n[0]; i++)
+        for (uint32_t j = 0; j < b.n[1]; j++)
+          for (uint32_t k = 0; k < b.n[2]; k++, p++) out[fidx(g, b, i, j, k)] = rec[p];
+    if (ok) count(w.cnt, C_COR + SDCSZ_T_RECON);
+    else count(w.cnt, C_UNC + SDCSZ_T_RECON);
+  }
+}
+
 template __global__ void k_decode_generic<float>(const uint8_t *, Header, Geo, DecWork, PlanDev, float *, uint32_t, Region);
 template __global__ void k_decode_generic<double>(const uint8_t *, Header, Geo, DecWork, PlanDev, double *, uint32_t, Region);
+template __global__ void k_decode_list<float>(const uint8_t *, Header, Geo, DecWork, PlanDev, float *, const uint64_t *, uint32_t);
+template __global__ void k_decode_list<double>(const uint8_t *, Header, Geo, DecWork, PlanDev, double *, const uint64_t *, uint32_t);
+template __global__ void k_decode_redo<float>(const uint8_t *, Header, Geo, DecWork, float *);
+template __global__ void k_decode_redo<double>(const uint8_t *, Header, Geo, DecWork, double *);
 
 }  // namespace sdcsz

@@ -16,16 +16,30 @@ __global__ void k_zero_u32(uint32_t *p, uint64_t n) {
 }
 
 // ---- value range of the finite values (value-range relative bound) ----------
+template <typename T> __device__ inline void minmax_finite(T v, T &lo, T &hi) {
+  const bool f = isfinite(v);
+  lo = (f && v < lo) ? v : lo;
+  hi = (f && v > hi) ? v : hi;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kRangeThreads) k_range(const T *__restrict__ in, uint64_t n, double *part) {
   T lo = (T)INFINITY, hi = (T)-INFINITY;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-    T v = in[i];
-    if (isfinite(v)) {
-      lo = v < lo ? v : lo;
-      hi = v > hi ? v : hi;
-    }
+  // 16-byte vector loads over the aligned body, scalar loads for the rest
+  constexpr uint32_t V = 16 / sizeof(T);
+  const uint64_t head = (((uintptr_t)in & 15) ? (16 - ((uintptr_t)in & 15)) / sizeof(T) : 0);
+  const uint64_t h = head < n ? head : n;
+  const uint64_t nv = (n - h) / V;
+  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, nth = (uint64_t)gridDim.x * blockDim.x;
+  typedef T vec_t __attribute__((ext_vector_type(V)));
+  const vec_t *vin = (const vec_t *)(in + h);
+  for (uint64_t i = tid; i < nv; i += nth) {
+    const vec_t v = vin[i];
+#pragma unroll
+    for (uint32_t c = 0; c < V; c++) minmax_finite<T>(v[c], lo, hi);
   }
+  for (uint64_t i = tid; i < h; i += nth) minmax_finite<T>(in[i], lo, hi);
+  for (uint64_t i = h + nv * V + tid; i < n; i += nth) minmax_finite<T>(in[i], lo, hi);
   __shared__ double slo[kRangeThreads], shi[kRangeThreads];
   slo[threadIdx.x] = (double)lo;
   shi[threadIdx.x] = (double)hi;
@@ -46,15 +60,31 @@ template __global__ void k_range<float>(const float *, uint64_t, double *);
 template __global__ void k_range<double>(const double *, uint64_t, double *);
 
 // eb_abs and its derived constants, computed in double then rounded once.
-__global__ void k_consts(const double *part, uint32_t nparts, uint32_t mode, double eb, EbDev *out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double eb_abs = eb;
-  if (mode == SDCSZ_REL) {
-    double lo = INFINITY, hi = -INFINITY;
-    for (uint32_t i = 0; i < nparts; i++) {
+__global__ void __launch_bounds__(256) k_consts(const double *part, uint32_t nparts, uint32_t mode, double eb,
+                                                 EbDev *out) {
+  // min/max are order-free, so a tree reduction gives the exact extremes
+  __shared__ double slo[256], shi[256];
+  double lo = INFINITY, hi = -INFINITY;
+  if (mode == SDCSZ_REL)
+    for (uint32_t i = threadIdx.x; i < nparts; i += blockDim.x) {
       lo = fmin(lo, part[2 * i]);
       hi = fmax(hi, part[2 * i + 1]);
     }
+  slo[threadIdx.x] = lo;
+  shi[threadIdx.x] = hi;
+  __syncthreads();
+  for (uint32_t s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + s]);
+      shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  double eb_abs = eb;
+  if (mode == SDCSZ_REL) {
+    lo = slo[0];
+    hi = shi[0];
     eb_abs = lo <= hi ? eb * (hi - lo) : 0.0;
   }
   EbDev e;
@@ -69,11 +99,11 @@ __global__ void k_consts(const double *part, uint32_t nparts, uint32_t mode, dou
   // result is subnormal), so a margin of 1e-6 on either side of eb leaves the
   // double comparison the only judge inside the band
   const double dlo = eb_abs * (1.0 - 1e-6), dhi = eb_abs * (1.0 + 1e-6);
-  float lo = (float)dlo, hi = (float)dhi;
-  if ((double)lo > dlo) lo = nextafterf(lo, 0.0f);
-  if ((double)hi < dhi) hi = nextafterf(hi, INFINITY);
-  e.lo = lo;
-  e.hi = hi;
+  float flo = (float)dlo, fhi = (float)dhi;
+  if ((double)flo > dlo) flo = nextafterf(flo, 0.0f);
+  if ((double)fhi < dhi) fhi = nextafterf(fhi, INFINITY);
+  e.lo = flo;
+  e.hi = fhi;
   *out = e;
 }
 
