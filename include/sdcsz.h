@@ -109,14 +109,17 @@ uint64_t sdcsz_compress_workspace_size(const sdcsz_params *p);
  * Huffman code over all codes, detection/correction of the codes and
  * per-block encoding.
  *   d_in      device, dims[0]*dims[1]*dims[2] values of dtype, C order; read only
- *   d_out     device, out_cap bytes; receives the stream
+ *   d_out     device, out_cap bytes, 8-byte aligned; receives the stream.
+ *             Nothing is written to it on SDCSZ_ENOSPC or SDCSZ_ESDC.
  *   h_out_size host; receives the stream size (also on SDCSZ_ENOSPC: the
  *             required size)
  *   h_rep     host, may be NULL; fault counters and stream statistics
  *   d_ws      device workspace of ws_size >= sdcsz_compress_workspace_size(p)
  * Returns SDCSZ_OK, SDCSZ_EINVAL, SDCSZ_ENOSPC, SDCSZ_ESDC (an uncorrectable
  * corruption, or a code without codeword when ABFT is off), SDCSZ_EHIP.
- * Synchronises `stream`.
+ * Synchronises `stream` twice: for the code histogram (the Huffman code is
+ * built on the host) and at the end.  The calling thread keeps a pinned
+ * host staging buffer of about 0.75 MiB from its first call on.
  */
 int sdcsz_compress(const void *d_in, const sdcsz_params *p, void *d_out, uint64_t out_cap,
                    uint64_t *h_out_size, sdcsz_report *h_rep, void *d_ws, uint64_t ws_size,

@@ -18,6 +18,9 @@ constexpr uint32_t kMaxBlockPts = 8192;
 constexpr uint32_t kMaxPatches = 8;  // fault-plan entries per block and call
 constexpr uint32_t kMaxRedo = 4096;  // blocks re-run after a detected mismatch
 
+// Result slots (u64) of a compression call, next to the counters.
+enum { R_SIZE = 0, R_OUTLIERS, R_REGRESSION, R_WORDS, R_WRITTEN, R_EB, R_N = 8 };
+
 // Counter slots (u64) in the device report area.
 enum {
   C_INJ = 0,
@@ -86,6 +89,10 @@ struct CompWork {
   EbDev *eb;
   uint32_t *redo_n;    // blocks queued for a re-run
   uint64_t *redo;      // kMaxRedo block ids
+  struct Header *hdr;  // stream header, filled on the device
+  uint64_t *res;       // R_* results of the call, read back once at its end
+  uint32_t *cb;        // n_sym pairs (symbol << 8 | length, codeword), ascending symbols
+  uint64_t *tot;       // scanned totals: payload words, outliers, regression blocks
 };
 
 // Decoder tables built from the stream's codebook (canonical code).
@@ -108,6 +115,8 @@ struct DecWork {
   uint32_t *lut;       // 2^kLutBits entries: symbol << 8 | length (0: longer code)
   uint32_t *redo_n;    // blocks queued for re-execution
   uint64_t *redo;      // kMaxRedo entries: block | reason << 56
+  uint32_t *err;       // non-zero: the codebook or the block table is not valid
+  uint64_t *tot;       // scanned totals: payload words, outliers, regression blocks
 };
 
 constexpr uint32_t kLutBits = 11;  // codeword prefix resolved by one table lookup
@@ -124,5 +133,20 @@ struct Header {
   uint64_t off_codebook, off_table, off_coef, off_sumdc, off_outliers, off_payload, total;
   uint32_t predictor;
 };
+
+__host__ __device__ inline uint64_t align8(uint64_t v) { return (v + 7) & ~7ull; }
+
+// Section offsets from the counts in the header: codebook, block table,
+// coefficients, sum_dc (ABFT only), outliers, payload; each 8-byte aligned.
+__host__ __device__ inline void section_offsets(Header &h) {
+  const uint64_t vb = h.dtype == SDCSZ_F32 ? 4 : 8;
+  h.off_codebook = kHeader;
+  h.off_table = align8(h.off_codebook + 4ull * h.n_sym);
+  h.off_coef = h.off_table + 8ull * h.n_blocks;
+  h.off_sumdc = align8(h.off_coef + 4ull * vb * h.n_regression);
+  h.off_outliers = h.off_sumdc + (h.abft ? 8ull * h.n_blocks : 0);
+  h.off_payload = align8(h.off_outliers + vb * h.n_outliers);
+  h.total = align8(h.off_payload + 4ull * h.payload_words);
+}
 
 }  // namespace sdcsz

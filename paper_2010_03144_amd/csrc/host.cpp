@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "common.h"
+#include "huffman.h"
 #include "kern.h"
 
 using namespace sdcsz;
@@ -68,7 +69,6 @@ PhaseTimer g_timer;
 
 uint32_t grid_for(uint64_t n, uint32_t per) { return (uint32_t)std::max<uint64_t>(1, (n + per - 1) / per); }
 uint64_t a256(uint64_t v) { return (v + 255) & ~255ull; }
-uint64_t a8(uint64_t v) { return (v + 7) & ~7ull; }
 uint32_t vbytes(uint32_t dtype) { return dtype == SDCSZ_F32 ? 4u : 8u; }
 
 // ---------------------------------------------------------------------------
@@ -180,8 +180,9 @@ template <typename T> RegTab<T> reg_table(const Geo &g) {
 // workspace layouts
 // ---------------------------------------------------------------------------
 struct CompLayout {
-  uint64_t cnt, eb, range, hist, enc, codes, vals, recon, meta, words, coef, sum_dc, sum_q, isum_q;
-  uint64_t off_pay, off_out, off_coef, scan, plan, bits, redo_n, redo, plan_blocks, total;
+  uint64_t cnt, res, redo_n, hist, enc, zero_end;
+  uint64_t eb, range, codes, vals, recon, meta, words, coef, sum_dc, sum_q, isum_q;
+  uint64_t off_pay, off_out, off_coef, scan, tot, plan, bits, redo, plan_blocks, hdr, cb, total;
 };
 
 CompLayout comp_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
@@ -194,11 +195,16 @@ CompLayout comp_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
     at = a256(at + bytes);
     return o;
   };
-  L.cnt = take(8 * C_N);
-  L.eb = take(sizeof(EbDev));
-  L.range = take(16ull * kRangeBlocks);
+  // cleared by one launch at the start of a call: counters, results, redo
+  // count, histogram and codeword table
+  L.cnt = take(8 * C_N + 8 * R_N + 8);
+  L.res = L.cnt + 8 * C_N;
+  L.redo_n = L.res + 8 * R_N;
   L.hist = take(4 * 65536);
   L.enc = take(4 * 65536);
+  L.zero_end = at;
+  L.eb = take(sizeof(EbDev));
+  L.range = take(16ull * kRangeBlocks);
   L.codes = take(2ull * 256 * g.groups * ((nb + 63) / 64));
   L.vals = take(vb * slots);
   L.recon = take(vb * slots);
@@ -212,11 +218,13 @@ CompLayout comp_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
   L.off_out = take(4 * (nb + 1));
   L.off_coef = take(4 * (nb + 1));
   L.scan = take(24 * chunks);
+  L.tot = take(24);
   L.plan = take(sizeof(sdcsz_fault) * (uint64_t)std::max<uint32_t>(nfaults, 1));
   L.bits = take(4 * (nb / 32 + 1));
-  L.redo_n = take(4);
   L.redo = take(8ull * kMaxRedo);
   L.plan_blocks = take(8ull * std::max<uint32_t>(nfaults, 1));
+  L.hdr = take(sizeof(Header));
+  L.cb = take(8ull * 65536);
   L.total = at;
   return L;
 }
@@ -263,7 +271,8 @@ void launch_fast(const T *in, const Geo &g, const RegTab<T> &rt, const PlanDev &
 }
 
 struct DecLayout {
-  uint64_t cnt, symbols, tab, recon, off_pay, off_out, off_coef, scan, plan, bits, lut, redo_n, redo, plan_blocks;
+  uint64_t cnt, redo_n, err, zero_end;
+  uint64_t symbols, tab, recon, off_pay, off_out, off_coef, scan, tot, plan, bits, lut, redo, plan_blocks;
   uint64_t total;
 };
 
@@ -277,7 +286,11 @@ DecLayout dec_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
     at = a256(at + bytes);
     return o;
   };
-  L.cnt = take(8 * C_N);
+  // counters, redo count and error flag: cleared together, read back together
+  L.cnt = take(8 * C_N + 8);
+  L.redo_n = L.cnt + 8 * C_N;
+  L.err = L.redo_n + 4;
+  L.zero_end = at;
   L.symbols = take(2 * 65536);
   L.tab = take(sizeof(DecTab));
   L.recon = take(vb * slots);
@@ -285,10 +298,10 @@ DecLayout dec_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
   L.off_out = take(4 * (nb + 1));
   L.off_coef = take(4 * (nb + 1));
   L.scan = take(24 * chunks);
+  L.tot = take(24);
   L.plan = take(sizeof(sdcsz_fault) * (uint64_t)std::max<uint32_t>(nfaults, 1));
   L.bits = take(4 * (nb / 32 + 1));
   L.lut = take(4ull << kLutBits);
-  L.redo_n = take(4);
   L.redo = take(8ull * kMaxRedo);
   L.plan_blocks = take(8ull * std::max<uint32_t>(nfaults, 1));
   L.total = at;
@@ -296,144 +309,38 @@ DecLayout dec_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
 }
 
 // ---------------------------------------------------------------------------
-// Huffman code: symbols with a non-zero count ordered by (count, symbol),
-// merged with two queues (ties go to the leaf queue); one symbol -> length 1;
-// deeper than 24 bits -> halve every count (minimum 1) and rebuild.
+// pinned host staging of the calling thread: the code histogram, the
+// codebook list and each call's results cross PCIe through it.  Allocated
+// on first use and kept until the process ends.
 // ---------------------------------------------------------------------------
-void tree_lengths(const std::vector<uint64_t> &cnt, std::vector<uint8_t> &len) {
-  len.assign(65536, 0);
-  std::vector<uint32_t> sym;
-  sym.reserve(1024);
-  for (uint32_t s = 0; s < 65536; s++)
-    if (cnt[s]) sym.push_back(s);
-  const size_t S = sym.size();
-  if (S == 0) return;
-  if (S == 1) {
-    len[sym[0]] = 1;
-    return;
-  }
-  std::sort(sym.begin(), sym.end(), [&](uint32_t a, uint32_t b) {
-    return cnt[a] != cnt[b] ? cnt[a] < cnt[b] : a < b;
-  });
-  // nodes 0..S-1 leaves (in sorted order), S.. internal in creation order
-  std::vector<uint64_t> wgt(2 * S - 1);
-  std::vector<uint32_t> up(2 * S - 1, 0);
-  for (size_t i = 0; i < S; i++) wgt[i] = cnt[sym[i]];
-  size_t li = 0, ii = S, top = S;
-  for (size_t m = 0; m + 1 < S; m++) {
-    size_t pick[2];
-    for (int r = 0; r < 2; r++) {
-      bool leaf = li < S && (ii >= top || wgt[li] <= wgt[ii]);
-      pick[r] = leaf ? li++ : ii++;
-    }
-    wgt[top] = wgt[pick[0]] + wgt[pick[1]];
-    up[pick[0]] = up[pick[1]] = (uint32_t)top;
-    top++;
-  }
-  // depth of node v = depth(parent) + 1; parents have larger indices
-  std::vector<uint32_t> dep(2 * S - 1, 0);
-  for (size_t v = 2 * S - 1; v-- > 0;)
-    if (v != 2 * S - 2) dep[v] = dep[up[v]] + 1;
-  for (size_t i = 0; i < S; i++) len[sym[i]] = (uint8_t)std::min<uint32_t>(dep[i], 255);
-}
+constexpr size_t kStageHist = 0;                             // 65536 u32 counts
+constexpr size_t kStageCb = kStageHist + 4 * 65536;         // 65536 pairs of u32
+constexpr size_t kStageRes = kStageCb + 8 * 65536;          // results of the call
+constexpr size_t kStageBytes = kStageRes + 8 * (C_N + R_N + 2);
 
-void code_lengths(const uint32_t *hist, std::vector<uint8_t> &len) {
-  std::vector<uint64_t> cnt(hist, hist + 65536);
-  for (;;) {
-    tree_lengths(cnt, len);
-    if (*std::max_element(len.begin(), len.end()) <= kMaxLen) return;
-    for (auto &c : cnt)
-      if (c) c = std::max<uint64_t>(1, c >> 1);
+struct Staging {
+  uint8_t *p = nullptr;
+  uint8_t *get() {
+    if (!p && hipHostMalloc((void **)&p, kStageBytes, hipHostMallocDefault) != hipSuccess) p = nullptr;
+    return p;
   }
-}
-
-// Canonical codes by length counts (codes of one length are consecutive in
-// symbol order; the first code of length l is (first(l-1) + count(l-1)) << 1).
-struct Canon {
-  uint32_t bl_count[kMaxLen + 2] = {0};
-  uint32_t first[kMaxLen + 2] = {0};
-  uint32_t start[kMaxLen + 2] = {0};
 };
-
-Canon canonical(const std::vector<uint8_t> &len, std::vector<uint32_t> *codes, std::vector<uint16_t> *order) {
-  Canon C;
-  for (uint32_t s = 0; s < 65536; s++)
-    if (len[s]) C.bl_count[len[s]]++;
-  uint32_t code = 0, acc = 0;
-  for (uint32_t l = 1; l <= kMaxLen; l++) {
-    code = (code + C.bl_count[l - 1]) << 1;
-    C.first[l] = code;
-    C.start[l] = acc;
-    acc += C.bl_count[l];
-  }
-  C.first[1] = 0;
-  if (codes) {
-    codes->assign(65536, 0);
-    std::vector<uint32_t> next(C.first, C.first + kMaxLen + 2);
-    for (uint32_t s = 0; s < 65536; s++)
-      if (len[s]) (*codes)[s] = next[len[s]]++;
-  }
-  if (order) {
-    order->assign(65536, 0);
-    std::vector<uint32_t> pos(C.start, C.start + kMaxLen + 2);
-    for (uint32_t s = 0; s < 65536; s++)
-      if (len[s]) (*order)[pos[len[s]]++] = (uint16_t)s;
-  }
-  return C;
-}
+thread_local Staging t_stage;
 
 // ---------------------------------------------------------------------------
 // header
 // ---------------------------------------------------------------------------
 const uint8_t kMagic[8] = {'S', 'D', 'C', 'S', 'Z', 0, 'v', '1'};
 
-void section_offsets(Header &h) {
-  const uint64_t vb = vbytes(h.dtype);
-  h.off_codebook = kHeader;
-  h.off_table = a8(h.off_codebook + 4ull * h.n_sym);
-  h.off_coef = h.off_table + 8ull * h.n_blocks;
-  h.off_sumdc = a8(h.off_coef + 4ull * vb * h.n_regression);
-  h.off_outliers = h.off_sumdc + (h.abft ? 8ull * h.n_blocks : 0);
-  h.off_payload = a8(h.off_outliers + vb * h.n_outliers);
-  h.total = a8(h.off_payload + 4ull * h.payload_words);
-}
-
-template <typename V> void put(uint8_t *b, uint64_t off, V v) { std::memcpy(b + off, &v, sizeof(V)); }
 template <typename V> V get(const uint8_t *b, uint64_t off) {
   V v;
   std::memcpy(&v, b + off, sizeof(V));
   return v;
 }
 
-void pack_header(const Header &h, uint8_t *o) {
-  std::memset(o, 0, kHeader);
-  std::memcpy(o, kMagic, 8);
-  put<uint32_t>(o, 8, h.dtype);
-  put<uint32_t>(o, 12, h.ndim);
-  for (int a = 0; a < 3; a++) put<uint64_t>(o, 16 + 8 * a, h.d[a]);
-  for (int a = 0; a < 3; a++) put<uint32_t>(o, 40 + 4 * a, h.b[a]);
-  put<uint32_t>(o, 52, h.eb_mode);
-  put<double>(o, 56, h.eb);
-  put<double>(o, 64, h.eb_abs);
-  put<uint32_t>(o, 72, h.abft);
-  put<uint32_t>(o, 76, h.n_sym);
-  put<uint64_t>(o, 80, h.n_blocks);
-  put<uint64_t>(o, 88, h.n_outliers);
-  put<uint64_t>(o, 96, h.n_regression);
-  put<uint64_t>(o, 104, h.payload_words);
-  put<uint64_t>(o, 112, h.off_codebook);
-  put<uint64_t>(o, 120, h.off_table);
-  put<uint64_t>(o, 128, h.off_coef);
-  put<uint64_t>(o, 136, h.off_sumdc);
-  put<uint64_t>(o, 144, h.off_outliers);
-  put<uint64_t>(o, 152, h.off_payload);
-  put<uint64_t>(o, 160, h.total);
-  put<uint32_t>(o, 168, h.predictor);
-}
-
 // parse + validate the header (and its geometry) from host bytes
-int unpack_header(const uint8_t *o, uint64_t avail, uint64_t stream_size, Header &h, Geo &g) {
-  if (avail < kHeader || stream_size < kHeader || std::memcmp(o, kMagic, 8) != 0) return SDCSZ_EFORMAT;
+int unpack_header(const uint8_t *o, uint64_t stream_size, Header &h, Geo &g) {
+  if (stream_size < kHeader || std::memcmp(o, kMagic, 8) != 0) return SDCSZ_EFORMAT;
   h.dtype = get<uint32_t>(o, 8);
   h.ndim = get<uint32_t>(o, 12);
   for (int a = 0; a < 3; a++) h.d[a] = get<uint64_t>(o, 16 + 8 * a);
@@ -482,8 +389,8 @@ void fill_report(sdcsz_report *r, const unsigned long long *cnt, uint64_t nb) {
   }
 }
 
-
-// upload a sorted plan and its per-block bitmap
+// upload a sorted plan and its per-block bitmap (from pageable memory: the
+// vectors must live until the stream has passed the copies)
 int upload_plan(const std::vector<sdcsz_fault> &pl, uint64_t nb, uint8_t *ws, uint64_t off_plan,
                 uint64_t off_bits, std::vector<uint32_t> &bits_host, hipStream_t st, PlanDev *pd) {
   pd->n = (uint32_t)pl.size();
@@ -497,23 +404,36 @@ int upload_plan(const std::vector<sdcsz_fault> &pl, uint64_t nb, uint8_t *ws, ui
   return SDCSZ_OK;
 }
 
+// exclusive scans of payload words, outliers and regression flags per block,
+// with the 64-bit totals in tot[0..2]
 int launch_scan(ScanSrc src, uint64_t n, uint64_t *part, uint64_t *off_pay, uint32_t *off_out,
-                uint32_t *off_coef, hipStream_t st) {
+                uint32_t *off_coef, uint64_t *tot, hipStream_t st) {
   if (n == 0) {
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, (unsigned long long *)off_pay, 1);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, off_out, 1);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, off_coef, 1);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, (unsigned long long *)tot, 3);
     return hipGetLastError() == hipSuccess ? SDCSZ_OK : SDCSZ_EHIP;
   }
   uint32_t chunks = (uint32_t)((n + kScanChunk - 1) / kScanChunk);
   hipLaunchKernelGGL(k_scan1, dim3(chunks), dim3(kScanThreads), 0, st, src, n, part);
   hipLaunchKernelGGL(k_scan2, dim3(1), dim3(kScanThreads), 0, st, part, chunks);
-  hipLaunchKernelGGL(k_scan3, dim3(chunks), dim3(kScanThreads), 0, st, src, n, part, off_pay, off_out, off_coef);
+  hipLaunchKernelGGL(k_scan3, dim3(chunks), dim3(kScanThreads), 0, st, src, n, part, off_pay, off_out, off_coef,
+                     tot);
   return hipGetLastError() == hipSuccess ? SDCSZ_OK : SDCSZ_EHIP;
 }
 
+// distinct blocks of a sorted plan
+std::vector<uint64_t> plan_block_list(const std::vector<sdcsz_fault> &plan) {
+  std::vector<uint64_t> pb;
+  for (auto &f : plan)
+    if (pb.empty() || pb.back() != f.block) pb.push_back(f.block);
+  return pb;
+}
+
 // ---------------------------------------------------------------------------
-// compression
+// compression: two host synchronisations, one for the code histogram (the
+// Huffman code is built on the host) and one for the results at the end
 // ---------------------------------------------------------------------------
 template <typename T>
 int compress_t(const void *d_in, const sdcsz_params *p, const Geo &g, uint8_t *d_out, uint64_t out_cap,
@@ -523,6 +443,8 @@ int compress_t(const void *d_in, const sdcsz_params *p, const Geo &g, uint8_t *d
   if (rc) return rc;
   const CompLayout L = comp_layout(g, p->dtype, p->n_faults);
   if (!ws || ws_size < L.total) return SDCSZ_ENOSPC;
+  uint8_t *hs = t_stage.get();
+  if (!hs) return SDCSZ_EHIP;
   CompWork w;
   w.codes = (uint16_t *)(ws + L.codes);
   w.vals = ws + L.vals;
@@ -544,14 +466,19 @@ int compress_t(const void *d_in, const sdcsz_params *p, const Geo &g, uint8_t *d
   w.eb = (EbDev *)(ws + L.eb);
   w.redo_n = (uint32_t *)(ws + L.redo_n);
   w.redo = (uint64_t *)(ws + L.redo);
+  w.hdr = (Header *)(ws + L.hdr);
+  w.res = (uint64_t *)(ws + L.res);
+  w.cb = (uint32_t *)(ws + L.cb);
+  w.tot = (uint64_t *)(ws + L.tot);
 
+  // host vectors read by asynchronous copies live until the histogram sync
   std::vector<uint32_t> bits_host;
   PlanDev pd;
   rc = upload_plan(plan, g.n_blocks, ws, L.plan, L.bits, bits_host, st, &pd);
   if (rc) return rc;
+  const std::vector<uint64_t> pb = plan_block_list(plan);
 
-  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, w.cnt, (uint64_t)C_N);
-  hipLaunchKernelGGL(k_zero_u32, dim3(256), dim3(256), 0, st, w.hist, (uint64_t)65536);
+  hipLaunchKernelGGL(k_zero_u32, dim3(256), dim3(256), 0, st, (uint32_t *)ws, L.zero_end / 4);
   uint32_t nparts = 0;
   g_timer.begin(PH_RANGE, st);
   if (p->eb_mode == SDCSZ_REL && g.n_values) {
@@ -564,21 +491,17 @@ int compress_t(const void *d_in, const sdcsz_params *p, const Geo &g, uint8_t *d
   g_timer.end(PH_RANGE, st);
   HIPCHK(hipGetLastError());
 
+  const bool fast = g.n_blocks && fast_shape(g, sizeof(T));
   if (g.n_blocks) {
     const RegTab<T> rt = reg_table<T>(g);
     g_timer.begin(PH_PREDICT, st);
-    if (fast_shape(g, sizeof(T))) {
+    if (fast) {
       // the distinct blocks the plan names run through the generic routine
-      std::vector<uint64_t> pb;
-      for (auto &f : plan)
-        if (pb.empty() || pb.back() != f.block) pb.push_back(f.block);
       const uint64_t *d_pb = (const uint64_t *)(ws + L.plan_blocks);
       if (!pb.empty())
         HIPCHK(hipMemcpyAsync(ws + L.plan_blocks, pb.data(), 8 * pb.size(), hipMemcpyHostToDevice, st));
-      hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, w.redo_n, (uint64_t)1);
       if (p->abft) launch_fast<T, true>((const T *)d_in, g, rt, pd, w, p->predictor, d_pb, (uint32_t)pb.size(), st);
       else launch_fast<T, false>((const T *)d_in, g, rt, pd, w, p->predictor, d_pb, (uint32_t)pb.size(), st);
-      if (!pb.empty()) HIPCHK(hipStreamSynchronize(st));  // keeps pb alive until its copy is done
     } else {
       hipLaunchKernelGGL(k_compress_generic<T>, dim3(grid_for(g.n_blocks, 64)), dim3(64), 0, st,
                          (const T *)d_in, g, rt, pd, w, p->abft, p->predictor);
@@ -595,58 +518,46 @@ int compress_t(const void *d_in, const sdcsz_params *p, const Geo &g, uint8_t *d
   }
 
   // Huffman code over the whole field's codes (host)
-  std::vector<uint32_t> hist(65536);
-  HIPCHK(hipMemcpyAsync(hist.data(), w.hist, 4 * 65536, hipMemcpyDeviceToHost, st));
-  EbDev ebh;
-  HIPCHK(hipMemcpyAsync(&ebh, w.eb, sizeof(EbDev), hipMemcpyDeviceToHost, st));
+  const uint32_t *hist = (const uint32_t *)(hs + kStageHist);
+  HIPCHK(hipMemcpyAsync(hs + kStageHist, w.hist, 4 * 65536, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  std::vector<uint32_t> used;
+  std::vector<uint64_t> counts;
+  for (uint32_t s = 0; s < 65536; s++)
+    if (hist[s]) {
+      used.push_back(s);
+      counts.push_back(hist[s]);
+    }
   std::vector<uint8_t> len;
-  code_lengths(hist.data(), len);
   std::vector<uint32_t> codes;
-  canonical(len, &codes, nullptr);
-  std::vector<uint32_t> enc(65536);
-  uint32_t n_sym = 0;
-  for (uint32_t s = 0; s < 65536; s++) {
-    enc[s] = (codes[s] << 8) | len[s];
-    n_sym += len[s] ? 1 : 0;
+  huffman_lengths(counts, kMaxLen, len);
+  canonical_codes(len, kMaxLen, codes);
+  const uint32_t n_sym = (uint32_t)used.size();
+  uint32_t *cb = (uint32_t *)(hs + kStageCb);
+  for (uint32_t t = 0; t < n_sym; t++) {
+    cb[2 * t] = (used[t] << 8) | len[t];
+    cb[2 * t + 1] = codes[t];
   }
-  HIPCHK(hipMemcpyAsync(w.enc, enc.data(), 4 * 65536, hipMemcpyHostToDevice, st));
+  if (n_sym) {
+    HIPCHK(hipMemcpyAsync(w.cb, cb, 8ull * n_sym, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_put_codes, dim3(grid_for(n_sym, 256)), dim3(256), 0, st, w.cb, n_sym, w.enc);
+  }
 
   if (g.n_blocks) {
     g_timer.begin(PH_CHECK, st);
-    if (fast_shape(g, sizeof(T)))
+    if (fast)
       hipLaunchKernelGGL((k_check_fast<6, 6, 6>), dim3(grid_for(g.n_blocks, 256)), dim3(256), 0, st, g, w, p->abft);
     else
       hipLaunchKernelGGL(k_codes_check, dim3(grid_for(g.n_blocks, 256)), dim3(256), 0, st, g, w, p->abft);
     g_timer.end(PH_CHECK, st);
-    ScanSrc src{w.words, w.meta, 1};
-    g_timer.begin(PH_SCAN_C, st);
-    rc = launch_scan(src, g.n_blocks, w.scan_part, w.off_pay, w.off_out, w.off_coef, st);
-    g_timer.end(PH_SCAN_C, st);
-    if (rc) return rc;
   }
-  uint64_t tot_pay = 0;
-  uint32_t tot_out = 0, tot_coef = 0;
-  unsigned long long cnt[C_N];
-  if (g.n_blocks) {
-    HIPCHK(hipMemcpyAsync(&tot_pay, w.off_pay + g.n_blocks, 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(&tot_out, w.off_out + g.n_blocks, 4, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(&tot_coef, w.off_coef + g.n_blocks, 4, hipMemcpyDeviceToHost, st));
-  }
-  HIPCHK(hipMemcpyAsync(cnt, w.cnt, sizeof(cnt), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  ScanSrc src{w.words, w.meta, 1};
+  g_timer.begin(PH_SCAN_C, st);
+  rc = launch_scan(src, g.n_blocks, w.scan_part, w.off_pay, w.off_out, w.off_coef, w.tot, st);
+  g_timer.end(PH_SCAN_C, st);
+  if (rc) return rc;
 
-  sdcsz_report rep;
-  fill_report(&rep, cnt, g.n_blocks);
-  rep.eb_abs = ebh.eb_abs;
-  bool unc = cnt[C_UNC + SDCSZ_T_INPUT] || cnt[C_UNC + SDCSZ_T_COEF] || cnt[C_UNC + SDCSZ_T_CODE] ||
-             cnt[C_MISSING];
-  if (unc) {
-    *h_out_size = 0;
-    if (h_rep) *h_rep = rep;
-    return SDCSZ_ESDC;
-  }
-
+  // header, codebook and pads on the device; the encoder follows its decision
   Header h;
   std::memset(&h, 0, sizeof(h));
   h.dtype = p->dtype;
@@ -657,61 +568,64 @@ int compress_t(const void *d_in, const sdcsz_params *p, const Geo &g, uint8_t *d
   }
   h.eb_mode = p->eb_mode;
   h.eb = p->eb;
-  h.eb_abs = ebh.eb_abs;
   h.abft = p->abft;
   h.n_sym = n_sym;
   h.n_blocks = g.n_blocks;
-  h.n_outliers = tot_out;
-  h.n_regression = tot_coef;
-  h.payload_words = tot_pay;
   h.predictor = p->predictor;
-  section_offsets(h);
-  rep.n_outliers = h.n_outliers;
-  rep.n_regression = h.n_regression;
-  rep.payload_words = h.payload_words;
-  rep.stream_size = h.total;
-  *h_out_size = h.total;
-  if (h_rep) *h_rep = rep;
-  if (h.total > out_cap || !d_out) return SDCSZ_ENOSPC;
-
-  // header + codebook (with its padding) from the host; zero the tail pads
-  std::vector<uint8_t> head(h.off_table, 0);
-  pack_header(h, head.data());
-  for (uint32_t s = 0, t = 0; s < 65536; s++)
-    if (len[s]) put<uint32_t>(head.data(), kHeader + 4ull * t++, (s << 8) | len[s]);
-  HIPCHK(hipMemcpyAsync(d_out, head.data(), head.size(), hipMemcpyHostToDevice, st));
-  if (h.off_payload > h.off_outliers)
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t *)(d_out + h.off_payload - 8), 2);
-  if (h.total > h.off_payload)
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t *)(d_out + h.total - 8), 2);
+  hipLaunchKernelGGL(k_header, dim3(grid_for(n_sym, 256)), dim3(256), 0, st, h, w, d_out, d_out ? out_cap : 0);
   g_timer.begin(PH_ENCODE, st);
-  if (g.n_blocks && fast_shape(g, sizeof(T)))
-    hipLaunchKernelGGL((k_encode_fast<T, 6, 6, 6>), dim3(grid_for(g.n_blocks, 256)), dim3(256), 0, st, g, w, d_out, h);
+  if (fast)
+    hipLaunchKernelGGL((k_encode_fast<T, 6, 6, 6>), dim3(grid_for(g.n_blocks, 256)), dim3(256), 0, st, g, w, d_out);
   else if (g.n_blocks)
-    hipLaunchKernelGGL(k_encode<T>, dim3(grid_for(g.n_blocks, 256)), dim3(256), 0, st, g, w, d_out, h);
+    hipLaunchKernelGGL(k_encode<T>, dim3(grid_for(g.n_blocks, 256)), dim3(256), 0, st, g, w, d_out);
   g_timer.end(PH_ENCODE, st);
   HIPCHK(hipGetLastError());
+
+  // counters and results: one copy, one synchronisation
+  unsigned long long *cnt = (unsigned long long *)(hs + kStageRes);
+  const uint64_t *res = (const uint64_t *)(hs + kStageRes + 8 * C_N);
+  HIPCHK(hipMemcpyAsync(hs + kStageRes, ws + L.cnt, 8 * (C_N + R_N), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   g_timer.resolve();
-  return SDCSZ_OK;
+
+  sdcsz_report rep;
+  fill_report(&rep, cnt, g.n_blocks);
+  double eb_abs;
+  std::memcpy(&eb_abs, &res[R_EB], 8);
+  rep.eb_abs = eb_abs;
+  const bool unc = cnt[C_UNC + SDCSZ_T_INPUT] || cnt[C_UNC + SDCSZ_T_COEF] || cnt[C_UNC + SDCSZ_T_CODE] ||
+                   cnt[C_MISSING];
+  if (unc) {
+    *h_out_size = 0;
+    if (h_rep) *h_rep = rep;
+    return SDCSZ_ESDC;
+  }
+  rep.n_outliers = res[R_OUTLIERS];
+  rep.n_regression = res[R_REGRESSION];
+  rep.payload_words = res[R_WORDS];
+  rep.stream_size = res[R_SIZE];
+  *h_out_size = res[R_SIZE];
+  if (h_rep) *h_rep = rep;
+  return res[R_WRITTEN] ? SDCSZ_OK : SDCSZ_ENOSPC;
 }
 
 // ---------------------------------------------------------------------------
-// decompression / verification / region
+// decompression / verification / region: one synchronisation for the header
+// (the host sizes the launches from it) and one for the results
 // ---------------------------------------------------------------------------
 struct Opened {
   Header h;
   Geo g;
-  std::vector<uint8_t> head;  // header + codebook bytes (host copy)
 };
 
 int open_stream(const void *d_stream, uint64_t size, hipStream_t st, Opened &o) {
   if (!d_stream) return SDCSZ_EINVAL;
-  uint64_t avail = std::min<uint64_t>(size, kHeader + 4ull * 65536);
-  o.head.assign(avail, 0);
-  HIPCHK(hipMemcpyAsync(o.head.data(), d_stream, avail, hipMemcpyDeviceToHost, st));
+  if (size < kHeader) return SDCSZ_EFORMAT;
+  uint8_t *hs = t_stage.get();
+  if (!hs) return SDCSZ_EHIP;
+  HIPCHK(hipMemcpyAsync(hs + kStageRes, d_stream, kHeader, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  return unpack_header(o.head.data(), avail, size, o.h, o.g);
+  return unpack_header(hs + kStageRes, size, o.h, o.g);
 }
 
 template <typename T>
@@ -725,38 +639,8 @@ int decode_t(const uint8_t *d_s, Opened &o, T *d_out, uint32_t mode, const Regio
   if (rc) return rc;
   const DecLayout L = dec_layout(g, h.dtype, n_faults);
   if (!ws || ws_size < L.total) return SDCSZ_ENOSPC;
-  // decoder tables from the codebook section
-  std::vector<uint8_t> len(65536, 0);
-  for (uint32_t t = 0; t < h.n_sym; t++) {
-    uint32_t e = get<uint32_t>(o.head.data(), kHeader + 4ull * t);
-    uint32_t s = e >> 8, l = e & 0xFF;
-    if (s > 65535 || l == 0 || l > kMaxLen || len[s]) return SDCSZ_EFORMAT;
-    len[s] = (uint8_t)l;
-  }
-  std::vector<uint16_t> order;
-  std::vector<uint32_t> codes;
-  Canon C = canonical(len, &codes, &order);
-  // one-lookup table for codewords of up to kLutBits bits
-  std::vector<uint32_t> lut(1u << kLutBits, 0);
-  for (uint32_t s = 0; s < 65536; s++)
-    if (len[s] && len[s] <= kLutBits) {
-      const uint32_t sh = kLutBits - len[s];
-      for (uint32_t v = codes[s] << sh; v < ((codes[s] + 1) << sh); v++) lut[v] = (s << 8) | len[s];
-    }
-  DecTab tab;
-  std::memset(&tab, 0, sizeof(tab));
-  tab.min_len = kMaxLen + 1;
-  tab.max_len = 0;
-  for (uint32_t l = 1; l <= kMaxLen; l++) {
-    tab.first[l] = C.first[l];
-    tab.count[l] = C.bl_count[l];
-    tab.start[l] = C.start[l];
-    if (C.bl_count[l]) {
-      tab.min_len = std::min(tab.min_len, l);
-      tab.max_len = std::max(tab.max_len, l);
-    }
-  }
-  if (tab.max_len == 0) tab.min_len = 1;
+  uint8_t *hs = t_stage.get();
+  if (!hs) return SDCSZ_EHIP;
   DecWork w;
   w.cnt = (unsigned long long *)(ws + L.cnt);
   w.symbols = (uint16_t *)(ws + L.symbols);
@@ -769,35 +653,28 @@ int decode_t(const uint8_t *d_s, Opened &o, T *d_out, uint32_t mode, const Regio
   w.lut = (uint32_t *)(ws + L.lut);
   w.redo_n = (uint32_t *)(ws + L.redo_n);
   w.redo = (uint64_t *)(ws + L.redo);
-  HIPCHK(hipMemcpyAsync(w.symbols, order.data(), 2 * 65536, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(w.tab, &tab, sizeof(tab), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(w.lut, lut.data(), 4ull << kLutBits, hipMemcpyHostToDevice, st));
+  w.err = (uint32_t *)(ws + L.err);
+  w.tot = (uint64_t *)(ws + L.tot);
   std::vector<uint32_t> bits_host;
   PlanDev pd;
   rc = upload_plan(plan, g.n_blocks, ws, L.plan, L.bits, bits_host, st, &pd);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, w.cnt, (uint64_t)C_N);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, st, (uint32_t *)ws, L.zero_end / 4);
+  // decoder tables from the codebook section, then the block table's scans
+  hipLaunchKernelGGL(k_dectab, dim3(1), dim3(256), 0, st, (const uint32_t *)(d_s + kHeader), h.n_sym, w);
   const uint32_t *table = (const uint32_t *)(d_s + h.off_table);
   ScanSrc src{table, table + 1, 2};
   g_timer.begin(PH_SCAN_D, st);
-  rc = launch_scan(src, g.n_blocks, w.scan_part, w.off_pay, w.off_out, w.off_coef, st);
+  rc = launch_scan(src, g.n_blocks, w.scan_part, w.off_pay, w.off_out, w.off_coef, w.tot, st);
+  hipLaunchKernelGGL(k_dec_check, dim3(1), dim3(64), 0, st, (const uint64_t *)w.tot, h.payload_words, h.n_outliers,
+                     h.n_regression, w.err);
   g_timer.end(PH_SCAN_D, st);
   if (rc) return rc;
-  uint64_t tot_pay = 0;
-  uint32_t tot_out = 0, tot_coef = 0;
-  HIPCHK(hipMemcpyAsync(&tot_pay, w.off_pay + g.n_blocks, 8, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(&tot_out, w.off_out + g.n_blocks, 4, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(&tot_coef, w.off_coef + g.n_blocks, 4, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  if (tot_pay != h.payload_words || tot_out != h.n_outliers || tot_coef != h.n_regression) return SDCSZ_EFORMAT;
   const bool fast = mode == 0 && fast_shape(g, sizeof(T));
-  std::vector<uint64_t> pb;
+  const std::vector<uint64_t> pb = plan_block_list(plan);
   if (g.n_blocks && fast) {
-    for (auto &f : plan)
-      if (pb.empty() || pb.back() != f.block) pb.push_back(f.block);
     const uint64_t *d_pb = (const uint64_t *)(ws + L.plan_blocks);
     if (!pb.empty()) HIPCHK(hipMemcpyAsync(ws + L.plan_blocks, pb.data(), 8 * pb.size(), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, w.redo_n, (uint64_t)1);
     g_timer.begin(PH_DECODE, st);
     if (!pb.empty())
       hipLaunchKernelGGL(k_decode_list<T>, dim3(grid_for(pb.size(), 64)), dim3(64), 0, st, d_s, h, g, w, pd, d_out,
@@ -816,18 +693,19 @@ int decode_t(const uint8_t *d_s, Opened &o, T *d_out, uint32_t mode, const Regio
     g_timer.end(PH_DECODE, st);
     HIPCHK(hipGetLastError());
   }
-  unsigned long long cnt[C_N];
-  uint32_t redo_n = 0;
-  HIPCHK(hipMemcpyAsync(cnt, w.cnt, sizeof(cnt), hipMemcpyDeviceToHost, st));
-  if (fast) HIPCHK(hipMemcpyAsync(&redo_n, w.redo_n, 4, hipMemcpyDeviceToHost, st));
+  // counters, redo count and error flag: one copy, one synchronisation
+  const unsigned long long *cnt = (const unsigned long long *)(hs + kStageRes);
+  const uint32_t *tail = (const uint32_t *)(hs + kStageRes + 8 * C_N);
+  HIPCHK(hipMemcpyAsync(hs + kStageRes, ws + L.cnt, 8 * C_N + 8, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   g_timer.resolve();
-  if (redo_n > kMaxRedo) {
+  if (tail[1]) return SDCSZ_EFORMAT;
+  if (fast && tail[0] > kMaxRedo) {
     // more blocks to re-execute than the queue holds: decode everything again
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, w.cnt, (uint64_t)C_N);
     hipLaunchKernelGGL(k_decode_generic<T>, dim3(grid_for(g.n_blocks, 64)), dim3(64), 0, st, d_s, h, g, w, pd,
                        d_out, mode, reg);
-    HIPCHK(hipMemcpyAsync(cnt, w.cnt, sizeof(cnt), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hs + kStageRes, w.cnt, 8 * C_N, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
   }
   sdcsz_report rep;

@@ -43,9 +43,14 @@ __global__ void k_codes_check(Geo g, CompWork w, uint32_t abft);
 __global__ void k_scan1(ScanSrc src, uint64_t n, uint64_t *part);
 __global__ void k_scan2(uint64_t *part, uint32_t nparts);
 __global__ void k_scan3(ScanSrc src, uint64_t n, const uint64_t *part, uint64_t *off_pay,
-                        uint32_t *off_out, uint32_t *off_coef);
+                        uint32_t *off_out, uint32_t *off_coef, uint64_t *tot);
+__global__ void k_put_codes(const uint32_t *cb, uint32_t n_sym, uint32_t *enc);
+__global__ void k_header(Header h, CompWork w, uint8_t *out, uint64_t out_cap);
+__global__ void k_dectab(const uint32_t *cbk, uint32_t n_sym, DecWork w);
+__global__ void k_dec_check(const uint64_t *tot, uint64_t payload_words, uint64_t n_outliers,
+                            uint64_t n_regression, uint32_t *err);
 template <typename T>
-__global__ void k_encode(Geo g, CompWork w, uint8_t *out, Header h);
+__global__ void k_encode(Geo g, CompWork w, uint8_t *out);
 
 template <typename T, int ND, int B0, int B1, int B2, bool ABFT>
 __global__ void k_compress_fast(const T *in, Geo g, RegTab<T> rt, PlanDev plan, CompWork w, uint32_t predictor,
@@ -67,7 +72,7 @@ __global__ void k_decode_redo(const uint8_t *s, Header h, Geo g, DecWork w, T *o
 
 template <int B0, int B1, int B2> __global__ void k_check_fast(Geo g, CompWork w, uint32_t abft);
 template <typename T, int B0, int B1, int B2>
-__global__ void k_encode_fast(Geo g, CompWork w, uint8_t *out, Header h);
+__global__ void k_encode_fast(Geo g, CompWork w, uint8_t *out);
 
 template <typename T>
 __global__ void k_compress_generic(const T *in, Geo g, RegTab<T> rt, PlanDev plan, CompWork w,

@@ -237,6 +237,7 @@ __device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, cons
 template <typename T, int ND, int B0, int B1, int B2>
 __global__ void __launch_bounds__(256)
 k_decode_fast(const uint8_t *__restrict__ s, Header h, Geo g, DecWork w, PlanDev plan, T *out, Launch L) {
+  if (*w.err) return;  // invalid codebook or block table: nothing is read
   __shared__ uint32_t lut[1u << kLutBits];
   for (uint32_t t = threadIdx.x; t < (1u << kLutBits); t += blockDim.x) lut[t] = w.lut[t];
   __syncthreads();

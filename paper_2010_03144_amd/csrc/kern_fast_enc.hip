@@ -108,7 +108,9 @@ __global__ void __launch_bounds__(256) k_check_fast(Geo g, CompWork w, uint32_t 
 // Per-block Huffman encoding (MSB first into 32-bit words) and the block's
 // table entry, coefficients, sum_dc and outliers at their scanned offsets.
 template <typename T, int B0, int B1, int B2>
-__global__ void __launch_bounds__(256) k_encode_fast(Geo g, CompWork w, uint8_t *out, Header h) {
+__global__ void __launch_bounds__(256) k_encode_fast(Geo g, CompWork w, uint8_t *out) {
+  if (!w.res[R_WRITTEN]) return;  // the stream is not written (see k_header)
+  const Header h = *w.hdr;
   __shared__ uint32_t encw[kEncWin];
   load_window(encw, w.enc);
   const uint64_t blk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -155,7 +157,7 @@ __global__ void __launch_bounds__(256) k_encode_fast(Geo g, CompWork w, uint8_t 
 }
 
 template __global__ void k_check_fast<6, 6, 6>(Geo, CompWork, uint32_t);
-template __global__ void k_encode_fast<float, 6, 6, 6>(Geo, CompWork, uint8_t *, Header);
-template __global__ void k_encode_fast<double, 6, 6, 6>(Geo, CompWork, uint8_t *, Header);
+template __global__ void k_encode_fast<float, 6, 6, 6>(Geo, CompWork, uint8_t *);
+template __global__ void k_encode_fast<double, 6, 6, 6>(Geo, CompWork, uint8_t *);
 
 }  // namespace sdcsz

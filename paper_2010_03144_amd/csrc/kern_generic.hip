@@ -189,6 +189,7 @@ template <typename T>
 __global__ void __launch_bounds__(64)
 k_decode_generic(const uint8_t *__restrict__ s, Header h, Geo g, DecWork w, PlanDev plan, T *out, uint32_t mode,
                  Region reg) {
+  if (*w.err) return;  // invalid codebook or block table: nothing is read
   const uint64_t blk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (blk < g.n_blocks) decode_one<T>(s, h, g, w, plan, out, mode, reg, blk);
 }
@@ -198,6 +199,7 @@ template <typename T>
 __global__ void __launch_bounds__(64)
 k_decode_list(const uint8_t *__restrict__ s, Header h, Geo g, DecWork w, PlanDev plan, T *out,
               const uint64_t *list, uint32_t n) {
+  if (*w.err) return;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   Region reg{};
   if (t < n) decode_one<T>(s, h, g, w, plan, out, 0, reg, list[t]);
@@ -209,6 +211,7 @@ k_decode_list(const uint8_t *__restrict__ s, Header h, Geo g, DecWork w, PlanDev
 template <typename T>
 __global__ void __launch_bounds__(64)
 k_decode_redo(const uint8_t *__restrict__ s, Header h, Geo g, DecWork w, T *out) {
+  if (*w.err) return;
   const uint32_t n = min(*w.redo_n, kMaxRedo);
   const DecTab tab = *w.tab;
   const T q = (T)(2.0 * h.eb_abs);

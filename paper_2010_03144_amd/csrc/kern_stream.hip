@@ -1,0 +1,214 @@
+// kern_stream.hip -- stream assembly and decoder tables on the device.
+//
+// Compression: the codeword table is scattered from the host's compact
+// codebook list; once the scans are done, k_header derives the section
+// offsets from the scanned totals and writes the header, the codebook
+// section and the alignment pads, but only when the call met no
+// uncorrectable error and the stream fits the caller's buffer (the encoder
+// kernels read the same decision).  Decompression: k_dectab validates the
+// codebook section and builds the canonical decoding tables; k_dec_check
+// compares the scanned block table with the header's counts.  The host reads
+// the outcome once, at the end of the call.
+#include "dev.h"
+#include "kern.h"
+
+namespace sdcsz {
+
+// enc[symbol] = codeword << 8 | length for each codebook entry.
+__global__ void __launch_bounds__(256) k_put_codes(const uint32_t *cb, uint32_t n_sym, uint32_t *enc) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_sym) return;
+  const uint32_t e = cb[2 * t], code = cb[2 * t + 1];
+  enc[e >> 8] = (code << 8) | (e & 0xFFu);
+}
+
+namespace {
+
+__device__ inline void put32(uint8_t *o, uint32_t off, uint32_t v) { *(uint32_t *)(o + off) = v; }
+__device__ inline void put64(uint8_t *o, uint32_t off, uint64_t v) {
+  put32(o, off, (uint32_t)v);
+  put32(o, off + 4, (uint32_t)(v >> 32));
+}
+
+// The 192-byte header: magic "SDCSZ\0v1", then the fields at fixed offsets
+// (unused bytes zero).
+__device__ void write_header(const Header &h, uint8_t *o) {
+  for (uint32_t off = 0; off < kHeader; off += 4) put32(o, off, 0u);
+  put32(o, 0, 0x53434453u);  // 'S' 'D' 'C' 'S'
+  put32(o, 4, 0x3176005Au);  // 'Z' 0 'v' '1'
+  put32(o, 8, h.dtype);
+  put32(o, 12, h.ndim);
+  for (uint32_t a = 0; a < 3; a++) put64(o, 16 + 8 * a, h.d[a]);
+  for (uint32_t a = 0; a < 3; a++) put32(o, 40 + 4 * a, h.b[a]);
+  put32(o, 52, h.eb_mode);
+  put64(o, 56, (uint64_t)__double_as_longlong(h.eb));
+  put64(o, 64, (uint64_t)__double_as_longlong(h.eb_abs));
+  put32(o, 72, h.abft);
+  put32(o, 76, h.n_sym);
+  put64(o, 80, h.n_blocks);
+  put64(o, 88, h.n_outliers);
+  put64(o, 96, h.n_regression);
+  put64(o, 104, h.payload_words);
+  put64(o, 112, h.off_codebook);
+  put64(o, 120, h.off_table);
+  put64(o, 128, h.off_coef);
+  put64(o, 136, h.off_sumdc);
+  put64(o, 144, h.off_outliers);
+  put64(o, 152, h.off_payload);
+  put64(o, 160, h.total);
+  put32(o, 168, h.predictor);
+}
+
+}  // namespace
+
+// Completes the header `h` (fixed fields set by the host) from the device
+// results and decides whether the stream is written: no uncorrectable error
+// in the input, coefficient or code stages, no code without a codeword, and
+// the stream fits `out_cap`.  Grid: one thread per codebook entry (>= 1).
+__global__ void __launch_bounds__(256) k_header(Header h, CompWork w, uint8_t *out, uint64_t out_cap) {
+  h.eb_abs = w.eb->eb_abs;
+  const uint64_t *tot = w.tot;  // left by the scan (zero without blocks)
+  h.payload_words = tot[0];
+  h.n_outliers = tot[1];
+  h.n_regression = tot[2];
+  section_offsets(h);
+  const unsigned long long *c = w.cnt;
+  const bool unc = c[C_UNC + SDCSZ_T_INPUT] || c[C_UNC + SDCSZ_T_COEF] || c[C_UNC + SDCSZ_T_CODE] || c[C_MISSING];
+  const bool ok = !unc && out != nullptr && h.total <= out_cap;
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) {
+    w.res[R_SIZE] = h.total;
+    w.res[R_OUTLIERS] = h.n_outliers;
+    w.res[R_REGRESSION] = h.n_regression;
+    w.res[R_WORDS] = h.payload_words;
+    w.res[R_WRITTEN] = ok ? 1u : 0u;
+    w.res[R_EB] = (uint64_t)__double_as_longlong(h.eb_abs);
+    *w.hdr = h;
+  }
+  if (!ok) return;
+  if (t < h.n_sym) put32(out, (uint32_t)(kHeader + 4 * t), w.cb[2 * t]);
+  if (t == 0) {
+    write_header(h, out);
+    const uint64_t vb = h.dtype == SDCSZ_F32 ? 4 : 8;
+    // 4-byte alignment pads after the codebook, the outliers and the payload
+    if (h.off_table > kHeader + 4ull * h.n_sym) put32(out + kHeader, 4 * h.n_sym, 0u);
+    const uint64_t out_end = h.off_outliers + vb * h.n_outliers;
+    if (h.off_payload > out_end) *(uint32_t *)(out + out_end) = 0u;
+    const uint64_t pay_end = h.off_payload + 4ull * h.payload_words;
+    if (h.total > pay_end) *(uint32_t *)(out + pay_end) = 0u;
+  }
+}
+
+// Canonical decoding tables from the codebook section (one u32 per used
+// symbol: symbol << 8 | length).  The entries must name distinct symbols
+// with lengths 1..kMaxLen; codes follow (length, symbol) order.  Writes
+// w.symbols (symbols by (length, symbol)), w.tab (first code, count and
+// first position per length) and w.lut (for each kLutBits-bit prefix the
+// shortest codeword it starts with, symbol << 8 | length, 0 if none); sets
+// *w.err on an invalid codebook.  One work-group of 256 threads.
+__global__ void __launch_bounds__(256) k_dectab(const uint32_t *cbk, uint32_t n_sym, DecWork w) {
+  __shared__ uint32_t lens4[65536 / 4];          // code length of each symbol, one byte each
+  __shared__ uint32_t part[kMaxLen + 1][256];     // per length: symbols in each thread's range
+  __shared__ uint32_t lut[1u << kLutBits];        // length << 16 | symbol of the shortest match
+  __shared__ uint32_t first[kMaxLen + 2], cnt[kMaxLen + 2], start[kMaxLen + 2];
+  __shared__ uint32_t smin, smax, bad;
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t i = tid; i < 65536 / 4; i += 256) lens4[i] = 0;
+  for (uint32_t i = tid; i < (1u << kLutBits); i += 256) lut[i] = 0xFFFFFFFFu;
+  for (uint32_t l = 0; l <= kMaxLen; l++) part[l][tid] = 0;
+  if (tid == 0) {
+    smin = 0xFFFFFFFFu;
+    smax = 0;
+    bad = 0;
+  }
+  __syncthreads();
+  for (uint32_t t = tid; t < n_sym; t += 256) {
+    const uint32_t e = cbk[t], s = e >> 8, l = e & 0xFFu;
+    if (s > 65535 || l == 0 || l > kMaxLen) {
+      atomicOr(&bad, 1u);
+      continue;
+    }
+    const uint32_t sh = 8 * (s & 3);
+    const uint32_t old = atomicOr(&lens4[s >> 2], l << sh);
+    if ((old >> sh) & 0xFFu) atomicOr(&bad, 1u);  // symbol listed twice
+    atomicMin(&smin, s);
+    atomicMax(&smax, s);
+  }
+  __syncthreads();
+  if (bad) {
+    if (tid == 0) *w.err = 1;
+    return;
+  }
+  auto len_of = [&](uint32_t s) { return (lens4[s >> 2] >> (8 * (s & 3))) & 0xFFu; };
+  // each thread takes a contiguous range of the used symbol span
+  const uint32_t span = smax >= smin ? smax - smin + 1 : 0;
+  const uint32_t per = (span + 255) / 256;
+  const uint32_t a = smin + tid * per, b = min(a + per, smin + span);
+  for (uint32_t s = a; s < b; s++) {
+    const uint32_t l = len_of(s);
+    if (l) part[l][tid]++;
+  }
+  __syncthreads();
+  if (tid <= kMaxLen) {  // exclusive scan of one length's counts over the threads
+    uint32_t acc = 0;
+    for (uint32_t i = 0; i < 256; i++) {
+      const uint32_t c = part[tid][i];
+      part[tid][i] = acc;
+      acc += c;
+    }
+    cnt[tid] = acc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // first code of length l: (first code + count of length l - 1) << 1, in
+    // 32-bit arithmetic (one past the last code of the previous used length,
+    // extended to l bits)
+    uint32_t code = 0, acc = 0, lo = kMaxLen + 1, hi = 0;
+    first[0] = start[0] = 0;
+    for (uint32_t l = 1; l <= kMaxLen; l++) {
+      code = (code + cnt[l - 1]) << 1;
+      first[l] = code;
+      start[l] = acc;
+      acc += cnt[l];
+      if (cnt[l]) {
+        lo = min(lo, l);
+        hi = max(hi, l);
+      }
+    }
+    DecTab *tb = w.tab;
+    for (uint32_t l = 0; l < kMaxLen + 2; l++) {
+      tb->first[l] = l <= kMaxLen ? first[l] : 0u;
+      tb->count[l] = l <= kMaxLen ? cnt[l] : 0u;
+      tb->start[l] = l <= kMaxLen ? start[l] : 0u;
+    }
+    tb->min_len = hi ? lo : 1u;
+    tb->max_len = hi;
+  }
+  __syncthreads();
+  for (uint32_t s = a; s < b; s++) {
+    const uint32_t l = len_of(s);
+    if (!l) continue;
+    const uint32_t r = part[l][tid]++;  // rank among the symbols of length l
+    w.symbols[start[l] + r] = (uint16_t)s;
+    if (l <= kLutBits) {
+      const uint64_t code = (uint64_t)first[l] + r;
+      if (code < (1ull << l)) {  // codes at or past 2^l can never be read
+        const uint32_t sh = kLutBits - l, key = (l << 16) | s;
+        for (uint32_t v = (uint32_t)code << sh; v < ((uint32_t)code + 1) << sh; v++) atomicMin(&lut[v], key);
+      }
+    }
+  }
+  __syncthreads();
+  for (uint32_t v = tid; v < (1u << kLutBits); v += 256) {
+    const uint32_t k = lut[v];
+    w.lut[v] = k == 0xFFFFFFFFu ? 0u : ((k & 0xFFFFu) << 8) | (k >> 16);
+  }
+}
+
+// The block table must add up to the header's counts (u64 totals of the scan).
+__global__ void k_dec_check(const uint64_t *tot, uint64_t payload_words, uint64_t n_outliers, uint64_t n_regression,
+                            uint32_t *err) {
+  if (threadIdx.x == 0 && (tot[0] != payload_words || tot[1] != n_outliers || tot[2] != n_regression)) *err = 1;
+}
+
+}  // namespace sdcsz

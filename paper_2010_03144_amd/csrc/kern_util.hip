@@ -244,7 +244,8 @@ __global__ void __launch_bounds__(kScanThreads) k_scan2(uint64_t *part, uint32_t
 }
 
 __global__ void __launch_bounds__(kScanThreads)
-k_scan3(ScanSrc src, uint64_t n, const uint64_t *part, uint64_t *off_pay, uint32_t *off_out, uint32_t *off_coef) {
+k_scan3(ScanSrc src, uint64_t n, const uint64_t *part, uint64_t *off_pay, uint32_t *off_out, uint32_t *off_coef,
+        uint64_t *total) {
   const uint64_t base = (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * kScanItems;
   Tri loc[kScanItems];
   Tri s{0, 0, 0};
@@ -270,13 +271,18 @@ k_scan3(ScanSrc src, uint64_t n, const uint64_t *part, uint64_t *off_pay, uint32
       off_pay[n] = run.a;
       off_out[n] = (uint32_t)run.b;
       off_coef[n] = (uint32_t)run.c;
+      total[0] = run.a;  // 64-bit totals: a table whose counts wrap 32 bits cannot match a header
+      total[1] = run.b;
+      total[2] = run.c;
     }
   }
 }
 
 // ---- stream assembly: one thread per block ----------------------------------
 template <typename T>
-__global__ void __launch_bounds__(256) k_encode(Geo g, CompWork w, uint8_t *out, Header h) {
+__global__ void __launch_bounds__(256) k_encode(Geo g, CompWork w, uint8_t *out) {
+  if (!w.res[R_WRITTEN]) return;  // the stream is not written (see k_header)
+  const Header h = *w.hdr;
   const uint64_t blk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (blk >= g.n_blocks) return;
   const Box b = box_of(g, blk);
@@ -311,7 +317,7 @@ __global__ void __launch_bounds__(256) k_encode(Geo g, CompWork w, uint8_t *out,
   }
   if (h.abft) ((uint64_t *)(out + h.off_sumdc))[blk] = w.sum_dc[blk];
 }
-template __global__ void k_encode<float>(Geo, CompWork, uint8_t *, Header);
-template __global__ void k_encode<double>(Geo, CompWork, uint8_t *, Header);
+template __global__ void k_encode<float>(Geo, CompWork, uint8_t *);
+template __global__ void k_encode<double>(Geo, CompWork, uint8_t *);
 
 }  // namespace sdcsz

@@ -144,6 +144,7 @@ class Codec:
         self.torch = torch
         self.device = torch.device(device)
         self._ws = {}
+        self._last = None  # (pointer, size, shape, dtype code, block) of the last stream compressed here
 
     def workspace(self, nbytes, tag):
         t = self._ws.get(tag)
@@ -174,7 +175,21 @@ class Codec:
                               out.numel(), C.byref(size), C.byref(rep), C.c_void_p(ws.data_ptr()),
                               ws.numel(), _stream_handle(self.device))
         stream = out[: size.value] if rc == OK else None
+        own = out.data_ptr() == self._ws["stream_out"].data_ptr() if "stream_out" in self._ws else False
+        self._last = ((out.data_ptr(), int(size.value), tuple(x.shape), p.dtype,
+                       tuple(int(b) for b in block)) if rc == OK and own else None)
         return rc, stream, report_dict(rep)
+
+    def _geometry(self, stream):
+        """(rc, params, shape) of a stream: from the last compression when the
+        stream is that call's output, still in this codec's buffer (only
+        compress writes there; the library validates the header anyway),
+        else read from the stream's header on the device."""
+        last = self._last
+        if last is not None and last[0] == stream.data_ptr() and last[1] == stream.numel():
+            p = make_params(last[2], last[3] == 0, last[4], 1.0)
+            return OK, p, last[2]
+        return self.info(stream)
 
     def info(self, stream):
         L = lib()
@@ -199,7 +214,7 @@ class Codec:
         """Returns (rc, tensor, report dict)."""
         torch = self.torch
         L = lib()
-        rc, p, shape = self.info(stream)
+        rc, p, shape = self._geometry(stream)
         if rc != OK:
             return rc, None, None
         dt = torch.float32 if p.dtype == 0 else torch.float64

@@ -156,3 +156,98 @@ def test_region(codec):
     rc_g, part_g, _ = codec.decompress_region(torch.from_numpy(s).cuda(), lo, hi)
     assert rc_r == rc_g == 0
     assert np.array_equal(part_r.view(np.uint32), part_g.cpu().numpy().view(np.uint32))
+
+
+def _codebook(s):
+    n_sym = int(np.frombuffer(s[76:80].tobytes(), "<u4")[0])
+    return n_sym, s[192:192 + 4 * n_sym].view("<u4")
+
+
+def _decode_both(codec, s):
+    rc_r, y_r, rep_r = ref.decompress(s)
+    rc_g, y_g, rep_g = codec.decompress(torch.from_numpy(s).cuda())
+    assert rc_r == rc_g, (rc_r, rc_g)
+    if rc_r in (0, sdcsz.ESDC):
+        same_counts(rep_r, rep_g)
+        assert np.array_equal(y_r.view(np.uint32), y_g.cpu().numpy().view(np.uint32))
+    return rc_r
+
+
+def test_codebook_entries_in_any_order(codec):
+    # the format names used symbols with their lengths; codes follow from
+    # (length, symbol) whatever order the entries are listed in
+    x = synth.grf_field((30, 24, 18), seed=4)
+    rc, s, _ = ref.compress(x, (6, 6, 6), 1e-3)
+    n_sym, cb = _codebook(s)
+    assert n_sym > 8
+    shuffled = s.copy()
+    perm = np.random.default_rng(5).permutation(n_sym)
+    shuffled[192:192 + 4 * n_sym] = cb[perm].view(np.uint8)
+    assert _decode_both(codec, shuffled) == 0
+    rc0, y0, _ = ref.decompress(s)
+    rc1, y1, _ = codec.decompress(torch.from_numpy(shuffled).cuda())
+    assert np.array_equal(y0.view(np.uint32), y1.cpu().numpy().view(np.uint32))
+
+
+@pytest.mark.parametrize("edit", ["duplicate", "zero_length", "too_long", "symbol_range"])
+def test_invalid_codebook_is_a_format_error(codec, edit):
+    x = synth.grf_field((24, 24, 24), seed=4)
+    rc, s, _ = ref.compress(x, (6, 6, 6), 1e-3)
+    n_sym, cb = _codebook(s)
+    bad = s.copy()
+    e = bad[192:192 + 4 * n_sym].view("<u4")
+    if edit == "duplicate":
+        e[1] = (e[0] & ~np.uint32(0xFF)) | (e[1] & np.uint32(0xFF))
+    elif edit == "zero_length":
+        e[2] &= ~np.uint32(0xFF)
+    elif edit == "too_long":
+        e[2] = (e[2] & ~np.uint32(0xFF)) | np.uint32(25)
+    else:
+        e[3] = (np.uint32(70000) << np.uint32(8)) | (e[3] & np.uint32(0xFF))
+    assert _decode_both(codec, bad) == sdcsz.EFORMAT
+
+
+def test_oversubscribed_codebook_decodes_like_the_oracle(codec):
+    # a length edited shorter breaks the prefix property: both sides still
+    # take, bit by bit, the shortest codeword that matches
+    x = synth.grf_field((24, 24, 24), seed=4)
+    rc, s, _ = ref.compress(x, (6, 6, 6), 1e-3)
+    n_sym, cb = _codebook(s)
+    for t, new_len in ((n_sym // 2, 2), (n_sym - 1, 1), (0, 3)):
+        bad = s.copy()
+        e = bad[192:192 + 4 * n_sym].view("<u4")
+        e[t] = (e[t] & ~np.uint32(0xFF)) | np.uint32(new_len)
+        _decode_both(codec, bad)
+
+
+def test_block_table_total_mismatch_is_a_format_error(codec):
+    x = synth.grf_field((24, 24, 24), seed=4)
+    rc, s, _ = ref.compress(x, (6, 6, 6), 1e-3)
+    from tests.gpu_util import sections
+    bad = s.copy()
+    tab = bad[sections(s)["table"]:].view("<u4")
+    tab[0] += 1
+    assert _decode_both(codec, bad) == sdcsz.EFORMAT
+
+
+def test_output_too_small_writes_nothing(codec):
+    import ctypes as C
+    x = synth.grf_field((30, 24, 18), seed=4)
+    xd = torch.from_numpy(x).cuda()
+    rc, s_r, _ = ref.compress(x, (6, 6, 6), 1e-3)
+    L = sdcsz.lib()
+    p = sdcsz.make_params(x.shape, True, (6, 6, 6), 1e-3)
+    ws = torch.empty(L.sdcsz_compress_workspace_size(C.byref(p)), dtype=torch.uint8, device="cuda")
+    out = torch.full((s_r.size + 64,), 0xA5, dtype=torch.uint8, device="cuda")
+    size = C.c_uint64(0)
+    rep = sdcsz.Report()
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    rc = L.sdcsz_compress(C.c_void_p(xd.data_ptr()), C.byref(p), C.c_void_p(out.data_ptr()), s_r.size - 8,
+                          C.byref(size), C.byref(rep), C.c_void_p(ws.data_ptr()), ws.numel(), st)
+    assert rc == sdcsz.ENOSPC and size.value == s_r.size
+    assert bool((out == 0xA5).all())
+    rc = L.sdcsz_compress(C.c_void_p(xd.data_ptr()), C.byref(p), C.c_void_p(out.data_ptr()), s_r.size,
+                          C.byref(size), C.byref(rep), C.c_void_p(ws.data_ptr()), ws.numel(), st)
+    assert rc == 0 and size.value == s_r.size
+    assert np.array_equal(out[: s_r.size].cpu().numpy(), s_r)
+    assert bool((out[s_r.size:] == 0xA5).all())
