@@ -47,6 +47,13 @@ def algorithmic_bytes(phase, n, nb, vb, rep, abft):
     return 0
 
 
+# kernel behind each timed phase (one launch per call)
+PHASE_KERNEL = {"range": "k_range<float>", "predict_quantize": "k_compress_fast<float,3,6,6,6,true>",
+                "code_check": "k_check_fast<6,6,6>", "encode": "k_encode_fast<float,6,6,6>",
+                "decode": "k_decode_fast<float,3,6,6,6>", "scan_compress": "k_scan1/2/3",
+                "scan_decompress": "k_scan1/2/3"}
+
+
 def source_digest():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2010_03144_amd", "csrc")
@@ -108,7 +115,12 @@ def main():
     ap.add_argument("--eb", type=float, default=1e-3)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="profiling pass: the timed steps, then two plain copy kernels over the field "
+                         "(known traffic, to scale HBM counters); implies --no-extras --no-cpu-baseline")
     args = ap.parse_args()
+    if args.copy_probe:
+        args.no_extras = args.no_cpu_baseline = True
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: this build runs the compressor on a single MI355X "
@@ -176,7 +188,8 @@ def main():
                                f"tanh front, value-range-relative eb {args.eb:g}, block 6x6x6, "
                                f"ABFT on; one compress + one decompress per step",
                    "field_bytes": n * vb, "eb_abs": rep["eb_abs"]},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2),
+        "roofline": {"bound": "hbm", "phase": dom, "kernel": PHASE_KERNEL.get(dom, dom),
+                     "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "algorithmic_bytes_per_launch": int(alg),
                      "avg_launch_ms": round(avg_s * 1e3, 4)},
@@ -190,6 +203,14 @@ def main():
         "phases_ms_per_step": {p: round(v[0] / args.steps, 4) for p, v in phases.items() if v[1]},
         "source_digest": digest,
     }
+
+    if args.copy_probe:
+        # out = in * 1: reads and writes field_bytes each, a reference for the counters
+        buf = torch.empty_like(xd)
+        for _ in range(2):
+            torch.mul(xd, 1.0, out=buf)
+        sync()
+        result["copy_probe_bytes"] = {"read": n * vb, "write": n * vb}
 
     if not args.no_extras:
         extras = {}

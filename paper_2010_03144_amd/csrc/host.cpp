@@ -264,9 +264,11 @@ void launch_fast(const T *in, const Geo &g, const RegTab<T> &rt, const PlanDev &
                        ABFT ? 1u : 0u, predictor, plan_blocks, n_plan_blocks);
   Launch L;
   const uint32_t wgs = fast_launch(g, &L);
+  g_timer.begin(PH_PREDICT, st);
   if (wgs)
     hipLaunchKernelGGL((k_compress_fast<T, 3, 6, 6, 6, ABFT>), dim3(wgs), dim3(256), 0, st, in, g, rt, pd, w,
                        predictor, L);
+  g_timer.end(PH_PREDICT, st);
   hipLaunchKernelGGL(k_redo<T>, dim3(1), dim3(64), 0, st, in, g, rt, pd, w, ABFT ? 1u : 0u, predictor);
 }
 
@@ -486,15 +488,14 @@ int compress_t(const void *d_in, const sdcsz_params *p, const Geo &g, uint8_t *d
     hipLaunchKernelGGL(k_range<T>, dim3(nparts), dim3(kRangeThreads), 0, st, (const T *)d_in, g.n_values,
                        (double *)w.range_part);
   }
+  g_timer.end(PH_RANGE, st);
   hipLaunchKernelGGL(k_consts, dim3(1), dim3(256), 0, st, (const double *)w.range_part, nparts, p->eb_mode,
                      p->eb, w.eb);
-  g_timer.end(PH_RANGE, st);
   HIPCHK(hipGetLastError());
 
   const bool fast = g.n_blocks && fast_shape(g, sizeof(T));
   if (g.n_blocks) {
     const RegTab<T> rt = reg_table<T>(g);
-    g_timer.begin(PH_PREDICT, st);
     if (fast) {
       // the distinct blocks the plan names run through the generic routine
       const uint64_t *d_pb = (const uint64_t *)(ws + L.plan_blocks);
@@ -503,10 +504,11 @@ int compress_t(const void *d_in, const sdcsz_params *p, const Geo &g, uint8_t *d
       if (p->abft) launch_fast<T, true>((const T *)d_in, g, rt, pd, w, p->predictor, d_pb, (uint32_t)pb.size(), st);
       else launch_fast<T, false>((const T *)d_in, g, rt, pd, w, p->predictor, d_pb, (uint32_t)pb.size(), st);
     } else {
+      g_timer.begin(PH_PREDICT, st);
       hipLaunchKernelGGL(k_compress_generic<T>, dim3(grid_for(g.n_blocks, 64)), dim3(64), 0, st,
                          (const T *)d_in, g, rt, pd, w, p->abft, p->predictor);
+      g_timer.end(PH_PREDICT, st);
     }
-    g_timer.end(PH_PREDICT, st);
     HIPCHK(hipGetLastError());
     bool any_code = false;
     for (auto &f : plan) any_code |= f.target == SDCSZ_T_CODE;
@@ -666,25 +668,25 @@ int decode_t(const uint8_t *d_s, Opened &o, T *d_out, uint32_t mode, const Regio
   ScanSrc src{table, table + 1, 2};
   g_timer.begin(PH_SCAN_D, st);
   rc = launch_scan(src, g.n_blocks, w.scan_part, w.off_pay, w.off_out, w.off_coef, w.tot, st);
+  g_timer.end(PH_SCAN_D, st);
   hipLaunchKernelGGL(k_dec_check, dim3(1), dim3(64), 0, st, (const uint64_t *)w.tot, h.payload_words, h.n_outliers,
                      h.n_regression, w.err);
-  g_timer.end(PH_SCAN_D, st);
   if (rc) return rc;
   const bool fast = mode == 0 && fast_shape(g, sizeof(T));
   const std::vector<uint64_t> pb = plan_block_list(plan);
   if (g.n_blocks && fast) {
     const uint64_t *d_pb = (const uint64_t *)(ws + L.plan_blocks);
     if (!pb.empty()) HIPCHK(hipMemcpyAsync(ws + L.plan_blocks, pb.data(), 8 * pb.size(), hipMemcpyHostToDevice, st));
-    g_timer.begin(PH_DECODE, st);
     if (!pb.empty())
       hipLaunchKernelGGL(k_decode_list<T>, dim3(grid_for(pb.size(), 64)), dim3(64), 0, st, d_s, h, g, w, pd, d_out,
                          d_pb, (uint32_t)pb.size());
     Launch FL;
     const uint32_t wgs = fast_launch(g, &FL);
+    g_timer.begin(PH_DECODE, st);
     if (wgs)
       hipLaunchKernelGGL((k_decode_fast<T, 3, 6, 6, 6>), dim3(wgs), dim3(256), 0, st, d_s, h, g, w, pd, d_out, FL);
-    hipLaunchKernelGGL(k_decode_redo<T>, dim3(1), dim3(64), 0, st, d_s, h, g, w, d_out);
     g_timer.end(PH_DECODE, st);
+    hipLaunchKernelGGL(k_decode_redo<T>, dim3(1), dim3(64), 0, st, d_s, h, g, w, d_out);
     HIPCHK(hipGetLastError());
   } else if (g.n_blocks) {
     g_timer.begin(PH_DECODE, st);

@@ -1,7 +1,7 @@
 // huffman.h -- Huffman code lengths and canonical codewords (host side).
 //
 // The code is built over the histogram of the quantization codes of the
-// whole field (the Huffman stage of the SZ pipeline, Sec. 2.1).  The tree
+// whole field (the Huffman stage of the SZ pipeline, Sec. 3.1; Algorithm 1).  The tree
 // merges the used symbols in (count, symbol) order with two queues, the
 // sorted leaves and the internal nodes in creation order, a tie going to the
 // leaf; one used symbol gets length 1.  A tree deeper than the length limit

@@ -107,15 +107,14 @@ __global__ void __launch_bounds__(256) k_header(Header h, CompWork w, uint8_t *o
 // shortest codeword it starts with, symbol << 8 | length, 0 if none); sets
 // *w.err on an invalid codebook.  One work-group of 256 threads.
 __global__ void __launch_bounds__(256) k_dectab(const uint32_t *cbk, uint32_t n_sym, DecWork w) {
-  __shared__ uint32_t lens4[65536 / 4];          // code length of each symbol, one byte each
-  __shared__ uint32_t part[kMaxLen + 1][256];     // per length: symbols in each thread's range
-  __shared__ uint32_t lut[1u << kLutBits];        // length << 16 | symbol of the shortest match
+  __shared__ uint32_t lens4[65536 / 4];       // code length of each symbol, one byte each
+  __shared__ uint32_t part[kMaxLen + 1][256];  // per length: symbols before each thread's range
+  __shared__ uint32_t wsum[kMaxLen + 1][4];    // per length: symbols in each wave's ranges
+  __shared__ uint16_t short_sym[1u << kLutBits];  // symbols of the codes of <= kLutBits bits, by position
   __shared__ uint32_t first[kMaxLen + 2], cnt[kMaxLen + 2], start[kMaxLen + 2];
   __shared__ uint32_t smin, smax, bad;
-  const uint32_t tid = threadIdx.x;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (uint32_t i = tid; i < 65536 / 4; i += 256) lens4[i] = 0;
-  for (uint32_t i = tid; i < (1u << kLutBits); i += 256) lut[i] = 0xFFFFFFFFu;
-  for (uint32_t l = 0; l <= kMaxLen; l++) part[l][tid] = 0;
   if (tid == 0) {
     smin = 0xFFFFFFFFu;
     smax = 0;
@@ -140,20 +139,37 @@ __global__ void __launch_bounds__(256) k_dectab(const uint32_t *cbk, uint32_t n_
     return;
   }
   auto len_of = [&](uint32_t s) { return (lens4[s >> 2] >> (8 * (s & 3))) & 0xFFu; };
-  // each thread takes a contiguous range of the used symbol span
+  // each thread takes a contiguous range of the used symbol span and counts
+  // its symbols per length
   const uint32_t span = smax >= smin ? smax - smin + 1 : 0;
   const uint32_t per = (span + 255) / 256;
   const uint32_t a = smin + tid * per, b = min(a + per, smin + span);
+  uint32_t mine[kMaxLen + 1];
+#pragma unroll
+  for (uint32_t l = 0; l <= kMaxLen; l++) mine[l] = 0;
   for (uint32_t s = a; s < b; s++) {
     const uint32_t l = len_of(s);
-    if (l) part[l][tid]++;
+#pragma unroll
+    for (uint32_t m = 1; m <= kMaxLen; m++) mine[m] += l == m ? 1u : 0u;
+  }
+  // exclusive prefix over the threads, per length: wave scans, then wave offsets
+#pragma unroll
+  for (uint32_t l = 1; l <= kMaxLen; l++) {
+    uint32_t v = mine[l];
+#pragma unroll
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+      const uint32_t u = (uint32_t)__shfl_up((int)v, d);
+      if (lane >= d) v += u;
+    }
+    part[l][tid] = v - mine[l];
+    if (lane == 63) wsum[l][wave] = v;
   }
   __syncthreads();
-  if (tid <= kMaxLen) {  // exclusive scan of one length's counts over the threads
+  if (tid <= kMaxLen) {
     uint32_t acc = 0;
-    for (uint32_t i = 0; i < 256; i++) {
-      const uint32_t c = part[tid][i];
-      part[tid][i] = acc;
+    for (uint32_t q = 0; q < 4; q++) {
+      const uint32_t c = tid ? wsum[tid][q] : 0u;
+      wsum[tid][q] = acc;
       acc += c;
     }
     cnt[tid] = acc;
@@ -188,20 +204,25 @@ __global__ void __launch_bounds__(256) k_dectab(const uint32_t *cbk, uint32_t n_
   for (uint32_t s = a; s < b; s++) {
     const uint32_t l = len_of(s);
     if (!l) continue;
-    const uint32_t r = part[l][tid]++;  // rank among the symbols of length l
-    w.symbols[start[l] + r] = (uint16_t)s;
-    if (l <= kLutBits) {
-      const uint64_t code = (uint64_t)first[l] + r;
-      if (code < (1ull << l)) {  // codes at or past 2^l can never be read
-        const uint32_t sh = kLutBits - l, key = (l << 16) | s;
-        for (uint32_t v = (uint32_t)code << sh; v < ((uint32_t)code + 1) << sh; v++) atomicMin(&lut[v], key);
-      }
-    }
+    const uint32_t pos = start[l] + wsum[l][wave] + part[l][tid]++;
+    w.symbols[pos] = (uint16_t)s;
+    if (pos < (1u << kLutBits)) short_sym[pos] = (uint16_t)s;
   }
   __syncthreads();
+  // prefix table: for each kLutBits-bit prefix the first length whose top
+  // bits fall among that length's codes (the rule of bit-by-bit decoding)
   for (uint32_t v = tid; v < (1u << kLutBits); v += 256) {
-    const uint32_t k = lut[v];
-    w.lut[v] = k == 0xFFFFFFFFu ? 0u : ((k & 0xFFFFu) << 8) | (k >> 16);
+    uint32_t e = 0;
+    for (uint32_t l = 1; l <= kLutBits; l++) {
+      const uint32_t c = v >> (kLutBits - l);
+      if (cnt[l] && c >= first[l] && c - first[l] < cnt[l]) {
+        const uint32_t pos = start[l] + c - first[l];
+        const uint32_t s = pos < (1u << kLutBits) ? (uint32_t)short_sym[pos] : (uint32_t)w.symbols[pos];
+        e = (s << 8) | l;
+        break;
+      }
+    }
+    w.lut[v] = e;
   }
 }
 

@@ -1,0 +1,84 @@
+"""GPU parity at the benchmark's full size: the 512^3 FP32 Gaussian random field
+with a front (seed 2), in the launch configuration bench.py times, against
+the oracle on the whole field (streams byte for byte, decompressed values bit
+for bit), plus the fault-injected run at eb 1e-4 (6 flips per target on
+distinct blocks, counts equal to the oracle's)."""
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_2010_03144_amd import sdcsz, synth
+from tests.gpu_util import first_difference
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SHAPE = (512, 512, 512)
+BLOCK = (6, 6, 6)
+
+
+@pytest.fixture(scope="module")
+def field():
+    print("generating 512^3 field (seed 2)", flush=True)
+    x = synth.grf_field(SHAPE, seed=2)
+    return x, torch.from_numpy(x).cuda()
+
+
+@pytest.fixture(scope="module")
+def codec():
+    return sdcsz.Codec("cuda:0")
+
+
+def counts_equal(a, b):
+    for t in sdcsz.TARGETS:
+        assert a[t] == b[t], (t, a[t], b[t])
+
+
+@pytest.mark.parametrize("eb,abft", [(1e-3, True), (1e-4, False)])
+def test_full_field_identical_to_oracle(codec, field, eb, abft):
+    x, xd = field
+    print(f"case 512^3 eb={eb} abft={abft}: gpu compress", flush=True)
+    rc_g, s_g, rep_g = codec.compress(xd, BLOCK, eb, abft=abft)
+    assert rc_g == 0
+    s_g_host = s_g.cpu().numpy()
+    print("oracle compress", flush=True)
+    rc_r, s_r, rep_r = ref.compress(x, BLOCK, eb, abft=abft)
+    assert rc_r == 0
+    assert np.array_equal(s_r, s_g_host), first_difference(s_r, s_g_host)
+    assert rep_r["eb_abs"] == rep_g["eb_abs"]
+    print("gpu decompress", flush=True)
+    rc, y_g, _ = codec.decompress(s_g)
+    assert rc == 0
+    y_g = y_g.cpu().numpy()
+    print("oracle decompress", flush=True)
+    rc, y_r, _ = ref.decompress(s_r)
+    assert rc == 0
+    assert np.array_equal(y_r.view(np.uint32), y_g.view(np.uint32))
+    err = np.abs(x.astype(np.float64) - y_g.astype(np.float64)).max()
+    assert err <= rep_g["eb_abs"]
+
+
+def test_full_field_fault_injection_matches_oracle(codec, field):
+    x, xd = field
+    counts = {"input": 6, "coef": 6, "code": 6, "dup_pred": 6, "dup_recon": 6}
+    plan = synth.fault_plan(SHAPE, BLOCK, np.float32, counts, seed=3)
+    print(f"case 512^3 eb=1e-4 fault plan {len(plan)} entries: gpu compress", flush=True)
+    rc_g, s_g, rep_g = codec.compress(xd, BLOCK, 1e-4, faults=plan)
+    print("oracle compress", flush=True)
+    rc_r, s_r, rep_r = ref.compress(x, BLOCK, 1e-4, faults=plan)
+    assert rc_r == rc_g == 0
+    counts_equal(rep_r, rep_g)
+    for t in ("input", "coef", "code"):
+        assert rep_g[t]["injected"] == rep_g[t]["corrected"] == 6, (t, rep_g[t])
+    s_g_host = s_g.cpu().numpy()
+    assert np.array_equal(s_r, s_g_host), first_difference(s_r, s_g_host)
+    # decompression: RECON flips on 6 distinct blocks, re-executed
+    rplan = synth.fault_plan(SHAPE, BLOCK, np.float32, {"recon": 6}, seed=33)
+    print("gpu decompress with recon faults", flush=True)
+    rc_g, y_g, rep_dg = codec.decompress(s_g, faults=rplan)
+    print("oracle decompress with recon faults", flush=True)
+    rc_r, y_r, rep_dr = ref.decompress(s_r, faults=rplan)
+    assert rc_r == rc_g == 0
+    counts_equal(rep_dr, rep_dg)
+    assert rep_dg["recon"]["detected"] == rep_dg["recon"]["corrected"] == 6
+    assert np.array_equal(y_r.view(np.uint32), y_g.cpu().numpy().view(np.uint32))
