@@ -686,7 +686,7 @@ int decode_t(const uint8_t *d_s, Opened &o, T *d_out, uint32_t mode, const Regio
     if (wgs)
       hipLaunchKernelGGL((k_decode_fast<T, 3, 6, 6, 6>), dim3(wgs), dim3(256), 0, st, d_s, h, g, w, pd, d_out, FL);
     g_timer.end(PH_DECODE, st);
-    hipLaunchKernelGGL(k_decode_redo<T>, dim3(1), dim3(64), 0, st, d_s, h, g, w, d_out);
+    hipLaunchKernelGGL(k_decode_redo<T>, dim3(kMaxRedo / 64), dim3(64), 0, st, d_s, h, g, w, d_out);
     HIPCHK(hipGetLastError());
   } else if (g.n_blocks) {
     g_timer.begin(PH_DECODE, st);

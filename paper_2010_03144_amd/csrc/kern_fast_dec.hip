@@ -2,10 +2,12 @@
 //
 // Algorithm 2 for one block per lane: canonical Huffman decoding through a
 // lookup table in LDS (the first kLutBits bits of a codeword; longer codes
-// take a short search by length), reconstruction with the arithmetic of
-// compression (previous reconstructed plane in registers), the checksum of
-// the block against sum_dc, and coalesced row stores.  A checksum mismatch
-// or an undecodable block is queued for k_decode_redo (re-execution from the
+// take a short search over the lengths their prefix allows) from a window
+// of the block's payload staged in LDS with 16-byte loads, reconstruction
+// with the arithmetic of compression (previous reconstructed plane in
+// registers), the checksum of the block against sum_dc, and coalesced row
+// stores.  A checksum mismatch, an undecodable block or a symbol beyond the
+// LDS tables queues the block for k_decode_redo (re-execution from the
 // compressed bytes); blocks named in a fault plan run in k_decode_list.
 #include "dev.h"
 #include "kern.h"
@@ -45,54 +47,89 @@ template <typename... V> __device__ inline void drow_fence(V &...v) {
   __asm__ volatile("" ::: "memory");
 }
 
-// Bit reader over one block's payload words (most significant bit first).
-struct Bits {
-  const uint32_t *pay;
-  uint32_t nw;    // payload words of the block
-  uint32_t wi;    // next word to fetch into `nxt`
-  uint32_t nxt;   // prefetched word
-  uint64_t buf;   // left-aligned unread bits
-  uint32_t nb;    // valid bits in buf
-  uint32_t used;  // bits consumed
-  __device__ void init(const uint32_t *p, uint32_t n) {
-    pay = p;
-    nw = n;
-    const uint32_t w0 = n > 0 ? p[0] : 0u, w1 = n > 1 ? p[1] : 0u;
-    buf = ((uint64_t)w0 << 32) | w1;
-    nb = 64;
-    wi = 2;
-    nxt = n > 2 ? p[2] : 0u;
-    used = 0;
-  }
-  // top bits available for the next codeword (>= 32 valid bits after refill)
-  __device__ inline void refill() {
-    if (nb < 32) {
-      buf |= (uint64_t)nxt << (32 - nb);
-      nb += 32;
-      wi++;
-      nxt = wi < nw ? pay[wi] : 0u;
+constexpr uint32_t kDecThreads = 256;
+constexpr uint32_t kWin = 20;  // payload words staged per lane for half a plane
+constexpr uint32_t kLongSyms = 5120;  // symbols of codes longer than kLutBits kept in LDS
+
+// The payload bits of one lane's block, staged three rows at a time into a
+// window of kWin words in LDS (word w of thread t at win[w * kDecThreads + t],
+// so a wave's accesses to one word index fall in distinct banks).  Three rows
+// of a 6x6x6 block hold at most 18 codewords of <= 24 bits (432 bits); the
+// window starts at the 16-byte group holding the current word (<= 127 bits
+// of skew), so 20 words always cover them, the word after the last bit
+// included.
+struct Window {
+  const uint8_t *pay;  // the block's first payload word
+  const uint8_t *end;  // end of the readable stream bytes
+  uint32_t *win;       // this thread's column of the LDS window
+  uint32_t pos;        // bits of the block consumed
+  uint32_t lp;         // bit position inside the window
+
+  __device__ void stage() {
+    const uint8_t *a = pay + 4ull * (pos >> 5);
+    const uint8_t *g = a - ((uintptr_t)a & 15);
+    lp = (uint32_t)(a - g) * 8 + (pos & 31);
+    constexpr uint32_t NG = kWin / 4;
+    if (__builtin_expect(g + 16 * NG <= end, 1)) {
+      uint4 v[NG];
+#pragma unroll
+      for (uint32_t t = 0; t < NG; t++) v[t] = ((const uint4 *)g)[t];
+#pragma unroll
+      for (uint32_t t = 0; t < NG; t++) {
+        win[(4 * t + 0) * kDecThreads] = v[t].x;
+        win[(4 * t + 1) * kDecThreads] = v[t].y;
+        win[(4 * t + 2) * kDecThreads] = v[t].z;
+        win[(4 * t + 3) * kDecThreads] = v[t].w;
+      }
+    } else {  // the window reaches past the stream: word by word, zeros beyond
+#pragma unroll 1
+      for (uint32_t q = 0; q < kWin; q++)
+        win[q * kDecThreads] = g + 4 * (q + 1) <= end ? ((const uint32_t *)g)[q] : 0u;
     }
   }
-  __device__ inline void skip(uint32_t len) {
-    buf <<= len;
-    nb -= len;
-    used += len;
+  // the next 32 bits of the block (most significant first)
+  __device__ inline uint32_t peek() const {
+    const uint32_t w = lp >> 5;
+    const uint64_t two = ((uint64_t)win[w * kDecThreads] << 32) | win[(w + 1) * kDecThreads];
+    return (uint32_t)((two << (lp & 31)) >> 32);
+  }
+  __device__ inline void skip(uint32_t n) {
+    lp += n;
+    pos += n;
   }
 };
 
-// Decode one symbol; sets *bad on an invalid code or a read past the block.
-__device__ inline uint32_t decode_sym(Bits &br, const uint32_t *lut, const DecTab *tab, const uint16_t *symbols,
-                                      bool *bad) {
-  br.refill();
-  const uint32_t e = lut[(uint32_t)(br.buf >> (64 - kLutBits))];
+// Canonical decoding tables in LDS: the prefix table, first code, count and
+// first position per length, and the symbols of the long codes from
+// position long_base on.
+struct DecLds {
+  uint32_t lut[1u << kLutBits];
+  uint32_t first[kMaxLen + 2], count[kMaxLen + 2], start[kMaxLen + 2];
+  uint32_t long_base, long_n;
+  uint16_t long_sym[kLongSyms];
+};
+
+// Decode one symbol.  The prefix table resolves codewords of up to kLutBits
+// bits; for a longer one it gives the range of lengths whose codes start
+// with that prefix, and the first length whose codes hold the top bits
+// wins.  Sets *bad when no codeword matches, and *defer when the symbol is
+// not held in LDS (the block is then decoded by the generic kernel).
+// Reading past the block's words is checked once, at the end of the block.
+__device__ inline uint32_t decode_sym(Window &br, const DecLds &t, bool *bad, bool *defer) {
+  const uint32_t v = br.peek();
+  const uint32_t e = t.lut[v >> (32 - kLutBits)];
   uint32_t len = e & 0xFFu, sym = e >> 8;
   if (__builtin_expect(len == 0, 0)) {
+    const uint32_t lmin = (e >> 8) & 0xFFu, lmax = e >> 16;
     sym = 0;
-    for (uint32_t l = kLutBits + 1; l <= kMaxLen; l++) {
-      const uint32_t c = (uint32_t)(br.buf >> (64 - l));
-      const uint32_t f = tab->first[l], n = tab->count[l];
-      if (n && c >= f && c - f < n) {
-        sym = symbols[tab->start[l] + c - f];
+#pragma unroll 1
+    for (uint32_t l = lmin; l <= lmax; l++) {
+      const uint32_t c = v >> (32 - l);
+      const uint32_t f = t.first[l], n = t.count[l];
+      if (c >= f && c - f < n) {
+        const uint32_t idx = t.start[l] + c - f - t.long_base;
+        if (idx < t.long_n) sym = t.long_sym[idx];
+        else *defer = true;
         len = l;
         break;
       }
@@ -102,7 +139,6 @@ __device__ inline uint32_t decode_sym(Bits &br, const uint32_t *lut, const DecTa
       len = 1;
     }
   }
-  if (br.used + len > br.nw * 32u) *bad = true;
   br.skip(len);
   return sym;
 }
@@ -112,7 +148,7 @@ __device__ inline uint32_t decode_sym(Bits &br, const uint32_t *lut, const DecTa
 template <typename T, int ND, int B0, int B1, int B2, bool FULL>
 __device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, const Header &h, const Geo &g,
                                              const DecWork &w, const PlanDev &plan, T *out, const Launch &L,
-                                             const uint32_t *lut, uint64_t idx, uint64_t nlanes) {
+                                             const DecLds &tl, uint32_t *win, uint64_t idx, uint64_t nlanes) {
   bool active = idx < nlanes;
   const uint64_t blk = dmap_block(g, L, FULL ? 0u : 1u, active ? idx : nlanes - 1);
   const Box bx = box_of(g, blk);
@@ -147,9 +183,13 @@ __device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, cons
     beta2 = cp[2];
     mu = cp[3];
   }
-  Bits br;
-  br.init((const uint32_t *)(s + h.off_payload) + w.off_pay[blk], (uint32_t)(w.off_pay[blk + 1] - w.off_pay[blk]));
-  bool bad = false;
+  const uint32_t nw = (uint32_t)(w.off_pay[blk + 1] - w.off_pay[blk]);
+  Window br;
+  br.pay = s + h.off_payload + 4ull * w.off_pay[blk];
+  br.end = s + h.total;
+  br.win = win;
+  br.pos = 0;
+  bool bad = false, defer = false;
   uint32_t used_out = 0;
   uint64_t sum = 0;
 
@@ -172,6 +212,7 @@ __device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, cons
 #pragma unroll
     for (int j = 0; j < B1; j++) {
       if (!FULL && (uint32_t)j >= n1) break;
+      if (j % 3 == 0) br.stage();
       T Aj = A0 + beta1 * ((T)j - c1);
       dpin(Aj);
       T rowold[B2], rv[B2];
@@ -179,7 +220,7 @@ __device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, cons
 #pragma unroll
       for (int k = 0; k < B2; k++) {
         const bool v = FULL || (uint32_t)k < n2;
-        const uint32_t sym = v ? decode_sym(br, lut, w.tab, w.symbols, &bad) : kRadius;
+        const uint32_t sym = v ? decode_sym(br, tl, &bad, &defer) : kRadius;
         const T a = Pw[j][k];
         rowold[k] = a;
         const T b = j > 0 ? Pw[j - 1][k] : (T)0;
@@ -198,8 +239,13 @@ __device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, cons
         const bool z = v && sym == 0;
         if (__builtin_expect(__ballot(z) != 0, 0)) {
           if (z) {
-            if (used_out < nout) r = outl[used_out];
-            else bad = true;
+            if (used_out < nout) {
+              T o = outl[used_out];
+              dpin(o);  // wait for the load here, not at every later use of r
+              r = o;
+            } else {
+              bad = true;
+            }
             used_out++;
           }
         }
@@ -216,13 +262,14 @@ __device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, cons
         if (FULL || (uint32_t)k < n2) *(T *)(dst + k * sizeof(T)) = rv[k];
 #pragma unroll
       for (int k = 0; k < B2; k++) Sv[k] = rowold[k];
-      drow_fence(cprev, sum, br.buf, br.nb);
+      drow_fence(cprev, sum, br.lp);
     }
   }
-  if (used_out != nout) bad = true;
+  if (used_out != nout || br.pos > nw * 32u) bad = true;
   const uint64_t *sumdc = (const uint64_t *)(s + h.off_sumdc);
   uint64_t why = 0;
-  if (bad) why = 2;
+  if (defer) why = 3;  // decoded again from the start: later symbols are not trusted
+  else if (bad) why = 2;
   else if (h.abft && sum != sumdc[blk]) {
     why = 1;
     count(w.cnt, C_DET + SDCSZ_T_RECON);
@@ -235,17 +282,31 @@ __device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, cons
 
 // Work-groups [0, L.full_wgs) take full blocks, the rest the partial shell.
 template <typename T, int ND, int B0, int B1, int B2>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kDecThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
 k_decode_fast(const uint8_t *__restrict__ s, Header h, Geo g, DecWork w, PlanDev plan, T *out, Launch L) {
   if (*w.err) return;  // invalid codebook or block table: nothing is read
-  __shared__ uint32_t lut[1u << kLutBits];
-  for (uint32_t t = threadIdx.x; t < (1u << kLutBits); t += blockDim.x) lut[t] = w.lut[t];
+  __shared__ DecLds tl;
+  __shared__ uint32_t win[kWin * kDecThreads];
+  for (uint32_t t = threadIdx.x; t < (1u << kLutBits); t += blockDim.x) tl.lut[t] = w.lut[t];
+  if (threadIdx.x < kMaxLen + 2) {
+    tl.first[threadIdx.x] = w.tab->first[threadIdx.x];
+    tl.count[threadIdx.x] = w.tab->count[threadIdx.x];
+    tl.start[threadIdx.x] = w.tab->start[threadIdx.x];
+  }
+  // symbols of the codes longer than kLutBits, as many as fit
+  const uint32_t lb = w.tab->start[kLutBits + 1];
+  const uint32_t ln = h.n_sym > lb ? min(h.n_sym - lb, kLongSyms) : 0u;
+  for (uint32_t t = threadIdx.x; t < ln; t += blockDim.x) tl.long_sym[t] = w.symbols[lb + t];
+  if (threadIdx.x == 0) {
+    tl.long_base = lb;
+    tl.long_n = ln;
+  }
   __syncthreads();
   if (blockIdx.x < L.full_wgs)
-    decode_lanes<T, ND, B0, B1, B2, true>(s, h, g, w, plan, out, L, lut,
+    decode_lanes<T, ND, B0, B1, B2, true>(s, h, g, w, plan, out, L, tl, win + threadIdx.x,
                                           (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, L.full_count);
   else
-    decode_lanes<T, ND, B0, B1, B2, false>(s, h, g, w, plan, out, L, lut,
+    decode_lanes<T, ND, B0, B1, B2, false>(s, h, g, w, plan, out, L, tl, win + threadIdx.x,
                                            (uint64_t)(blockIdx.x - L.full_wgs) * blockDim.x + threadIdx.x,
                                            L.shell_count);
 }

@@ -207,7 +207,9 @@ k_decode_list(const uint8_t *__restrict__ s, Header h, Geo g, DecWork w, PlanDev
 
 // Blocks the specialised decoder queued: a checksum mismatch (already counted
 // as detected) is re-executed from the compressed bytes; a block that could
-// not be decoded is decoded once more and, failing again, zeroed.
+// not be decoded is decoded once more and, failing again, zeroed; a block
+// with a symbol beyond the specialised decoder's tables runs the whole
+// per-block procedure here.  One thread per queue entry.
 template <typename T>
 __global__ void __launch_bounds__(64)
 k_decode_redo(const uint8_t *__restrict__ s, Header h, Geo g, DecWork w, T *out) {
@@ -216,8 +218,13 @@ k_decode_redo(const uint8_t *__restrict__ s, Header h, Geo g, DecWork w, T *out)
   const DecTab tab = *w.tab;
   const T q = (T)(2.0 * h.eb_abs);
   const uint64_t *sumdc = (const uint64_t *)(s + h.off_sumdc);
-  for (uint32_t e = threadIdx.x; e < n; e += blockDim.x) {
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
     const uint64_t blk = w.redo[e] & ((1ull << 56) - 1), why = w.redo[e] >> 56;
+    if (why == 3) {
+      const PlanDev none{nullptr, 0, nullptr};
+      decode_one<T>(s, h, g, w, none, out, 0, Region{}, blk);
+      continue;
+    }
     const Box b = box_of(g, blk);
     T *rec = (T *)w.recon + blk * (uint64_t)g.bpts;
     bool ok = decode_block_generic<T>(s, h, g, b, blk, w, tab, q, rec);

@@ -210,7 +210,10 @@ __global__ void __launch_bounds__(256) k_dectab(const uint32_t *cbk, uint32_t n_
   }
   __syncthreads();
   // prefix table: for each kLutBits-bit prefix the first length whose top
-  // bits fall among that length's codes (the rule of bit-by-bit decoding)
+  // bits fall among that length's codes (the rule of bit-by-bit decoding):
+  // symbol << 8 | length.  A prefix that only longer codes start with holds
+  // the range of their lengths instead, lmax << 16 | lmin << 8 (length 0);
+  // 0 when no codeword starts with it.
   for (uint32_t v = tid; v < (1u << kLutBits); v += 256) {
     uint32_t e = 0;
     for (uint32_t l = 1; l <= kLutBits; l++) {
@@ -221,6 +224,21 @@ __global__ void __launch_bounds__(256) k_dectab(const uint32_t *cbk, uint32_t n_
         e = (s << 8) | l;
         break;
       }
+    }
+    if (e == 0) {
+      uint32_t lmin = 0, lmax = 0;
+      for (uint32_t l = kLutBits + 1; l <= kMaxLen; l++) {
+        if (!cnt[l]) continue;
+        // 11-bit prefixes of the readable codes of length l (codes < 2^l)
+        const uint64_t c0 = first[l], c1 = min((uint64_t)first[l] + cnt[l], 1ull << l);
+        if (c0 >= c1) continue;
+        const uint64_t p0 = c0 >> (l - kLutBits), p1 = (c1 - 1) >> (l - kLutBits);
+        if (v >= p0 && v <= p1) {
+          if (!lmin) lmin = l;
+          lmax = l;
+        }
+      }
+      if (lmin) e = (lmax << 16) | (lmin << 8);
     }
     w.lut[v] = e;
   }

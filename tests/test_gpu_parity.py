@@ -251,3 +251,14 @@ def test_output_too_small_writes_nothing(codec):
     assert rc == 0 and size.value == s_r.size
     assert np.array_equal(out[: s_r.size].cpu().numpy(), s_r)
     assert bool((out[s_r.size:] == 0xA5).all())
+
+
+@pytest.mark.parametrize("shape,eb", [((48, 42, 36), 2e-5), ((102, 102, 102), 1e-5)])
+def test_large_codebooks_decode_like_the_oracle(codec, shape, eb):
+    # tens of thousands of symbols: long codewords beyond the specialised
+    # decoder's LDS tables send blocks to the generic path (and, past the
+    # re-run queue's capacity, the whole field)
+    x = synth.grf_field(shape, seed=9)
+    s, rep = check_roundtrip(codec, x, (6, 6, 6), eb)
+    n_sym = int(np.frombuffer(s[76:80].tobytes(), "<u4")[0])
+    assert n_sym > 8000, n_sym
