@@ -329,6 +329,15 @@ struct Staging {
 };
 thread_local Staging t_stage;
 
+// Huffman construction buffers of the calling thread, reused across calls
+struct HuffmanScratch {
+  HuffmanBuilder b;
+  std::vector<uint32_t> sym, code;
+  std::vector<uint64_t> cnt;
+  std::vector<uint8_t> len;
+};
+thread_local HuffmanScratch t_huff;
+
 // ---------------------------------------------------------------------------
 // header
 // ---------------------------------------------------------------------------
@@ -523,16 +532,26 @@ int compress_t(const void *d_in, const sdcsz_params *p, const Geo &g, uint8_t *d
   const uint32_t *hist = (const uint32_t *)(hs + kStageHist);
   HIPCHK(hipMemcpyAsync(hs + kStageHist, w.hist, 4 * 65536, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  std::vector<uint32_t> used;
-  std::vector<uint64_t> counts;
-  for (uint32_t s = 0; s < 65536; s++)
-    if (hist[s]) {
-      used.push_back(s);
-      counts.push_back(hist[s]);
+  std::vector<uint32_t> &used = t_huff.sym;
+  std::vector<uint64_t> &counts = t_huff.cnt;
+  used.clear();
+  counts.clear();
+  const uint64_t *h64 = (const uint64_t *)hist;
+  for (uint32_t q = 0; q < 32768; q++) {
+    const uint64_t v = h64[q];
+    if (!v) continue;
+    if ((uint32_t)v) {
+      used.push_back(2 * q);
+      counts.push_back((uint32_t)v);
     }
-  std::vector<uint8_t> len;
-  std::vector<uint32_t> codes;
-  huffman_lengths(counts, kMaxLen, len);
+    if (v >> 32) {
+      used.push_back(2 * q + 1);
+      counts.push_back(v >> 32);
+    }
+  }
+  std::vector<uint8_t> &len = t_huff.len;
+  std::vector<uint32_t> &codes = t_huff.code;
+  t_huff.b.lengths(counts, kMaxLen, len);
   canonical_codes(len, kMaxLen, codes);
   const uint32_t n_sym = (uint32_t)used.size();
   uint32_t *cb = (uint32_t *)(hs + kStageCb);

@@ -14,9 +14,17 @@ namespace {
 constexpr uint32_t kEncWin = 4096;
 constexpr uint32_t kEncLo = kRadius - kEncWin / 2;
 
+// Codeword table entry of a code: from the LDS window, or (rarely) from the
+// global table, waiting for that load inside its own branch.
 __device__ inline uint32_t enc_of(uint32_t code, const uint32_t *encw, const uint32_t *enc) {
   const uint32_t c = code - kEncLo;
-  return c < kEncWin ? encw[c] : enc[code];
+  uint32_t e = encw[c < kEncWin ? c : 0u];
+  if (__builtin_expect(c >= kEncWin, 0)) {
+    uint32_t f = enc[code];
+    __asm__ volatile("" : "+v"(f));
+    e = f;
+  }
+  return e;
 }
 
 __device__ inline void load_window(uint32_t *encw, const uint32_t *enc) {
@@ -24,19 +32,27 @@ __device__ inline void load_window(uint32_t *encw, const uint32_t *enc) {
   __syncthreads();
 }
 
-template <int B0, int B1, int B2> struct BlockCodes {
-  static constexpr int NG = (B0 * B1 * B2 + 3) / 4;
-  uint32_t v[2 * NG];  // two codes per word, padded point order
-  __device__ void load(const uint16_t *codes, uint64_t blk, uint32_t groups) {
-    const uint2 *cb = (const uint2 *)(codes + code_index(blk, 0, groups));
+// The codes of one lane's block, one plane at a time: plane i sits in
+// buffer i & 1 while plane i + 1 loads into the other (8 bytes per lane per
+// access, coalesced across the wave in the interleaved staging layout).
+template <int B0, int B1, int B2> struct PlaneCodes {
+  static constexpr int PG = B1 * B2 / 4;  // 4-code groups per plane
+  static_assert((B1 * B2) % 4 == 0, "a plane fills whole groups");
+  const uint2 *cb;
+  uint32_t v[2][2 * PG];  // two codes per word
+  __device__ void init(const uint16_t *codes, uint64_t blk, uint32_t groups) {
+    cb = (const uint2 *)(codes + code_index(blk, 0, groups));
+  }
+  __device__ void load(int i) {
 #pragma unroll
-    for (int gi = 0; gi < NG; gi++) {
-      const uint2 u = cb[(uint64_t)gi * 64];
-      v[2 * gi] = u.x;
-      v[2 * gi + 1] = u.y;
+    for (int gi = 0; gi < PG; gi++) {
+      const uint2 u = cb[(uint64_t)(i * PG + gi) * 64];
+      v[i & 1][2 * gi] = u.x;
+      v[i & 1][2 * gi + 1] = u.y;
     }
   }
-  __device__ uint32_t at(int qp) const { return (v[qp >> 1] >> (16 * (qp & 1))) & 0xFFFFu; }
+  // code q (= j * B2 + k) of plane i
+  __device__ uint32_t at(int i, int q) const { return (v[i & 1][q >> 1] >> (16 * (q & 1))) & 0xFFFFu; }
 };
 
 }  // namespace
@@ -51,12 +67,15 @@ __global__ void __launch_bounds__(256) k_check_fast(Geo g, CompWork w, uint32_t 
   if (blk >= g.n_blocks) return;
   const Box b = box_of(g, blk);
   const uint32_t n1 = b.n[1], n2 = b.n[2];
-  BlockCodes<B0, B1, B2> bc;
-  bc.load(w.codes, blk, g.groups);
+  PlaneCodes<B0, B1, B2> bc;
+  bc.init(w.codes, blk, g.groups);
+  bc.load(0);
   uint64_t s = 0, is = 0, bits = 0;
   bool missing = false;
 #pragma unroll
-  for (int i = 0; i < B0; i++)
+  for (int i = 0; i < B0; i++) {
+    if (i + 1 < B0) bc.load(i + 1);
+    __asm__ volatile("" ::: "memory");  // keep later planes' loads from being hoisted
 #pragma unroll
     for (int j = 0; j < B1; j++) {
       const uint32_t rowbase = ((uint32_t)i * n1 + (uint32_t)j) * n2;
@@ -64,7 +83,7 @@ __global__ void __launch_bounds__(256) k_check_fast(Geo g, CompWork w, uint32_t 
 #pragma unroll
       for (int k = 0; k < B2; k++) {
         const bool v = (uint32_t)i < b.n[0] && (uint32_t)j < n1 && (uint32_t)k < n2;
-        const uint32_t c = v ? bc.at((i * B1 + j) * B2 + k) : 0u;
+        const uint32_t c = v ? bc.at(i, j * B2 + k) : 0u;
         const uint32_t len = enc_of(c, encw, w.enc) & 0xFFu;
         if (v) {
           rs += c;
@@ -76,6 +95,7 @@ __global__ void __launch_bounds__(256) k_check_fast(Geo g, CompWork w, uint32_t 
       s += rs;
       is += (uint64_t)rowbase * rs + rk;
     }
+  }
   if (abft && (s != w.sum_q[blk] || is != w.isum_q[blk])) {
     // detected: locate and repair one code, then size the block again
     auto pos = [&](uint64_t p) -> uint64_t {
@@ -107,38 +127,80 @@ __global__ void __launch_bounds__(256) k_check_fast(Geo g, CompWork w, uint32_t 
 
 // Per-block Huffman encoding (MSB first into 32-bit words) and the block's
 // table entry, coefficients, sum_dc and outliers at their scanned offsets.
+// Finished words go to a per-lane ring of 16 words in LDS; at the end of
+// each row the lane writes out what is complete, whole aligned 32-byte
+// chunks as two 16-byte stores, so HBM sees full sectors instead of one
+// partial write per word (only a block's first and last chunk are partial).
 template <typename T, int B0, int B1, int B2>
 __global__ void __launch_bounds__(256) k_encode_fast(Geo g, CompWork w, uint8_t *out) {
   if (!w.res[R_WRITTEN]) return;  // the stream is not written (see k_header)
   const Header h = *w.hdr;
   __shared__ uint32_t encw[kEncWin];
+  __shared__ uint32_t ring_all[16 * 256];
   load_window(encw, w.enc);
   const uint64_t blk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (blk >= g.n_blocks) return;
   const Box b = box_of(g, blk);
-  BlockCodes<B0, B1, B2> bc;
-  bc.load(w.codes, blk, g.groups);
-  uint32_t *dst = (uint32_t *)(out + h.off_payload) + w.off_pay[blk];
+  PlaneCodes<B0, B1, B2> bc;
+  bc.init(w.codes, blk, g.groups);
+  bc.load(0);
+  uint32_t *ring = ring_all + threadIdx.x;  // word with absolute index a at ring[(a & 15) * 256]
+  uint32_t *pay = (uint32_t *)(out + h.off_payload);
+  uint64_t wabs = w.off_pay[blk];  // absolute index of the next word produced
+  uint64_t fl = wabs;              // first word not yet written out
+  auto flush = [&]() {
+    if (fl & 7) {  // block head: single words up to the first chunk boundary
+      const uint64_t hb = (fl + 7) & ~7ull;
+      if (wabs >= hb)
+        for (; fl < hb; fl++) pay[fl] = ring[(fl & 15) * 256];
+    }
+    if (!(fl & 7) && fl + 8 <= wabs) {
+      const uint32_t s0 = (uint32_t)(fl & 8);
+      uint4 u0, u1;
+      u0.x = ring[(s0 + 0) * 256];
+      u0.y = ring[(s0 + 1) * 256];
+      u0.z = ring[(s0 + 2) * 256];
+      u0.w = ring[(s0 + 3) * 256];
+      u1.x = ring[(s0 + 4) * 256];
+      u1.y = ring[(s0 + 5) * 256];
+      u1.z = ring[(s0 + 6) * 256];
+      u1.w = ring[(s0 + 7) * 256];
+      uint4 *d = (uint4 *)(pay + fl);
+      d[0] = u0;
+      d[1] = u1;
+      fl += 8;
+    }
+  };
   uint64_t acc = 0;
   uint32_t nacc = 0;
 #pragma unroll
-  for (int i = 0; i < B0; i++)
+  for (int i = 0; i < B0; i++) {
+    if (i + 1 < B0) bc.load(i + 1);
 #pragma unroll
-    for (int j = 0; j < B1; j++)
+    for (int j = 0; j < B1; j++) {
 #pragma unroll
       for (int k = 0; k < B2; k++) {
         const bool v = (uint32_t)i < b.n[0] && (uint32_t)j < b.n[1] && (uint32_t)k < b.n[2];
-        const uint32_t e = enc_of(v ? bc.at((i * B1 + j) * B2 + k) : kRadius, encw, w.enc);
+        const uint32_t e = enc_of(v ? bc.at(i, j * B2 + k) : kRadius, encw, w.enc);
         const uint32_t len = v ? (e & 0xFFu) : 0u;
         acc = (acc << len) | (e >> 8 & ((1u << len) - 1u));
         nacc += len;
         if (nacc >= 32) {
           nacc -= 32;
-          *dst++ = (uint32_t)(acc >> nacc);
+          ring[(wabs & 15) * 256] = (uint32_t)(acc >> nacc);
+          wabs++;
           acc &= (1ull << nacc) - 1;
         }
       }
-  if (nacc > 0) *dst = (uint32_t)(acc << (32 - nacc));
+      flush();
+    }
+  }
+  if (nacc > 0) {
+    ring[(wabs & 15) * 256] = (uint32_t)(acc << (32 - nacc));
+    wabs++;
+  }
+  flush();
+  for (; fl < wabs; fl++) pay[fl] = ring[(fl & 15) * 256];  // block tail
   const uint32_t meta = w.meta[blk];
   uint32_t *tab = (uint32_t *)(out + h.off_table) + 2 * blk;
   tab[0] = w.words[blk];
