@@ -1,5 +1,6 @@
 // host.cpp -- C ABI, parameter validation, workspace layout, Huffman codebook
 // construction, stream header handling and kernel orchestration.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,9 +22,11 @@ namespace {
   } while (0)
 
 // ---------------------------------------------------------------------------
-// kernel-phase timing with HIP events on the call's stream
+// kernel-phase timing: with timing on, a phase's first and last kernel
+// dispatches record its start and stop events themselves
+// (hipExtLaunchKernelGGL), so timing adds no packets to the stream
 // ---------------------------------------------------------------------------
-enum { PH_RANGE, PH_PREDICT, PH_CODEFAULT, PH_CHECK, PH_SCAN_C, PH_ENCODE, PH_SCAN_D, PH_DECODE };
+enum { PH_RANGE, PH_PREDICT, PH_CODEFAULT, PH_CHECK, PH_SCAN_C, PH_ENCODE, PH_SCAN_D, PH_DECODE, PH_NONE = -1 };
 const char *kPhaseNames[SDCSZ_N_PHASES] = {"range",      "predict_quantize", "code_faults", "code_check",
                                            "scan_compress", "encode",        "scan_decompress", "decode"};
 
@@ -34,23 +37,18 @@ struct PhaseTimer {
   bool pending[SDCSZ_N_PHASES] = {};
   double ms[SDCSZ_N_PHASES] = {};
   uint64_t launches[SDCSZ_N_PHASES] = {};
-  void begin(int ph, hipStream_t st) {
-    if (!on) return;
+  bool ready() {
+    if (!on) return false;
     if (!made) {
       for (int i = 0; i < SDCSZ_N_PHASES; i++)
         for (int j = 0; j < 2; j++)
           if (hipEventCreate(&ev[i][j]) != hipSuccess) {
             on = false;
-            return;
+            return false;
           }
       made = true;
     }
-    (void)hipEventRecord(ev[ph][0], st);
-  }
-  void end(int ph, hipStream_t st) {
-    if (!on || !made) return;
-    (void)hipEventRecord(ev[ph][1], st);
-    pending[ph] = true;
+    return true;
   }
   void resolve() {
     for (int i = 0; i < SDCSZ_N_PHASES; i++)
@@ -66,6 +64,21 @@ struct PhaseTimer {
   }
 };
 PhaseTimer g_timer;
+
+// Launch one kernel of phase `ph` (PH_NONE: untimed); `first`/`last` mark the
+// phase's first and last kernel.
+template <typename F, typename... Args>
+void launch(int ph, bool first, bool last, F kernel, dim3 grid, dim3 block, hipStream_t st, Args... args) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (ph >= 0 && g_timer.ready()) {
+    if (first) a = g_timer.ev[ph][0];
+    if (last) {
+      b = g_timer.ev[ph][1];
+      g_timer.pending[ph] = true;
+    }
+  }
+  hipExtLaunchKernelGGL(kernel, grid, block, 0, st, a, b, 0, args...);
+}
 
 uint32_t grid_for(uint64_t n, uint32_t per) { return (uint32_t)std::max<uint64_t>(1, (n + per - 1) / per); }
 uint64_t a256(uint64_t v) { return (v + 255) & ~255ull; }
@@ -264,11 +277,9 @@ void launch_fast(const T *in, const Geo &g, const RegTab<T> &rt, const PlanDev &
                        ABFT ? 1u : 0u, predictor, plan_blocks, n_plan_blocks);
   Launch L;
   const uint32_t wgs = fast_launch(g, &L);
-  g_timer.begin(PH_PREDICT, st);
   if (wgs)
-    hipLaunchKernelGGL((k_compress_fast<T, 3, 6, 6, 6, ABFT>), dim3(wgs), dim3(256), 0, st, in, g, rt, pd, w,
-                       predictor, L);
-  g_timer.end(PH_PREDICT, st);
+    launch(PH_PREDICT, true, true, k_compress_fast<T, 3, 6, 6, 6, ABFT>, dim3(wgs), dim3(256), st, in, g, rt, pd, w,
+           predictor, L);
   hipLaunchKernelGGL(k_redo<T>, dim3(1), dim3(64), 0, st, in, g, rt, pd, w, ABFT ? 1u : 0u, predictor);
 }
 
@@ -418,7 +429,7 @@ int upload_plan(const std::vector<sdcsz_fault> &pl, uint64_t nb, uint8_t *ws, ui
 // exclusive scans of payload words, outliers and regression flags per block,
 // with the 64-bit totals in tot[0..2]
 int launch_scan(ScanSrc src, uint64_t n, uint64_t *part, uint64_t *off_pay, uint32_t *off_out,
-                uint32_t *off_coef, uint64_t *tot, hipStream_t st) {
+                uint32_t *off_coef, uint64_t *tot, int ph, hipStream_t st) {
   if (n == 0) {
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, (unsigned long long *)off_pay, 1);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, off_out, 1);
@@ -427,10 +438,10 @@ int launch_scan(ScanSrc src, uint64_t n, uint64_t *part, uint64_t *off_pay, uint
     return hipGetLastError() == hipSuccess ? SDCSZ_OK : SDCSZ_EHIP;
   }
   uint32_t chunks = (uint32_t)((n + kScanChunk - 1) / kScanChunk);
-  hipLaunchKernelGGL(k_scan1, dim3(chunks), dim3(kScanThreads), 0, st, src, n, part);
-  hipLaunchKernelGGL(k_scan2, dim3(1), dim3(kScanThreads), 0, st, part, chunks);
-  hipLaunchKernelGGL(k_scan3, dim3(chunks), dim3(kScanThreads), 0, st, src, n, part, off_pay, off_out, off_coef,
-                     tot);
+  launch(ph, true, false, k_scan1, dim3(chunks), dim3(kScanThreads), st, src, n, part);
+  launch(ph, false, false, k_scan2, dim3(1), dim3(kScanThreads), st, part, chunks);
+  launch(ph, false, true, k_scan3, dim3(chunks), dim3(kScanThreads), st, src, n, (const uint64_t *)part, off_pay,
+         off_out, off_coef, tot);
   return hipGetLastError() == hipSuccess ? SDCSZ_OK : SDCSZ_EHIP;
 }
 
@@ -491,13 +502,11 @@ int compress_t(const void *d_in, const sdcsz_params *p, const Geo &g, uint8_t *d
 
   hipLaunchKernelGGL(k_zero_u32, dim3(256), dim3(256), 0, st, (uint32_t *)ws, L.zero_end / 4);
   uint32_t nparts = 0;
-  g_timer.begin(PH_RANGE, st);
   if (p->eb_mode == SDCSZ_REL && g.n_values) {
     nparts = (uint32_t)std::min<uint64_t>(kRangeBlocks, grid_for(g.n_values, kRangeThreads * 8));
-    hipLaunchKernelGGL(k_range<T>, dim3(nparts), dim3(kRangeThreads), 0, st, (const T *)d_in, g.n_values,
-                       (double *)w.range_part);
+    launch(PH_RANGE, true, true, k_range<T>, dim3(nparts), dim3(kRangeThreads), st, (const T *)d_in, g.n_values,
+           (double *)w.range_part);
   }
-  g_timer.end(PH_RANGE, st);
   hipLaunchKernelGGL(k_consts, dim3(1), dim3(256), 0, st, (const double *)w.range_part, nparts, p->eb_mode,
                      p->eb, w.eb);
   HIPCHK(hipGetLastError());
@@ -513,18 +522,14 @@ int compress_t(const void *d_in, const sdcsz_params *p, const Geo &g, uint8_t *d
       if (p->abft) launch_fast<T, true>((const T *)d_in, g, rt, pd, w, p->predictor, d_pb, (uint32_t)pb.size(), st);
       else launch_fast<T, false>((const T *)d_in, g, rt, pd, w, p->predictor, d_pb, (uint32_t)pb.size(), st);
     } else {
-      g_timer.begin(PH_PREDICT, st);
-      hipLaunchKernelGGL(k_compress_generic<T>, dim3(grid_for(g.n_blocks, 64)), dim3(64), 0, st,
-                         (const T *)d_in, g, rt, pd, w, p->abft, p->predictor);
-      g_timer.end(PH_PREDICT, st);
+      launch(PH_PREDICT, true, true, k_compress_generic<T>, dim3(grid_for(g.n_blocks, 64)), dim3(64), st,
+             (const T *)d_in, g, rt, pd, w, p->abft, p->predictor);
     }
     HIPCHK(hipGetLastError());
     bool any_code = false;
     for (auto &f : plan) any_code |= f.target == SDCSZ_T_CODE;
     if (any_code) {
-      g_timer.begin(PH_CODEFAULT, st);
-      hipLaunchKernelGGL(k_code_faults, dim3(1), dim3(64), 0, st, pd, g, w.codes, w.cnt);
-      g_timer.end(PH_CODEFAULT, st);
+      launch(PH_CODEFAULT, true, true, k_code_faults, dim3(1), dim3(64), st, pd, g, w.codes, w.cnt);
     }
   }
 
@@ -565,17 +570,14 @@ int compress_t(const void *d_in, const sdcsz_params *p, const Geo &g, uint8_t *d
   }
 
   if (g.n_blocks) {
-    g_timer.begin(PH_CHECK, st);
     if (fast)
-      hipLaunchKernelGGL((k_check_fast<6, 6, 6>), dim3(grid_for(g.n_blocks, 256)), dim3(256), 0, st, g, w, p->abft);
+      launch(PH_CHECK, true, true, k_check_fast<6, 6, 6>, dim3(grid_for(g.n_blocks, 256)), dim3(256), st, g, w,
+             p->abft);
     else
-      hipLaunchKernelGGL(k_codes_check, dim3(grid_for(g.n_blocks, 256)), dim3(256), 0, st, g, w, p->abft);
-    g_timer.end(PH_CHECK, st);
+      launch(PH_CHECK, true, true, k_codes_check, dim3(grid_for(g.n_blocks, 256)), dim3(256), st, g, w, p->abft);
   }
   ScanSrc src{w.words, w.meta, 1};
-  g_timer.begin(PH_SCAN_C, st);
-  rc = launch_scan(src, g.n_blocks, w.scan_part, w.off_pay, w.off_out, w.off_coef, w.tot, st);
-  g_timer.end(PH_SCAN_C, st);
+  rc = launch_scan(src, g.n_blocks, w.scan_part, w.off_pay, w.off_out, w.off_coef, w.tot, PH_SCAN_C, st);
   if (rc) return rc;
 
   // header, codebook and pads on the device; the encoder follows its decision
@@ -594,12 +596,11 @@ int compress_t(const void *d_in, const sdcsz_params *p, const Geo &g, uint8_t *d
   h.n_blocks = g.n_blocks;
   h.predictor = p->predictor;
   hipLaunchKernelGGL(k_header, dim3(grid_for(n_sym, 256)), dim3(256), 0, st, h, w, d_out, d_out ? out_cap : 0);
-  g_timer.begin(PH_ENCODE, st);
   if (fast)
-    hipLaunchKernelGGL((k_encode_fast<T, 6, 6, 6>), dim3(grid_for(g.n_blocks, 256)), dim3(256), 0, st, g, w, d_out);
+    launch(PH_ENCODE, true, true, k_encode_fast<T, 6, 6, 6>, dim3(grid_for(g.n_blocks, 256)), dim3(256), st, g, w,
+           d_out);
   else if (g.n_blocks)
-    hipLaunchKernelGGL(k_encode<T>, dim3(grid_for(g.n_blocks, 256)), dim3(256), 0, st, g, w, d_out);
-  g_timer.end(PH_ENCODE, st);
+    launch(PH_ENCODE, true, true, k_encode<T>, dim3(grid_for(g.n_blocks, 256)), dim3(256), st, g, w, d_out);
   HIPCHK(hipGetLastError());
 
   // counters and results: one copy, one synchronisation
@@ -685,9 +686,7 @@ int decode_t(const uint8_t *d_s, Opened &o, T *d_out, uint32_t mode, const Regio
   hipLaunchKernelGGL(k_dectab, dim3(1), dim3(256), 0, st, (const uint32_t *)(d_s + kHeader), h.n_sym, w);
   const uint32_t *table = (const uint32_t *)(d_s + h.off_table);
   ScanSrc src{table, table + 1, 2};
-  g_timer.begin(PH_SCAN_D, st);
-  rc = launch_scan(src, g.n_blocks, w.scan_part, w.off_pay, w.off_out, w.off_coef, w.tot, st);
-  g_timer.end(PH_SCAN_D, st);
+  rc = launch_scan(src, g.n_blocks, w.scan_part, w.off_pay, w.off_out, w.off_coef, w.tot, PH_SCAN_D, st);
   hipLaunchKernelGGL(k_dec_check, dim3(1), dim3(64), 0, st, (const uint64_t *)w.tot, h.payload_words, h.n_outliers,
                      h.n_regression, w.err);
   if (rc) return rc;
@@ -701,17 +700,14 @@ int decode_t(const uint8_t *d_s, Opened &o, T *d_out, uint32_t mode, const Regio
                          d_pb, (uint32_t)pb.size());
     Launch FL;
     const uint32_t wgs = fast_launch(g, &FL);
-    g_timer.begin(PH_DECODE, st);
     if (wgs)
-      hipLaunchKernelGGL((k_decode_fast<T, 3, 6, 6, 6>), dim3(wgs), dim3(256), 0, st, d_s, h, g, w, pd, d_out, FL);
-    g_timer.end(PH_DECODE, st);
+      launch(PH_DECODE, true, true, k_decode_fast<T, 3, 6, 6, 6>, dim3(wgs), dim3(256), st, d_s, h, g, w, pd, d_out,
+             FL);
     hipLaunchKernelGGL(k_decode_redo<T>, dim3(kMaxRedo / 64), dim3(64), 0, st, d_s, h, g, w, d_out);
     HIPCHK(hipGetLastError());
   } else if (g.n_blocks) {
-    g_timer.begin(PH_DECODE, st);
-    hipLaunchKernelGGL(k_decode_generic<T>, dim3(grid_for(g.n_blocks, 64)), dim3(64), 0, st, d_s, h, g, w, pd,
-                       d_out, mode, reg);
-    g_timer.end(PH_DECODE, st);
+    launch(PH_DECODE, true, true, k_decode_generic<T>, dim3(grid_for(g.n_blocks, 64)), dim3(64), st, d_s, h, g, w,
+           pd, d_out, mode, reg);
     HIPCHK(hipGetLastError());
   }
   // counters, redo count and error flag: one copy, one synchronisation

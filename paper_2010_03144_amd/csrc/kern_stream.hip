@@ -104,21 +104,30 @@ __global__ void __launch_bounds__(256) k_header(Header h, CompWork w, uint8_t *o
 // with lengths 1..kMaxLen; codes follow (length, symbol) order.  Writes
 // w.symbols (symbols by (length, symbol)), w.tab (first code, count and
 // first position per length) and w.lut (for each kLutBits-bit prefix the
-// shortest codeword it starts with, symbol << 8 | length, 0 if none); sets
-// *w.err on an invalid codebook.  One work-group of 256 threads.
+// shortest codeword it starts with, symbol << 8 | length; for a prefix that
+// only longer codewords start with, the range of their lengths,
+// lmax << 16 | lmin << 8; 0 if none); sets *w.err on an invalid codebook.
+// One work-group of 256 threads.  Entries in ascending symbol order (as the
+// compressor writes them) are ranked per length with wave ballots; any
+// other order goes through a table of the lengths of all 65536 symbols.
 __global__ void __launch_bounds__(256) k_dectab(const uint32_t *cbk, uint32_t n_sym, DecWork w) {
   __shared__ uint32_t lens4[65536 / 4];       // code length of each symbol, one byte each
   __shared__ uint32_t part[kMaxLen + 1][256];  // per length: symbols before each thread's range
-  __shared__ uint32_t wsum[kMaxLen + 1][4];    // per length: symbols in each wave's ranges
-  __shared__ uint16_t short_sym[1u << kLutBits];  // symbols of the codes of <= kLutBits bits, by position
+  __shared__ uint32_t wsum[kMaxLen + 1][4];    // per length: symbols in each wave's part
+  __shared__ uint32_t run[kMaxLen + 1];        // per length: symbols placed so far
+  __shared__ uint16_t short_sym[1u << kLutBits];  // symbols at positions < 2^kLutBits
   __shared__ uint32_t first[kMaxLen + 2], cnt[kMaxLen + 2], start[kMaxLen + 2];
-  __shared__ uint32_t smin, smax, bad;
+  __shared__ uint32_t smin, smax, bad, unordered;
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (uint32_t i = tid; i < 65536 / 4; i += 256) lens4[i] = 0;
+  if (tid <= kMaxLen) {
+    cnt[tid] = 0;
+    run[tid] = 0;
+  }
   if (tid == 0) {
     smin = 0xFFFFFFFFu;
     smax = 0;
     bad = 0;
+    unordered = 0;
   }
   __syncthreads();
   for (uint32_t t = tid; t < n_sym; t += 256) {
@@ -127,52 +136,67 @@ __global__ void __launch_bounds__(256) k_dectab(const uint32_t *cbk, uint32_t n_
       atomicOr(&bad, 1u);
       continue;
     }
-    const uint32_t sh = 8 * (s & 3);
-    const uint32_t old = atomicOr(&lens4[s >> 2], l << sh);
-    if ((old >> sh) & 0xFFu) atomicOr(&bad, 1u);  // symbol listed twice
-    atomicMin(&smin, s);
-    atomicMax(&smax, s);
+    if (t > 0 && (cbk[t - 1] >> 8) >= s) atomicOr(&unordered, 1u);
+    atomicAdd(&cnt[l], 1u);
   }
   __syncthreads();
   if (bad) {
     if (tid == 0) *w.err = 1;
     return;
   }
+  const bool ordered = !unordered;
   auto len_of = [&](uint32_t s) { return (lens4[s >> 2] >> (8 * (s & 3))) & 0xFFu; };
-  // each thread takes a contiguous range of the used symbol span and counts
-  // its symbols per length
-  const uint32_t span = smax >= smin ? smax - smin + 1 : 0;
-  const uint32_t per = (span + 255) / 256;
-  const uint32_t a = smin + tid * per, b = min(a + per, smin + span);
-  uint32_t mine[kMaxLen + 1];
-#pragma unroll
-  for (uint32_t l = 0; l <= kMaxLen; l++) mine[l] = 0;
-  for (uint32_t s = a; s < b; s++) {
-    const uint32_t l = len_of(s);
-#pragma unroll
-    for (uint32_t m = 1; m <= kMaxLen; m++) mine[m] += l == m ? 1u : 0u;
-  }
-  // exclusive prefix over the threads, per length: wave scans, then wave offsets
-#pragma unroll
-  for (uint32_t l = 1; l <= kMaxLen; l++) {
-    uint32_t v = mine[l];
-#pragma unroll
-    for (uint32_t d = 1; d < 64; d <<= 1) {
-      const uint32_t u = (uint32_t)__shfl_up((int)v, d);
-      if (lane >= d) v += u;
+  uint32_t a = 0, b = 0;  // unordered case: this thread's range of the symbol span
+  if (!ordered) {
+    // lengths by symbol (a symbol listed twice is an error), then counts
+    // per length over contiguous symbol ranges, one per thread
+    for (uint32_t i = tid; i < 65536 / 4; i += 256) lens4[i] = 0;
+    __syncthreads();
+    for (uint32_t t = tid; t < n_sym; t += 256) {
+      const uint32_t e = cbk[t], s = e >> 8, l = e & 0xFFu;
+      const uint32_t sh = 8 * (s & 3);
+      const uint32_t old = atomicOr(&lens4[s >> 2], l << sh);
+      if ((old >> sh) & 0xFFu) atomicOr(&bad, 1u);
+      atomicMin(&smin, s);
+      atomicMax(&smax, s);
     }
-    part[l][tid] = v - mine[l];
-    if (lane == 63) wsum[l][wave] = v;
-  }
-  __syncthreads();
-  if (tid <= kMaxLen) {
-    uint32_t acc = 0;
-    for (uint32_t q = 0; q < 4; q++) {
-      const uint32_t c = tid ? wsum[tid][q] : 0u;
-      wsum[tid][q] = acc;
-      acc += c;
+    __syncthreads();
+    if (bad) {
+      if (tid == 0) *w.err = 1;
+      return;
     }
-    cnt[tid] = acc;
+    const uint32_t span = smax >= smin ? smax - smin + 1 : 0;
+    const uint32_t per = (span + 255) / 256;
+    a = smin + tid * per;
+    b = min(a + per, smin + span);
+    uint32_t mine[kMaxLen + 1];
+#pragma unroll
+    for (uint32_t l = 0; l <= kMaxLen; l++) mine[l] = 0;
+    for (uint32_t s = a; s < b; s++) {
+      const uint32_t l = len_of(s);
+#pragma unroll
+      for (uint32_t m = 1; m <= kMaxLen; m++) mine[m] += l == m ? 1u : 0u;
+    }
+#pragma unroll
+    for (uint32_t l = 1; l <= kMaxLen; l++) {
+      uint32_t v = mine[l];
+#pragma unroll
+      for (uint32_t d = 1; d < 64; d <<= 1) {
+        const uint32_t u = (uint32_t)__shfl_up((int)v, d);
+        if (lane >= d) v += u;
+      }
+      part[l][tid] = v - mine[l];
+      if (lane == 63) wsum[l][wave] = v;
+    }
+    __syncthreads();
+    if (tid <= kMaxLen) {
+      uint32_t acc = 0;
+      for (uint32_t q = 0; q < 4; q++) {
+        const uint32_t c = tid ? wsum[tid][q] : 0u;
+        wsum[tid][q] = acc;
+        acc += c;
+      }
+    }
   }
   __syncthreads();
   if (tid == 0) {
@@ -181,6 +205,7 @@ __global__ void __launch_bounds__(256) k_dectab(const uint32_t *cbk, uint32_t n_
     // extended to l bits)
     uint32_t code = 0, acc = 0, lo = kMaxLen + 1, hi = 0;
     first[0] = start[0] = 0;
+    cnt[0] = 0;
     for (uint32_t l = 1; l <= kMaxLen; l++) {
       code = (code + cnt[l - 1]) << 1;
       first[l] = code;
@@ -201,19 +226,42 @@ __global__ void __launch_bounds__(256) k_dectab(const uint32_t *cbk, uint32_t n_
     tb->max_len = hi;
   }
   __syncthreads();
-  for (uint32_t s = a; s < b; s++) {
-    const uint32_t l = len_of(s);
-    if (!l) continue;
-    const uint32_t pos = start[l] + wsum[l][wave] + part[l][tid]++;
+  auto place = [&](uint32_t pos, uint32_t s) {
     w.symbols[pos] = (uint16_t)s;
     if (pos < (1u << kLutBits)) short_sym[pos] = (uint16_t)s;
+  };
+  if (ordered) {
+    // rank of each entry among the earlier entries of its length
+    const uint64_t below = (1ull << lane) - 1;
+    for (uint32_t base = 0; base < n_sym; base += 256) {
+      const uint32_t t = base + tid;
+      const uint32_t e = t < n_sym ? cbk[t] : 0u, l = e & 0xFFu;
+      uint32_t rank = 0;
+      for (uint32_t m = 1; m <= kMaxLen; m++) {
+        const uint64_t mask = __ballot(l == m);
+        if (l == m) rank = (uint32_t)__popcll(mask & below);
+        if (lane == 0) wsum[m][wave] = (uint32_t)__popcll(mask);
+      }
+      __syncthreads();
+      if (l) {
+        uint32_t off = run[l];
+        for (uint32_t q = 0; q < wave; q++) off += wsum[l][q];
+        place(start[l] + off + rank, e >> 8);
+      }
+      __syncthreads();
+      if (tid >= 1 && tid <= kMaxLen) run[tid] += wsum[tid][0] + wsum[tid][1] + wsum[tid][2] + wsum[tid][3];
+      __syncthreads();
+    }
+  } else {
+    for (uint32_t s = a; s < b; s++) {
+      const uint32_t l = len_of(s);
+      if (!l) continue;
+      place(start[l] + wsum[l][wave] + part[l][tid]++, s);
+    }
   }
   __syncthreads();
   // prefix table: for each kLutBits-bit prefix the first length whose top
-  // bits fall among that length's codes (the rule of bit-by-bit decoding):
-  // symbol << 8 | length.  A prefix that only longer codes start with holds
-  // the range of their lengths instead, lmax << 16 | lmin << 8 (length 0);
-  // 0 when no codeword starts with it.
+  // bits fall among that length's codes (the rule of bit-by-bit decoding)
   for (uint32_t v = tid; v < (1u << kLutBits); v += 256) {
     uint32_t e = 0;
     for (uint32_t l = 1; l <= kLutBits; l++) {
