@@ -67,23 +67,31 @@ __global__ void __launch_bounds__(256) k_check_fast(Geo g, CompWork w, uint32_t 
   if (blk >= g.n_blocks) return;
   const Box b = box_of(g, blk);
   const uint32_t n1 = b.n[1], n2 = b.n[2];
-  PlaneCodes<B0, B1, B2> bc;
-  bc.init(w.codes, blk, g.groups);
-  bc.load(0);
+  // planes in a rolled loop (one plane of code groups live, the next in flight)
+  const uint2 *cb = (const uint2 *)(w.codes + code_index(blk, 0, g.groups));
+  constexpr int PG = B1 * B2 / 4;
+  static_assert((B1 * B2) % 4 == 0, "a plane fills whole groups");
+  uint2 cur[PG], nxt[PG];
+#pragma unroll
+  for (int t = 0; t < PG; t++) cur[t] = cb[(uint64_t)t * 64];
   uint64_t s = 0, is = 0, bits = 0;
   bool missing = false;
-#pragma unroll
+#pragma unroll 1
   for (int i = 0; i < B0; i++) {
-    if (i + 1 < B0) bc.load(i + 1);
-    __asm__ volatile("" ::: "memory");  // keep later planes' loads from being hoisted
+    if (i + 1 < B0) {
+#pragma unroll
+      for (int t = 0; t < PG; t++) nxt[t] = cb[(uint64_t)((i + 1) * PG + t) * 64];
+    }
 #pragma unroll
     for (int j = 0; j < B1; j++) {
       const uint32_t rowbase = ((uint32_t)i * n1 + (uint32_t)j) * n2;
       uint32_t rs = 0, rk = 0;
 #pragma unroll
       for (int k = 0; k < B2; k++) {
+        const int q = j * B2 + k;
+        const uint32_t word = (q & 2) ? cur[q >> 2].y : cur[q >> 2].x;
         const bool v = (uint32_t)i < b.n[0] && (uint32_t)j < n1 && (uint32_t)k < n2;
-        const uint32_t c = v ? bc.at(i, j * B2 + k) : 0u;
+        const uint32_t c = v ? ((word >> (16 * (q & 1))) & 0xFFFFu) : 0u;
         const uint32_t len = enc_of(c, encw, w.enc) & 0xFFu;
         if (v) {
           rs += c;
@@ -95,6 +103,8 @@ __global__ void __launch_bounds__(256) k_check_fast(Geo g, CompWork w, uint32_t 
       s += rs;
       is += (uint64_t)rowbase * rs + rk;
     }
+#pragma unroll
+    for (int t = 0; t < PG; t++) cur[t] = nxt[t];
   }
   if (abft && (s != w.sum_q[blk] || is != w.isum_q[blk])) {
     // detected: locate and repair one code, then size the block again
