@@ -88,19 +88,23 @@ template <int ND, int B0, int B1, int B2> constexpr int sample_slot(int i0, int 
 
 // Checksum-word accumulation: S = sum of the words, Q = sum of the running
 // sums; the paper's isum = sum_j j * w_j (0-based j) is then n_words*S - Q.
+// Here the pair only detects (the block is then redone by the generic
+// routine, which locates and repairs with the exact 64-bit checksums), so
+// it is kept modulo 2^32: a corrupted word changes S by a non-zero amount
+// below 2^32 in magnitude, which no 32-bit wrap can hide.
 template <typename T> struct Ck;
 template <> struct Ck<float> {
-  __device__ static inline void add(float v, uint64_t &S, uint64_t &Q) {
+  __device__ static inline void add(float v, uint32_t &S, uint32_t &Q) {
     S += __float_as_uint(v);
     Q += S;
   }
 };
 template <> struct Ck<double> {
-  __device__ static inline void add(double v, uint64_t &S, uint64_t &Q) {
-    uint64_t u = (uint64_t)__double_as_longlong(v);
-    S += u & 0xFFFFFFFFull;
+  __device__ static inline void add(double v, uint32_t &S, uint32_t &Q) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    S += (uint32_t)u;
     Q += S;
-    S += u >> 32;
+    S += (uint32_t)(u >> 32);
     Q += S;
   }
 };
@@ -171,31 +175,34 @@ __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const G
       const T v = *(const T *)(wbase + (loff + ii * PSB + jj * RSB + kk * (uint32_t)sizeof(T)));
       return valid(i, j, k) ? v : (T)0;
     };
-    const uint64_t nwords = (uint64_t)n0 * n1 * n2 * Wd<T>::per;
 
     // ---- first pass: input checksums, regression sums, Lorenzo costs ------
     T x[B0][B1][B2];
     T sx[NS > 0 ? NS : 1];
-    uint64_t S1 = 0, Q1 = 0;
+    uint32_t S1 = 0, Q1 = 0;
     uint32_t e_lor = 0;
     T S0 = 0, Sa0 = 0, Sa1 = 0, Sa2 = 0;
 #pragma unroll
-    for (int k = 0; k < B2; k++) x[0][0][k] = ld(0, 0, k);
+    for (int j = 0; j < B1; j++)
+#pragma unroll
+      for (int k = 0; k < B2; k++) x[0][j][k] = ld(0, j, k);
 #pragma unroll
     for (int i = 0; i < B0; i++) {
       T P = 0, A = 0, Bv = 0;
       T D[B2];
 #pragma unroll
       for (int k = 0; k < B2; k++) D[k] = 0;
+      // loads run one plane ahead of the work (a row's work is far shorter
+      // than the memory latency)
+      if (i + 1 < B0) {
+#pragma unroll
+        for (int j = 0; j < B1; j++)
+#pragma unroll
+          for (int k = 0; k < B2; k++) x[i + 1][j][k] = ld(i + 1, j, k);
+      }
 #pragma unroll
       for (int j = 0; j < B1; j++) {
         T R = 0;
-        // issue the next row's loads, then work on this row
-        const int jn = j + 1 < B1 ? j + 1 : 0, in_ = j + 1 < B1 ? i : i + 1;
-        if (in_ < B0) {
-#pragma unroll
-          for (int k = 0; k < B2; k++) x[in_][jn][k] = ld(in_, jn, k);
-        }
 #pragma unroll
         for (int k = 0; k < B2; k++) {
           if (valid(i, j, k)) {
@@ -261,7 +268,7 @@ __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const G
 
     uint64_t why = 0;
     if (ABFT) {  // coefficient checksums, taken again where the coefficients are used
-      uint64_t sc = 0, qc = 0, sc2 = 0, qc2 = 0;
+      uint32_t sc = 0, qc = 0, sc2 = 0, qc2 = 0;
       Ck<T>::add(beta0, sc, qc);
       Ck<T>::add(beta1, sc, qc);
       Ck<T>::add(beta2, sc, qc);
@@ -291,14 +298,18 @@ __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const G
       Bk[k] = beta2 * ((T)k - c2);
       Bk2[k] = beta2d * ((T)k - c2);
     }
-    uint64_t S2 = 0, Q2 = 0, s_dc = 0, is_q = 0;
+    uint32_t S2 = 0, Q2 = 0;
+    uint64_t s_dc = 0, is_q = 0;
     uint32_t s_q = 0, nout = 0;
     uint32_t mis_p = 0, mis_r = 0;  // OR of bit differences between the duplicated results
     T *outl = (T *)w.vals + blk * (uint64_t)g.bpts;
     uint2 *cbase = (uint2 *)(w.codes + code_index(blk, 0, g.groups));  // next group is 64 vectors on
-    T xn[B2];  // the row after the current one, loaded one row ahead
+    T xn[B2], xn2[B2];  // the next two rows, loaded two rows ahead of their use
 #pragma unroll
-    for (int k = 0; k < B2; k++) xn[k] = ld(0, 0, k);
+    for (int k = 0; k < B2; k++) {
+      xn[k] = ld(0, 0, k);
+      xn2[k] = ld(0, 1, k);
+    }
 #pragma unroll 1
     for (int i = 0; i < B0; i++) {
       if (!FULL && (uint32_t)i >= n0) break;
@@ -314,13 +325,16 @@ __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const G
         if (ABFT) pin(Ajd);
         T xr[B2];
 #pragma unroll
-        for (int k = 0; k < B2; k++) xr[k] = xn[k];
-        if (j + 1 < B1) {
+        for (int k = 0; k < B2; k++) {
+          xr[k] = xn[k];
+          xn[k] = xn2[k];
+        }
+        if (j + 2 < B1) {
 #pragma unroll
-          for (int k = 0; k < B2; k++) xn[k] = ld(i, j + 1, k);
+          for (int k = 0; k < B2; k++) xn2[k] = ld(i, j + 2, k);
         } else if (i + 1 < B0) {
 #pragma unroll
-          for (int k = 0; k < B2; k++) xn[k] = ld(i + 1, 0, k);
+          for (int k = 0; k < B2; k++) xn2[k] = ld(i + 1, j + 2 - B1, k);
         }
         T rowold[B2];
         T cprev = 0, Up = 0, Up2 = 0;
@@ -361,8 +375,9 @@ __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const G
           const T diff = xv - pred;
           const T t = fabs(diff) * inv + (T)0.5;
           const bool inr = t < (T)32768;
-          const int m = (int)t;
-          const int sm = diff < (T)0 ? -m : m;
+          // m = trunc(t) with the sign of the difference; truncating the
+          // signed value gives the same integer (-0.0 gives 0 either way)
+          const int sm = (int)copysign(t, diff);
           const T r1 = pred + (T)sm * q;
           if (ABFT) mis_r |= Wd<T>::diff(r1, pred + (T)launder(sm) * q);  // dec_dup()
           const bool bok = Bound<T>::ok(xv, r1, eb);
@@ -424,8 +439,7 @@ __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const G
       w.sum_dc[blk] = s_dc;
       w.sum_q[blk] = s_q;
       w.isum_q[blk] = is_q;
-      const uint64_t is1 = nwords * S1 - Q1, is2 = nwords * S2 - Q2;
-      if (S1 != S2 || is1 != is2) why |= kWhyInput;
+      if (S1 != S2 || Q1 != Q2) why |= kWhyInput;
       if (mis_p) why |= kWhyPred;
       if (mis_r) why |= kWhyRecon;
       if (__builtin_expect(why != 0, 0)) {
