@@ -118,8 +118,9 @@ uint64_t sdcsz_compress_workspace_size(const sdcsz_params *p);
  * Returns SDCSZ_OK, SDCSZ_EINVAL, SDCSZ_ENOSPC, SDCSZ_ESDC (an uncorrectable
  * corruption, or a code without codeword when ABFT is off), SDCSZ_EHIP.
  * Synchronises `stream` twice: for the code histogram (the Huffman code is
- * built on the host) and at the end.  The calling thread keeps a pinned
- * host staging buffer of about 0.75 MiB from its first call on.
+ * built on the host; a third time when more than 32768 symbols are used) and
+ * at the end.  The calling thread keeps a pinned host staging buffer (at
+ * least 1 MiB, grown for large batches) from its first call on.
  */
 int sdcsz_compress(const void *d_in, const sdcsz_params *p, void *d_out, uint64_t out_cap,
                    uint64_t *h_out_size, sdcsz_report *h_rep, void *d_ws, uint64_t ws_size,
@@ -177,6 +178,62 @@ int sdcsz_verify(const void *d_stream, uint64_t stream_size, void *d_data, uint6
 int sdcsz_decompress_region(const void *d_stream, uint64_t stream_size, const uint64_t *h_lo,
                             const uint64_t *h_hi, void *d_out, uint64_t out_cap,
                             sdcsz_report *h_rep, void *d_ws, uint64_t ws_size, void *stream);
+
+/*
+ * Batches: many fields in one call (the independent-block design of Sec. 5.1
+ * makes fields, like blocks, independent units of work).  Each phase runs as
+ * one launch per kernel class over all fields of the batch (a table on the
+ * device names the field of every work-group), and the host synchronises
+ * for the whole batch: compression once for the code histograms (twice when
+ * they hold more than 32768 used symbols in all), once at the end;
+ * decompression once for the headers and once at the end.  Every field is
+ * processed exactly as a single call would process it: its stream, output
+ * and report are identical.  Huffman codes of a batch are built on up to 16
+ * host threads.
+ */
+typedef struct {
+  const void *d_in;      /* device: the field, C order (as for sdcsz_compress)      */
+  sdcsz_params params;   /* the field's parameters (faults: host array or NULL)    */
+  void *d_out;           /* device: the field's stream buffer, out_cap bytes       */
+  uint64_t out_cap;
+  uint64_t out_size;     /* out: stream size (required size on SDCSZ_ENOSPC)      */
+  int rc;                /* out: this field's return code                          */
+  sdcsz_report rep;      /* out                                                    */
+} sdcsz_comp_item;
+
+/* Device workspace for sdcsz_compress_batch on these items (fields with
+ * invalid parameters count for nothing). */
+uint64_t sdcsz_compress_batch_workspace_size(const sdcsz_comp_item *h_items, uint32_t n);
+
+/*
+ * Compress n fields.  h_items: host array; each item's rc, out_size and rep
+ * are written.  Returns SDCSZ_OK when every field succeeded, else the first
+ * failing item's code (SDCSZ_ENOSPC for every item when the workspace is too
+ * small, SDCSZ_EHIP on a runtime error).  Synchronises `stream`.
+ */
+int sdcsz_compress_batch(sdcsz_comp_item *h_items, uint32_t n, void *d_ws, uint64_t ws_size,
+                         void *stream);
+
+typedef struct {
+  const void *d_stream;  /* device: a stream, stream_size bytes                    */
+  uint64_t stream_size;
+  void *d_out;           /* device: n_values * sizeof(dtype) bytes, C order        */
+  uint64_t out_cap;
+  int rc;                /* out                                                    */
+  sdcsz_report rep;      /* out                                                    */
+} sdcsz_dec_item;
+
+/* Device workspace for sdcsz_decompress_batch: the parameters of each stream
+ * (from sdcsz_stream_info or the compression call), in item order. */
+uint64_t sdcsz_decompress_batch_workspace_size(const sdcsz_params *h_params, uint32_t n);
+
+/*
+ * Decompress n streams (Algorithm 2 for each; no fault plans).  Returns
+ * SDCSZ_OK when every stream decoded, else the first failing item's code.
+ * Synchronises `stream`.
+ */
+int sdcsz_decompress_batch(sdcsz_dec_item *h_items, uint32_t n, void *d_ws, uint64_t ws_size,
+                           void *stream);
 
 /* Human-readable name of a return code. */
 const char *sdcsz_strerror(int code);

@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
+#include <thread>
 #include <vector>
 
 #include "common.h"
@@ -190,12 +192,12 @@ template <typename T> RegTab<T> reg_table(const Geo &g) {
 }
 
 // ---------------------------------------------------------------------------
-// workspace layouts
+// per-field workspace layouts
 // ---------------------------------------------------------------------------
 struct CompLayout {
   uint64_t cnt, res, redo_n, hist, enc, zero_end;
   uint64_t eb, range, codes, vals, recon, meta, words, coef, sum_dc, sum_q, isum_q;
-  uint64_t off_pay, off_out, off_coef, scan, tot, plan, bits, redo, plan_blocks, hdr, cb, total;
+  uint64_t off_pay, off_out, off_coef, scan, tot, plan, bits, redo, plan_blocks, hdr, total;
 };
 
 CompLayout comp_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
@@ -237,50 +239,8 @@ CompLayout comp_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
   L.redo = take(8ull * kMaxRedo);
   L.plan_blocks = take(8ull * std::max<uint32_t>(nfaults, 1));
   L.hdr = take(sizeof(Header));
-  L.cb = take(8ull * 65536);
   L.total = at;
   return L;
-}
-
-// Specialised kernel for this block shape, if there is one.  Its lanes
-// address the input with 32-bit byte offsets from the wave's lowest block,
-// so it takes fields below 2 GiB.
-bool fast_shape(const Geo &g, uint32_t vb) {
-  if (!(g.ndim == 3 && g.b[0] == 6 && g.b[1] == 6 && g.b[2] == 6)) return false;
-  return g.n_values * vb < (1ull << 31);
-}
-
-// One launch of a specialised kernel: the first work-groups take the
-// sub-grid of full blocks, the others the shell of partial blocks along the
-// upper faces.  Returns the number of work-groups of 256 lanes.
-uint32_t fast_launch(const Geo &g, Launch *L) {
-  bool part[3];
-  std::memset(L, 0, sizeof(*L));
-  for (int a = 0; a < 3; a++) {
-    part[a] = g.rem[a] != g.b[a];
-    L->nf[a] = g.nb[a] - (part[a] ? 1 : 0);
-  }
-  L->full_count = (uint64_t)L->nf[0] * L->nf[1] * L->nf[2];
-  L->s2 = part[2] ? (uint64_t)g.nb[0] * g.nb[1] : 0;
-  L->s1 = part[1] ? (uint64_t)g.nb[0] * L->nf[2] : 0;
-  const uint64_t s0 = part[0] ? (uint64_t)L->nf[1] * L->nf[2] : 0;
-  L->shell_count = L->s2 + L->s1 + s0;
-  L->full_wgs = (uint32_t)((L->full_count + 255) / 256);
-  return L->full_wgs + (uint32_t)((L->shell_count + 255) / 256);
-}
-
-template <typename T, bool ABFT>
-void launch_fast(const T *in, const Geo &g, const RegTab<T> &rt, const PlanDev &pd, const CompWork &w,
-                 uint32_t predictor, const uint64_t *plan_blocks, uint32_t n_plan_blocks, hipStream_t st) {
-  if (n_plan_blocks)
-    hipLaunchKernelGGL(k_compress_list<T>, dim3(grid_for(n_plan_blocks, 64)), dim3(64), 0, st, in, g, rt, pd, w,
-                       ABFT ? 1u : 0u, predictor, plan_blocks, n_plan_blocks);
-  Launch L;
-  const uint32_t wgs = fast_launch(g, &L);
-  if (wgs)
-    launch(PH_PREDICT, true, true, k_compress_fast<T, 3, 6, 6, 6, ABFT>, dim3(wgs), dim3(256), st, in, g, rt, pd, w,
-           predictor, L);
-  hipLaunchKernelGGL(k_redo<T>, dim3(1), dim3(64), 0, st, in, g, rt, pd, w, ABFT ? 1u : 0u, predictor);
 }
 
 struct DecLayout {
@@ -321,33 +281,57 @@ DecLayout dec_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
   return L;
 }
 
-// ---------------------------------------------------------------------------
-// pinned host staging of the calling thread: the code histogram, the
-// codebook list and each call's results cross PCIe through it.  Allocated
-// on first use and kept until the process ends.
-// ---------------------------------------------------------------------------
-constexpr size_t kStageHist = 0;                             // 65536 u32 counts
-constexpr size_t kStageCb = kStageHist + 4 * 65536;         // 65536 pairs of u32
-constexpr size_t kStageRes = kStageCb + 8 * 65536;          // results of the call
-constexpr size_t kStageBytes = kStageRes + 8 * (C_N + R_N + 2);
+// Specialised kernel for this block shape, if there is one.  Its lanes
+// address the input with 32-bit byte offsets from the wave's lowest block,
+// so it takes fields below 2 GiB.
+bool fast_shape(const Geo &g, uint32_t vb) {
+  if (!(g.ndim == 3 && g.b[0] == 6 && g.b[1] == 6 && g.b[2] == 6)) return false;
+  return g.n_values * vb < (1ull << 31);
+}
 
+// One launch of a specialised kernel: the first work-groups take the
+// sub-grid of full blocks, the others the shell of partial blocks along the
+// upper faces.  Returns the number of work-groups of 256 lanes.
+uint32_t fast_launch(const Geo &g, Launch *L) {
+  bool part[3];
+  std::memset(L, 0, sizeof(*L));
+  for (int a = 0; a < 3; a++) {
+    part[a] = g.rem[a] != g.b[a];
+    L->nf[a] = g.nb[a] - (part[a] ? 1 : 0);
+  }
+  L->full_count = (uint64_t)L->nf[0] * L->nf[1] * L->nf[2];
+  L->s2 = part[2] ? (uint64_t)g.nb[0] * g.nb[1] : 0;
+  L->s1 = part[1] ? (uint64_t)g.nb[0] * L->nf[2] : 0;
+  const uint64_t s0 = part[0] ? (uint64_t)L->nf[1] * L->nf[2] : 0;
+  L->shell_count = L->s2 + L->s1 + s0;
+  L->full_wgs = (uint32_t)((L->full_count + 255) / 256);
+  return L->full_wgs + (uint32_t)((L->shell_count + 255) / 256);
+}
+
+uint32_t scan_chunks(uint64_t nb) { return (uint32_t)((nb + kScanChunk - 1) / kScanChunk); }
+
+// ---------------------------------------------------------------------------
+// pinned host staging of the calling thread (grown on demand, kept until the
+// process ends): job tables go to the device and histograms, headers and
+// results come back through it
+// ---------------------------------------------------------------------------
 struct Staging {
   uint8_t *p = nullptr;
-  uint8_t *get() {
-    if (!p && hipHostMalloc((void **)&p, kStageBytes, hipHostMallocDefault) != hipSuccess) p = nullptr;
+  size_t cap = 0;
+  // only called between calls or after a synchronisation (no copy in flight)
+  uint8_t *get(size_t n) {
+    if (n > cap) {
+      if (p) (void)hipHostFree(p);
+      p = nullptr;
+      cap = 0;
+      const size_t want = std::max<size_t>(n, 1u << 20);
+      if (hipHostMalloc((void **)&p, want, hipHostMallocDefault) != hipSuccess) return nullptr;
+      cap = want;
+    }
     return p;
   }
 };
 thread_local Staging t_stage;
-
-// Huffman construction buffers of the calling thread, reused across calls
-struct HuffmanScratch {
-  HuffmanBuilder b;
-  std::vector<uint32_t> sym, code;
-  std::vector<uint64_t> cnt;
-  std::vector<uint8_t> len;
-};
-thread_local HuffmanScratch t_huff;
 
 // ---------------------------------------------------------------------------
 // header
@@ -400,7 +384,7 @@ int unpack_header(const uint8_t *o, uint64_t stream_size, Header &h, Geo &g) {
   return SDCSZ_OK;
 }
 
-void fill_report(sdcsz_report *r, const unsigned long long *cnt, uint64_t nb) {
+void fill_report(sdcsz_report *r, const uint64_t *cnt, uint64_t nb) {
   std::memset(r, 0, sizeof(*r));
   r->n_blocks = nb;
   for (int t = 0; t < SDCSZ_N_TARGETS; t++) {
@@ -409,40 +393,6 @@ void fill_report(sdcsz_report *r, const unsigned long long *cnt, uint64_t nb) {
     r->corrected[t] = cnt[C_COR + t];
     r->uncorrectable[t] = cnt[C_UNC + t];
   }
-}
-
-// upload a sorted plan and its per-block bitmap (from pageable memory: the
-// vectors must live until the stream has passed the copies)
-int upload_plan(const std::vector<sdcsz_fault> &pl, uint64_t nb, uint8_t *ws, uint64_t off_plan,
-                uint64_t off_bits, std::vector<uint32_t> &bits_host, hipStream_t st, PlanDev *pd) {
-  pd->n = (uint32_t)pl.size();
-  pd->f = (const sdcsz_fault *)(ws + off_plan);
-  pd->bits = (const uint32_t *)(ws + off_bits);
-  if (pl.empty()) return SDCSZ_OK;
-  bits_host.assign(nb / 32 + 1, 0);
-  for (auto &f : pl) bits_host[f.block >> 5] |= 1u << (f.block & 31);
-  HIPCHK(hipMemcpyAsync(ws + off_plan, pl.data(), pl.size() * sizeof(sdcsz_fault), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(ws + off_bits, bits_host.data(), bits_host.size() * 4, hipMemcpyHostToDevice, st));
-  return SDCSZ_OK;
-}
-
-// exclusive scans of payload words, outliers and regression flags per block,
-// with the 64-bit totals in tot[0..2]
-int launch_scan(ScanSrc src, uint64_t n, uint64_t *part, uint64_t *off_pay, uint32_t *off_out,
-                uint32_t *off_coef, uint64_t *tot, int ph, hipStream_t st) {
-  if (n == 0) {
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, (unsigned long long *)off_pay, 1);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, off_out, 1);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, off_coef, 1);
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, (unsigned long long *)tot, 3);
-    return hipGetLastError() == hipSuccess ? SDCSZ_OK : SDCSZ_EHIP;
-  }
-  uint32_t chunks = (uint32_t)((n + kScanChunk - 1) / kScanChunk);
-  launch(ph, true, false, k_scan1, dim3(chunks), dim3(kScanThreads), st, src, n, part);
-  launch(ph, false, false, k_scan2, dim3(1), dim3(kScanThreads), st, part, chunks);
-  launch(ph, false, true, k_scan3, dim3(chunks), dim3(kScanThreads), st, src, n, (const uint64_t *)part, off_pay,
-         off_out, off_coef, tot);
-  return hipGetLastError() == hipSuccess ? SDCSZ_OK : SDCSZ_EHIP;
 }
 
 // distinct blocks of a sorted plan
@@ -454,286 +404,805 @@ std::vector<uint64_t> plan_block_list(const std::vector<sdcsz_fault> &plan) {
 }
 
 // ---------------------------------------------------------------------------
-// compression: two host synchronisations, one for the code histogram (the
-// Huffman code is built on the host) and one for the results at the end
+// launch tables: the jobs of one launch and the work-groups each owns
 // ---------------------------------------------------------------------------
-template <typename T>
-int compress_t(const void *d_in, const sdcsz_params *p, const Geo &g, uint8_t *d_out, uint64_t out_cap,
-               uint64_t *h_out_size, sdcsz_report *h_rep, uint8_t *ws, uint64_t ws_size, hipStream_t st) {
-  std::vector<sdcsz_fault> plan;
-  int rc = check_plan(g, p->dtype, p->faults, p->n_faults, false, plan);
-  if (rc) return rc;
-  const CompLayout L = comp_layout(g, p->dtype, p->n_faults);
-  if (!ws || ws_size < L.total) return SDCSZ_ENOSPC;
-  uint8_t *hs = t_stage.get();
-  if (!hs) return SDCSZ_EHIP;
-  CompWork w;
-  w.codes = (uint16_t *)(ws + L.codes);
-  w.vals = ws + L.vals;
-  w.recon = ws + L.recon;
-  w.meta = (uint32_t *)(ws + L.meta);
-  w.words = (uint32_t *)(ws + L.words);
-  w.coef = ws + L.coef;
-  w.sum_dc = (uint64_t *)(ws + L.sum_dc);
-  w.sum_q = (uint64_t *)(ws + L.sum_q);
-  w.isum_q = (uint64_t *)(ws + L.isum_q);
-  w.hist = (uint32_t *)(ws + L.hist);
-  w.enc = (uint32_t *)(ws + L.enc);
-  w.cnt = (unsigned long long *)(ws + L.cnt);
-  w.off_pay = (uint64_t *)(ws + L.off_pay);
-  w.off_out = (uint32_t *)(ws + L.off_out);
-  w.off_coef = (uint32_t *)(ws + L.off_coef);
-  w.scan_part = (uint64_t *)(ws + L.scan);
-  w.range_part = ws + L.range;
-  w.eb = (EbDev *)(ws + L.eb);
-  w.redo_n = (uint32_t *)(ws + L.redo_n);
-  w.redo = (uint64_t *)(ws + L.redo);
-  w.hdr = (Header *)(ws + L.hdr);
-  w.res = (uint64_t *)(ws + L.res);
-  w.cb = (uint32_t *)(ws + L.cb);
-  w.tot = (uint64_t *)(ws + L.tot);
-
-  // host vectors read by asynchronous copies live until the histogram sync
-  std::vector<uint32_t> bits_host;
-  PlanDev pd;
-  rc = upload_plan(plan, g.n_blocks, ws, L.plan, L.bits, bits_host, st, &pd);
-  if (rc) return rc;
-  const std::vector<uint64_t> pb = plan_block_list(plan);
-
-  hipLaunchKernelGGL(k_zero_u32, dim3(256), dim3(256), 0, st, (uint32_t *)ws, L.zero_end / 4);
-  uint32_t nparts = 0;
-  if (p->eb_mode == SDCSZ_REL && g.n_values) {
-    nparts = (uint32_t)std::min<uint64_t>(kRangeBlocks, grid_for(g.n_values, kRangeThreads * 8));
-    launch(PH_RANGE, true, true, k_range<T>, dim3(nparts), dim3(kRangeThreads), st, (const T *)d_in, g.n_values,
-           (double *)w.range_part);
+struct Tab {
+  std::vector<uint32_t> wg{0}, id;
+  void add(uint32_t job, uint64_t wgs) {
+    if (!wgs) return;
+    id.push_back(job);
+    wg.push_back(wg.back() + (uint32_t)wgs);
   }
-  hipLaunchKernelGGL(k_consts, dim3(1), dim3(256), 0, st, (const double *)w.range_part, nparts, p->eb_mode,
-                     p->eb, w.eb);
-  HIPCHK(hipGetLastError());
+  uint32_t total() const { return wg.back(); }
+  uint32_t n() const { return (uint32_t)id.size(); }
+};
 
-  const bool fast = g.n_blocks && fast_shape(g, sizeof(T));
-  if (g.n_blocks) {
-    const RegTab<T> rt = reg_table<T>(g);
-    if (fast) {
-      // the distinct blocks the plan names run through the generic routine
-      const uint64_t *d_pb = (const uint64_t *)(ws + L.plan_blocks);
-      if (!pb.empty())
-        HIPCHK(hipMemcpyAsync(ws + L.plan_blocks, pb.data(), 8 * pb.size(), hipMemcpyHostToDevice, st));
-      if (p->abft) launch_fast<T, true>((const T *)d_in, g, rt, pd, w, p->predictor, d_pb, (uint32_t)pb.size(), st);
-      else launch_fast<T, false>((const T *)d_in, g, rt, pd, w, p->predictor, d_pb, (uint32_t)pb.size(), st);
-    } else {
-      launch(PH_PREDICT, true, true, k_compress_generic<T>, dim3(grid_for(g.n_blocks, 64)), dim3(64), st,
-             (const T *)d_in, g, rt, pd, w, p->abft, p->predictor);
-    }
-    HIPCHK(hipGetLastError());
-    bool any_code = false;
-    for (auto &f : plan) any_code |= f.target == SDCSZ_T_CODE;
-    if (any_code) {
-      launch(PH_CODEFAULT, true, true, k_code_faults, dim3(1), dim3(64), st, pd, g, w.codes, w.cnt);
+// The jobs and the launch tables of one stage, laid out in pinned memory and
+// copied to the batch area of the workspace with one transfer.
+struct Upload {
+  std::vector<Tab *> tabs;
+  std::vector<JobTab> dev;
+  size_t bytes(size_t njobs) const {
+    size_t b = a256(sizeof(Job) * njobs);
+    for (auto *t : tabs) b += 4 * (t->wg.size() + t->id.size());
+    return a256(b);
+  }
+  // writes jobs + tables at host[0..) for device address dbase; fills dev[]
+  void place(const std::vector<Job> &jobs, uint8_t *host, uint8_t *dbase) {
+    std::memcpy(host, jobs.data(), sizeof(Job) * jobs.size());
+    size_t at = a256(sizeof(Job) * jobs.size());
+    dev.clear();
+    for (auto *t : tabs) {
+      JobTab jt;
+      jt.jobs = (const Job *)dbase;
+      jt.n = t->n();
+      std::memcpy(host + at, t->wg.data(), 4 * t->wg.size());
+      jt.wg = (const uint32_t *)(dbase + at);
+      at += 4 * t->wg.size();
+      std::memcpy(host + at, t->id.data(), 4 * t->id.size());
+      jt.id = (const uint32_t *)(dbase + at);
+      at += 4 * t->id.size();
+      dev.push_back(jt);
     }
   }
+};
 
-  // Huffman code over the whole field's codes (host)
-  const uint32_t *hist = (const uint32_t *)(hs + kStageHist);
-  HIPCHK(hipMemcpyAsync(hs + kStageHist, w.hist, 4 * 65536, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  std::vector<uint32_t> &used = t_huff.sym;
-  std::vector<uint64_t> &counts = t_huff.cnt;
-  used.clear();
-  counts.clear();
-  const uint64_t *h64 = (const uint64_t *)hist;
-  for (uint32_t q = 0; q < 32768; q++) {
-    const uint64_t v = h64[q];
-    if (!v) continue;
-    if ((uint32_t)v) {
-      used.push_back(2 * q);
-      counts.push_back((uint32_t)v);
-    }
-    if (v >> 32) {
-      used.push_back(2 * q + 1);
-      counts.push_back(v >> 32);
-    }
+// A phase's launches (one per kernel class), the first recording the
+// phase's start event and the last its stop event.
+struct PhaseLaunch {
+  int ph;
+  std::vector<std::function<void(bool, bool)>> fs;
+  void run() {
+    for (size_t i = 0; i < fs.size(); i++) fs[i](i == 0, i + 1 == fs.size());
   }
-  std::vector<uint8_t> &len = t_huff.len;
-  std::vector<uint32_t> &codes = t_huff.code;
-  t_huff.b.lengths(counts, kMaxLen, len);
-  canonical_codes(len, kMaxLen, codes);
-  const uint32_t n_sym = (uint32_t)used.size();
-  uint32_t *cb = (uint32_t *)(hs + kStageCb);
-  for (uint32_t t = 0; t < n_sym; t++) {
-    cb[2 * t] = (used[t] << 8) | len[t];
-    cb[2 * t + 1] = codes[t];
-  }
-  if (n_sym) {
-    HIPCHK(hipMemcpyAsync(w.cb, cb, 8ull * n_sym, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_put_codes, dim3(grid_for(n_sym, 256)), dim3(256), 0, st, w.cb, n_sym, w.enc);
-  }
+};
 
-  if (g.n_blocks) {
-    if (fast)
-      launch(PH_CHECK, true, true, k_check_fast<6, 6, 6>, dim3(grid_for(g.n_blocks, 256)), dim3(256), st, g, w,
-             p->abft);
-    else
-      launch(PH_CHECK, true, true, k_codes_check, dim3(grid_for(g.n_blocks, 256)), dim3(256), st, g, w, p->abft);
-  }
-  ScanSrc src{w.words, w.meta, 1};
-  rc = launch_scan(src, g.n_blocks, w.scan_part, w.off_pay, w.off_out, w.off_coef, w.tot, PH_SCAN_C, st);
-  if (rc) return rc;
+// ---------------------------------------------------------------------------
+// Huffman codebooks of a batch, built on host threads
+// ---------------------------------------------------------------------------
+struct CodebookJob {
+  const uint64_t *pairs;  // (symbol << 32 | count), ascending symbols
+  uint32_t n;
+  uint32_t *out;          // n pairs (symbol << 8 | length, codeword)
+};
 
-  // header, codebook and pads on the device; the encoder follows its decision
-  Header h;
-  std::memset(&h, 0, sizeof(h));
-  h.dtype = p->dtype;
-  h.ndim = p->ndim;
-  for (int a = 0; a < 3; a++) {
-    h.d[a] = g.d[a];
-    h.b[a] = g.b[a];
+void build_codebook(const CodebookJob &c, HuffmanBuilder &b, std::vector<uint64_t> &cnt, std::vector<uint8_t> &len,
+                    std::vector<uint32_t> &code) {
+  cnt.resize(c.n);
+  for (uint32_t i = 0; i < c.n; i++) cnt[i] = c.pairs[i] & 0xFFFFFFFFull;
+  b.lengths(cnt, kMaxLen, len);
+  canonical_codes(len, kMaxLen, code);
+  for (uint32_t i = 0; i < c.n; i++) {
+    c.out[2 * i] = ((uint32_t)(c.pairs[i] >> 32) << 8) | len[i];
+    c.out[2 * i + 1] = code[i];
   }
-  h.eb_mode = p->eb_mode;
-  h.eb = p->eb;
-  h.abft = p->abft;
-  h.n_sym = n_sym;
-  h.n_blocks = g.n_blocks;
-  h.predictor = p->predictor;
-  hipLaunchKernelGGL(k_header, dim3(grid_for(n_sym, 256)), dim3(256), 0, st, h, w, d_out, d_out ? out_cap : 0);
-  if (fast)
-    launch(PH_ENCODE, true, true, k_encode_fast<T, 6, 6, 6>, dim3(grid_for(g.n_blocks, 256)), dim3(256), st, g, w,
-           d_out);
-  else if (g.n_blocks)
-    launch(PH_ENCODE, true, true, k_encode<T>, dim3(grid_for(g.n_blocks, 256)), dim3(256), st, g, w, d_out);
-  HIPCHK(hipGetLastError());
+}
 
-  // counters and results: one copy, one synchronisation
-  unsigned long long *cnt = (unsigned long long *)(hs + kStageRes);
-  const uint64_t *res = (const uint64_t *)(hs + kStageRes + 8 * C_N);
-  HIPCHK(hipMemcpyAsync(hs + kStageRes, ws + L.cnt, 8 * (C_N + R_N), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  g_timer.resolve();
-
-  sdcsz_report rep;
-  fill_report(&rep, cnt, g.n_blocks);
-  double eb_abs;
-  std::memcpy(&eb_abs, &res[R_EB], 8);
-  rep.eb_abs = eb_abs;
-  const bool unc = cnt[C_UNC + SDCSZ_T_INPUT] || cnt[C_UNC + SDCSZ_T_COEF] || cnt[C_UNC + SDCSZ_T_CODE] ||
-                   cnt[C_MISSING];
-  if (unc) {
-    *h_out_size = 0;
-    if (h_rep) *h_rep = rep;
-    return SDCSZ_ESDC;
+void build_codebooks(const std::vector<CodebookJob> &cj) {
+  uint64_t work = 0;
+  for (auto &c : cj) work += c.n;
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const unsigned nt = (unsigned)std::min<uint64_t>(hw, std::max<uint64_t>(1, std::min<uint64_t>(cj.size(), work / 4096)));
+  auto run = [&](unsigned t) {
+    HuffmanBuilder b;
+    std::vector<uint64_t> cnt;
+    std::vector<uint8_t> len;
+    std::vector<uint32_t> code;
+    for (size_t i = t; i < cj.size(); i += nt) build_codebook(cj[i], b, cnt, len, code);
+  };
+  if (nt <= 1) {
+    run(0);
+    return;
   }
-  rep.n_outliers = res[R_OUTLIERS];
-  rep.n_regression = res[R_REGRESSION];
-  rep.payload_words = res[R_WORDS];
-  rep.stream_size = res[R_SIZE];
-  *h_out_size = res[R_SIZE];
-  if (h_rep) *h_rep = rep;
-  return res[R_WRITTEN] ? SDCSZ_OK : SDCSZ_ENOSPC;
+  std::vector<std::thread> th;
+  for (unsigned t = 1; t < nt; t++) th.emplace_back(run, t);
+  run(0);
+  for (auto &x : th) x.join();
 }
 
 // ---------------------------------------------------------------------------
-// decompression / verification / region: one synchronisation for the header
-// (the host sizes the launches from it) and one for the results
+// compression of a batch of fields
 // ---------------------------------------------------------------------------
-struct Opened {
+struct CompItem {  // one field of a compression call
+  const void *d_in;
+  const sdcsz_params *p;
+  uint8_t *d_out;
+  uint64_t out_cap;
+  uint64_t out_size;
+  int rc;
+  sdcsz_report rep;
+};
+
+constexpr uint64_t kPairPrefix = 32768;  // histogram entries returned with the first synchronisation
+
+struct CompPlan {  // host state of one field
+  Geo g;
+  CompLayout L;
+  uint8_t *ws;
+  bool fast;
+  std::vector<sdcsz_fault> plan;
+  std::vector<uint32_t> bits;
+  std::vector<uint64_t> pb;
+  bool any_code;
+  uint64_t pair_off;  // first entry of the field's histogram / codebook list
+};
+
+struct BatchArea {  // device batch area and its size
+  uint64_t jobs, cb, counts, pairs, chunks, res, total;
+};
+
+constexpr uint32_t kHistChunks = 64;  // histogram chunks per field (k_hist_*)
+
+// jobs + up to 32 launch tables of (2 n + 1) entries
+uint64_t jobs_region(uint64_t njobs) { return a256(sizeof(Job) * njobs) + 32 * a256(4 * (2 * njobs + 1)); }
+
+BatchArea comp_batch_area(uint64_t njobs, uint64_t cap_pairs) {
+  BatchArea B;
+  uint64_t at = 0;
+  auto take = [&](uint64_t bytes) {
+    uint64_t o = at;
+    at = a256(at + bytes);
+    return o;
+  };
+  B.jobs = take(jobs_region(njobs));
+  B.cb = B.jobs + jobs_region(njobs);  // right after the tables: one upload carries both
+  at = a256(B.cb + 8 * cap_pairs);
+  B.counts = take(4 * njobs + 8);      // the pairs follow right after, for one copy back
+  B.pairs = B.counts + ((4 * njobs + 7) & ~7ull);
+  at = a256(B.pairs + 8 * cap_pairs);
+  B.chunks = take(4ull * kHistChunks * njobs);
+  B.res = take(8ull * (C_N + R_N) * njobs);
+  B.total = at;
+  return B;
+}
+
+uint64_t pair_cap(const Geo &g) { return std::min<uint64_t>(65536, g.n_values + 1); }
+
+// workspace of a batch: the batch area, then each valid field's area
+uint64_t comp_batch_ws(const CompItem *it, uint32_t n) {
+  uint64_t per = 0, cap = 0, nj = 0;
+  for (uint32_t i = 0; i < n; i++) {
+    Geo g;
+    if (check_params(it[i].p, &g)) continue;
+    per += comp_layout(g, it[i].p->dtype, it[i].p->n_faults).total;
+    cap += pair_cap(g);
+    nj++;
+  }
+  return comp_batch_area(nj, cap).total + per;
+}
+
+template <typename T> void fill_rt(Job &J) {
+  if (sizeof(T) == 4) J.rtf = reg_table<float>(J.g);
+  else J.rtd = reg_table<double>(J.g);
+}
+
+int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStream_t st) {
+  // ---- validation and layouts
+  std::vector<CompPlan> fp;
+  std::vector<uint32_t> item_of;  // job -> item
+  uint64_t cap = 0, per = 0;
+  for (uint32_t i = 0; i < n; i++) {
+    CompItem &c = it[i];
+    c.out_size = 0;
+    std::memset(&c.rep, 0, sizeof(c.rep));
+    CompPlan f;
+    c.rc = check_params(c.p, &f.g);
+    if (!c.rc && f.g.n_values && !c.d_in) c.rc = SDCSZ_EINVAL;
+    if (!c.rc) c.rc = check_plan(f.g, c.p->dtype, c.p->faults, c.p->n_faults, false, f.plan);
+    if (c.rc) continue;
+    f.L = comp_layout(f.g, c.p->dtype, c.p->n_faults);
+    f.fast = f.g.n_blocks && fast_shape(f.g, vbytes(c.p->dtype));
+    f.pb = plan_block_list(f.plan);
+    f.any_code = false;
+    for (auto &e : f.plan) f.any_code |= e.target == SDCSZ_T_CODE;
+    f.pair_off = cap;
+    cap += pair_cap(f.g);
+    per += f.L.total;
+    fp.push_back(std::move(f));
+    item_of.push_back(i);
+  }
+  const uint32_t nj = (uint32_t)fp.size();
+  if (nj == 0) return SDCSZ_OK;
+  const BatchArea B = comp_batch_area(nj, cap);
+  if (!ws || ws_size < B.total + per) {
+    for (uint32_t j = 0; j < nj; j++) it[item_of[j]].rc = SDCSZ_ENOSPC;
+    return SDCSZ_ENOSPC;
+  }
+  // ---- jobs
+  std::vector<Job> jobs(nj);
+  uint64_t at = B.total;
+  for (uint32_t j = 0; j < nj; j++) {
+    CompPlan &f = fp[j];
+    const CompItem &c = it[item_of[j]];
+    f.ws = ws + at;
+    at += f.L.total;
+    Job &J = jobs[j];
+    std::memset(&J, 0, sizeof(J));
+    uint8_t *w = f.ws;
+    J.g = f.g;
+    CompWork &cw = J.cw;
+    cw.codes = (uint16_t *)(w + f.L.codes);
+    cw.vals = w + f.L.vals;
+    cw.recon = w + f.L.recon;
+    cw.meta = (uint32_t *)(w + f.L.meta);
+    cw.words = (uint32_t *)(w + f.L.words);
+    cw.coef = w + f.L.coef;
+    cw.sum_dc = (uint64_t *)(w + f.L.sum_dc);
+    cw.sum_q = (uint64_t *)(w + f.L.sum_q);
+    cw.isum_q = (uint64_t *)(w + f.L.isum_q);
+    cw.hist = (uint32_t *)(w + f.L.hist);
+    cw.enc = (uint32_t *)(w + f.L.enc);
+    cw.cnt = (unsigned long long *)(w + f.L.cnt);
+    cw.off_pay = (uint64_t *)(w + f.L.off_pay);
+    cw.off_out = (uint32_t *)(w + f.L.off_out);
+    cw.off_coef = (uint32_t *)(w + f.L.off_coef);
+    cw.scan_part = (uint64_t *)(w + f.L.scan);
+    cw.range_part = w + f.L.range;
+    cw.eb = (EbDev *)(w + f.L.eb);
+    cw.redo_n = (uint32_t *)(w + f.L.redo_n);
+    cw.redo = (uint64_t *)(w + f.L.redo);
+    cw.hdr = (Header *)(w + f.L.hdr);
+    cw.res = (uint64_t *)(w + f.L.res);
+    cw.cb = (uint32_t *)(ws + B.cb) + 2 * f.pair_off;
+    cw.tot = (uint64_t *)(w + f.L.tot);
+    J.plan.n = (uint32_t)f.plan.size();
+    J.plan.f = (const sdcsz_fault *)(w + f.L.plan);
+    J.plan.bits = (const uint32_t *)(w + f.L.bits);
+    if (f.fast) fast_launch(f.g, &J.L);
+    Header &h = J.h;
+    h.dtype = c.p->dtype;
+    h.ndim = c.p->ndim;
+    for (int a = 0; a < 3; a++) {
+      h.d[a] = f.g.d[a];
+      h.b[a] = f.g.b[a];
+    }
+    h.eb_mode = c.p->eb_mode;
+    h.eb = c.p->eb;
+    h.abft = c.p->abft;
+    h.n_blocks = f.g.n_blocks;
+    h.predictor = c.p->predictor;
+    J.ss = ScanSrc{cw.words, cw.meta, 1};
+    J.sc_part = cw.scan_part;
+    J.sc_off_pay = cw.off_pay;
+    J.sc_off_out = cw.off_out;
+    J.sc_off_coef = cw.off_coef;
+    J.sc_tot = cw.tot;
+    J.src = (const uint8_t *)c.d_in;
+    J.dst = c.d_out;
+    J.dst_cap = c.d_out ? c.out_cap : 0;
+    J.zero = (uint32_t *)(w + f.L.cnt);
+    J.zero_words = (f.L.zero_end - f.L.cnt) / 4;
+    J.stat = (const uint64_t *)(w + f.L.cnt);
+    J.stat_words = C_N + R_N;
+    J.eb = c.p->eb;
+    J.dtype = c.p->dtype;
+    J.abft = c.p->abft;
+    J.predictor = c.p->predictor;
+    J.eb_mode = c.p->eb_mode;
+    J.nparts = (c.p->eb_mode == SDCSZ_REL && f.g.n_values)
+                   ? (uint32_t)std::min<uint64_t>(kRangeBlocks, grid_for(f.g.n_values, kRangeThreads * 8))
+                   : 1u;
+    if (J.dtype == SDCSZ_F32) fill_rt<float>(J);
+    else fill_rt<double>(J);
+    // fault plans (pageable sources live in fp until the first synchronisation)
+    if (!f.plan.empty()) {
+      f.bits.assign(f.g.n_blocks / 32 + 1, 0);
+      for (auto &e : f.plan) f.bits[e.block >> 5] |= 1u << (e.block & 31);
+      HIPCHK(hipMemcpyAsync(w + f.L.plan, f.plan.data(), f.plan.size() * sizeof(sdcsz_fault), hipMemcpyHostToDevice,
+                            st));
+      HIPCHK(hipMemcpyAsync(w + f.L.bits, f.bits.data(), f.bits.size() * 4, hipMemcpyHostToDevice, st));
+      if (f.fast)
+        HIPCHK(hipMemcpyAsync(w + f.L.plan_blocks, f.pb.data(), 8 * f.pb.size(), hipMemcpyHostToDevice, st));
+    }
+  }
+  // ---- stage A tables: zero, range + constants, prediction/quantization,
+  // re-runs, histogram compaction
+  Tab t_zero, t_range[2], t_fast[2][2], t_gen[2], t_redo[2], t_hist, t_hchunk;  // t_hist: one work-group per job
+  for (uint32_t j = 0; j < nj; j++) {
+    const Job &J = jobs[j];
+    const CompPlan &f = fp[j];
+    t_zero.add(j, std::min<uint64_t>(64, grid_for(J.zero_words, 256)));
+    if (J.eb_mode == SDCSZ_REL && f.g.n_values) t_range[J.dtype].add(j, J.nparts);
+    if (f.fast) {
+      Launch L;
+      t_fast[J.dtype][J.abft].add(j, fast_launch(f.g, &L));
+      t_redo[J.dtype].add(j, 1);
+    } else if (f.g.n_blocks) {
+      t_gen[J.dtype].add(j, grid_for(f.g.n_blocks, 64));
+    }
+    t_hist.add(j, 1);
+    t_hchunk.add(j, kHistChunks);
+  }
+  Upload up;
+  up.tabs = {&t_zero, &t_range[0], &t_range[1], &t_fast[0][0], &t_fast[0][1], &t_fast[1][0], &t_fast[1][1],
+             &t_gen[0], &t_gen[1], &t_redo[0], &t_redo[1], &t_hist, &t_hchunk};
+  uint8_t *hs = t_stage.get(std::max<size_t>(up.bytes(nj), 4 * nj + 8 + 8 * kPairPrefix + 64));
+  if (!hs) return SDCSZ_EHIP;
+  up.place(jobs, hs, ws + B.jobs);
+  HIPCHK(hipMemcpyAsync(ws + B.jobs, hs, up.bytes(nj), hipMemcpyHostToDevice, st));
+  const JobTab &d_zero = up.dev[0];
+  const JobTab *d_range = &up.dev[1];
+  const JobTab d_fast[2][2] = {{up.dev[3], up.dev[4]}, {up.dev[5], up.dev[6]}};
+  const JobTab *d_gen = &up.dev[7];
+  const JobTab *d_redo = &up.dev[9];
+  const JobTab &d_hist = up.dev[11];
+  const JobTab &d_hchunk = up.dev[12];
+  auto grid = [](const Tab &t) { return dim3(t.total()); };
+  launch(PH_NONE, false, false, k_zero_jobs, grid(t_zero), dim3(256), st, d_zero);
+  {
+    PhaseLaunch pl{PH_RANGE, {}};
+    if (t_range[0].total())
+      pl.fs.push_back([&](bool a, bool b) { launch(PH_RANGE, a, b, k_range<float>, grid(t_range[0]), dim3(kRangeThreads), st, d_range[0]); });
+    if (t_range[1].total())
+      pl.fs.push_back([&](bool a, bool b) { launch(PH_RANGE, a, b, k_range<double>, grid(t_range[1]), dim3(kRangeThreads), st, d_range[1]); });
+    pl.run();
+  }
+  launch(PH_NONE, false, false, k_consts, grid(t_hist), dim3(kRangeThreads), st, d_hist);
+  // blocks a fault plan names run first through the paper-order routine
+  for (uint32_t j = 0; j < nj; j++) {
+    const CompPlan &f = fp[j];
+    const Job &J = jobs[j];
+    if (!f.fast || f.pb.empty()) continue;
+    const uint64_t *d_pb = (const uint64_t *)(f.ws + f.L.plan_blocks);
+    if (J.dtype == SDCSZ_F32)
+      launch(PH_NONE, false, false, k_compress_list<float>, dim3(grid_for(f.pb.size(), 64)), dim3(64), st,
+             (const float *)J.src, J.g, J.rtf, J.plan, J.cw, J.abft, J.predictor, d_pb, (uint32_t)f.pb.size());
+    else
+      launch(PH_NONE, false, false, k_compress_list<double>, dim3(grid_for(f.pb.size(), 64)), dim3(64), st,
+             (const double *)J.src, J.g, J.rtd, J.plan, J.cw, J.abft, J.predictor, d_pb, (uint32_t)f.pb.size());
+  }
+  {
+    PhaseLaunch pl{PH_PREDICT, {}};
+    if (t_fast[0][1].total())
+      pl.fs.push_back([&](bool a, bool b) { launch(PH_PREDICT, a, b, k_compress_fast<float, 3, 6, 6, 6, true>, grid(t_fast[0][1]), dim3(256), st, d_fast[0][1]); });
+    if (t_fast[0][0].total())
+      pl.fs.push_back([&](bool a, bool b) { launch(PH_PREDICT, a, b, k_compress_fast<float, 3, 6, 6, 6, false>, grid(t_fast[0][0]), dim3(256), st, d_fast[0][0]); });
+    if (t_fast[1][1].total())
+      pl.fs.push_back([&](bool a, bool b) { launch(PH_PREDICT, a, b, k_compress_fast<double, 3, 6, 6, 6, true>, grid(t_fast[1][1]), dim3(256), st, d_fast[1][1]); });
+    if (t_fast[1][0].total())
+      pl.fs.push_back([&](bool a, bool b) { launch(PH_PREDICT, a, b, k_compress_fast<double, 3, 6, 6, 6, false>, grid(t_fast[1][0]), dim3(256), st, d_fast[1][0]); });
+    if (t_gen[0].total())
+      pl.fs.push_back([&](bool a, bool b) { launch(PH_PREDICT, a, b, k_compress_generic<float>, grid(t_gen[0]), dim3(64), st, d_gen[0]); });
+    if (t_gen[1].total())
+      pl.fs.push_back([&](bool a, bool b) { launch(PH_PREDICT, a, b, k_compress_generic<double>, grid(t_gen[1]), dim3(64), st, d_gen[1]); });
+    pl.run();
+  }
+  if (t_redo[0].total()) launch(PH_NONE, false, false, k_redo<float>, grid(t_redo[0]), dim3(64), st, d_redo[0]);
+  if (t_redo[1].total()) launch(PH_NONE, false, false, k_redo<double>, grid(t_redo[1]), dim3(64), st, d_redo[1]);
+  for (uint32_t j = 0; j < nj; j++)
+    if (fp[j].any_code)
+      launch(PH_CODEFAULT, true, true, k_code_faults, dim3(1), dim3(64), st, jobs[j].plan, jobs[j].g,
+             jobs[j].cw.codes, jobs[j].cw.cnt);
+  uint32_t *d_counts = (uint32_t *)(ws + B.counts);
+  uint64_t *d_pairs = (uint64_t *)(ws + B.pairs);
+  uint32_t *d_chunks = (uint32_t *)(ws + B.chunks);
+  launch(PH_NONE, false, false, k_hist_count, grid(t_hchunk), dim3(256), st, d_hchunk, d_chunks);
+  launch(PH_NONE, false, false, k_hist_scan, dim3(1), dim3(256), st, nj, d_chunks, d_counts);
+  launch(PH_NONE, false, false, k_hist_pack, grid(t_hchunk), dim3(256), st, d_hchunk, (const uint32_t *)d_chunks,
+         d_pairs);
+  HIPCHK(hipGetLastError());
+
+  // ---- histograms back (the first kPairPrefix entries with the counts)
+  const uint64_t head = B.pairs - B.counts;
+  const uint64_t pre = std::min<uint64_t>(kPairPrefix, cap);
+  HIPCHK(hipMemcpyAsync(hs, ws + B.counts, head + 8 * pre, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<uint32_t> cnt_sym((const uint32_t *)hs, (const uint32_t *)hs + nj);
+  uint64_t total_pairs = 0;
+  for (uint32_t j = 0; j < nj; j++) total_pairs += cnt_sym[j];
+  // pinned room, in stage B: [jobs and tables | codebook lists] (one upload,
+  // mirroring the device batch area), then the histogram pairs, then results
+  const uint64_t JR = jobs_region(nj);
+  const uint64_t at_pairs = a256(JR + 8 * total_pairs);
+  const uint64_t at_res = a256(at_pairs + 8 * total_pairs);
+  const size_t need = at_res + 8ull * (C_N + R_N) * nj + 256;
+  std::vector<uint64_t> first_pairs;
+  if (total_pairs <= pre) {
+    first_pairs.assign((const uint64_t *)(hs + head), (const uint64_t *)(hs + head) + total_pairs);
+    hs = t_stage.get(need);
+    if (!hs) return SDCSZ_EHIP;
+    std::memcpy(hs + at_pairs, first_pairs.data(), 8 * total_pairs);
+  } else {
+    hs = t_stage.get(need);
+    if (!hs) return SDCSZ_EHIP;
+    HIPCHK(hipMemcpyAsync(hs + at_pairs, ws + B.pairs, 8 * total_pairs, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  // ---- codebooks (host), then stage B: codewords, code check, scans,
+  // header, encoding, results
+  const uint64_t *pairs = (const uint64_t *)(hs + at_pairs);
+  uint32_t *cbh = (uint32_t *)(hs + JR);
+  std::vector<CodebookJob> cj(nj);
+  uint64_t off = 0;
+  for (uint32_t j = 0; j < nj; j++) {
+    cj[j] = CodebookJob{pairs + off, cnt_sym[j], cbh + 2 * off};
+    jobs[j].n_sym = cnt_sym[j];
+    jobs[j].h.n_sym = cnt_sym[j];
+    jobs[j].cw.cb = (uint32_t *)(ws + B.cb) + 2 * off;
+    off += cnt_sym[j];
+  }
+  build_codebooks(cj);
+  Tab t_put, t_chk_fast, t_chk_gen, t_s1, t_s2, t_hdr, t_enc_fast[2], t_enc_gen[2], t_res;
+  for (uint32_t j = 0; j < nj; j++) {
+    const Job &J = jobs[j];
+    const CompPlan &f = fp[j];
+    if (J.n_sym) t_put.add(j, grid_for(J.n_sym, 256));
+    if (f.fast) {
+      t_chk_fast.add(j, grid_for(f.g.n_blocks, 256));
+      t_enc_fast[J.dtype].add(j, grid_for(f.g.n_blocks, 256));
+    } else if (f.g.n_blocks) {
+      t_chk_gen.add(j, grid_for(f.g.n_blocks, 256));
+      t_enc_gen[J.dtype].add(j, grid_for(f.g.n_blocks, 256));
+    }
+    t_s1.add(j, scan_chunks(f.g.n_blocks));
+    t_s2.add(j, 1);
+    t_hdr.add(j, grid_for(J.n_sym, 256));
+    t_res.add(j, 1);
+  }
+  Upload ub;
+  ub.tabs = {&t_put, &t_chk_fast, &t_chk_gen, &t_s1, &t_s2, &t_hdr, &t_enc_fast[0], &t_enc_fast[1],
+             &t_enc_gen[0], &t_enc_gen[1], &t_res};
+  ub.place(jobs, hs, ws + B.jobs);
+  HIPCHK(hipMemcpyAsync(ws + B.jobs, hs, JR + 8 * total_pairs, hipMemcpyHostToDevice, st));
+  const std::vector<JobTab> &D = ub.dev;
+  if (t_put.total()) launch(PH_NONE, false, false, k_put_codes, grid(t_put), dim3(256), st, D[0]);
+  {
+    PhaseLaunch pl{PH_CHECK, {}};
+    if (t_chk_fast.total())
+      pl.fs.push_back([&](bool a, bool b) { launch(PH_CHECK, a, b, k_check_fast<6, 6, 6>, grid(t_chk_fast), dim3(256), st, D[1]); });
+    if (t_chk_gen.total())
+      pl.fs.push_back([&](bool a, bool b) { launch(PH_CHECK, a, b, k_codes_check, grid(t_chk_gen), dim3(256), st, D[2]); });
+    pl.run();
+  }
+  if (t_s1.total()) launch(PH_SCAN_C, true, false, k_scan1, grid(t_s1), dim3(kScanThreads), st, D[3]);
+  launch(PH_SCAN_C, !t_s1.total(), !t_s1.total(), k_scan2, grid(t_s2), dim3(kScanThreads), st, D[4]);
+  if (t_s1.total()) launch(PH_SCAN_C, false, true, k_scan3, grid(t_s1), dim3(kScanThreads), st, D[3]);
+  launch(PH_NONE, false, false, k_header, grid(t_hdr), dim3(256), st, D[5]);
+  {
+    PhaseLaunch pl{PH_ENCODE, {}};
+    if (t_enc_fast[0].total())
+      pl.fs.push_back([&](bool a, bool b) { launch(PH_ENCODE, a, b, k_encode_fast<float, 6, 6, 6>, grid(t_enc_fast[0]), dim3(256), st, D[6]); });
+    if (t_enc_fast[1].total())
+      pl.fs.push_back([&](bool a, bool b) { launch(PH_ENCODE, a, b, k_encode_fast<double, 6, 6, 6>, grid(t_enc_fast[1]), dim3(256), st, D[7]); });
+    if (t_enc_gen[0].total())
+      pl.fs.push_back([&](bool a, bool b) { launch(PH_ENCODE, a, b, k_encode<float>, grid(t_enc_gen[0]), dim3(256), st, D[8]); });
+    if (t_enc_gen[1].total())
+      pl.fs.push_back([&](bool a, bool b) { launch(PH_ENCODE, a, b, k_encode<double>, grid(t_enc_gen[1]), dim3(256), st, D[9]); });
+    pl.run();
+  }
+  const uint64_t *d_res = (const uint64_t *)(ws + B.res);
+  if (nj == 1) d_res = jobs[0].stat;  // one field: no gather needed
+  else launch(PH_NONE, false, false, k_results, grid(t_res), dim3(64), st, D[10], (uint64_t *)d_res,
+              (uint32_t)(C_N + R_N));
+  HIPCHK(hipGetLastError());
+  uint64_t *hres = (uint64_t *)(hs + at_res);
+  HIPCHK(hipMemcpyAsync(hres, d_res, 8ull * (C_N + R_N) * nj, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  g_timer.resolve();
+
+  // ---- per-field outcome
+  int first = SDCSZ_OK;
+  for (uint32_t j = 0; j < nj; j++) {
+    CompItem &c = it[item_of[j]];
+    const uint64_t *cnt = hres + (uint64_t)j * (C_N + R_N), *res = cnt + C_N;
+    fill_report(&c.rep, cnt, fp[j].g.n_blocks);
+    std::memcpy(&c.rep.eb_abs, &res[R_EB], 8);
+    const bool unc = cnt[C_UNC + SDCSZ_T_INPUT] || cnt[C_UNC + SDCSZ_T_COEF] || cnt[C_UNC + SDCSZ_T_CODE] ||
+                     cnt[C_MISSING];
+    if (unc) {
+      c.out_size = 0;
+      c.rc = SDCSZ_ESDC;
+    } else {
+      c.rep.n_outliers = res[R_OUTLIERS];
+      c.rep.n_regression = res[R_REGRESSION];
+      c.rep.payload_words = res[R_WORDS];
+      c.rep.stream_size = res[R_SIZE];
+      c.out_size = res[R_SIZE];
+      c.rc = res[R_WRITTEN] ? SDCSZ_OK : SDCSZ_ENOSPC;
+    }
+  }
+  for (uint32_t i = 0; i < n; i++)
+    if (it[i].rc && !first) first = it[i].rc;
+  return first;
+}
+
+// ---------------------------------------------------------------------------
+// decompression, verification and region decompression of a batch
+// ---------------------------------------------------------------------------
+struct DecItem {  // one stream of a decompression call
+  const uint8_t *d_stream;
+  uint64_t stream_size;
+  uint8_t *d_out;
+  uint64_t out_cap;
+  uint32_t mode;  // 0 decompress, 1 verify, 2 region
+  Region reg;
+  uint64_t need;  // bytes the output must hold
+  const sdcsz_fault *faults;
+  uint32_t n_faults;
+  int rc;
+  sdcsz_report rep;
   Header h;
   Geo g;
 };
 
-int open_stream(const void *d_stream, uint64_t size, hipStream_t st, Opened &o) {
-  if (!d_stream) return SDCSZ_EINVAL;
-  if (size < kHeader) return SDCSZ_EFORMAT;
-  uint8_t *hs = t_stage.get();
-  if (!hs) return SDCSZ_EHIP;
-  HIPCHK(hipMemcpyAsync(hs + kStageRes, d_stream, kHeader, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  return unpack_header(hs + kStageRes, size, o.h, o.g);
+struct DecPlan {
+  DecLayout L;
+  uint8_t *ws;
+  bool fast;
+  std::vector<sdcsz_fault> plan;
+  std::vector<uint32_t> bits;
+  std::vector<uint64_t> pb;
+};
+
+uint64_t dec_batch_area(uint64_t njobs) {
+  return a256(sizeof(Job) * njobs) + 32 * a256(4 * (2 * njobs + 1)) + a256(8ull * (C_N + 1) * njobs) +
+         a256(kHeader * njobs);
 }
 
-template <typename T>
-int decode_t(const uint8_t *d_s, Opened &o, T *d_out, uint32_t mode, const Region &reg,
-             const sdcsz_fault *faults, uint32_t n_faults, sdcsz_report *h_rep, uint8_t *ws, uint64_t ws_size,
-             hipStream_t st) {
-  const Header &h = o.h;
-  const Geo &g = o.g;
-  std::vector<sdcsz_fault> plan;
-  int rc = check_plan(g, h.dtype, faults, n_faults, true, plan);
-  if (rc) return rc;
-  const DecLayout L = dec_layout(g, h.dtype, n_faults);
-  if (!ws || ws_size < L.total) return SDCSZ_ENOSPC;
-  uint8_t *hs = t_stage.get();
-  if (!hs) return SDCSZ_EHIP;
-  DecWork w;
-  w.cnt = (unsigned long long *)(ws + L.cnt);
-  w.symbols = (uint16_t *)(ws + L.symbols);
-  w.tab = (DecTab *)(ws + L.tab);
-  w.recon = ws + L.recon;
-  w.off_pay = (uint64_t *)(ws + L.off_pay);
-  w.off_out = (uint32_t *)(ws + L.off_out);
-  w.off_coef = (uint32_t *)(ws + L.off_coef);
-  w.scan_part = (uint64_t *)(ws + L.scan);
-  w.lut = (uint32_t *)(ws + L.lut);
-  w.redo_n = (uint32_t *)(ws + L.redo_n);
-  w.redo = (uint64_t *)(ws + L.redo);
-  w.err = (uint32_t *)(ws + L.err);
-  w.tot = (uint64_t *)(ws + L.tot);
-  std::vector<uint32_t> bits_host;
-  PlanDev pd;
-  rc = upload_plan(plan, g.n_blocks, ws, L.plan, L.bits, bits_host, st, &pd);
-  if (rc) return rc;
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, st, (uint32_t *)ws, L.zero_end / 4);
-  // decoder tables from the codebook section, then the block table's scans
-  hipLaunchKernelGGL(k_dectab, dim3(1), dim3(256), 0, st, (const uint32_t *)(d_s + kHeader), h.n_sym, w);
-  const uint32_t *table = (const uint32_t *)(d_s + h.off_table);
-  ScanSrc src{table, table + 1, 2};
-  rc = launch_scan(src, g.n_blocks, w.scan_part, w.off_pay, w.off_out, w.off_coef, w.tot, PH_SCAN_D, st);
-  hipLaunchKernelGGL(k_dec_check, dim3(1), dim3(64), 0, st, (const uint64_t *)w.tot, h.payload_words, h.n_outliers,
-                     h.n_regression, w.err);
-  if (rc) return rc;
-  const bool fast = mode == 0 && fast_shape(g, sizeof(T));
-  const std::vector<uint64_t> pb = plan_block_list(plan);
-  if (g.n_blocks && fast) {
-    const uint64_t *d_pb = (const uint64_t *)(ws + L.plan_blocks);
-    if (!pb.empty()) HIPCHK(hipMemcpyAsync(ws + L.plan_blocks, pb.data(), 8 * pb.size(), hipMemcpyHostToDevice, st));
-    if (!pb.empty())
-      hipLaunchKernelGGL(k_decode_list<T>, dim3(grid_for(pb.size(), 64)), dim3(64), 0, st, d_s, h, g, w, pd, d_out,
-                         d_pb, (uint32_t)pb.size());
-    Launch FL;
-    const uint32_t wgs = fast_launch(g, &FL);
-    if (wgs)
-      launch(PH_DECODE, true, true, k_decode_fast<T, 3, 6, 6, 6>, dim3(wgs), dim3(256), st, d_s, h, g, w, pd, d_out,
-             FL);
-    hipLaunchKernelGGL(k_decode_redo<T>, dim3(kMaxRedo / 64), dim3(64), 0, st, d_s, h, g, w, d_out);
-    HIPCHK(hipGetLastError());
-  } else if (g.n_blocks) {
-    launch(PH_DECODE, true, true, k_decode_generic<T>, dim3(grid_for(g.n_blocks, 64)), dim3(64), st, d_s, h, g, w,
-           pd, d_out, mode, reg);
-    HIPCHK(hipGetLastError());
+// read and check the headers of a batch of streams (one synchronisation)
+int read_headers(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStream_t st) {
+  std::vector<uint32_t> idx;
+  for (uint32_t i = 0; i < n; i++) {
+    it[i].rc = SDCSZ_OK;
+    std::memset(&it[i].rep, 0, sizeof(it[i].rep));
+    if (!it[i].d_stream) it[i].rc = SDCSZ_EINVAL;
+    else if (it[i].stream_size < kHeader) it[i].rc = SDCSZ_EFORMAT;
+    else idx.push_back(i);
   }
-  // counters, redo count and error flag: one copy, one synchronisation
-  const unsigned long long *cnt = (const unsigned long long *)(hs + kStageRes);
-  const uint32_t *tail = (const uint32_t *)(hs + kStageRes + 8 * C_N);
-  HIPCHK(hipMemcpyAsync(hs + kStageRes, ws + L.cnt, 8 * C_N + 8, hipMemcpyDeviceToHost, st));
+  if (idx.empty()) return SDCSZ_OK;
+  uint8_t *hs = t_stage.get(kHeader * idx.size() + (sizeof(Job) + 64) * idx.size() + 4096);
+  if (!hs) return SDCSZ_EHIP;
+  if (idx.size() == 1) {
+    HIPCHK(hipMemcpyAsync(hs, it[idx[0]].d_stream, kHeader, hipMemcpyDeviceToHost, st));
+  } else {
+    // gather the headers on the device, then one copy back
+    const uint64_t need = dec_batch_area(idx.size());
+    if (!ws || ws_size < need) return SDCSZ_ENOSPC;
+    std::vector<Job> jobs(idx.size());
+    Tab t;
+    for (size_t j = 0; j < idx.size(); j++) {
+      std::memset(&jobs[j], 0, sizeof(Job));
+      jobs[j].src = it[idx[j]].d_stream;
+      t.add((uint32_t)j, 1);
+    }
+    Upload up;
+    up.tabs = {&t};
+    uint8_t *hj = hs + a256(kHeader * idx.size());
+    up.place(jobs, hj, ws);
+    HIPCHK(hipMemcpyAsync(ws, hj, up.bytes(idx.size()), hipMemcpyHostToDevice, st));
+    uint8_t *dh = ws + a256(up.bytes(idx.size()));
+    launch(PH_NONE, false, false, k_headers, dim3(t.total()), dim3(64), st, up.dev[0], dh);
+    HIPCHK(hipMemcpyAsync(hs, dh, kHeader * idx.size(), hipMemcpyDeviceToHost, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  for (size_t j = 0; j < idx.size(); j++) {
+    DecItem &d = it[idx[j]];
+    d.rc = unpack_header(hs + kHeader * j, d.stream_size, d.h, d.g);
+  }
+  return SDCSZ_OK;
+}
+
+uint64_t dec_batch_ws(const Geo *g, const uint32_t *dtype, const uint32_t *nf, uint32_t n) {
+  uint64_t per = 0;
+  for (uint32_t i = 0; i < n; i++) per += dec_layout(g[i], dtype[i], nf[i]).total;
+  return dec_batch_area(n) + per;
+}
+
+// items whose headers were read (rc == OK): decode with one more synchronisation
+int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStream_t st) {
+  std::vector<DecPlan> fp;
+  std::vector<uint32_t> item_of;
+  uint64_t per = 0;
+  for (uint32_t i = 0; i < n; i++) {
+    DecItem &d = it[i];
+    if (d.rc) continue;
+    if (d.mode == 1 && !d.h.abft) d.rc = SDCSZ_EINVAL;
+    else if (d.mode == 2) {
+      uint64_t cnt = 1;
+      for (int a = 0; a < 3; a++) {
+        if (d.reg.lo[a] >= d.reg.hi[a] || d.reg.hi[a] > d.g.d[a]) d.rc = SDCSZ_EINVAL;
+        cnt *= d.reg.hi[a] - d.reg.lo[a];
+      }
+      d.need = cnt * vbytes(d.h.dtype);
+    } else {
+      d.need = d.g.n_values * vbytes(d.h.dtype);
+    }
+    if (d.rc) continue;
+    if (d.out_cap < d.need || (d.need && !d.d_out)) {
+      d.rc = SDCSZ_ENOSPC;
+      continue;
+    }
+    DecPlan f;
+    d.rc = check_plan(d.g, d.h.dtype, d.faults, d.n_faults, true, f.plan);
+    if (d.rc) continue;
+    f.L = dec_layout(d.g, d.h.dtype, d.n_faults);
+    f.fast = d.mode == 0 && d.g.n_blocks && fast_shape(d.g, vbytes(d.h.dtype));
+    f.pb = f.fast ? plan_block_list(f.plan) : std::vector<uint64_t>();
+    per += f.L.total;
+    fp.push_back(std::move(f));
+    item_of.push_back(i);
+  }
+  const uint32_t nj = (uint32_t)fp.size();
+  if (nj == 0) return SDCSZ_OK;
+  const uint64_t area = dec_batch_area(nj);
+  if (!ws || ws_size < area + per) {
+    for (uint32_t j = 0; j < nj; j++) it[item_of[j]].rc = SDCSZ_ENOSPC;
+    return SDCSZ_ENOSPC;
+  }
+  std::vector<Job> jobs(nj);
+  uint64_t at = area;
+  for (uint32_t j = 0; j < nj; j++) {
+    DecPlan &f = fp[j];
+    const DecItem &d = it[item_of[j]];
+    f.ws = ws + at;
+    at += f.L.total;
+    uint8_t *w = f.ws;
+    Job &J = jobs[j];
+    std::memset(&J, 0, sizeof(J));
+    J.g = d.g;
+    J.h = d.h;
+    DecWork &dw = J.dw;
+    dw.cnt = (unsigned long long *)(w + f.L.cnt);
+    dw.symbols = (uint16_t *)(w + f.L.symbols);
+    dw.tab = (DecTab *)(w + f.L.tab);
+    dw.recon = w + f.L.recon;
+    dw.off_pay = (uint64_t *)(w + f.L.off_pay);
+    dw.off_out = (uint32_t *)(w + f.L.off_out);
+    dw.off_coef = (uint32_t *)(w + f.L.off_coef);
+    dw.scan_part = (uint64_t *)(w + f.L.scan);
+    dw.lut = (uint32_t *)(w + f.L.lut);
+    dw.redo_n = (uint32_t *)(w + f.L.redo_n);
+    dw.redo = (uint64_t *)(w + f.L.redo);
+    dw.err = (uint32_t *)(w + f.L.err);
+    dw.tot = (uint64_t *)(w + f.L.tot);
+    J.plan.n = (uint32_t)f.plan.size();
+    J.plan.f = (const sdcsz_fault *)(w + f.L.plan);
+    J.plan.bits = (const uint32_t *)(w + f.L.bits);
+    if (f.fast) fast_launch(d.g, &J.L);
+    J.reg = d.reg;
+    J.mode = d.mode;
+    const uint32_t *table = (const uint32_t *)(d.d_stream + d.h.off_table);
+    J.ss = ScanSrc{table, table + 1, 2};
+    J.sc_part = dw.scan_part;
+    J.sc_off_pay = dw.off_pay;
+    J.sc_off_out = dw.off_out;
+    J.sc_off_coef = dw.off_coef;
+    J.sc_tot = dw.tot;
+    J.src = d.d_stream;
+    J.dst = d.d_out;
+    J.dst_cap = d.out_cap;
+    J.zero = (uint32_t *)(w + f.L.cnt);
+    J.zero_words = (f.L.zero_end - f.L.cnt) / 4;
+    J.stat = (const uint64_t *)(w + f.L.cnt);
+    J.stat_words = C_N + 1;
+    J.dtype = d.h.dtype;
+    J.abft = d.h.abft;
+    if (!f.plan.empty()) {
+      f.bits.assign(d.g.n_blocks / 32 + 1, 0);
+      for (auto &e : f.plan) f.bits[e.block >> 5] |= 1u << (e.block & 31);
+      HIPCHK(hipMemcpyAsync(w + f.L.plan, f.plan.data(), f.plan.size() * sizeof(sdcsz_fault), hipMemcpyHostToDevice,
+                            st));
+      HIPCHK(hipMemcpyAsync(w + f.L.bits, f.bits.data(), f.bits.size() * 4, hipMemcpyHostToDevice, st));
+      if (!f.pb.empty())
+        HIPCHK(hipMemcpyAsync(w + f.L.plan_blocks, f.pb.data(), 8 * f.pb.size(), hipMemcpyHostToDevice, st));
+    }
+  }
+  Tab t_zero, t_one, t_s1, t_fast[2], t_gen[2], t_redo[2];
+  for (uint32_t j = 0; j < nj; j++) {
+    const Job &J = jobs[j];
+    t_zero.add(j, 1);
+    t_one.add(j, 1);
+    t_s1.add(j, scan_chunks(J.g.n_blocks));
+    if (fp[j].fast) {
+      Launch L;
+      t_fast[J.dtype].add(j, fast_launch(J.g, &L));
+      t_redo[J.dtype].add(j, kMaxRedo / 64);  // one thread per queue slot
+    } else if (J.g.n_blocks) {
+      t_gen[J.dtype].add(j, grid_for(J.g.n_blocks, 64));
+    }
+  }
+  Upload up;
+  up.tabs = {&t_zero, &t_one, &t_s1, &t_fast[0], &t_fast[1], &t_gen[0], &t_gen[1], &t_redo[0], &t_redo[1]};
+  const size_t res_bytes = 8ull * (C_N + 1) * nj;
+  uint8_t *hs = t_stage.get(up.bytes(nj) + res_bytes + 4096);
+  if (!hs) return SDCSZ_EHIP;
+  up.place(jobs, hs, ws);
+  HIPCHK(hipMemcpyAsync(ws, hs, up.bytes(nj), hipMemcpyHostToDevice, st));
+  const std::vector<JobTab> &D = up.dev;
+  auto grid = [](const Tab &t) { return dim3(t.total()); };
+  launch(PH_NONE, false, false, k_zero_jobs, grid(t_zero), dim3(256), st, D[0]);
+  launch(PH_NONE, false, false, k_dectab, grid(t_one), dim3(256), st, D[1]);
+  if (t_s1.total()) launch(PH_SCAN_D, true, false, k_scan1, grid(t_s1), dim3(kScanThreads), st, D[2]);
+  launch(PH_SCAN_D, !t_s1.total(), !t_s1.total(), k_scan2, grid(t_one), dim3(kScanThreads), st, D[1]);
+  if (t_s1.total()) launch(PH_SCAN_D, false, true, k_scan3, grid(t_s1), dim3(kScanThreads), st, D[2]);
+  launch(PH_NONE, false, false, k_dec_check, grid(t_one), dim3(64), st, D[1]);
+  // blocks a fault plan names (full decompression) run through the generic routine first
+  for (uint32_t j = 0; j < nj; j++) {
+    const DecPlan &f = fp[j];
+    const Job &J = jobs[j];
+    if (f.pb.empty()) continue;
+    const uint64_t *d_pb = (const uint64_t *)(f.ws + f.L.plan_blocks);
+    if (J.dtype == SDCSZ_F32)
+      launch(PH_NONE, false, false, k_decode_list<float>, dim3(grid_for(f.pb.size(), 64)), dim3(64), st, J.src, J.h,
+             J.g, J.dw, J.plan, (float *)J.dst, d_pb, (uint32_t)f.pb.size());
+    else
+      launch(PH_NONE, false, false, k_decode_list<double>, dim3(grid_for(f.pb.size(), 64)), dim3(64), st, J.src, J.h,
+             J.g, J.dw, J.plan, (double *)J.dst, d_pb, (uint32_t)f.pb.size());
+  }
+  {
+    PhaseLaunch pl{PH_DECODE, {}};
+    if (t_fast[0].total())
+      pl.fs.push_back([&](bool a, bool b) { launch(PH_DECODE, a, b, k_decode_fast<float, 3, 6, 6, 6>, grid(t_fast[0]), dim3(256), st, D[3]); });
+    if (t_fast[1].total())
+      pl.fs.push_back([&](bool a, bool b) { launch(PH_DECODE, a, b, k_decode_fast<double, 3, 6, 6, 6>, grid(t_fast[1]), dim3(256), st, D[4]); });
+    if (t_gen[0].total())
+      pl.fs.push_back([&](bool a, bool b) { launch(PH_DECODE, a, b, k_decode_generic<float>, grid(t_gen[0]), dim3(64), st, D[5]); });
+    if (t_gen[1].total())
+      pl.fs.push_back([&](bool a, bool b) { launch(PH_DECODE, a, b, k_decode_generic<double>, grid(t_gen[1]), dim3(64), st, D[6]); });
+    pl.run();
+  }
+  if (t_redo[0].total()) launch(PH_NONE, false, false, k_decode_redo<float>, grid(t_redo[0]), dim3(64), st, D[7]);
+  if (t_redo[1].total()) launch(PH_NONE, false, false, k_decode_redo<double>, grid(t_redo[1]), dim3(64), st, D[8]);
+  const uint64_t *d_res = (const uint64_t *)(ws + a256(up.bytes(nj)));
+  if (nj == 1) d_res = jobs[0].stat;  // one stream: no gather needed
+  else launch(PH_NONE, false, false, k_results, grid(t_one), dim3(64), st, D[1], (uint64_t *)d_res,
+              (uint32_t)(C_N + 1));
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(hs + up.bytes(nj), d_res, res_bytes, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   g_timer.resolve();
-  if (tail[1]) return SDCSZ_EFORMAT;
-  if (fast && tail[0] > kMaxRedo) {
-    // more blocks to re-execute than the queue holds: decode everything again
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, w.cnt, (uint64_t)C_N);
-    hipLaunchKernelGGL(k_decode_generic<T>, dim3(grid_for(g.n_blocks, 64)), dim3(64), 0, st, d_s, h, g, w, pd,
-                       d_out, mode, reg);
-    HIPCHK(hipMemcpyAsync(hs + kStageRes, w.cnt, 8 * C_N, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+  std::vector<uint64_t> resv((const uint64_t *)(hs + up.bytes(nj)), (const uint64_t *)(hs + up.bytes(nj)) + (C_N + 1) * nj);
+  // more blocks to re-execute than the queue holds: decode those fields again
+  // in full with the generic kernel
+  std::vector<uint32_t> again;
+  for (uint32_t j = 0; j < nj; j++) {
+    const uint32_t *tail = (const uint32_t *)(resv.data() + (uint64_t)j * (C_N + 1) + C_N);
+    if (!tail[1] && fp[j].fast && tail[0] > kMaxRedo) again.push_back(j);
   }
-  sdcsz_report rep;
-  fill_report(&rep, cnt, g.n_blocks);
-  rep.eb_abs = h.eb_abs;
-  rep.n_outliers = h.n_outliers;
-  rep.n_regression = h.n_regression;
-  rep.payload_words = h.payload_words;
-  rep.stream_size = h.total;
-  if (h_rep) *h_rep = rep;
-  return cnt[C_UNC + SDCSZ_T_RECON] ? SDCSZ_ESDC : SDCSZ_OK;
+  if (!again.empty()) {
+    Tab t_ag[2], t_res2;
+    for (uint32_t j : again) {
+      jobs[j].mode = 0;
+      t_ag[jobs[j].dtype].add(j, grid_for(jobs[j].g.n_blocks, 64));
+      t_res2.add(j, 1);
+      launch(PH_NONE, false, false, k_zero_u64, dim3(1), dim3(64), st, jobs[j].dw.cnt, (uint64_t)C_N);
+    }
+    Upload u2;
+    u2.tabs = {&t_ag[0], &t_ag[1], &t_res2};
+    uint8_t *h2 = t_stage.get(u2.bytes(nj) + res_bytes + 4096);
+    if (!h2) return SDCSZ_EHIP;
+    u2.place(jobs, h2, ws);
+    HIPCHK(hipMemcpyAsync(ws, h2, u2.bytes(nj), hipMemcpyHostToDevice, st));
+    if (t_ag[0].total())
+      launch(PH_NONE, false, false, k_decode_generic<float>, grid(t_ag[0]), dim3(64), st, u2.dev[0]);
+    if (t_ag[1].total())
+      launch(PH_NONE, false, false, k_decode_generic<double>, grid(t_ag[1]), dim3(64), st, u2.dev[1]);
+    uint64_t *d_res2 = (uint64_t *)(ws + a256(u2.bytes(nj)));
+    launch(PH_NONE, false, false, k_results, grid(t_res2), dim3(64), st, u2.dev[2], d_res2, (uint32_t)(C_N + 1));
+    HIPCHK(hipMemcpyAsync(h2 + u2.bytes(nj), d_res2, 8ull * (C_N + 1) * again.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const uint64_t *r2 = (const uint64_t *)(h2 + u2.bytes(nj));
+    for (size_t q = 0; q < again.size(); q++)
+      std::memcpy(resv.data() + (uint64_t)again[q] * (C_N + 1), r2 + q * (C_N + 1), 8 * (C_N + 1));
+  }
+  const uint64_t *hres = resv.data();
+  int first = SDCSZ_OK;
+  for (uint32_t j = 0; j < nj; j++) {
+    DecItem &d = it[item_of[j]];
+    const uint64_t *cnt = hres + (uint64_t)j * (C_N + 1);
+    const uint32_t *tail = (const uint32_t *)(cnt + C_N);
+    fill_report(&d.rep, cnt, d.g.n_blocks);
+    d.rep.eb_abs = d.h.eb_abs;
+    d.rep.n_outliers = d.h.n_outliers;
+    d.rep.n_regression = d.h.n_regression;
+    d.rep.payload_words = d.h.payload_words;
+    d.rep.stream_size = d.h.total;
+    if (tail[1]) d.rc = SDCSZ_EFORMAT;
+    else d.rc = cnt[C_UNC + SDCSZ_T_RECON] ? SDCSZ_ESDC : SDCSZ_OK;
+  }
+  for (uint32_t i = 0; i < n; i++)
+    if (it[i].rc && !first) first = it[i].rc;
+  return first;
 }
 
 }  // namespace
@@ -795,7 +1264,9 @@ uint64_t sdcsz_max_compressed_size(const sdcsz_params *p) {
 uint64_t sdcsz_compress_workspace_size(const sdcsz_params *p) {
   Geo g;
   if (check_params(p, &g)) return 0;
-  return comp_layout(g, p->dtype, p->n_faults).total;
+  CompItem c{};
+  c.p = p;
+  return comp_batch_ws(&c, 1);
 }
 
 int sdcsz_compress(const void *d_in, const sdcsz_params *p, void *d_out, uint64_t out_cap, uint64_t *h_out_size,
@@ -804,103 +1275,178 @@ int sdcsz_compress(const void *d_in, const sdcsz_params *p, void *d_out, uint64_
   int rc = check_params(p, &g);
   if (rc) return rc;
   if (!h_out_size || (g.n_values && !d_in)) return SDCSZ_EINVAL;
-  hipStream_t st = (hipStream_t)stream;
-  if (p->dtype == SDCSZ_F32)
-    return compress_t<float>(d_in, p, g, (uint8_t *)d_out, out_cap, h_out_size, h_rep, (uint8_t *)d_ws, ws_size, st);
-  return compress_t<double>(d_in, p, g, (uint8_t *)d_out, out_cap, h_out_size, h_rep, (uint8_t *)d_ws, ws_size, st);
+  CompItem c{};
+  c.d_in = d_in;
+  c.p = p;
+  c.d_out = (uint8_t *)d_out;
+  c.out_cap = out_cap;
+  rc = compress_batch(&c, 1, (uint8_t *)d_ws, ws_size, (hipStream_t)stream);
+  if (rc == SDCSZ_EHIP) return rc;
+  *h_out_size = c.out_size;
+  if (h_rep && (c.rc == SDCSZ_OK || c.rc == SDCSZ_ENOSPC || c.rc == SDCSZ_ESDC)) *h_rep = c.rep;
+  return c.rc;
+}
+
+uint64_t sdcsz_compress_batch_workspace_size(const sdcsz_comp_item *h_items, uint32_t n) {
+  if (!h_items) return 0;
+  std::vector<CompItem> c(n);
+  for (uint32_t i = 0; i < n; i++) c[i].p = &h_items[i].params;
+  return comp_batch_ws(c.data(), n);
+}
+
+int sdcsz_compress_batch(sdcsz_comp_item *h_items, uint32_t n, void *d_ws, uint64_t ws_size, void *stream) {
+  if (!h_items && n) return SDCSZ_EINVAL;
+  std::vector<CompItem> c(n);
+  for (uint32_t i = 0; i < n; i++) {
+    c[i].d_in = h_items[i].d_in;
+    c[i].p = &h_items[i].params;
+    c[i].d_out = (uint8_t *)h_items[i].d_out;
+    c[i].out_cap = h_items[i].out_cap;
+  }
+  const int rc = compress_batch(c.data(), n, (uint8_t *)d_ws, ws_size, (hipStream_t)stream);
+  for (uint32_t i = 0; i < n; i++) {
+    h_items[i].out_size = c[i].out_size;
+    h_items[i].rc = rc == SDCSZ_EHIP ? SDCSZ_EHIP : c[i].rc;
+    h_items[i].rep = c[i].rep;
+  }
+  return rc;
 }
 
 int sdcsz_stream_info(const void *d_stream, uint64_t stream_size, sdcsz_params *h_p, uint64_t *h_n_blocks,
                       double *h_eb_abs, void *stream) {
-  Opened o;
-  int rc = open_stream(d_stream, stream_size, (hipStream_t)stream, o);
+  DecItem d{};
+  d.d_stream = (const uint8_t *)d_stream;
+  d.stream_size = stream_size;
+  int rc = read_headers(&d, 1, nullptr, 0, (hipStream_t)stream);
   if (rc) return rc;
+  if (d.rc) return d.rc;
   if (h_p) {
     std::memset(h_p, 0, sizeof(*h_p));
-    h_p->dtype = o.h.dtype;
-    h_p->ndim = o.h.ndim;
-    for (uint32_t a = 0; a < o.h.ndim; a++) {
-      h_p->dims[a] = o.h.d[3 - o.h.ndim + a];
-      h_p->block[a] = o.h.b[3 - o.h.ndim + a];
+    h_p->dtype = d.h.dtype;
+    h_p->ndim = d.h.ndim;
+    for (uint32_t a = 0; a < d.h.ndim; a++) {
+      h_p->dims[a] = d.h.d[3 - d.h.ndim + a];
+      h_p->block[a] = d.h.b[3 - d.h.ndim + a];
     }
-    h_p->eb_mode = o.h.eb_mode;
-    h_p->predictor = o.h.predictor;
-    h_p->eb = o.h.eb;
-    h_p->abft = o.h.abft;
+    h_p->eb_mode = d.h.eb_mode;
+    h_p->predictor = d.h.predictor;
+    h_p->eb = d.h.eb;
+    h_p->abft = d.h.abft;
   }
-  if (h_n_blocks) *h_n_blocks = o.h.n_blocks;
-  if (h_eb_abs) *h_eb_abs = o.h.eb_abs;
+  if (h_n_blocks) *h_n_blocks = d.h.n_blocks;
+  if (h_eb_abs) *h_eb_abs = d.h.eb_abs;
   return SDCSZ_OK;
 }
 
 uint64_t sdcsz_decompress_workspace_size(const sdcsz_params *p) {
   Geo g;
   if (!p || p->dtype > 1 || !geometry(p->ndim, p->dims, p->block, &g)) return 0;
-  return dec_layout(g, p->dtype, p->n_faults).total;
+  const uint32_t dt = p->dtype, nf = p->n_faults;
+  return dec_batch_ws(&g, &dt, &nf, 1);
 }
+
+uint64_t sdcsz_decompress_batch_workspace_size(const sdcsz_params *h_params, uint32_t n) {
+  if (!h_params && n) return 0;
+  std::vector<Geo> g(n);
+  std::vector<uint32_t> dt(n), nf(n);
+  for (uint32_t i = 0; i < n; i++) {
+    const sdcsz_params *p = &h_params[i];
+    if (p->dtype > 1 || !geometry(p->ndim, p->dims, p->block, &g[i])) return 0;
+    dt[i] = p->dtype;
+    nf[i] = p->n_faults;
+  }
+  return dec_batch_ws(g.data(), dt.data(), nf.data(), n);
+}
+
+namespace {
+int decode_one_call(DecItem &d, uint8_t *ws, uint64_t ws_size, hipStream_t st, sdcsz_report *h_rep) {
+  int rc = read_headers(&d, 1, nullptr, 0, st);
+  if (rc) return rc;
+  if (d.rc) return d.rc;
+  rc = decode_batch(&d, 1, ws, ws_size, st);
+  if (rc == SDCSZ_EHIP) return rc;
+  if (h_rep && (d.rc == SDCSZ_OK || d.rc == SDCSZ_ESDC)) *h_rep = d.rep;
+  return d.rc;
+}
+}  // namespace
 
 int sdcsz_decompress(const void *d_stream, uint64_t stream_size, void *d_out, uint64_t out_cap,
                      const sdcsz_fault *h_faults, uint32_t n_faults, sdcsz_report *h_rep, void *d_ws, uint64_t ws_size,
                      void *stream) {
-  hipStream_t st = (hipStream_t)stream;
-  Opened o;
-  int rc = open_stream(d_stream, stream_size, st, o);
-  if (rc) return rc;
-  if (out_cap < o.g.n_values * vbytes(o.h.dtype) || (o.g.n_values && !d_out)) return SDCSZ_ENOSPC;
-  Region reg{};
-  if (o.h.dtype == SDCSZ_F32)
-    return decode_t<float>((const uint8_t *)d_stream, o, (float *)d_out, 0, reg, h_faults, n_faults, h_rep,
-                           (uint8_t *)d_ws, ws_size, st);
-  return decode_t<double>((const uint8_t *)d_stream, o, (double *)d_out, 0, reg, h_faults, n_faults, h_rep,
-                          (uint8_t *)d_ws, ws_size, st);
+  DecItem d{};
+  d.d_stream = (const uint8_t *)d_stream;
+  d.stream_size = stream_size;
+  d.d_out = (uint8_t *)d_out;
+  d.out_cap = out_cap;
+  d.faults = h_faults;
+  d.n_faults = n_faults;
+  return decode_one_call(d, (uint8_t *)d_ws, ws_size, (hipStream_t)stream, h_rep);
 }
 
 int sdcsz_verify(const void *d_stream, uint64_t stream_size, void *d_data, uint64_t data_size,
                  const sdcsz_fault *h_faults, uint32_t n_faults, sdcsz_report *h_rep, void *d_ws, uint64_t ws_size,
                  void *stream) {
-  hipStream_t st = (hipStream_t)stream;
-  Opened o;
-  int rc = open_stream(d_stream, stream_size, st, o);
-  if (rc) return rc;
-  if (!o.h.abft) return SDCSZ_EINVAL;
-  if (data_size < o.g.n_values * vbytes(o.h.dtype) || (o.g.n_values && !d_data)) return SDCSZ_ENOSPC;
-  Region reg{};
-  if (o.h.dtype == SDCSZ_F32)
-    return decode_t<float>((const uint8_t *)d_stream, o, (float *)d_data, 1, reg, h_faults, n_faults, h_rep,
-                           (uint8_t *)d_ws, ws_size, st);
-  return decode_t<double>((const uint8_t *)d_stream, o, (double *)d_data, 1, reg, h_faults, n_faults, h_rep,
-                          (uint8_t *)d_ws, ws_size, st);
+  DecItem d{};
+  d.d_stream = (const uint8_t *)d_stream;
+  d.stream_size = stream_size;
+  d.d_out = (uint8_t *)d_data;
+  d.out_cap = data_size;
+  d.mode = 1;
+  d.faults = h_faults;
+  d.n_faults = n_faults;
+  return decode_one_call(d, (uint8_t *)d_ws, ws_size, (hipStream_t)stream, h_rep);
 }
 
 int sdcsz_decompress_region(const void *d_stream, uint64_t stream_size, const uint64_t *h_lo, const uint64_t *h_hi,
                             void *d_out, uint64_t out_cap, sdcsz_report *h_rep, void *d_ws, uint64_t ws_size,
                             void *stream) {
+  DecItem d{};
+  d.d_stream = (const uint8_t *)d_stream;
+  d.stream_size = stream_size;
+  d.d_out = (uint8_t *)d_out;
+  d.out_cap = out_cap;
+  d.mode = 2;
   hipStream_t st = (hipStream_t)stream;
-  Opened o;
-  int rc = open_stream(d_stream, stream_size, st, o);
+  int rc = read_headers(&d, 1, nullptr, 0, st);
   if (rc) return rc;
+  if (d.rc) return d.rc;
   if (!h_lo || !h_hi) return SDCSZ_EINVAL;
-  Region reg;
-  uint64_t cnt = 1;
-  const uint32_t off = 3 - o.h.ndim;
+  const uint32_t off = 3 - d.h.ndim;
   for (int a = 0; a < 3; a++) {
-    reg.lo[a] = 0;
-    reg.hi[a] = 1;
+    d.reg.lo[a] = 0;
+    d.reg.hi[a] = 1;
   }
-  for (uint32_t a = 0; a < o.h.ndim; a++) {
-    reg.lo[off + a] = h_lo[a];
-    reg.hi[off + a] = h_hi[a];
+  for (uint32_t a = 0; a < d.h.ndim; a++) {
+    d.reg.lo[off + a] = h_lo[a];
+    d.reg.hi[off + a] = h_hi[a];
   }
-  for (int a = 0; a < 3; a++) {
-    if (reg.lo[a] >= reg.hi[a] || reg.hi[a] > o.g.d[a]) return SDCSZ_EINVAL;
-    cnt *= reg.hi[a] - reg.lo[a];
+  rc = decode_batch(&d, 1, (uint8_t *)d_ws, ws_size, st);
+  if (rc == SDCSZ_EHIP) return rc;
+  if (h_rep && (d.rc == SDCSZ_OK || d.rc == SDCSZ_ESDC)) *h_rep = d.rep;
+  return d.rc;
+}
+
+int sdcsz_decompress_batch(sdcsz_dec_item *h_items, uint32_t n, void *d_ws, uint64_t ws_size, void *stream) {
+  if (!h_items && n) return SDCSZ_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<DecItem> d(n);
+  for (uint32_t i = 0; i < n; i++) {
+    std::memset(&d[i], 0, sizeof(DecItem));
+    d[i].d_stream = (const uint8_t *)h_items[i].d_stream;
+    d[i].stream_size = h_items[i].stream_size;
+    d[i].d_out = (uint8_t *)h_items[i].d_out;
+    d[i].out_cap = h_items[i].out_cap;
   }
-  if (out_cap < cnt * vbytes(o.h.dtype) || !d_out) return SDCSZ_ENOSPC;
-  if (o.h.dtype == SDCSZ_F32)
-    return decode_t<float>((const uint8_t *)d_stream, o, (float *)d_out, 2, reg, nullptr, 0, h_rep, (uint8_t *)d_ws,
-                           ws_size, st);
-  return decode_t<double>((const uint8_t *)d_stream, o, (double *)d_out, 2, reg, nullptr, 0, h_rep, (uint8_t *)d_ws,
-                          ws_size, st);
+  int rc = read_headers(d.data(), n, (uint8_t *)d_ws, ws_size, st);
+  if (rc == SDCSZ_OK) rc = decode_batch(d.data(), n, (uint8_t *)d_ws, ws_size, st);
+  for (uint32_t i = 0; i < n; i++) {
+    h_items[i].rc = rc == SDCSZ_EHIP ? SDCSZ_EHIP : d[i].rc;
+    h_items[i].rep = d[i].rep;
+  }
+  if (rc) return rc;
+  for (uint32_t i = 0; i < n; i++)
+    if (d[i].rc) return d[i].rc;
+  return SDCSZ_OK;
 }
 
 }  // extern "C"

@@ -1,4 +1,5 @@
-// kern.h -- kernel declarations (definitions in kern_*.hip).
+// kern.h -- kernel declarations (definitions in kern_*.hip) and the job
+// tables through which every launch covers one or many fields.
 #pragma once
 
 #include "common.h"
@@ -21,6 +22,7 @@ constexpr uint32_t kScanItems = 8;
 constexpr uint32_t kScanChunk = kScanThreads * kScanItems;
 constexpr uint32_t kRangeThreads = 256;
 constexpr uint32_t kHistWin = 2048;  // codes counted in LDS around the radius
+constexpr uint32_t kRangeBlocks = 2048;
 
 // Work of one specialised launch: work-groups [0, full_wgs) take the
 // sub-grid of full blocks, the others the shell of partial blocks at the
@@ -32,53 +34,104 @@ struct Launch {
   uint64_t s2, s1;     // sizes of the first two shell slabs
   uint64_t full_count, shell_count;
 };
-constexpr uint32_t kRangeBlocks = 2048;
+
+// One field of a launch: its geometry, device work areas and parameters.
+struct Job {
+  Geo g;
+  CompWork cw;          // compression work areas
+  DecWork dw;           // decompression work areas
+  PlanDev plan;
+  Launch L;
+  Header h;             // compression: fixed header fields; decompression: the stream's header
+  Region reg;           // decompression mode 2
+  ScanSrc ss;           // what the block scans read, and where they write
+  uint64_t *sc_part, *sc_off_pay, *sc_tot;
+  uint32_t *sc_off_out, *sc_off_coef;
+  const uint8_t *src;   // compression: the field's values; decompression: its stream
+  uint8_t *dst;         // compression: the stream buffer; decompression: the output values
+  uint64_t dst_cap;
+  uint32_t *zero;       // cleared at the start of the call
+  uint64_t zero_words;
+  const uint64_t *stat; // counters and results read back at the end of the call
+  uint32_t stat_words;
+  double eb;
+  uint32_t dtype, abft, predictor, eb_mode, mode, nparts, n_sym;
+  RegTab<float> rtf;
+  RegTab<double> rtd;
+};
+
+template <typename T> __device__ __host__ inline const RegTab<T> &rt_of(const Job &J);
+template <> __device__ __host__ inline const RegTab<float> &rt_of<float>(const Job &J) { return J.rtf; }
+template <> __device__ __host__ inline const RegTab<double> &rt_of<double>(const Job &J) { return J.rtd; }
+
+// The work-groups of one launch: the slot-th job of the launch is
+// jobs[id[slot]] and owns work-groups [wg[slot], wg[slot + 1]).
+struct JobTab {
+  const Job *jobs;
+  const uint32_t *wg;  // n + 1 entries
+  const uint32_t *id;  // n entries
+  uint32_t n;
+};
+
+// slot of the job that owns work-group b (wg[] ascending, wg[0] = 0)
+__device__ inline uint32_t job_slot(const JobTab &t, uint32_t b) {
+  uint32_t lo = 0, hi = t.n;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (t.wg[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// The calling work-group's job, its index in the job's share of the launch
+// and the size of that share.
+struct JobWg {
+  const Job *J;
+  uint32_t b, nb, slot;
+};
+__device__ inline JobWg job_of(const JobTab &t) {
+  const uint32_t s = job_slot(t, blockIdx.x);
+  return JobWg{t.jobs + t.id[s], blockIdx.x - t.wg[s], t.wg[s + 1] - t.wg[s], s};
+}
 
 __global__ void k_zero_u64(unsigned long long *p, uint64_t n);
 __global__ void k_zero_u32(uint32_t *p, uint64_t n);
-template <typename T> __global__ void k_range(const T *in, uint64_t n, double *part);
-__global__ void k_consts(const double *part, uint32_t nparts, uint32_t mode, double eb, EbDev *out);
+__global__ void k_zero_jobs(JobTab t);
+template <typename T> __global__ void k_range(JobTab t);
+__global__ void k_consts(JobTab t);
 __global__ void k_code_faults(PlanDev plan, Geo g, uint16_t *codes, unsigned long long *cnt);
-__global__ void k_codes_check(Geo g, CompWork w, uint32_t abft);
-__global__ void k_scan1(ScanSrc src, uint64_t n, uint64_t *part);
-__global__ void k_scan2(uint64_t *part, uint32_t nparts);
-__global__ void k_scan3(ScanSrc src, uint64_t n, const uint64_t *part, uint64_t *off_pay,
-                        uint32_t *off_out, uint32_t *off_coef, uint64_t *tot);
-__global__ void k_put_codes(const uint32_t *cb, uint32_t n_sym, uint32_t *enc);
-__global__ void k_header(Header h, CompWork w, uint8_t *out, uint64_t out_cap);
-__global__ void k_dectab(const uint32_t *cbk, uint32_t n_sym, DecWork w);
-__global__ void k_dec_check(const uint64_t *tot, uint64_t payload_words, uint64_t n_outliers,
-                            uint64_t n_regression, uint32_t *err);
-template <typename T>
-__global__ void k_encode(Geo g, CompWork w, uint8_t *out);
+__global__ void k_codes_check(JobTab t);
+__global__ void k_scan1(JobTab t);
+__global__ void k_scan2(JobTab t);
+__global__ void k_scan3(JobTab t);
+template <typename T> __global__ void k_encode(JobTab t);
+__global__ void k_hist_count(JobTab t, uint32_t *chunk_cnt);
+__global__ void k_hist_scan(uint32_t n, uint32_t *chunk_cnt, uint32_t *counts);
+__global__ void k_hist_pack(JobTab t, const uint32_t *chunk_off, uint64_t *dst);
+__global__ void k_put_codes(JobTab t);
+__global__ void k_header(JobTab t);
+__global__ void k_results(JobTab t, uint64_t *dst, uint32_t per);
+__global__ void k_headers(JobTab t, uint8_t *dst);
+__global__ void k_dectab(JobTab t);
+__global__ void k_dec_check(JobTab t);
 
-template <typename T, int ND, int B0, int B1, int B2, bool ABFT>
-__global__ void k_compress_fast(const T *in, Geo g, RegTab<T> rt, PlanDev plan, CompWork w, uint32_t predictor,
-                                Launch L);
+template <typename T, int ND, int B0, int B1, int B2, bool ABFT> __global__ void k_compress_fast(JobTab t);
 template <typename T>
 __global__ void k_compress_list(const T *in, Geo g, RegTab<T> rt, PlanDev plan, CompWork w, uint32_t abft,
                                 uint32_t predictor, const uint64_t *list, uint32_t n);
-template <typename T>
-__global__ void k_redo(const T *in, Geo g, RegTab<T> rt, PlanDev plan, CompWork w, uint32_t abft,
-                       uint32_t predictor);
+template <typename T> __global__ void k_redo(JobTab t);
 
-template <typename T, int ND, int B0, int B1, int B2>
-__global__ void k_decode_fast(const uint8_t *s, Header h, Geo g, DecWork w, PlanDev plan, T *out, Launch L);
+template <typename T, int ND, int B0, int B1, int B2> __global__ void k_decode_fast(JobTab t);
 template <typename T>
 __global__ void k_decode_list(const uint8_t *s, Header h, Geo g, DecWork w, PlanDev plan, T *out,
                               const uint64_t *list, uint32_t n);
-template <typename T>
-__global__ void k_decode_redo(const uint8_t *s, Header h, Geo g, DecWork w, T *out);
+template <typename T> __global__ void k_decode_redo(JobTab t);
 
-template <int B0, int B1, int B2> __global__ void k_check_fast(Geo g, CompWork w, uint32_t abft);
-template <typename T, int B0, int B1, int B2>
-__global__ void k_encode_fast(Geo g, CompWork w, uint8_t *out);
+template <int B0, int B1, int B2> __global__ void k_check_fast(JobTab t);
+template <typename T, int B0, int B1, int B2> __global__ void k_encode_fast(JobTab t);
 
-template <typename T>
-__global__ void k_compress_generic(const T *in, Geo g, RegTab<T> rt, PlanDev plan, CompWork w,
-                                   uint32_t abft, uint32_t predictor);
-template <typename T>
-__global__ void k_decode_generic(const uint8_t *s, Header h, Geo g, DecWork w, PlanDev plan,
-                                 T *out, uint32_t mode, Region reg);
+template <typename T> __global__ void k_compress_generic(JobTab t);
+template <typename T> __global__ void k_decode_generic(JobTab t);
 
 }  // namespace sdcsz

@@ -456,19 +456,25 @@ __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const G
 
 // Work-groups [0, L.full_wgs) take full blocks, the rest the partial shell.
 template <typename T, int ND, int B0, int B1, int B2, bool ABFT>
-__global__ void __launch_bounds__(256)
-k_compress_fast(const T *__restrict__ in, Geo g, RegTab<T> rt, PlanDev plan, CompWork w, uint32_t predictor,
-                Launch L) {
+__global__ void __launch_bounds__(256) k_compress_fast(JobTab tab) {
+  const JobWg jw = job_of(tab);
+  const T *__restrict__ in = (const T *)jw.J->src;
+  const Geo g = jw.J->g;
+  const RegTab<T> &rt = rt_of<T>(*jw.J);  // stays in memory: indexed by each block's pattern
+  const PlanDev plan = jw.J->plan;
+  const CompWork w = jw.J->cw;
+  const uint32_t predictor = jw.J->predictor;
+  const Launch L = jw.J->L;
   __shared__ uint32_t hist[kHistWin];
   for (uint32_t t = threadIdx.x; t < kHistWin; t += blockDim.x) hist[t] = 0;
   __syncthreads();
   uint32_t hot = 0;
-  if (blockIdx.x < L.full_wgs)
+  if (jw.b < L.full_wgs)
     compress_lanes<T, ND, B0, B1, B2, true, ABFT>(in, g, rt, plan, w, predictor, L, hist, hot,
-                                                  (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, L.full_count);
+                                                  (uint64_t)jw.b * blockDim.x + threadIdx.x, L.full_count);
   else
     compress_lanes<T, ND, B0, B1, B2, false, ABFT>(in, g, rt, plan, w, predictor, L, hist, hot,
-                                                   (uint64_t)(blockIdx.x - L.full_wgs) * blockDim.x + threadIdx.x,
+                                                   (uint64_t)(jw.b - L.full_wgs) * blockDim.x + threadIdx.x,
                                                    L.shell_count);
   // wave total of the zero-residual bin (lanes that ran the pass agree; the
   // others hold 0), then flush the window
@@ -492,9 +498,14 @@ __global__ void __launch_bounds__(64) k_compress_list(const T *__restrict__ in, 
 // Blocks whose checks disagreed in the specialised pass: take the block's
 // codes back out of the histogram and run the block again from the input
 // with the generic routine.
-template <typename T>
-__global__ void __launch_bounds__(64) k_redo(const T *__restrict__ in, Geo g, RegTab<T> rt, PlanDev plan,
-                                              CompWork w, uint32_t abft, uint32_t predictor) {
+template <typename T> __global__ void __launch_bounds__(64) k_redo(JobTab tab) {
+  const Job &J = *job_of(tab).J;
+  const T *__restrict__ in = (const T *)J.src;
+  const Geo g = J.g;
+  const RegTab<T> &rt = rt_of<T>(J);
+  const PlanDev plan = J.plan;
+  const CompWork w = J.cw;
+  const uint32_t abft = J.abft, predictor = J.predictor;
   const uint32_t n = min(*w.redo_n, kMaxRedo);
   for (uint32_t s = threadIdx.x; s < n; s += blockDim.x) {
     const uint64_t e = w.redo[s];
@@ -512,9 +523,8 @@ __global__ void __launch_bounds__(64) k_redo(const T *__restrict__ in, Geo g, Re
   }
 }
 
-#define SDCSZ_INST_FAST(T, ND, B0, B1, B2, ABFT)                                                          \
-  template __global__ void k_compress_fast<T, ND, B0, B1, B2, ABFT>(const T *, Geo, RegTab<T>, PlanDev, CompWork, \
-                                                                    uint32_t, Launch);
+#define SDCSZ_INST_FAST(T, ND, B0, B1, B2, ABFT) \
+  template __global__ void k_compress_fast<T, ND, B0, B1, B2, ABFT>(JobTab);
 #define SDCSZ_INST_SHAPE(T, ND, B0, B1, B2) \
   SDCSZ_INST_FAST(T, ND, B0, B1, B2, true)  \
   SDCSZ_INST_FAST(T, ND, B0, B1, B2, false)
@@ -524,7 +534,7 @@ template __global__ void k_compress_list<float>(const float *, Geo, RegTab<float
                                                 uint32_t, const uint64_t *, uint32_t);
 template __global__ void k_compress_list<double>(const double *, Geo, RegTab<double>, PlanDev, CompWork, uint32_t,
                                                  uint32_t, const uint64_t *, uint32_t);
-template __global__ void k_redo<float>(const float *, Geo, RegTab<float>, PlanDev, CompWork, uint32_t, uint32_t);
-template __global__ void k_redo<double>(const double *, Geo, RegTab<double>, PlanDev, CompWork, uint32_t, uint32_t);
+template __global__ void k_redo<float>(JobTab);
+template __global__ void k_redo<double>(JobTab);
 
 }  // namespace sdcsz

@@ -283,7 +283,15 @@ __device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, cons
 // Work-groups [0, L.full_wgs) take full blocks, the rest the partial shell.
 template <typename T, int ND, int B0, int B1, int B2>
 __global__ void __launch_bounds__(kDecThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
-k_decode_fast(const uint8_t *__restrict__ s, Header h, Geo g, DecWork w, PlanDev plan, T *out, Launch L) {
+k_decode_fast(JobTab tab) {
+  const JobWg jw = job_of(tab);
+  const uint8_t *__restrict__ s = jw.J->src;
+  const Header h = jw.J->h;
+  const Geo g = jw.J->g;
+  const DecWork w = jw.J->dw;
+  const PlanDev plan = jw.J->plan;
+  T *out = (T *)jw.J->dst;
+  const Launch L = jw.J->L;
   if (*w.err) return;  // invalid codebook or block table: nothing is read
   __shared__ DecLds tl;
   __shared__ uint32_t win[kWin * kDecThreads];
@@ -302,17 +310,16 @@ k_decode_fast(const uint8_t *__restrict__ s, Header h, Geo g, DecWork w, PlanDev
     tl.long_n = ln;
   }
   __syncthreads();
-  if (blockIdx.x < L.full_wgs)
+  if (jw.b < L.full_wgs)
     decode_lanes<T, ND, B0, B1, B2, true>(s, h, g, w, plan, out, L, tl, win + threadIdx.x,
-                                          (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, L.full_count);
+                                          (uint64_t)jw.b * blockDim.x + threadIdx.x, L.full_count);
   else
     decode_lanes<T, ND, B0, B1, B2, false>(s, h, g, w, plan, out, L, tl, win + threadIdx.x,
-                                           (uint64_t)(blockIdx.x - L.full_wgs) * blockDim.x + threadIdx.x,
+                                           (uint64_t)(jw.b - L.full_wgs) * blockDim.x + threadIdx.x,
                                            L.shell_count);
 }
 
-#define SDCSZ_INST_DEC(T, ND, B0, B1, B2) \
-  template __global__ void k_decode_fast<T, ND, B0, B1, B2>(const uint8_t *, Header, Geo, DecWork, PlanDev, T *, Launch);
+#define SDCSZ_INST_DEC(T, ND, B0, B1, B2) template __global__ void k_decode_fast<T, ND, B0, B1, B2>(JobTab);
 SDCSZ_INST_DEC(float, 3, 6, 6, 6)
 SDCSZ_INST_DEC(double, 3, 6, 6, 6)
 

@@ -59,11 +59,14 @@ template <int B0, int B1, int B2> struct PlaneCodes {
 
 // Verify/correct the codes of each block with sum_q/isum_q (Algorithm 1,
 // before encoding) and size its payload in 32-bit words.
-template <int B0, int B1, int B2>
-__global__ void __launch_bounds__(256) k_check_fast(Geo g, CompWork w, uint32_t abft) {
+template <int B0, int B1, int B2> __global__ void __launch_bounds__(256) k_check_fast(JobTab jt) {
+  const JobWg jw = job_of(jt);
+  const Geo g = jw.J->g;
+  const CompWork w = jw.J->cw;
+  const uint32_t abft = jw.J->abft;
   __shared__ uint32_t encw[kEncWin];
   load_window(encw, w.enc);
-  const uint64_t blk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t blk = (uint64_t)jw.b * blockDim.x + threadIdx.x;
   if (blk >= g.n_blocks) return;
   const Box b = box_of(g, blk);
   const uint32_t n1 = b.n[1], n2 = b.n[2];
@@ -141,14 +144,17 @@ __global__ void __launch_bounds__(256) k_check_fast(Geo g, CompWork w, uint32_t 
 // each row the lane writes out what is complete, whole aligned 32-byte
 // chunks as two 16-byte stores, so HBM sees full sectors instead of one
 // partial write per word (only a block's first and last chunk are partial).
-template <typename T, int B0, int B1, int B2>
-__global__ void __launch_bounds__(256) k_encode_fast(Geo g, CompWork w, uint8_t *out) {
+template <typename T, int B0, int B1, int B2> __global__ void __launch_bounds__(256) k_encode_fast(JobTab jt) {
+  const JobWg jw = job_of(jt);
+  const Geo g = jw.J->g;
+  const CompWork w = jw.J->cw;
+  uint8_t *out = jw.J->dst;
   if (!w.res[R_WRITTEN]) return;  // the stream is not written (see k_header)
   const Header h = *w.hdr;
   __shared__ uint32_t encw[kEncWin];
   __shared__ uint32_t ring_all[16 * 256];
   load_window(encw, w.enc);
-  const uint64_t blk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t blk = (uint64_t)jw.b * blockDim.x + threadIdx.x;
   if (blk >= g.n_blocks) return;
   const Box b = box_of(g, blk);
   PlaneCodes<B0, B1, B2> bc;
@@ -228,8 +234,8 @@ __global__ void __launch_bounds__(256) k_encode_fast(Geo g, CompWork w, uint8_t 
   if (h.abft) ((uint64_t *)(out + h.off_sumdc))[blk] = w.sum_dc[blk];
 }
 
-template __global__ void k_check_fast<6, 6, 6>(Geo, CompWork, uint32_t);
-template __global__ void k_encode_fast<float, 6, 6, 6>(Geo, CompWork, uint8_t *);
-template __global__ void k_encode_fast<double, 6, 6, 6>(Geo, CompWork, uint8_t *);
+template __global__ void k_check_fast<6, 6, 6>(JobTab);
+template __global__ void k_encode_fast<float, 6, 6, 6>(JobTab);
+template __global__ void k_encode_fast<double, 6, 6, 6>(JobTab);
 
 }  // namespace sdcsz

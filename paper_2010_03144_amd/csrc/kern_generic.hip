@@ -8,17 +8,16 @@
 
 namespace sdcsz {
 
-template <typename T>
-__global__ void __launch_bounds__(64)
-k_compress_generic(const T *__restrict__ in, Geo g, RegTab<T> rt, PlanDev plan, CompWork w,
-                   uint32_t abft, uint32_t predictor) {
-  const uint64_t blk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (blk >= g.n_blocks) return;
-  compress_block_generic<T>(in, g, rt, plan, w, abft, predictor, blk);
+template <typename T> __global__ void __launch_bounds__(64) k_compress_generic(JobTab tab) {
+  const JobWg jw = job_of(tab);
+  const Job &J = *jw.J;
+  const uint64_t blk = (uint64_t)jw.b * blockDim.x + threadIdx.x;
+  if (blk >= J.g.n_blocks) return;
+  compress_block_generic<T>((const T *)J.src, J.g, rt_of<T>(J), J.plan, J.cw, J.abft, J.predictor, blk);
 }
 
-template __global__ void k_compress_generic<float>(const float *, Geo, RegTab<float>, PlanDev, CompWork, uint32_t, uint32_t);
-template __global__ void k_compress_generic<double>(const double *, Geo, RegTab<double>, PlanDev, CompWork, uint32_t, uint32_t);
+template __global__ void k_compress_generic<float>(JobTab);
+template __global__ void k_compress_generic<double>(JobTab);
 
 // ---------------------------------------------------------------------------
 // Decoding one block (Algorithm 2, lines 3-8) into block-major scratch.
@@ -185,13 +184,12 @@ __device__ __noinline__ void decode_one(const uint8_t *__restrict__ s, const Hea
   }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(64)
-k_decode_generic(const uint8_t *__restrict__ s, Header h, Geo g, DecWork w, PlanDev plan, T *out, uint32_t mode,
-                 Region reg) {
-  if (*w.err) return;  // invalid codebook or block table: nothing is read
-  const uint64_t blk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (blk < g.n_blocks) decode_one<T>(s, h, g, w, plan, out, mode, reg, blk);
+template <typename T> __global__ void __launch_bounds__(64) k_decode_generic(JobTab tab) {
+  const JobWg jw = job_of(tab);
+  const Job &J = *jw.J;
+  if (*J.dw.err) return;  // invalid codebook or block table: nothing is read
+  const uint64_t blk = (uint64_t)jw.b * blockDim.x + threadIdx.x;
+  if (blk < J.g.n_blocks) decode_one<T>(J.src, J.h, J.g, J.dw, J.plan, (T *)J.dst, J.mode, J.reg, blk);
 }
 
 // full decompression of listed blocks (the blocks a fault plan names)
@@ -210,15 +208,19 @@ k_decode_list(const uint8_t *__restrict__ s, Header h, Geo g, DecWork w, PlanDev
 // not be decoded is decoded once more and, failing again, zeroed; a block
 // with a symbol beyond the specialised decoder's tables runs the whole
 // per-block procedure here.  One thread per queue entry.
-template <typename T>
-__global__ void __launch_bounds__(64)
-k_decode_redo(const uint8_t *__restrict__ s, Header h, Geo g, DecWork w, T *out) {
+template <typename T> __global__ void __launch_bounds__(64) k_decode_redo(JobTab jt) {
+  const JobWg jw = job_of(jt);
+  const uint8_t *__restrict__ s = jw.J->src;
+  const Header h = jw.J->h;
+  const Geo g = jw.J->g;
+  const DecWork w = jw.J->dw;
+  T *out = (T *)jw.J->dst;
   if (*w.err) return;
   const uint32_t n = min(*w.redo_n, kMaxRedo);
   const DecTab tab = *w.tab;
   const T q = (T)(2.0 * h.eb_abs);
   const uint64_t *sumdc = (const uint64_t *)(s + h.off_sumdc);
-  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+  for (uint32_t e = jw.b * blockDim.x + threadIdx.x; e < n; e += jw.nb * blockDim.x) {
     const uint64_t blk = w.redo[e] & ((1ull << 56) - 1), why = w.redo[e] >> 56;
     if (why == 3) {
       const PlanDev none{nullptr, 0, nullptr};
@@ -244,11 +246,11 @@ k_decode_redo(const uint8_t *__restrict__ s, Header h, Geo g, DecWork w, T *out)
   }
 }
 
-template __global__ void k_decode_generic<float>(const uint8_t *, Header, Geo, DecWork, PlanDev, float *, uint32_t, Region);
-template __global__ void k_decode_generic<double>(const uint8_t *, Header, Geo, DecWork, PlanDev, double *, uint32_t, Region);
+template __global__ void k_decode_generic<float>(JobTab);
+template __global__ void k_decode_generic<double>(JobTab);
 template __global__ void k_decode_list<float>(const uint8_t *, Header, Geo, DecWork, PlanDev, float *, const uint64_t *, uint32_t);
 template __global__ void k_decode_list<double>(const uint8_t *, Header, Geo, DecWork, PlanDev, double *, const uint64_t *, uint32_t);
-template __global__ void k_decode_redo<float>(const uint8_t *, Header, Geo, DecWork, float *);
-template __global__ void k_decode_redo<double>(const uint8_t *, Header, Geo, DecWork, double *);
+template __global__ void k_decode_redo<float>(JobTab);
+template __global__ void k_decode_redo<double>(JobTab);
 
 }  // namespace sdcsz

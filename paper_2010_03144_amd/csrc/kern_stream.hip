@@ -15,11 +15,100 @@
 namespace sdcsz {
 
 // enc[symbol] = codeword << 8 | length for each codebook entry.
-__global__ void __launch_bounds__(256) k_put_codes(const uint32_t *cb, uint32_t n_sym, uint32_t *enc) {
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_sym) return;
-  const uint32_t e = cb[2 * t], code = cb[2 * t + 1];
-  enc[e >> 8] = (code << 8) | (e & 0xFFu);
+__global__ void __launch_bounds__(256) k_put_codes(JobTab t) {
+  const JobWg jw = job_of(t);
+  const Job &J = *jw.J;
+  const uint32_t i = jw.b * blockDim.x + threadIdx.x;
+  if (i >= J.n_sym) return;
+  const uint32_t e = J.cw.cb[2 * i], code = J.cw.cb[2 * i + 1];
+  J.cw.enc[e >> 8] = (code << 8) | (e & 0xFFu);
+}
+
+// Histogram of each job compacted to (symbol << 32 | count) for the used
+// symbols, in symbol order, all jobs one after another.  The 65536 symbols
+// of a job are cut into kHistChunks chunks: k_hist_count counts the used
+// symbols of every chunk (one work-group per chunk), k_hist_scan (one
+// work-group) turns the counts into offsets and per-job totals, k_hist_pack
+// writes every chunk's entries at its offset.
+constexpr uint32_t kHistChunks = 64, kHistChunk = 65536 / kHistChunks;
+
+__global__ void __launch_bounds__(256) k_hist_count(JobTab t, uint32_t *chunk_cnt) {
+  const JobWg jw = job_of(t);
+  const uint32_t *hist = jw.J->cw.hist + jw.b * kHistChunk;
+  uint32_t c = 0;
+  for (uint32_t s = threadIdx.x; s < kHistChunk; s += blockDim.x) c += hist[s] ? 1u : 0u;
+  for (int off = 32; off > 0; off >>= 1) c += (uint32_t)__shfl_xor((int)c, off);
+  __shared__ uint32_t wsum[4];
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) chunk_cnt[jw.slot * kHistChunks + jw.b] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+// one work-group: exclusive scan of the n * kHistChunks chunk counts in
+// place, and each job's total into counts[]
+__global__ void __launch_bounds__(256) k_hist_scan(uint32_t n, uint32_t *chunk_cnt, uint32_t *counts) {
+  __shared__ uint32_t pre[256];
+  __shared__ uint64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const uint32_t total = n * kHistChunks;
+  for (uint32_t base = 0; base < total; base += 256) {
+    const uint32_t i = base + threadIdx.x;
+    const uint32_t v = i < total ? chunk_cnt[i] : 0u;
+    pre[threadIdx.x] = v;
+    __syncthreads();
+    for (uint32_t off = 1; off < 256; off <<= 1) {
+      const uint32_t u = threadIdx.x >= off ? pre[threadIdx.x - off] : 0u;
+      __syncthreads();
+      pre[threadIdx.x] += u;
+      __syncthreads();
+    }
+    if (i < total) chunk_cnt[i] = (uint32_t)carry + pre[threadIdx.x] - v;
+    // a job's chunks all sit in one piece of 256 (kHistChunks divides 256)
+    if (i < total && i % kHistChunks == kHistChunks - 1)
+      counts[i / kHistChunks] = pre[threadIdx.x] - (i % 256 >= kHistChunks ? pre[i % 256 - kHistChunks] : 0u);
+    __syncthreads();
+    if (threadIdx.x == 0) carry += pre[255];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256) k_hist_pack(JobTab t, const uint32_t *chunk_off, uint64_t *dst) {
+  const JobWg jw = job_of(t);
+  const uint32_t s0 = jw.b * kHistChunk;
+  const uint32_t *hist = jw.J->cw.hist;
+  constexpr uint32_t per = kHistChunk / 256;
+  uint32_t mine = 0;
+  for (uint32_t q = 0; q < per; q++) mine += hist[s0 + threadIdx.x * per + q] ? 1u : 0u;
+  __shared__ uint32_t pre[256];
+  pre[threadIdx.x] = mine;
+  __syncthreads();
+  for (uint32_t off = 1; off < 256; off <<= 1) {
+    const uint32_t v = threadIdx.x >= off ? pre[threadIdx.x - off] : 0u;
+    __syncthreads();
+    pre[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint64_t at = chunk_off[jw.slot * kHistChunks + jw.b] + pre[threadIdx.x] - mine;
+  for (uint32_t q = 0; q < per; q++) {
+    const uint32_t s = s0 + threadIdx.x * per + q;
+    const uint32_t c = hist[s];
+    if (c) dst[at++] = ((uint64_t)s << 32) | c;
+  }
+}
+
+// Each job's counters and results, one after another (per words each).
+__global__ void __launch_bounds__(64) k_results(JobTab t, uint64_t *dst, uint32_t per) {
+  const JobWg jw = job_of(t);
+  for (uint32_t i = threadIdx.x; i < per; i += blockDim.x) dst[(uint64_t)jw.slot * per + i] = jw.J->stat[i];
+}
+
+// Each job's stream header, one after another.
+__global__ void __launch_bounds__(64) k_headers(JobTab t, uint8_t *dst) {
+  const JobWg jw = job_of(t);
+  const uint32_t *src = (const uint32_t *)jw.J->src;
+  uint32_t *d = (uint32_t *)(dst + (uint64_t)jw.slot * kHeader);
+  for (uint32_t i = threadIdx.x; i < kHeader / 4; i += blockDim.x) d[i] = src[i];
 }
 
 namespace {
@@ -61,11 +150,16 @@ __device__ void write_header(const Header &h, uint8_t *o) {
 
 }  // namespace
 
-// Completes the header `h` (fixed fields set by the host) from the device
+// Completes the header (fixed fields set by the host) from the device
 // results and decides whether the stream is written: no uncorrectable error
 // in the input, coefficient or code stages, no code without a codeword, and
-// the stream fits `out_cap`.  Grid: one thread per codebook entry (>= 1).
-__global__ void __launch_bounds__(256) k_header(Header h, CompWork w, uint8_t *out, uint64_t out_cap) {
+// the stream fits the caller's buffer.  One thread per codebook entry (>= 1).
+__global__ void __launch_bounds__(256) k_header(JobTab tb) {
+  const JobWg jw = job_of(tb);
+  Header h = jw.J->h;
+  const CompWork &w = jw.J->cw;
+  uint8_t *out = jw.J->dst;
+  const uint64_t out_cap = jw.J->dst_cap;
   h.eb_abs = w.eb->eb_abs;
   const uint64_t *tot = w.tot;  // left by the scan (zero without blocks)
   h.payload_words = tot[0];
@@ -75,7 +169,7 @@ __global__ void __launch_bounds__(256) k_header(Header h, CompWork w, uint8_t *o
   const unsigned long long *c = w.cnt;
   const bool unc = c[C_UNC + SDCSZ_T_INPUT] || c[C_UNC + SDCSZ_T_COEF] || c[C_UNC + SDCSZ_T_CODE] || c[C_MISSING];
   const bool ok = !unc && out != nullptr && h.total <= out_cap;
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t t = jw.b * blockDim.x + threadIdx.x;
   if (t == 0) {
     w.res[R_SIZE] = h.total;
     w.res[R_OUTLIERS] = h.n_outliers;
@@ -110,7 +204,11 @@ __global__ void __launch_bounds__(256) k_header(Header h, CompWork w, uint8_t *o
 // One work-group of 256 threads.  Entries in ascending symbol order (as the
 // compressor writes them) are ranked per length with wave ballots; any
 // other order goes through a table of the lengths of all 65536 symbols.
-__global__ void __launch_bounds__(256) k_dectab(const uint32_t *cbk, uint32_t n_sym, DecWork w) {
+__global__ void __launch_bounds__(256) k_dectab(JobTab tb) {
+  const Job &J = *job_of(tb).J;
+  const uint32_t *cbk = (const uint32_t *)(J.src + kHeader);
+  const uint32_t n_sym = J.h.n_sym;
+  const DecWork &w = J.dw;
   __shared__ uint32_t lens4[65536 / 4];       // code length of each symbol, one byte each
   __shared__ uint32_t part[kMaxLen + 1][256];  // per length: symbols before each thread's range
   __shared__ uint32_t wsum[kMaxLen + 1][4];    // per length: symbols in each wave's part
@@ -293,9 +391,11 @@ __global__ void __launch_bounds__(256) k_dectab(const uint32_t *cbk, uint32_t n_
 }
 
 // The block table must add up to the header's counts (u64 totals of the scan).
-__global__ void k_dec_check(const uint64_t *tot, uint64_t payload_words, uint64_t n_outliers, uint64_t n_regression,
-                            uint32_t *err) {
-  if (threadIdx.x == 0 && (tot[0] != payload_words || tot[1] != n_outliers || tot[2] != n_regression)) *err = 1;
+__global__ void __launch_bounds__(64) k_dec_check(JobTab t) {
+  const Job &J = *job_of(t).J;
+  const uint64_t *tot = J.dw.tot;
+  if (threadIdx.x == 0 && (tot[0] != J.h.payload_words || tot[1] != J.h.n_outliers || tot[2] != J.h.n_regression))
+    *J.dw.err = 1;
 }
 
 }  // namespace sdcsz

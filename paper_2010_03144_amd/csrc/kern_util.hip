@@ -15,6 +15,14 @@ __global__ void k_zero_u32(uint32_t *p, uint64_t n) {
     p[i] = 0;
 }
 
+// each job's area that must start at zero (counters, results, histogram, ...)
+__global__ void __launch_bounds__(256) k_zero_jobs(JobTab t) {
+  const JobWg jw = job_of(t);
+  const Job &J = *jw.J;
+  for (uint64_t i = (uint64_t)jw.b * blockDim.x + threadIdx.x; i < J.zero_words; i += (uint64_t)jw.nb * blockDim.x)
+    J.zero[i] = 0;
+}
+
 // ---- value range of the finite values (value-range relative bound) ----------
 template <typename T> __device__ inline void minmax_finite(T v, T &lo, T &hi) {
   const bool f = isfinite(v);
@@ -22,71 +30,12 @@ template <typename T> __device__ inline void minmax_finite(T v, T &lo, T &hi) {
   hi = (f && v > hi) ? v : hi;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kRangeThreads) k_range(const T *__restrict__ in, uint64_t n, double *part) {
-  T lo = (T)INFINITY, hi = (T)-INFINITY;
-  // 16-byte vector loads over the aligned body, scalar loads for the rest
-  constexpr uint32_t V = 16 / sizeof(T);
-  const uint64_t head = (((uintptr_t)in & 15) ? (16 - ((uintptr_t)in & 15)) / sizeof(T) : 0);
-  const uint64_t h = head < n ? head : n;
-  const uint64_t nv = (n - h) / V;
-  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, nth = (uint64_t)gridDim.x * blockDim.x;
-  typedef T vec_t __attribute__((ext_vector_type(V)));
-  const vec_t *vin = (const vec_t *)(in + h);
-  for (uint64_t i = tid; i < nv; i += nth) {
-    const vec_t v = vin[i];
-#pragma unroll
-    for (uint32_t c = 0; c < V; c++) minmax_finite<T>(v[c], lo, hi);
-  }
-  for (uint64_t i = tid; i < h; i += nth) minmax_finite<T>(in[i], lo, hi);
-  for (uint64_t i = h + nv * V + tid; i < n; i += nth) minmax_finite<T>(in[i], lo, hi);
-  __shared__ double slo[kRangeThreads], shi[kRangeThreads];
-  slo[threadIdx.x] = (double)lo;
-  shi[threadIdx.x] = (double)hi;
-  __syncthreads();
-  for (uint32_t s = kRangeThreads / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + s]);
-      shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + s]);
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = slo[0];
-    part[2 * blockIdx.x + 1] = shi[0];
-  }
-}
-template __global__ void k_range<float>(const float *, uint64_t, double *);
-template __global__ void k_range<double>(const double *, uint64_t, double *);
+namespace {
 
-// eb_abs and its derived constants, computed in double then rounded once.
-__global__ void __launch_bounds__(256) k_consts(const double *part, uint32_t nparts, uint32_t mode, double eb,
-                                                 EbDev *out) {
-  // min/max are order-free, so a tree reduction gives the exact extremes
-  __shared__ double slo[256], shi[256];
-  double lo = INFINITY, hi = -INFINITY;
-  if (mode == SDCSZ_REL)
-    for (uint32_t i = threadIdx.x; i < nparts; i += blockDim.x) {
-      lo = fmin(lo, part[2 * i]);
-      hi = fmax(hi, part[2 * i + 1]);
-    }
-  slo[threadIdx.x] = lo;
-  shi[threadIdx.x] = hi;
-  __syncthreads();
-  for (uint32_t s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + s]);
-      shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + s]);
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x != 0) return;
+// eb_abs and its derived constants, computed in double then rounded once
+__device__ void write_consts(uint32_t mode, double eb, double lo, double hi, EbDev *out) {
   double eb_abs = eb;
-  if (mode == SDCSZ_REL) {
-    lo = slo[0];
-    hi = shi[0];
-    eb_abs = lo <= hi ? eb * (hi - lo) : 0.0;
-  }
+  if (mode == SDCSZ_REL) eb_abs = lo <= hi ? eb * (hi - lo) : 0.0;
   EbDev e;
   e.eb_abs = eb_abs;
   e.q = 2.0 * eb_abs;
@@ -107,6 +56,75 @@ __global__ void __launch_bounds__(256) k_consts(const double *part, uint32_t npa
   *out = e;
 }
 
+// min and max over the work-group (order-free, so exact)
+__device__ void wg_minmax(double &lo, double &hi) {
+  __shared__ double slo[kRangeThreads], shi[kRangeThreads];
+  slo[threadIdx.x] = lo;
+  shi[threadIdx.x] = hi;
+  __syncthreads();
+  for (uint32_t s = kRangeThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + s]);
+      shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  lo = slo[0];
+  hi = shi[0];
+  __syncthreads();
+}
+
+}  // namespace
+
+// Value range of the finite values (value-range-relative bound): each job
+// takes J.nparts work-groups, each writing its partial extremes.
+template <typename T> __global__ void __launch_bounds__(kRangeThreads) k_range(JobTab t) {
+  const JobWg jw = job_of(t);
+  const Job &J = *jw.J;
+  const T *in = (const T *)J.src;
+  const uint64_t n = J.eb_mode == SDCSZ_REL ? J.g.n_values : 0;
+  double *part = (double *)J.cw.range_part;
+  T lo = (T)INFINITY, hi = (T)-INFINITY;
+  // 16-byte vector loads over the aligned body, scalar loads for the rest
+  constexpr uint32_t V = 16 / sizeof(T);
+  const uint64_t head = (((uintptr_t)in & 15) ? (16 - ((uintptr_t)in & 15)) / sizeof(T) : 0);
+  const uint64_t h = head < n ? head : n;
+  const uint64_t nv = (n - h) / V;
+  const uint64_t tid = (uint64_t)jw.b * blockDim.x + threadIdx.x, nth = (uint64_t)jw.nb * blockDim.x;
+  typedef T vec_t __attribute__((ext_vector_type(V)));
+  const vec_t *vin = (const vec_t *)(in + h);
+  for (uint64_t i = tid; i < nv; i += nth) {
+    const vec_t v = vin[i];
+#pragma unroll
+    for (uint32_t c = 0; c < V; c++) minmax_finite<T>(v[c], lo, hi);
+  }
+  for (uint64_t i = tid; i < h; i += nth) minmax_finite<T>(in[i], lo, hi);
+  for (uint64_t i = h + nv * V + tid; i < n; i += nth) minmax_finite<T>(in[i], lo, hi);
+  double dlo = (double)lo, dhi = (double)hi;
+  wg_minmax(dlo, dhi);
+  if (threadIdx.x == 0) {
+    part[2 * jw.b] = dlo;
+    part[2 * jw.b + 1] = dhi;
+  }
+}
+template __global__ void k_range<float>(JobTab);
+template __global__ void k_range<double>(JobTab);
+
+// The error-bound constants of each job (one work-group per job) from the
+// partial extremes of its range work-groups (none with an absolute bound).
+__global__ void __launch_bounds__(kRangeThreads) k_consts(JobTab t) {
+  const Job &J = *job_of(t).J;
+  const double *part = (const double *)J.cw.range_part;
+  const uint32_t np = J.eb_mode == SDCSZ_REL && J.g.n_values ? J.nparts : 0u;
+  double dlo = INFINITY, dhi = -INFINITY;
+  for (uint32_t i = threadIdx.x; i < np; i += blockDim.x) {
+    dlo = fmin(dlo, part[2 * i]);
+    dhi = fmax(dhi, part[2 * i + 1]);
+  }
+  wg_minmax(dlo, dhi);
+  if (threadIdx.x == 0) write_consts(J.eb_mode, J.eb, dlo, dhi, J.cw.eb);
+}
+
 // ---- codes at rest: fault injection, then detection/correction + sizing ----
 __global__ void k_code_faults(PlanDev plan, Geo g, uint16_t *codes, unsigned long long *cnt) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -123,8 +141,12 @@ __global__ void k_code_faults(PlanDev plan, Geo g, uint16_t *codes, unsigned lon
 
 // One thread per block: verify/correct the block's codes with sum_q/isum_q
 // (Algorithm 1, before encoding) and size its Huffman payload in words.
-__global__ void __launch_bounds__(256) k_codes_check(Geo g, CompWork w, uint32_t abft) {
-  const uint64_t blk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_codes_check(JobTab t) {
+  const JobWg jw = job_of(t);
+  const Geo &g = jw.J->g;
+  const CompWork &w = jw.J->cw;
+  const uint32_t abft = jw.J->abft;
+  const uint64_t blk = (uint64_t)jw.b * blockDim.x + threadIdx.x;
   if (blk >= g.n_blocks) return;
   const Box b = box_of(g, blk);
   uint16_t *codes = w.codes;
@@ -204,8 +226,17 @@ __device__ Tri block_exclusive(Tri v, Tri *total) {
 }
 }  // namespace
 
-__global__ void __launch_bounds__(kScanThreads) k_scan1(ScanSrc src, uint64_t n, uint64_t *part) {
-  const uint64_t base = (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * kScanItems;
+// Exclusive scans of (payload words, outliers, regression flag) per block:
+// k_scan1 totals per chunk of kScanChunk blocks, k_scan2 (one work-group per
+// job) scans the chunk totals, k_scan3 writes the offsets and the 64-bit
+// totals.  A job without blocks gets zero offsets and totals from k_scan2.
+__global__ void __launch_bounds__(kScanThreads) k_scan1(JobTab t) {
+  const JobWg jw = job_of(t);
+  const ScanSrc src = jw.J->ss;
+  const uint64_t n = jw.J->g.n_blocks;
+  uint64_t *part = jw.J->sc_part;
+  const uint32_t bid = jw.b;
+  const uint64_t base = (uint64_t)bid * kScanChunk + (uint64_t)threadIdx.x * kScanItems;
   Tri s{0, 0, 0};
   for (uint32_t u = 0; u < kScanItems; u++)
     if (base + u < n) {
@@ -217,14 +248,27 @@ __global__ void __launch_bounds__(kScanThreads) k_scan1(ScanSrc src, uint64_t n,
   Tri tot;
   block_exclusive(s, &tot);
   if (threadIdx.x == 0) {
-    part[3 * blockIdx.x] = tot.a;
-    part[3 * blockIdx.x + 1] = tot.b;
-    part[3 * blockIdx.x + 2] = tot.c;
+    part[3 * bid] = tot.a;
+    part[3 * bid + 1] = tot.b;
+    part[3 * bid + 2] = tot.c;
   }
 }
 
-// single work-group: exclusive scan of the chunk totals, in place
-__global__ void __launch_bounds__(kScanThreads) k_scan2(uint64_t *part, uint32_t nparts) {
+// one work-group per job: exclusive scan of the chunk totals, in place
+__global__ void __launch_bounds__(kScanThreads) k_scan2(JobTab t) {
+  const Job &J = *job_of(t).J;
+  const uint64_t nblk = J.g.n_blocks;
+  if (nblk == 0) {
+    if (threadIdx.x == 0) {
+      J.sc_off_pay[0] = 0;
+      J.sc_off_out[0] = 0;
+      J.sc_off_coef[0] = 0;
+      J.sc_tot[0] = J.sc_tot[1] = J.sc_tot[2] = 0;
+    }
+    return;
+  }
+  uint64_t *part = J.sc_part;
+  const uint32_t nparts = (uint32_t)((nblk + kScanChunk - 1) / kScanChunk);
   Tri carry{0, 0, 0};
   for (uint32_t base = 0; base < nparts; base += kScanThreads) {
     uint32_t i = base + threadIdx.x;
@@ -243,10 +287,16 @@ __global__ void __launch_bounds__(kScanThreads) k_scan2(uint64_t *part, uint32_t
   }
 }
 
-__global__ void __launch_bounds__(kScanThreads)
-k_scan3(ScanSrc src, uint64_t n, const uint64_t *part, uint64_t *off_pay, uint32_t *off_out, uint32_t *off_coef,
-        uint64_t *total) {
-  const uint64_t base = (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * kScanItems;
+__global__ void __launch_bounds__(kScanThreads) k_scan3(JobTab t) {
+  const JobWg jw = job_of(t);
+  const Job &J = *jw.J;
+  const ScanSrc src = J.ss;
+  const uint64_t n = J.g.n_blocks;
+  const uint64_t *part = J.sc_part;
+  uint64_t *off_pay = J.sc_off_pay, *total = J.sc_tot;
+  uint32_t *off_out = J.sc_off_out, *off_coef = J.sc_off_coef;
+  const uint32_t bid = jw.b;
+  const uint64_t base = (uint64_t)bid * kScanChunk + (uint64_t)threadIdx.x * kScanItems;
   Tri loc[kScanItems];
   Tri s{0, 0, 0};
   for (uint32_t u = 0; u < kScanItems; u++) {
@@ -257,7 +307,7 @@ k_scan3(ScanSrc src, uint64_t n, const uint64_t *part, uint64_t *off_pay, uint32
   }
   Tri tot;
   Tri ex = block_exclusive(s, &tot);
-  Tri run{part[3 * blockIdx.x] + ex.a, part[3 * blockIdx.x + 1] + ex.b, part[3 * blockIdx.x + 2] + ex.c};
+  Tri run{part[3 * bid] + ex.a, part[3 * bid + 1] + ex.b, part[3 * bid + 2] + ex.c};
   for (uint32_t u = 0; u < kScanItems; u++) {
     if (base + u < n) {
       off_pay[base + u] = run.a;
@@ -279,11 +329,14 @@ k_scan3(ScanSrc src, uint64_t n, const uint64_t *part, uint64_t *off_pay, uint32
 }
 
 // ---- stream assembly: one thread per block ----------------------------------
-template <typename T>
-__global__ void __launch_bounds__(256) k_encode(Geo g, CompWork w, uint8_t *out) {
+template <typename T> __global__ void __launch_bounds__(256) k_encode(JobTab t) {
+  const JobWg jw = job_of(t);
+  const Geo &g = jw.J->g;
+  const CompWork &w = jw.J->cw;
+  uint8_t *out = jw.J->dst;
   if (!w.res[R_WRITTEN]) return;  // the stream is not written (see k_header)
   const Header h = *w.hdr;
-  const uint64_t blk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t blk = (uint64_t)jw.b * blockDim.x + threadIdx.x;
   if (blk >= g.n_blocks) return;
   const Box b = box_of(g, blk);
   uint32_t *dst = (uint32_t *)(out + h.off_payload) + w.off_pay[blk];
@@ -317,7 +370,7 @@ __global__ void __launch_bounds__(256) k_encode(Geo g, CompWork w, uint8_t *out)
   }
   if (h.abft) ((uint64_t *)(out + h.off_sumdc))[blk] = w.sum_dc[blk];
 }
-template __global__ void k_encode<float>(Geo, CompWork, uint8_t *);
-template __global__ void k_encode<double>(Geo, CompWork, uint8_t *);
+template __global__ void k_encode<float>(JobTab);
+template __global__ void k_encode<double>(JobTab);
 
 }  // namespace sdcsz

@@ -19,7 +19,9 @@ TARGETS = ["input", "coef", "code", "recon", "dup_pred", "dup_recon"]
 ERRORS = {OK: "ok", EINVAL: "EINVAL", ENOSPC: "ENOSPC", EFORMAT: "EFORMAT", ESDC: "ESDC", EHIP: "EHIP"}
 FUNCTIONS = ["sdcsz_max_compressed_size", "sdcsz_compress_workspace_size", "sdcsz_compress",
              "sdcsz_stream_info", "sdcsz_decompress_workspace_size", "sdcsz_decompress",
-             "sdcsz_verify", "sdcsz_decompress_region", "sdcsz_strerror", "sdcsz_timing_enable",
+             "sdcsz_verify", "sdcsz_decompress_region", "sdcsz_compress_batch_workspace_size",
+             "sdcsz_compress_batch", "sdcsz_decompress_batch_workspace_size",
+             "sdcsz_decompress_batch", "sdcsz_strerror", "sdcsz_timing_enable",
              "sdcsz_timing_read", "sdcsz_phase_name"]
 N_PHASES = 8
 
@@ -54,6 +56,17 @@ class Report(C.Structure):
                 ("stream_size", C.c_uint64), ("eb_abs", C.c_double)]
 
 
+class CompItem(C.Structure):
+    _fields_ = [("d_in", C.c_void_p), ("params", Params), ("d_out", C.c_void_p),
+                ("out_cap", C.c_uint64), ("out_size", C.c_uint64), ("rc", C.c_int),
+                ("rep", Report)]
+
+
+class DecItem(C.Structure):
+    _fields_ = [("d_stream", C.c_void_p), ("stream_size", C.c_uint64), ("d_out", C.c_void_p),
+                ("out_cap", C.c_uint64), ("rc", C.c_int), ("rep", Report)]
+
+
 _lib = None
 
 
@@ -81,6 +94,12 @@ def lib():
                                    C.c_uint64, vp]
         L.sdcsz_decompress_region.argtypes = [vp, C.c_uint64, P(C.c_uint64), P(C.c_uint64), vp,
                                               C.c_uint64, P(Report), vp, C.c_uint64, vp]
+        L.sdcsz_compress_batch_workspace_size.restype = C.c_uint64
+        L.sdcsz_compress_batch_workspace_size.argtypes = [P(CompItem), C.c_uint32]
+        L.sdcsz_compress_batch.argtypes = [P(CompItem), C.c_uint32, vp, C.c_uint64, vp]
+        L.sdcsz_decompress_batch_workspace_size.restype = C.c_uint64
+        L.sdcsz_decompress_batch_workspace_size.argtypes = [P(Params), C.c_uint32]
+        L.sdcsz_decompress_batch.argtypes = [P(DecItem), C.c_uint32, vp, C.c_uint64, vp]
         L.sdcsz_strerror.restype = C.c_char_p
         L.sdcsz_strerror.argtypes = [C.c_int]
         L.sdcsz_timing_enable.argtypes = [C.c_int]
@@ -144,11 +163,14 @@ class Codec:
         self.torch = torch
         self.device = torch.device(device)
         self._ws = {}
-        self._last = None  # (pointer, size, shape, dtype code, block) of the last stream compressed here
+        # streams this codec wrote into its own buffers: pointer -> (size, shape, dtype, block)
+        self._meta = {}
 
     def workspace(self, nbytes, tag):
         t = self._ws.get(tag)
         if t is None or t.numel() < nbytes:
+            if t is not None:
+                self._meta.pop(t.data_ptr(), None)  # its memory may be reused
             t = self.torch.empty(max(int(nbytes), 256), dtype=self.torch.uint8, device=self.device)
             self._ws[tag] = t
         return t
@@ -175,20 +197,25 @@ class Codec:
                               out.numel(), C.byref(size), C.byref(rep), C.c_void_p(ws.data_ptr()),
                               ws.numel(), _stream_handle(self.device))
         stream = out[: size.value] if rc == OK else None
-        own = out.data_ptr() == self._ws["stream_out"].data_ptr() if "stream_out" in self._ws else False
-        self._last = ((out.data_ptr(), int(size.value), tuple(x.shape), p.dtype,
-                       tuple(int(b) for b in block)) if rc == OK and own else None)
+        self._remember(out, rc, int(size.value), tuple(x.shape), p.dtype, block)
         return rc, stream, report_dict(rep)
+
+    def _remember(self, buf, rc, size, shape, dtype, block):
+        own = any(t.data_ptr() == buf.data_ptr() for t in self._ws.values())
+        if rc == OK and own:
+            self._meta[buf.data_ptr()] = (size, shape, dtype, tuple(int(b) for b in block))
+        else:
+            self._meta.pop(buf.data_ptr(), None)
 
     def _geometry(self, stream):
         """(rc, params, shape) of a stream: from the last compression when the
         stream is that call's output, still in this codec's buffer (only
         compress writes there; the library validates the header anyway),
         else read from the stream's header on the device."""
-        last = self._last
-        if last is not None and last[0] == stream.data_ptr() and last[1] == stream.numel():
-            p = make_params(last[2], last[3] == 0, last[4], 1.0)
-            return OK, p, last[2]
+        m = self._meta.get(stream.data_ptr())
+        if m is not None and m[0] == stream.numel():
+            p = make_params(m[1], m[2] == 0, m[3], 1.0)
+            return OK, p, m[1]
         return self.info(stream)
 
     def info(self, stream):
@@ -245,6 +272,78 @@ class Codec:
                             _stream_handle(self.device))
         del keep
         return rc, report_dict(rep)
+
+    # ------------------------------------------------------------------ batches
+    def compress_batch(self, fields, block, eb, eb_mode="rel", abft=True, predictor="auto",
+                       faults=None, outs=None):
+        """Compress several fields in one call.  Each of `block` (a tuple),
+        `eb`, `eb_mode`, `abft` and `predictor` is one value for every field or
+        a list with one value per field; `faults` is None or a list with one
+        plan (or None) per field.  Returns (rc, [(rc, stream, report)]); the
+        streams are views into `outs` (one buffer per field) or into buffers
+        this codec keeps per batch slot."""
+        torch = self.torch
+        L = lib()
+        n = len(fields)
+        pick = lambda v, i: v[i] if isinstance(v, list) else v
+        items = (CompItem * max(n, 1))()
+        keep = []
+        caps = []
+        for i, x in enumerate(fields):
+            assert x.is_cuda and x.is_contiguous() and x.dtype in (torch.float32, torch.float64)
+            fl = faults[i] if faults is not None else None
+            p = make_params(tuple(x.shape), x.dtype == torch.float32, pick(block, i), pick(eb, i),
+                            pick(eb_mode, i), pick(abft, i), pick(predictor, i), fl)
+            keep.append(p)
+            items[i].d_in = x.data_ptr()
+            items[i].params = p
+            caps.append(L.sdcsz_max_compressed_size(C.byref(p)))
+        bufs = []
+        for i in range(n):
+            if outs is not None:
+                out = outs[i]
+            else:
+                out = self.workspace(caps[i], f"batch_out_{i}")
+            bufs.append(out)
+            items[i].d_out = out.data_ptr()
+            items[i].out_cap = out.numel()
+        ws_n = L.sdcsz_compress_batch_workspace_size(items, n)
+        ws = self.workspace(ws_n, "compress_batch")
+        rc = L.sdcsz_compress_batch(items, n, C.c_void_p(ws.data_ptr()), ws.numel(),
+                                    _stream_handle(self.device))
+        res = []
+        for i in range(n):
+            it = items[i]
+            self._remember(bufs[i], it.rc, int(it.out_size), tuple(fields[i].shape), it.params.dtype,
+                           pick(block, i))
+            res.append((it.rc, bufs[i][: it.out_size] if it.rc == OK else None, report_dict(it.rep)))
+        return rc, res
+
+    def decompress_batch(self, streams, outs=None):
+        """Decompress several streams in one call; returns (rc, [(rc, tensor, report)])."""
+        torch = self.torch
+        L = lib()
+        n = len(streams)
+        items = (DecItem * max(n, 1))()
+        params = (Params * max(n, 1))()
+        outs = list(outs) if outs is not None else [None] * n
+        for i, s in enumerate(streams):
+            rc, p, shape = self._geometry(s)
+            if rc != OK:
+                return rc, None
+            params[i] = p
+            dt = torch.float32 if p.dtype == 0 else torch.float64
+            if outs[i] is None:
+                outs[i] = torch.empty(shape, dtype=dt, device=self.device)
+            items[i].d_stream = s.data_ptr()
+            items[i].stream_size = s.numel()
+            items[i].d_out = outs[i].data_ptr()
+            items[i].out_cap = outs[i].numel() * outs[i].element_size()
+        ws_n = L.sdcsz_decompress_batch_workspace_size(params, n)
+        ws = self.workspace(ws_n, "decompress_batch")
+        rc = L.sdcsz_decompress_batch(items, n, C.c_void_p(ws.data_ptr()), ws.numel(),
+                                      _stream_handle(self.device))
+        return rc, [(items[i].rc, outs[i], report_dict(items[i].rep)) for i in range(n)]
 
     def decompress_region(self, stream, lo, hi):
         torch = self.torch

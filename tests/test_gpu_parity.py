@@ -262,3 +262,55 @@ def test_large_codebooks_decode_like_the_oracle(codec, shape, eb):
     s, rep = check_roundtrip(codec, x, (6, 6, 6), eb)
     n_sym = int(np.frombuffer(s[76:80].tobytes(), "<u4")[0])
     assert n_sym > 8000, n_sym
+
+
+def _config4_like_fields(n, seed):
+    """Fields of uneven shapes, dtypes and bounds, as in a batch of mixed
+    2D/3D outputs (GRF, spectral slope U[-4,-2]); small sizes for the oracle."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        two_d = i % 2 == 1
+        dtype = np.float64 if i % 4 == 3 else np.float32
+        if two_d:
+            shape = tuple(int(v) for v in rng.integers(40, 160, size=2))
+            block = (16, 16)
+        else:
+            shape = tuple(int(v) for v in rng.integers(14, 44, size=3))
+            block = (6, 6, 6)
+        eb = float(10 ** rng.uniform(-5, -2))
+        x = synth.grf_field(shape, seed=int(rng.integers(1 << 30)), slope=float(rng.uniform(-4, -2)),
+                            dtype=dtype)
+        out.append((x, block, eb))
+    return out
+
+
+def test_batch_matches_single_calls_and_oracle(codec):
+    fields = _config4_like_fields(12, seed=4)
+    xs = [torch.from_numpy(x).cuda() for x, _, _ in fields]
+    rc, res = codec.compress_batch(xs, [b for _, b, _ in fields], [e for _, _, e in fields])
+    assert rc == 0, rc
+    for (x, block, eb), (rc_i, s_g, rep_g) in zip(fields, res):
+        print(f"case batch field shape={x.shape} dtype={x.dtype} eb={eb:.3g}", flush=True)
+        assert rc_i == 0
+        rc_r, s_r, rep_r = ref.compress(x, block, eb)
+        s_g = s_g.cpu().numpy()
+        assert np.array_equal(s_r, s_g), first_difference(s_r, s_g)
+        same_counts(rep_r, rep_g)
+    # decompress the whole batch in one call
+    streams = [s for _, s, _ in res]
+    rc, dres = codec.decompress_batch(streams)
+    assert rc == 0, rc
+    for (x, block, eb), (rc_i, y, rep) in zip(fields, dres):
+        assert rc_i == 0
+        rc_r, y_r, _ = ref.decompress(ref.compress(x, block, eb)[1])
+        assert np.array_equal(y_r.view(np.uint8), y.cpu().numpy().view(np.uint8))
+
+
+def test_batch_item_errors_stay_per_item(codec):
+    good = torch.from_numpy(synth.grf_field((20, 20, 20), seed=5)).cuda()
+    rc, res = codec.compress_batch([good, good], [(6, 6, 6), (0, 6, 6)], 1e-3)
+    assert rc == sdcsz.EINVAL
+    assert res[0][0] == 0 and res[1][0] == sdcsz.EINVAL
+    rc_r, s_r, _ = ref.compress(good.cpu().numpy(), (6, 6, 6), 1e-3)
+    assert np.array_equal(res[0][1].cpu().numpy(), s_r)
