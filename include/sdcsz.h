@@ -219,16 +219,20 @@ typedef struct {
   uint64_t stream_size;
   void *d_out;           /* device: n_values * sizeof(dtype) bytes, C order        */
   uint64_t out_cap;
+  const sdcsz_fault *faults;  /* host, n_faults entries (SDCSZ_T_RECON), or NULL   */
+  uint32_t n_faults;
   int rc;                /* out                                                    */
   sdcsz_report rep;      /* out                                                    */
 } sdcsz_dec_item;
 
 /* Device workspace for sdcsz_decompress_batch: the parameters of each stream
- * (from sdcsz_stream_info or the compression call), in item order. */
+ * (from sdcsz_stream_info or the compression call; n_faults = the item's
+ * plan length), in item order. */
 uint64_t sdcsz_decompress_batch_workspace_size(const sdcsz_params *h_params, uint32_t n);
 
 /*
- * Decompress n streams (Algorithm 2 for each; no fault plans).  Returns
+ * Decompress n streams (Algorithm 2 for each, with each item's RECON fault
+ * plan applied as in sdcsz_decompress).  Returns
  * SDCSZ_OK when every stream decoded, else the first failing item's code.
  * Synchronises `stream`.
  */

@@ -1436,6 +1436,8 @@ int sdcsz_decompress_batch(sdcsz_dec_item *h_items, uint32_t n, void *d_ws, uint
     d[i].stream_size = h_items[i].stream_size;
     d[i].d_out = (uint8_t *)h_items[i].d_out;
     d[i].out_cap = h_items[i].out_cap;
+    d[i].faults = h_items[i].faults;
+    d[i].n_faults = h_items[i].n_faults;
   }
   int rc = read_headers(d.data(), n, (uint8_t *)d_ws, ws_size, st);
   if (rc == SDCSZ_OK) rc = decode_batch(d.data(), n, (uint8_t *)d_ws, ws_size, st);

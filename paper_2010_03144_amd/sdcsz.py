@@ -64,7 +64,8 @@ class CompItem(C.Structure):
 
 class DecItem(C.Structure):
     _fields_ = [("d_stream", C.c_void_p), ("stream_size", C.c_uint64), ("d_out", C.c_void_p),
-                ("out_cap", C.c_uint64), ("rc", C.c_int), ("rep", Report)]
+                ("out_cap", C.c_uint64), ("faults", C.POINTER(Fault)), ("n_faults", C.c_uint32),
+                ("rc", C.c_int), ("rep", Report)]
 
 
 _lib = None
@@ -319,18 +320,25 @@ class Codec:
             res.append((it.rc, bufs[i][: it.out_size] if it.rc == OK else None, report_dict(it.rep)))
         return rc, res
 
-    def decompress_batch(self, streams, outs=None):
-        """Decompress several streams in one call; returns (rc, [(rc, tensor, report)])."""
+    def decompress_batch(self, streams, outs=None, faults=None):
+        """Decompress several streams in one call (faults: None or one RECON
+        plan or None per stream); returns (rc, [(rc, tensor, report)])."""
         torch = self.torch
         L = lib()
         n = len(streams)
         items = (DecItem * max(n, 1))()
         params = (Params * max(n, 1))()
         outs = list(outs) if outs is not None else [None] * n
+        keep = []
         for i, s in enumerate(streams):
             rc, p, shape = self._geometry(s)
             if rc != OK:
                 return rc, None
+            fptr, nf, k = _faults(faults[i] if faults is not None else None)
+            keep.append(k)
+            items[i].faults = fptr
+            items[i].n_faults = nf
+            p.n_faults = nf
             params[i] = p
             dt = torch.float32 if p.dtype == 0 else torch.float64
             if outs[i] is None:

@@ -166,3 +166,92 @@ def fault_plan(shape, block, dtype, counts, seed=3):
             bit = int(rng.integers(0, 32 * per if name.startswith("dup") else 32))
             rows.append((tid, bit, blk, word))
     return np.array(rows, dtype=np.int64)
+
+
+# ---------------------------------------------------------------------------
+# Mixed-field workloads (many fields of uneven shapes, dtypes and bounds)
+# ---------------------------------------------------------------------------
+SLOPES = (-2.0, -2.5, -3.0, -3.5, -4.0)
+
+
+class FieldPool:
+    """Base volumes of Gaussian random fields, one per spectral slope in
+    SLOPES (3D and 2D), from which fields of any shape up to the base shape
+    are cut.  A crop of a stationary random field is a field of the same
+    spectrum, so many fields of uneven shapes cost a handful of FFTs."""
+
+    def __init__(self, shape3=(384, 384, 256), shape2=(4096, 4096), seed=40):
+        self.shape3, self.shape2 = tuple(shape3), tuple(shape2)
+        self.seed = seed
+        self._v = {}
+
+    def base(self, nd, slope_idx):
+        key = (nd, slope_idx)
+        if key not in self._v:
+            shape = self.shape3 if nd == 3 else self.shape2
+            self._v[key] = grf_field(shape, seed=self.seed + 10 * nd + slope_idx,
+                                     slope=SLOPES[slope_idx], front=False, dtype=np.float64)
+        return self._v[key]
+
+    def field(self, shape, slope_idx, dtype, rng):
+        b = self.base(len(shape), slope_idx)
+        lo = [int(rng.integers(0, b.shape[a] - shape[a] + 1)) for a in range(len(shape))]
+        sl = tuple(slice(l, l + n) for l, n in zip(lo, shape))
+        return np.ascontiguousarray(b[sl]).astype(dtype)
+
+
+def log_uniform_int(rng, lo, hi):
+    return int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+
+
+def batch_specs(n=192, seed=4, frac_2d=0.5, frac_f64=0.25, shape3_hi=(384, 384, 256), shape2_hi=4096):
+    """Field descriptions of a mixed batch: 3D shapes log-uniform per axis in
+    [32, 384] x [32, 384] x [32, 256] with 6x6x6 blocks, 2D shapes in
+    [256, 4096]^2 with 16x16 blocks, FP64 with probability frac_f64, spectral
+    slope index uniform over SLOPES, value-range-relative bound log-uniform in
+    [1e-5, 1e-2].  Returns a list of dicts (shape, block, dtype, slope, eb)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        if rng.uniform() < frac_2d:
+            shape = tuple(log_uniform_int(rng, 256, shape2_hi) for _ in range(2))
+            block = (16, 16)
+        else:
+            shape = (log_uniform_int(rng, 32, shape3_hi[0]), log_uniform_int(rng, 32, shape3_hi[1]),
+                     log_uniform_int(rng, 32, shape3_hi[2]))
+            block = (6, 6, 6)
+        dtype = np.float64 if rng.uniform() < frac_f64 else np.float32
+        out.append({"shape": shape, "block": block, "dtype": dtype,
+                    "slope": int(rng.integers(len(SLOPES))),
+                    "eb": float(math.exp(rng.uniform(math.log(1e-5), math.log(1e-2))))})
+    return out
+
+
+def batch_fields(specs, pool, seed=5):
+    rng = np.random.default_rng(seed)
+    return [pool.field(s["shape"], s["slope"], s["dtype"], rng) for s in specs]
+
+
+def request_stream(rate=200.0, duration=60.0, seed=5, size_lo=1 << 20, size_hi=1 << 30,
+                   frac_decompress=0.5, frac_f64=0.25, frac_faults=0.2):
+    """Poisson arrivals of compress/decompress requests: arrival time,
+    kind, value bytes (log-uniform in [size_lo, size_hi]), dtype, bound
+    (log-uniform in [1e-5, 1e-2]) and whether the request carries a fault
+    plan.  Shapes are 3D with 6x6x6 blocks, the axes as equal as the size
+    allows."""
+    rng = np.random.default_rng(seed)
+    t, out = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            break
+        dtype = np.float64 if rng.uniform() < frac_f64 else np.float32
+        nbytes = math.exp(rng.uniform(math.log(size_lo), math.log(size_hi)))
+        nvals = max(216, int(nbytes / np.dtype(dtype).itemsize))
+        e = max(6, int(round(nvals ** (1.0 / 3.0))))
+        shape = (e, e, max(6, nvals // (e * e)))
+        out.append({"t": t, "kind": "decompress" if rng.uniform() < frac_decompress else "compress",
+                    "shape": shape, "dtype": dtype,
+                    "eb": float(math.exp(rng.uniform(math.log(1e-5), math.log(1e-2)))),
+                    "faults": bool(rng.uniform() < frac_faults), "seed": int(rng.integers(1 << 30))})
+    return out
