@@ -281,13 +281,31 @@ DecLayout dec_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
   return L;
 }
 
-// Specialised kernel for this block shape, if there is one.  Its lanes
-// address the input with 32-bit byte offsets from the wave's lowest block,
-// so it takes fields below 2 GiB.
-bool fast_shape(const Geo &g, uint32_t vb) {
-  if (!(g.ndim == 3 && g.b[0] == 6 && g.b[1] == 6 && g.b[2] == 6)) return false;
-  return g.n_values * vb < (1ull << 31);
+// Block shapes with specialised kernels (one lane per block): class 0 is
+// 6x6x6 in 3D, class 1 is 16x16 in 2D.  Their lanes address the field with
+// 32-bit byte offsets from the wave's lowest block, so they take fields
+// below 2 GiB.  Returns -1 for the generic kernels.
+constexpr int kClasses = 2;
+int fast_class(const Geo &g, uint32_t vb) {
+  if (!g.n_blocks || g.n_values * vb >= (1ull << 31)) return -1;
+  if (g.ndim == 3 && g.b[0] == 6 && g.b[1] == 6 && g.b[2] == 6) return 0;
+  if (g.ndim == 2 && g.b[1] == 16 && g.b[2] == 16) return 1;
+  return -1;
 }
+
+using JobKernel = void (*)(JobTab);
+// [class][dtype][abft]
+const JobKernel kCompFast[kClasses][2][2] = {
+    {{k_compress_fast<float, 3, 6, 6, 6, false>, k_compress_fast<float, 3, 6, 6, 6, true>},
+     {k_compress_fast<double, 3, 6, 6, 6, false>, k_compress_fast<double, 3, 6, 6, 6, true>}},
+    {{k_compress_fast<float, 2, 1, 16, 16, false>, k_compress_fast<float, 2, 1, 16, 16, true>},
+     {k_compress_fast<double, 2, 1, 16, 16, false>, k_compress_fast<double, 2, 1, 16, 16, true>}}};
+const JobKernel kCheckFast[kClasses] = {k_check_fast<3, 6, 6, 6>, k_check_fast<2, 1, 16, 16>};
+// [class][dtype]
+const JobKernel kEncFast[kClasses][2] = {{k_encode_fast<float, 3, 6, 6, 6>, k_encode_fast<double, 3, 6, 6, 6>},
+                                         {k_encode_fast<float, 2, 1, 16, 16>, k_encode_fast<double, 2, 1, 16, 16>}};
+const JobKernel kDecFast[kClasses][2] = {{k_decode_fast<float, 3, 6, 6, 6>, k_decode_fast<double, 3, 6, 6, 6>},
+                                         {k_decode_fast<float, 2, 1, 16, 16>, k_decode_fast<double, 2, 1, 16, 16>}};
 
 // One launch of a specialised kernel: the first work-groups take the
 // sub-grid of full blocks, the others the shell of partial blocks along the
@@ -520,6 +538,7 @@ struct CompPlan {  // host state of one field
   CompLayout L;
   uint8_t *ws;
   bool fast;
+  int cls;  // shape class of the specialised kernels, -1 for generic
   std::vector<sdcsz_fault> plan;
   std::vector<uint32_t> bits;
   std::vector<uint64_t> pb;
@@ -591,7 +610,8 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     if (!c.rc) c.rc = check_plan(f.g, c.p->dtype, c.p->faults, c.p->n_faults, false, f.plan);
     if (c.rc) continue;
     f.L = comp_layout(f.g, c.p->dtype, c.p->n_faults);
-    f.fast = f.g.n_blocks && fast_shape(f.g, vbytes(c.p->dtype));
+    f.cls = fast_class(f.g, vbytes(c.p->dtype));
+    f.fast = f.cls >= 0;
     f.pb = plan_block_list(f.plan);
     f.any_code = false;
     for (auto &e : f.plan) f.any_code |= e.target == SDCSZ_T_CODE;
@@ -697,7 +717,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   }
   // ---- stage A tables: zero, range + constants, prediction/quantization,
   // re-runs, histogram compaction
-  Tab t_zero, t_range[2], t_fast[2][2], t_gen[2], t_redo[2], t_hist, t_hchunk;  // t_hist: one work-group per job
+  Tab t_zero, t_range[2], t_fast[kClasses][2][2], t_gen[2], t_redo[2], t_hist, t_hchunk;  // t_hist: one work-group per job
   for (uint32_t j = 0; j < nj; j++) {
     const Job &J = jobs[j];
     const CompPlan &f = fp[j];
@@ -705,7 +725,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     if (J.eb_mode == SDCSZ_REL && f.g.n_values) t_range[J.dtype].add(j, J.nparts);
     if (f.fast) {
       Launch L;
-      t_fast[J.dtype][J.abft].add(j, fast_launch(f.g, &L));
+      t_fast[f.cls][J.dtype][J.abft ? 1 : 0].add(j, fast_launch(f.g, &L));
       t_redo[J.dtype].add(j, 1);
     } else if (f.g.n_blocks) {
       t_gen[J.dtype].add(j, grid_for(f.g.n_blocks, 64));
@@ -714,19 +734,21 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     t_hchunk.add(j, kHistChunks);
   }
   Upload up;
-  up.tabs = {&t_zero, &t_range[0], &t_range[1], &t_fast[0][0], &t_fast[0][1], &t_fast[1][0], &t_fast[1][1],
-             &t_gen[0], &t_gen[1], &t_redo[0], &t_redo[1], &t_hist, &t_hchunk};
+  up.tabs = {&t_zero, &t_range[0], &t_range[1], &t_gen[0], &t_gen[1], &t_redo[0], &t_redo[1], &t_hist, &t_hchunk};
+  for (int c = 0; c < kClasses; c++)
+    for (int d = 0; d < 2; d++)
+      for (int a = 0; a < 2; a++) up.tabs.push_back(&t_fast[c][d][a]);
   uint8_t *hs = t_stage.get(std::max<size_t>(up.bytes(nj), 4 * nj + 8 + 8 * kPairPrefix + 64));
   if (!hs) return SDCSZ_EHIP;
   up.place(jobs, hs, ws + B.jobs);
   HIPCHK(hipMemcpyAsync(ws + B.jobs, hs, up.bytes(nj), hipMemcpyHostToDevice, st));
   const JobTab &d_zero = up.dev[0];
   const JobTab *d_range = &up.dev[1];
-  const JobTab d_fast[2][2] = {{up.dev[3], up.dev[4]}, {up.dev[5], up.dev[6]}};
-  const JobTab *d_gen = &up.dev[7];
-  const JobTab *d_redo = &up.dev[9];
-  const JobTab &d_hist = up.dev[11];
-  const JobTab &d_hchunk = up.dev[12];
+  const JobTab *d_gen = &up.dev[3];
+  const JobTab *d_redo = &up.dev[5];
+  const JobTab &d_hist = up.dev[7];
+  const JobTab &d_hchunk = up.dev[8];
+  const JobTab *d_fast = &up.dev[9];  // [class][dtype][abft] in that order
   auto grid = [](const Tab &t) { return dim3(t.total()); };
   launch(PH_NONE, false, false, k_zero_jobs, grid(t_zero), dim3(256), st, d_zero);
   {
@@ -753,14 +775,15 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   }
   {
     PhaseLaunch pl{PH_PREDICT, {}};
-    if (t_fast[0][1].total())
-      pl.fs.push_back([&](bool a, bool b) { launch(PH_PREDICT, a, b, k_compress_fast<float, 3, 6, 6, 6, true>, grid(t_fast[0][1]), dim3(256), st, d_fast[0][1]); });
-    if (t_fast[0][0].total())
-      pl.fs.push_back([&](bool a, bool b) { launch(PH_PREDICT, a, b, k_compress_fast<float, 3, 6, 6, 6, false>, grid(t_fast[0][0]), dim3(256), st, d_fast[0][0]); });
-    if (t_fast[1][1].total())
-      pl.fs.push_back([&](bool a, bool b) { launch(PH_PREDICT, a, b, k_compress_fast<double, 3, 6, 6, 6, true>, grid(t_fast[1][1]), dim3(256), st, d_fast[1][1]); });
-    if (t_fast[1][0].total())
-      pl.fs.push_back([&](bool a, bool b) { launch(PH_PREDICT, a, b, k_compress_fast<double, 3, 6, 6, 6, false>, grid(t_fast[1][0]), dim3(256), st, d_fast[1][0]); });
+    for (int c = 0; c < kClasses; c++)
+      for (int d = 0; d < 2; d++)
+        for (int a = 1; a >= 0; a--) {
+          const Tab &t = t_fast[c][d][a];
+          if (!t.total()) continue;
+          const JobTab jt = d_fast[(c * 2 + d) * 2 + a];
+          const JobKernel k = kCompFast[c][d][a];
+          pl.fs.push_back([&t, jt, k, st, &grid](bool x, bool y) { launch(PH_PREDICT, x, y, k, grid(t), dim3(256), st, jt); });
+        }
     if (t_gen[0].total())
       pl.fs.push_back([&](bool a, bool b) { launch(PH_PREDICT, a, b, k_compress_generic<float>, grid(t_gen[0]), dim3(64), st, d_gen[0]); });
     if (t_gen[1].total())
@@ -822,14 +845,14 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     off += cnt_sym[j];
   }
   build_codebooks(cj);
-  Tab t_put, t_chk_fast, t_chk_gen, t_s1, t_s2, t_hdr, t_enc_fast[2], t_enc_gen[2], t_res;
+  Tab t_put, t_chk_fast[kClasses], t_chk_gen, t_s1, t_s2, t_hdr, t_enc_fast[kClasses][2], t_enc_gen[2], t_res;
   for (uint32_t j = 0; j < nj; j++) {
     const Job &J = jobs[j];
     const CompPlan &f = fp[j];
     if (J.n_sym) t_put.add(j, grid_for(J.n_sym, 256));
     if (f.fast) {
-      t_chk_fast.add(j, grid_for(f.g.n_blocks, 256));
-      t_enc_fast[J.dtype].add(j, grid_for(f.g.n_blocks, 256));
+      t_chk_fast[f.cls].add(j, grid_for(f.g.n_blocks, 256));
+      t_enc_fast[f.cls][J.dtype].add(j, grid_for(f.g.n_blocks, 256));
     } else if (f.g.n_blocks) {
       t_chk_gen.add(j, grid_for(f.g.n_blocks, 256));
       t_enc_gen[J.dtype].add(j, grid_for(f.g.n_blocks, 256));
@@ -840,39 +863,51 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     t_res.add(j, 1);
   }
   Upload ub;
-  ub.tabs = {&t_put, &t_chk_fast, &t_chk_gen, &t_s1, &t_s2, &t_hdr, &t_enc_fast[0], &t_enc_fast[1],
-             &t_enc_gen[0], &t_enc_gen[1], &t_res};
+  ub.tabs = {&t_put, &t_chk_gen, &t_s1, &t_s2, &t_hdr, &t_enc_gen[0], &t_enc_gen[1], &t_res};
+  for (int c = 0; c < kClasses; c++) {
+    ub.tabs.push_back(&t_chk_fast[c]);
+    for (int d = 0; d < 2; d++) ub.tabs.push_back(&t_enc_fast[c][d]);
+  }
   ub.place(jobs, hs, ws + B.jobs);
   HIPCHK(hipMemcpyAsync(ws + B.jobs, hs, JR + 8 * total_pairs, hipMemcpyHostToDevice, st));
   const std::vector<JobTab> &D = ub.dev;
   if (t_put.total()) launch(PH_NONE, false, false, k_put_codes, grid(t_put), dim3(256), st, D[0]);
   {
     PhaseLaunch pl{PH_CHECK, {}};
-    if (t_chk_fast.total())
-      pl.fs.push_back([&](bool a, bool b) { launch(PH_CHECK, a, b, k_check_fast<6, 6, 6>, grid(t_chk_fast), dim3(256), st, D[1]); });
+    for (int c = 0; c < kClasses; c++) {
+      const Tab &t = t_chk_fast[c];
+      if (!t.total()) continue;
+      const JobTab jt = D[8 + 3 * c];
+      const JobKernel k = kCheckFast[c];
+      pl.fs.push_back([&t, jt, k, st, &grid](bool x, bool y) { launch(PH_CHECK, x, y, k, grid(t), dim3(256), st, jt); });
+    }
     if (t_chk_gen.total())
-      pl.fs.push_back([&](bool a, bool b) { launch(PH_CHECK, a, b, k_codes_check, grid(t_chk_gen), dim3(256), st, D[2]); });
+      pl.fs.push_back([&](bool a, bool b) { launch(PH_CHECK, a, b, k_codes_check, grid(t_chk_gen), dim3(256), st, D[1]); });
     pl.run();
   }
-  if (t_s1.total()) launch(PH_SCAN_C, true, false, k_scan1, grid(t_s1), dim3(kScanThreads), st, D[3]);
-  launch(PH_SCAN_C, !t_s1.total(), !t_s1.total(), k_scan2, grid(t_s2), dim3(kScanThreads), st, D[4]);
-  if (t_s1.total()) launch(PH_SCAN_C, false, true, k_scan3, grid(t_s1), dim3(kScanThreads), st, D[3]);
-  launch(PH_NONE, false, false, k_header, grid(t_hdr), dim3(256), st, D[5]);
+  if (t_s1.total()) launch(PH_SCAN_C, true, false, k_scan1, grid(t_s1), dim3(kScanThreads), st, D[2]);
+  launch(PH_SCAN_C, !t_s1.total(), !t_s1.total(), k_scan2, grid(t_s2), dim3(kScanThreads), st, D[3]);
+  if (t_s1.total()) launch(PH_SCAN_C, false, true, k_scan3, grid(t_s1), dim3(kScanThreads), st, D[2]);
+  launch(PH_NONE, false, false, k_header, grid(t_hdr), dim3(256), st, D[4]);
   {
     PhaseLaunch pl{PH_ENCODE, {}};
-    if (t_enc_fast[0].total())
-      pl.fs.push_back([&](bool a, bool b) { launch(PH_ENCODE, a, b, k_encode_fast<float, 6, 6, 6>, grid(t_enc_fast[0]), dim3(256), st, D[6]); });
-    if (t_enc_fast[1].total())
-      pl.fs.push_back([&](bool a, bool b) { launch(PH_ENCODE, a, b, k_encode_fast<double, 6, 6, 6>, grid(t_enc_fast[1]), dim3(256), st, D[7]); });
+    for (int c = 0; c < kClasses; c++)
+      for (int d = 0; d < 2; d++) {
+        const Tab &t = t_enc_fast[c][d];
+        if (!t.total()) continue;
+        const JobTab jt = D[8 + 3 * c + 1 + d];
+        const JobKernel k = kEncFast[c][d];
+        pl.fs.push_back([&t, jt, k, st, &grid](bool x, bool y) { launch(PH_ENCODE, x, y, k, grid(t), dim3(256), st, jt); });
+      }
     if (t_enc_gen[0].total())
-      pl.fs.push_back([&](bool a, bool b) { launch(PH_ENCODE, a, b, k_encode<float>, grid(t_enc_gen[0]), dim3(256), st, D[8]); });
+      pl.fs.push_back([&](bool a, bool b) { launch(PH_ENCODE, a, b, k_encode<float>, grid(t_enc_gen[0]), dim3(256), st, D[5]); });
     if (t_enc_gen[1].total())
-      pl.fs.push_back([&](bool a, bool b) { launch(PH_ENCODE, a, b, k_encode<double>, grid(t_enc_gen[1]), dim3(256), st, D[9]); });
+      pl.fs.push_back([&](bool a, bool b) { launch(PH_ENCODE, a, b, k_encode<double>, grid(t_enc_gen[1]), dim3(256), st, D[6]); });
     pl.run();
   }
   const uint64_t *d_res = (const uint64_t *)(ws + B.res);
   if (nj == 1) d_res = jobs[0].stat;  // one field: no gather needed
-  else launch(PH_NONE, false, false, k_results, grid(t_res), dim3(64), st, D[10], (uint64_t *)d_res,
+  else launch(PH_NONE, false, false, k_results, grid(t_res), dim3(64), st, D[7], (uint64_t *)d_res,
               (uint32_t)(C_N + R_N));
   HIPCHK(hipGetLastError());
   uint64_t *hres = (uint64_t *)(hs + at_res);
@@ -929,6 +964,7 @@ struct DecPlan {
   DecLayout L;
   uint8_t *ws;
   bool fast;
+  int cls;
   std::vector<sdcsz_fault> plan;
   std::vector<uint32_t> bits;
   std::vector<uint64_t> pb;
@@ -1016,7 +1052,8 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     d.rc = check_plan(d.g, d.h.dtype, d.faults, d.n_faults, true, f.plan);
     if (d.rc) continue;
     f.L = dec_layout(d.g, d.h.dtype, d.n_faults);
-    f.fast = d.mode == 0 && d.g.n_blocks && fast_shape(d.g, vbytes(d.h.dtype));
+    f.cls = d.mode == 0 ? fast_class(d.g, vbytes(d.h.dtype)) : -1;
+    f.fast = f.cls >= 0;
     f.pb = f.fast ? plan_block_list(f.plan) : std::vector<uint64_t>();
     per += f.L.total;
     fp.push_back(std::move(f));
@@ -1087,7 +1124,7 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
         HIPCHK(hipMemcpyAsync(w + f.L.plan_blocks, f.pb.data(), 8 * f.pb.size(), hipMemcpyHostToDevice, st));
     }
   }
-  Tab t_zero, t_one, t_s1, t_fast[2], t_gen[2], t_redo[2];
+  Tab t_zero, t_one, t_s1, t_fast[kClasses][2], t_gen[2], t_redo[2];
   for (uint32_t j = 0; j < nj; j++) {
     const Job &J = jobs[j];
     t_zero.add(j, 1);
@@ -1095,14 +1132,16 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     t_s1.add(j, scan_chunks(J.g.n_blocks));
     if (fp[j].fast) {
       Launch L;
-      t_fast[J.dtype].add(j, fast_launch(J.g, &L));
+      t_fast[fp[j].cls][J.dtype].add(j, fast_launch(J.g, &L));
       t_redo[J.dtype].add(j, kMaxRedo / 64);  // one thread per queue slot
     } else if (J.g.n_blocks) {
       t_gen[J.dtype].add(j, grid_for(J.g.n_blocks, 64));
     }
   }
   Upload up;
-  up.tabs = {&t_zero, &t_one, &t_s1, &t_fast[0], &t_fast[1], &t_gen[0], &t_gen[1], &t_redo[0], &t_redo[1]};
+  up.tabs = {&t_zero, &t_one, &t_s1, &t_gen[0], &t_gen[1], &t_redo[0], &t_redo[1]};
+  for (int c = 0; c < kClasses; c++)
+    for (int d = 0; d < 2; d++) up.tabs.push_back(&t_fast[c][d]);
   const size_t res_bytes = 8ull * (C_N + 1) * nj;
   uint8_t *hs = t_stage.get(up.bytes(nj) + res_bytes + 4096);
   if (!hs) return SDCSZ_EHIP;
@@ -1131,18 +1170,22 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
   }
   {
     PhaseLaunch pl{PH_DECODE, {}};
-    if (t_fast[0].total())
-      pl.fs.push_back([&](bool a, bool b) { launch(PH_DECODE, a, b, k_decode_fast<float, 3, 6, 6, 6>, grid(t_fast[0]), dim3(256), st, D[3]); });
-    if (t_fast[1].total())
-      pl.fs.push_back([&](bool a, bool b) { launch(PH_DECODE, a, b, k_decode_fast<double, 3, 6, 6, 6>, grid(t_fast[1]), dim3(256), st, D[4]); });
+    for (int c = 0; c < kClasses; c++)
+      for (int d = 0; d < 2; d++) {
+        const Tab &t = t_fast[c][d];
+        if (!t.total()) continue;
+        const JobTab jt = D[7 + 2 * c + d];
+        const JobKernel k = kDecFast[c][d];
+        pl.fs.push_back([&t, jt, k, st, &grid](bool x, bool y) { launch(PH_DECODE, x, y, k, grid(t), dim3(256), st, jt); });
+      }
     if (t_gen[0].total())
-      pl.fs.push_back([&](bool a, bool b) { launch(PH_DECODE, a, b, k_decode_generic<float>, grid(t_gen[0]), dim3(64), st, D[5]); });
+      pl.fs.push_back([&](bool a, bool b) { launch(PH_DECODE, a, b, k_decode_generic<float>, grid(t_gen[0]), dim3(64), st, D[3]); });
     if (t_gen[1].total())
-      pl.fs.push_back([&](bool a, bool b) { launch(PH_DECODE, a, b, k_decode_generic<double>, grid(t_gen[1]), dim3(64), st, D[6]); });
+      pl.fs.push_back([&](bool a, bool b) { launch(PH_DECODE, a, b, k_decode_generic<double>, grid(t_gen[1]), dim3(64), st, D[4]); });
     pl.run();
   }
-  if (t_redo[0].total()) launch(PH_NONE, false, false, k_decode_redo<float>, grid(t_redo[0]), dim3(64), st, D[7]);
-  if (t_redo[1].total()) launch(PH_NONE, false, false, k_decode_redo<double>, grid(t_redo[1]), dim3(64), st, D[8]);
+  if (t_redo[0].total()) launch(PH_NONE, false, false, k_decode_redo<float>, grid(t_redo[0]), dim3(64), st, D[5]);
+  if (t_redo[1].total()) launch(PH_NONE, false, false, k_decode_redo<double>, grid(t_redo[1]), dim3(64), st, D[6]);
   const uint64_t *d_res = (const uint64_t *)(ws + a256(up.bytes(nj)));
   if (nj == 1) d_res = jobs[0].stat;  // one stream: no gather needed
   else launch(PH_NONE, false, false, k_results, grid(t_one), dim3(64), st, D[1], (uint64_t *)d_res,

@@ -128,8 +128,8 @@ __global__ void k_decode_list(const uint8_t *s, Header h, Geo g, DecWork w, Plan
                               const uint64_t *list, uint32_t n);
 template <typename T> __global__ void k_decode_redo(JobTab t);
 
-template <int B0, int B1, int B2> __global__ void k_check_fast(JobTab t);
-template <typename T, int B0, int B1, int B2> __global__ void k_encode_fast(JobTab t);
+template <int ND, int B0, int B1, int B2> __global__ void k_check_fast(JobTab t);
+template <typename T, int ND, int B0, int B1, int B2> __global__ void k_encode_fast(JobTab t);
 
 template <typename T> __global__ void k_compress_generic(JobTab t);
 template <typename T> __global__ void k_decode_generic(JobTab t);

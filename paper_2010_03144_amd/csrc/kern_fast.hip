@@ -454,6 +454,275 @@ __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const G
   }
 }
 
+// One lane's 2D block of B1 rows by B2 columns (the geometry's slowest axis
+// has extent 1).  The same arithmetic as compress_lanes with ND == 2, but the
+// block streams through registers a row at a time: rows are loaded one ahead
+// in the first pass and two ahead in the prediction pass, which keeps the
+// previous reconstructed row only, so a 16x16 block needs no more registers
+// than a 6x6x6 one.
+template <typename T, int B1, int B2, bool FULL, bool ABFT>
+__device__ __forceinline__ void compress_rows(const T *__restrict__ in, const Geo &g, const RegTab<T> &rt,
+                                              const PlanDev &plan, const CompWork &w, uint32_t predictor,
+                                              const Launch &L, uint32_t *hist, uint32_t &hot, uint64_t idx,
+                                              uint64_t nlanes) {
+  static_assert(B2 % 4 == 0, "a row must fill whole 4-code groups");
+  // FP32 keeps the sampled values in registers; FP64 reads them again
+  // (from cache) for the regression cost
+  constexpr int NS = sizeof(T) == 4 ? sample_slot<2, 1, B1, B2>(1, 0, 0) : 0;
+  bool active = idx < nlanes;
+  const uint64_t blk = map_block(g, L, FULL ? 0u : 1u, active ? idx : nlanes - 1);
+  const Box bx = box_of(g, blk);
+  const uint64_t org = fidx(g, bx, 0, 0, 0);
+  uint64_t omin = org;
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)omin, off);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(omin >> 32), off);
+    const uint64_t o = ((uint64_t)hi << 32) | lo;
+    omin = o < omin ? o : omin;
+  }
+  const uint64_t org0 = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(omin >> 32)) << 32) |
+                        (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)omin);
+  const char *wbase = (const char *)(in + org0);
+  const uint32_t loff = (uint32_t)((org - org0) * sizeof(T));
+  if (active && plan_hit(plan, blk)) active = false;  // done by k_compress_list
+  if (!active) return;
+  const EbDev eb = *w.eb;
+  const T q = EbSel<T>::q(eb), inv = EbSel<T>::inv(eb), inv_e = EbSel<T>::inv_e(eb);
+  const uint32_t n1 = FULL ? B1 : bx.n[1], n2 = FULL ? B2 : bx.n[2];
+  const uint32_t pat = FULL ? 0 : bx.pat;
+  const T c0 = rt.c[pat][0], c1 = rt.c[pat][1], c2 = rt.c[pat][2];
+  const uint32_t RSB = (uint32_t)(g.d[2] * sizeof(T));
+  auto valid = [&](int j, int k) -> bool { return FULL || ((uint32_t)j < n1 && (uint32_t)k < n2); };
+  auto ld = [&](int j, int k) -> T {
+    if (FULL) return *(const T *)(wbase + (loff + (uint32_t)j * RSB) + k * sizeof(T));
+    const uint32_t jj = min((uint32_t)j, n1 - 1), kk = min((uint32_t)k, n2 - 1);
+    const T v = *(const T *)(wbase + (loff + jj * RSB + kk * (uint32_t)sizeof(T)));
+    return valid(j, k) ? v : (T)0;
+  };
+
+  // ---- first pass: input checksums, regression sums, Lorenzo costs --------
+  T xc[B2], xn[B2], xp[B2];  // rows j, j + 1 (in flight) and j - 1
+  T sx[NS > 0 ? NS : 1];
+  T D[B2];
+  uint32_t S1 = 0, Q1 = 0, e_lor = 0;
+  T P = 0, A = 0;
+#pragma unroll
+  for (int k = 0; k < B2; k++) {
+    xc[k] = ld(0, k);
+    xp[k] = 0;
+    D[k] = 0;
+  }
+#pragma unroll
+  for (int j = 0; j < B1; j++) {
+    if (j + 1 < B1) {
+#pragma unroll
+      for (int k = 0; k < B2; k++) xn[k] = ld(j + 1, k);
+    }
+    T R = 0;
+#pragma unroll
+    for (int k = 0; k < B2; k++) {
+      if (valid(j, k)) {
+        if (ABFT) Ck<T>::add(xc[k], S1, Q1);
+        R = R + xc[k];
+        D[k] = D[k] + xc[k];
+      }
+      if (is_sample<2, 1, B1, B2>(0, j, k)) {
+        // Lorenzo on the original values (zero outside the block)
+        const T up = j > 0 ? xp[k] : (T)0, left = k > 0 ? xc[k - 1] : (T)0;
+        const T diag = (j > 0 && k > 0) ? xp[k - 1] : (T)0;
+        const T pl = (up + left) - diag;
+        if (NS > 0) sx[sample_slot<2, 1, B1, B2>(0, j, k)] = xc[k];
+        if (valid(j, k)) e_lor += cost<T>(xc[k] - pl, inv_e) + 1u;
+      }
+    }
+    if (valid(j, 0)) {
+      P = P + R;
+      A = A + ((T)j - c1) * R;
+    }
+    row_fence(P, A, S1, Q1, e_lor);
+#pragma unroll
+    for (int k = 0; k < B2; k++) {
+      pin(D[k]);
+      xp[k] = xc[k];
+      xc[k] = xn[k];
+    }
+  }
+  T Bv = 0;
+#pragma unroll
+  for (int k = 0; k < B2; k++)
+    if (valid(0, k)) Bv = Bv + ((T)k - c2) * D[k];
+  // the slowest axis has one plane: its sums start from zero like the
+  // paper-order routine's
+  const T S0 = (T)0 + P, Sa1 = (T)0 + A, Sa2 = (T)0 + Bv;
+  T beta0 = 0;
+  T beta1 = n1 > 1 ? Sa1 * rt.K[pat][1] : (T)0;
+  T beta2 = n2 > 1 ? Sa2 * rt.K[pat][2] : (T)0;
+  T mu = S0 * rt.inv_pts[pat];
+
+  bool is_reg;
+  if (predictor == SDCSZ_PRED_LORENZO) is_reg = false;
+  else if (predictor == SDCSZ_PRED_REGRESSION) is_reg = true;
+  else {
+    uint32_t e_reg = 0;
+#pragma unroll
+    for (int j = 0; j < B1; j++)
+#pragma unroll
+      for (int k = 0; k < B2; k++) {
+        if (!is_sample<2, 1, B1, B2>(0, j, k)) continue;
+        const T pr = ((beta0 * ((T)0 - c0) + beta1 * ((T)j - c1)) + beta2 * ((T)k - c2)) + mu;
+        const T xs = NS > 0 ? sx[NS > 0 ? sample_slot<2, 1, B1, B2>(0, j, k) : 0] : ld(j, k);
+        if (valid(j, k)) e_reg += cost<T>(xs - pr, inv_e);
+      }
+    is_reg = e_reg <= e_lor;
+  }
+
+  uint64_t why = 0;
+  if (ABFT) {  // coefficient checksums, taken again where the coefficients are used
+    uint32_t sc = 0, qc = 0, sc2 = 0, qc2 = 0;
+    Ck<T>::add(beta0, sc, qc);
+    Ck<T>::add(beta1, sc, qc);
+    Ck<T>::add(beta2, sc, qc);
+    Ck<T>::add(mu, sc, qc);
+    beta0 = launder(beta0);
+    beta1 = launder(beta1);
+    beta2 = launder(beta2);
+    mu = launder(mu);
+    Ck<T>::add(beta0, sc2, qc2);
+    Ck<T>::add(beta1, sc2, qc2);
+    Ck<T>::add(beta2, sc2, qc2);
+    Ck<T>::add(mu, sc2, qc2);
+    if (sc != sc2 || qc != qc2) why |= kWhyCoef;
+  }
+
+  // ---- prediction pass, a row per iteration --------------------------------
+  const T beta0d = ABFT ? launder(beta0) : beta0, beta1d = ABFT ? launder(beta1) : beta1;
+  const T beta2d = ABFT ? launder(beta2) : beta2;
+  const T A0 = beta0 * ((T)0 - c0), A0d = beta0d * ((T)0 - c0);
+  T Bk[B2], Bk2[B2], Pr[B2];  // Pr: reconstructed row j - 1
+#pragma unroll
+  for (int k = 0; k < B2; k++) {
+    Bk[k] = beta2 * ((T)k - c2);
+    Bk2[k] = beta2d * ((T)k - c2);
+    Pr[k] = 0;
+  }
+  uint32_t S2 = 0, Q2 = 0;
+  uint64_t s_dc = 0, is_q = 0;
+  uint32_t s_q = 0, nout = 0;
+  uint32_t mis_p = 0, mis_r = 0;
+  T *outl = (T *)w.vals + blk * (uint64_t)g.bpts;
+  uint2 *cbase = (uint2 *)(w.codes + code_index(blk, 0, g.groups));
+  T xn1[B2], xn2[B2];  // the next two rows, loaded two rows ahead of their use
+#pragma unroll
+  for (int k = 0; k < B2; k++) {
+    xn1[k] = ld(0, k);
+    xn2[k] = ld(1, k);
+  }
+#pragma unroll 1
+  for (int j = 0; j < B1; j++) {
+    if (!FULL && (uint32_t)j >= n1) break;
+    T Aj = A0 + beta1 * ((T)j - c1), Ajd = A0d + beta1d * ((T)j - c1);
+    pin(Aj);
+    if (ABFT) pin(Ajd);
+    T xr[B2];
+#pragma unroll
+    for (int k = 0; k < B2; k++) {
+      xr[k] = xn1[k];
+      xn1[k] = xn2[k];
+    }
+    if (j + 2 < B1) {
+#pragma unroll
+      for (int k = 0; k < B2; k++) xn2[k] = ld(j + 2, k);
+    }
+    T cprev = 0, fold = 0;
+    uint32_t rs = 0, rk = 0, pk0 = 0, pk1 = 0;
+#pragma unroll
+    for (int k = 0; k < B2; k++) {
+      const bool v = valid(j, k);
+      const T xv = xr[k];
+      if (ABFT && v) Ck<T>::add(xv, S2, Q2);
+      const T b = Pr[k], f = fold;  // r(j-1,k), r(j-1,k-1)
+      fold = b;
+      const T lor = (b + cprev) - f;
+      const T reg = (Aj + Bk[k]) + mu;
+      const T pred = is_reg ? reg : lor;
+      if (ABFT) {  // pred' <- f_dup()
+        const T lor2 = (launder(b) + cprev) - f;
+        const T reg2 = (Ajd + Bk2[k]) + mu;
+        mis_p |= Wd<T>::diff(pred, is_reg ? reg2 : lor2);
+      }
+      const T diff = xv - pred;
+      const T t = fabs(diff) * inv + (T)0.5;
+      const bool inr = t < (T)32768;
+      const int sm = (int)copysign(t, diff);
+      const T r1 = pred + (T)sm * q;
+      if (ABFT) mis_r |= Wd<T>::diff(r1, pred + (T)launder(sm) * q);  // dec_dup()
+      const bool bok = Bound<T>::ok(xv, r1, eb);
+      const bool ok = inr && bok;
+      const uint32_t code = (ok && v) ? (uint32_t)(sm + (int)kRadius) : 0u;
+      const T r_out = ok ? r1 : xv;
+      Pr[k] = r_out;
+      cprev = r_out;
+      const bool is_out = v && !ok;
+      if (__builtin_expect(__ballot(is_out) != 0, 0)) {
+        if (is_out) outl[nout] = xv;
+        nout += is_out ? 1u : 0u;
+      }
+      const bool z = v && code == kRadius;
+      hot += (uint32_t)__popcll(__ballot(z));
+      if (v) {
+        if (ABFT) {
+          s_dc += Wd<T>::sum(r_out);
+          rs += code;
+          rk += (uint32_t)k * code;
+        }
+        if (!z) {
+          const uint32_t cb = code - kHistLo;
+          if (cb < kHistWin) atomicAdd(&hist[cb], 1u);
+          else atomicAdd(w.hist + code, 1u);
+        }
+      }
+      if ((k & 1) == 0) {
+        if ((k & 2) == 0) pk0 = code;
+        else pk1 = code;
+      } else {
+        if ((k & 2) == 0) pk0 |= code << 16;
+        else pk1 |= code << 16;
+      }
+      if ((k & 3) == 3) cbase[(uint64_t)((j * B2 + k) >> 2) * 64] = make_uint2(pk0, pk1);
+      // work in steps of 4 points (the duplicated computations of a whole
+      // row at once would need twice the registers)
+      if ((k & 3) == 3 && k + 1 < B2) row_fence(cprev, fold, S2, Q2, s_dc, rs, rk, nout, mis_p, mis_r);
+    }
+    if (ABFT) {
+      is_q += (uint64_t)((uint32_t)j * n2) * rs + rk;
+      s_q += rs;
+    }
+    row_fence(S2, Q2, s_dc, is_q, s_q, nout, mis_p, mis_r);
+  }
+  w.meta[blk] = (nout << 1) | (is_reg ? 1u : 0u);
+  T *cf = (T *)w.coef + 4 * blk;
+  cf[0] = beta0;
+  cf[1] = beta1;
+  cf[2] = beta2;
+  cf[3] = mu;
+  if (ABFT) {
+    w.sum_dc[blk] = s_dc;
+    w.sum_q[blk] = s_q;
+    w.isum_q[blk] = is_q;
+    if (S1 != S2 || Q1 != Q2) why |= kWhyInput;
+    if (mis_p) why |= kWhyPred;
+    if (mis_r) why |= kWhyRecon;
+    if (__builtin_expect(why != 0, 0)) {
+      if (why & kWhyInput) count(w.cnt, C_DET + SDCSZ_T_INPUT);
+      if (why & kWhyCoef) count(w.cnt, C_DET + SDCSZ_T_COEF);
+      if (why & kWhyPred) count(w.cnt, C_DET + SDCSZ_T_DUP_PRED);
+      if (why & kWhyRecon) count(w.cnt, C_DET + SDCSZ_T_DUP_RECON);
+      const uint32_t slot = atomicAdd(w.redo_n, 1u);
+      if (slot < kMaxRedo) w.redo[slot] = blk | (why << 56);
+    }
+  }
+}
+
 // Work-groups [0, L.full_wgs) take full blocks, the rest the partial shell.
 template <typename T, int ND, int B0, int B1, int B2, bool ABFT>
 __global__ void __launch_bounds__(256) k_compress_fast(JobTab tab) {
@@ -469,13 +738,19 @@ __global__ void __launch_bounds__(256) k_compress_fast(JobTab tab) {
   for (uint32_t t = threadIdx.x; t < kHistWin; t += blockDim.x) hist[t] = 0;
   __syncthreads();
   uint32_t hot = 0;
-  if (jw.b < L.full_wgs)
-    compress_lanes<T, ND, B0, B1, B2, true, ABFT>(in, g, rt, plan, w, predictor, L, hist, hot,
-                                                  (uint64_t)jw.b * blockDim.x + threadIdx.x, L.full_count);
-  else
-    compress_lanes<T, ND, B0, B1, B2, false, ABFT>(in, g, rt, plan, w, predictor, L, hist, hot,
-                                                   (uint64_t)(jw.b - L.full_wgs) * blockDim.x + threadIdx.x,
-                                                   L.shell_count);
+  const bool full = jw.b < L.full_wgs;
+  const uint64_t idx = (uint64_t)(full ? jw.b : jw.b - L.full_wgs) * blockDim.x + threadIdx.x;
+  if constexpr (ND == 2) {
+    static_assert(B0 == 1, "2D blocks have one plane");
+    if (full) compress_rows<T, B1, B2, true, ABFT>(in, g, rt, plan, w, predictor, L, hist, hot, idx, L.full_count);
+    else compress_rows<T, B1, B2, false, ABFT>(in, g, rt, plan, w, predictor, L, hist, hot, idx, L.shell_count);
+  } else {
+    if (full)
+      compress_lanes<T, ND, B0, B1, B2, true, ABFT>(in, g, rt, plan, w, predictor, L, hist, hot, idx, L.full_count);
+    else
+      compress_lanes<T, ND, B0, B1, B2, false, ABFT>(in, g, rt, plan, w, predictor, L, hist, hot, idx,
+                                                     L.shell_count);
+  }
   // wave total of the zero-residual bin (lanes that ran the pass agree; the
   // others hold 0), then flush the window
   for (int off = 32; off > 0; off >>= 1) hot = max(hot, (uint32_t)__shfl_xor((int)hot, off));
@@ -530,6 +805,8 @@ template <typename T> __global__ void __launch_bounds__(64) k_redo(JobTab tab) {
   SDCSZ_INST_FAST(T, ND, B0, B1, B2, false)
 SDCSZ_INST_SHAPE(float, 3, 6, 6, 6)
 SDCSZ_INST_SHAPE(double, 3, 6, 6, 6)
+SDCSZ_INST_SHAPE(float, 2, 1, 16, 16)
+SDCSZ_INST_SHAPE(double, 2, 1, 16, 16)
 template __global__ void k_compress_list<float>(const float *, Geo, RegTab<float>, PlanDev, CompWork, uint32_t,
                                                 uint32_t, const uint64_t *, uint32_t);
 template __global__ void k_compress_list<double>(const double *, Geo, RegTab<double>, PlanDev, CompWork, uint32_t,

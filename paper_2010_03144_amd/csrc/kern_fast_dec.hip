@@ -280,6 +280,120 @@ __device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, cons
   }
 }
 
+// One lane's 2D block of B1 rows by B2 columns, a row per iteration with the
+// previous reconstructed row in registers; the window is staged once per row
+// (B2 codewords of <= 24 bits plus the <= 127-bit skew fit in kWin words for
+// B2 <= 16).
+template <typename T, int B1, int B2, bool FULL>
+__device__ __forceinline__ void decode_rows(const uint8_t *__restrict__ s, const Header &h, const Geo &g,
+                                            const DecWork &w, const PlanDev &plan, T *out, const Launch &L,
+                                            const DecLds &tl, uint32_t *win, uint64_t idx, uint64_t nlanes) {
+  static_assert(B2 * kMaxLen + 127 + 32 <= 32 * (int)kWin, "a row's codewords fit the window");
+  bool active = idx < nlanes;
+  const uint64_t blk = dmap_block(g, L, FULL ? 0u : 1u, active ? idx : nlanes - 1);
+  const Box bx = box_of(g, blk);
+  const uint64_t org = fidx(g, bx, 0, 0, 0);
+  uint64_t omin = org;
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)omin, off);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(omin >> 32), off);
+    const uint64_t o = ((uint64_t)hi << 32) | lo;
+    omin = o < omin ? o : omin;
+  }
+  const uint64_t org0 = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(omin >> 32)) << 32) |
+                        (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)omin);
+  char *wbase = (char *)(out + org0);
+  const uint32_t loff = (uint32_t)((org - org0) * sizeof(T));
+  if (active && plan_hit(plan, blk)) active = false;  // done by k_decode_list
+  if (!active) return;
+
+  const uint32_t n0 = bx.n[0], n1 = FULL ? B1 : bx.n[1], n2 = FULL ? B2 : bx.n[2];
+  const uint32_t RSB = (uint32_t)(g.d[2] * sizeof(T));
+  const T q = (T)(2.0 * h.eb_abs);
+  const T c0 = (T)(n0 - 1) * (T)0.5, c1 = (T)(n1 - 1) * (T)0.5, c2 = (T)(n2 - 1) * (T)0.5;
+  const uint32_t meta = *(const uint32_t *)(s + h.off_table + 8 * blk + 4);
+  const bool is_reg = meta & 1u;
+  const uint32_t nout = meta >> 1;
+  const T *outl = (const T *)(s + h.off_outliers) + w.off_out[blk];
+  T beta0 = 0, beta1 = 0, beta2 = 0, mu = 0;
+  if (is_reg) {
+    const T *cp = (const T *)(s + h.off_coef) + 4ull * w.off_coef[blk];
+    beta0 = cp[0];
+    beta1 = cp[1];
+    beta2 = cp[2];
+    mu = cp[3];
+  }
+  const uint32_t nw = (uint32_t)(w.off_pay[blk + 1] - w.off_pay[blk]);
+  Window br;
+  br.pay = s + h.off_payload + 4ull * w.off_pay[blk];
+  br.end = s + h.total;
+  br.win = win;
+  br.pos = 0;
+  bool bad = false, defer = false;
+  uint32_t used_out = 0;
+  uint64_t sum = 0;
+  const T A0 = beta0 * ((T)0 - c0);
+  T Bk[B2], Pr[B2];  // Pr: reconstructed row j - 1
+#pragma unroll
+  for (int k = 0; k < B2; k++) {
+    Bk[k] = beta2 * ((T)k - c2);
+    Pr[k] = 0;
+  }
+#pragma unroll 1
+  for (int j = 0; j < B1; j++) {
+    if (!FULL && (uint32_t)j >= n1) break;
+    br.stage();
+    T Aj = A0 + beta1 * ((T)j - c1);
+    dpin(Aj);
+    T cprev = 0, fold = 0;
+#pragma unroll
+    for (int k = 0; k < B2; k++) {
+      const bool v = FULL || (uint32_t)k < n2;
+      const uint32_t sym = v ? decode_sym(br, tl, &bad, &defer) : kRadius;
+      const T b = Pr[k], f = fold;  // r(j-1,k), r(j-1,k-1)
+      fold = b;
+      const T lor = (b + cprev) - f;
+      const T reg = (Aj + Bk[k]) + mu;
+      const T pred = is_reg ? reg : lor;
+      T r = pred + (T)((int)sym - (int)kRadius) * q;
+      const bool z = v && sym == 0;
+      if (__builtin_expect(__ballot(z) != 0, 0)) {
+        if (z) {
+          if (used_out < nout) {
+            T o = outl[used_out];
+            dpin(o);  // wait for the load here, not at every later use of r
+            r = o;
+          } else {
+            bad = true;
+          }
+          used_out++;
+        }
+      }
+      Pr[k] = r;
+      cprev = r;
+      if (v) sum += Wd<T>::sum(r);
+    }
+    char *dst = wbase + (loff + (uint32_t)j * RSB);
+#pragma unroll
+    for (int k = 0; k < B2; k++)
+      if (FULL || (uint32_t)k < n2) *(T *)(dst + k * sizeof(T)) = Pr[k];
+    drow_fence(sum, br.lp);
+  }
+  if (used_out != nout || br.pos > nw * 32u) bad = true;
+  const uint64_t *sumdc = (const uint64_t *)(s + h.off_sumdc);
+  uint64_t why = 0;
+  if (defer) why = 3;  // decoded again from the start: later symbols are not trusted
+  else if (bad) why = 2;
+  else if (h.abft && sum != sumdc[blk]) {
+    why = 1;
+    count(w.cnt, C_DET + SDCSZ_T_RECON);
+  }
+  if (__builtin_expect(why != 0, 0)) {
+    const uint32_t slot = atomicAdd(w.redo_n, 1u);
+    if (slot < kMaxRedo) w.redo[slot] = blk | (why << 56);
+  }
+}
+
 // Work-groups [0, L.full_wgs) take full blocks, the rest the partial shell.
 template <typename T, int ND, int B0, int B1, int B2>
 __global__ void __launch_bounds__(kDecThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
@@ -310,17 +424,24 @@ k_decode_fast(JobTab tab) {
     tl.long_n = ln;
   }
   __syncthreads();
-  if (jw.b < L.full_wgs)
-    decode_lanes<T, ND, B0, B1, B2, true>(s, h, g, w, plan, out, L, tl, win + threadIdx.x,
-                                          (uint64_t)jw.b * blockDim.x + threadIdx.x, L.full_count);
-  else
-    decode_lanes<T, ND, B0, B1, B2, false>(s, h, g, w, plan, out, L, tl, win + threadIdx.x,
-                                           (uint64_t)(jw.b - L.full_wgs) * blockDim.x + threadIdx.x,
-                                           L.shell_count);
+  const bool full = jw.b < L.full_wgs;
+  const uint64_t idx = (uint64_t)(full ? jw.b : jw.b - L.full_wgs) * blockDim.x + threadIdx.x;
+  if constexpr (ND == 2) {
+    static_assert(B0 == 1, "2D blocks have one plane");
+    if (full) decode_rows<T, B1, B2, true>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx, L.full_count);
+    else decode_rows<T, B1, B2, false>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx, L.shell_count);
+  } else {
+    if (full)
+      decode_lanes<T, ND, B0, B1, B2, true>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx, L.full_count);
+    else
+      decode_lanes<T, ND, B0, B1, B2, false>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx, L.shell_count);
+  }
 }
 
 #define SDCSZ_INST_DEC(T, ND, B0, B1, B2) template __global__ void k_decode_fast<T, ND, B0, B1, B2>(JobTab);
 SDCSZ_INST_DEC(float, 3, 6, 6, 6)
 SDCSZ_INST_DEC(double, 3, 6, 6, 6)
+SDCSZ_INST_DEC(float, 2, 1, 16, 16)
+SDCSZ_INST_DEC(double, 2, 1, 16, 16)
 
 }  // namespace sdcsz

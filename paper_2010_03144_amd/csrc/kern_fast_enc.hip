@@ -57,9 +57,22 @@ template <int B0, int B1, int B2> struct PlaneCodes {
 
 }  // namespace
 
+// The codes of a block are walked in units of whole 4-code groups: planes of
+// a 3D block (U0 planes of U1 x U2 codes), rows of a 2D block (U0 = B1 rows
+// of one row of B2 codes).  Ext gives a block's actual extents in that view.
+template <int ND, int B0, int B1, int B2> struct Units {
+  static constexpr int U0 = ND == 2 ? B1 : B0, U1 = ND == 2 ? 1 : B1, U2 = B2;
+  __device__ static void ext(const Box &b, uint32_t &e0, uint32_t &e1, uint32_t &e2) {
+    e0 = ND == 2 ? b.n[1] : b.n[0];
+    e1 = ND == 2 ? 1u : b.n[1];
+    e2 = b.n[2];
+  }
+};
+
 // Verify/correct the codes of each block with sum_q/isum_q (Algorithm 1,
 // before encoding) and size its payload in 32-bit words.
-template <int B0, int B1, int B2> __global__ void __launch_bounds__(256) k_check_fast(JobTab jt) {
+template <int ND, int B0, int B1, int B2> __global__ void __launch_bounds__(256) k_check_fast(JobTab jt) {
+  using U = Units<ND, B0, B1, B2>;
   const JobWg jw = job_of(jt);
   const Geo g = jw.J->g;
   const CompWork w = jw.J->cw;
@@ -69,31 +82,32 @@ template <int B0, int B1, int B2> __global__ void __launch_bounds__(256) k_check
   const uint64_t blk = (uint64_t)jw.b * blockDim.x + threadIdx.x;
   if (blk >= g.n_blocks) return;
   const Box b = box_of(g, blk);
-  const uint32_t n1 = b.n[1], n2 = b.n[2];
-  // planes in a rolled loop (one plane of code groups live, the next in flight)
+  uint32_t e0, n1, n2;
+  U::ext(b, e0, n1, n2);
+  // units in a rolled loop (one unit of code groups live, the next in flight)
   const uint2 *cb = (const uint2 *)(w.codes + code_index(blk, 0, g.groups));
-  constexpr int PG = B1 * B2 / 4;
-  static_assert((B1 * B2) % 4 == 0, "a plane fills whole groups");
+  constexpr int PG = U::U1 * U::U2 / 4;
+  static_assert((U::U1 * U::U2) % 4 == 0, "a unit fills whole groups");
   uint2 cur[PG], nxt[PG];
 #pragma unroll
   for (int t = 0; t < PG; t++) cur[t] = cb[(uint64_t)t * 64];
   uint64_t s = 0, is = 0, bits = 0;
   bool missing = false;
 #pragma unroll 1
-  for (int i = 0; i < B0; i++) {
-    if (i + 1 < B0) {
+  for (int i = 0; i < U::U0; i++) {
+    if (i + 1 < U::U0) {
 #pragma unroll
       for (int t = 0; t < PG; t++) nxt[t] = cb[(uint64_t)((i + 1) * PG + t) * 64];
     }
 #pragma unroll
-    for (int j = 0; j < B1; j++) {
+    for (int j = 0; j < U::U1; j++) {
       const uint32_t rowbase = ((uint32_t)i * n1 + (uint32_t)j) * n2;
       uint32_t rs = 0, rk = 0;
 #pragma unroll
-      for (int k = 0; k < B2; k++) {
-        const int q = j * B2 + k;
+      for (int k = 0; k < U::U2; k++) {
+        const int q = j * U::U2 + k;
         const uint32_t word = (q & 2) ? cur[q >> 2].y : cur[q >> 2].x;
-        const bool v = (uint32_t)i < b.n[0] && (uint32_t)j < n1 && (uint32_t)k < n2;
+        const bool v = (uint32_t)i < e0 && (uint32_t)j < n1 && (uint32_t)k < n2;
         const uint32_t c = v ? ((word >> (16 * (q & 1))) & 0xFFFFu) : 0u;
         const uint32_t len = enc_of(c, encw, w.enc) & 0xFFu;
         if (v) {
@@ -111,8 +125,9 @@ template <int B0, int B1, int B2> __global__ void __launch_bounds__(256) k_check
   }
   if (abft && (s != w.sum_q[blk] || is != w.isum_q[blk])) {
     // detected: locate and repair one code, then size the block again
-    auto pos = [&](uint64_t p) -> uint64_t {
-      const uint32_t k = (uint32_t)(p % n2), j = (uint32_t)((p / n2) % n1), i = (uint32_t)(p / ((uint64_t)n2 * n1));
+    auto pos = [&](uint64_t p) -> uint64_t {  // in the geometry's own axes
+      const uint32_t m1 = b.n[1], m2 = b.n[2];
+      const uint32_t k = (uint32_t)(p % m2), j = (uint32_t)((p / m2) % m1), i = (uint32_t)(p / ((uint64_t)m2 * m1));
       return code_index(blk, padded_index(g, i, j, k), g.groups);
     };
     uint64_t jf;
@@ -144,7 +159,8 @@ template <int B0, int B1, int B2> __global__ void __launch_bounds__(256) k_check
 // each row the lane writes out what is complete, whole aligned 32-byte
 // chunks as two 16-byte stores, so HBM sees full sectors instead of one
 // partial write per word (only a block's first and last chunk are partial).
-template <typename T, int B0, int B1, int B2> __global__ void __launch_bounds__(256) k_encode_fast(JobTab jt) {
+template <typename T, int ND, int B0, int B1, int B2> __global__ void __launch_bounds__(256) k_encode_fast(JobTab jt) {
+  using U = Units<ND, B0, B1, B2>;
   const JobWg jw = job_of(jt);
   const Geo g = jw.J->g;
   const CompWork w = jw.J->cw;
@@ -157,7 +173,9 @@ template <typename T, int B0, int B1, int B2> __global__ void __launch_bounds__(
   const uint64_t blk = (uint64_t)jw.b * blockDim.x + threadIdx.x;
   if (blk >= g.n_blocks) return;
   const Box b = box_of(g, blk);
-  PlaneCodes<B0, B1, B2> bc;
+  uint32_t e0, e1, e2;
+  U::ext(b, e0, e1, e2);
+  PlaneCodes<U::U0, U::U1, U::U2> bc;
   bc.init(w.codes, blk, g.groups);
   bc.load(0);
   uint32_t *ring = ring_all + threadIdx.x;  // word with absolute index a at ring[(a & 15) * 256]
@@ -189,15 +207,18 @@ template <typename T, int B0, int B1, int B2> __global__ void __launch_bounds__(
   };
   uint64_t acc = 0;
   uint32_t nacc = 0;
+  // at most 8 codes (<= 6 words) between flushes: with <= 7 words left
+  // after a flush, the 16-word ring never overruns
+  constexpr int FE = U::U2 < 8 ? U::U2 : 8;
 #pragma unroll
-  for (int i = 0; i < B0; i++) {
-    if (i + 1 < B0) bc.load(i + 1);
+  for (int i = 0; i < U::U0; i++) {
+    if (i + 1 < U::U0) bc.load(i + 1);
 #pragma unroll
-    for (int j = 0; j < B1; j++) {
+    for (int j = 0; j < U::U1; j++) {
 #pragma unroll
-      for (int k = 0; k < B2; k++) {
-        const bool v = (uint32_t)i < b.n[0] && (uint32_t)j < b.n[1] && (uint32_t)k < b.n[2];
-        const uint32_t e = enc_of(v ? bc.at(i, j * B2 + k) : kRadius, encw, w.enc);
+      for (int k = 0; k < U::U2; k++) {
+        const bool v = (uint32_t)i < e0 && (uint32_t)j < e1 && (uint32_t)k < e2;
+        const uint32_t e = enc_of(v ? bc.at(i, j * U::U2 + k) : kRadius, encw, w.enc);
         const uint32_t len = v ? (e & 0xFFu) : 0u;
         acc = (acc << len) | (e >> 8 & ((1u << len) - 1u));
         nacc += len;
@@ -207,8 +228,8 @@ template <typename T, int B0, int B1, int B2> __global__ void __launch_bounds__(
           wabs++;
           acc &= (1ull << nacc) - 1;
         }
+        if ((k + 1) % FE == 0 || k + 1 == U::U2) flush();
       }
-      flush();
     }
   }
   if (nacc > 0) {
@@ -234,8 +255,11 @@ template <typename T, int B0, int B1, int B2> __global__ void __launch_bounds__(
   if (h.abft) ((uint64_t *)(out + h.off_sumdc))[blk] = w.sum_dc[blk];
 }
 
-template __global__ void k_check_fast<6, 6, 6>(JobTab);
-template __global__ void k_encode_fast<float, 6, 6, 6>(JobTab);
-template __global__ void k_encode_fast<double, 6, 6, 6>(JobTab);
+template __global__ void k_check_fast<3, 6, 6, 6>(JobTab);
+template __global__ void k_check_fast<2, 1, 16, 16>(JobTab);
+template __global__ void k_encode_fast<float, 3, 6, 6, 6>(JobTab);
+template __global__ void k_encode_fast<double, 3, 6, 6, 6>(JobTab);
+template __global__ void k_encode_fast<float, 2, 1, 16, 16>(JobTab);
+template __global__ void k_encode_fast<double, 2, 1, 16, 16>(JobTab);
 
 }  // namespace sdcsz

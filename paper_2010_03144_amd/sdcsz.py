@@ -150,6 +150,20 @@ def make_params(shape, is_f32, block, eb, eb_mode="rel", abft=True, predictor="a
     return p
 
 
+def max_compressed_size(shape, is_f32, block):
+    """Upper bound of the stream size of a field (bytes)."""
+    p = make_params(tuple(shape), is_f32, block, 1.0)
+    return int(lib().sdcsz_max_compressed_size(C.byref(p)))
+
+
+def workspace_sizes(shape, is_f32, block, n_faults=0):
+    """(compress, decompress) device workspace bytes of one field."""
+    L = lib()
+    p = make_params(tuple(shape), is_f32, block, 1.0)
+    p.n_faults = n_faults
+    return int(L.sdcsz_compress_workspace_size(C.byref(p))), int(L.sdcsz_decompress_workspace_size(C.byref(p)))
+
+
 def _stream_handle(device):
     import torch
     return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
@@ -238,11 +252,16 @@ class Codec:
         return self.workspace(n, "decompress")
 
     # ---------------------------------------------------------------- decompress
-    def decompress(self, stream, faults=None, out=None):
-        """Returns (rc, tensor, report dict)."""
+    def decompress(self, stream, faults=None, out=None, geom=None):
+        """Returns (rc, tensor, report dict).  geom: (shape, is_f32, block)
+        when the caller knows them (the library checks them against the
+        header), else they are taken from the stream."""
         torch = self.torch
         L = lib()
-        rc, p, shape = self._geometry(stream)
+        if geom is not None:
+            rc, p, shape = OK, make_params(tuple(geom[0]), geom[1], geom[2], 1.0), tuple(geom[0])
+        else:
+            rc, p, shape = self._geometry(stream)
         if rc != OK:
             return rc, None, None
         dt = torch.float32 if p.dtype == 0 else torch.float64
@@ -320,9 +339,12 @@ class Codec:
             res.append((it.rc, bufs[i][: it.out_size] if it.rc == OK else None, report_dict(it.rep)))
         return rc, res
 
-    def decompress_batch(self, streams, outs=None, faults=None):
+    def decompress_batch(self, streams, outs=None, faults=None, geoms=None):
         """Decompress several streams in one call (faults: None or one RECON
-        plan or None per stream); returns (rc, [(rc, tensor, report)])."""
+        plan or None per stream; geoms: None or (shape, is_f32, block) per
+        stream when the caller knows them, which saves reading the headers
+        here: the library checks them against the headers anyway).  Returns
+        (rc, [(rc, tensor, report)])."""
         torch = self.torch
         L = lib()
         n = len(streams)
@@ -331,7 +353,11 @@ class Codec:
         outs = list(outs) if outs is not None else [None] * n
         keep = []
         for i, s in enumerate(streams):
-            rc, p, shape = self._geometry(s)
+            if geoms is not None and geoms[i] is not None:
+                shape, is_f32, blk = geoms[i]
+                rc, p, shape = OK, make_params(tuple(shape), is_f32, blk, 1.0), tuple(shape)
+            else:
+                rc, p, shape = self._geometry(s)
             if rc != OK:
                 return rc, None
             fptr, nf, k = _faults(faults[i] if faults is not None else None)

@@ -255,3 +255,32 @@ def request_stream(rate=200.0, duration=60.0, seed=5, size_lo=1 << 20, size_hi=1
                     "eb": float(math.exp(rng.uniform(math.log(1e-5), math.log(1e-2)))),
                     "faults": bool(rng.uniform() < frac_faults), "seed": int(rng.integers(1 << 30))})
     return out
+
+
+def sparse_fault_plan(shape, block, dtype, counts, seed):
+    """fault_plan for a few flips on a large grid: the struck blocks are drawn
+    one at a time (distinct, uniform) instead of by a permutation of all
+    blocks, so a plan costs O(flips)."""
+    rng = np.random.default_rng(seed)
+    per = 1 if np.dtype(dtype) == np.float32 else 2
+    nblk = int(np.prod(block_grid(shape, block)))
+    total = sum(counts.values())
+    if total > nblk:
+        raise ValueError("more faults than blocks")
+    taken, rows = set(), []
+    for name in sorted(counts, key=lambda t: TARGET_IDS[t]):
+        tid = TARGET_IDS[name]
+        for _ in range(counts[name]):
+            while True:
+                blk = int(rng.integers(0, nblk))
+                if blk not in taken:
+                    taken.add(blk)
+                    break
+            pts = block_points(shape, block, blk)
+            nwords = pts * per if name in ("input", "recon") else (4 * per if name == "coef" else pts)
+            word = int(rng.integers(0, nwords))
+            bit = int(rng.integers(0, 32 * per if name.startswith("dup") else 32))
+            rows.append((tid, bit, blk, word))
+    if not rows:
+        return np.zeros((0, 4), dtype=np.int64)
+    return np.array(rows, dtype=np.int64)

@@ -65,6 +65,41 @@ def test_grf_tiles_and_ragged_tail(codec, dtype, eb, abft):
     check_roundtrip(codec, x, (6, 6, 6), eb, abft=abft)
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("eb", [1e-2, 1e-5])
+@pytest.mark.parametrize("abft", [True, False])
+def test_grf_2d_tiles_and_ragged_tail(codec, dtype, eb, abft):
+    # 44 x 64 blocks of 16x16 (12-row and 5-column partial edges): 11 work-groups
+    # of full blocks and one of the partial shell in the 2D row-streaming kernels
+    x = synth.grf_field((700, 1013), seed=12, slope=-2.5, front=True, dtype=dtype)
+    check_roundtrip(codec, x, (16, 16), eb, abft=abft)
+
+
+@pytest.mark.parametrize("predictor", ["lorenzo", "regression"])
+def test_2d_forced_predictors(codec, predictor):
+    x = synth.grf_field((333, 517), seed=13)
+    check_roundtrip(codec, x, (16, 16), 1e-3, predictor=predictor)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_2d_fault_counts_match_oracle(codec, dtype):
+    shape, block = (400, 390), (16, 16)
+    x = synth.grf_field(shape, seed=14, dtype=dtype)
+    plan = synth.fault_plan(shape, block, dtype, {"input": 5, "coef": 5, "code": 5, "dup_pred": 5,
+                                                  "dup_recon": 5}, seed=41)
+    (rc_r, s_r, rep_r), (rc_g, s_g, rep_g) = both(codec, x, block, 1e-4, faults=plan)
+    assert rc_r == rc_g == 0, (rc_r, rc_g)
+    same_counts(rep_r, rep_g)
+    assert np.array_equal(s_r, s_g), first_difference(s_r, s_g)
+    rplan = synth.fault_plan(shape, block, dtype, {"recon": 9}, seed=42)
+    rc_r, y_r, rep_dr = ref.decompress(s_r, faults=rplan)
+    rc_g, y_g, rep_dg = codec.decompress(torch.from_numpy(s_g).cuda(), faults=rplan)
+    assert rc_r == rc_g == 0
+    same_counts(rep_dr, rep_dg)
+    assert rep_dg["recon"]["detected"] == rep_dg["recon"]["corrected"] == 9
+    assert np.array_equal(y_r.view(np.uint8), y_g.cpu().numpy().view(np.uint8))
+
+
 @pytest.mark.parametrize("predictor", ["lorenzo", "regression"])
 def test_forced_predictors(codec, predictor):
     x = synth.grf_field((30, 31, 32), seed=7)
