@@ -106,7 +106,7 @@ def cpu_baseline(x, block, eb):
                       f"compress {t1 - t0:.2f} s + decompress {t2 - t1:.2f} s"}
 
 
-def batch_bench(codec, torch, reps=3):
+def batch_bench(codec, torch, reps=3, plain_loop=True):
     """Mixed batch: 192 2D/3D FP32/FP64 fields of uneven shapes, each with its
     own bound (Gaussian random fields, spectral slopes -2..-4), compressed and
     decompressed by one batched call each, against a loop of plain per-field
@@ -123,11 +123,19 @@ def batch_bench(codec, torch, reps=3):
     ys = {k: [torch.empty_like(x) for x in fields] for k in ("b", "p")}
     sync = torch.cuda.synchronize
 
+    geoms = [(tuple(x.shape), x.dtype == torch.float32, b) for x, b in zip(fields, blocks)]
+    split = {}
+
     def batched():
+        t0 = time.perf_counter()
         rc, cres = codec.compress_batch(fields, blocks, ebs, outs=outs["b"])
         assert rc == 0 and all(r[0] == 0 for r in cres), rc
-        rc, dres = codec.decompress_batch([r[1] for r in cres], outs=ys["b"])
+        t1 = time.perf_counter()
+        rc, dres = codec.decompress_batch([r[1] for r in cres], outs=ys["b"], geoms=geoms)
         assert rc == 0 and all(r[0] == 0 for r in dres), rc
+        t2 = time.perf_counter()
+        split.setdefault("compress", []).append(t1 - t0)
+        split.setdefault("decompress", []).append(t2 - t1)
         return [r[1] for r in cres]
 
     def plain():
@@ -135,7 +143,7 @@ def batch_bench(codec, torch, reps=3):
         for i, x in enumerate(fields):
             rc, st, _ = codec.compress(x, blocks[i], ebs[i], out=outs["p"][i])
             assert rc == 0, rc
-            rc, _, _ = codec.decompress(st, out=ys["p"][i])
+            rc, _, _ = codec.decompress(st, out=ys["p"][i], geom=geoms[i])
             assert rc == 0, rc
             streams.append(st)
         return streams
@@ -153,11 +161,15 @@ def batch_bench(codec, torch, reps=3):
 
     log("batch: batched calls")
     t_b, s_b = timed(batched)
+    split_ms = {k: round(float(np.median(v[1:])) * 1e3, 3) for k, v in split.items()}
     sdcsz.timing_enable(True)
     batched()
     sync()
     phases = sdcsz.timing_read()
     sdcsz.timing_enable(False)
+    if not plain_loop:  # profiling the batched calls alone
+        return {"batched": {"ms": round(t_b * 1e3, 3)}, "split_ms": split_ms,
+                "batched_phases_ms": {p: round(v[0], 4) for p, v in phases.items() if v[1]}}
     log("batch: per-field calls")
     t_p, s_p = timed(plain)
     same = all(a.numel() == b.numel() and torch.equal(a, b) for a, b in zip(s_b, s_p))
@@ -170,10 +182,134 @@ def batch_bench(codec, torch, reps=3):
     return {"workload": "192 fields: 50% 2D (256..4096)^2 blocks 16x16, 50% 3D (32..384)^2x(32..256) "
                         "blocks 6x6x6, 25% FP64, eb log-uniform 1e-5..1e-2 REL, ABFT on (seed 4)",
             "fields": len(fields), "field_bytes": nbytes, "compression_ratio": round(nbytes / sbytes, 4),
-            "batched": {"ms": round(t_b * 1e3, 3), "gbs": round(nbytes / t_b / 1e9, 3)},
+            "batched": {"ms": round(t_b * 1e3, 3), "gbs": round(nbytes / t_b / 1e9, 3), "split_ms": split_ms},
             "per_field": {"ms": round(t_p * 1e3, 3), "gbs": round(nbytes / t_p / 1e9, 3)},
             "speedup": round(t_p / t_b, 3), "identical": bool(same),
             "batched_phases_ms": {p: round(v[0], 4) for p, v in phases.items() if v[1]}}
+
+
+SERVE_SIZES = 31  # request size classes 1 MiB * 2^(k/3), k = 0..30 (1 MiB .. 1 GiB)
+
+
+def serve_pool(torch, xd):
+    """Device-resident request fields: per size class and dtype, a C-order crop
+    of the 512^3 field (near-cubic; FP32 crops come from the field stacked on
+    its mirror image along the slowest axis, so 1 GiB fits; FP64 crops are
+    the field cast)."""
+    base = {True: torch.cat([xd, xd.flip(0)], 0), False: xd.double()}
+    pool = {}
+    for k in range(SERVE_SIZES):
+        nbytes = (1 << 20) * 2 ** (k / 3)
+        for is32 in (True, False):
+            b = base[is32]
+            n = nbytes / (4 if is32 else 8)
+            e = min(b.shape[1], max(16, round(n ** (1 / 3))))
+            a = min(b.shape[0], max(1, round(n / (e * e))))
+            pool[(k, is32)] = b[:a, :e, :e].contiguous()
+    del base
+    return pool
+
+
+def serve_bench(torch, xd, seconds, rate=200.0, seed=5):
+    """Poisson stream of compress/decompress requests (sizes log-uniform
+    1 MiB..1 GiB, 25% FP64, bound log-uniform 1e-5..1e-2, 20% with fault
+    plans: input, coefficient and code flips for compression, reconstructed-
+    value flips for decompression, one per 1e5 blocks and at least one per
+    target), served with continuous batching against the plain loop; then
+    the same requests all at once, for throughput capacity."""
+    import math
+    from paper_2010_03144_amd import sdcsz, serve, synth
+    block = (6, 6, 6)
+    log(f"serve: pool of request fields, {seconds:g} s at {rate:g} req/s")
+    pool = serve_pool(torch, xd)
+    specs = synth.request_stream(rate=rate, duration=seconds, seed=seed)
+    codec = sdcsz.Codec("cuda:0")
+    streams = {}
+    rows = []
+    for i, sp in enumerate(specs):
+        is32 = sp["dtype"] == np.float32
+        nb = math.prod(sp["shape"]) * (4 if is32 else 8)
+        k = min(SERVE_SIZES - 1, max(0, round(3 * math.log2(nb / (1 << 20)))))
+        x = pool[(k, is32)]
+        shape = tuple(x.shape)
+        nblk = math.prod(-(-d // b) for d, b in zip(shape, block))
+        m = max(1, round(nblk * 1e-5))
+        if sp["kind"] == "compress":
+            plan = (synth.sparse_fault_plan(shape, block, np.float32 if is32 else np.float64,
+                                            {"input": m, "coef": m, "code": m}, sp["seed"])
+                    if sp["faults"] else None)
+            rows.append(("compress", sp["t"], x, sp["eb"], plan, None))
+        else:
+            bucket = min(2, max(0, int(math.floor(math.log10(sp["eb"]) + 5))))
+            key = (k, is32, bucket)
+            if key not in streams:
+                rc, st, _ = codec.compress(x, block, 10 ** (-4.5 + bucket))
+                assert rc == 0, rc
+                streams[key] = st.clone()
+            plan = (synth.sparse_fault_plan(shape, block, np.float32 if is32 else np.float64, {"recon": m},
+                                            sp["seed"]) if sp["faults"] else None)
+            rows.append(("decompress", sp["t"], streams[key], None, plan, (shape, is32, block)))
+    fp_cache = {}
+
+    def make(offsets=True):
+        out = []
+        for kind, t, data, eb, plan, geom in rows:
+            if kind == "compress":
+                r = serve.Request("compress", data, block, eb, faults=plan)
+            else:
+                r = serve.Request("decompress", data, faults=plan, geom=geom)
+            key = (kind, data.data_ptr(), 0 if plan is None else len(plan))
+            if key not in fp_cache:
+                fp_cache[key] = serve.device_footprint(r)
+            r.footprint = fp_cache[key]
+            r.t_arrival = t if offsets else 0.0
+            out.append(r)
+        return out
+
+    def summary(reqs, t0):
+        assert all(r.rc == 0 for r in reqs), [r.rc for r in reqs if r.rc != 0][:5]
+        lat = np.array([r.latency for r in reqs]) * 1e3
+        nbytes = sum(serve.field_bytes(r) for r in reqs)
+        span = max(r.t_done for r in reqs) - t0
+        inj = sum(sum(r.report[t]["injected"] for t in sdcsz.TARGETS) for r in reqs)
+        cor = sum(sum(r.report[t]["corrected"] for t in sdcsz.TARGETS) for r in reqs)
+        return {"p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "max_ms": round(float(lat.max()), 3), "gbs": round(nbytes / span / 1e9, 3),
+                "faults_injected": int(inj), "faults_corrected": int(cor)}
+
+    def served(reqs):
+        with serve.Server("cuda:0", workers=2, hbm_budget=200e9, max_batch=64, keep_results=False) as srv:
+            t0 = srv.clock() + 0.05
+            serve.replay(srv, reqs, t0)
+            peak, nb = srv.peak_in_use, list(srv.batches)
+        out = summary(reqs, t0)
+        out.update({"batches": len(nb), "mean_batch": round(float(np.mean(nb)), 2), "peak_admitted_bytes": int(peak)})
+        return out
+
+    def plain(reqs):
+        t0 = time.perf_counter() + 0.05
+        serve.serve_one_at_a_time(reqs, t0, keep_results=False)
+        return summary(reqs, t0)
+
+    log("serve: warm-up")
+    warm = make(False)[:32]
+    served(warm)
+    plain(make(False)[:32])
+    torch.cuda.synchronize()
+    log(f"serve: {len(rows)} requests served with continuous batching")
+    s_at_rate = served(make())
+    log("serve: the same requests one at a time")
+    p_at_rate = plain(make())
+    log("serve: all requests at once (capacity)")
+    s_cap = served(make(False))
+    p_cap = plain(make(False))
+    offered = sum(serve.field_bytes(r) for r in make()) / seconds / 1e9
+    return {"workload": f"Poisson {rate:g} req/s for {seconds:g} s ({len(rows)} requests): 50% compress / 50% "
+                        f"decompress, sizes log-uniform 1 MiB..1 GiB (31 size classes, crops of the 512^3 "
+                        f"field), 25% FP64, eb log-uniform 1e-5..1e-2 REL, block 6x6x6, ABFT on, 20% with "
+                        f"fault plans; HBM admission budget 200 GB, 2 workers (seed {seed})",
+            "offered_gbs": round(offered, 3), "served": s_at_rate, "one_at_a_time": p_at_rate,
+            "capacity_served_gbs": s_cap["gbs"], "capacity_one_at_a_time_gbs": p_cap["gbs"]}
 
 
 def main():
@@ -186,7 +322,11 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed 192-field batch")
-    ap.add_argument("--only", choices=["batch"], help="run one part alone and print its JSON")
+    ap.add_argument("--only", choices=["batch", "serve"], help="run one part alone and print its JSON")
+    ap.add_argument("--batch-only-batched", action="store_true",
+                    help="with --only batch: skip the per-field loop (for profiling the batched calls)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the served request stream (the full workload is 60 s)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="profiling pass: the timed steps, then two plain copy kernels over the field "
                          "(known traffic, to scale HBM counters); implies --no-extras --no-cpu-baseline")
@@ -204,7 +344,13 @@ def main():
     from paper_2010_03144_amd import sdcsz, synth
 
     if args.only == "batch":
-        print(json.dumps(batch_bench(sdcsz.Codec("cuda:0"), torch)), flush=True)
+        print(json.dumps(batch_bench(sdcsz.Codec("cuda:0"), torch, plain_loop=not args.batch_only_batched)),
+              flush=True)
+        return
+    if args.only == "serve":
+        log("generating 512^3 FP32 field")
+        xd = torch.from_numpy(synth.grf_field((512, 512, 512), seed=2)).cuda()
+        print(json.dumps(serve_bench(torch, xd, args.serve_seconds)), flush=True)
         return
 
     shape = (args.size,) * 3
@@ -239,7 +385,7 @@ def main():
     ms_d = sum(phases[p][0] for p in dec_ph) / args.steps
 
     # roofline of the dominant kernel
-    dom = max(phases, key=lambda p: phases[p][0])
+    dom = max(PHASE_KERNEL, key=lambda p: phases[p][0])
     dom_ms, dom_launches = phases[dom]
     avg_s = dom_ms / max(dom_launches, 1) / 1e3
     alg = algorithmic_bytes(dom, n, nb, vb, rep, True)
@@ -277,6 +423,7 @@ def main():
         "compression_ratio": round(n * vb / stream_bytes, 4),
         "max_abs_err": err,
         "phases_ms_per_step": {p: round(v[0] / args.steps, 4) for p, v in phases.items() if v[1]},
+        "host_ms_per_step": {p: round(v[0] / args.steps, 4) for p, v in phases.items() if p.startswith("host")},
         "source_digest": digest,
     }
 
@@ -299,6 +446,7 @@ def main():
 
     if not args.no_batch and not args.copy_probe:
         result["batch"] = batch_bench(codec, torch)
+        result["serve"] = serve_bench(torch, xd, args.serve_seconds)
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

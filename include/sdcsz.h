@@ -243,17 +243,20 @@ int sdcsz_decompress_batch(sdcsz_dec_item *h_items, uint32_t n, void *d_ws, uint
 const char *sdcsz_strerror(int code);
 
 /*
- * Kernel-phase timing (instrumentation).  When enabled, every call records
- * HIP events on its stream around each kernel phase and accumulates the
- * elapsed device time per phase.  Process-wide state; not thread safe.
- * Phases: 0 range, 1 predict+quantize (per block), 2 code faults,
+ * Phase timing (instrumentation).  When enabled, every call records HIP
+ * events on its stream around each kernel phase and accumulates the elapsed
+ * device time per phase, and accumulates host wall time in the host phases.
+ * Process-wide state; not thread safe.
+ * Device phases: 0 range, 1 predict+quantize (per block), 2 code faults,
  * 3 code check+size, 4 compression scan, 5 encode+assemble,
  * 6 decompression scan, 7 decode+check (per block).
+ * Host phases: 8 codebook construction, 9 waiting in stream
+ * synchronisations, 10 whole compression/decompression calls.
  */
-#define SDCSZ_N_PHASES 8
+#define SDCSZ_N_PHASES 11
 typedef struct {
-  double ms[SDCSZ_N_PHASES];       /* accumulated device milliseconds */
-  uint64_t launches[SDCSZ_N_PHASES];
+  double ms[SDCSZ_N_PHASES];       /* accumulated milliseconds */
+  uint64_t launches[SDCSZ_N_PHASES];  /* kernel phases timed / host spans */
 } sdcsz_timing;
 /* on != 0 enables and clears the accumulators; 0 disables. */
 void sdcsz_timing_enable(int on);

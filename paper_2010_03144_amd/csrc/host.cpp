@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -28,9 +29,12 @@ namespace {
 // dispatches record its start and stop events themselves
 // (hipExtLaunchKernelGGL), so timing adds no packets to the stream
 // ---------------------------------------------------------------------------
-enum { PH_RANGE, PH_PREDICT, PH_CODEFAULT, PH_CHECK, PH_SCAN_C, PH_ENCODE, PH_SCAN_D, PH_DECODE, PH_NONE = -1 };
-const char *kPhaseNames[SDCSZ_N_PHASES] = {"range",      "predict_quantize", "code_faults", "code_check",
-                                           "scan_compress", "encode",        "scan_decompress", "decode"};
+enum { PH_RANGE, PH_PREDICT, PH_CODEFAULT, PH_CHECK, PH_SCAN_C, PH_ENCODE, PH_SCAN_D, PH_DECODE,
+       PH_HOST_CODEBOOK, PH_HOST_WAIT, PH_HOST_CALL, PH_NONE = -1 };
+constexpr int kDevicePhases = PH_HOST_CODEBOOK;
+const char *kPhaseNames[SDCSZ_N_PHASES] = {"range",         "predict_quantize", "code_faults",    "code_check",
+                                           "scan_compress", "encode",           "scan_decompress", "decode",
+                                           "host_codebooks", "host_wait",       "host_call"};
 
 struct PhaseTimer {
   bool on = false;
@@ -42,7 +46,7 @@ struct PhaseTimer {
   bool ready() {
     if (!on) return false;
     if (!made) {
-      for (int i = 0; i < SDCSZ_N_PHASES; i++)
+      for (int i = 0; i < kDevicePhases; i++)
         for (int j = 0; j < 2; j++)
           if (hipEventCreate(&ev[i][j]) != hipSuccess) {
             on = false;
@@ -53,7 +57,7 @@ struct PhaseTimer {
     return true;
   }
   void resolve() {
-    for (int i = 0; i < SDCSZ_N_PHASES; i++)
+    for (int i = 0; i < kDevicePhases; i++)
       if (pending[i]) {
         float t = 0;
         (void)hipEventSynchronize(ev[i][1]);
@@ -66,6 +70,23 @@ struct PhaseTimer {
   }
 };
 PhaseTimer g_timer;
+
+// Host wall time of a scope, added to a host phase while timing is on.
+struct HostSpan {
+  int ph;
+  std::chrono::steady_clock::time_point t0;
+  explicit HostSpan(int p) : ph(p), t0(std::chrono::steady_clock::now()) {}
+  ~HostSpan() {
+    if (!g_timer.on) return;
+    g_timer.ms[ph] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    g_timer.launches[ph]++;
+  }
+};
+
+hipError_t sync_wait(hipStream_t st) {
+  HostSpan h(PH_HOST_WAIT);
+  return hipStreamSynchronize(st);
+}
 
 // Launch one kernel of phase `ph` (PH_NONE: untimed); `first`/`last` mark the
 // phase's first and last kernel.
@@ -596,6 +617,7 @@ template <typename T> void fill_rt(Job &J) {
 }
 
 int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStream_t st) {
+  HostSpan call(PH_HOST_CALL);
   // ---- validation and layouts
   std::vector<CompPlan> fp;
   std::vector<uint32_t> item_of;  // job -> item
@@ -809,7 +831,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   const uint64_t head = B.pairs - B.counts;
   const uint64_t pre = std::min<uint64_t>(kPairPrefix, cap);
   HIPCHK(hipMemcpyAsync(hs, ws + B.counts, head + 8 * pre, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(sync_wait(st));
   std::vector<uint32_t> cnt_sym((const uint32_t *)hs, (const uint32_t *)hs + nj);
   uint64_t total_pairs = 0;
   for (uint32_t j = 0; j < nj; j++) total_pairs += cnt_sym[j];
@@ -829,7 +851,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     hs = t_stage.get(need);
     if (!hs) return SDCSZ_EHIP;
     HIPCHK(hipMemcpyAsync(hs + at_pairs, ws + B.pairs, 8 * total_pairs, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(sync_wait(st));
   }
   // ---- codebooks (host), then stage B: codewords, code check, scans,
   // header, encoding, results
@@ -844,7 +866,10 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     jobs[j].cw.cb = (uint32_t *)(ws + B.cb) + 2 * off;
     off += cnt_sym[j];
   }
-  build_codebooks(cj);
+  {
+    HostSpan h(PH_HOST_CODEBOOK);
+    build_codebooks(cj);
+  }
   Tab t_put, t_chk_fast[kClasses], t_chk_gen, t_s1, t_s2, t_hdr, t_enc_fast[kClasses][2], t_enc_gen[2], t_res;
   for (uint32_t j = 0; j < nj; j++) {
     const Job &J = jobs[j];
@@ -912,7 +937,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   HIPCHK(hipGetLastError());
   uint64_t *hres = (uint64_t *)(hs + at_res);
   HIPCHK(hipMemcpyAsync(hres, d_res, 8ull * (C_N + R_N) * nj, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(sync_wait(st));
   g_timer.resolve();
 
   // ---- per-field outcome
@@ -1010,7 +1035,7 @@ int read_headers(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     launch(PH_NONE, false, false, k_headers, dim3(t.total()), dim3(64), st, up.dev[0], dh);
     HIPCHK(hipMemcpyAsync(hs, dh, kHeader * idx.size(), hipMemcpyDeviceToHost, st));
   }
-  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(sync_wait(st));
   for (size_t j = 0; j < idx.size(); j++) {
     DecItem &d = it[idx[j]];
     d.rc = unpack_header(hs + kHeader * j, d.stream_size, d.h, d.g);
@@ -1026,6 +1051,7 @@ uint64_t dec_batch_ws(const Geo *g, const uint32_t *dtype, const uint32_t *nf, u
 
 // items whose headers were read (rc == OK): decode with one more synchronisation
 int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStream_t st) {
+  HostSpan call(PH_HOST_CALL);
   std::vector<DecPlan> fp;
   std::vector<uint32_t> item_of;
   uint64_t per = 0;
@@ -1192,7 +1218,7 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
               (uint32_t)(C_N + 1));
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(hs + up.bytes(nj), d_res, res_bytes, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(sync_wait(st));
   g_timer.resolve();
   std::vector<uint64_t> resv((const uint64_t *)(hs + up.bytes(nj)), (const uint64_t *)(hs + up.bytes(nj)) + (C_N + 1) * nj);
   // more blocks to re-execute than the queue holds: decode those fields again
@@ -1223,7 +1249,7 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     uint64_t *d_res2 = (uint64_t *)(ws + a256(u2.bytes(nj)));
     launch(PH_NONE, false, false, k_results, grid(t_res2), dim3(64), st, u2.dev[2], d_res2, (uint32_t)(C_N + 1));
     HIPCHK(hipMemcpyAsync(h2 + u2.bytes(nj), d_res2, 8ull * (C_N + 1) * again.size(), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(sync_wait(st));
     const uint64_t *r2 = (const uint64_t *)(h2 + u2.bytes(nj));
     for (size_t q = 0; q < again.size(); q++)
       std::memcpy(resv.data() + (uint64_t)again[q] * (C_N + 1), r2 + q * (C_N + 1), 8 * (C_N + 1));

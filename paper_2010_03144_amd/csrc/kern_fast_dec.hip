@@ -6,9 +6,9 @@
 // of the block's payload staged in LDS with 16-byte loads, reconstruction
 // with the arithmetic of compression (previous reconstructed plane in
 // registers), the checksum of the block against sum_dc, and coalesced row
-// stores.  A checksum mismatch, an undecodable block or a symbol beyond the
-// LDS tables queues the block for k_decode_redo (re-execution from the
-// compressed bytes); blocks named in a fault plan run in k_decode_list.
+// stores.  A checksum mismatch or an undecodable block queues the block for
+// k_decode_redo (re-execution from the compressed bytes); blocks named in a
+// fault plan run in k_decode_list.
 #include "dev.h"
 #include "kern.h"
 
@@ -112,10 +112,11 @@ struct DecLds {
 // Decode one symbol.  The prefix table resolves codewords of up to kLutBits
 // bits; for a longer one it gives the range of lengths whose codes start
 // with that prefix, and the first length whose codes hold the top bits
-// wins.  Sets *bad when no codeword matches, and *defer when the symbol is
-// not held in LDS (the block is then decoded by the generic kernel).
-// Reading past the block's words is checked once, at the end of the block.
-__device__ inline uint32_t decode_sym(Window &br, const DecLds &t, bool *bad, bool *defer) {
+// wins.  The symbols of long codes come from LDS, or (the rarest codes of a
+// large codebook, beyond kLongSyms) from the global table, waiting for that
+// load inside its own branch.  Sets *bad when no codeword matches.  Reading
+// past the block's words is checked once, at the end of the block.
+__device__ inline uint32_t decode_sym(Window &br, const DecLds &t, const uint16_t *gsym, bool *bad) {
   const uint32_t v = br.peek();
   const uint32_t e = t.lut[v >> (32 - kLutBits)];
   uint32_t len = e & 0xFFu, sym = e >> 8;
@@ -128,8 +129,13 @@ __device__ inline uint32_t decode_sym(Window &br, const DecLds &t, bool *bad, bo
       const uint32_t f = t.first[l], n = t.count[l];
       if (c >= f && c - f < n) {
         const uint32_t idx = t.start[l] + c - f - t.long_base;
-        if (idx < t.long_n) sym = t.long_sym[idx];
-        else *defer = true;
+        if (idx < t.long_n) {
+          sym = t.long_sym[idx];
+        } else {
+          uint32_t gs = gsym[t.long_base + idx];
+          __asm__ volatile("" : "+v"(gs));
+          sym = gs;
+        }
         len = l;
         break;
       }
@@ -189,7 +195,7 @@ __device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, cons
   br.end = s + h.total;
   br.win = win;
   br.pos = 0;
-  bool bad = false, defer = false;
+  bool bad = false;
   uint32_t used_out = 0;
   uint64_t sum = 0;
 
@@ -220,7 +226,7 @@ __device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, cons
 #pragma unroll
       for (int k = 0; k < B2; k++) {
         const bool v = FULL || (uint32_t)k < n2;
-        const uint32_t sym = v ? decode_sym(br, tl, &bad, &defer) : kRadius;
+        const uint32_t sym = v ? decode_sym(br, tl, w.symbols, &bad) : kRadius;
         const T a = Pw[j][k];
         rowold[k] = a;
         const T b = j > 0 ? Pw[j - 1][k] : (T)0;
@@ -268,8 +274,7 @@ __device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, cons
   if (used_out != nout || br.pos > nw * 32u) bad = true;
   const uint64_t *sumdc = (const uint64_t *)(s + h.off_sumdc);
   uint64_t why = 0;
-  if (defer) why = 3;  // decoded again from the start: later symbols are not trusted
-  else if (bad) why = 2;
+  if (bad) why = 2;
   else if (h.abft && sum != sumdc[blk]) {
     why = 1;
     count(w.cnt, C_DET + SDCSZ_T_RECON);
@@ -329,7 +334,7 @@ __device__ __forceinline__ void decode_rows(const uint8_t *__restrict__ s, const
   br.end = s + h.total;
   br.win = win;
   br.pos = 0;
-  bool bad = false, defer = false;
+  bool bad = false;
   uint32_t used_out = 0;
   uint64_t sum = 0;
   const T A0 = beta0 * ((T)0 - c0);
@@ -349,7 +354,7 @@ __device__ __forceinline__ void decode_rows(const uint8_t *__restrict__ s, const
 #pragma unroll
     for (int k = 0; k < B2; k++) {
       const bool v = FULL || (uint32_t)k < n2;
-      const uint32_t sym = v ? decode_sym(br, tl, &bad, &defer) : kRadius;
+      const uint32_t sym = v ? decode_sym(br, tl, w.symbols, &bad) : kRadius;
       const T b = Pr[k], f = fold;  // r(j-1,k), r(j-1,k-1)
       fold = b;
       const T lor = (b + cprev) - f;
@@ -382,8 +387,7 @@ __device__ __forceinline__ void decode_rows(const uint8_t *__restrict__ s, const
   if (used_out != nout || br.pos > nw * 32u) bad = true;
   const uint64_t *sumdc = (const uint64_t *)(s + h.off_sumdc);
   uint64_t why = 0;
-  if (defer) why = 3;  // decoded again from the start: later symbols are not trusted
-  else if (bad) why = 2;
+  if (bad) why = 2;
   else if (h.abft && sum != sumdc[blk]) {
     why = 1;
     count(w.cnt, C_DET + SDCSZ_T_RECON);

@@ -23,7 +23,8 @@ FUNCTIONS = ["sdcsz_max_compressed_size", "sdcsz_compress_workspace_size", "sdcs
              "sdcsz_compress_batch", "sdcsz_decompress_batch_workspace_size",
              "sdcsz_decompress_batch", "sdcsz_strerror", "sdcsz_timing_enable",
              "sdcsz_timing_read", "sdcsz_phase_name"]
-N_PHASES = 8
+N_PHASES = 11
+DEVICE_PHASES = 8  # phases 0..7 are device (kernel) time, 8.. host wall time
 
 
 class SdcszError(RuntimeError):
@@ -45,7 +46,7 @@ class Params(C.Structure):
 
 
 class Timing(C.Structure):
-    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_uint64 * 8)]
+    _fields_ = [("ms", C.c_double * N_PHASES), ("launches", C.c_uint64 * N_PHASES)]
 
 
 class Report(C.Structure):
