@@ -323,6 +323,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed 192-field batch")
     ap.add_argument("--only", choices=["batch", "serve"], help="run one part alone and print its JSON")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--tune-file", help="load launch shapes from this JSON file instead of autotuning")
+    ap.add_argument("--save-tune", help="write the autotuned launch shapes to this JSON file")
     ap.add_argument("--batch-only-batched", action="store_true",
                     help="with --only batch: skip the per-field loop (for profiling the batched calls)")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
@@ -341,7 +344,18 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2010_03144_amd import sdcsz, synth
+    from paper_2010_03144_amd import sdcsz, synth, tune
+
+    tuned = None
+    if args.tune_file:
+        tuned = tune.load(args.tune_file)
+    elif not args.no_autotune:
+        log("autotuning launch shapes")
+        t0 = time.perf_counter()
+        tuned, _ = tune.autotune("cuda:0", log=log)
+        log(f"autotune took {time.perf_counter() - t0:.1f} s")
+        if args.save_tune:
+            tune.save(tuned, args.save_tune)
 
     if args.only == "batch":
         print(json.dumps(batch_bench(sdcsz.Codec("cuda:0"), torch, plain_loop=not args.batch_only_batched)),
@@ -425,6 +439,7 @@ def main():
         "phases_ms_per_step": {p: round(v[0] / args.steps, 4) for p, v in phases.items() if v[1]},
         "host_ms_per_step": {p: round(v[0] / args.steps, 4) for p, v in phases.items() if p.startswith("host")},
         "source_digest": digest,
+        "launch_shapes": tuned,
     }
 
     if args.copy_probe:

@@ -239,6 +239,25 @@ uint64_t sdcsz_decompress_batch_workspace_size(const sdcsz_params *h_params, uin
 int sdcsz_decompress_batch(sdcsz_dec_item *h_items, uint32_t n, void *d_ws, uint64_t ws_size,
                            void *stream);
 
+/*
+ * Launch shapes of the block-shape-specialised kernels (set by an
+ * autotuner; they never change a result).  stage: 0 prediction and
+ * quantization, 1 code check, 2 encoding, 3 decoding.  shape_class: 0 the
+ * 6x6x6 3D kernels, 1 the 16x16 2D kernels.  dtype: SDCSZ_F32 or SDCSZ_F64.
+ * A launch over `blocks` blocks (summed over the fields of a batch that share
+ * the kernel) runs lanes[i] lanes per work-group, one block per lane, for the
+ * first i with blocks <= max_blocks[i], and 256 lanes beyond the last entry.
+ * n <= SDCSZ_TUNE_MAX entries with strictly ascending max_blocks and lanes
+ * 64, 128 or 256 (host arrays, copied); n = 0 restores the default.
+ * Process-wide state: set it while no call is running.  Returns SDCSZ_OK or
+ * SDCSZ_EINVAL.
+ */
+#define SDCSZ_TUNE_MAX 8
+int sdcsz_tune_set(int stage, int shape_class, int dtype, uint32_t n, const uint64_t *max_blocks,
+                   const uint32_t *lanes);
+/* The current entries (max_blocks and lanes hold SDCSZ_TUNE_MAX entries). */
+int sdcsz_tune_get(int stage, int shape_class, int dtype, uint32_t *n, uint64_t *max_blocks, uint32_t *lanes);
+
 /* Human-readable name of a return code. */
 const char *sdcsz_strerror(int code);
 

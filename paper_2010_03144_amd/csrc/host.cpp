@@ -328,10 +328,29 @@ const JobKernel kEncFast[kClasses][2] = {{k_encode_fast<float, 3, 6, 6, 6>, k_en
 const JobKernel kDecFast[kClasses][2] = {{k_decode_fast<float, 3, 6, 6, 6>, k_decode_fast<double, 3, 6, 6, 6>},
                                          {k_decode_fast<float, 2, 1, 16, 16>, k_decode_fast<double, 2, 1, 16, 16>}};
 
+// Lanes per work-group (one block per lane) of the specialised kernels, by
+// stage, shape class and data type: the first entry whose max_blocks holds
+// the launch's block count, 256 beyond the last (set by the autotuner).
+constexpr int kTuneStages = 4;  // prediction/quantization, code check, encoding, decoding
+enum { TS_PREDICT, TS_CHECK, TS_ENCODE, TS_DECODE };
+struct TuneRow {
+  uint32_t n = 0;
+  uint64_t max_blocks[SDCSZ_TUNE_MAX] = {};
+  uint32_t lanes[SDCSZ_TUNE_MAX] = {};
+};
+TuneRow g_tune[kTuneStages][kClasses][2];
+
+uint32_t tuned_lanes(int stage, int cls, uint32_t dtype, uint64_t blocks) {
+  const TuneRow &r = g_tune[stage][cls][dtype];
+  for (uint32_t i = 0; i < r.n; i++)
+    if (blocks <= r.max_blocks[i]) return r.lanes[i];
+  return 256;
+}
+
 // One launch of a specialised kernel: the first work-groups take the
 // sub-grid of full blocks, the others the shell of partial blocks along the
-// upper faces.  Returns the number of work-groups of 256 lanes.
-uint32_t fast_launch(const Geo &g, Launch *L) {
+// upper faces.  Returns the number of work-groups of `lanes` lanes.
+uint32_t fast_launch(const Geo &g, Launch *L, uint32_t lanes) {
   bool part[3];
   std::memset(L, 0, sizeof(*L));
   for (int a = 0; a < 3; a++) {
@@ -343,8 +362,8 @@ uint32_t fast_launch(const Geo &g, Launch *L) {
   L->s1 = part[1] ? (uint64_t)g.nb[0] * L->nf[2] : 0;
   const uint64_t s0 = part[0] ? (uint64_t)L->nf[1] * L->nf[2] : 0;
   L->shell_count = L->s2 + L->s1 + s0;
-  L->full_wgs = (uint32_t)((L->full_count + 255) / 256);
-  return L->full_wgs + (uint32_t)((L->shell_count + 255) / 256);
+  L->full_wgs = (uint32_t)((L->full_count + lanes - 1) / lanes);
+  return L->full_wgs + (uint32_t)((L->shell_count + lanes - 1) / lanes);
 }
 
 uint32_t scan_chunks(uint64_t nb) { return (uint32_t)((nb + kScanChunk - 1) / kScanChunk); }
@@ -690,7 +709,6 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     J.plan.n = (uint32_t)f.plan.size();
     J.plan.f = (const sdcsz_fault *)(w + f.L.plan);
     J.plan.bits = (const uint32_t *)(w + f.L.bits);
-    if (f.fast) fast_launch(f.g, &J.L);
     Header &h = J.h;
     h.dtype = c.p->dtype;
     h.ndim = c.p->ndim;
@@ -740,14 +758,29 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   // ---- stage A tables: zero, range + constants, prediction/quantization,
   // re-runs, histogram compaction
   Tab t_zero, t_range[2], t_fast[kClasses][2][2], t_gen[2], t_redo[2], t_hist, t_hchunk;  // t_hist: one work-group per job
+  uint64_t nb_fast[kClasses][2][2] = {}, nb_cls[kClasses] = {}, nb_enc[kClasses][2] = {};
+  for (uint32_t j = 0; j < nj; j++)
+    if (fp[j].fast) {
+      nb_fast[fp[j].cls][jobs[j].dtype][jobs[j].abft ? 1 : 0] += fp[j].g.n_blocks;
+      nb_cls[fp[j].cls] += fp[j].g.n_blocks;
+      nb_enc[fp[j].cls][jobs[j].dtype] += fp[j].g.n_blocks;
+    }
+  uint32_t ln_fast[kClasses][2][2], ln_chk[kClasses], ln_enc[kClasses][2];
+  for (int c = 0; c < kClasses; c++) {
+    ln_chk[c] = tuned_lanes(TS_CHECK, c, 0, nb_cls[c]);
+    for (int d = 0; d < 2; d++) {
+      ln_enc[c][d] = tuned_lanes(TS_ENCODE, c, d, nb_enc[c][d]);
+      for (int a = 0; a < 2; a++) ln_fast[c][d][a] = tuned_lanes(TS_PREDICT, c, d, nb_fast[c][d][a]);
+    }
+  }
   for (uint32_t j = 0; j < nj; j++) {
-    const Job &J = jobs[j];
+    Job &J = jobs[j];
     const CompPlan &f = fp[j];
     t_zero.add(j, std::min<uint64_t>(64, grid_for(J.zero_words, 256)));
     if (J.eb_mode == SDCSZ_REL && f.g.n_values) t_range[J.dtype].add(j, J.nparts);
     if (f.fast) {
-      Launch L;
-      t_fast[f.cls][J.dtype][J.abft ? 1 : 0].add(j, fast_launch(f.g, &L));
+      const int a = J.abft ? 1 : 0;
+      t_fast[f.cls][J.dtype][a].add(j, fast_launch(f.g, &J.L, ln_fast[f.cls][J.dtype][a]));
       t_redo[J.dtype].add(j, 1);
     } else if (f.g.n_blocks) {
       t_gen[J.dtype].add(j, grid_for(f.g.n_blocks, 64));
@@ -804,7 +837,8 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
           if (!t.total()) continue;
           const JobTab jt = d_fast[(c * 2 + d) * 2 + a];
           const JobKernel k = kCompFast[c][d][a];
-          pl.fs.push_back([&t, jt, k, st, &grid](bool x, bool y) { launch(PH_PREDICT, x, y, k, grid(t), dim3(256), st, jt); });
+          const uint32_t ln = ln_fast[c][d][a];
+          pl.fs.push_back([&t, jt, k, ln, st, &grid](bool x, bool y) { launch(PH_PREDICT, x, y, k, grid(t), dim3(ln), st, jt); });
         }
     if (t_gen[0].total())
       pl.fs.push_back([&](bool a, bool b) { launch(PH_PREDICT, a, b, k_compress_generic<float>, grid(t_gen[0]), dim3(64), st, d_gen[0]); });
@@ -876,8 +910,8 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     const CompPlan &f = fp[j];
     if (J.n_sym) t_put.add(j, grid_for(J.n_sym, 256));
     if (f.fast) {
-      t_chk_fast[f.cls].add(j, grid_for(f.g.n_blocks, 256));
-      t_enc_fast[f.cls][J.dtype].add(j, grid_for(f.g.n_blocks, 256));
+      t_chk_fast[f.cls].add(j, grid_for(f.g.n_blocks, ln_chk[f.cls]));
+      t_enc_fast[f.cls][J.dtype].add(j, grid_for(f.g.n_blocks, ln_enc[f.cls][J.dtype]));
     } else if (f.g.n_blocks) {
       t_chk_gen.add(j, grid_for(f.g.n_blocks, 256));
       t_enc_gen[J.dtype].add(j, grid_for(f.g.n_blocks, 256));
@@ -904,7 +938,8 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
       if (!t.total()) continue;
       const JobTab jt = D[8 + 3 * c];
       const JobKernel k = kCheckFast[c];
-      pl.fs.push_back([&t, jt, k, st, &grid](bool x, bool y) { launch(PH_CHECK, x, y, k, grid(t), dim3(256), st, jt); });
+      const uint32_t ln = ln_chk[c];
+      pl.fs.push_back([&t, jt, k, ln, st, &grid](bool x, bool y) { launch(PH_CHECK, x, y, k, grid(t), dim3(ln), st, jt); });
     }
     if (t_chk_gen.total())
       pl.fs.push_back([&](bool a, bool b) { launch(PH_CHECK, a, b, k_codes_check, grid(t_chk_gen), dim3(256), st, D[1]); });
@@ -922,7 +957,8 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
         if (!t.total()) continue;
         const JobTab jt = D[8 + 3 * c + 1 + d];
         const JobKernel k = kEncFast[c][d];
-        pl.fs.push_back([&t, jt, k, st, &grid](bool x, bool y) { launch(PH_ENCODE, x, y, k, grid(t), dim3(256), st, jt); });
+        const uint32_t ln = ln_enc[c][d];
+        pl.fs.push_back([&t, jt, k, ln, st, &grid](bool x, bool y) { launch(PH_ENCODE, x, y, k, grid(t), dim3(ln), st, jt); });
       }
     if (t_enc_gen[0].total())
       pl.fs.push_back([&](bool a, bool b) { launch(PH_ENCODE, a, b, k_encode<float>, grid(t_enc_gen[0]), dim3(256), st, D[5]); });
@@ -1121,7 +1157,6 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     J.plan.n = (uint32_t)f.plan.size();
     J.plan.f = (const sdcsz_fault *)(w + f.L.plan);
     J.plan.bits = (const uint32_t *)(w + f.L.bits);
-    if (f.fast) fast_launch(d.g, &J.L);
     J.reg = d.reg;
     J.mode = d.mode;
     const uint32_t *table = (const uint32_t *)(d.d_stream + d.h.off_table);
@@ -1151,14 +1186,19 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     }
   }
   Tab t_zero, t_one, t_s1, t_fast[kClasses][2], t_gen[2], t_redo[2];
+  uint64_t nb_dec[kClasses][2] = {};
+  for (uint32_t j = 0; j < nj; j++)
+    if (fp[j].fast) nb_dec[fp[j].cls][jobs[j].dtype] += jobs[j].g.n_blocks;
+  uint32_t ln_dec[kClasses][2];
+  for (int c = 0; c < kClasses; c++)
+    for (int d = 0; d < 2; d++) ln_dec[c][d] = tuned_lanes(TS_DECODE, c, d, nb_dec[c][d]);
   for (uint32_t j = 0; j < nj; j++) {
-    const Job &J = jobs[j];
+    Job &J = jobs[j];
     t_zero.add(j, 1);
     t_one.add(j, 1);
     t_s1.add(j, scan_chunks(J.g.n_blocks));
     if (fp[j].fast) {
-      Launch L;
-      t_fast[fp[j].cls][J.dtype].add(j, fast_launch(J.g, &L));
+      t_fast[fp[j].cls][J.dtype].add(j, fast_launch(J.g, &J.L, ln_dec[fp[j].cls][J.dtype]));
       t_redo[J.dtype].add(j, kMaxRedo / 64);  // one thread per queue slot
     } else if (J.g.n_blocks) {
       t_gen[J.dtype].add(j, grid_for(J.g.n_blocks, 64));
@@ -1202,7 +1242,8 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
         if (!t.total()) continue;
         const JobTab jt = D[7 + 2 * c + d];
         const JobKernel k = kDecFast[c][d];
-        pl.fs.push_back([&t, jt, k, st, &grid](bool x, bool y) { launch(PH_DECODE, x, y, k, grid(t), dim3(256), st, jt); });
+        const uint32_t ln = ln_dec[c][d];
+        pl.fs.push_back([&t, jt, k, ln, st, &grid](bool x, bool y) { launch(PH_DECODE, x, y, k, grid(t), dim3(ln), st, jt); });
       }
     if (t_gen[0].total())
       pl.fs.push_back([&](bool a, bool b) { launch(PH_DECODE, a, b, k_decode_generic<float>, grid(t_gen[0]), dim3(64), st, D[3]); });
@@ -1291,6 +1332,38 @@ const char *sdcsz_strerror(int code) {
     case SDCSZ_EHIP: return "HIP runtime error";
     default: return "unknown error";
   }
+}
+
+int sdcsz_tune_set(int stage, int shape_class, int dtype, uint32_t n, const uint64_t *max_blocks,
+                   const uint32_t *lanes) {
+  if (stage < 0 || stage >= kTuneStages || shape_class < 0 || shape_class >= kClasses || dtype < 0 || dtype > 1 ||
+      n > SDCSZ_TUNE_MAX || (n && (!max_blocks || !lanes)))
+    return SDCSZ_EINVAL;
+  for (uint32_t i = 0; i < n; i++) {
+    if (lanes[i] != 64 && lanes[i] != 128 && lanes[i] != 256) return SDCSZ_EINVAL;
+    if (i && max_blocks[i] <= max_blocks[i - 1]) return SDCSZ_EINVAL;
+  }
+  TuneRow r;
+  r.n = n;
+  for (uint32_t i = 0; i < n; i++) {
+    r.max_blocks[i] = max_blocks[i];
+    r.lanes[i] = lanes[i];
+  }
+  g_tune[stage][shape_class][dtype] = r;
+  return SDCSZ_OK;
+}
+
+int sdcsz_tune_get(int stage, int shape_class, int dtype, uint32_t *n, uint64_t *max_blocks, uint32_t *lanes) {
+  if (stage < 0 || stage >= kTuneStages || shape_class < 0 || shape_class >= kClasses || dtype < 0 || dtype > 1 ||
+      !n || !max_blocks || !lanes)
+    return SDCSZ_EINVAL;
+  const TuneRow &r = g_tune[stage][shape_class][dtype];
+  *n = r.n;
+  for (uint32_t i = 0; i < r.n; i++) {
+    max_blocks[i] = r.max_blocks[i];
+    lanes[i] = r.lanes[i];
+  }
+  return SDCSZ_OK;
 }
 
 void sdcsz_timing_enable(int on) {

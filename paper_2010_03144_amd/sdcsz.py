@@ -22,8 +22,11 @@ FUNCTIONS = ["sdcsz_max_compressed_size", "sdcsz_compress_workspace_size", "sdcs
              "sdcsz_verify", "sdcsz_decompress_region", "sdcsz_compress_batch_workspace_size",
              "sdcsz_compress_batch", "sdcsz_decompress_batch_workspace_size",
              "sdcsz_decompress_batch", "sdcsz_strerror", "sdcsz_timing_enable",
-             "sdcsz_timing_read", "sdcsz_phase_name"]
+             "sdcsz_timing_read", "sdcsz_phase_name", "sdcsz_tune_set", "sdcsz_tune_get"]
 N_PHASES = 11
+TUNE_MAX = 8
+TUNE_STAGES = ["predict", "check", "encode", "decode"]
+SHAPE_CLASSES = [((6, 6, 6), 3), ((16, 16), 2)]  # (block, ndim) of the specialised kernels
 DEVICE_PHASES = 8  # phases 0..7 are device (kernel) time, 8.. host wall time
 
 
@@ -110,6 +113,8 @@ def lib():
         L.sdcsz_timing_read.restype = None
         L.sdcsz_phase_name.argtypes = [C.c_int]
         L.sdcsz_phase_name.restype = C.c_char_p
+        L.sdcsz_tune_set.argtypes = [C.c_int, C.c_int, C.c_int, C.c_uint32, P(C.c_uint64), P(C.c_uint32)]
+        L.sdcsz_tune_get.argtypes = [C.c_int, C.c_int, C.c_int, P(C.c_uint32), P(C.c_uint64), P(C.c_uint32)]
         _lib = L
     return _lib
 
@@ -411,6 +416,24 @@ def timing_read():
     t = Timing()
     L.sdcsz_timing_read(C.byref(t))
     return {L.sdcsz_phase_name(i).decode(): (t.ms[i], t.launches[i]) for i in range(N_PHASES)}
+
+
+def tune_set(stage, shape_class, dtype, entries):
+    """entries: [(max_blocks, lanes), ...] ascending; [] restores the default."""
+    m = max(len(entries), 1)
+    mb = (C.c_uint64 * m)(*[int(e[0]) for e in entries])
+    ln = (C.c_uint32 * m)(*[int(e[1]) for e in entries])
+    return lib().sdcsz_tune_set(stage, shape_class, dtype, len(entries), mb, ln)
+
+
+def tune_get(stage, shape_class, dtype):
+    n = C.c_uint32(0)
+    mb = (C.c_uint64 * TUNE_MAX)()
+    ln = (C.c_uint32 * TUNE_MAX)()
+    rc = lib().sdcsz_tune_get(stage, shape_class, dtype, C.byref(n), mb, ln)
+    if rc != OK:
+        raise SdcszError(rc, "sdcsz_tune_get")
+    return [(int(mb[i]), int(ln[i])) for i in range(n.value)]
 
 
 def strerror(rc):

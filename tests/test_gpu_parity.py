@@ -349,3 +349,32 @@ def test_batch_item_errors_stay_per_item(codec):
     assert res[0][0] == 0 and res[1][0] == sdcsz.EINVAL
     rc_r, s_r, _ = ref.compress(good.cpu().numpy(), (6, 6, 6), 1e-3)
     assert np.array_equal(res[0][1].cpu().numpy(), s_r)
+
+
+@pytest.mark.parametrize("lanes", [64, 128])
+def test_launch_shape_does_not_change_results(codec, lanes):
+    from paper_2010_03144_amd import tune
+    cases = [(synth.grf_field((50, 47, 44), seed=21), (6, 6, 6)),
+             (synth.grf_field((50, 47, 44), seed=22, dtype=np.float64), (6, 6, 6)),
+             (synth.grf_field((300, 417), seed=23), (16, 16)),
+             (synth.grf_field((300, 417), seed=24, dtype=np.float64), (16, 16))]
+    ref_out = []
+    for x, block in cases:
+        rc, s, _ = codec.compress(torch.from_numpy(x).cuda(), block, 1e-3)
+        assert rc == 0
+        rc, y, _ = codec.decompress(s)
+        ref_out.append((s.cpu().numpy(), y.cpu().numpy()))
+    try:
+        for si in range(len(sdcsz.TUNE_STAGES)):
+            for ci in range(len(sdcsz.SHAPE_CLASSES)):
+                for dt in (0, 1):
+                    assert sdcsz.tune_set(si, ci, dt, [(tune.UNBOUNDED, lanes)]) == sdcsz.OK
+        for (x, block), (s_ref, y_ref) in zip(cases, ref_out):
+            print(f"case lanes={lanes} shape={x.shape} dtype={x.dtype}", flush=True)
+            rc, s, _ = codec.compress(torch.from_numpy(x).cuda(), block, 1e-3)
+            assert rc == 0
+            assert np.array_equal(s.cpu().numpy(), s_ref), first_difference(s_ref, s.cpu().numpy())
+            rc, y, _ = codec.decompress(s)
+            assert rc == 0 and np.array_equal(y.cpu().numpy().view(np.uint8), y_ref.view(np.uint8))
+    finally:
+        tune.reset()
