@@ -43,25 +43,37 @@ enum { SDCSZ_ABS = 0, SDCSZ_REL = 1 };
 enum { SDCSZ_PRED_AUTO = 0, SDCSZ_PRED_LORENZO = 1, SDCSZ_PRED_REGRESSION = 2 };
 
 /* Fault-injection targets (evaluation mode A, Sec. 6.1; decompression errors,
- * Sec. 5.3).  A plan is plain data applied at fixed program points. */
+ * Sec. 5.3; errors in the prediction preparation, Sec. 4.1 and 4.2).  A plan
+ * is plain data applied at fixed program points. */
 enum {
-  SDCSZ_T_INPUT = 0,     /* input word, after the block's input checksums     */
+  SDCSZ_T_INPUT = 0,     /* input word, after the block's input checksums and
+                            after predictor selection                          */
   SDCSZ_T_COEF = 1,      /* regression-coefficient word, after its checksums  */
   SDCSZ_T_CODE = 2,      /* quantization code at rest, before encoding        */
   SDCSZ_T_RECON = 3,     /* decompressed word, before its checksum            */
   SDCSZ_T_DUP_PRED = 4,  /* first copy of the duplicated prediction           */
   SDCSZ_T_DUP_RECON = 5, /* first copy of the duplicated reconstruction       */
-  SDCSZ_N_TARGETS = 6
+  SDCSZ_T_PREP_INPUT = 6,  /* input word, after the input checksums but before
+                              regression and sampling read it (the memory
+                              error persists until the input is checked)     */
+  SDCSZ_T_PREP_COEF = 7,   /* computed regression coefficient, before its
+                              checksums are taken (a computation error)      */
+  SDCSZ_T_PREP_SAMPLE = 8, /* sampled error estimate before the predictor
+                              comparison (a computation error): word 0 the
+                              Lorenzo estimate, word 1 the regression one    */
+  SDCSZ_N_TARGETS = 9
 };
 
 typedef struct {
   uint32_t target; /* SDCSZ_T_*                                                 */
   uint32_t bit;    /* bit to flip: < 32 for word targets (CODE: taken mod 16),
-                      < 32 * words-per-value for DUP_* targets                  */
+                      < 32 * words-per-value for DUP_* targets, < 64 for
+                      PREP_SAMPLE (the estimates are 64-bit integers)          */
   uint64_t block;  /* linear block id (C order over the block grid)             */
-  uint64_t word;   /* INPUT/RECON: 32-bit word in the block (FP64: 2 per value,
-                      low half first); COEF: word of the 4 coefficients;
-                      CODE/DUP_*: point index (C order inside the block)        */
+  uint64_t word;   /* INPUT/PREP_INPUT/RECON: 32-bit word in the block (FP64: 2
+                      per value, low half first); COEF/PREP_COEF: word of the
+                      4 coefficients; CODE/DUP_*: point index (C order inside
+                      the block); PREP_SAMPLE: 0 or 1                          */
 } sdcsz_fault;
 
 typedef struct {
@@ -73,8 +85,8 @@ typedef struct {
   uint32_t predictor; /* SDCSZ_PRED_*                                           */
   double eb;          /* error bound: finite and > 0                            */
   uint32_t abft;      /* 1: checksums + instruction duplication (ftrsz); 0: not */
-  uint32_t n_faults;  /* entries in `faults` (compression uses INPUT, COEF, CODE,
-                         DUP_PRED, DUP_RECON; other targets are ignored)        */
+  uint32_t n_faults;  /* entries in `faults` (compression uses every target but
+                         RECON, which it ignores)                               */
   const sdcsz_fault *faults; /* host array, NULL when n_faults == 0             */
 } sdcsz_params;
 

@@ -11,8 +11,8 @@ import numpy as np
 
 from . import build_oracle
 
-TARGETS = ["input", "coef", "code", "recon", "dup_pred", "dup_recon"]
-T_INPUT, T_COEF, T_CODE, T_RECON, T_DUP_PRED, T_DUP_RECON = range(6)
+TARGETS = ["input", "coef", "code", "recon", "dup_pred", "dup_recon", "prep_input", "prep_coef", "prep_sample"]
+T_INPUT, T_COEF, T_CODE, T_RECON, T_DUP_PRED, T_DUP_RECON, T_PREP_INPUT, T_PREP_COEF, T_PREP_SAMPLE = range(9)
 OK, EINVAL, ENOSPC, EFORMAT, ESDC = 0, -1, -2, -3, -4
 
 
@@ -29,9 +29,9 @@ class Params(C.Structure):
 
 
 class Report(C.Structure):
-    _fields_ = [("n_blocks", C.c_uint64), ("injected", C.c_uint64 * 6),
-                ("detected", C.c_uint64 * 6), ("corrected", C.c_uint64 * 6),
-                ("uncorrectable", C.c_uint64 * 6), ("n_outliers", C.c_uint64),
+    _fields_ = [("n_blocks", C.c_uint64), ("injected", C.c_uint64 * len(TARGETS)),
+                ("detected", C.c_uint64 * len(TARGETS)), ("corrected", C.c_uint64 * len(TARGETS)),
+                ("uncorrectable", C.c_uint64 * len(TARGETS)), ("n_outliers", C.c_uint64),
                 ("n_regression", C.c_uint64), ("payload_words", C.c_uint64),
                 ("stream_size", C.c_uint64), ("eb_abs", C.c_double)]
 

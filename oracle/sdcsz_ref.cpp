@@ -568,18 +568,45 @@ int compress_impl(const T *in, const ref_params *p, const Geometry &g, uint8_t *
   std::vector<BlockOut<T>> B(g.n_blocks);
   std::vector<T> xb, rb;
 
-  /* Loop 1: regression coefficients and input checksums of every block. */
+  /* Loop 1: input checksums and regression coefficients of every block.
+   * Errors in the prediction preparation (Sec. 4.1, 4.2): a PREP_INPUT flip
+   * strikes the input memory after its checksums were taken, so the
+   * regression and the sampling read the corrupted word (and the third loop
+   * finds it); a PREP_COEF flip is a computation error in the coefficients,
+   * made before their checksums are taken. */
   for (uint64_t blk = 0; blk < g.n_blocks; blk++) {
     BlockBox bb = block_box(g, blk);
     xb.resize(bb.pts);
     for (uint64_t i = 0, q = 0; i < bb.n[0]; i++)
       for (uint64_t j = 0; j < bb.n[1]; j++)
         for (uint64_t k = 0; k < bb.n[2]; k++) xb[q++] = X[field_index(g, bb, i, j, k)];
-    regression<T>(xb.data(), bb.n, B[blk].coef);
     if (abft) {
       std::vector<uint32_t> w(bb.pts * W<T>::per);
       for (uint64_t q = 0; q < bb.pts; q++) W<T>::put(xb[q], &w[q * W<T>::per]);
       sdcsz_ref_checksums(w.data(), w.size(), &B[blk].sum_in, &B[blk].isum_in);
+    }
+    for (auto &f : faults.list) {
+      if (f.block != blk || f.target != REF_T_PREP_INPUT) continue;
+      uint64_t q = f.word / W<T>::per;
+      uint64_t k = q % bb.n[2], j = (q / bb.n[2]) % bb.n[1], i = q / (bb.n[2] * bb.n[1]);
+      uint64_t at = field_index(g, bb, i, j, k);
+      uint32_t w[2] = {0, 0};
+      W<T>::put(X[at], w);
+      w[f.word % W<T>::per] ^= 1u << (f.bit % 32);
+      X[at] = W<T>::get(w);
+      xb[q] = X[at];
+      rep->injected[REF_T_PREP_INPUT]++;
+    }
+    regression<T>(xb.data(), bb.n, B[blk].coef);
+    for (auto &f : faults.list) {
+      if (f.block != blk || f.target != REF_T_PREP_COEF) continue;
+      uint32_t cw[8];
+      for (int a = 0; a < 4; a++) W<T>::put(B[blk].coef[a], &cw[a * W<T>::per]);
+      cw[f.word] ^= 1u << (f.bit % 32);
+      for (int a = 0; a < 4; a++) B[blk].coef[a] = W<T>::get(&cw[a * W<T>::per]);
+      rep->injected[REF_T_PREP_COEF]++;
+    }
+    if (abft) {
       uint32_t cw[8];
       for (int a = 0; a < 4; a++) W<T>::put(B[blk].coef[a], &cw[a * W<T>::per]);
       sdcsz_ref_checksums(cw, 4 * W<T>::per, &B[blk].sum_c, &B[blk].isum_c);
@@ -608,6 +635,11 @@ int compress_impl(const T *in, const ref_params *p, const Geometry &g, uint8_t *
       T pr = regression_predict<T>(B[blk].coef, c, i, j, k);
       e_lor += sample_cost<T>(x - pl, K.inv_e);
       e_reg += sample_cost<T>(x - pr, K.inv_e);
+    }
+    for (auto &f : faults.list) {  /* computation errors in the estimates */
+      if (f.block != blk || f.target != REF_T_PREP_SAMPLE) continue;
+      (f.word == 0 ? e_lor : e_reg) ^= 1ull << (f.bit % 64);
+      rep->injected[REF_T_PREP_SAMPLE]++;
     }
     B[blk].is_reg = e_reg <= e_lor;
   }
@@ -647,9 +679,11 @@ int compress_impl(const T *in, const ref_params *p, const Geometry &g, uint8_t *
       std::vector<uint32_t> w(bb.pts * W<T>::per);
       for (uint64_t q = 0; q < bb.pts; q++) W<T>::put(xb[q], &w[q * W<T>::per]);
       int st = sdcsz_ref_correct(w.data(), w.size(), o.sum_in, o.isum_in, 32);
-      if (st != 0) rep->detected[REF_T_INPUT]++;
-      if (st == 1) rep->corrected[REF_T_INPUT]++;
-      if (st < 0) { rep->uncorrectable[REF_T_INPUT]++; n_unc++; }
+      /* a detection in a block struck before its preparation counts there */
+      const int ti = faults.any(REF_T_PREP_INPUT, blk) ? REF_T_PREP_INPUT : REF_T_INPUT;
+      if (st != 0) rep->detected[ti]++;
+      if (st == 1) rep->corrected[ti]++;
+      if (st < 0) { rep->uncorrectable[ti]++; n_unc++; }
       for (uint64_t q = 0; q < bb.pts; q++) xb[q] = W<T>::get(&w[q * W<T>::per]);
       uint32_t cw[8];
       for (int a = 0; a < 4; a++) W<T>::put(o.coef[a], &cw[a * W<T>::per]);
@@ -1081,11 +1115,16 @@ bool valid_params(const ref_params *p, Geometry *g) {
     uint32_t per = p->dtype == 0 ? 1 : 2;
     switch (f.target) {
       case REF_T_INPUT:
+      case REF_T_PREP_INPUT:
       case REF_T_RECON:
         if (f.word >= bb.pts * per || f.bit >= 32) return false;
         break;
       case REF_T_COEF:
+      case REF_T_PREP_COEF:
         if (f.word >= 4ull * per || f.bit >= 32) return false;
+        break;
+      case REF_T_PREP_SAMPLE:
+        if (f.word >= 2 || f.bit >= 64) return false;
         break;
       case REF_T_CODE:
         if (f.word >= bb.pts || f.bit >= 32) return false;

@@ -33,7 +33,12 @@ enum {
   REF_T_RECON = 3,     /* decompressed word before its checksum          */
   REF_T_DUP_PRED = 4,  /* first copy of the duplicated prediction        */
   REF_T_DUP_RECON = 5, /* first copy of the duplicated reconstruction    */
-  REF_N_TARGETS = 6
+  REF_T_PREP_INPUT = 6,  /* input word after its checksums, before the
+                            regression and the sampling read it           */
+  REF_T_PREP_COEF = 7,   /* computed coefficient before its checksums     */
+  REF_T_PREP_SAMPLE = 8, /* sampled estimate (word 0 Lorenzo, 1 regression,
+                            bit < 64) before the predictor comparison     */
+  REF_N_TARGETS = 9
 };
 enum { REF_OK = 0, REF_EINVAL = -1, REF_ENOSPC = -2, REF_EFORMAT = -3, REF_ESDC = -4 };
 

@@ -41,6 +41,13 @@ template <typename T> struct BlockReader {
   }
 };
 
+// The block's values as the regression and the sampling read them (through
+// the reader: prediction-preparation input faults are visible there).
+template <typename T> __device__ inline T prep_at(const BlockReader<T> &rd, const Box &b, uint32_t i, uint32_t j,
+                                                  uint32_t k) {
+  return rd.get((i * b.n[1] + j) * b.n[2] + k, i, j, k);
+}
+
 template <typename T>
 __device__ void regression_generic(const BlockReader<T> &rd, const Box &b, const RegTab<T> &rt, T coef[4]) {
   const T *c = rt.c[b.pat];
@@ -49,13 +56,13 @@ __device__ void regression_generic(const BlockReader<T> &rd, const Box &b, const
     T P = 0, A = 0, B = 0;
     for (uint32_t j = 0; j < b.n[1]; j++) {
       T R = 0;
-      for (uint32_t k = 0; k < b.n[2]; k++) R = R + rd.raw(i, j, k);
+      for (uint32_t k = 0; k < b.n[2]; k++) R = R + prep_at(rd, b, i, j, k);
       P = P + R;
       A = A + ((T)j - c[1]) * R;
     }
     for (uint32_t k = 0; k < b.n[2]; k++) {
       T D = 0;
-      for (uint32_t j = 0; j < b.n[1]; j++) D = D + rd.raw(i, j, k);
+      for (uint32_t j = 0; j < b.n[1]; j++) D = D + prep_at(rd, b, i, j, k);
       B = B + ((T)k - c[2]) * D;
     }
     S0 = S0 + P;
@@ -114,9 +121,35 @@ __device__ __noinline__ void compress_block_generic(const T *__restrict__ in, co
   rd.fixed = false;
   const uint64_t nw = (uint64_t)b.pts * Wd<T>::per;
 
+  // ---- prediction-preparation faults: input words flipped after the input
+  // checksums (taken below from the memory as it was) but before the
+  // regression and the sampling read them
+  const bool hit = plan_hit(plan, blk);
+  const uint32_t pfirst = hit ? plan_first(plan, blk) : 0;
+  bool prep_in = false;
+  if (hit)
+    for (uint32_t t = pfirst; t < plan.n && plan.f[t].block == blk; t++)
+      if (plan.f[t].target == SDCSZ_T_PREP_INPUT && rd.np < kMaxPatches) {
+        rd.pj[rd.np] = plan.f[t].word;
+        rd.pm[rd.np] = 1u << (plan.f[t].bit & 31);
+        rd.np++;
+        prep_in = true;
+        count(w.cnt, C_INJ + SDCSZ_T_PREP_INPUT);
+      }
+  const int t_in = prep_in ? SDCSZ_T_PREP_INPUT : SDCSZ_T_INPUT;  // where a detection is counted
+
   // ---- first loop: regression coefficients + input/coefficient checksums
   T coef[4];
   regression_generic<T>(rd, b, rt, coef);
+  if (hit)  // computation errors in the regression, before its checksums
+    for (uint32_t t = pfirst; t < plan.n && plan.f[t].block == blk; t++)
+      if (plan.f[t].target == SDCSZ_T_PREP_COEF) {
+        uint32_t cw[8];
+        for (int a = 0; a < 4; a++) Wd<T>::split(coef[a], cw + a * Wd<T>::per);
+        cw[plan.f[t].word] ^= 1u << (plan.f[t].bit & 31);
+        for (int a = 0; a < 4; a++) coef[a] = Wd<T>::join(cw + a * Wd<T>::per);
+        count(w.cnt, C_INJ + SDCSZ_T_PREP_COEF);
+      }
   uint64_t s_in = 0, is_in = 0, s_c = 0, is_c = 0;
   if (abft) {
     for (uint32_t i = 0, p = 0; i < b.n[0]; i++)
@@ -148,10 +181,10 @@ __device__ __noinline__ void compress_block_generic(const T *__restrict__ in, co
   else {
     uint64_t e_lor = 0, e_reg = 0, ns = 0;
     auto orig = [&](int i, int j, int k) -> T {
-      return (i < 0 || j < 0 || k < 0) ? (T)0 : rd.raw((uint32_t)i, (uint32_t)j, (uint32_t)k);
+      return (i < 0 || j < 0 || k < 0) ? (T)0 : prep_at(rd, b, (uint32_t)i, (uint32_t)j, (uint32_t)k);
     };
     auto sample = [&](uint32_t i, uint32_t j, uint32_t k) {
-      T x = rd.raw(i, j, k);
+      T x = prep_at(rd, b, i, j, k);
       T pl = lorenzo_gen<T>(orig, g.ndim, (int)i, (int)j, (int)k);
       T pr = reg_pred<T>(coef, c, i, j, k);
       e_lor += cost<T>(x - pl, inv_e);
@@ -183,6 +216,13 @@ __device__ __noinline__ void compress_block_generic(const T *__restrict__ in, co
       }
     }
     e_lor += ns;
+    if (hit)  // computation errors in the sampled estimates
+      for (uint32_t t = pfirst; t < plan.n && plan.f[t].block == blk; t++)
+        if (plan.f[t].target == SDCSZ_T_PREP_SAMPLE) {
+          uint64_t &e = plan.f[t].word == 0 ? e_lor : e_reg;
+          e ^= 1ull << (plan.f[t].bit & 63);
+          count(w.cnt, C_INJ + SDCSZ_T_PREP_SAMPLE);
+        }
     is_reg = e_reg <= e_lor;
   }
 
@@ -224,15 +264,15 @@ __device__ __noinline__ void compress_block_generic(const T *__restrict__ in, co
     uint64_t jf;
     uint32_t vf;
     int st = locate_repair(s2, i2, s_in, is_in, nw, 32, [&](uint64_t j) { return rd.word(j); }, &jf, &vf);
-    if (st != 0) count(w.cnt, C_DET + SDCSZ_T_INPUT);
+    if (st != 0) count(w.cnt, C_DET + t_in);
     if (st == 1) {
       rd.fixed = true;
       rd.fj = jf;
       rd.fv = vf;
-      count(w.cnt, C_COR + SDCSZ_T_INPUT);
+      count(w.cnt, C_COR + t_in);
     }
     if (st < 0) {
-      count(w.cnt, C_UNC + SDCSZ_T_INPUT);
+      count(w.cnt, C_UNC + t_in);
       bad = true;
     }
     uint32_t cw[8];

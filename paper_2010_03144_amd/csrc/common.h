@@ -24,12 +24,13 @@ enum { R_SIZE = 0, R_OUTLIERS, R_REGRESSION, R_WORDS, R_WRITTEN, R_EB, R_N = 8 }
 // Counter slots (u64) in the device report area.
 enum {
   C_INJ = 0,
-  C_DET = 6,
-  C_COR = 12,
-  C_UNC = 18,
-  C_MISSING = 24,  // a code without codeword was met while encoding
-  C_N = 32
+  C_DET = SDCSZ_N_TARGETS,
+  C_COR = 2 * SDCSZ_N_TARGETS,
+  C_UNC = 3 * SDCSZ_N_TARGETS,
+  C_MISSING = 4 * SDCSZ_N_TARGETS,  // a code without codeword was met while encoding
+  C_N = 40
 };
+static_assert(C_MISSING < C_N, "counter layout");
 
 // Block grid of a field normalised to three axes (leading axes of extent 1).
 struct Geo {

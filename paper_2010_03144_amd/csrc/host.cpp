@@ -163,11 +163,16 @@ int check_plan(const Geo &g, uint32_t dtype, const sdcsz_fault *f, uint32_t n, b
     const uint64_t pts = block_pts(g, e.block);
     switch (e.target) {
       case SDCSZ_T_INPUT:
+      case SDCSZ_T_PREP_INPUT:
       case SDCSZ_T_RECON:
         if (e.word >= pts * per || e.bit >= 32) return SDCSZ_EINVAL;
         break;
       case SDCSZ_T_COEF:
+      case SDCSZ_T_PREP_COEF:
         if (e.word >= 4ull * per || e.bit >= 32) return SDCSZ_EINVAL;
+        break;
+      case SDCSZ_T_PREP_SAMPLE:
+        if (e.word >= 2 || e.bit >= 64) return SDCSZ_EINVAL;
         break;
       case SDCSZ_T_CODE:
         if (e.word >= pts || e.bit >= 32) return SDCSZ_EINVAL;
@@ -984,7 +989,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     fill_report(&c.rep, cnt, fp[j].g.n_blocks);
     std::memcpy(&c.rep.eb_abs, &res[R_EB], 8);
     const bool unc = cnt[C_UNC + SDCSZ_T_INPUT] || cnt[C_UNC + SDCSZ_T_COEF] || cnt[C_UNC + SDCSZ_T_CODE] ||
-                     cnt[C_MISSING];
+                     cnt[C_UNC + SDCSZ_T_PREP_INPUT] || cnt[C_MISSING];
     if (unc) {
       c.out_size = 0;
       c.rc = SDCSZ_ESDC;

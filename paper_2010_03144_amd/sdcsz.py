@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsdcsz.so")
 
 OK, EINVAL, ENOSPC, EFORMAT, ESDC, EHIP = 0, -1, -2, -3, -4, -5
-TARGETS = ["input", "coef", "code", "recon", "dup_pred", "dup_recon"]
+TARGETS = ["input", "coef", "code", "recon", "dup_pred", "dup_recon", "prep_input", "prep_coef", "prep_sample"]
 ERRORS = {OK: "ok", EINVAL: "EINVAL", ENOSPC: "ENOSPC", EFORMAT: "EFORMAT", ESDC: "ESDC", EHIP: "EHIP"}
 FUNCTIONS = ["sdcsz_max_compressed_size", "sdcsz_compress_workspace_size", "sdcsz_compress",
              "sdcsz_stream_info", "sdcsz_decompress_workspace_size", "sdcsz_decompress",
@@ -53,9 +53,9 @@ class Timing(C.Structure):
 
 
 class Report(C.Structure):
-    _fields_ = [("n_blocks", C.c_uint64), ("injected", C.c_uint64 * 6),
-                ("detected", C.c_uint64 * 6), ("corrected", C.c_uint64 * 6),
-                ("uncorrectable", C.c_uint64 * 6), ("n_outliers", C.c_uint64),
+    _fields_ = [("n_blocks", C.c_uint64), ("injected", C.c_uint64 * len(TARGETS)),
+                ("detected", C.c_uint64 * len(TARGETS)), ("corrected", C.c_uint64 * len(TARGETS)),
+                ("uncorrectable", C.c_uint64 * len(TARGETS)), ("n_outliers", C.c_uint64),
                 ("n_regression", C.c_uint64), ("payload_words", C.c_uint64),
                 ("stream_size", C.c_uint64), ("eb_abs", C.c_double)]
 

@@ -108,7 +108,21 @@ def linear_field(shape, coeffs, offset=0.0, dtype=np.float32):
 # ---------------------------------------------------------------------------
 # block geometry (index bookkeeping only) and fault plans
 # ---------------------------------------------------------------------------
-TARGET_IDS = {"input": 0, "coef": 1, "code": 2, "recon": 3, "dup_pred": 4, "dup_recon": 5}
+TARGET_IDS = {"input": 0, "coef": 1, "code": 2, "recon": 3, "dup_pred": 4, "dup_recon": 5,
+              "prep_input": 6, "prep_coef": 7, "prep_sample": 8}
+
+
+def _word_bit_range(name, pts, per):
+    """(words, bits) a flip of this target is drawn from."""
+    if name in ("input", "recon", "prep_input"):
+        return pts * per, 32
+    if name in ("coef", "prep_coef"):
+        return 4 * per, 32
+    if name == "prep_sample":
+        return 2, 64
+    if name.startswith("dup"):
+        return pts, 32 * per
+    return pts, 32  # code
 
 
 def block_grid(shape, block):
@@ -135,9 +149,11 @@ def fault_plan(shape, block, dtype, counts, seed=3):
 
     counts: {target name: number of flips}.  Returns an int64 array of rows
     (target, bit, block, word) in the layout of the library's fault record.
-    word ranges: input/recon -> 32-bit words of the block; coef -> the 4
-    coefficients' words; code/dup_* -> point index.  Bits are drawn from the
-    32-bit word (codes use the bit modulo 16); dup_* draw from the whole value.
+    word ranges: input/prep_input/recon -> 32-bit words of the block;
+    coef/prep_coef -> the 4 coefficients' words; code/dup_* -> point index;
+    prep_sample -> 0 (Lorenzo estimate) or 1 (regression estimate).  Bits are
+    drawn from the 32-bit word (codes use the bit modulo 16); dup_* draw from
+    the whole value, prep_sample from the 64-bit estimate.
     """
     rng = np.random.default_rng(seed)
     per = 1 if np.dtype(dtype) == np.float32 else 2
@@ -156,14 +172,9 @@ def fault_plan(shape, block, dtype, counts, seed=3):
             blk = int(blocks[at])
             at += 1
             pts = block_points(shape, block, blk)
-            if name in ("input", "recon"):
-                nwords = pts * per
-            elif name == "coef":
-                nwords = 4 * per
-            else:
-                nwords = pts
+            nwords, nbits = _word_bit_range(name, pts, per)
             word = int(rng.integers(0, nwords))
-            bit = int(rng.integers(0, 32 * per if name.startswith("dup") else 32))
+            bit = int(rng.integers(0, nbits))
             rows.append((tid, bit, blk, word))
     return np.array(rows, dtype=np.int64)
 
@@ -277,9 +288,9 @@ def sparse_fault_plan(shape, block, dtype, counts, seed):
                     taken.add(blk)
                     break
             pts = block_points(shape, block, blk)
-            nwords = pts * per if name in ("input", "recon") else (4 * per if name == "coef" else pts)
+            nwords, nbits = _word_bit_range(name, pts, per)
             word = int(rng.integers(0, nwords))
-            bit = int(rng.integers(0, 32 * per if name.startswith("dup") else 32))
+            bit = int(rng.integers(0, nbits))
             rows.append((tid, bit, blk, word))
     if not rows:
         return np.zeros((0, 4), dtype=np.int64)

@@ -378,3 +378,17 @@ def test_launch_shape_does_not_change_results(codec, lanes):
             assert rc == 0 and np.array_equal(y.cpu().numpy().view(np.uint8), y_ref.view(np.uint8))
     finally:
         tune.reset()
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("shape,block", [((48, 42, 36), (6, 6, 6)), ((400, 390), (16, 16))])
+def test_preparation_fault_counts_and_streams_match_oracle(codec, dtype, shape, block):
+    x = synth.grf_field(shape, seed=15, dtype=dtype)
+    plan = synth.fault_plan(shape, block, dtype, {"prep_input": 6, "prep_coef": 6, "prep_sample": 6,
+                                                  "input": 3, "coef": 3}, seed=45)
+    for abft in (True, False):
+        (rc_r, s_r, rep_r), (rc_g, s_g, rep_g) = both(codec, x, block, 1e-3, abft=abft, faults=plan)
+        assert rc_r == rc_g, (rc_r, rc_g)
+        same_counts(rep_r, rep_g)
+        if rc_r == 0:
+            assert np.array_equal(s_r, s_g), first_difference(s_r, s_g)

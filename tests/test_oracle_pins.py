@@ -405,3 +405,63 @@ def test_cr_decrease_bound_example():
     dec = 1 - size0 / size1
     assert abs(dec - (r0 - 1) / (r0 + n - 1)) < 1e-15
     assert dec < g["bound_below"]
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_prediction_preparation_errors_keep_the_bound_and_stay_local(dtype):
+    """Sec. 4.1-4.2: an error in the regression, in the sampled estimates, or
+    in the input as those two read it can change only the struck block's
+    coefficients, predictor and codes (so the compression ratio), never the
+    error bound; with ABFT the input error is still found and repaired before
+    the prediction reads the input."""
+    shape, block = (36, 30, 24), (6, 6, 6)  # 6 x 5 x 4 = 120 full blocks
+    x = synth.grf_field(shape, seed=3, dtype=dtype)
+    rc, clean, rep0, d0 = ref.compress(x, block, 1e-3, debug=True)
+    assert rc == 0
+    plan = synth.fault_plan(shape, block, dtype, {"prep_input": 8, "prep_coef": 8, "prep_sample": 8}, seed=44)
+    rc, s, rep, d1 = ref.compress(x, block, 1e-3, faults=plan, debug=True)
+    assert rc == 0
+    assert rep["prep_input"]["injected"] == rep["prep_input"]["detected"] == rep["prep_input"]["corrected"] == 8
+    for t in ("prep_coef", "prep_sample"):
+        assert rep[t]["injected"] == 8 and rep[t]["detected"] == 0, t
+    assert rep["input"]["detected"] == 0
+    struck = {int(b) for b in plan[:, 2]}
+    for b in range(120):
+        c0, c1 = d0["codes"][216 * b:216 * (b + 1)], d1["codes"][216 * b:216 * (b + 1)]
+        if b not in struck:
+            assert np.array_equal(c0, c1), b
+            assert d0["is_regression"][b] == d1["is_regression"][b]
+            assert np.array_equal(d0["coef"][4 * b:4 * b + 4].view(np.uint8), d1["coef"][4 * b:4 * b + 4].view(np.uint8))
+    for row in plan:
+        if row[0] == synth.TARGET_IDS["prep_coef"]:  # the corrupted coefficient is the one kept
+            b = int(row[2])
+            assert not np.array_equal(d0["coef"][4 * b:4 * b + 4].view(np.uint8),
+                                      d1["coef"][4 * b:4 * b + 4].view(np.uint8))
+    rc, y, _ = ref.decompress(s)
+    assert rc == 0 and max_err(x, y) <= rep["eb_abs"]
+
+
+def test_sampling_error_can_flip_the_predictor_only():
+    """A flip of the top bit of one estimate reverses the comparison: the
+    block takes the other predictor, and its values still respect the bound."""
+    shape, block = (12, 12, 12), (6, 6, 6)
+    x = synth.grf_field(shape, seed=8)
+    rc, _, _, d0 = ref.compress(x, block, 1e-3, debug=True)
+    for b in range(8):
+        word = 1 if d0["is_regression"][b] else 0  # inflate the winner's estimate
+        plan = np.array([[synth.TARGET_IDS["prep_sample"], 62, b, word]], np.int64)
+        rc, s, rep, d1 = ref.compress(x, block, 1e-3, faults=plan, debug=True)
+        assert rc == 0 and rep["prep_sample"]["injected"] == 1
+        assert d1["is_regression"][b] != d0["is_regression"][b]
+        others = [c for c in range(8) if c != b]
+        assert all(d1["is_regression"][c] == d0["is_regression"][c] for c in others)
+        assert max_err(x, ref.decompress(s)[1]) <= rep["eb_abs"]
+
+
+def test_without_abft_a_preparation_input_error_reaches_the_output():
+    shape, block = (24, 24, 24), (6, 6, 6)
+    x = synth.bumps_field(shape, seed=2)
+    plan = np.array([[synth.TARGET_IDS["prep_input"], 30, 17, 100]], np.int64)
+    rc, s, rep = ref.compress(x, block, 1e-3, abft=False, faults=plan)
+    assert rc == 0 and rep["prep_input"]["detected"] == 0
+    assert max_err(x, ref.decompress(s)[1]) > rep["eb_abs"]
