@@ -188,6 +188,23 @@ def batch_bench(codec, torch, reps=3, plain_loop=True):
             "batched_phases_ms": {p: round(v[0], 4) for p, v in phases.items() if v[1]}}
 
 
+def block_size_report(codec, xd, ebs=(1e-2, 1e-3, 1e-4)):
+    """Rate-distortion of cubic blocks 4..20 on a 256^3 crop of the field
+    (Sec. 6.2's exploration), and the block the autotuner picks for the whole
+    field at each bound from four 64^3 samples."""
+    from paper_2010_03144_amd import blocksize
+    crop = xd[:256, :256, :256].contiguous()
+    rd = blocksize.rate_distortion(codec, crop, ebs)
+    table = {str(e): [{"eb": eb, "bits_per_value": round(b, 4), "psnr_db": round(p, 3), "cr": round(c, 4)}
+                      for eb, b, p, c in rows] for e, rows in rd.items()}
+    picks = {}
+    for eb in ebs:
+        best, rates = blocksize.best_block(codec, xd, eb)
+        picks[f"{eb:g}"] = {"block": best, "bits_per_value": {str(e): round(r, 4) for e, r in rates.items()}}
+    return {"crop": "256^3 corner of the 512^3 field, REL eb, ABFT on", "rate_distortion": table,
+            "autotuned_block": picks}
+
+
 def prep_fault_report(codec, torch, x, xd, block, eb=1e-3, k=10, trials=5):
     """Compression-ratio impact of computation errors in the prediction
     preparation (regression coefficients and sampled estimates, Sec. 4.1),
@@ -491,6 +508,8 @@ def main():
 
     if not args.no_extras:
         result["prep_faults"] = prep_fault_report(codec, torch, x, xd, block)
+        log("block-size rate-distortion")
+        result["block_size"] = block_size_report(codec, xd)
 
     if not args.no_batch and not args.copy_probe:
         result["batch"] = batch_bench(codec, torch)

@@ -108,7 +108,8 @@ def test_forced_predictors(codec, predictor):
 
 @pytest.mark.parametrize("shape,block", [((300, 257), (16, 16)), ((5000,), (64,)), ((7, 13, 5), (6, 6, 6)),
                                          ((33, 20), (8, 5)), ((1, 1, 1), (6, 6, 6)), ((9, 9, 9), (4, 4, 4)),
-                                         ((40, 40, 40), (10, 10, 10))])
+                                         ((40, 40, 40), (10, 10, 10)), ((35, 33, 37), (8, 8, 8)),
+                                         ((45, 41, 43), (20, 20, 20)), ((26, 27, 25), (12, 12, 12))])
 def test_shapes(codec, shape, block):
     x = synth.grf_field(shape, seed=4, dtype=np.float32)
     check_roundtrip(codec, x, block, 1e-3)

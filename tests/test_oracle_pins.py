@@ -465,3 +465,39 @@ def test_without_abft_a_preparation_input_error_reaches_the_output():
     rc, s, rep = ref.compress(x, block, 1e-3, abft=False, faults=plan)
     assert rc == 0 and rep["prep_input"]["detected"] == 0
     assert max_err(x, ref.decompress(s)[1]) > rep["eb_abs"]
+
+
+class _OracleCodec:
+    """The oracle behind the Codec calls the block-size tools make."""
+
+    def compress(self, x, block, eb, eb_mode="rel", abft=True):
+        import torch
+        rc, s, rep = ref.compress(x.numpy(), block, eb, eb_mode=eb_mode, abft=abft)
+        return rc, torch.from_numpy(s), rep
+
+    def decompress(self, s):
+        import torch
+        rc, y, rep = ref.decompress(s.numpy())
+        return rc, torch.from_numpy(y), rep
+
+
+def test_block_size_tools_on_the_oracle():
+    """PSNR and bit-rate as defined in the paper's evaluation, and the block
+    chosen is the one with the fewest bits at the same absolute bound."""
+    torch = pytest.importorskip("torch")
+    from paper_2010_03144_amd import blocksize
+    x = torch.from_numpy(synth.grf_field((40, 36, 32), seed=9))
+    y = x + 1e-3 * torch.from_numpy(np.random.default_rng(1).standard_normal(x.shape).astype(np.float32))
+    xd, yd = x.double().numpy(), y.double().numpy()
+    want = 20 * np.log10(xd.max() - xd.min()) - 10 * np.log10(np.mean((xd - yd) ** 2))
+    assert abs(blocksize.psnr(x, y) - want) < 1e-9
+    rd = blocksize.rate_distortion(_OracleCodec(), x, [1e-2, 1e-3], edges=(4, 8))
+    for e, rows in rd.items():
+        (eb1, b1, p1, _), (eb2, b2, p2, _) = rows
+        assert b2 > b1 and p2 > p1  # a tighter bound costs bits and buys PSNR
+    best, rates = blocksize.best_block(_OracleCodec(), x, 1e-3, edges=(4, 6, 10), side=16, count=2)
+    assert best == min(rates, key=rates.get) and set(rates) == {4, 6, 10}
+    eb_abs = 1e-3 * float(x.max() - x.min())
+    v = blocksize.sample_views(x, 16, 2)[0]
+    rc, s, _ = ref.compress(v.numpy(), (6, 6, 6), eb_abs, eb_mode="abs")
+    assert rc == 0
