@@ -725,7 +725,8 @@ __device__ __forceinline__ void compress_rows(const T *__restrict__ in, const Ge
 
 // Work-groups [0, L.full_wgs) take full blocks, the rest the partial shell.
 template <typename T, int ND, int B0, int B1, int B2, bool ABFT>
-__global__ void __launch_bounds__(256) k_compress_fast(JobTab tab) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ND == 3 && sizeof(T) == 4 ? 3 : 1)))
+k_compress_fast(JobTab tab) {
   const JobWg jw = job_of(tab);
   const T *__restrict__ in = (const T *)jw.J->src;
   const Geo g = jw.J->g;
