@@ -320,9 +320,15 @@ def serve_bench(torch, xd, seconds, rate=200.0, seed=5):
         span = max(r.t_done for r in reqs) - t0
         inj = sum(sum(r.report[t]["injected"] for t in sdcsz.TARGETS) for r in reqs)
         cor = sum(sum(r.report[t]["corrected"] for t in sdcsz.TARGETS) for r in reqs)
+        slow = sorted(reqs, key=lambda r: -r.latency)[:5]
         return {"p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
                 "max_ms": round(float(lat.max()), 3), "gbs": round(nbytes / span / 1e9, 3),
-                "faults_injected": int(inj), "faults_corrected": int(cor)}
+                "faults_injected": int(inj), "faults_corrected": int(cor),
+                "slowest": [{"kind": r.kind, "mib": round(serve.field_bytes(r) / 2**20, 1),
+                             "dtype": "f32" if (r.geom[1] if r.geom else r.data.dtype == torch.float32) else "f64",
+                             "eb": r.eb, "faults": 0 if r.faults is None else len(r.faults),
+                             "wait_ms": round((r.t_start - r.t_arrival) * 1e3, 3),
+                             "ms": round(r.latency * 1e3, 3)} for r in slow]}
 
     def served(reqs):
         with serve.Server("cuda:0", workers=2, hbm_budget=200e9, max_batch=64, keep_results=False) as srv:
