@@ -91,7 +91,8 @@ hipError_t sync_wait(hipStream_t st) {
 // Launch one kernel of phase `ph` (PH_NONE: untimed); `first`/`last` mark the
 // phase's first and last kernel.
 template <typename F, typename... Args>
-void launch(int ph, bool first, bool last, F kernel, dim3 grid, dim3 block, hipStream_t st, Args... args) {
+void launch_shm(int ph, bool first, bool last, F kernel, dim3 grid, dim3 block, uint32_t shm, hipStream_t st,
+                Args... args) {
   hipEvent_t a = nullptr, b = nullptr;
   if (ph >= 0 && g_timer.ready()) {
     if (first) a = g_timer.ev[ph][0];
@@ -100,7 +101,11 @@ void launch(int ph, bool first, bool last, F kernel, dim3 grid, dim3 block, hipS
       g_timer.pending[ph] = true;
     }
   }
-  hipExtLaunchKernelGGL(kernel, grid, block, 0, st, a, b, 0, args...);
+  hipExtLaunchKernelGGL(kernel, grid, block, shm, st, a, b, 0, args...);
+}
+template <typename F, typename... Args>
+void launch(int ph, bool first, bool last, F kernel, dim3 grid, dim3 block, hipStream_t st, Args... args) {
+  launch_shm(ph, first, last, kernel, grid, block, 0, st, args...);
 }
 
 uint32_t grid_for(uint64_t n, uint32_t per) { return (uint32_t)std::max<uint64_t>(1, (n + per - 1) / per); }
@@ -747,6 +752,11 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     J.nparts = (c.p->eb_mode == SDCSZ_REL && f.g.n_values)
                    ? (uint32_t)std::min<uint64_t>(kRangeBlocks, grid_for(f.g.n_values, kRangeThreads * 8))
                    : 1u;
+    // LDS histogram window of the compression kernel: the codes of loose
+    // value-range bounds stay within +-1024 of the zero residual; tighter
+    // (and absolute) bounds spread further, and codes outside the window cost
+    // a global atomic each
+    J.hist_win = c.p->eb_mode != SDCSZ_REL ? 8192u : c.p->eb >= 5e-4 ? 2048u : c.p->eb >= 5e-5 ? 8192u : kHistWin;
     if (J.dtype == SDCSZ_F32) fill_rt<float>(J);
     else fill_rt<double>(J);
     // fault plans (pageable sources live in fp until the first synchronisation)
@@ -764,8 +774,11 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   // re-runs, histogram compaction
   Tab t_zero, t_range[2], t_fast[kClasses][2][2], t_gen[2], t_redo[2], t_hist, t_hchunk;  // t_hist: one work-group per job
   uint64_t nb_fast[kClasses][2][2] = {}, nb_cls[kClasses] = {}, nb_enc[kClasses][2] = {};
+  uint32_t hw_fast[kClasses][2][2] = {};  // widest histogram window of each launch
   for (uint32_t j = 0; j < nj; j++)
     if (fp[j].fast) {
+      uint32_t &hw = hw_fast[fp[j].cls][jobs[j].dtype][jobs[j].abft ? 1 : 0];
+      hw = std::max(hw, jobs[j].hist_win);
       nb_fast[fp[j].cls][jobs[j].dtype][jobs[j].abft ? 1 : 0] += fp[j].g.n_blocks;
       nb_cls[fp[j].cls] += fp[j].g.n_blocks;
       nb_enc[fp[j].cls][jobs[j].dtype] += fp[j].g.n_blocks;
@@ -842,8 +855,10 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
           if (!t.total()) continue;
           const JobTab jt = d_fast[(c * 2 + d) * 2 + a];
           const JobKernel k = kCompFast[c][d][a];
-          const uint32_t ln = ln_fast[c][d][a];
-          pl.fs.push_back([&t, jt, k, ln, st, &grid](bool x, bool y) { launch(PH_PREDICT, x, y, k, grid(t), dim3(ln), st, jt); });
+          const uint32_t ln = ln_fast[c][d][a], shm = 4 * hw_fast[c][d][a];
+          pl.fs.push_back([&t, jt, k, ln, shm, st, &grid](bool x, bool y) {
+            launch_shm(PH_PREDICT, x, y, k, grid(t), dim3(ln), shm, st, jt);
+          });
         }
     if (t_gen[0].total())
       pl.fs.push_back([&](bool a, bool b) { launch(PH_PREDICT, a, b, k_compress_generic<float>, grid(t_gen[0]), dim3(64), st, d_gen[0]); });

@@ -21,7 +21,7 @@ constexpr uint32_t kScanThreads = 256;
 constexpr uint32_t kScanItems = 8;
 constexpr uint32_t kScanChunk = kScanThreads * kScanItems;
 constexpr uint32_t kRangeThreads = 256;
-constexpr uint32_t kHistWin = 2048;  // codes counted in LDS around the radius
+constexpr uint32_t kHistWin = 16384;  // largest LDS histogram window of the compression kernel (64 KiB)
 constexpr uint32_t kRangeBlocks = 2048;
 
 // Work of one specialised launch: work-groups [0, full_wgs) take the
@@ -56,6 +56,7 @@ struct Job {
   uint32_t stat_words;
   double eb;
   uint32_t dtype, abft, predictor, eb_mode, mode, nparts, n_sym;
+  uint32_t hist_win;  // codes counted in LDS by the compression kernel (<= kHistWin)
   RegTab<float> rtf;
   RegTab<double> rtd;
 };

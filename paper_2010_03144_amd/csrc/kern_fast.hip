@@ -17,7 +17,6 @@ namespace sdcsz {
 
 namespace {
 
-constexpr uint32_t kHistLo = kRadius - kHistWin / 2;
 // reasons a block is queued for a re-run (high byte of the queue entry)
 constexpr uint64_t kWhyInput = 1, kWhyCoef = 2, kWhyPred = 4, kWhyRecon = 8;
 
@@ -135,7 +134,8 @@ template <> struct Bound<double> {
 template <typename T, int ND, int B0, int B1, int B2, bool FULL, bool ABFT>
 __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const Geo &g, const RegTab<T> &rt,
                                                const PlanDev &plan, const CompWork &w, uint32_t predictor,
-                                               const Launch &L, uint32_t *hist, uint32_t &hot, uint64_t idx,
+                                               const Launch &L, uint32_t *hist, uint32_t hlo, uint32_t hw,
+                                               uint32_t &hot, uint64_t idx,
                                                uint64_t nlanes) {
   constexpr int PL = B1 * B2;  // points per plane
   static_assert(PL % 4 == 0, "a plane must fill whole 4-code groups");
@@ -401,8 +401,8 @@ __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const G
               rk += (uint32_t)k * code;
             }
             if (!z) {
-              const uint32_t cb = code - kHistLo;
-              if (cb < kHistWin) atomicAdd(&hist[cb], 1u);
+              const uint32_t cb = code - hlo;
+              if (cb < hw) atomicAdd(&hist[cb], 1u);
               else atomicAdd(w.hist + code, 1u);
             }
           }
@@ -463,7 +463,8 @@ __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const G
 template <typename T, int B1, int B2, bool FULL, bool ABFT>
 __device__ __forceinline__ void compress_rows(const T *__restrict__ in, const Geo &g, const RegTab<T> &rt,
                                               const PlanDev &plan, const CompWork &w, uint32_t predictor,
-                                              const Launch &L, uint32_t *hist, uint32_t &hot, uint64_t idx,
+                                              const Launch &L, uint32_t *hist, uint32_t hlo, uint32_t hw,
+                                              uint32_t &hot, uint64_t idx,
                                               uint64_t nlanes) {
   static_assert(B2 % 4 == 0, "a row must fill whole 4-code groups");
   // FP32 keeps the sampled values in registers; FP64 reads them again
@@ -676,8 +677,8 @@ __device__ __forceinline__ void compress_rows(const T *__restrict__ in, const Ge
           rk += (uint32_t)k * code;
         }
         if (!z) {
-          const uint32_t cb = code - kHistLo;
-          if (cb < kHistWin) atomicAdd(&hist[cb], 1u);
+          const uint32_t cb = code - hlo;
+          if (cb < hw) atomicAdd(&hist[cb], 1u);
           else atomicAdd(w.hist + code, 1u);
         }
       }
@@ -735,30 +736,36 @@ k_compress_fast(JobTab tab) {
   const CompWork w = jw.J->cw;
   const uint32_t predictor = jw.J->predictor;
   const Launch L = jw.J->L;
-  __shared__ uint32_t hist[kHistWin];
-  for (uint32_t t = threadIdx.x; t < kHistWin; t += blockDim.x) hist[t] = 0;
+  // LDS window of the histogram: hw codes centred on the zero residual
+  // (wider for small bounds, whose codes spread further; the launch sizes
+  // the dynamic LDS for the widest window of its jobs); the rest go to the
+  // global histogram
+  const uint32_t hw = jw.J->hist_win, hlo = kRadius - hw / 2;
+  extern __shared__ uint32_t hist[];
+  for (uint32_t t = threadIdx.x; t < hw; t += blockDim.x) hist[t] = 0;
   __syncthreads();
   uint32_t hot = 0;
   const bool full = jw.b < L.full_wgs;
   const uint64_t idx = (uint64_t)(full ? jw.b : jw.b - L.full_wgs) * blockDim.x + threadIdx.x;
   if constexpr (ND == 2) {
     static_assert(B0 == 1, "2D blocks have one plane");
-    if (full) compress_rows<T, B1, B2, true, ABFT>(in, g, rt, plan, w, predictor, L, hist, hot, idx, L.full_count);
-    else compress_rows<T, B1, B2, false, ABFT>(in, g, rt, plan, w, predictor, L, hist, hot, idx, L.shell_count);
+    if (full) compress_rows<T, B1, B2, true, ABFT>(in, g, rt, plan, w, predictor, L, hist, hlo, hw, hot, idx, L.full_count);
+    else compress_rows<T, B1, B2, false, ABFT>(in, g, rt, plan, w, predictor, L, hist, hlo, hw, hot, idx, L.shell_count);
   } else {
     if (full)
-      compress_lanes<T, ND, B0, B1, B2, true, ABFT>(in, g, rt, plan, w, predictor, L, hist, hot, idx, L.full_count);
+      compress_lanes<T, ND, B0, B1, B2, true, ABFT>(in, g, rt, plan, w, predictor, L, hist, hlo, hw, hot, idx,
+                                                    L.full_count);
     else
-      compress_lanes<T, ND, B0, B1, B2, false, ABFT>(in, g, rt, plan, w, predictor, L, hist, hot, idx,
+      compress_lanes<T, ND, B0, B1, B2, false, ABFT>(in, g, rt, plan, w, predictor, L, hist, hlo, hw, hot, idx,
                                                      L.shell_count);
   }
   // wave total of the zero-residual bin (lanes that ran the pass agree; the
   // others hold 0), then flush the window
   for (int off = 32; off > 0; off >>= 1) hot = max(hot, (uint32_t)__shfl_xor((int)hot, off));
-  if ((threadIdx.x & 63) == 0 && hot) atomicAdd(&hist[kRadius - kHistLo], hot);
+  if ((threadIdx.x & 63) == 0 && hot) atomicAdd(&hist[kRadius - hlo], hot);
   __syncthreads();
-  for (uint32_t t = threadIdx.x; t < kHistWin; t += blockDim.x)
-    if (hist[t]) atomicAdd(w.hist + kHistLo + t, hist[t]);
+  for (uint32_t t = threadIdx.x; t < hw; t += blockDim.x)
+    if (hist[t]) atomicAdd(w.hist + hlo + t, hist[t]);
 }
 
 // The blocks a fault plan names, in the paper's order with the plan applied
