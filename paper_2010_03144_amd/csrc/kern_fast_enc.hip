@@ -27,6 +27,31 @@ __device__ inline uint32_t enc_of(uint32_t code, const uint32_t *encw, const uin
   return e;
 }
 
+// Code length of a code: from a byte table in LDS for the codes around the
+// zero residual (the check only needs lengths; nearby codes share LDS words,
+// so a wave's lookups mostly broadcast instead of meeting bank conflicts),
+// else from the global table inside its own branch.
+constexpr uint32_t kLenWin = 4096;
+constexpr uint32_t kLenLo = kRadius - kLenWin / 2;
+__device__ inline uint32_t len_of(uint32_t code, const uint8_t *lenw, const uint32_t *enc) {
+  const uint32_t c = code - kLenLo;
+  uint32_t l = lenw[c < kLenWin ? c : 0u];
+  if (__builtin_expect(c >= kLenWin, 0)) {
+    uint32_t f = enc[code] & 0xFFu;
+    __asm__ volatile("" : "+v"(f));
+    l = f;
+  }
+  return l;
+}
+
+__device__ inline void load_lengths(uint8_t *lenw, const uint32_t *enc) {
+  for (uint32_t t = threadIdx.x; t < kLenWin / 4; t += blockDim.x) {
+    const uint32_t *e = enc + kLenLo + 4 * t;
+    ((uint32_t *)lenw)[t] = (e[0] & 0xFFu) | (e[1] & 0xFFu) << 8 | (e[2] & 0xFFu) << 16 | (e[3] & 0xFFu) << 24;
+  }
+  __syncthreads();
+}
+
 __device__ inline void load_window(uint32_t *encw, const uint32_t *enc) {
   for (uint32_t t = threadIdx.x; t < kEncWin; t += blockDim.x) encw[t] = enc[kEncLo + t];
   __syncthreads();
@@ -77,8 +102,8 @@ template <int ND, int B0, int B1, int B2> __global__ void __launch_bounds__(256)
   const Geo g = jw.J->g;
   const CompWork w = jw.J->cw;
   const uint32_t abft = jw.J->abft;
-  __shared__ uint32_t encw[kEncWin];
-  load_window(encw, w.enc);
+  __shared__ __align__(16) uint8_t lenw[kLenWin];
+  load_lengths(lenw, w.enc);
   const uint64_t blk = (uint64_t)jw.b * blockDim.x + threadIdx.x;
   if (blk >= g.n_blocks) return;
   const Box b = box_of(g, blk);
@@ -109,7 +134,7 @@ template <int ND, int B0, int B1, int B2> __global__ void __launch_bounds__(256)
         const uint32_t word = (q & 2) ? cur[q >> 2].y : cur[q >> 2].x;
         const bool v = (uint32_t)i < e0 && (uint32_t)j < n1 && (uint32_t)k < n2;
         const uint32_t c = v ? ((word >> (16 * (q & 1))) & 0xFFFFu) : 0u;
-        const uint32_t len = enc_of(c, encw, w.enc) & 0xFFu;
+        const uint32_t len = len_of(c, lenw, w.enc);
         if (v) {
           rs += c;
           rk += (uint32_t)k * c;
@@ -141,7 +166,7 @@ template <int ND, int B0, int B1, int B2> __global__ void __launch_bounds__(256)
       bits = 0;
       missing = false;
       for (uint32_t p = 0; p < b.pts; p++) {
-        const uint32_t len = enc_of(w.codes[pos(p)], encw, w.enc) & 0xFFu;
+        const uint32_t len = len_of(w.codes[pos(p)], lenw, w.enc);
         bits += len;
         missing |= len == 0;
       }
