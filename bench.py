@@ -345,17 +345,24 @@ def serve_bench(torch, xd, seconds, rate=200.0, seed=5):
         return summary(reqs, t0)
 
     log("serve: warm-up")
-    warm = make(False)[:32]
-    served(warm)
-    plain(make(False)[:32])
+    served(make(False)[:200])  # first launches of every kernel variant the stream uses
+    plain(make(False)[:200])
     torch.cuda.synchronize()
-    log(f"serve: {len(rows)} requests served with continuous batching")
-    s_at_rate = served(make())
-    log("serve: the same requests one at a time")
-    p_at_rate = plain(make())
-    log("serve: all requests at once (capacity)")
-    s_cap = served(make(False))
-    p_cap = plain(make(False))
+    # the timed runs hold tens of thousands of request objects: keep Python's
+    # cyclic collector from pausing the request threads (both modes alike)
+    import gc
+    gc.collect()
+    gc.disable()
+    try:
+        log(f"serve: {len(rows)} requests served with continuous batching")
+        s_at_rate = served(make())
+        log("serve: the same requests one at a time")
+        p_at_rate = plain(make())
+        log("serve: all requests at once (capacity)")
+        s_cap = served(make(False))
+        p_cap = plain(make(False))
+    finally:
+        gc.enable()
     offered = sum(serve.field_bytes(r) for r in make()) / seconds / 1e9
     return {"workload": f"Poisson {rate:g} req/s for {seconds:g} s ({len(rows)} requests): 50% compress / 50% "
                         f"decompress, sizes log-uniform 1 MiB..1 GiB (31 size classes, crops of the 512^3 "

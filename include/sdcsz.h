@@ -131,8 +131,8 @@ uint64_t sdcsz_compress_workspace_size(const sdcsz_params *p);
  * corruption, or a code without codeword when ABFT is off), SDCSZ_EHIP.
  * Synchronises `stream` twice: for the code histogram (the Huffman code is
  * built on the host; a third time when more than 32768 symbols are used) and
- * at the end.  The calling thread keeps a pinned host staging buffer (at
- * least 1 MiB, grown for large batches) from its first call on.
+ * at the end.  The calling thread keeps a pinned host staging buffer (8 MiB,
+ * doubled when a large batch needs more) from its first call until it exits.
  */
 int sdcsz_compress(const void *d_in, const sdcsz_params *p, void *d_out, uint64_t out_cap,
                    uint64_t *h_out_size, sdcsz_report *h_rep, void *d_ws, uint64_t ws_size,

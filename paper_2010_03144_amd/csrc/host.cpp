@@ -386,17 +386,23 @@ uint32_t scan_chunks(uint64_t nb) { return (uint32_t)((nb + kScanChunk - 1) / kS
 struct Staging {
   uint8_t *p = nullptr;
   size_t cap = 0;
-  // only called between calls or after a synchronisation (no copy in flight)
+  // only called between calls or after a synchronisation (no copy in flight);
+  // starts at 8 MiB (a field's histogram pairs and codebook list need up to
+  // about 1 MiB) and at least doubles, so regrowing (a device-wide wait in
+  // hipHostFree plus a new pinned allocation) stays rare
   uint8_t *get(size_t n) {
     if (n > cap) {
       if (p) (void)hipHostFree(p);
       p = nullptr;
+      const size_t want = std::max<size_t>({n, 2 * cap, size_t(8) << 20});
       cap = 0;
-      const size_t want = std::max<size_t>(n, 1u << 20);
       if (hipHostMalloc((void **)&p, want, hipHostMallocDefault) != hipSuccess) return nullptr;
       cap = want;
     }
     return p;
+  }
+  ~Staging() {
+    if (p) (void)hipHostFree(p);
   }
 };
 thread_local Staging t_stage;
