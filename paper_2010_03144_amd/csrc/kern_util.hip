@@ -93,8 +93,10 @@ template <typename T> __global__ void __launch_bounds__(kRangeThreads) k_range(J
   const uint64_t tid = (uint64_t)jw.b * blockDim.x + threadIdx.x, nth = (uint64_t)jw.nb * blockDim.x;
   typedef T vec_t __attribute__((ext_vector_type(V)));
   const vec_t *vin = (const vec_t *)(in + h);
+  // non-temporal: the pass streams at close to HBM rate instead of also
+  // filling the caches (which saves the compression kernel less than it costs)
   for (uint64_t i = tid; i < nv; i += nth) {
-    const vec_t v = vin[i];
+    const vec_t v = __builtin_nontemporal_load(vin + i);
 #pragma unroll
     for (uint32_t c = 0; c < V; c++) minmax_finite<T>(v[c], lo, hi);
   }
