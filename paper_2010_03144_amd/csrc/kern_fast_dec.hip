@@ -261,11 +261,12 @@ __device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, cons
         Up = U1;
         if (v) sum += Wd<T>::sum(r);
       }
-      // store the row
+      // store the row (non-temporal: the output is not read again here, and
+      // keeping it out of the caches leaves them to the payload windows)
       char *dst = wbase + (loff + (uint32_t)i * PSB + (uint32_t)j * RSB);
 #pragma unroll
       for (int k = 0; k < B2; k++)
-        if (FULL || (uint32_t)k < n2) *(T *)(dst + k * sizeof(T)) = rv[k];
+        if (FULL || (uint32_t)k < n2) __builtin_nontemporal_store(rv[k], (T *)(dst + k * sizeof(T)));
 #pragma unroll
       for (int k = 0; k < B2; k++) Sv[k] = rowold[k];
       drow_fence(cprev, sum, br.lp);
@@ -378,10 +379,10 @@ __device__ __forceinline__ void decode_rows(const uint8_t *__restrict__ s, const
       cprev = r;
       if (v) sum += Wd<T>::sum(r);
     }
-    char *dst = wbase + (loff + (uint32_t)j * RSB);
+    char *dst = wbase + (loff + (uint32_t)j * RSB);  // non-temporal row stores, as in 3D
 #pragma unroll
     for (int k = 0; k < B2; k++)
-      if (FULL || (uint32_t)k < n2) *(T *)(dst + k * sizeof(T)) = Pr[k];
+      if (FULL || (uint32_t)k < n2) __builtin_nontemporal_store(Pr[k], (T *)(dst + k * sizeof(T)));
     drow_fence(sum, br.lp);
   }
   if (used_out != nout || br.pos > nw * 32u) bad = true;

@@ -71,7 +71,10 @@ template <int B0, int B1, int B2> struct PlaneCodes {
   __device__ void load(int i) {
 #pragma unroll
     for (int gi = 0; gi < PG; gi++) {
-      const uint2 u = cb[(uint64_t)(i * PG + gi) * 64];
+      // last read of the codes: non-temporal, so they do not displace the
+      // output in the caches
+      const uint64_t u64 = __builtin_nontemporal_load((const uint64_t *)(cb + (uint64_t)(i * PG + gi) * 64));
+      const uint2 u = make_uint2((uint32_t)u64, (uint32_t)(u64 >> 32));
       v[i & 1][2 * gi] = u.x;
       v[i & 1][2 * gi + 1] = u.y;
     }
