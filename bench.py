@@ -290,9 +290,9 @@ def serve_bench(torch, xd, seconds, rate=200.0, seed=5):
             bucket = min(2, max(0, int(math.floor(math.log10(sp["eb"]) + 5))))
             key = (k, is32, bucket)
             if key not in streams:
-                rc, st, _ = codec.compress(x, block, 10 ** (-4.5 + bucket))
+                rc, st, rep = codec.compress(x, block, 10 ** (-4.5 + bucket))
                 assert rc == 0, rc
-                streams[key] = st.clone()
+                streams[key] = (st.clone(), rep["header"])
             plan = (synth.sparse_fault_plan(shape, block, np.float32 if is32 else np.float64, {"recon": m},
                                             sp["seed"]) if sp["faults"] else None)
             rows.append(("decompress", sp["t"], streams[key], None, plan, (shape, is32, block)))
@@ -304,7 +304,8 @@ def serve_bench(torch, xd, seconds, rate=200.0, seed=5):
             if kind == "compress":
                 r = serve.Request("compress", data, block, eb, faults=plan)
             else:
-                r = serve.Request("decompress", data, faults=plan, geom=geom)
+                data, header = data
+                r = serve.Request("decompress", data, faults=plan, geom=geom, header=header)
             key = (kind, data.data_ptr(), 0 if plan is None else len(plan))
             if key not in fp_cache:
                 fp_cache[key] = serve.device_footprint(r)

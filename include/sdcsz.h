@@ -198,11 +198,14 @@ int sdcsz_decompress_region(const void *d_stream, uint64_t stream_size, const ui
  * device names the field of every work-group), and the host synchronises
  * for the whole batch: compression once for the code histograms (twice when
  * they hold more than 32768 used symbols in all), once at the end;
- * decompression once for the headers and once at the end.  Every field is
+ * decompression once for the headers (skipped when every item brings its
+ * header) and once at the end.  Every field is
  * processed exactly as a single call would process it: its stream, output
  * and report are identical.  Huffman codes of a batch are built on up to 16
  * host threads.
  */
+#define SDCSZ_HEADER_BYTES 192 /* fixed size of a stream's header */
+
 typedef struct {
   const void *d_in;      /* device: the field, C order (as for sdcsz_compress)      */
   sdcsz_params params;   /* the field's parameters (faults: host array or NULL)    */
@@ -211,6 +214,9 @@ typedef struct {
   uint64_t out_size;     /* out: stream size (required size on SDCSZ_ENOSPC)      */
   int rc;                /* out: this field's return code                          */
   sdcsz_report rep;      /* out                                                    */
+  uint8_t header[SDCSZ_HEADER_BYTES]; /* out: the stream's header, when written;
+                            pass it to sdcsz_decompress_batch to spare the
+                            header read-back there                              */
 } sdcsz_comp_item;
 
 /* Device workspace for sdcsz_compress_batch on these items (fields with
@@ -233,6 +239,13 @@ typedef struct {
   uint64_t out_cap;
   const sdcsz_fault *faults;  /* host, n_faults entries (SDCSZ_T_RECON), or NULL   */
   uint32_t n_faults;
+  const void *h_header;  /* host copy of the stream's SDCSZ_HEADER_BYTES header (as
+                            returned by the compression), or NULL: then the
+                            header is read back from the device first (one
+                            more synchronisation).  A given header is checked
+                            against the stream's own on the device; a mismatch
+                            ends the item in SDCSZ_EFORMAT (the output is then
+                            unspecified)                                         */
   int rc;                /* out                                                    */
   sdcsz_report rep;      /* out                                                    */
 } sdcsz_dec_item;
@@ -246,7 +259,7 @@ uint64_t sdcsz_decompress_batch_workspace_size(const sdcsz_params *h_params, uin
  * Decompress n streams (Algorithm 2 for each, with each item's RECON fault
  * plan applied as in sdcsz_decompress).  Returns
  * SDCSZ_OK when every stream decoded, else the first failing item's code.
- * Synchronises `stream`.
+ * Synchronises `stream` once, or twice when an item gives no header.
  */
 int sdcsz_decompress_batch(sdcsz_dec_item *h_items, uint32_t n, void *d_ws, uint64_t ws_size,
                            void *stream);

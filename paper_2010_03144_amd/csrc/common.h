@@ -14,6 +14,7 @@ namespace sdcsz {
 constexpr uint32_t kRadius = 32768;  // code of a zero residual; 0 marks an outlier
 constexpr uint32_t kMaxLen = 24;     // longest Huffman codeword
 constexpr uint64_t kHeader = 192;    // fixed stream header bytes
+static_assert(kHeader == SDCSZ_HEADER_BYTES, "header size");
 constexpr uint32_t kMaxBlockPts = 8192;
 constexpr uint32_t kMaxPatches = 8;  // fault-plan entries per block and call
 constexpr uint32_t kMaxRedo = 4096;  // blocks re-run after a detected mismatch
@@ -92,6 +93,7 @@ struct CompWork {
   uint64_t *redo;      // kMaxRedo block ids
   struct Header *hdr;  // stream header, filled on the device
   uint64_t *res;       // R_* results of the call, read back once at its end
+  uint8_t *hdr_bytes;  // the stream's kHeader header bytes, read back with the results
   uint32_t *cb;        // n_sym pairs (symbol << 8 | length, codeword), ascending symbols
   uint64_t *tot;       // scanned totals: payload words, outliers, regression blocks
 };

@@ -243,7 +243,9 @@ CompLayout comp_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
   };
   // cleared by one launch at the start of a call: counters, results, redo
   // count, histogram and codeword table
-  L.cnt = take(8 * C_N + 8 * R_N + 8);
+  // counters, results, redo count and the header bytes are adjacent: the
+  // end of a call reads them back with one copy
+  L.cnt = take(8 * C_N + 8 * R_N + 8 + kHeader);
   L.res = L.cnt + 8 * C_N;
   L.redo_n = L.res + 8 * R_N;
   L.hist = take(4 * 65536);
@@ -585,9 +587,13 @@ struct CompItem {  // one field of a compression call
   uint64_t out_size;
   int rc;
   sdcsz_report rep;
+  uint8_t header[kHeader];  // the stream's header, when written
 };
 
 constexpr uint64_t kPairPrefix = 32768;  // histogram entries returned with the first synchronisation
+// u64 words per field read back at the end of a compression: counters,
+// results, redo count, header bytes
+constexpr uint32_t kResWords = C_N + R_N + 1 + kHeader / 8;
 
 struct CompPlan {  // host state of one field
   Geo g;
@@ -626,7 +632,7 @@ BatchArea comp_batch_area(uint64_t njobs, uint64_t cap_pairs) {
   B.pairs = B.counts + ((4 * njobs + 7) & ~7ull);
   at = a256(B.pairs + 8 * cap_pairs);
   B.chunks = take(4ull * kHistChunks * njobs);
-  B.res = take(8ull * (C_N + R_N) * njobs);
+  B.res = take(8ull * kResWords * njobs);
   B.total = at;
   return B;
 }
@@ -719,6 +725,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     cw.redo_n = (uint32_t *)(w + f.L.redo_n);
     cw.redo = (uint64_t *)(w + f.L.redo);
     cw.hdr = (Header *)(w + f.L.hdr);
+    cw.hdr_bytes = w + f.L.redo_n + 8;
     cw.res = (uint64_t *)(w + f.L.res);
     cw.cb = (uint32_t *)(ws + B.cb) + 2 * f.pair_off;
     cw.tot = (uint64_t *)(w + f.L.tot);
@@ -749,7 +756,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     J.zero = (uint32_t *)(w + f.L.cnt);
     J.zero_words = (f.L.zero_end - f.L.cnt) / 4;
     J.stat = (const uint64_t *)(w + f.L.cnt);
-    J.stat_words = C_N + R_N;
+    J.stat_words = kResWords;
     J.eb = c.p->eb;
     J.dtype = c.p->dtype;
     J.abft = c.p->abft;
@@ -900,7 +907,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   const uint64_t JR = jobs_region(nj);
   const uint64_t at_pairs = a256(JR + 8 * total_pairs);
   const uint64_t at_res = a256(at_pairs + 8 * total_pairs);
-  const size_t need = at_res + 8ull * (C_N + R_N) * nj + 256;
+  const size_t need = at_res + 8ull * kResWords * nj + 256;
   std::vector<uint64_t> first_pairs;
   if (total_pairs <= pre) {
     first_pairs.assign((const uint64_t *)(hs + head), (const uint64_t *)(hs + head) + total_pairs);
@@ -995,10 +1002,10 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   const uint64_t *d_res = (const uint64_t *)(ws + B.res);
   if (nj == 1) d_res = jobs[0].stat;  // one field: no gather needed
   else launch(PH_NONE, false, false, k_results, grid(t_res), dim3(64), st, D[7], (uint64_t *)d_res,
-              (uint32_t)(C_N + R_N));
+              (uint32_t)kResWords);
   HIPCHK(hipGetLastError());
   uint64_t *hres = (uint64_t *)(hs + at_res);
-  HIPCHK(hipMemcpyAsync(hres, d_res, 8ull * (C_N + R_N) * nj, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(hres, d_res, 8ull * kResWords * nj, hipMemcpyDeviceToHost, st));
   HIPCHK(sync_wait(st));
   g_timer.resolve();
 
@@ -1006,7 +1013,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   int first = SDCSZ_OK;
   for (uint32_t j = 0; j < nj; j++) {
     CompItem &c = it[item_of[j]];
-    const uint64_t *cnt = hres + (uint64_t)j * (C_N + R_N), *res = cnt + C_N;
+    const uint64_t *cnt = hres + (uint64_t)j * kResWords, *res = cnt + C_N;
     fill_report(&c.rep, cnt, fp[j].g.n_blocks);
     std::memcpy(&c.rep.eb_abs, &res[R_EB], 8);
     const bool unc = cnt[C_UNC + SDCSZ_T_INPUT] || cnt[C_UNC + SDCSZ_T_COEF] || cnt[C_UNC + SDCSZ_T_CODE] ||
@@ -1021,6 +1028,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
       c.rep.stream_size = res[R_SIZE];
       c.out_size = res[R_SIZE];
       c.rc = res[R_WRITTEN] ? SDCSZ_OK : SDCSZ_ENOSPC;
+      if (c.rc == SDCSZ_OK) std::memcpy(c.header, res + R_N + 1, kHeader);
     }
   }
   for (uint32_t i = 0; i < n; i++)
@@ -1041,6 +1049,7 @@ struct DecItem {  // one stream of a decompression call
   uint64_t need;  // bytes the output must hold
   const sdcsz_fault *faults;
   uint32_t n_faults;
+  const uint8_t *h_header;  // the caller's copy of the header, or null
   int rc;
   sdcsz_report rep;
   Header h;
@@ -1070,6 +1079,7 @@ int read_headers(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     std::memset(&it[i].rep, 0, sizeof(it[i].rep));
     if (!it[i].d_stream) it[i].rc = SDCSZ_EINVAL;
     else if (it[i].stream_size < kHeader) it[i].rc = SDCSZ_EFORMAT;
+    else if (it[i].h_header) it[i].rc = unpack_header(it[i].h_header, it[i].stream_size, it[i].h, it[i].g);
     else idx.push_back(i);
   }
   if (idx.empty()) return SDCSZ_OK;
@@ -1235,10 +1245,22 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
   for (int c = 0; c < kClasses; c++)
     for (int d = 0; d < 2; d++) up.tabs.push_back(&t_fast[c][d]);
   const size_t res_bytes = 8ull * (C_N + 1) * nj;
-  uint8_t *hs = t_stage.get(up.bytes(nj) + res_bytes + 4096);
+  // caller-given headers go to the end of the batch area (uploaded with the
+  // jobs) for k_dectab to check against the streams
+  const uint64_t hdr_at = dec_batch_area(nj) - a256(kHeader * nj);
+  bool any_hdr = false;
+  for (uint32_t j = 0; j < nj; j++) {
+    const DecItem &d = it[item_of[j]];
+    jobs[j].hdr_expect = d.h_header ? (const uint32_t *)(ws + hdr_at + kHeader * j) : nullptr;
+    any_hdr |= d.h_header != nullptr;
+  }
+  const uint64_t up_bytes = any_hdr ? hdr_at + kHeader * nj : up.bytes(nj);
+  uint8_t *hs = t_stage.get(std::max<uint64_t>(up_bytes, up.bytes(nj) + res_bytes) + 4096);
   if (!hs) return SDCSZ_EHIP;
   up.place(jobs, hs, ws);
-  HIPCHK(hipMemcpyAsync(ws, hs, up.bytes(nj), hipMemcpyHostToDevice, st));
+  for (uint32_t j = 0; j < nj; j++)
+    if (it[item_of[j]].h_header) std::memcpy(hs + hdr_at + kHeader * j, it[item_of[j]].h_header, kHeader);
+  HIPCHK(hipMemcpyAsync(ws, hs, up_bytes, hipMemcpyHostToDevice, st));
   const std::vector<JobTab> &D = up.dev;
   auto grid = [](const Tab &t) { return dim3(t.total()); };
   launch(PH_NONE, false, false, k_zero_jobs, grid(t_zero), dim3(256), st, D[0]);
@@ -1476,6 +1498,8 @@ int sdcsz_compress_batch(sdcsz_comp_item *h_items, uint32_t n, void *d_ws, uint6
     h_items[i].out_size = c[i].out_size;
     h_items[i].rc = rc == SDCSZ_EHIP ? SDCSZ_EHIP : c[i].rc;
     h_items[i].rep = c[i].rep;
+    if (h_items[i].rc == SDCSZ_OK) std::memcpy(h_items[i].header, c[i].header, kHeader);
+    else std::memset(h_items[i].header, 0, kHeader);
   }
   return rc;
 }
@@ -1606,6 +1630,7 @@ int sdcsz_decompress_batch(sdcsz_dec_item *h_items, uint32_t n, void *d_ws, uint
     d[i].out_cap = h_items[i].out_cap;
     d[i].faults = h_items[i].faults;
     d[i].n_faults = h_items[i].n_faults;
+    d[i].h_header = (const uint8_t *)h_items[i].h_header;
   }
   int rc = read_headers(d.data(), n, (uint8_t *)d_ws, ws_size, st);
   if (rc == SDCSZ_OK) rc = decode_batch(d.data(), n, (uint8_t *)d_ws, ws_size, st);

@@ -57,6 +57,7 @@ struct Job {
   double eb;
   uint32_t dtype, abft, predictor, eb_mode, mode, nparts, n_sym;
   uint32_t hist_win;  // codes counted in LDS by the compression kernel (<= kHistWin)
+  const uint32_t *hdr_expect;  // decompression: the header the caller gave (device copy), or null
   RegTab<float> rtf;
   RegTab<double> rtd;
 };

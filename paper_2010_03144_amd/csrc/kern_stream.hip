@@ -167,7 +167,8 @@ __global__ void __launch_bounds__(256) k_header(JobTab tb) {
   h.n_regression = tot[2];
   section_offsets(h);
   const unsigned long long *c = w.cnt;
-  const bool unc = c[C_UNC + SDCSZ_T_INPUT] || c[C_UNC + SDCSZ_T_COEF] || c[C_UNC + SDCSZ_T_CODE] || c[C_MISSING];
+  const bool unc = c[C_UNC + SDCSZ_T_INPUT] || c[C_UNC + SDCSZ_T_COEF] || c[C_UNC + SDCSZ_T_CODE] ||
+                   c[C_UNC + SDCSZ_T_PREP_INPUT] || c[C_MISSING];
   const bool ok = !unc && out != nullptr && h.total <= out_cap;
   const uint32_t t = jw.b * blockDim.x + threadIdx.x;
   if (t == 0) {
@@ -183,6 +184,7 @@ __global__ void __launch_bounds__(256) k_header(JobTab tb) {
   if (t < h.n_sym) put32(out, (uint32_t)(kHeader + 4 * t), w.cb[2 * t]);
   if (t == 0) {
     write_header(h, out);
+    write_header(h, w.hdr_bytes);  // the caller's copy
     const uint64_t vb = h.dtype == SDCSZ_F32 ? 4 : 8;
     // 4-byte alignment pads after the codebook, the outliers and the payload
     if (h.off_table > kHeader + 4ull * h.n_sym) put32(out + kHeader, 4 * h.n_sym, 0u);
@@ -215,8 +217,20 @@ __global__ void __launch_bounds__(256) k_dectab(JobTab tb) {
   __shared__ uint32_t run[kMaxLen + 1];        // per length: symbols placed so far
   __shared__ uint16_t short_sym[1u << kLutBits];  // symbols at positions < 2^kLutBits
   __shared__ uint32_t first[kMaxLen + 2], cnt[kMaxLen + 2], start[kMaxLen + 2];
-  __shared__ uint32_t smin, smax, bad, unordered;
+  __shared__ uint32_t smin, smax, bad, unordered, hmis;
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // a header the caller supplied (the host sized everything from it) must be
+  // the stream's own, word for word
+  if (J.hdr_expect) {
+    if (tid == 0) hmis = 0;
+    __syncthreads();
+    if (tid < kHeader / 4 && ((const uint32_t *)J.src)[tid] != J.hdr_expect[tid]) atomicOr(&hmis, 1u);
+    __syncthreads();
+    if (hmis) {
+      if (tid == 0) *w.err = 1;
+      return;
+    }
+  }
   if (tid <= kMaxLen) {
     cnt[tid] = 0;
     run[tid] = 0;

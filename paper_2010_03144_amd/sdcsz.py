@@ -24,6 +24,7 @@ FUNCTIONS = ["sdcsz_max_compressed_size", "sdcsz_compress_workspace_size", "sdcs
              "sdcsz_decompress_batch", "sdcsz_strerror", "sdcsz_timing_enable",
              "sdcsz_timing_read", "sdcsz_phase_name", "sdcsz_tune_set", "sdcsz_tune_get"]
 N_PHASES = 11
+HEADER_BYTES = 192
 TUNE_MAX = 8
 TUNE_STAGES = ["predict", "check", "encode", "decode"]
 SHAPE_CLASSES = [((6, 6, 6), 3), ((16, 16), 2)]  # (block, ndim) of the specialised kernels
@@ -63,13 +64,13 @@ class Report(C.Structure):
 class CompItem(C.Structure):
     _fields_ = [("d_in", C.c_void_p), ("params", Params), ("d_out", C.c_void_p),
                 ("out_cap", C.c_uint64), ("out_size", C.c_uint64), ("rc", C.c_int),
-                ("rep", Report)]
+                ("rep", Report), ("header", C.c_uint8 * HEADER_BYTES)]
 
 
 class DecItem(C.Structure):
     _fields_ = [("d_stream", C.c_void_p), ("stream_size", C.c_uint64), ("d_out", C.c_void_p),
                 ("out_cap", C.c_uint64), ("faults", C.POINTER(Fault)), ("n_faults", C.c_uint32),
-                ("rc", C.c_int), ("rep", Report)]
+                ("h_header", C.c_void_p), ("rc", C.c_int), ("rep", Report)]
 
 
 _lib = None
@@ -212,21 +213,35 @@ class Codec:
         if out is None or out.numel() < cap:
             out = self.workspace(cap, "stream_out")
         ws = self.workspace(ws_n, "compress")
-        size = C.c_uint64(0)
-        rep = Report()
-        rc = L.sdcsz_compress(C.c_void_p(x.data_ptr()), C.byref(p), C.c_void_p(out.data_ptr()),
-                              out.numel(), C.byref(size), C.byref(rep), C.c_void_p(ws.data_ptr()),
-                              ws.numel(), _stream_handle(self.device))
-        stream = out[: size.value] if rc == OK else None
-        self._remember(out, rc, int(size.value), tuple(x.shape), p.dtype, block)
-        return rc, stream, report_dict(rep)
+        item = (CompItem * 1)()  # one field through the batch entry: it also returns the header
+        item[0].d_in = x.data_ptr()
+        item[0].params = p
+        item[0].d_out = out.data_ptr()
+        item[0].out_cap = out.numel()
+        rc = L.sdcsz_compress_batch(item, 1, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(self.device))
+        rc = item[0].rc if rc in (OK, item[0].rc) else rc
+        size = int(item[0].out_size)
+        stream = out[:size] if rc == OK else None
+        header = bytes(item[0].header) if rc == OK else None
+        self._remember(out, rc, size, tuple(x.shape), p.dtype, block, header)
+        rep = report_dict(item[0].rep)
+        rep["header"] = header
+        return rc, stream, rep
 
-    def _remember(self, buf, rc, size, shape, dtype, block):
+    def _remember(self, buf, rc, size, shape, dtype, block, header=None):
         own = any(t.data_ptr() == buf.data_ptr() for t in self._ws.values())
         if rc == OK and own:
-            self._meta[buf.data_ptr()] = (size, shape, dtype, tuple(int(b) for b in block))
+            self._meta[buf.data_ptr()] = (size, shape, dtype, tuple(int(b) for b in block), header)
         else:
             self._meta.pop(buf.data_ptr(), None)
+
+    def _header(self, stream):
+        """The header bytes of a stream this codec wrote into its own buffer
+        (the library checks them against the stream on the device)."""
+        m = self._meta.get(stream.data_ptr())
+        if m is not None and m[0] == stream.numel():
+            return m[4]
+        return None
 
     def _geometry(self, stream):
         """(rc, params, shape) of a stream: from the last compression when the
@@ -258,10 +273,13 @@ class Codec:
         return self.workspace(n, "decompress")
 
     # ---------------------------------------------------------------- decompress
-    def decompress(self, stream, faults=None, out=None, geom=None):
+    def decompress(self, stream, faults=None, out=None, geom=None, header=None):
         """Returns (rc, tensor, report dict).  geom: (shape, is_f32, block)
         when the caller knows them (the library checks them against the
-        header), else they are taken from the stream."""
+        header), else they are taken from the stream.  header: the stream's
+        header bytes (from its compression report; a stream this codec wrote
+        into its own buffer brings its own), which spares the read-back of
+        the header (the library checks it against the stream on the device)."""
         torch = self.torch
         L = lib()
         if geom is not None:
@@ -270,11 +288,27 @@ class Codec:
             rc, p, shape = self._geometry(stream)
         if rc != OK:
             return rc, None, None
+        if header is None:
+            header = self._header(stream)
         dt = torch.float32 if p.dtype == 0 else torch.float64
         if out is None:
             out = torch.empty(shape, dtype=dt, device=self.device)
         fptr, nf, keep = _faults(faults)
         ws = self._dec_ws(p, nf)
+        if header is not None:
+            hbuf = C.create_string_buffer(bytes(header), HEADER_BYTES)
+            item = (DecItem * 1)()
+            item[0].d_stream = stream.data_ptr()
+            item[0].stream_size = stream.numel()
+            item[0].d_out = out.data_ptr()
+            item[0].out_cap = out.numel() * out.element_size()
+            item[0].faults = fptr
+            item[0].n_faults = nf
+            item[0].h_header = C.cast(hbuf, C.c_void_p)
+            rc = L.sdcsz_decompress_batch(item, 1, C.c_void_p(ws.data_ptr()), ws.numel(),
+                                          _stream_handle(self.device))
+            del keep, hbuf
+            return item[0].rc if rc in (OK, item[0].rc) else rc, out, report_dict(item[0].rep)
         rep = Report()
         rc = L.sdcsz_decompress(C.c_void_p(stream.data_ptr()), stream.numel(),
                                 C.c_void_p(out.data_ptr()), out.numel() * out.element_size(), fptr,
@@ -340,16 +374,21 @@ class Codec:
         res = []
         for i in range(n):
             it = items[i]
+            header = bytes(it.header) if it.rc == OK else None
             self._remember(bufs[i], it.rc, int(it.out_size), tuple(fields[i].shape), it.params.dtype,
-                           pick(block, i))
-            res.append((it.rc, bufs[i][: it.out_size] if it.rc == OK else None, report_dict(it.rep)))
+                           pick(block, i), header)
+            rep = report_dict(it.rep)
+            rep["header"] = header
+            res.append((it.rc, bufs[i][: it.out_size] if it.rc == OK else None, rep))
         return rc, res
 
-    def decompress_batch(self, streams, outs=None, faults=None, geoms=None):
+    def decompress_batch(self, streams, outs=None, faults=None, geoms=None, headers=None):
         """Decompress several streams in one call (faults: None or one RECON
         plan or None per stream; geoms: None or (shape, is_f32, block) per
         stream when the caller knows them, which saves reading the headers
-        here: the library checks them against the headers anyway).  Returns
+        here: the library checks them against the headers anyway; headers:
+        None or the header bytes (or None) per stream, which spare the
+        header read-back when every stream has one).  Returns
         (rc, [(rc, tensor, report)])."""
         torch = self.torch
         L = lib()
@@ -370,6 +409,13 @@ class Codec:
             keep.append(k)
             items[i].faults = fptr
             items[i].n_faults = nf
+            hb = headers[i] if headers is not None else None
+            if hb is None:
+                hb = self._header(s)
+            if hb is not None:
+                hbuf = C.create_string_buffer(bytes(hb), HEADER_BYTES)
+                keep.append(hbuf)
+                items[i].h_header = C.cast(hbuf, C.c_void_p)
             p.n_faults = nf
             params[i] = p
             dt = torch.float32 if p.dtype == 0 else torch.float64

@@ -33,16 +33,18 @@ EEXEC = -7   # the batch's execution raised (the exception is kept in req.error)
 
 class Request:
     """One request.  kind is "compress" (data: a device field) or
-    "decompress" (data: a device stream; geom = (shape, is_f32, block) when
-    known).  After completion: rc, result (stream or field tensor), report,
+    "decompress" (data: a device stream; geom = (shape, is_f32, block) and
+    header = the stream's header bytes when known, which spares reading them
+    back).  After completion: rc, result (stream or field tensor), report,
     and the times t_arrival, t_start, t_done (time.perf_counter seconds)."""
 
     def __init__(self, kind, data, block=None, eb=None, eb_mode="rel", abft=True, predictor="auto",
-                 faults=None, geom=None, footprint=None, nbytes=None, tag=None):
+                 faults=None, geom=None, footprint=None, nbytes=None, tag=None, header=None):
         assert kind in ("compress", "decompress")
         self.kind, self.data, self.block, self.eb = kind, data, block, eb
         self.eb_mode, self.abft, self.predictor, self.faults = eb_mode, abft, predictor, faults
         self.geom, self.footprint, self.nbytes, self.tag = geom, footprint, nbytes, tag
+        self.header = header
         self.rc = None
         self.result = None
         self.result_bytes = None  # size of the result (bytes), kept when the result is dropped
@@ -116,7 +118,7 @@ class GpuExecutor:
                                                    faults=[r.faults for r in g], outs=outs)
                 else:
                     rc, res = codec.decompress_batch([r.data for r in g], faults=[r.faults for r in g],
-                                                     geoms=[r.geom for r in g])
+                                                     geoms=[r.geom for r in g], headers=[r.header for r in g])
                 t = now()
                 for i, r in enumerate(g):
                     if res is None:
@@ -276,7 +278,7 @@ def serve_one_at_a_time(requests, t0, device="cuda:0", clock=time.perf_counter, 
             r.rc, r.result, r.report = codec.compress(r.data, r.block, r.eb, r.eb_mode, r.abft, r.predictor,
                                                       faults=r.faults, out=out)
         else:
-            r.rc, r.result, r.report = codec.decompress(r.data, faults=r.faults, geom=r.geom)
+            r.rc, r.result, r.report = codec.decompress(r.data, faults=r.faults, geom=r.geom, header=r.header)
         r.t_done = clock()
         _finish(r, keep_results)
         r.done.set()

@@ -352,6 +352,38 @@ def test_batch_item_errors_stay_per_item(codec):
     assert np.array_equal(res[0][1].cpu().numpy(), s_r)
 
 
+def test_caller_header_is_checked_against_the_stream(codec):
+    """Compression returns the stream header; decompression given that copy
+    matches decompression that reads it back, and a copy that differs from
+    the stream (here only in the stored bound, which the host cannot tell)
+    is a format error that writes nothing."""
+    x = synth.grf_field((30, 26, 22), seed=21)
+    rc, s, rep = codec.compress(torch.from_numpy(x).cuda(), (6, 6, 6), 1e-3)
+    assert rc == 0
+    s = s.clone()  # not the codec's own buffer: nothing cached for it
+    hdr = rep["header"]
+    assert hdr == bytes(s[: sdcsz.HEADER_BYTES].cpu().numpy())
+    rc_r, y_r, _ = ref.decompress(s.cpu().numpy())
+    for h in (None, hdr):
+        print(f"case header given={h is not None}", flush=True)
+        rc, y, _ = codec.decompress(s, header=h)
+        assert rc == rc_r == 0
+        assert np.array_equal(y_r.view(np.uint8), y.cpu().numpy().view(np.uint8))
+    bad = bytearray(hdr)
+    bad[56] ^= 1  # lowest mantissa bit of the stored bound
+    out = torch.full(x.shape, 7.0, device="cuda:0")
+    rc, y, _ = codec.decompress(s, out=out, header=bytes(bad))
+    assert rc == sdcsz.EFORMAT
+    assert bool((out == 7.0).all())
+    # a batch mixing items with a correct header, a wrong one and none
+    print("case header batch", flush=True)
+    rc, res = codec.decompress_batch([s, s, s], headers=[hdr, bytes(bad), None])
+    assert rc == sdcsz.EFORMAT
+    assert [r[0] for r in res] == [0, sdcsz.EFORMAT, 0]
+    for i in (0, 2):
+        assert np.array_equal(y_r.view(np.uint8), res[i][1].cpu().numpy().view(np.uint8))
+
+
 @pytest.mark.parametrize("lanes", [64, 128])
 def test_launch_shape_does_not_change_results(codec, lanes):
     from paper_2010_03144_amd import tune
