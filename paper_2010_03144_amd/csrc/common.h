@@ -29,9 +29,10 @@ enum {
   C_COR = 2 * SDCSZ_N_TARGETS,
   C_UNC = 3 * SDCSZ_N_TARGETS,
   C_MISSING = 4 * SDCSZ_N_TARGETS,  // a code without codeword was met while encoding
+  C_HIST_DONE,                       // histogram chunks finished (the call's first job only)
   C_N = 40
 };
-static_assert(C_MISSING < C_N, "counter layout");
+static_assert(C_HIST_DONE < C_N, "counter layout");
 
 // Block grid of a field normalised to three axes (leading axes of extent 1).
 struct Geo {

@@ -590,7 +590,14 @@ struct CompItem {  // one field of a compression call
   uint8_t header[kHeader];  // the stream's header, when written
 };
 
-constexpr uint64_t kPairPrefix = 32768;  // histogram entries returned with the first synchronisation
+// Histogram entries returned with the first synchronisation (the rest, if
+// any, take a second one): twice the last call's total on this thread, or
+// half the previous guess if that is more (at least kPairMin), so that a
+// steady workload copies little more than it needs and a mixed one rarely
+// takes the second round trip.
+constexpr uint64_t kPairPrefix = 32768;  // guess of a thread's first call
+constexpr uint64_t kPairMin = 4096;
+thread_local uint64_t t_pair_guess = kPairPrefix;
 // u64 words per field read back at the end of a compression: counters,
 // results, redo count, header bytes
 constexpr uint32_t kResWords = C_N + R_N + 1 + kHeader / 8;
@@ -824,7 +831,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   for (int c = 0; c < kClasses; c++)
     for (int d = 0; d < 2; d++)
       for (int a = 0; a < 2; a++) up.tabs.push_back(&t_fast[c][d][a]);
-  uint8_t *hs = t_stage.get(std::max<size_t>(up.bytes(nj), 4 * nj + 8 + 8 * kPairPrefix + 64));
+  uint8_t *hs = t_stage.get(std::max<size_t>(up.bytes(nj), 4 * nj + 8 + 8 * t_pair_guess + 64));
   if (!hs) return SDCSZ_EHIP;
   up.place(jobs, hs, ws + B.jobs);
   HIPCHK(hipMemcpyAsync(ws + B.jobs, hs, up.bytes(nj), hipMemcpyHostToDevice, st));
@@ -888,20 +895,20 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   uint32_t *d_counts = (uint32_t *)(ws + B.counts);
   uint64_t *d_pairs = (uint64_t *)(ws + B.pairs);
   uint32_t *d_chunks = (uint32_t *)(ws + B.chunks);
-  launch(PH_NONE, false, false, k_hist_count, grid(t_hchunk), dim3(256), st, d_hchunk, d_chunks);
-  launch(PH_NONE, false, false, k_hist_scan, dim3(1), dim3(256), st, nj, d_chunks, d_counts);
+  launch(PH_NONE, false, false, k_hist_count, grid(t_hchunk), dim3(256), st, d_hchunk, d_chunks, d_counts);
   launch(PH_NONE, false, false, k_hist_pack, grid(t_hchunk), dim3(256), st, d_hchunk, (const uint32_t *)d_chunks,
          d_pairs);
   HIPCHK(hipGetLastError());
 
-  // ---- histograms back (the first kPairPrefix entries with the counts)
+  // ---- histograms back (the first t_pair_guess entries with the counts)
   const uint64_t head = B.pairs - B.counts;
-  const uint64_t pre = std::min<uint64_t>(kPairPrefix, cap);
+  const uint64_t pre = std::min<uint64_t>(t_pair_guess, cap);
   HIPCHK(hipMemcpyAsync(hs, ws + B.counts, head + 8 * pre, hipMemcpyDeviceToHost, st));
   HIPCHK(sync_wait(st));
   std::vector<uint32_t> cnt_sym((const uint32_t *)hs, (const uint32_t *)hs + nj);
   uint64_t total_pairs = 0;
   for (uint32_t j = 0; j < nj; j++) total_pairs += cnt_sym[j];
+  t_pair_guess = std::max<uint64_t>({kPairMin, 2 * total_pairs, t_pair_guess / 2});
   // pinned room, in stage B: [jobs and tables | codebook lists] (one upload,
   // mirroring the device batch area), then the histogram pairs, then results
   const uint64_t JR = jobs_region(nj);
@@ -938,6 +945,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     build_codebooks(cj);
   }
   Tab t_put, t_chk_fast[kClasses], t_chk_gen, t_s1, t_s2, t_hdr, t_enc_fast[kClasses][2], t_enc_gen[2], t_res;
+  bool any_empty = false;
   for (uint32_t j = 0; j < nj; j++) {
     const Job &J = jobs[j];
     const CompPlan &f = fp[j];
@@ -951,6 +959,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     }
     t_s1.add(j, scan_chunks(f.g.n_blocks));
     t_s2.add(j, 1);
+    any_empty |= f.g.n_blocks == 0;
     t_hdr.add(j, grid_for(J.n_sym, 256));
     t_res.add(j, 1);
   }
@@ -978,9 +987,11 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
       pl.fs.push_back([&](bool a, bool b) { launch(PH_CHECK, a, b, k_codes_check, grid(t_chk_gen), dim3(256), st, D[1]); });
     pl.run();
   }
-  if (t_s1.total()) launch(PH_SCAN_C, true, false, k_scan1, grid(t_s1), dim3(kScanThreads), st, D[2]);
-  launch(PH_SCAN_C, !t_s1.total(), !t_s1.total(), k_scan2, grid(t_s2), dim3(kScanThreads), st, D[3]);
-  if (t_s1.total()) launch(PH_SCAN_C, false, true, k_scan3, grid(t_s1), dim3(kScanThreads), st, D[2]);
+  if (any_empty) launch(PH_SCAN_C, true, !t_s1.total(), k_scan2, grid(t_s2), dim3(kScanThreads), st, D[3]);
+  if (t_s1.total()) {
+    launch(PH_SCAN_C, !any_empty, false, k_scan1, grid(t_s1), dim3(kScanThreads), st, D[2]);
+    launch(PH_SCAN_C, false, true, k_scan3, grid(t_s1), dim3(kScanThreads), st, D[2]);
+  }
   launch(PH_NONE, false, false, k_header, grid(t_hdr), dim3(256), st, D[4]);
   {
     PhaseLaunch pl{PH_ENCODE, {}};
@@ -1265,9 +1276,13 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
   auto grid = [](const Tab &t) { return dim3(t.total()); };
   launch(PH_NONE, false, false, k_zero_jobs, grid(t_zero), dim3(256), st, D[0]);
   launch(PH_NONE, false, false, k_dectab, grid(t_one), dim3(256), st, D[1]);
-  if (t_s1.total()) launch(PH_SCAN_D, true, false, k_scan1, grid(t_s1), dim3(kScanThreads), st, D[2]);
-  launch(PH_SCAN_D, !t_s1.total(), !t_s1.total(), k_scan2, grid(t_one), dim3(kScanThreads), st, D[1]);
-  if (t_s1.total()) launch(PH_SCAN_D, false, true, k_scan3, grid(t_s1), dim3(kScanThreads), st, D[2]);
+  bool any_empty = false;
+  for (uint32_t j = 0; j < nj; j++) any_empty |= jobs[j].g.n_blocks == 0;
+  if (any_empty) launch(PH_SCAN_D, true, !t_s1.total(), k_scan2, grid(t_one), dim3(kScanThreads), st, D[1]);
+  if (t_s1.total()) {
+    launch(PH_SCAN_D, !any_empty, false, k_scan1, grid(t_s1), dim3(kScanThreads), st, D[2]);
+    launch(PH_SCAN_D, false, true, k_scan3, grid(t_s1), dim3(kScanThreads), st, D[2]);
+  }
   launch(PH_NONE, false, false, k_dec_check, grid(t_one), dim3(64), st, D[1]);
   // blocks a fault plan names (full decompression) run through the generic routine first
   for (uint32_t j = 0; j < nj; j++) {

@@ -27,49 +27,69 @@ __global__ void __launch_bounds__(256) k_put_codes(JobTab t) {
 // Histogram of each job compacted to (symbol << 32 | count) for the used
 // symbols, in symbol order, all jobs one after another.  The 65536 symbols
 // of a job are cut into kHistChunks chunks: k_hist_count counts the used
-// symbols of every chunk (one work-group per chunk), k_hist_scan (one
-// work-group) turns the counts into offsets and per-job totals, k_hist_pack
-// writes every chunk's entries at its offset.
+// symbols of every chunk (one work-group per chunk), and the call's last
+// work-group to finish (a ticket among the first job's counters) turns the
+// counts into offsets and per-job totals; k_hist_pack writes every chunk's
+// entries at its offset.
 constexpr uint32_t kHistChunks = 64, kHistChunk = 65536 / kHistChunks;
+static_assert(kHistChunks == 64, "a job's chunk counts are one wave's lanes");
 
-__global__ void __launch_bounds__(256) k_hist_count(JobTab t, uint32_t *chunk_cnt) {
+namespace {
+// exclusive scan of one value per thread over a 256-thread work-group;
+// *total: the sum over the work-group, *wave_total: over the thread's wave
+__device__ inline uint32_t wg_exclusive_u32(uint32_t v, uint32_t *total, uint32_t *wave_total) {
+  __shared__ uint32_t ws[4];
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t inc = v;
+#pragma unroll
+  for (uint32_t d = 1; d < 64; d <<= 1) {
+    const uint32_t u = __shfl_up(inc, d);
+    if (lane >= d) inc += u;
+  }
+  if (lane == 63) ws[wave] = inc;
+  __syncthreads();
+  uint32_t pre = 0, all = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < 4; q++) {
+    pre += q < wave ? ws[q] : 0u;
+    all += ws[q];
+  }
+  *wave_total = ws[wave];
+  __syncthreads();  // ws is free for the next call
+  *total = all;
+  return pre + inc - v;
+}
+}  // namespace
+
+__global__ void __launch_bounds__(256) k_hist_count(JobTab t, uint32_t *chunk_cnt, uint32_t *counts) {
   const JobWg jw = job_of(t);
   const uint32_t *hist = jw.J->cw.hist + jw.b * kHistChunk;
   uint32_t c = 0;
   for (uint32_t s = threadIdx.x; s < kHistChunk; s += blockDim.x) c += hist[s] ? 1u : 0u;
   for (int off = 32; off > 0; off >>= 1) c += (uint32_t)__shfl_xor((int)c, off);
   __shared__ uint32_t wsum[4];
+  __shared__ uint32_t last;
   if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
   __syncthreads();
-  if (threadIdx.x == 0) chunk_cnt[jw.slot * kHistChunks + jw.b] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-}
-
-// one work-group: exclusive scan of the n * kHistChunks chunk counts in
-// place, and each job's total into counts[]
-__global__ void __launch_bounds__(256) k_hist_scan(uint32_t n, uint32_t *chunk_cnt, uint32_t *counts) {
-  __shared__ uint32_t pre[256];
-  __shared__ uint64_t carry;
-  if (threadIdx.x == 0) carry = 0;
+  if (threadIdx.x == 0) {
+    chunk_cnt[jw.slot * kHistChunks + jw.b] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __threadfence();
+    last = atomicAdd(&t.jobs[0].cw.cnt[C_HIST_DONE], 1ull) + 1 == gridDim.x;
+  }
   __syncthreads();
-  const uint32_t total = n * kHistChunks;
+  if (!last) return;
+  __threadfence();
+  // exclusive scan of all chunk counts in place; a job's chunks are one wave
+  const uint32_t total = gridDim.x;
+  uint32_t carry = 0;
   for (uint32_t base = 0; base < total; base += 256) {
     const uint32_t i = base + threadIdx.x;
     const uint32_t v = i < total ? chunk_cnt[i] : 0u;
-    pre[threadIdx.x] = v;
-    __syncthreads();
-    for (uint32_t off = 1; off < 256; off <<= 1) {
-      const uint32_t u = threadIdx.x >= off ? pre[threadIdx.x - off] : 0u;
-      __syncthreads();
-      pre[threadIdx.x] += u;
-      __syncthreads();
-    }
-    if (i < total) chunk_cnt[i] = (uint32_t)carry + pre[threadIdx.x] - v;
-    // a job's chunks all sit in one piece of 256 (kHistChunks divides 256)
-    if (i < total && i % kHistChunks == kHistChunks - 1)
-      counts[i / kHistChunks] = pre[threadIdx.x] - (i % 256 >= kHistChunks ? pre[i % 256 - kHistChunks] : 0u);
-    __syncthreads();
-    if (threadIdx.x == 0) carry += pre[255];
-    __syncthreads();
+    uint32_t all, job_total;
+    const uint32_t ex = wg_exclusive_u32(v, &all, &job_total);
+    if (i < total) chunk_cnt[i] = carry + ex;
+    if (i < total && (threadIdx.x & 63) == 63) counts[i / kHistChunks] = job_total;
+    carry += all;
   }
 }
 
@@ -80,16 +100,8 @@ __global__ void __launch_bounds__(256) k_hist_pack(JobTab t, const uint32_t *chu
   constexpr uint32_t per = kHistChunk / 256;
   uint32_t mine = 0;
   for (uint32_t q = 0; q < per; q++) mine += hist[s0 + threadIdx.x * per + q] ? 1u : 0u;
-  __shared__ uint32_t pre[256];
-  pre[threadIdx.x] = mine;
-  __syncthreads();
-  for (uint32_t off = 1; off < 256; off <<= 1) {
-    const uint32_t v = threadIdx.x >= off ? pre[threadIdx.x - off] : 0u;
-    __syncthreads();
-    pre[threadIdx.x] += v;
-    __syncthreads();
-  }
-  uint64_t at = chunk_off[jw.slot * kHistChunks + jw.b] + pre[threadIdx.x] - mine;
+  uint32_t all, wt;
+  uint64_t at = chunk_off[jw.slot * kHistChunks + jw.b] + wg_exclusive_u32(mine, &all, &wt);
   for (uint32_t q = 0; q < per; q++) {
     const uint32_t s = s0 + threadIdx.x * per + q;
     const uint32_t c = hist[s];

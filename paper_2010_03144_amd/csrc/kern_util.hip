@@ -199,39 +199,53 @@ __device__ inline Tri item(const ScanSrc &s, uint64_t i) {
   return Tri{s.words[i * s.stride], m >> 1, m & 1u};
 }
 
-// exclusive scan of one Tri per thread across the work-group; returns the
-// exclusive prefix and sets *total.
-__device__ Tri block_exclusive(Tri v, Tri *total) {
-  __shared__ uint64_t sh[3][kScanThreads];
-  const uint32_t t = threadIdx.x;
-  sh[0][t] = v.a;
-  sh[1][t] = v.b;
-  sh[2][t] = v.c;
-  __syncthreads();
-  for (uint32_t off = 1; off < kScanThreads; off <<= 1) {
-    uint64_t a = 0, b = 0, c = 0;
-    if (t >= off) {
-      a = sh[0][t - off];
-      b = sh[1][t - off];
-      c = sh[2][t - off];
-    }
-    __syncthreads();
-    sh[0][t] += a;
-    sh[1][t] += b;
-    sh[2][t] += c;
-    __syncthreads();
+__device__ inline uint64_t wave_inclusive(uint64_t v) {
+  const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+  for (uint32_t d = 1; d < 64; d <<= 1) {
+    const uint64_t u = __shfl_up(v, d);
+    if (lane >= d) v += u;
   }
-  Tri incl{sh[0][t], sh[1][t], sh[2][t]};
-  *total = Tri{sh[0][kScanThreads - 1], sh[1][kScanThreads - 1], sh[2][kScanThreads - 1]};
+  return v;
+}
+
+// exclusive scan of one Tri per thread across the work-group (wave scans,
+// then the wave totals); returns the exclusive prefix and sets *total.
+__device__ Tri block_exclusive(Tri v, Tri *total) {
+  constexpr uint32_t kWaves = kScanThreads / 64;
+  __shared__ uint64_t wsum[3][kWaves];
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const Tri inc{wave_inclusive(v.a), wave_inclusive(v.b), wave_inclusive(v.c)};
+  if (lane == 63) {
+    wsum[0][wave] = inc.a;
+    wsum[1][wave] = inc.b;
+    wsum[2][wave] = inc.c;
+  }
   __syncthreads();
-  return Tri{incl.a - v.a, incl.b - v.b, incl.c - v.c};
+  Tri pre{0, 0, 0}, all{0, 0, 0};
+#pragma unroll
+  for (uint32_t q = 0; q < kWaves; q++) {
+    const Tri w{wsum[0][q], wsum[1][q], wsum[2][q]};
+    if (q < wave) {
+      pre.a += w.a;
+      pre.b += w.b;
+      pre.c += w.c;
+    }
+    all.a += w.a;
+    all.b += w.b;
+    all.c += w.c;
+  }
+  __syncthreads();  // wsum is free for the next call
+  *total = all;
+  return Tri{pre.a + inc.a - v.a, pre.b + inc.b - v.b, pre.c + inc.c - v.c};
 }
 }  // namespace
 
 // Exclusive scans of (payload words, outliers, regression flag) per block:
-// k_scan1 totals per chunk of kScanChunk blocks, k_scan2 (one work-group per
-// job) scans the chunk totals, k_scan3 writes the offsets and the 64-bit
-// totals.  A job without blocks gets zero offsets and totals from k_scan2.
+// k_scan1 totals per chunk of kScanChunk blocks; k_scan3 adds up the totals
+// of the chunks before its own and writes the offsets, and the 64-bit totals
+// after the last block.  k_scan2 gives a job without blocks its zero offset
+// and totals (launched only when a call has such a job).
 __global__ void __launch_bounds__(kScanThreads) k_scan1(JobTab t) {
   const JobWg jw = job_of(t);
   const ScanSrc src = jw.J->ss;
@@ -256,36 +270,14 @@ __global__ void __launch_bounds__(kScanThreads) k_scan1(JobTab t) {
   }
 }
 
-// one work-group per job: exclusive scan of the chunk totals, in place
+// one work-group per job: zero offset and totals of a job without blocks
 __global__ void __launch_bounds__(kScanThreads) k_scan2(JobTab t) {
   const Job &J = *job_of(t).J;
-  const uint64_t nblk = J.g.n_blocks;
-  if (nblk == 0) {
-    if (threadIdx.x == 0) {
-      J.sc_off_pay[0] = 0;
-      J.sc_off_out[0] = 0;
-      J.sc_off_coef[0] = 0;
-      J.sc_tot[0] = J.sc_tot[1] = J.sc_tot[2] = 0;
-    }
-    return;
-  }
-  uint64_t *part = J.sc_part;
-  const uint32_t nparts = (uint32_t)((nblk + kScanChunk - 1) / kScanChunk);
-  Tri carry{0, 0, 0};
-  for (uint32_t base = 0; base < nparts; base += kScanThreads) {
-    uint32_t i = base + threadIdx.x;
-    Tri v{0, 0, 0};
-    if (i < nparts) v = Tri{part[3 * i], part[3 * i + 1], part[3 * i + 2]};
-    Tri tot;
-    Tri ex = block_exclusive(v, &tot);
-    if (i < nparts) {
-      part[3 * i] = carry.a + ex.a;
-      part[3 * i + 1] = carry.b + ex.b;
-      part[3 * i + 2] = carry.c + ex.c;
-    }
-    carry.a += tot.a;
-    carry.b += tot.b;
-    carry.c += tot.c;
+  if (J.g.n_blocks == 0 && threadIdx.x == 0) {
+    J.sc_off_pay[0] = 0;
+    J.sc_off_out[0] = 0;
+    J.sc_off_coef[0] = 0;
+    J.sc_tot[0] = J.sc_tot[1] = J.sc_tot[2] = 0;
   }
 }
 
@@ -298,6 +290,15 @@ __global__ void __launch_bounds__(kScanThreads) k_scan3(JobTab t) {
   uint64_t *off_pay = J.sc_off_pay, *total = J.sc_tot;
   uint32_t *off_out = J.sc_off_out, *off_coef = J.sc_off_coef;
   const uint32_t bid = jw.b;
+  // totals of the chunks before this one
+  Tri before{0, 0, 0};
+  for (uint32_t i = threadIdx.x; i < bid; i += kScanThreads) {
+    before.a += part[3 * i];
+    before.b += part[3 * i + 1];
+    before.c += part[3 * i + 2];
+  }
+  Tri chunk;
+  block_exclusive(before, &chunk);
   const uint64_t base = (uint64_t)bid * kScanChunk + (uint64_t)threadIdx.x * kScanItems;
   Tri loc[kScanItems];
   Tri s{0, 0, 0};
@@ -309,7 +310,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan3(JobTab t) {
   }
   Tri tot;
   Tri ex = block_exclusive(s, &tot);
-  Tri run{part[3 * bid] + ex.a, part[3 * bid + 1] + ex.b, part[3 * bid + 2] + ex.c};
+  Tri run{chunk.a + ex.a, chunk.b + ex.b, chunk.c + ex.c};
   for (uint32_t u = 0; u < kScanItems; u++) {
     if (base + u < n) {
       off_pay[base + u] = run.a;
