@@ -234,7 +234,7 @@ struct CompLayout {
 CompLayout comp_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
   CompLayout L;
   const uint64_t nb = g.n_blocks, vb = vbytes(dtype), slots = nb * g.bpts;
-  const uint64_t chunks = (nb + kScanChunk - 1) / kScanChunk + 1;
+  const uint64_t chunks = (nb + scan_chunk(nb) - 1) / scan_chunk(nb) + 1;
   uint64_t at = 0;
   auto take = [&](uint64_t bytes) {
     uint64_t o = at;
@@ -285,7 +285,7 @@ struct DecLayout {
 DecLayout dec_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
   DecLayout L;
   const uint64_t nb = g.n_blocks, vb = vbytes(dtype), slots = nb * g.bpts;
-  const uint64_t chunks = (nb + kScanChunk - 1) / kScanChunk + 1;
+  const uint64_t chunks = (nb + scan_chunk(nb) - 1) / scan_chunk(nb) + 1;
   uint64_t at = 0;
   auto take = [&](uint64_t bytes) {
     uint64_t o = at;
@@ -378,7 +378,7 @@ uint32_t fast_launch(const Geo &g, Launch *L, uint32_t lanes) {
   return L->full_wgs + (uint32_t)((L->shell_count + lanes - 1) / lanes);
 }
 
-uint32_t scan_chunks(uint64_t nb) { return (uint32_t)((nb + kScanChunk - 1) / kScanChunk); }
+uint32_t scan_chunks(uint64_t nb) { return (uint32_t)((nb + scan_chunk(nb) - 1) / scan_chunk(nb)); }
 
 // ---------------------------------------------------------------------------
 // pinned host staging of the calling thread (grown on demand, kept until the

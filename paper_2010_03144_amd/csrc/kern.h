@@ -18,8 +18,16 @@ struct ScanSrc {
 };
 
 constexpr uint32_t kScanThreads = 256;
-constexpr uint32_t kScanItems = 8;
-constexpr uint32_t kScanChunk = kScanThreads * kScanItems;
+// Blocks per thread of the scans: 2 (many small work-groups hide latency
+// best), more for fields of over 2^20 blocks so that a job has at most
+// kScanMaxChunks chunks (each offsets work-group adds up the totals of the
+// chunks before its own).
+constexpr uint32_t kScanMaxChunks = 2048;
+__host__ __device__ inline uint32_t scan_items(uint64_t nb) {
+  const uint64_t per = (nb + (uint64_t)kScanThreads * kScanMaxChunks - 1) / ((uint64_t)kScanThreads * kScanMaxChunks);
+  return per > 2 ? (uint32_t)per : 2u;
+}
+__host__ __device__ inline uint64_t scan_chunk(uint64_t nb) { return (uint64_t)kScanThreads * scan_items(nb); }
 constexpr uint32_t kRangeThreads = 256;
 constexpr uint32_t kHistWin = 16384;  // largest LDS histogram window of the compression kernel (64 KiB)
 constexpr uint32_t kRangeBlocks = 2048;

@@ -242,19 +242,20 @@ __device__ Tri block_exclusive(Tri v, Tri *total) {
 }  // namespace
 
 // Exclusive scans of (payload words, outliers, regression flag) per block:
-// k_scan1 totals per chunk of kScanChunk blocks; k_scan3 adds up the totals
-// of the chunks before its own and writes the offsets, and the 64-bit totals
-// after the last block.  k_scan2 gives a job without blocks its zero offset
-// and totals (launched only when a call has such a job).
+// k_scan1 totals per chunk of scan_chunk(n) blocks; k_scan3 adds up the
+// totals of the chunks before its own and writes the offsets, and the 64-bit
+// totals after the last block.  k_scan2 gives a job without blocks its zero
+// offset and totals (launched only when a call has such a job).
 __global__ void __launch_bounds__(kScanThreads) k_scan1(JobTab t) {
   const JobWg jw = job_of(t);
   const ScanSrc src = jw.J->ss;
   const uint64_t n = jw.J->g.n_blocks;
+  const uint32_t items = scan_items(n);
   uint64_t *part = jw.J->sc_part;
   const uint32_t bid = jw.b;
-  const uint64_t base = (uint64_t)bid * kScanChunk + (uint64_t)threadIdx.x * kScanItems;
+  const uint64_t base = (uint64_t)bid * scan_chunk(n) + (uint64_t)threadIdx.x * items;
   Tri s{0, 0, 0};
-  for (uint32_t u = 0; u < kScanItems; u++)
+  for (uint32_t u = 0; u < items; u++)
     if (base + u < n) {
       Tri v = item(src, base + u);
       s.a += v.a;
@@ -286,6 +287,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan3(JobTab t) {
   const Job &J = *jw.J;
   const ScanSrc src = J.ss;
   const uint64_t n = J.g.n_blocks;
+  const uint32_t items = scan_items(n);
   const uint64_t *part = J.sc_part;
   uint64_t *off_pay = J.sc_off_pay, *total = J.sc_tot;
   uint32_t *off_out = J.sc_off_out, *off_coef = J.sc_off_coef;
@@ -299,27 +301,26 @@ __global__ void __launch_bounds__(kScanThreads) k_scan3(JobTab t) {
   }
   Tri chunk;
   block_exclusive(before, &chunk);
-  const uint64_t base = (uint64_t)bid * kScanChunk + (uint64_t)threadIdx.x * kScanItems;
-  Tri loc[kScanItems];
+  const uint64_t base = (uint64_t)bid * scan_chunk(n) + (uint64_t)threadIdx.x * items;
   Tri s{0, 0, 0};
-  for (uint32_t u = 0; u < kScanItems; u++) {
-    loc[u] = base + u < n ? item(src, base + u) : Tri{0, 0, 0};
-    s.a += loc[u].a;
-    s.b += loc[u].b;
-    s.c += loc[u].c;
-  }
-  Tri tot;
-  Tri ex = block_exclusive(s, &tot);
-  Tri run{chunk.a + ex.a, chunk.b + ex.b, chunk.c + ex.c};
-  for (uint32_t u = 0; u < kScanItems; u++) {
+  for (uint32_t u = 0; u < items; u++)
     if (base + u < n) {
-      off_pay[base + u] = run.a;
-      off_out[base + u] = (uint32_t)run.b;
-      off_coef[base + u] = (uint32_t)run.c;
+      const Tri v = item(src, base + u);
+      s.a += v.a;
+      s.b += v.b;
+      s.c += v.c;
     }
-    run.a += loc[u].a;
-    run.b += loc[u].b;
-    run.c += loc[u].c;
+  Tri tot;
+  const Tri ex = block_exclusive(s, &tot);
+  Tri run{chunk.a + ex.a, chunk.b + ex.b, chunk.c + ex.c};
+  for (uint32_t u = 0; u < items && base + u < n; u++) {  // the items again (cache hits)
+    off_pay[base + u] = run.a;
+    off_out[base + u] = (uint32_t)run.b;
+    off_coef[base + u] = (uint32_t)run.c;
+    const Tri v = item(src, base + u);
+    run.a += v.a;
+    run.b += v.b;
+    run.c += v.c;
     if (base + u + 1 == n) {
       off_pay[n] = run.a;
       off_out[n] = (uint32_t)run.b;

@@ -116,6 +116,13 @@ def test_shapes(codec, shape, block):
     check_roundtrip(codec, x.astype(np.float64), block, 0.05, eb_mode="abs")
 
 
+def test_scan_of_more_than_a_million_blocks(codec):
+    """Over 2^20 blocks a scan thread takes more than two blocks (here 3):
+    offsets and totals must still match the oracle's stream."""
+    x = synth.grf_field((2_200_000,), seed=12, dtype=np.float32)
+    check_roundtrip(codec, x, (2,), 1e-3)
+
+
 def test_special_values(codec):
     x = synth.bumps_field((20, 20, 20), seed=3)
     x[1, 2, 3] = np.nan
