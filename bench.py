@@ -359,9 +359,13 @@ def serve_bench(torch, xd, seconds, rate=200.0, seed=5):
         s_at_rate = served(make())
         log("serve: the same requests one at a time")
         p_at_rate = plain(make())
-        log("serve: all requests at once (capacity)")
-        s_cap = served(make(False))
-        p_cap = plain(make(False))
+        # capacity varies from run to run (by 2x between runs on one box):
+        # three alternating runs of each form, the median reported
+        log("serve: all requests at once (capacity), 3 runs of each form")
+        s_caps, p_caps = [], []
+        for _ in range(3):
+            s_caps.append(served(make(False))["gbs"])
+            p_caps.append(plain(make(False))["gbs"])
     finally:
         gc.enable()
     offered = sum(serve.field_bytes(r) for r in make()) / seconds / 1e9
@@ -370,7 +374,8 @@ def serve_bench(torch, xd, seconds, rate=200.0, seed=5):
                         f"field), 25% FP64, eb log-uniform 1e-5..1e-2 REL, block 6x6x6, ABFT on, 20% with "
                         f"fault plans; HBM admission budget 200 GB, 2 workers (seed {seed})",
             "offered_gbs": round(offered, 3), "served": s_at_rate, "one_at_a_time": p_at_rate,
-            "capacity_served_gbs": s_cap["gbs"], "capacity_one_at_a_time_gbs": p_cap["gbs"]}
+            "capacity_served_gbs": float(np.median(s_caps)), "capacity_one_at_a_time_gbs": float(np.median(p_caps)),
+            "capacity_runs_gbs": {"served": s_caps, "one_at_a_time": p_caps}}
 
 
 def main():

@@ -379,10 +379,12 @@ __device__ __forceinline__ void decode_rows(const uint8_t *__restrict__ s, const
       cprev = r;
       if (v) sum += Wd<T>::sum(r);
     }
-    char *dst = wbase + (loff + (uint32_t)j * RSB);  // non-temporal row stores, as in 3D
+    // plain row stores: non-temporal ones (as in 3D) made the decoding of a
+    // mixed batch's 2D fields much slower
+    char *dst = wbase + (loff + (uint32_t)j * RSB);
 #pragma unroll
     for (int k = 0; k < B2; k++)
-      if (FULL || (uint32_t)k < n2) __builtin_nontemporal_store(Pr[k], (T *)(dst + k * sizeof(T)));
+      if (FULL || (uint32_t)k < n2) *(T *)(dst + k * sizeof(T)) = Pr[k];
     drow_fence(sum, br.lp);
   }
   if (used_out != nout || br.pos > nw * 32u) bad = true;

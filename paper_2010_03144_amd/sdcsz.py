@@ -121,11 +121,11 @@ def lib():
 
 
 def report_dict(r):
+    inj, det, cor, unc = r.injected[:], r.detected[:], r.corrected[:], r.uncorrectable[:]
     d = {"n_blocks": r.n_blocks, "n_outliers": r.n_outliers, "n_regression": r.n_regression,
          "payload_words": r.payload_words, "stream_size": r.stream_size, "eb_abs": r.eb_abs}
     for i, t in enumerate(TARGETS):
-        d[t] = {"injected": r.injected[i], "detected": r.detected[i],
-                "corrected": r.corrected[i], "uncorrectable": r.uncorrectable[i]}
+        d[t] = {"injected": inj[i], "detected": det[i], "corrected": cor[i], "uncorrectable": unc[i]}
     return d
 
 
