@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -554,17 +555,24 @@ void build_codebook(const CodebookJob &c, HuffmanBuilder &b, std::vector<uint64_
   }
 }
 
+// Threads take the fields largest first from a shared counter, so that the
+// few fields with tens of thousands of symbols start at once and the small
+// ones fill in around them.
 void build_codebooks(const std::vector<CodebookJob> &cj) {
   uint64_t work = 0;
   for (auto &c : cj) work += c.n;
   const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   const unsigned nt = (unsigned)std::min<uint64_t>(hw, std::max<uint64_t>(1, std::min<uint64_t>(cj.size(), work / 4096)));
-  auto run = [&](unsigned t) {
+  std::vector<uint32_t> order(cj.size());
+  for (uint32_t i = 0; i < order.size(); i++) order[i] = i;
+  if (nt > 1) std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cj[a].n > cj[b].n; });
+  std::atomic<size_t> next{0};
+  auto run = [&](unsigned) {
     HuffmanBuilder b;
     std::vector<uint64_t> cnt;
     std::vector<uint8_t> len;
     std::vector<uint32_t> code;
-    for (size_t i = t; i < cj.size(); i += nt) build_codebook(cj[i], b, cnt, len, code);
+    for (size_t k; (k = next.fetch_add(1)) < order.size();) build_codebook(cj[order[k]], b, cnt, len, code);
   };
   if (nt <= 1) {
     run(0);
