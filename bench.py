@@ -205,6 +205,45 @@ def block_size_report(codec, xd, ebs=(1e-2, 1e-3, 1e-4)):
             "autotuned_block": picks}
 
 
+def region_report(codec, torch, xd, block, eb=1e-3, edges=(32, 64, 128, 256, 512), reps=5):
+    """Random-access decompression (Sec. 5.1): time to decompress a centred
+    cube of each edge out of the stream of the whole field, against full
+    decompression of the same stream; every region must equal the matching
+    slice of the full result bit for bit."""
+    rc, s, _ = codec.compress(xd, block, eb)
+    assert rc == 0, rc
+    s = s.clone()  # a stream of its own (its header is read back like any caller's)
+    sync = torch.cuda.synchronize
+
+    def med(fn):
+        fn()
+        sync()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            r = fn()
+            sync()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), r
+
+    t_full, (rc, y, _) = med(lambda: codec.decompress(s))
+    assert rc == 0, rc
+    rows = []
+    for e in edges:
+        lo = [(n - min(e, n)) // 2 for n in xd.shape]
+        hi = [a + min(e, n) for a, n in zip(lo, xd.shape)]
+        t, (rc, r, _) = med(lambda: codec.decompress_region(s, lo, hi))
+        assert rc == 0, rc
+        want = y[tuple(slice(a, b) for a, b in zip(lo, hi))]
+        assert torch.equal(r.view(torch.int32), want.contiguous().view(torch.int32)), e
+        frac = r.numel() / xd.numel()
+        rows.append({"edge": e, "fraction": round(frac, 6), "ms": round(t * 1e3, 4),
+                     "vs_full": round(t / t_full, 4)})
+    return {"workload": f"centred cubes out of the {'x'.join(map(str, xd.shape))} field's stream (eb {eb:g} REL, "
+                        f"ABFT on), median of {reps}; each region equals the slice of full decompression",
+            "full_ms": round(t_full * 1e3, 4), "regions": rows}
+
+
 def prep_fault_report(codec, torch, x, xd, block, eb=1e-3, k=10, trials=5):
     """Compression-ratio impact of computation errors in the prediction
     preparation (regression coefficients and sampled estimates, Sec. 4.1),
@@ -388,7 +427,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed 192-field batch")
-    ap.add_argument("--only", choices=["batch", "serve"], help="run one part alone and print its JSON")
+    ap.add_argument("--only", choices=["batch", "serve", "region"], help="run one part alone and print its JSON")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--tune-file", help="load launch shapes from this JSON file instead of autotuning")
     ap.add_argument("--save-tune", help="write the autotuned launch shapes to this JSON file")
@@ -427,10 +466,13 @@ def main():
         print(json.dumps(batch_bench(sdcsz.Codec("cuda:0"), torch, plain_loop=not args.batch_only_batched)),
               flush=True)
         return
-    if args.only == "serve":
+    if args.only in ("serve", "region"):
         log("generating 512^3 FP32 field")
         xd = torch.from_numpy(synth.grf_field((512, 512, 512), seed=2)).cuda()
-        print(json.dumps(serve_bench(torch, xd, args.serve_seconds)), flush=True)
+        if args.only == "serve":
+            print(json.dumps(serve_bench(torch, xd, args.serve_seconds)), flush=True)
+        else:
+            print(json.dumps(region_report(sdcsz.Codec("cuda:0"), torch, xd, (6, 6, 6))), flush=True)
         return
 
     shape = (args.size,) * 3
@@ -527,6 +569,8 @@ def main():
 
     if not args.no_extras:
         result["prep_faults"] = prep_fault_report(codec, torch, x, xd, block)
+        log("region decompression")
+        result["region"] = region_report(codec, torch, xd, block)
         log("block-size rate-distortion")
         result["block_size"] = block_size_report(codec, xd)
 

@@ -1169,7 +1169,9 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     d.rc = check_plan(d.g, d.h.dtype, d.faults, d.n_faults, true, f.plan);
     if (d.rc) continue;
     f.L = dec_layout(d.g, d.h.dtype, d.n_faults);
-    f.cls = d.mode == 0 ? fast_class(d.g, vbytes(d.h.dtype)) : -1;
+    // full and region decompression take the specialised decoder where the
+    // block shape has one; verification the generic kernel
+    f.cls = d.mode != 1 ? fast_class(d.g, vbytes(d.h.dtype)) : -1;
     f.fast = f.cls >= 0;
     f.pb = f.fast ? plan_block_list(f.plan) : std::vector<uint64_t>();
     per += f.L.total;
@@ -1252,7 +1254,20 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     t_zero.add(j, 1);
     t_one.add(j, 1);
     t_s1.add(j, scan_chunks(J.g.n_blocks));
-    if (fp[j].fast) {
+    if (fp[j].fast && J.mode == 2) {
+      // the box of blocks the region touches, one lane each (masked path)
+      uint64_t nbox = 1;
+      for (int a = 0; a < 3; a++) {
+        J.rblk.lo[a] = J.reg.lo[a] / J.g.b[a];
+        J.rblk.hi[a] = (J.reg.hi[a] - 1) / J.g.b[a] + 1;
+        nbox *= J.rblk.hi[a] - J.rblk.lo[a];
+      }
+      std::memset(&J.L, 0, sizeof(J.L));
+      J.L.shell_count = nbox;
+      const uint32_t ln = ln_dec[fp[j].cls][J.dtype];
+      t_fast[fp[j].cls][J.dtype].add(j, grid_for(nbox, ln));
+      t_redo[J.dtype].add(j, kMaxRedo / 64);
+    } else if (fp[j].fast) {
       t_fast[fp[j].cls][J.dtype].add(j, fast_launch(J.g, &J.L, ln_dec[fp[j].cls][J.dtype]));
       t_redo[J.dtype].add(j, kMaxRedo / 64);  // one thread per queue slot
     } else if (J.g.n_blocks) {
@@ -1342,8 +1357,7 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
   }
   if (!again.empty()) {
     Tab t_ag[2], t_res2;
-    for (uint32_t j : again) {
-      jobs[j].mode = 0;
+    for (uint32_t j : again) {  // full (mode 0) or region (mode 2) decompression, as in the first pass
       t_ag[jobs[j].dtype].add(j, grid_for(jobs[j].g.n_blocks, 64));
       t_res2.add(j, 1);
       launch(PH_NONE, false, false, k_zero_u64, dim3(1), dim3(64), st, jobs[j].dw.cnt, (uint64_t)C_N);

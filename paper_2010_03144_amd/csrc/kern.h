@@ -51,7 +51,8 @@ struct Job {
   PlanDev plan;
   Launch L;
   Header h;             // compression: fixed header fields; decompression: the stream's header
-  Region reg;           // decompression mode 2
+  Region reg;           // decompression mode 2: the region (values)
+  Region rblk;          // decompression mode 2 on the specialised decoder: the blocks it touches
   ScanSrc ss;           // what the block scans read, and where they write
   uint64_t *sc_part, *sc_off_pay, *sc_tot;
   uint32_t *sc_off_out, *sc_off_coef;

@@ -41,6 +41,23 @@ __device__ inline uint64_t dmap_block(const Geo &g, const Launch &L, uint32_t mo
   return (c0 * g.nb[1] + c1) * g.nb[2] + c2;
 }
 
+// Block of a region launch: lane idx walks, in C order, the box of blocks
+// the region touches (block coordinates rb.lo .. rb.hi).
+__device__ inline uint64_t rmap_block(const Geo &g, const Region &rb, uint64_t idx) {
+  const uint64_t e1 = rb.hi[1] - rb.lo[1], e2 = rb.hi[2] - rb.lo[2];
+  const uint64_t c2 = rb.lo[2] + idx % e2, t = idx / e2;
+  const uint64_t c1 = rb.lo[1] + t % e1, c0 = rb.lo[0] + t / e1;
+  return (c0 * g.nb[1] + c1) * g.nb[2] + c2;
+}
+
+// The output row of a region that holds field row (z, y), or null when the
+// row lies outside the region; a store through it must still check its
+// column x against [r.lo[2], r.hi[2]) and write at x - r.lo[2].
+template <typename T> __device__ inline T *region_row(T *out, const Region &r, uint64_t z, uint64_t y) {
+  if (z < r.lo[0] || z >= r.hi[0] || y < r.lo[1] || y >= r.hi[1]) return nullptr;
+  return out + ((z - r.lo[0]) * (r.hi[1] - r.lo[1]) + (y - r.lo[1])) * (r.hi[2] - r.lo[2]);
+}
+
 template <typename V> __device__ inline void dpin(V &v) { __asm__ volatile("" : "+v"(v)); }
 template <typename... V> __device__ inline void drow_fence(V &...v) {
   (dpin(v), ...);
@@ -151,12 +168,15 @@ __device__ inline uint32_t decode_sym(Window &br, const DecLds &t, const uint16_
 
 }  // namespace
 
-template <typename T, int ND, int B0, int B1, int B2, bool FULL>
+template <typename T, int ND, int B0, int B1, int B2, bool FULL, bool REG>
 __device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, const Header &h, const Geo &g,
                                              const DecWork &w, const PlanDev &plan, T *out, const Launch &L,
-                                             const DecLds &tl, uint32_t *win, uint64_t idx, uint64_t nlanes) {
+                                             const DecLds &tl, uint32_t *win, uint64_t idx, uint64_t nlanes,
+                                             const Region &reg, const Region &rb) {
+  static_assert(!(REG && FULL), "a region launch takes the masked path");
   bool active = idx < nlanes;
-  const uint64_t blk = dmap_block(g, L, FULL ? 0u : 1u, active ? idx : nlanes - 1);
+  const uint64_t blk = REG ? rmap_block(g, rb, active ? idx : nlanes - 1)
+                           : dmap_block(g, L, FULL ? 0u : 1u, active ? idx : nlanes - 1);
   const Box bx = box_of(g, blk);
   const uint64_t org = fidx(g, bx, 0, 0, 0);
   uint64_t omin = org;
@@ -261,12 +281,24 @@ __device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, cons
         Up = U1;
         if (v) sum += Wd<T>::sum(r);
       }
-      // store the row (non-temporal: the output is not read again here, and
-      // keeping it out of the caches leaves them to the payload windows)
-      char *dst = wbase + (loff + (uint32_t)i * PSB + (uint32_t)j * RSB);
+      if constexpr (REG) {
+        // the part of the row inside the region
+        T *row = region_row(out, reg, bx.o[0] + (uint64_t)i, bx.o[1] + (uint64_t)j);
+        if (row) {
 #pragma unroll
-      for (int k = 0; k < B2; k++)
-        if (FULL || (uint32_t)k < n2) __builtin_nontemporal_store(rv[k], (T *)(dst + k * sizeof(T)));
+          for (int k = 0; k < B2; k++) {
+            const uint64_t x = bx.o[2] + (uint64_t)k;
+            if ((uint32_t)k < n2 && x >= reg.lo[2] && x < reg.hi[2]) row[x - reg.lo[2]] = rv[k];
+          }
+        }
+      } else {
+        // store the row (non-temporal: the output is not read again here, and
+        // keeping it out of the caches leaves them to the payload windows)
+        char *dst = wbase + (loff + (uint32_t)i * PSB + (uint32_t)j * RSB);
+#pragma unroll
+        for (int k = 0; k < B2; k++)
+          if (FULL || (uint32_t)k < n2) __builtin_nontemporal_store(rv[k], (T *)(dst + k * sizeof(T)));
+      }
 #pragma unroll
       for (int k = 0; k < B2; k++) Sv[k] = rowold[k];
       drow_fence(cprev, sum, br.lp);
@@ -290,13 +322,16 @@ __device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, cons
 // previous reconstructed row in registers; the window is staged once per row
 // (B2 codewords of <= 24 bits plus the <= 127-bit skew fit in kWin words for
 // B2 <= 16).
-template <typename T, int B1, int B2, bool FULL>
+template <typename T, int B1, int B2, bool FULL, bool REG>
 __device__ __forceinline__ void decode_rows(const uint8_t *__restrict__ s, const Header &h, const Geo &g,
                                             const DecWork &w, const PlanDev &plan, T *out, const Launch &L,
-                                            const DecLds &tl, uint32_t *win, uint64_t idx, uint64_t nlanes) {
+                                            const DecLds &tl, uint32_t *win, uint64_t idx, uint64_t nlanes,
+                                            const Region &reg, const Region &rb) {
   static_assert(B2 * kMaxLen + 127 + 32 <= 32 * (int)kWin, "a row's codewords fit the window");
+  static_assert(!(REG && FULL), "a region launch takes the masked path");
   bool active = idx < nlanes;
-  const uint64_t blk = dmap_block(g, L, FULL ? 0u : 1u, active ? idx : nlanes - 1);
+  const uint64_t blk = REG ? rmap_block(g, rb, active ? idx : nlanes - 1)
+                           : dmap_block(g, L, FULL ? 0u : 1u, active ? idx : nlanes - 1);
   const Box bx = box_of(g, blk);
   const uint64_t org = fidx(g, bx, 0, 0, 0);
   uint64_t omin = org;
@@ -379,12 +414,23 @@ __device__ __forceinline__ void decode_rows(const uint8_t *__restrict__ s, const
       cprev = r;
       if (v) sum += Wd<T>::sum(r);
     }
-    // plain row stores: non-temporal ones (as in 3D) made the decoding of a
-    // mixed batch's 2D fields much slower
-    char *dst = wbase + (loff + (uint32_t)j * RSB);
+    if constexpr (REG) {
+      T *row = region_row(out, reg, bx.o[0], bx.o[1] + (uint64_t)j);
+      if (row) {
 #pragma unroll
-    for (int k = 0; k < B2; k++)
-      if (FULL || (uint32_t)k < n2) *(T *)(dst + k * sizeof(T)) = Pr[k];
+        for (int k = 0; k < B2; k++) {
+          const uint64_t x = bx.o[2] + (uint64_t)k;
+          if ((uint32_t)k < n2 && x >= reg.lo[2] && x < reg.hi[2]) row[x - reg.lo[2]] = Pr[k];
+        }
+      }
+    } else {
+      // plain row stores: non-temporal ones (as in 3D) made the decoding of a
+      // mixed batch's 2D fields much slower
+      char *dst = wbase + (loff + (uint32_t)j * RSB);
+#pragma unroll
+      for (int k = 0; k < B2; k++)
+        if (FULL || (uint32_t)k < n2) *(T *)(dst + k * sizeof(T)) = Pr[k];
+    }
     drow_fence(sum, br.lp);
   }
   if (used_out != nout || br.pos > nw * 32u) bad = true;
@@ -431,17 +477,35 @@ k_decode_fast(JobTab tab) {
     tl.long_n = ln;
   }
   __syncthreads();
+  const Region &reg = jw.J->reg, &rb = jw.J->rblk;
+  if (jw.J->mode == 2) {
+    // region decompression: one lane per block of the box of blocks the
+    // region touches (L.shell_count of them), each storing only its part of
+    // the region, at region-relative offsets
+    const uint64_t idx = (uint64_t)jw.b * blockDim.x + threadIdx.x;
+    if constexpr (ND == 2)
+      decode_rows<T, B1, B2, false, true>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx, L.shell_count, reg, rb);
+    else
+      decode_lanes<T, ND, B0, B1, B2, false, true>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx,
+                                                   L.shell_count, reg, rb);
+    return;
+  }
   const bool full = jw.b < L.full_wgs;
   const uint64_t idx = (uint64_t)(full ? jw.b : jw.b - L.full_wgs) * blockDim.x + threadIdx.x;
   if constexpr (ND == 2) {
     static_assert(B0 == 1, "2D blocks have one plane");
-    if (full) decode_rows<T, B1, B2, true>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx, L.full_count);
-    else decode_rows<T, B1, B2, false>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx, L.shell_count);
+    if (full)
+      decode_rows<T, B1, B2, true, false>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx, L.full_count, reg, rb);
+    else
+      decode_rows<T, B1, B2, false, false>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx, L.shell_count, reg,
+                                           rb);
   } else {
     if (full)
-      decode_lanes<T, ND, B0, B1, B2, true>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx, L.full_count);
+      decode_lanes<T, ND, B0, B1, B2, true, false>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx, L.full_count,
+                                                   reg, rb);
     else
-      decode_lanes<T, ND, B0, B1, B2, false>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx, L.shell_count);
+      decode_lanes<T, ND, B0, B1, B2, false, false>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx,
+                                                    L.shell_count, reg, rb);
   }
 }
 

@@ -217,6 +217,7 @@ template <typename T> __global__ void __launch_bounds__(64) k_decode_redo(JobTab
   T *out = (T *)jw.J->dst;
   if (*w.err) return;
   const uint32_t n = min(*w.redo_n, kMaxRedo);
+  const uint32_t mode = jw.J->mode == 2 ? 2u : 0u;  // the fast decoder runs full (0) or region (2) decompression
   const DecTab tab = *w.tab;
   const T q = (T)(2.0 * h.eb_abs);
   const uint64_t *sumdc = (const uint64_t *)(s + h.off_sumdc);
@@ -224,7 +225,7 @@ template <typename T> __global__ void __launch_bounds__(64) k_decode_redo(JobTab
     const uint64_t blk = w.redo[e] & ((1ull << 56) - 1), why = w.redo[e] >> 56;
     if (why == 3) {
       const PlanDev none{nullptr, 0, nullptr};
-      decode_one<T>(s, h, g, w, none, out, 0, Region{}, blk);
+      decode_one<T>(s, h, g, w, none, out, mode, jw.J->reg, blk);
       continue;
     }
     const Box b = box_of(g, blk);
@@ -237,10 +238,23 @@ template <typename T> __global__ void __launch_bounds__(64) k_decode_redo(JobTab
     }
     if (!ok)
       for (uint32_t p = 0; p < b.pts; p++) rec[p] = (T)0;
-    if (ok || why == 2)
+    if (ok || why == 2) {
+      const Region &reg = jw.J->reg;
       for (uint32_t i = 0, p = 0; i < b.n[0]; i++)
         for (uint32_t j = 0; j < b.n[1]; j++)
-          for (uint32_t k = 0; k < b.n[2]; k++, p++) out[fidx(g, b, i, j, k)] = rec[p];
+          for (uint32_t k = 0; k < b.n[2]; k++, p++) {
+            if (mode == 2) {  // region decompression: region-relative, inside the region only
+              const uint64_t z = b.o[0] + i, y = b.o[1] + j, x = b.o[2] + k;
+              if (z < reg.lo[0] || z >= reg.hi[0] || y < reg.lo[1] || y >= reg.hi[1] || x < reg.lo[2] ||
+                  x >= reg.hi[2])
+                continue;
+              out[((z - reg.lo[0]) * (reg.hi[1] - reg.lo[1]) + (y - reg.lo[1])) * (reg.hi[2] - reg.lo[2]) +
+                  (x - reg.lo[2])] = rec[p];
+            } else {
+              out[fidx(g, b, i, j, k)] = rec[p];
+            }
+          }
+    }
     if (ok) count(w.cnt, C_COR + SDCSZ_T_RECON);
     else count(w.cnt, C_UNC + SDCSZ_T_RECON);
   }

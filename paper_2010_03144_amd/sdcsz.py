@@ -432,9 +432,11 @@ class Codec:
         return rc, [(items[i].rc, outs[i], report_dict(items[i].rep)) for i in range(n)]
 
     def decompress_region(self, stream, lo, hi):
+        """Values of the box [lo, hi) of a stream's field: (rc, tensor of the
+        box's shape, report).  Only the blocks the box touches are decoded."""
         torch = self.torch
         L = lib()
-        rc, p, shape = self.info(stream)
+        rc, p, shape = self._geometry(stream)
         if rc != OK:
             return rc, None, None
         dt = torch.float32 if p.dtype == 0 else torch.float64

@@ -201,6 +201,57 @@ def test_region(codec):
     assert np.array_equal(part_r.view(np.uint32), part_g.cpu().numpy().view(np.uint32))
 
 
+def _regions(shape, block, rng, n):
+    """Regions of a field: the whole field, single values at the corners,
+    regions aligned to blocks, regions inside one block, slabs, regions
+    touching the partial blocks at the upper faces, and random boxes."""
+    nd = len(shape)
+    out = [((0,) * nd, tuple(shape)), ((0,) * nd, (1,) * nd),
+           (tuple(v - 1 for v in shape), tuple(shape)),
+           (tuple(block), tuple(min(2 * b, v) for b, v in zip(block, shape))),
+           (tuple(1 for _ in shape), tuple(min(b - 1, v) for b, v in zip(block, shape))),
+           (tuple(v // 2 for v in shape), tuple(shape)),
+           ((0,) * (nd - 1) + (shape[-1] // 3,), tuple(shape[:-1]) + (shape[-1] // 3 + 1,))]
+    for _ in range(n):
+        lo = [int(rng.integers(0, v)) for v in shape]
+        hi = [int(rng.integers(a + 1, v + 1)) for a, v in zip(lo, shape)]
+        out.append((tuple(lo), tuple(hi)))
+    return out
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("shape,block", [((40, 37, 35), (6, 6, 6)), ((70, 83), (16, 16)), ((5000,), (64,))])
+def test_regions_match_oracle(codec, dtype, shape, block):
+    """Region decompression on the specialised decoder (6x6x6, 16x16) and
+    the generic one (1D): every region equals the oracle's, and the slice of
+    full decompression."""
+    x = synth.grf_field(shape, seed=8, dtype=dtype)
+    rc, s, _ = ref.compress(x, block, 1e-3)
+    assert rc == 0
+    sd = torch.from_numpy(s).cuda()
+    rc, full, _ = codec.decompress(sd)
+    assert rc == 0
+    full = full.cpu().numpy()
+    u = np.uint32 if dtype == np.float32 else np.uint64
+    for lo, hi in _regions(shape, block, np.random.default_rng(3), 12):
+        print(f"case region shape={shape} dtype={np.dtype(dtype).name} lo={lo} hi={hi}", flush=True)
+        rc_r, part_r, _ = ref.decompress_region(s, lo, hi)
+        rc_g, part_g, _ = codec.decompress_region(sd, lo, hi)
+        assert rc_r == rc_g == 0, (rc_r, rc_g)
+        part_g = part_g.cpu().numpy()
+        assert np.array_equal(part_r.view(u), part_g.view(u))
+        assert np.array_equal(full[tuple(slice(a, b) for a, b in zip(lo, hi))].view(u), part_g.view(u))
+
+
+def test_region_invalid_bounds(codec):
+    x = synth.grf_field((20, 20, 20), seed=9)
+    rc, s, _ = codec.compress(torch.from_numpy(x).cuda(), (6, 6, 6), 1e-3)
+    assert rc == 0
+    for lo, hi in (((0, 0, 0), (21, 20, 20)), ((5, 5, 5), (5, 6, 6)), ((3, 3, 3), (2, 9, 9))):
+        rc, _, _ = codec.decompress_region(s, lo, hi)
+        assert rc == sdcsz.EINVAL, (lo, hi, rc)
+
+
 def _codebook(s):
     n_sym = int(np.frombuffer(s[76:80].tobytes(), "<u4")[0])
     return n_sym, s[192:192 + 4 * n_sym].view("<u4")
