@@ -903,7 +903,8 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   uint32_t *d_counts = (uint32_t *)(ws + B.counts);
   uint64_t *d_pairs = (uint64_t *)(ws + B.pairs);
   uint32_t *d_chunks = (uint32_t *)(ws + B.chunks);
-  launch(PH_NONE, false, false, k_hist_count, grid(t_hchunk), dim3(256), st, d_hchunk, d_chunks, d_counts);
+  launch(PH_NONE, false, false, k_hist_count, grid(t_hchunk), dim3(256), st, d_hchunk, d_chunks);
+  launch(PH_NONE, false, false, k_hist_scan, dim3(1), dim3(256), st, nj, d_chunks, d_counts);
   launch(PH_NONE, false, false, k_hist_pack, grid(t_hchunk), dim3(256), st, d_hchunk, (const uint32_t *)d_chunks,
          d_pairs);
   HIPCHK(hipGetLastError());
@@ -1084,6 +1085,11 @@ struct DecPlan {
   std::vector<uint32_t> bits;
   std::vector<uint64_t> pb;
 };
+
+// work-groups (of 64 threads) per job of the decoder's re-execution kernel:
+// its queue is almost always empty, and on a large batch thousands of
+// work-groups that only find it empty cost tens of microseconds
+constexpr uint32_t kRedoWgs = 8;
 
 uint64_t dec_batch_area(uint64_t njobs) {
   return a256(sizeof(Job) * njobs) + 32 * a256(4 * (2 * njobs + 1)) + a256(8ull * (C_N + 1) * njobs) +
@@ -1266,10 +1272,10 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
       J.L.shell_count = nbox;
       const uint32_t ln = ln_dec[fp[j].cls][J.dtype];
       t_fast[fp[j].cls][J.dtype].add(j, grid_for(nbox, ln));
-      t_redo[J.dtype].add(j, kMaxRedo / 64);
+      t_redo[J.dtype].add(j, kRedoWgs);
     } else if (fp[j].fast) {
       t_fast[fp[j].cls][J.dtype].add(j, fast_launch(J.g, &J.L, ln_dec[fp[j].cls][J.dtype]));
-      t_redo[J.dtype].add(j, kMaxRedo / 64);  // one thread per queue slot
+      t_redo[J.dtype].add(j, kRedoWgs);
     } else if (J.g.n_blocks) {
       t_gen[J.dtype].add(j, grid_for(J.g.n_blocks, 64));
     }

@@ -117,7 +117,8 @@ __global__ void k_scan1(JobTab t);
 __global__ void k_scan2(JobTab t);
 __global__ void k_scan3(JobTab t);
 template <typename T> __global__ void k_encode(JobTab t);
-__global__ void k_hist_count(JobTab t, uint32_t *chunk_cnt, uint32_t *counts);
+__global__ void k_hist_count(JobTab t, uint32_t *chunk_cnt);
+__global__ void k_hist_scan(uint32_t n, uint32_t *chunk_cnt, uint32_t *counts);
 __global__ void k_hist_pack(JobTab t, const uint32_t *chunk_off, uint64_t *dst);
 __global__ void k_put_codes(JobTab t);
 __global__ void k_header(JobTab t);

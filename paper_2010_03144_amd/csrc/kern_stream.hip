@@ -27,10 +27,12 @@ __global__ void __launch_bounds__(256) k_put_codes(JobTab t) {
 // Histogram of each job compacted to (symbol << 32 | count) for the used
 // symbols, in symbol order, all jobs one after another.  The 65536 symbols
 // of a job are cut into kHistChunks chunks: k_hist_count counts the used
-// symbols of every chunk (one work-group per chunk), and the call's last
-// work-group to finish (a ticket among the first job's counters) turns the
-// counts into offsets and per-job totals; k_hist_pack writes every chunk's
-// entries at its offset.
+// symbols of every chunk (one work-group per chunk), k_hist_scan (one
+// work-group) turns the counts into offsets and per-job totals, k_hist_pack
+// writes every chunk's entries at its offset.  (Letting the count kernel's
+// last work-group do the scan costs a device-scope fence per work-group,
+// which on a batch's 12,288 work-groups took far longer than the launch it
+// saves.)
 constexpr uint32_t kHistChunks = 64, kHistChunk = 65536 / kHistChunks;
 static_assert(kHistChunks == 64, "a job's chunk counts are one wave's lanes");
 
@@ -61,26 +63,22 @@ __device__ inline uint32_t wg_exclusive_u32(uint32_t v, uint32_t *total, uint32_
 }
 }  // namespace
 
-__global__ void __launch_bounds__(256) k_hist_count(JobTab t, uint32_t *chunk_cnt, uint32_t *counts) {
+__global__ void __launch_bounds__(256) k_hist_count(JobTab t, uint32_t *chunk_cnt) {
   const JobWg jw = job_of(t);
   const uint32_t *hist = jw.J->cw.hist + jw.b * kHistChunk;
   uint32_t c = 0;
   for (uint32_t s = threadIdx.x; s < kHistChunk; s += blockDim.x) c += hist[s] ? 1u : 0u;
   for (int off = 32; off > 0; off >>= 1) c += (uint32_t)__shfl_xor((int)c, off);
   __shared__ uint32_t wsum[4];
-  __shared__ uint32_t last;
   if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    chunk_cnt[jw.slot * kHistChunks + jw.b] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-    __threadfence();
-    last = atomicAdd(&t.jobs[0].cw.cnt[C_HIST_DONE], 1ull) + 1 == gridDim.x;
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  // exclusive scan of all chunk counts in place; a job's chunks are one wave
-  const uint32_t total = gridDim.x;
+  if (threadIdx.x == 0) chunk_cnt[jw.slot * kHistChunks + jw.b] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+// one work-group: exclusive scan of the n * kHistChunks chunk counts in
+// place, and each job's total into counts[] (a job's chunks are one wave)
+__global__ void __launch_bounds__(256) k_hist_scan(uint32_t n, uint32_t *chunk_cnt, uint32_t *counts) {
+  const uint32_t total = n * kHistChunks;
   uint32_t carry = 0;
   for (uint32_t base = 0; base < total; base += 256) {
     const uint32_t i = base + threadIdx.x;
@@ -215,9 +213,10 @@ __global__ void __launch_bounds__(256) k_header(JobTab tb) {
 // shortest codeword it starts with, symbol << 8 | length; for a prefix that
 // only longer codewords start with, the range of their lengths,
 // lmax << 16 | lmin << 8; 0 if none); sets *w.err on an invalid codebook.
-// One work-group of 256 threads.  Entries in ascending symbol order (as the
-// compressor writes them) are ranked per length with wave ballots; any
-// other order goes through a table of the lengths of all 65536 symbols.
+// One work-group of 256 threads.  Up to 4096 entries in ascending symbol
+// order (as the compressor writes them) are ranked per length with wave
+// ballots; more entries, or any other order, go through a table of the
+// lengths of all 65536 symbols.
 __global__ void __launch_bounds__(256) k_dectab(JobTab tb) {
   const Job &J = *job_of(tb).J;
   const uint32_t *cbk = (const uint32_t *)(J.src + kHeader);
@@ -231,6 +230,7 @@ __global__ void __launch_bounds__(256) k_dectab(JobTab tb) {
   __shared__ uint32_t first[kMaxLen + 2], cnt[kMaxLen + 2], start[kMaxLen + 2];
   __shared__ uint32_t smin, smax, bad, unordered, hmis;
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool small = n_sym <= 4096;
   // a header the caller supplied (the host sized everything from it) must be
   // the stream's own, word for word
   if (J.hdr_expect) {
@@ -253,42 +253,96 @@ __global__ void __launch_bounds__(256) k_dectab(JobTab tb) {
     bad = 0;
     unordered = 0;
   }
+  auto len_of = [&](uint32_t s) { return (lens4[s >> 2] >> (8 * (s & 3))) & 0xFFu; };
+  if (!small)
+    for (uint32_t i = tid; i < 65536 / 4; i += 256) lens4[i] = 0;
   __syncthreads();
-  for (uint32_t t = tid; t < n_sym; t += 256) {
-    const uint32_t e = cbk[t], s = e >> 8, l = e & 0xFFu;
-    if (s > 65535 || l == 0 || l > kMaxLen) {
-      atomicOr(&bad, 1u);
-      continue;
+  // one pass over the entries, kU at a time per thread (their loads in
+  // flight together): validity and order; few entries are counted per
+  // length here, many go into the table of lengths by symbol (a symbol
+  // listed twice is an error)
+  constexpr uint32_t kU = 8;
+  uint32_t elo = 0xFFFFFFFFu, ehi = 0;
+  for (uint32_t base = tid; base < n_sym; base += 256 * kU) {
+    uint32_t ev[kU], pv[kU];
+#pragma unroll
+    for (uint32_t u = 0; u < kU; u++) {
+      const uint32_t t = base + u * 256;
+      ev[u] = t < n_sym ? cbk[t] : 0u;
+      pv[u] = t > 0 && t < n_sym ? cbk[t - 1] : 0u;
     }
-    if (t > 0 && (cbk[t - 1] >> 8) >= s) atomicOr(&unordered, 1u);
-    atomicAdd(&cnt[l], 1u);
+#pragma unroll
+    for (uint32_t u = 0; u < kU; u++) {
+      const uint32_t t = base + u * 256;
+      if (t >= n_sym) continue;
+      const uint32_t s = ev[u] >> 8, l = ev[u] & 0xFFu;
+      if (s > 65535 || l == 0 || l > kMaxLen) {
+        atomicOr(&bad, 1u);
+        continue;
+      }
+      if (t > 0 && (pv[u] >> 8) >= s) atomicOr(&unordered, 1u);
+      if (small) {
+        atomicAdd(&cnt[l], 1u);
+      } else {
+        const uint32_t sh = 8 * (s & 3);
+        const uint32_t old = atomicOr(&lens4[s >> 2], l << sh);
+        if ((old >> sh) & 0xFFu) atomicOr(&bad, 1u);
+        elo = min(elo, s);
+        ehi = max(ehi, s);
+      }
+    }
+  }
+  if (!small) {
+    for (int off = 32; off > 0; off >>= 1) {
+      elo = min(elo, (uint32_t)__shfl_xor((int)elo, off));
+      ehi = max(ehi, (uint32_t)__shfl_xor((int)ehi, off));
+    }
+    if (lane == 0) {
+      atomicMin(&smin, elo);
+      atomicMax(&smax, ehi);
+    }
   }
   __syncthreads();
   if (bad) {
     if (tid == 0) *w.err = 1;
     return;
   }
-  const bool ordered = !unordered;
-  auto len_of = [&](uint32_t s) { return (lens4[s >> 2] >> (8 * (s & 3))) & 0xFFu; };
+  // entries in ascending symbol order are ranked with ballots, a chunk of
+  // 256 at a time; many entries (or any other order) go through the table of
+  // the lengths of all symbols, which ranks a thread's range of symbols at
+  // once (the ballot loop took 0.24 ms for 65,536 entries)
+  const bool ordered = !unordered && small;
   uint32_t a = 0, b = 0;  // unordered case: this thread's range of the symbol span
-  if (!ordered) {
-    // lengths by symbol (a symbol listed twice is an error), then counts
-    // per length over contiguous symbol ranges, one per thread
+  if (!ordered && small) {
+    // few entries out of order: their lengths by symbol (a symbol listed
+    // twice is an error)
     for (uint32_t i = tid; i < 65536 / 4; i += 256) lens4[i] = 0;
     __syncthreads();
+    uint32_t lo = 0xFFFFFFFFu, hi = 0;  // this thread's extremes, then one atomic per wave
     for (uint32_t t = tid; t < n_sym; t += 256) {
       const uint32_t e = cbk[t], s = e >> 8, l = e & 0xFFu;
       const uint32_t sh = 8 * (s & 3);
       const uint32_t old = atomicOr(&lens4[s >> 2], l << sh);
       if ((old >> sh) & 0xFFu) atomicOr(&bad, 1u);
-      atomicMin(&smin, s);
-      atomicMax(&smax, s);
+      lo = min(lo, s);
+      hi = max(hi, s);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      lo = min(lo, (uint32_t)__shfl_xor((int)lo, off));
+      hi = max(hi, (uint32_t)__shfl_xor((int)hi, off));
+    }
+    if (lane == 0) {
+      atomicMin(&smin, lo);
+      atomicMax(&smax, hi);
     }
     __syncthreads();
     if (bad) {
       if (tid == 0) *w.err = 1;
       return;
     }
+  }
+  if (!ordered) {
+    // counts per length over contiguous symbol ranges, one per thread
     const uint32_t span = smax >= smin ? smax - smin + 1 : 0;
     const uint32_t per = (span + 255) / 256;
     a = smin + tid * per;
@@ -320,6 +374,7 @@ __global__ void __launch_bounds__(256) k_dectab(JobTab tb) {
         wsum[tid][q] = acc;
         acc += c;
       }
+      if (!small && tid > 0) cnt[tid] = acc;  // symbols of length tid
     }
   }
   __syncthreads();
