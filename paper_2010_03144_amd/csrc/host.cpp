@@ -1304,7 +1304,7 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
   const std::vector<JobTab> &D = up.dev;
   auto grid = [](const Tab &t) { return dim3(t.total()); };
   launch(PH_NONE, false, false, k_zero_jobs, grid(t_zero), dim3(256), st, D[0]);
-  launch(PH_NONE, false, false, k_dectab, grid(t_one), dim3(256), st, D[1]);
+  launch(PH_NONE, false, false, k_dectab, grid(t_one), dim3(kDecTabThreads), st, D[1]);
   bool any_empty = false;
   for (uint32_t j = 0; j < nj; j++) any_empty |= jobs[j].g.n_blocks == 0;
   if (any_empty) launch(PH_SCAN_D, true, !t_s1.total(), k_scan2, grid(t_one), dim3(kScanThreads), st, D[1]);

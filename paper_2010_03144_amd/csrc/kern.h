@@ -18,6 +18,7 @@ struct ScanSrc {
 };
 
 constexpr uint32_t kScanThreads = 256;
+constexpr uint32_t kDecTabThreads = 1024, kDecTabWaves = kDecTabThreads / 64;  // decoder-table kernel
 // Blocks per thread of the scans: 2 (many small work-groups hide latency
 // best), more for fields of over 2^20 blocks so that a job has at most
 // kScanMaxChunks chunks (each offsets work-group adds up the totals of the

@@ -213,18 +213,20 @@ __global__ void __launch_bounds__(256) k_header(JobTab tb) {
 // shortest codeword it starts with, symbol << 8 | length; for a prefix that
 // only longer codewords start with, the range of their lengths,
 // lmax << 16 | lmin << 8; 0 if none); sets *w.err on an invalid codebook.
-// One work-group of 256 threads.  Up to 4096 entries in ascending symbol
-// order (as the compressor writes them) are ranked per length with wave
-// ballots; more entries, or any other order, go through a table of the
-// lengths of all 65536 symbols.
-__global__ void __launch_bounds__(256) k_dectab(JobTab tb) {
+// One work-group of kDecTabThreads threads (the serial parts of a thread's
+// work shrink with more threads, and four waves per SIMD hide the LDS
+// latency).  Up to 4096 entries in ascending symbol order (as the
+// compressor writes them) are ranked per length with wave ballots; more
+// entries, or any other order, go through a table of the lengths of all
+// 65536 symbols.
+__global__ void __launch_bounds__(kDecTabThreads) k_dectab(JobTab tb) {
   const Job &J = *job_of(tb).J;
   const uint32_t *cbk = (const uint32_t *)(J.src + kHeader);
   const uint32_t n_sym = J.h.n_sym;
   const DecWork &w = J.dw;
   __shared__ uint32_t lens4[65536 / 4];       // code length of each symbol, one byte each
-  __shared__ uint32_t part[kMaxLen + 1][256];  // per length: symbols before each thread's range
-  __shared__ uint32_t wsum[kMaxLen + 1][4];    // per length: symbols in each wave's part
+  __shared__ uint16_t part[kMaxLen + 1][kDecTabThreads];  // per length: symbols before each thread's range, in its wave
+  __shared__ uint32_t wsum[kMaxLen + 1][kDecTabWaves];    // per length: symbols in each wave's part
   __shared__ uint32_t run[kMaxLen + 1];        // per length: symbols placed so far
   __shared__ uint16_t short_sym[1u << kLutBits];  // symbols at positions < 2^kLutBits
   __shared__ uint32_t first[kMaxLen + 2], cnt[kMaxLen + 2], start[kMaxLen + 2];
@@ -255,7 +257,7 @@ __global__ void __launch_bounds__(256) k_dectab(JobTab tb) {
   }
   auto len_of = [&](uint32_t s) { return (lens4[s >> 2] >> (8 * (s & 3))) & 0xFFu; };
   if (!small)
-    for (uint32_t i = tid; i < 65536 / 4; i += 256) lens4[i] = 0;
+    for (uint32_t i = tid; i < 65536 / 4; i += kDecTabThreads) lens4[i] = 0;
   __syncthreads();
   // one pass over the entries, kU at a time per thread (their loads in
   // flight together): validity and order; few entries are counted per
@@ -263,17 +265,17 @@ __global__ void __launch_bounds__(256) k_dectab(JobTab tb) {
   // listed twice is an error)
   constexpr uint32_t kU = 8;
   uint32_t elo = 0xFFFFFFFFu, ehi = 0;
-  for (uint32_t base = tid; base < n_sym; base += 256 * kU) {
+  for (uint32_t base = tid; base < n_sym; base += kDecTabThreads * kU) {
     uint32_t ev[kU], pv[kU];
 #pragma unroll
     for (uint32_t u = 0; u < kU; u++) {
-      const uint32_t t = base + u * 256;
+      const uint32_t t = base + u * kDecTabThreads;
       ev[u] = t < n_sym ? cbk[t] : 0u;
       pv[u] = t > 0 && t < n_sym ? cbk[t - 1] : 0u;
     }
 #pragma unroll
     for (uint32_t u = 0; u < kU; u++) {
-      const uint32_t t = base + u * 256;
+      const uint32_t t = base + u * kDecTabThreads;
       if (t >= n_sym) continue;
       const uint32_t s = ev[u] >> 8, l = ev[u] & 0xFFu;
       if (s > 65535 || l == 0 || l > kMaxLen) {
@@ -308,7 +310,7 @@ __global__ void __launch_bounds__(256) k_dectab(JobTab tb) {
     return;
   }
   // entries in ascending symbol order are ranked with ballots, a chunk of
-  // 256 at a time; many entries (or any other order) go through the table of
+  // kDecTabThreads at a time; many entries (or any other order) go through the table of
   // the lengths of all symbols, which ranks a thread's range of symbols at
   // once (the ballot loop took 0.24 ms for 65,536 entries)
   const bool ordered = !unordered && small;
@@ -316,10 +318,10 @@ __global__ void __launch_bounds__(256) k_dectab(JobTab tb) {
   if (!ordered && small) {
     // few entries out of order: their lengths by symbol (a symbol listed
     // twice is an error)
-    for (uint32_t i = tid; i < 65536 / 4; i += 256) lens4[i] = 0;
+    for (uint32_t i = tid; i < 65536 / 4; i += kDecTabThreads) lens4[i] = 0;
     __syncthreads();
     uint32_t lo = 0xFFFFFFFFu, hi = 0;  // this thread's extremes, then one atomic per wave
-    for (uint32_t t = tid; t < n_sym; t += 256) {
+    for (uint32_t t = tid; t < n_sym; t += kDecTabThreads) {
       const uint32_t e = cbk[t], s = e >> 8, l = e & 0xFFu;
       const uint32_t sh = 8 * (s & 3);
       const uint32_t old = atomicOr(&lens4[s >> 2], l << sh);
@@ -344,7 +346,7 @@ __global__ void __launch_bounds__(256) k_dectab(JobTab tb) {
   if (!ordered) {
     // counts per length over contiguous symbol ranges, one per thread
     const uint32_t span = smax >= smin ? smax - smin + 1 : 0;
-    const uint32_t per = (span + 255) / 256;
+    const uint32_t per = (span + kDecTabThreads - 1) / kDecTabThreads;
     a = smin + tid * per;
     b = min(a + per, smin + span);
     uint32_t mine[kMaxLen + 1];
@@ -363,13 +365,13 @@ __global__ void __launch_bounds__(256) k_dectab(JobTab tb) {
         const uint32_t u = (uint32_t)__shfl_up((int)v, d);
         if (lane >= d) v += u;
       }
-      part[l][tid] = v - mine[l];
+      part[l][tid] = (uint16_t)(v - mine[l]);
       if (lane == 63) wsum[l][wave] = v;
     }
     __syncthreads();
     if (tid <= kMaxLen) {
       uint32_t acc = 0;
-      for (uint32_t q = 0; q < 4; q++) {
+      for (uint32_t q = 0; q < kDecTabWaves; q++) {
         const uint32_t c = tid ? wsum[tid][q] : 0u;
         wsum[tid][q] = acc;
         acc += c;
@@ -412,7 +414,7 @@ __global__ void __launch_bounds__(256) k_dectab(JobTab tb) {
   if (ordered) {
     // rank of each entry among the earlier entries of its length
     const uint64_t below = (1ull << lane) - 1;
-    for (uint32_t base = 0; base < n_sym; base += 256) {
+    for (uint32_t base = 0; base < n_sym; base += kDecTabThreads) {
       const uint32_t t = base + tid;
       const uint32_t e = t < n_sym ? cbk[t] : 0u, l = e & 0xFFu;
       uint32_t rank = 0;
@@ -428,7 +430,8 @@ __global__ void __launch_bounds__(256) k_dectab(JobTab tb) {
         place(start[l] + off + rank, e >> 8);
       }
       __syncthreads();
-      if (tid >= 1 && tid <= kMaxLen) run[tid] += wsum[tid][0] + wsum[tid][1] + wsum[tid][2] + wsum[tid][3];
+      if (tid >= 1 && tid <= kMaxLen)
+        for (uint32_t q = 0; q < kDecTabWaves; q++) run[tid] += wsum[tid][q];
       __syncthreads();
     }
   } else {
@@ -441,7 +444,7 @@ __global__ void __launch_bounds__(256) k_dectab(JobTab tb) {
   __syncthreads();
   // prefix table: for each kLutBits-bit prefix the first length whose top
   // bits fall among that length's codes (the rule of bit-by-bit decoding)
-  for (uint32_t v = tid; v < (1u << kLutBits); v += 256) {
+  for (uint32_t v = tid; v < (1u << kLutBits); v += kDecTabThreads) {
     uint32_t e = 0;
     for (uint32_t l = 1; l <= kLutBits; l++) {
       const uint32_t c = v >> (kLutBits - l);
