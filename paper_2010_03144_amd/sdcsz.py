@@ -189,11 +189,21 @@ class Codec:
         self._meta = {}
 
     def workspace(self, nbytes, tag):
+        """A device buffer of at least nbytes kept under `tag`.  It grows by
+        half at least, and a large one it replaces goes back to the device
+        (not to torch's cache, where blocks of outgrown sizes would pile up
+        until allocations fail and the allocator's retries stall every
+        stream)."""
         t = self._ws.get(tag)
         if t is None or t.numel() < nbytes:
+            old = 0
             if t is not None:
+                old = t.numel()
                 self._meta.pop(t.data_ptr(), None)  # its memory may be reused
-            t = self.torch.empty(max(int(nbytes), 256), dtype=self.torch.uint8, device=self.device)
+                self._ws[tag] = t = None
+                if old >= 1 << 30:
+                    self.torch.cuda.empty_cache()
+            t = self.torch.empty(max(int(nbytes), old + old // 2, 256), dtype=self.torch.uint8, device=self.device)
             self._ws[tag] = t
         return t
 

@@ -22,6 +22,7 @@ The execution backend is replaceable (`executor`), so the queueing and
 admission logic can run without a GPU.
 """
 import collections
+import math
 import threading
 import time
 
@@ -94,11 +95,38 @@ class GpuExecutor:
         import torch
         self.torch = torch
         self.device = torch.device(device)
+        # True when results are released as soon as they are measured: the
+        # outputs of a batch are then views into one buffer per worker and
+        # kind, reused by its next batches.  Fresh outputs of every size
+        # for every batch leave torch's caching allocator with hundreds of GB
+        # of blocks of the wrong sizes, and its out-of-memory retries (which
+        # free and reallocate everything) cut the throughput several-fold.
+        self.reuse_outputs = False
 
     def worker_context(self):
         torch = self.torch
         stream = torch.cuda.Stream(device=self.device)  # default priority
         return {"stream": stream, "codec": sdcsz.Codec(self.device)}
+
+    def _outputs(self, ctx, key, sizes):
+        """Byte views of the given sizes (256-byte aligned), fresh tensors
+        unless outputs are reused, else views into the worker's buffer for
+        `key` (grown by at least half when too small)."""
+        torch = self.torch
+        if not self.reuse_outputs:
+            return [torch.empty(n, dtype=torch.uint8, device=self.device) for n in sizes]
+        offs, total = [], 0
+        for n in sizes:
+            offs.append(total)
+            total += (int(n) + 255) // 256 * 256
+        buf = ctx.get(key)
+        if buf is None or buf.numel() < total:
+            old = 0 if buf is None else buf.numel()
+            ctx[key] = buf = None  # released, and returned to the device, before the larger one is taken
+            if old >= 1 << 30:
+                torch.cuda.empty_cache()
+            buf = ctx[key] = torch.empty(max(total, old + old // 2, 1), dtype=torch.uint8, device=self.device)
+        return [buf[o:o + int(n)] for o, n in zip(offs, sizes)]
 
     def run(self, ctx, batch, now):
         torch = self.torch
@@ -109,15 +137,20 @@ class GpuExecutor:
         with torch.cuda.stream(ctx["stream"]):
             for g in groups:  # the group with less data first
                 if g is comp:
-                    outs = [torch.empty(sdcsz.max_compressed_size(r.data.shape, r.data.dtype == torch.float32,
-                                                                  r.block), dtype=torch.uint8, device=self.device)
-                            for r in g]
+                    outs = self._outputs(ctx, "compress", [sdcsz.max_compressed_size(
+                        r.data.shape, r.data.dtype == torch.float32, r.block) for r in g])
                     rc, res = codec.compress_batch([r.data for r in g], [tuple(r.block) for r in g],
                                                    [r.eb for r in g], [r.eb_mode for r in g],
                                                    [r.abft for r in g], [r.predictor for r in g],
                                                    faults=[r.faults for r in g], outs=outs)
                 else:
-                    rc, res = codec.decompress_batch([r.data for r in g], faults=[r.faults for r in g],
+                    outs = None
+                    if self.reuse_outputs and all(r.geom is not None for r in g):
+                        dts = [torch.float32 if r.geom[1] else torch.float64 for r in g]
+                        nbs = [math.prod(r.geom[0]) * (4 if r.geom[1] else 8) for r in g]
+                        outs = [v.view(dt).view(tuple(r.geom[0]))
+                                for v, dt, r in zip(self._outputs(ctx, "decompress", nbs), dts, g)]
+                    rc, res = codec.decompress_batch([r.data for r in g], outs=outs, faults=[r.faults for r in g],
                                                      geoms=[r.geom for r in g], headers=[r.header for r in g])
                 t = now()
                 for i, r in enumerate(g):
@@ -135,6 +168,8 @@ class Server:
         self.max_batch = int(max_batch)
         self.max_batch_bytes = int(max_batch_bytes)
         self.executor = executor if executor is not None else GpuExecutor(device)
+        if hasattr(self.executor, "reuse_outputs"):
+            self.executor.reuse_outputs = not keep_results
         self.clock = clock
         self.keep_results = keep_results  # False: results are measured, then released
         self._q = collections.deque()

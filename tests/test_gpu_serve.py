@@ -100,3 +100,35 @@ def test_each_result_same_alone_and_in_the_mix(mix, workers, budget, max_batch):
         _same(r, _alone(codec, r))
     if max_batch > 1 and workers == 2:
         assert max(batches) > 1  # some requests were served together
+
+
+class _Capturing(serve.GpuExecutor):
+    """Keeps a copy of each result before the server releases it."""
+
+    def run(self, ctx, batch, now):
+        super().run(ctx, batch, now)
+        # on the worker's stream, finished before its next batch reuses the buffers
+        with torch.cuda.stream(ctx["stream"]):
+            for r in batch:
+                r.kept = r.result.clone() if r.result is not None else None
+        ctx["stream"].synchronize()
+
+
+def test_released_results_come_from_reused_buffers_and_match(mix):
+    """keep_results=False: a batch's outputs are views into per-worker
+    buffers reused by the next batches; each result, copied before release,
+    still equals the request run alone."""
+    codec, fields, streams = mix
+    for rep in range(2):  # the second round reuses the buffers the first grew
+        reqs = _requests(fields, streams)
+        ex = _Capturing("cuda:0")
+        print(f"case released results round={rep} requests={len(reqs)}", flush=True)
+        with serve.Server("cuda:0", workers=2, hbm_budget=200e9, max_batch=8, executor=ex,
+                          keep_results=False) as srv:
+            assert ex.reuse_outputs
+            serve.replay(srv, reqs, srv.clock())
+        torch.cuda.synchronize()
+        for r in reqs:
+            assert r.result is None and r.result_bytes > 0
+            r.result = r.kept
+            _same(r, _alone(codec, r))
