@@ -28,7 +28,10 @@ def log(*a):
 
 
 def algorithmic_bytes(phase, n, nb, vb, rep, abft):
-    """Bytes the method must move in one launch of a phase."""
+    """Bytes the method must move in one launch of a phase: n values of vb
+    bytes in nb blocks, with the outliers, regression blocks and payload
+    words of the report; 2-byte codes, 4-byte block-table words and 8-byte
+    per-block sums."""
     n_out, n_reg, pw = rep["n_outliers"], rep["n_regression"], rep["payload_words"]
     sums = 24 * nb if abft else 0  # sum_dc, sum_q, isum_q per block
     if phase == "range":
@@ -467,8 +470,9 @@ def main():
         args.no_extras = args.no_cpu_baseline = True
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build runs the compressor on a single MI355X "
-              "and has no multi-GPU path (see DESIGN.md for how it would shard).",
+        print("bench.py measures one GPU: the compressor runs on a single MI355X and has no "
+              "multi-GPU path (several GPUs would each compress their own slab of a field's blocks, "
+              "with no exchange on the hot path).",
               file=sys.stderr)
         sys.exit(2)
 
