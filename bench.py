@@ -261,6 +261,47 @@ def region_report(codec, torch, xd, block, eb=1e-3, edges=(32, 64, 128, 256, 512
             "full_ms": round(t_full * 1e3, 4), "full_device_ms": round(d_full, 4), "regions": rows}
 
 
+def fault_report(codec, torch, x, xd, block, eb=1e-4, k=6, reps=3):
+    """Bit flips at rest (Sec. 3.2, 5.3): k flips on each of INPUT, COEF and
+    CODE during compression and k on RECON during decompression, on distinct
+    blocks of the field; the counts per target, whether the stream and the
+    values equal those of the fault-free run, and the step time with and
+    without the plans."""
+    from paper_2010_03144_amd import sdcsz, synth
+    plan = synth.sparse_fault_plan(x.shape, block, np.float32, {"input": k, "coef": k, "code": k}, seed=3)
+    rplan = synth.sparse_fault_plan(x.shape, block, np.float32, {"recon": k}, seed=33)
+    sync = torch.cuda.synchronize
+
+    def step(faults):
+        rc, s, rep = codec.compress(xd, block, eb, faults=faults)
+        assert rc == 0, rc
+        s = s.clone()
+        rc, y, drep = codec.decompress(s, faults=rplan if faults is not None else None)
+        assert rc == 0, rc
+        return s, y, rep, drep
+
+    def timed(faults):
+        step(faults)
+        sync()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            step(faults)
+            sync()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    s0, y0, _, _ = step(None)
+    s1, y1, rep, drep = step(plan)
+    counts = {t: rep[t] for t in ("input", "coef", "code")}
+    counts["recon"] = drep["recon"]
+    return {"workload": f"{'x'.join(map(str, x.shape))} FP32 field, eb {eb:g} REL, ABFT on; {k} flips on each of "
+                        f"INPUT, COEF, CODE (compression) and RECON (decompression), distinct blocks (seeds 3, 33)",
+            "counts": counts, "stream_equals_fault_free": bool(torch.equal(s0, s1)),
+            "values_equal_fault_free": bool(torch.equal(y0.view(torch.int32), y1.view(torch.int32))),
+            "ms_per_step_with_faults": round(timed(plan) * 1e3, 4), "ms_per_step_without": round(timed(None) * 1e3, 4)}
+
+
 def prep_fault_report(codec, torch, x, xd, block, eb=1e-3, k=10, trials=5):
     """Compression-ratio impact of computation errors in the prediction
     preparation (regression coefficients and sampled estimates, Sec. 4.1),
@@ -596,6 +637,8 @@ def main():
         result["eb_sweep"] = extras
 
     if not args.no_extras:
+        log("bit flips at rest")
+        result["faults"] = fault_report(codec, torch, x, xd, block)
         result["prep_faults"] = prep_fault_report(codec, torch, x, xd, block)
         log("region decompression")
         result["region"] = region_report(codec, torch, xd, block)
