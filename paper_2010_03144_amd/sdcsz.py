@@ -9,7 +9,6 @@ missing.
 import ctypes as C
 import os
 
-import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsdcsz.so")
