@@ -72,6 +72,10 @@ def test_full_field_fault_injection_matches_oracle(codec, field):
         assert rep_g[t]["injected"] == rep_g[t]["corrected"] == 6, (t, rep_g[t])
     s_g_host = s_g.cpu().numpy()
     assert np.array_equal(s_r, s_g_host), first_difference(s_r, s_g_host)
+    # every flip corrected: the stream is the fault-free one
+    rc, s_clean, _ = codec.compress(xd, BLOCK, 1e-4)
+    assert rc == 0 and np.array_equal(s_clean.cpu().numpy(), s_g_host)
+    s_g = torch.from_numpy(s_g_host).cuda()
     # decompression: RECON flips on 6 distinct blocks, re-executed
     rplan = synth.fault_plan(SHAPE, BLOCK, np.float32, {"recon": 6}, seed=33)
     print("gpu decompress with recon faults", flush=True)
