@@ -316,30 +316,45 @@ DecLayout dec_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
 }
 
 // Block shapes with specialised kernels (one lane per block): class 0 is
-// 6x6x6 in 3D, class 1 is 16x16 in 2D.  Their lanes address the field with
-// 32-bit byte offsets from the wave's lowest block, so they take fields
-// below 2 GiB.  Returns -1 for the generic kernels.
+// 6x6x6 in 3D, class 1 is 16x16 in 2D; -1 means the generic kernels.
 constexpr int kClasses = 2;
+// The specialised kernels address a field below 2 GiB from a wave-uniform
+// base with 32-bit offsets; a wider field takes their "wide" instantiation
+// (a base per lane at the block's origin), which needs the offsets inside a
+// block to stay below 2^31 bytes.
+bool wide_field(const Geo &g, uint32_t vb) { return g.n_values * vb >= (1ull << 31); }
+
 int fast_class(const Geo &g, uint32_t vb) {
-  if (!g.n_blocks || g.n_values * vb >= (1ull << 31)) return -1;
+  if (!g.n_blocks) return -1;
+  const uint64_t in_block =
+      ((uint64_t)(g.b[0] - 1) * g.d[1] * g.d[2] + (uint64_t)(g.b[1] - 1) * g.d[2] + g.b[2]) * vb;
+  if (in_block >= (1ull << 31)) return -1;
   if (g.ndim == 3 && g.b[0] == 6 && g.b[1] == 6 && g.b[2] == 6) return 0;
   if (g.ndim == 2 && g.b[1] == 16 && g.b[2] == 16) return 1;
   return -1;
 }
 
 using JobKernel = void (*)(JobTab);
-// [class][dtype][abft]
-const JobKernel kCompFast[kClasses][2][2] = {
-    {{k_compress_fast<float, 3, 6, 6, 6, false>, k_compress_fast<float, 3, 6, 6, 6, true>},
-     {k_compress_fast<double, 3, 6, 6, 6, false>, k_compress_fast<double, 3, 6, 6, 6, true>}},
-    {{k_compress_fast<float, 2, 1, 16, 16, false>, k_compress_fast<float, 2, 1, 16, 16, true>},
-     {k_compress_fast<double, 2, 1, 16, 16, false>, k_compress_fast<double, 2, 1, 16, 16, true>}}};
+// [class][dtype][abft][wide]
+const JobKernel kCompFast[kClasses][2][2][2] = {
+    {{{k_compress_fast<float, 3, 6, 6, 6, false, false>, k_compress_fast<float, 3, 6, 6, 6, false, true>},
+      {k_compress_fast<float, 3, 6, 6, 6, true, false>, k_compress_fast<float, 3, 6, 6, 6, true, true>}},
+     {{k_compress_fast<double, 3, 6, 6, 6, false, false>, k_compress_fast<double, 3, 6, 6, 6, false, true>},
+      {k_compress_fast<double, 3, 6, 6, 6, true, false>, k_compress_fast<double, 3, 6, 6, 6, true, true>}}},
+    {{{k_compress_fast<float, 2, 1, 16, 16, false, false>, k_compress_fast<float, 2, 1, 16, 16, false, true>},
+      {k_compress_fast<float, 2, 1, 16, 16, true, false>, k_compress_fast<float, 2, 1, 16, 16, true, true>}},
+     {{k_compress_fast<double, 2, 1, 16, 16, false, false>, k_compress_fast<double, 2, 1, 16, 16, false, true>},
+      {k_compress_fast<double, 2, 1, 16, 16, true, false>, k_compress_fast<double, 2, 1, 16, 16, true, true>}}}};
 const JobKernel kCheckFast[kClasses] = {k_check_fast<3, 6, 6, 6>, k_check_fast<2, 1, 16, 16>};
 // [class][dtype]
 const JobKernel kEncFast[kClasses][2] = {{k_encode_fast<float, 3, 6, 6, 6>, k_encode_fast<double, 3, 6, 6, 6>},
                                          {k_encode_fast<float, 2, 1, 16, 16>, k_encode_fast<double, 2, 1, 16, 16>}};
-const JobKernel kDecFast[kClasses][2] = {{k_decode_fast<float, 3, 6, 6, 6>, k_decode_fast<double, 3, 6, 6, 6>},
-                                         {k_decode_fast<float, 2, 1, 16, 16>, k_decode_fast<double, 2, 1, 16, 16>}};
+// [class][dtype][wide]
+const JobKernel kDecFast[kClasses][2][2] = {
+    {{k_decode_fast<float, 3, 6, 6, 6, false>, k_decode_fast<float, 3, 6, 6, 6, true>},
+     {k_decode_fast<double, 3, 6, 6, 6, false>, k_decode_fast<double, 3, 6, 6, 6, true>}},
+    {{k_decode_fast<float, 2, 1, 16, 16, false>, k_decode_fast<float, 2, 1, 16, 16, true>},
+     {k_decode_fast<double, 2, 1, 16, 16, false>, k_decode_fast<double, 2, 1, 16, 16, true>}}};
 
 // Lanes per work-group (one block per lane) of the specialised kernels, by
 // stage, shape class and data type: the first entry whose max_blocks holds
@@ -803,8 +818,10 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   Tab t_zero, t_range[2], t_fast[kClasses][2][2], t_gen[2], t_redo[2], t_hist, t_hchunk;  // t_hist: one work-group per job
   uint64_t nb_fast[kClasses][2][2] = {}, nb_cls[kClasses] = {}, nb_enc[kClasses][2] = {};
   uint32_t hw_fast[kClasses][2][2] = {};  // widest histogram window of each launch
+  bool wide_fast[kClasses][2][2] = {};   // a launch with a field of 2 GiB or more takes the wide kernel
   for (uint32_t j = 0; j < nj; j++)
     if (fp[j].fast) {
+      wide_fast[fp[j].cls][jobs[j].dtype][jobs[j].abft ? 1 : 0] |= wide_field(fp[j].g, vbytes(jobs[j].dtype));
       uint32_t &hw = hw_fast[fp[j].cls][jobs[j].dtype][jobs[j].abft ? 1 : 0];
       hw = std::max(hw, jobs[j].hist_win);
       nb_fast[fp[j].cls][jobs[j].dtype][jobs[j].abft ? 1 : 0] += fp[j].g.n_blocks;
@@ -882,7 +899,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
           const Tab &t = t_fast[c][d][a];
           if (!t.total()) continue;
           const JobTab jt = d_fast[(c * 2 + d) * 2 + a];
-          const JobKernel k = kCompFast[c][d][a];
+          const JobKernel k = kCompFast[c][d][a][wide_fast[c][d][a] ? 1 : 0];
           const uint32_t ln = ln_fast[c][d][a], shm = 4 * hw_fast[c][d][a];
           pl.fs.push_back([&t, jt, k, ln, shm, st, &grid](bool x, bool y) {
             launch_shm(PH_PREDICT, x, y, k, grid(t), dim3(ln), shm, st, jt);
@@ -1250,8 +1267,12 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
   }
   Tab t_zero, t_one, t_s1, t_fast[kClasses][2], t_gen[2], t_redo[2];
   uint64_t nb_dec[kClasses][2] = {};
+  bool wide_dec[kClasses][2] = {};  // a launch with a field of 2 GiB or more takes the wide kernel
   for (uint32_t j = 0; j < nj; j++)
-    if (fp[j].fast) nb_dec[fp[j].cls][jobs[j].dtype] += jobs[j].g.n_blocks;
+    if (fp[j].fast) {
+      nb_dec[fp[j].cls][jobs[j].dtype] += jobs[j].g.n_blocks;
+      wide_dec[fp[j].cls][jobs[j].dtype] |= wide_field(jobs[j].g, vbytes(jobs[j].dtype));
+    }
   uint32_t ln_dec[kClasses][2];
   for (int c = 0; c < kClasses; c++)
     for (int d = 0; d < 2; d++) ln_dec[c][d] = tuned_lanes(TS_DECODE, c, d, nb_dec[c][d]);
@@ -1333,7 +1354,7 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
         const Tab &t = t_fast[c][d];
         if (!t.total()) continue;
         const JobTab jt = D[7 + 2 * c + d];
-        const JobKernel k = kDecFast[c][d];
+        const JobKernel k = kDecFast[c][d][wide_dec[c][d] ? 1 : 0];
         const uint32_t ln = ln_dec[c][d];
         pl.fs.push_back([&t, jt, k, ln, st, &grid](bool x, bool y) { launch(PH_DECODE, x, y, k, grid(t), dim3(ln), st, jt); });
       }

@@ -131,7 +131,7 @@ template <> struct Bound<double> {
 
 // One lane's block: full blocks (FULL) have compile-time extents, blocks of
 // the partial shell mask every point by their actual extents.
-template <typename T, int ND, int B0, int B1, int B2, bool FULL, bool ABFT>
+template <typename T, int ND, int B0, int B1, int B2, bool FULL, bool ABFT, bool WIDE>
 __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const Geo &g, const RegTab<T> &rt,
                                                const PlanDev &plan, const CompWork &w, uint32_t predictor,
                                                const Launch &L, uint32_t *hist, uint32_t hlo, uint32_t hw,
@@ -143,8 +143,8 @@ __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const G
   bool active = idx < nlanes;
   const uint64_t blk = map_block(g, L, FULL ? 0u : 1u, active ? idx : nlanes - 1);
   // wave-uniform base of the input (the wave's lowest block origin); lanes
-  // address it with 32-bit byte offsets (the host takes this kernel only for
-  // fields below 2 GiB, so every offset fits)
+  // address it with 32-bit byte offsets (fields below 2 GiB, so every offset
+  // fits; wider fields take the WIDE instantiation)
   const Box bx = box_of(g, blk);
   const uint64_t org = fidx(g, bx, 0, 0, 0);
   uint64_t omin = org;
@@ -156,8 +156,10 @@ __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const G
   }
   const uint64_t org0 = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(omin >> 32)) << 32) |
                         (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)omin);
-  const char *wbase = (const char *)(in + org0);
-  const uint32_t loff = (uint32_t)((org - org0) * sizeof(T));
+  // below 2 GiB: a wave-uniform base and 32-bit per-lane offsets; wider
+  // fields: a per-lane base at the block's origin (32-bit offsets inside it)
+  const char *wbase = WIDE ? (const char *)(in + org) : (const char *)(in + org0);
+  const uint32_t loff = WIDE ? 0u : (uint32_t)((org - org0) * sizeof(T));
   if (active && plan_hit(plan, blk)) active = false;  // done by k_compress_list
   if (active) {
     const EbDev eb = *w.eb;
@@ -460,7 +462,7 @@ __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const G
 // in the first pass and two ahead in the prediction pass, which keeps the
 // previous reconstructed row only, so a 16x16 block needs no more registers
 // than a 6x6x6 one.
-template <typename T, int B1, int B2, bool FULL, bool ABFT>
+template <typename T, int B1, int B2, bool FULL, bool ABFT, bool WIDE>
 __device__ __forceinline__ void compress_rows(const T *__restrict__ in, const Geo &g, const RegTab<T> &rt,
                                               const PlanDev &plan, const CompWork &w, uint32_t predictor,
                                               const Launch &L, uint32_t *hist, uint32_t hlo, uint32_t hw,
@@ -483,8 +485,10 @@ __device__ __forceinline__ void compress_rows(const T *__restrict__ in, const Ge
   }
   const uint64_t org0 = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(omin >> 32)) << 32) |
                         (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)omin);
-  const char *wbase = (const char *)(in + org0);
-  const uint32_t loff = (uint32_t)((org - org0) * sizeof(T));
+  // below 2 GiB: a wave-uniform base and 32-bit per-lane offsets; wider
+  // fields: a per-lane base at the block's origin (32-bit offsets inside it)
+  const char *wbase = WIDE ? (const char *)(in + org) : (const char *)(in + org0);
+  const uint32_t loff = WIDE ? 0u : (uint32_t)((org - org0) * sizeof(T));
   if (active && plan_hit(plan, blk)) active = false;  // done by k_compress_list
   if (!active) return;
   const EbDev eb = *w.eb;
@@ -725,7 +729,7 @@ __device__ __forceinline__ void compress_rows(const T *__restrict__ in, const Ge
 }
 
 // Work-groups [0, L.full_wgs) take full blocks, the rest the partial shell.
-template <typename T, int ND, int B0, int B1, int B2, bool ABFT>
+template <typename T, int ND, int B0, int B1, int B2, bool ABFT, bool WIDE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ND == 3 && sizeof(T) == 4 ? 3 : 1)))
 k_compress_fast(JobTab tab) {
   const JobWg jw = job_of(tab);
@@ -749,15 +753,18 @@ k_compress_fast(JobTab tab) {
   const uint64_t idx = (uint64_t)(full ? jw.b : jw.b - L.full_wgs) * blockDim.x + threadIdx.x;
   if constexpr (ND == 2) {
     static_assert(B0 == 1, "2D blocks have one plane");
-    if (full) compress_rows<T, B1, B2, true, ABFT>(in, g, rt, plan, w, predictor, L, hist, hlo, hw, hot, idx, L.full_count);
-    else compress_rows<T, B1, B2, false, ABFT>(in, g, rt, plan, w, predictor, L, hist, hlo, hw, hot, idx, L.shell_count);
+    if (full)
+      compress_rows<T, B1, B2, true, ABFT, WIDE>(in, g, rt, plan, w, predictor, L, hist, hlo, hw, hot, idx, L.full_count);
+    else
+      compress_rows<T, B1, B2, false, ABFT, WIDE>(in, g, rt, plan, w, predictor, L, hist, hlo, hw, hot, idx,
+                                                  L.shell_count);
   } else {
     if (full)
-      compress_lanes<T, ND, B0, B1, B2, true, ABFT>(in, g, rt, plan, w, predictor, L, hist, hlo, hw, hot, idx,
-                                                    L.full_count);
+      compress_lanes<T, ND, B0, B1, B2, true, ABFT, WIDE>(in, g, rt, plan, w, predictor, L, hist, hlo, hw, hot, idx,
+                                                          L.full_count);
     else
-      compress_lanes<T, ND, B0, B1, B2, false, ABFT>(in, g, rt, plan, w, predictor, L, hist, hlo, hw, hot, idx,
-                                                     L.shell_count);
+      compress_lanes<T, ND, B0, B1, B2, false, ABFT, WIDE>(in, g, rt, plan, w, predictor, L, hist, hlo, hw, hot,
+                                                           idx, L.shell_count);
   }
   // wave total of the zero-residual bin (lanes that ran the pass agree; the
   // others hold 0), then flush the window
@@ -806,11 +813,13 @@ template <typename T> __global__ void __launch_bounds__(64) k_redo(JobTab tab) {
   }
 }
 
-#define SDCSZ_INST_FAST(T, ND, B0, B1, B2, ABFT) \
-  template __global__ void k_compress_fast<T, ND, B0, B1, B2, ABFT>(JobTab);
-#define SDCSZ_INST_SHAPE(T, ND, B0, B1, B2) \
-  SDCSZ_INST_FAST(T, ND, B0, B1, B2, true)  \
-  SDCSZ_INST_FAST(T, ND, B0, B1, B2, false)
+#define SDCSZ_INST_FAST(T, ND, B0, B1, B2, ABFT, WIDE) \
+  template __global__ void k_compress_fast<T, ND, B0, B1, B2, ABFT, WIDE>(JobTab);
+#define SDCSZ_INST_SHAPE(T, ND, B0, B1, B2)         \
+  SDCSZ_INST_FAST(T, ND, B0, B1, B2, true, false)  \
+  SDCSZ_INST_FAST(T, ND, B0, B1, B2, false, false) \
+  SDCSZ_INST_FAST(T, ND, B0, B1, B2, true, true)   \
+  SDCSZ_INST_FAST(T, ND, B0, B1, B2, false, true)
 SDCSZ_INST_SHAPE(float, 3, 6, 6, 6)
 SDCSZ_INST_SHAPE(double, 3, 6, 6, 6)
 SDCSZ_INST_SHAPE(float, 2, 1, 16, 16)

@@ -168,7 +168,7 @@ __device__ inline uint32_t decode_sym(Window &br, const DecLds &t, const uint16_
 
 }  // namespace
 
-template <typename T, int ND, int B0, int B1, int B2, bool FULL, bool REG>
+template <typename T, int ND, int B0, int B1, int B2, bool FULL, bool REG, bool WIDE>
 __device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, const Header &h, const Geo &g,
                                              const DecWork &w, const PlanDev &plan, T *out, const Launch &L,
                                              const DecLds &tl, uint32_t *win, uint64_t idx, uint64_t nlanes,
@@ -188,8 +188,10 @@ __device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, cons
   }
   const uint64_t org0 = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(omin >> 32)) << 32) |
                         (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)omin);
-  char *wbase = (char *)(out + org0);
-  const uint32_t loff = (uint32_t)((org - org0) * sizeof(T));
+  // below 2 GiB: a wave-uniform base and 32-bit per-lane offsets; wider
+  // fields: a per-lane base at the block's origin (32-bit offsets inside it)
+  char *wbase = WIDE ? (char *)(out + org) : (char *)(out + org0);
+  const uint32_t loff = WIDE ? 0u : (uint32_t)((org - org0) * sizeof(T));
   if (active && plan_hit(plan, blk)) active = false;  // done by k_decode_list
   if (!active) return;
 
@@ -322,7 +324,7 @@ __device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, cons
 // previous reconstructed row in registers; the window is staged once per row
 // (B2 codewords of <= 24 bits plus the <= 127-bit skew fit in kWin words for
 // B2 <= 16).
-template <typename T, int B1, int B2, bool FULL, bool REG>
+template <typename T, int B1, int B2, bool FULL, bool REG, bool WIDE>
 __device__ __forceinline__ void decode_rows(const uint8_t *__restrict__ s, const Header &h, const Geo &g,
                                             const DecWork &w, const PlanDev &plan, T *out, const Launch &L,
                                             const DecLds &tl, uint32_t *win, uint64_t idx, uint64_t nlanes,
@@ -343,8 +345,10 @@ __device__ __forceinline__ void decode_rows(const uint8_t *__restrict__ s, const
   }
   const uint64_t org0 = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(omin >> 32)) << 32) |
                         (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)omin);
-  char *wbase = (char *)(out + org0);
-  const uint32_t loff = (uint32_t)((org - org0) * sizeof(T));
+  // below 2 GiB: a wave-uniform base and 32-bit per-lane offsets; wider
+  // fields: a per-lane base at the block's origin (32-bit offsets inside it)
+  char *wbase = WIDE ? (char *)(out + org) : (char *)(out + org0);
+  const uint32_t loff = WIDE ? 0u : (uint32_t)((org - org0) * sizeof(T));
   if (active && plan_hit(plan, blk)) active = false;  // done by k_decode_list
   if (!active) return;
 
@@ -448,7 +452,7 @@ __device__ __forceinline__ void decode_rows(const uint8_t *__restrict__ s, const
 }
 
 // Work-groups [0, L.full_wgs) take full blocks, the rest the partial shell.
-template <typename T, int ND, int B0, int B1, int B2>
+template <typename T, int ND, int B0, int B1, int B2, bool WIDE>
 __global__ void __launch_bounds__(kDecThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
 k_decode_fast(JobTab tab) {
   const JobWg jw = job_of(tab);
@@ -484,9 +488,9 @@ k_decode_fast(JobTab tab) {
     // the region, at region-relative offsets
     const uint64_t idx = (uint64_t)jw.b * blockDim.x + threadIdx.x;
     if constexpr (ND == 2)
-      decode_rows<T, B1, B2, false, true>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx, L.shell_count, reg, rb);
+      decode_rows<T, B1, B2, false, true, WIDE>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx, L.shell_count, reg, rb);
     else
-      decode_lanes<T, ND, B0, B1, B2, false, true>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx,
+      decode_lanes<T, ND, B0, B1, B2, false, true, WIDE>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx,
                                                    L.shell_count, reg, rb);
     return;
   }
@@ -495,21 +499,23 @@ k_decode_fast(JobTab tab) {
   if constexpr (ND == 2) {
     static_assert(B0 == 1, "2D blocks have one plane");
     if (full)
-      decode_rows<T, B1, B2, true, false>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx, L.full_count, reg, rb);
+      decode_rows<T, B1, B2, true, false, WIDE>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx, L.full_count, reg, rb);
     else
-      decode_rows<T, B1, B2, false, false>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx, L.shell_count, reg,
+      decode_rows<T, B1, B2, false, false, WIDE>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx, L.shell_count, reg,
                                            rb);
   } else {
     if (full)
-      decode_lanes<T, ND, B0, B1, B2, true, false>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx, L.full_count,
+      decode_lanes<T, ND, B0, B1, B2, true, false, WIDE>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx, L.full_count,
                                                    reg, rb);
     else
-      decode_lanes<T, ND, B0, B1, B2, false, false>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx,
+      decode_lanes<T, ND, B0, B1, B2, false, false, WIDE>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx,
                                                     L.shell_count, reg, rb);
   }
 }
 
-#define SDCSZ_INST_DEC(T, ND, B0, B1, B2) template __global__ void k_decode_fast<T, ND, B0, B1, B2>(JobTab);
+#define SDCSZ_INST_DEC(T, ND, B0, B1, B2)                                    \
+  template __global__ void k_decode_fast<T, ND, B0, B1, B2, false>(JobTab); \
+  template __global__ void k_decode_fast<T, ND, B0, B1, B2, true>(JobTab);
 SDCSZ_INST_DEC(float, 3, 6, 6, 6)
 SDCSZ_INST_DEC(double, 3, 6, 6, 6)
 SDCSZ_INST_DEC(float, 2, 1, 16, 16)

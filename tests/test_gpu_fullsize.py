@@ -86,3 +86,39 @@ def test_full_field_fault_injection_matches_oracle(codec, field):
     counts_equal(rep_dr, rep_dg)
     assert rep_dg["recon"]["detected"] == rep_dg["recon"]["corrected"] == 6
     assert np.array_equal(y_r.view(np.uint32), y_g.cpu().numpy().view(np.uint32))
+
+
+def test_field_above_2gib_matches_oracle(codec, field):
+    """A 2.18 GB FP32 field (1040 x 1024 x 512, mirrored copies of the 512^3
+    field): the specialised kernels' wide instantiation (a base per lane
+    instead of 32-bit offsets from the wave's lowest block) gives the
+    oracle's stream byte for byte and its values bit for bit, and a region
+    beyond the first 2 GiB equals the slice of full decompression."""
+    x, _ = field
+    x2 = np.concatenate([x, x[:, ::-1, :]], axis=1)
+    big = np.ascontiguousarray(np.concatenate([x2, x2[::-1], x2[:16]], axis=0))
+    del x2
+    assert big.nbytes > 2 ** 31
+    xd = torch.from_numpy(big).cuda()
+    print(f"case {big.shape} ({big.nbytes / 1e9:.2f} GB) eb=1e-3: gpu compress", flush=True)
+    rc_g, s_g, rep_g = codec.compress(xd, BLOCK, 1e-3)
+    assert rc_g == 0
+    s_host = s_g.cpu().numpy()
+    print("gpu decompress", flush=True)
+    rc, y_g, _ = codec.decompress(s_g)
+    assert rc == 0
+    lo, hi = (1000, 900, 300), (1040, 1024, 512)
+    rc, part, _ = codec.decompress_region(s_g, lo, hi)
+    assert rc == 0
+    assert torch.equal(part.view(torch.int32), y_g[1000:, 900:, 300:].contiguous().view(torch.int32))
+    y_g = y_g.cpu().numpy()
+    del xd
+    print("oracle compress", flush=True)
+    rc_r, s_r, rep_r = ref.compress(big, BLOCK, 1e-3)
+    assert rc_r == 0
+    assert np.array_equal(s_r, s_host), first_difference(s_r, s_host)
+    counts_equal(rep_r, rep_g)
+    print("oracle decompress", flush=True)
+    rc, y_r, _ = ref.decompress(s_r)
+    assert rc == 0
+    assert np.array_equal(y_r.view(np.uint32), y_g.view(np.uint32))
