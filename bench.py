@@ -51,10 +51,10 @@ def algorithmic_bytes(phase, n, nb, vb, rep, abft):
 
 
 # kernel behind each timed phase (one launch per call)
-PHASE_KERNEL = {"range": "k_range<float>", "predict_quantize": "k_compress_fast<float,3,6,6,6,true>",
+PHASE_KERNEL = {"range": "k_range<float>", "predict_quantize": "k_compress_fast<float,3,6,6,6,true,false>",
                 "code_check": "k_check_fast<3,6,6,6>", "encode": "k_encode_fast<float,3,6,6,6>",
-                "decode": "k_decode_fast<float,3,6,6,6>", "scan_compress": "k_scan1/2/3",
-                "scan_decompress": "k_scan1/2/3"}
+                "decode": "k_decode_fast<float,3,6,6,6,false>", "scan_compress": "k_scan1/3",
+                "scan_decompress": "k_scan1/3"}
 
 
 def source_digest():
