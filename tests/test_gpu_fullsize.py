@@ -122,3 +122,29 @@ def test_field_above_2gib_matches_oracle(codec, field):
     rc, y_r, _ = ref.decompress(s_r)
     assert rc == 0
     assert np.array_equal(y_r.view(np.uint32), y_g.view(np.uint32))
+
+
+def test_wide_2d_fp64_field_round_trip_and_oracle_regions(codec):
+    """A 2.15 GB FP64 2D field (16384 x 16400, 16x16 blocks, made on the
+    device): the wide 2D kernels keep every value within the bound, and the
+    oracle decoding regions of the GPU's stream (at both ends of the field)
+    gives the GPU's values bit for bit."""
+    g = torch.Generator(device="cuda:0").manual_seed(21)
+    xd = torch.randn((16384, 16400), generator=g, device="cuda:0", dtype=torch.float64).cumsum(1).cumsum(0)
+    xd = (xd / xd.std()).contiguous()
+    assert xd.numel() * 8 > 2 ** 31
+    print("case 16384x16400 FP64 eb=1e-4: gpu compress", flush=True)
+    rc, s, rep = codec.compress(xd, (16, 16), 1e-4)
+    assert rc == 0
+    s = s.clone()
+    rc, y, _ = codec.decompress(s)
+    assert rc == 0
+    assert float((xd - y).abs().max()) <= rep["eb_abs"]
+    s_host = s.cpu().numpy()
+    for lo, hi in (((0, 0), (40, 37)), ((16300, 16350), (16384, 16400)), ((9000, 7000), (9033, 7100))):
+        print(f"region {lo} {hi}", flush=True)
+        rc_r, part_r, _ = ref.decompress_region(s_host, lo, hi)
+        rc_g, part_g, _ = codec.decompress_region(s, lo, hi)
+        assert rc_r == rc_g == 0
+        assert np.array_equal(part_r.view(np.uint64), part_g.cpu().numpy().view(np.uint64))
+        assert torch.equal(part_g.view(torch.int64), y[lo[0]:hi[0], lo[1]:hi[1]].contiguous().view(torch.int64))
