@@ -299,7 +299,7 @@ __device__ __noinline__ void compress_block_generic(const T *__restrict__ in, co
 
   // ---- per-point prediction, quantization, reconstruction, double check
   const uint64_t base = blk * (uint64_t)g.bpts;
-  T *rec = (T *)w.recon + base;
+  const Slot<T> rec = slot_of<T>(w.recon, blk, g.bpts);
   T *outl = (T *)w.vals + base;
   auto rat = [&](int i, int j, int k) -> T {
     return (i < 0 || j < 0 || k < 0) ? (T)0 : rec[((uint32_t)i * b.n[1] + (uint32_t)j) * b.n[2] + (uint32_t)k];

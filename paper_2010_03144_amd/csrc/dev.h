@@ -140,6 +140,19 @@ __device__ inline uint32_t padded_index(const Geo &g, uint32_t i, uint32_t j, ui
   return (i * g.b[1] + j) * g.b[2] + k;
 }
 
+// A block's slot of the generic kernels' recon scratch, interleaved across
+// 64 consecutive blocks: point p of block blk sits at
+// ((blk / 64) * bpts + p) * 64 + blk % 64, so the lanes of a wave (one block
+// each) touch consecutive values.  The area holds bpts values for every
+// block of the block count rounded up to 64.
+template <typename T> struct Slot {
+  T *p;
+  __device__ T &operator[](uint32_t i) const { return p[(uint64_t)i * 64]; }
+};
+template <typename T> __device__ inline Slot<T> slot_of(void *base, uint64_t blk, uint32_t bpts) {
+  return Slot<T>{(T *)base + (blk >> 6) * (uint64_t)bpts * 64 + (blk & 63)};
+}
+
 __device__ inline void count(unsigned long long *cnt, int slot, unsigned long long v = 1) {
   atomicAdd(cnt + slot, v);
 }

@@ -256,7 +256,7 @@ CompLayout comp_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
   L.range = take(16ull * kRangeBlocks);
   L.codes = take(2ull * 256 * g.groups * ((nb + 63) / 64));
   L.vals = take(vb * slots);
-  L.recon = take(vb * slots);
+  L.recon = take(vb * ((nb + 63) / 64) * 64 * g.bpts);  // interleaved across 64 blocks
   L.meta = take(4 * nb);
   L.words = take(4 * nb);
   L.coef = take(4 * vb * nb);
@@ -285,7 +285,7 @@ struct DecLayout {
 
 DecLayout dec_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
   DecLayout L;
-  const uint64_t nb = g.n_blocks, vb = vbytes(dtype), slots = nb * g.bpts;
+  const uint64_t nb = g.n_blocks, vb = vbytes(dtype);
   const uint64_t chunks = (nb + scan_chunk(nb) - 1) / scan_chunk(nb) + 1;
   uint64_t at = 0;
   auto take = [&](uint64_t bytes) {
@@ -300,7 +300,7 @@ DecLayout dec_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
   L.zero_end = at;
   L.symbols = take(2 * 65536);
   L.tab = take(sizeof(DecTab));
-  L.recon = take(vb * slots);
+  L.recon = take(vb * ((nb + 63) / 64) * 64 * g.bpts);  // interleaved across 64 blocks
   L.off_pay = take(8 * (nb + 1));
   L.off_out = take(4 * (nb + 1));
   L.off_coef = take(4 * (nb + 1));

@@ -27,7 +27,7 @@ template __global__ void k_compress_generic<double>(JobTab);
 template <typename T>
 __device__ bool decode_block_generic(const uint8_t *__restrict__ s, const Header &h, const Geo &g,
                                      const Box &b, uint64_t blk, const DecWork &w,
-                                     const DecTab &tab, T q, T *rec) {
+                                     const DecTab &tab, T q, Slot<T> rec) {
   const uint32_t meta = *(const uint32_t *)(s + h.off_table + 8 * blk + 4);
   const bool is_reg = meta & 1u;
   const uint32_t nout = meta >> 1;
@@ -95,7 +95,7 @@ __device__ __noinline__ void decode_one(const uint8_t *__restrict__ s, const Hea
   }
   const DecTab tab = *w.tab;
   const T q = (T)(2.0 * h.eb_abs);
-  T *rec = (T *)w.recon + blk * (uint64_t)g.bpts;
+  const Slot<T> rec = slot_of<T>(w.recon, blk, g.bpts);
   auto store = [&]() {
     for (uint32_t i = 0, p = 0; i < b.n[0]; i++)
       for (uint32_t j = 0; j < b.n[1]; j++)
@@ -229,7 +229,7 @@ template <typename T> __global__ void __launch_bounds__(64) k_decode_redo(JobTab
       continue;
     }
     const Box b = box_of(g, blk);
-    T *rec = (T *)w.recon + blk * (uint64_t)g.bpts;
+    const Slot<T> rec = slot_of<T>(w.recon, blk, g.bpts);
     bool ok = decode_block_generic<T>(s, h, g, b, blk, w, tab, q, rec);
     if (ok && h.abft) {
       uint64_t sum = 0;
