@@ -1,12 +1,22 @@
 /*
  * sdcsz_ref.cpp -- CPU oracle (test infrastructure only; see sdcsz_ref.h).
  *
- * Plain, slow, single-threaded.  Built with -O1 -ffp-contract=off and no fast
- * math, so every floating-point operation below is one IEEE operation in the
- * field's own type T, rounded to nearest, in the order written.
+ * Plain, slow, single-threaded.  Built by build_oracle.py with -O2
+ * -ffp-contract=off and no fast math, so every floating-point operation below
+ * is one IEEE operation in the field's own type T, rounded to nearest, in the
+ * order written.
  *
  * Parity is against this file.  Where the paper leaves a detail open the
  * reading taken is stated next to the code and listed in the design notes.
+ *
+ * Parity unpinned: the predictor selection (Algorithm 1, second loop).  The
+ * paper fixes neither the sample set, nor the error measure, nor the rule on
+ * equal estimates, so three parts of it are readings that no closed form or
+ * paper value can check: the sample set of a partial block (the configured
+ * block's diagonals clipped to the partial extents), the tie rule (regression
+ * when E_reg <= E_lor) and the allowance of one bound per sample added to
+ * E_lor.  The selection only moves the compression ratio; the error bound
+ * holds under either predictor.
  */
 #include "sdcsz_ref.h"
 
@@ -613,7 +623,9 @@ int compress_impl(const T *in, const ref_params *p, const Geometry &g, uint8_t *
     }
   }
 
-  /* Loop 2: sample and estimate E_reg and E_lor, keep the smaller. */
+  /* Loop 2: sample and estimate E_reg and E_lor, keep the smaller.
+   * Selection: parity unpinned (sample set of partial blocks, the tie rule
+   * and the per-sample allowance are readings; see the file header). */
   std::vector<uint64_t> samples;
   for (uint64_t blk = 0; blk < g.n_blocks; blk++) {
     BlockBox bb = block_box(g, blk);
