@@ -169,6 +169,32 @@ int sdcsz_decompress(const void *d_stream, uint64_t stream_size, void *d_out, ui
                      void *d_ws, uint64_t ws_size, void *stream);
 
 /*
+ * Decompression that allocates nothing, for callers that cannot allocate
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): sdcsz_decompress with the same kernels and results,
+ * but its workspace is a fixed device array of SDCSZ_NOALLOC_SCRATCH_BYTES
+ * inside the library (one per GPU, held from the library's load until the
+ * process ends) and its host staging a static buffer; it calls no hipMalloc,
+ * hipFree, hipHostMalloc or other device or pinned-memory allocator.
+ *   d_stream, d_out, h_faults, h_rep: as for sdcsz_decompress (the caller
+ *             passes the stream and the output buffer)
+ * Streams of block shapes with a specialised decoder (6x6x6 in 3D, 16x16 in
+ * 2D) and no fault plan need about 16 bytes per block plus 8.5 MiB (FP64)
+ * of the array, so fields up to about 3.5 million blocks fit; other shapes
+ * and fault plans stage every block's values there and fit only when small.
+ * A stream whose workspace exceeds the array returns SDCSZ_ENOSPC and
+ * writes nothing.  More than 4096 blocks that fail their checksum cannot
+ * all be re-executed here: the others stay uncorrected, are counted
+ * uncorrectable and the call returns SDCSZ_ESDC.
+ * Calls are serialised inside the process (the array and the host staging
+ * are shared); each call clears the counters it needs with a kernel, and the
+ * array keeps the last call's contents.  Synchronises `stream`.
+ */
+#define SDCSZ_NOALLOC_SCRATCH_BYTES (64ull * 1024 * 1024)
+int sdcsz_decompress_noalloc(const void *d_stream, uint64_t stream_size, void *d_out, uint64_t out_cap,
+                             const sdcsz_fault *h_faults, uint32_t n_faults, sdcsz_report *h_rep, void *stream);
+
+/*
  * Stand-alone check of a decompressed buffer held by the caller (the checksum
  * half of Algorithm 2): each block's checksum is compared with sum_dc; a
  * mismatching block is decoded again from the stream and written over the

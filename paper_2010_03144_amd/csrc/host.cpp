@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -17,6 +18,12 @@
 #include "kern.h"
 
 using namespace sdcsz;
+
+// Device scratch of sdcsz_decompress_noalloc: one array per GPU, held from the
+// library's load until the process ends.  Host code must not pass this name
+// to a kernel or a copy: it only stands in for the device array, whose
+// address hipGetSymbolAddress gives per device.
+static __device__ __align__(256) uint8_t scratch[SDCSZ_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -283,9 +290,13 @@ struct DecLayout {
   uint64_t total;
 };
 
-DecLayout dec_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
+// small_recon: the recon scratch holds only the re-execution queue's slots
+// (a specialised decoder without fault-plan blocks stages nothing else there);
+// otherwise one slot per block, as the generic kernels need.
+DecLayout dec_layout(const Geo &g, uint32_t dtype, uint32_t nfaults, bool small_recon = false) {
   DecLayout L;
   const uint64_t nb = g.n_blocks, vb = vbytes(dtype);
+  const uint64_t slots = small_recon ? std::min<uint64_t>((nb + 63) / 64 * 64, kMaxRedo) : (nb + 63) / 64 * 64;
   const uint64_t chunks = (nb + scan_chunk(nb) - 1) / scan_chunk(nb) + 1;
   uint64_t at = 0;
   auto take = [&](uint64_t bytes) {
@@ -300,7 +311,7 @@ DecLayout dec_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
   L.zero_end = at;
   L.symbols = take(2 * 65536);
   L.tab = take(sizeof(DecTab));
-  L.recon = take(vb * ((nb + 63) / 64) * 64 * g.bpts);  // interleaved across 64 blocks
+  L.recon = take(vb * slots * g.bpts);  // interleaved across 64 slots
   L.off_pay = take(8 * (nb + 1));
   L.off_out = take(4 * (nb + 1));
   L.off_coef = take(4 * (nb + 1));
@@ -404,11 +415,13 @@ uint32_t scan_chunks(uint64_t nb) { return (uint32_t)((nb + scan_chunk(nb) - 1) 
 struct Staging {
   uint8_t *p = nullptr;
   size_t cap = 0;
+  bool fixed = false;  // a caller-provided buffer: never grown nor freed
   // only called between calls or after a synchronisation (no copy in flight);
   // starts at 8 MiB (a field's histogram pairs and codebook list need up to
   // about 1 MiB) and at least doubles, so regrowing (a device-wide wait in
   // hipHostFree plus a new pinned allocation) stays rare
   uint8_t *get(size_t n) {
+    if (fixed) return n <= cap ? p : nullptr;
     if (n > cap) {
       if (p) (void)hipHostFree(p);
       p = nullptr;
@@ -420,10 +433,14 @@ struct Staging {
     return p;
   }
   ~Staging() {
-    if (p) (void)hipHostFree(p);
+    if (p && !fixed) (void)hipHostFree(p);
   }
 };
 thread_local Staging t_stage;
+// the staging of decompression calls: the thread's own, unless a call that
+// must not allocate has put a fixed buffer in its place
+thread_local Staging *t_stage_over = nullptr;
+Staging &dec_stage() { return t_stage_over ? *t_stage_over : t_stage; }
 
 // ---------------------------------------------------------------------------
 // header
@@ -1087,6 +1104,7 @@ struct DecItem {  // one stream of a decompression call
   const sdcsz_fault *faults;
   uint32_t n_faults;
   const uint8_t *h_header;  // the caller's copy of the header, or null
+  bool small_recon;  // the no-allocation call: a recon scratch of queue slots only
   int rc;
   sdcsz_report rep;
   Header h;
@@ -1097,6 +1115,7 @@ struct DecPlan {
   DecLayout L;
   uint8_t *ws;
   bool fast;
+  bool small;  // recon scratch of queue slots only (see dec_layout)
   int cls;
   std::vector<sdcsz_fault> plan;
   std::vector<uint32_t> bits;
@@ -1125,7 +1144,7 @@ int read_headers(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     else idx.push_back(i);
   }
   if (idx.empty()) return SDCSZ_OK;
-  uint8_t *hs = t_stage.get(kHeader * idx.size() + (sizeof(Job) + 64) * idx.size() + 4096);
+  uint8_t *hs = dec_stage().get(kHeader * idx.size() + (sizeof(Job) + 64) * idx.size() + 4096);
   if (!hs) return SDCSZ_EHIP;
   if (idx.size() == 1) {
     HIPCHK(hipMemcpyAsync(hs, it[idx[0]].d_stream, kHeader, hipMemcpyDeviceToHost, st));
@@ -1191,12 +1210,13 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     DecPlan f;
     d.rc = check_plan(d.g, d.h.dtype, d.faults, d.n_faults, true, f.plan);
     if (d.rc) continue;
-    f.L = dec_layout(d.g, d.h.dtype, d.n_faults);
     // full and region decompression take the specialised decoder where the
     // block shape has one; verification the generic kernel
     f.cls = d.mode != 1 ? fast_class(d.g, vbytes(d.h.dtype)) : -1;
     f.fast = f.cls >= 0;
     f.pb = f.fast ? plan_block_list(f.plan) : std::vector<uint64_t>();
+    f.small = d.small_recon && f.fast && f.pb.empty();
+    f.L = dec_layout(d.g, d.h.dtype, d.n_faults, f.small);
     per += f.L.total;
     fp.push_back(std::move(f));
     item_of.push_back(i);
@@ -1316,7 +1336,7 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     any_hdr |= d.h_header != nullptr;
   }
   const uint64_t up_bytes = any_hdr ? hdr_at + kHeader * nj : up.bytes(nj);
-  uint8_t *hs = t_stage.get(std::max<uint64_t>(up_bytes, up.bytes(nj) + res_bytes) + 4096);
+  uint8_t *hs = dec_stage().get(std::max<uint64_t>(up_bytes, up.bytes(nj) + res_bytes) + 4096);
   if (!hs) return SDCSZ_EHIP;
   up.place(jobs, hs, ws);
   for (uint32_t j = 0; j < nj; j++)
@@ -1377,10 +1397,16 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
   std::vector<uint64_t> resv((const uint64_t *)(hs + up.bytes(nj)), (const uint64_t *)(hs + up.bytes(nj)) + (C_N + 1) * nj);
   // more blocks to re-execute than the queue holds: decode those fields again
   // in full with the generic kernel
+  // (a call with queue-sized recon scratch cannot: the blocks beyond the
+  // queue stay uncorrected and the item ends in ESDC)
   std::vector<uint32_t> again;
+  std::vector<uint64_t> overflow(nj, 0);
   for (uint32_t j = 0; j < nj; j++) {
     const uint32_t *tail = (const uint32_t *)(resv.data() + (uint64_t)j * (C_N + 1) + C_N);
-    if (!tail[1] && fp[j].fast && tail[0] > kMaxRedo) again.push_back(j);
+    if (!tail[1] && fp[j].fast && tail[0] > kMaxRedo) {
+      if (fp[j].small) overflow[j] = tail[0] - kMaxRedo;
+      else again.push_back(j);
+    }
   }
   if (!again.empty()) {
     Tab t_ag[2], t_res2;
@@ -1391,7 +1417,7 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     }
     Upload u2;
     u2.tabs = {&t_ag[0], &t_ag[1], &t_res2};
-    uint8_t *h2 = t_stage.get(u2.bytes(nj) + res_bytes + 4096);
+    uint8_t *h2 = dec_stage().get(u2.bytes(nj) + res_bytes + 4096);
     if (!h2) return SDCSZ_EHIP;
     u2.place(jobs, h2, ws);
     HIPCHK(hipMemcpyAsync(ws, h2, u2.bytes(nj), hipMemcpyHostToDevice, st));
@@ -1419,8 +1445,9 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     d.rep.n_regression = d.h.n_regression;
     d.rep.payload_words = d.h.payload_words;
     d.rep.stream_size = d.h.total;
+    d.rep.uncorrectable[SDCSZ_T_RECON] += overflow[j];
     if (tail[1]) d.rc = SDCSZ_EFORMAT;
-    else d.rc = cnt[C_UNC + SDCSZ_T_RECON] ? SDCSZ_ESDC : SDCSZ_OK;
+    else d.rc = (cnt[C_UNC + SDCSZ_T_RECON] || overflow[j]) ? SDCSZ_ESDC : SDCSZ_OK;
   }
   for (uint32_t i = 0; i < n; i++)
     if (it[i].rc && !first) first = it[i].rc;
@@ -1615,6 +1642,14 @@ uint64_t sdcsz_decompress_batch_workspace_size(const sdcsz_params *h_params, uin
 }
 
 namespace {
+// sdcsz_decompress_noalloc: the device address of `scratch` per device, and a
+// static pageable host buffer for the call's job tables, header and results
+// (a single stream needs a few KiB).  One call at a time in the process.
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+void *g_scratch_ptr[kNoAllocDevices] = {};
+alignas(256) uint8_t g_noalloc_host[1u << 20];
+
 int decode_one_call(DecItem &d, uint8_t *ws, uint64_t ws_size, hipStream_t st, sdcsz_report *h_rep) {
   int rc = read_headers(&d, 1, nullptr, 0, st);
   if (rc) return rc;
@@ -1637,6 +1672,37 @@ int sdcsz_decompress(const void *d_stream, uint64_t stream_size, void *d_out, ui
   d.faults = h_faults;
   d.n_faults = n_faults;
   return decode_one_call(d, (uint8_t *)d_ws, ws_size, (hipStream_t)stream, h_rep);
+}
+
+int sdcsz_decompress_noalloc(const void *d_stream, uint64_t stream_size, void *d_out, uint64_t out_cap,
+                             const sdcsz_fault *h_faults, uint32_t n_faults, sdcsz_report *h_rep, void *stream) {
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNoAllocDevices) return SDCSZ_EHIP;
+  if (!g_scratch_ptr[dev]) {
+    // the array's device address on this device (the host-side name is only
+    // a stand-in); looked up once per device, with that device current
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SDCSZ_EHIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  Staging fixed;
+  fixed.p = g_noalloc_host;
+  fixed.cap = sizeof(g_noalloc_host);
+  fixed.fixed = true;
+  t_stage_over = &fixed;
+  DecItem d{};
+  d.d_stream = (const uint8_t *)d_stream;
+  d.stream_size = stream_size;
+  d.d_out = (uint8_t *)d_out;
+  d.out_cap = out_cap;
+  d.faults = h_faults;
+  d.n_faults = n_faults;
+  d.small_recon = true;
+  const int rc = decode_one_call(d, (uint8_t *)g_scratch_ptr[dev], SDCSZ_NOALLOC_SCRATCH_BYTES,
+                                 (hipStream_t)stream, h_rep);
+  t_stage_over = nullptr;
+  return rc;
 }
 
 int sdcsz_verify(const void *d_stream, uint64_t stream_size, void *d_data, uint64_t data_size,

@@ -83,11 +83,13 @@ __device__ bool decode_block_generic(const uint8_t *__restrict__ s, const Header
 // One thread per block: decode, store, then the checksum half of Algorithm 2
 // with re-execution.  mode 0: full decompression into `out` (field layout);
 // mode 1: verify the caller's `out` (decode only on mismatch); mode 2: region
-// [lo, hi) into `out` laid out over the region.
+// [lo, hi) into `out` laid out over the region.  The block's values are
+// staged in slot `slot` of the recon scratch (the block id for kernels over
+// the whole field, the queue entry for re-execution).
 template <typename T>
 __device__ __noinline__ void decode_one(const uint8_t *__restrict__ s, const Header &h, const Geo &g,
                                         const DecWork &w, const PlanDev &plan, T *out, uint32_t mode,
-                                        const Region &reg, uint64_t blk) {
+                                        const Region &reg, uint64_t blk, uint64_t slot) {
   const Box b = box_of(g, blk);
   if (mode == 2) {
     for (int a = 0; a < 3; a++)
@@ -95,7 +97,7 @@ __device__ __noinline__ void decode_one(const uint8_t *__restrict__ s, const Hea
   }
   const DecTab tab = *w.tab;
   const T q = (T)(2.0 * h.eb_abs);
-  const Slot<T> rec = slot_of<T>(w.recon, blk, g.bpts);
+  const Slot<T> rec = slot_of<T>(w.recon, slot, g.bpts);
   auto store = [&]() {
     for (uint32_t i = 0, p = 0; i < b.n[0]; i++)
       for (uint32_t j = 0; j < b.n[1]; j++)
@@ -189,7 +191,7 @@ template <typename T> __global__ void __launch_bounds__(64) k_decode_generic(Job
   const Job &J = *jw.J;
   if (*J.dw.err) return;  // invalid codebook or block table: nothing is read
   const uint64_t blk = (uint64_t)jw.b * blockDim.x + threadIdx.x;
-  if (blk < J.g.n_blocks) decode_one<T>(J.src, J.h, J.g, J.dw, J.plan, (T *)J.dst, J.mode, J.reg, blk);
+  if (blk < J.g.n_blocks) decode_one<T>(J.src, J.h, J.g, J.dw, J.plan, (T *)J.dst, J.mode, J.reg, blk, blk);
 }
 
 // full decompression of listed blocks (the blocks a fault plan names)
@@ -200,7 +202,7 @@ k_decode_list(const uint8_t *__restrict__ s, Header h, Geo g, DecWork w, PlanDev
   if (*w.err) return;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   Region reg{};
-  if (t < n) decode_one<T>(s, h, g, w, plan, out, 0, reg, list[t]);
+  if (t < n) decode_one<T>(s, h, g, w, plan, out, 0, reg, list[t], list[t]);
 }
 
 // Blocks the specialised decoder queued: a checksum mismatch (already counted
@@ -225,11 +227,11 @@ template <typename T> __global__ void __launch_bounds__(64) k_decode_redo(JobTab
     const uint64_t blk = w.redo[e] & ((1ull << 56) - 1), why = w.redo[e] >> 56;
     if (why == 3) {
       const PlanDev none{nullptr, 0, nullptr};
-      decode_one<T>(s, h, g, w, none, out, mode, jw.J->reg, blk);
+      decode_one<T>(s, h, g, w, none, out, mode, jw.J->reg, blk, e);
       continue;
     }
     const Box b = box_of(g, blk);
-    const Slot<T> rec = slot_of<T>(w.recon, blk, g.bpts);
+    const Slot<T> rec = slot_of<T>(w.recon, e, g.bpts);  // one slot per queue entry
     bool ok = decode_block_generic<T>(s, h, g, b, blk, w, tab, q, rec);
     if (ok && h.abft) {
       uint64_t sum = 0;

@@ -21,9 +21,11 @@ FUNCTIONS = ["sdcsz_max_compressed_size", "sdcsz_compress_workspace_size", "sdcs
              "sdcsz_verify", "sdcsz_decompress_region", "sdcsz_compress_batch_workspace_size",
              "sdcsz_compress_batch", "sdcsz_decompress_batch_workspace_size",
              "sdcsz_decompress_batch", "sdcsz_strerror", "sdcsz_timing_enable",
-             "sdcsz_timing_read", "sdcsz_phase_name", "sdcsz_tune_set", "sdcsz_tune_get"]
+             "sdcsz_timing_read", "sdcsz_phase_name", "sdcsz_tune_set", "sdcsz_tune_get",
+             "sdcsz_decompress_noalloc"]
 N_PHASES = 11
 HEADER_BYTES = 192
+NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024  # device array of sdcsz_decompress_noalloc
 TUNE_MAX = 8
 TUNE_STAGES = ["predict", "check", "encode", "decode"]
 SHAPE_CLASSES = [((6, 6, 6), 3), ((16, 16), 2)]  # (block, ndim) of the specialised kernels
@@ -95,6 +97,8 @@ def lib():
         L.sdcsz_stream_info.argtypes = [vp, C.c_uint64, P(Params), P(C.c_uint64), P(C.c_double), vp]
         L.sdcsz_decompress.argtypes = [vp, C.c_uint64, vp, C.c_uint64, P(Fault), C.c_uint32, P(Report),
                                        vp, C.c_uint64, vp]
+        L.sdcsz_decompress_noalloc.argtypes = [vp, C.c_uint64, vp, C.c_uint64, P(Fault), C.c_uint32,
+                                               P(Report), vp]
         L.sdcsz_verify.argtypes = [vp, C.c_uint64, vp, C.c_uint64, P(Fault), C.c_uint32, P(Report), vp,
                                    C.c_uint64, vp]
         L.sdcsz_decompress_region.argtypes = [vp, C.c_uint64, P(C.c_uint64), P(C.c_uint64), vp,
@@ -325,6 +329,19 @@ class Codec:
                                 _stream_handle(self.device))
         del keep
         return rc, out, report_dict(rep)
+
+    def decompress_noalloc(self, stream, out, faults=None):
+        """sdcsz_decompress_noalloc: decompress `stream` into the caller's
+        `out` (a contiguous tensor of the field's size) with the library's
+        fixed device array as workspace; nothing is allocated.  Returns
+        (rc, report dict)."""
+        fptr, nf, keep = _faults(faults)
+        rep = Report()
+        rc = lib().sdcsz_decompress_noalloc(C.c_void_p(stream.data_ptr()), stream.numel(),
+                                            C.c_void_p(out.data_ptr()), out.numel() * out.element_size(),
+                                            fptr, nf, C.byref(rep), _stream_handle(self.device))
+        del keep
+        return rc, report_dict(rep)
 
     def verify(self, stream, data, faults=None):
         """Check `data` (repaired in place) against the stream's checksums."""
