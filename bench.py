@@ -261,7 +261,7 @@ def region_report(codec, torch, xd, block, eb=1e-3, edges=(32, 64, 128, 256, 512
             "full_ms": round(t_full * 1e3, 4), "full_device_ms": round(d_full, 4), "regions": rows}
 
 
-def fault_report(codec, torch, x, xd, block, eb=1e-4, k=6, reps=3):
+def fault_report(codec, torch, x, xd, block, eb=1e-4, k=6, reps=15):
     """Bit flips at rest (Sec. 3.2, 5.3): k flips on each of INPUT, COEF and
     CODE during compression and k on RECON during decompression, on distinct
     blocks of the field; the counts per target, whether the stream and the
@@ -280,26 +280,32 @@ def fault_report(codec, torch, x, xd, block, eb=1e-4, k=6, reps=3):
         assert rc == 0, rc
         return s, y, rep, drep
 
-    def timed(faults):
-        step(faults)
+    def timed():
+        # steps with and without the plans alternate, so drift hits both alike
+        step(plan)
+        step(None)
         sync()
-        ts = []
+        ts = {True: [], False: []}
         for _ in range(reps):
-            t0 = time.perf_counter()
-            step(faults)
-            sync()
-            ts.append(time.perf_counter() - t0)
-        return float(np.median(ts))
+            for f in (True, False):
+                t0 = time.perf_counter()
+                step(plan if f else None)
+                sync()
+                ts[f].append(time.perf_counter() - t0)
+        return float(np.median(ts[True])), float(np.median(ts[False]))
 
     s0, y0, _, _ = step(None)
     s1, y1, rep, drep = step(plan)
     counts = {t: rep[t] for t in ("input", "coef", "code")}
     counts["recon"] = drep["recon"]
+    t_with, t_without = timed()
     return {"workload": f"{'x'.join(map(str, x.shape))} FP32 field, eb {eb:g} REL, ABFT on; {k} flips on each of "
                         f"INPUT, COEF, CODE (compression) and RECON (decompression), distinct blocks (seeds 3, 33)",
-            "counts": counts, "stream_equals_fault_free": bool(torch.equal(s0, s1)),
+            "counts": counts, "generic_plan_blocks": rep["generic_plan_blocks"] + drep["generic_plan_blocks"],
+            "stream_equals_fault_free": bool(torch.equal(s0, s1)),
             "values_equal_fault_free": bool(torch.equal(y0.view(torch.int32), y1.view(torch.int32))),
-            "ms_per_step_with_faults": round(timed(plan) * 1e3, 4), "ms_per_step_without": round(timed(None) * 1e3, 4)}
+            "ms_per_step_with_faults": round(t_with * 1e3, 4), "ms_per_step_without": round(t_without * 1e3, 4),
+            "overhead": round(t_with / t_without - 1, 4)}
 
 
 def prep_fault_report(codec, torch, x, xd, block, eb=1e-3, k=10, trials=5):
@@ -495,7 +501,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed 192-field batch")
-    ap.add_argument("--only", choices=["batch", "serve", "region"], help="run one part alone and print its JSON")
+    ap.add_argument("--only", choices=["batch", "serve", "region", "faults"], help="run one part alone and print its JSON")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--tune-file", help="load launch shapes from this JSON file instead of autotuning")
     ap.add_argument("--save-tune", help="write the autotuned launch shapes to this JSON file")
@@ -535,13 +541,16 @@ def main():
         print(json.dumps(batch_bench(sdcsz.Codec("cuda:0"), torch, plain_loop=not args.batch_only_batched)),
               flush=True)
         return
-    if args.only in ("serve", "region"):
+    if args.only in ("serve", "region", "faults"):
         log("generating 512^3 FP32 field")
-        xd = torch.from_numpy(synth.grf_field((512, 512, 512), seed=2)).cuda()
+        x = synth.grf_field((512, 512, 512), seed=2)
+        xd = torch.from_numpy(x).cuda()
         if args.only == "serve":
             print(json.dumps(serve_bench(torch, xd, args.serve_seconds)), flush=True)
-        else:
+        elif args.only == "region":
             print(json.dumps(region_report(sdcsz.Codec("cuda:0"), torch, xd, (6, 6, 6))), flush=True)
+        else:
+            print(json.dumps(fault_report(sdcsz.Codec("cuda:0"), torch, x, xd, (6, 6, 6))), flush=True)
         return
 
     shape = (args.size,) * 3

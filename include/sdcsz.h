@@ -101,6 +101,12 @@ typedef struct {
   uint64_t payload_words; /* 32-bit words of Huffman payload                 */
   uint64_t stream_size;   /* bytes of the compressed stream                  */
   double eb_abs;          /* absolute bound actually enforced                */
+  uint64_t generic_plan_blocks; /* fault-plan blocks of a field with specialised
+                             kernels that the generic per-block routine ran
+                             instead (errors of the prediction preparation,
+                             several flips of a kind in one block, fields of
+                             2 GiB or more); the others run in the specialised
+                             kernels' fault-applying instantiation            */
 } sdcsz_report;
 
 /* Upper bound of the stream size for these parameters (0 if invalid). */
@@ -128,7 +134,9 @@ uint64_t sdcsz_compress_workspace_size(const sdcsz_params *p);
  *   h_rep     host, may be NULL; fault counters and stream statistics
  *   d_ws      device workspace of ws_size >= sdcsz_compress_workspace_size(p)
  * Returns SDCSZ_OK, SDCSZ_EINVAL, SDCSZ_ENOSPC, SDCSZ_ESDC (an uncorrectable
- * corruption, or a code without codeword when ABFT is off), SDCSZ_EHIP.
+ * corruption, a code without codeword when ABFT is off, or more than 4096
+ * blocks whose checks disagree in one call: the re-execution queue holds
+ * 4096), SDCSZ_EHIP.
  * Synchronises `stream` twice: for the code histogram (the Huffman code is
  * built on the host; a third time when more than 32768 symbols are used) and
  * at the end.  The calling thread keeps a pinned host staging buffer (8 MiB,

@@ -30,9 +30,10 @@ enum {
   C_UNC = 3 * SDCSZ_N_TARGETS,
   C_MISSING = 4 * SDCSZ_N_TARGETS,  // a code without codeword was met while encoding
   C_HIST_DONE,                       // histogram chunks finished (the call's first job only)
+  C_LIST,                            // fault-plan blocks run by the generic per-block routine
   C_N = 40
 };
-static_assert(C_HIST_DONE < C_N, "counter layout");
+static_assert(C_LIST < C_N, "counter layout");
 
 // Block grid of a field normalised to three axes (leading axes of extent 1).
 struct Geo {
@@ -63,11 +64,14 @@ template <typename T> struct RegTab {
   T c[8][3];     // (n_a - 1) / 2
 };
 
-// Fault plan on the device: entries sorted by block, one bit per block.
+// Fault plan on the device: entries sorted by block, one bit per block with
+// entries (bits), and one per block that the generic per-block routine takes
+// instead of the specialised kernels (gen; null when there is none).
 struct PlanDev {
   const sdcsz_fault *f;
   uint32_t n;
   const uint32_t *bits;
+  const uint32_t *gen;
 };
 
 // Per-call device areas of compression (inside the caller's workspace).
@@ -91,7 +95,7 @@ struct CompWork {
   void *range_part;    // 2 doubles + flag per range work-group
   EbDev *eb;
   uint32_t *redo_n;    // blocks queued for a re-run
-  uint64_t *redo;      // kMaxRedo block ids
+  uint64_t *redo;      // kMaxRedo entries of 3 words: block | reason << 56, first-pass S and Q
   struct Header *hdr;  // stream header, filled on the device
   uint64_t *res;       // R_* results of the call, read back once at its end
   uint8_t *hdr_bytes;  // the stream's kHeader header bytes, read back with the results

@@ -236,7 +236,7 @@ template <typename T> RegTab<T> reg_table(const Geo &g) {
 struct CompLayout {
   uint64_t cnt, res, redo_n, hist, enc, zero_end;
   uint64_t eb, range, codes, vals, recon, meta, words, coef, sum_dc, sum_q, isum_q;
-  uint64_t off_pay, off_out, off_coef, scan, tot, plan, bits, redo, plan_blocks, hdr, total;
+  uint64_t off_pay, off_out, off_coef, scan, tot, plan, bits, gen, redo, plan_blocks, hdr, total;
 };
 
 CompLayout comp_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
@@ -277,7 +277,8 @@ CompLayout comp_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
   L.tot = take(24);
   L.plan = take(sizeof(sdcsz_fault) * (uint64_t)std::max<uint32_t>(nfaults, 1));
   L.bits = take(4 * (nb / 32 + 1));
-  L.redo = take(8ull * kMaxRedo);
+  L.gen = take(4 * (nb / 32 + 1));
+  L.redo = take(24ull * kMaxRedo);  // block | reason, first-pass checksums
   L.plan_blocks = take(8ull * std::max<uint32_t>(nfaults, 1));
   L.hdr = take(sizeof(Header));
   L.total = at;
@@ -286,17 +287,18 @@ CompLayout comp_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
 
 struct DecLayout {
   uint64_t cnt, redo_n, err, zero_end;
-  uint64_t symbols, tab, recon, off_pay, off_out, off_coef, scan, tot, plan, bits, lut, redo, plan_blocks;
+  uint64_t symbols, tab, recon, off_pay, off_out, off_coef, scan, tot, plan, bits, gen, lut, redo, plan_blocks;
   uint64_t total;
 };
 
-// small_recon: the recon scratch holds only the re-execution queue's slots
-// (a specialised decoder without fault-plan blocks stages nothing else there);
-// otherwise one slot per block, as the generic kernels need.
+// small_recon: no recon scratch (the specialised decoder and its
+// re-execution keep blocks in registers; only the generic kernels stage
+// values there, one slot per block, including the fallback that decodes a
+// whole field again when more blocks fail than the re-execution queue holds).
 DecLayout dec_layout(const Geo &g, uint32_t dtype, uint32_t nfaults, bool small_recon = false) {
   DecLayout L;
   const uint64_t nb = g.n_blocks, vb = vbytes(dtype);
-  const uint64_t slots = small_recon ? std::min<uint64_t>((nb + 63) / 64 * 64, kMaxRedo) : (nb + 63) / 64 * 64;
+  const uint64_t slots = small_recon ? 0 : (nb + 63) / 64 * 64;
   const uint64_t chunks = (nb + scan_chunk(nb) - 1) / scan_chunk(nb) + 1;
   uint64_t at = 0;
   auto take = [&](uint64_t bytes) {
@@ -319,6 +321,7 @@ DecLayout dec_layout(const Geo &g, uint32_t dtype, uint32_t nfaults, bool small_
   L.tot = take(24);
   L.plan = take(sizeof(sdcsz_fault) * (uint64_t)std::max<uint32_t>(nfaults, 1));
   L.bits = take(4 * (nb / 32 + 1));
+  L.gen = take(4 * (nb / 32 + 1));
   L.lut = take(4ull << kLutBits);
   L.redo = take(8ull * kMaxRedo);
   L.plan_blocks = take(8ull * std::max<uint32_t>(nfaults, 1));
@@ -347,25 +350,42 @@ int fast_class(const Geo &g, uint32_t vb) {
 
 using JobKernel = void (*)(JobTab);
 // [class][dtype][abft][wide]
-const JobKernel kCompFast[kClasses][2][2][2] = {
-    {{{k_compress_fast<float, 3, 6, 6, 6, false, false>, k_compress_fast<float, 3, 6, 6, 6, false, true>},
-      {k_compress_fast<float, 3, 6, 6, 6, true, false>, k_compress_fast<float, 3, 6, 6, 6, true, true>}},
-     {{k_compress_fast<double, 3, 6, 6, 6, false, false>, k_compress_fast<double, 3, 6, 6, 6, false, true>},
-      {k_compress_fast<double, 3, 6, 6, 6, true, false>, k_compress_fast<double, 3, 6, 6, 6, true, true>}}},
-    {{{k_compress_fast<float, 2, 1, 16, 16, false, false>, k_compress_fast<float, 2, 1, 16, 16, false, true>},
-      {k_compress_fast<float, 2, 1, 16, 16, true, false>, k_compress_fast<float, 2, 1, 16, 16, true, true>}},
-     {{k_compress_fast<double, 2, 1, 16, 16, false, false>, k_compress_fast<double, 2, 1, 16, 16, false, true>},
-      {k_compress_fast<double, 2, 1, 16, 16, true, false>, k_compress_fast<double, 2, 1, 16, 16, true, true>}}}};
+// [class][dtype][abft][variant]: variant 0 narrow, 1 wide (fields of 2 GiB
+// or more), 2 narrow with fault plans applied
+#define SDCSZ_CF(T, ND, B0, B1, B2, A)                                                               \
+  {                                                                                                  \
+    k_compress_fast<T, ND, B0, B1, B2, A, false, false>, k_compress_fast<T, ND, B0, B1, B2, A, true, false>, \
+        k_compress_fast<T, ND, B0, B1, B2, A, false, true>                                          \
+  }
+const JobKernel kCompFast[kClasses][2][2][3] = {
+    {{SDCSZ_CF(float, 3, 6, 6, 6, false), SDCSZ_CF(float, 3, 6, 6, 6, true)},
+     {SDCSZ_CF(double, 3, 6, 6, 6, false), SDCSZ_CF(double, 3, 6, 6, 6, true)}},
+    {{SDCSZ_CF(float, 2, 1, 16, 16, false), SDCSZ_CF(float, 2, 1, 16, 16, true)},
+     {SDCSZ_CF(double, 2, 1, 16, 16, false), SDCSZ_CF(double, 2, 1, 16, 16, true)}}};
+#undef SDCSZ_CF
+// [class][dtype]
+const JobKernel kRedoFast[kClasses][2] = {{k_redo<float, 3, 6, 6, 6>, k_redo<double, 3, 6, 6, 6>},
+                                          {k_redo<float, 2, 1, 16, 16>, k_redo<double, 2, 1, 16, 16>}};
 const JobKernel kCheckFast[kClasses] = {k_check_fast<3, 6, 6, 6>, k_check_fast<2, 1, 16, 16>};
 // [class][dtype]
 const JobKernel kEncFast[kClasses][2] = {{k_encode_fast<float, 3, 6, 6, 6>, k_encode_fast<double, 3, 6, 6, 6>},
                                          {k_encode_fast<float, 2, 1, 16, 16>, k_encode_fast<double, 2, 1, 16, 16>}};
-// [class][dtype][wide]
-const JobKernel kDecFast[kClasses][2][2] = {
-    {{k_decode_fast<float, 3, 6, 6, 6, false>, k_decode_fast<float, 3, 6, 6, 6, true>},
-     {k_decode_fast<double, 3, 6, 6, 6, false>, k_decode_fast<double, 3, 6, 6, 6, true>}},
-    {{k_decode_fast<float, 2, 1, 16, 16, false>, k_decode_fast<float, 2, 1, 16, 16, true>},
-     {k_decode_fast<double, 2, 1, 16, 16, false>, k_decode_fast<double, 2, 1, 16, 16, true>}}};
+// [class][dtype][variant]: 0 narrow, 1 wide, 2 narrow with fault plans applied
+const JobKernel kDecFast[kClasses][2][3] = {
+    {{k_decode_fast<float, 3, 6, 6, 6, false, false>, k_decode_fast<float, 3, 6, 6, 6, true, false>,
+      k_decode_fast<float, 3, 6, 6, 6, false, true>},
+     {k_decode_fast<double, 3, 6, 6, 6, false, false>, k_decode_fast<double, 3, 6, 6, 6, true, false>,
+      k_decode_fast<double, 3, 6, 6, 6, false, true>}},
+    {{k_decode_fast<float, 2, 1, 16, 16, false, false>, k_decode_fast<float, 2, 1, 16, 16, true, false>,
+      k_decode_fast<float, 2, 1, 16, 16, false, true>},
+     {k_decode_fast<double, 2, 1, 16, 16, false, false>, k_decode_fast<double, 2, 1, 16, 16, true, false>,
+      k_decode_fast<double, 2, 1, 16, 16, false, true>}}};
+// [class][dtype][region]
+const JobKernel kDecRedo[kClasses][2][2] = {
+    {{k_decode_redo<float, 3, 6, 6, 6, false>, k_decode_redo<float, 3, 6, 6, 6, true>},
+     {k_decode_redo<double, 3, 6, 6, 6, false>, k_decode_redo<double, 3, 6, 6, 6, true>}},
+    {{k_decode_redo<float, 2, 1, 16, 16, false>, k_decode_redo<float, 2, 1, 16, 16, true>},
+     {k_decode_redo<double, 2, 1, 16, 16, false>, k_decode_redo<double, 2, 1, 16, 16, true>}}};
 
 // Lanes per work-group (one block per lane) of the specialised kernels, by
 // stage, shape class and data type: the first entry whose max_blocks holds
@@ -502,6 +522,35 @@ void fill_report(sdcsz_report *r, const uint64_t *cnt, uint64_t nb) {
     r->corrected[t] = cnt[C_COR + t];
     r->uncorrectable[t] = cnt[C_UNC + t];
   }
+  r->generic_plan_blocks = cnt[C_LIST];
+}
+
+// The blocks of a sorted plan that the generic per-block routine takes on a
+// field of the specialised kernels: all of them when the launch cannot apply
+// plans (faults_ok false: the wide instantiation), else those whose entries
+// the fault-applying instantiation does not model: errors of the prediction
+// preparation, more than one flip of a kind, or a flip of the duplicated
+// reconstruction together with an input or prediction flip (compression:
+// the specialised pass meets the reconstruction flip with the earlier error
+// still in its values, where the paper-order routine has corrected it, and
+// whether a reconstruction is computed at all depends on those values), more
+// than one RECON flip (decompression).
+std::vector<uint64_t> generic_blocks(const std::vector<sdcsz_fault> &plan, bool faults_ok, bool decomp) {
+  std::vector<uint64_t> out;
+  for (size_t i = 0; i < plan.size();) {
+    size_t j = i;
+    uint32_t cnt[SDCSZ_N_TARGETS] = {};
+    for (; j < plan.size() && plan[j].block == plan[i].block; j++) cnt[plan[j].target]++;
+    bool gen = !faults_ok;
+    if (decomp) gen = gen || cnt[SDCSZ_T_RECON] > 1;
+    else
+      gen = gen || cnt[SDCSZ_T_PREP_INPUT] || cnt[SDCSZ_T_PREP_COEF] || cnt[SDCSZ_T_PREP_SAMPLE] ||
+            cnt[SDCSZ_T_INPUT] > 1 || cnt[SDCSZ_T_COEF] > 1 || cnt[SDCSZ_T_DUP_PRED] > 1 ||
+            cnt[SDCSZ_T_DUP_RECON] > 1 || (cnt[SDCSZ_T_DUP_RECON] && (cnt[SDCSZ_T_INPUT] || cnt[SDCSZ_T_DUP_PRED]));
+    if (gen) out.push_back(plan[i].block);
+    i = j;
+  }
+  return out;
 }
 
 // distinct blocks of a sorted plan
@@ -649,11 +698,24 @@ struct CompPlan {  // host state of one field
   bool fast;
   int cls;  // shape class of the specialised kernels, -1 for generic
   std::vector<sdcsz_fault> plan;
-  std::vector<uint32_t> bits;
-  std::vector<uint64_t> pb;
+  std::vector<uint32_t> bits, gen;
+  std::vector<uint64_t> pb;  // blocks the generic routine takes (k_compress_list)
+  bool faults;               // the fault-applying instantiation serves the others
   bool any_code;
   uint64_t pair_off;  // first entry of the field's histogram / codebook list
 };
+
+// distinct blocks of a sorted plan
+size_t plan_blocks(const std::vector<sdcsz_fault> &plan) {
+  size_t n = 0;
+  for (size_t i = 0; i < plan.size(); i++) n += i == 0 || plan[i].block != plan[i - 1].block;
+  return n;
+}
+
+// work-groups per field of the re-execution kernels: the queue is almost
+// always empty, and on a large batch thousands of work-groups that only
+// find it empty cost tens of microseconds
+constexpr uint32_t kRedoWgs = 8;
 
 struct BatchArea {  // device batch area and its size
   uint64_t jobs, cb, counts, pairs, chunks, res, total;
@@ -722,7 +784,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     f.L = comp_layout(f.g, c.p->dtype, c.p->n_faults);
     f.cls = fast_class(f.g, vbytes(c.p->dtype));
     f.fast = f.cls >= 0;
-    f.pb = plan_block_list(f.plan);
+    f.faults = false;
     f.any_code = false;
     for (auto &e : f.plan) f.any_code |= e.target == SDCSZ_T_CODE;
     f.pair_off = cap;
@@ -737,6 +799,21 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   if (!ws || ws_size < B.total + per) {
     for (uint32_t j = 0; j < nj; j++) it[item_of[j]].rc = SDCSZ_ENOSPC;
     return SDCSZ_ENOSPC;
+  }
+  // a launch with a field of 2 GiB or more takes the wide kernel, which
+  // applies no fault plan: its fields' plan blocks take the generic routine
+  bool wide_fast[kClasses][2][2] = {};
+  for (uint32_t j = 0; j < nj; j++) {
+    const sdcsz_params *p = it[item_of[j]].p;
+    if (fp[j].fast) wide_fast[fp[j].cls][p->dtype][p->abft ? 1 : 0] |= wide_field(fp[j].g, vbytes(p->dtype));
+  }
+  for (uint32_t j = 0; j < nj; j++) {
+    CompPlan &f = fp[j];
+    const sdcsz_params *p = it[item_of[j]].p;
+    if (!f.fast || f.plan.empty()) continue;
+    const bool wide = wide_fast[f.cls][p->dtype][p->abft ? 1 : 0];
+    f.pb = generic_blocks(f.plan, !wide, false);
+    f.faults = f.pb.size() < plan_blocks(f.plan);
   }
   // ---- jobs
   std::vector<Job> jobs(nj);
@@ -779,6 +856,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     J.plan.n = (uint32_t)f.plan.size();
     J.plan.f = (const sdcsz_fault *)(w + f.L.plan);
     J.plan.bits = (const uint32_t *)(w + f.L.bits);
+    J.plan.gen = nullptr;
     Header &h = J.h;
     h.dtype = c.p->dtype;
     h.ndim = c.p->ndim;
@@ -826,19 +904,28 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
       HIPCHK(hipMemcpyAsync(w + f.L.plan, f.plan.data(), f.plan.size() * sizeof(sdcsz_fault), hipMemcpyHostToDevice,
                             st));
       HIPCHK(hipMemcpyAsync(w + f.L.bits, f.bits.data(), f.bits.size() * 4, hipMemcpyHostToDevice, st));
-      if (f.fast)
+      if (!f.pb.empty()) {
         HIPCHK(hipMemcpyAsync(w + f.L.plan_blocks, f.pb.data(), 8 * f.pb.size(), hipMemcpyHostToDevice, st));
+        if (!f.faults) {
+          J.plan.gen = J.plan.bits;  // every plan block
+        } else {
+          f.gen.assign(f.g.n_blocks / 32 + 1, 0);
+          for (uint64_t b : f.pb) f.gen[b >> 5] |= 1u << (b & 31);
+          HIPCHK(hipMemcpyAsync(w + f.L.gen, f.gen.data(), f.gen.size() * 4, hipMemcpyHostToDevice, st));
+          J.plan.gen = (const uint32_t *)(w + f.L.gen);
+        }
+      }
     }
   }
   // ---- stage A tables: zero, range + constants, prediction/quantization,
   // re-runs, histogram compaction
-  Tab t_zero, t_range[2], t_fast[kClasses][2][2], t_gen[2], t_redo[2], t_hist, t_hchunk;  // t_hist: one work-group per job
+  Tab t_zero, t_range[2], t_fast[kClasses][2][2], t_gen[2], t_redo[kClasses][2], t_hist, t_hchunk;  // t_hist: one work-group per job
   uint64_t nb_fast[kClasses][2][2] = {}, nb_cls[kClasses] = {}, nb_enc[kClasses][2] = {};
   uint32_t hw_fast[kClasses][2][2] = {};  // widest histogram window of each launch
-  bool wide_fast[kClasses][2][2] = {};   // a launch with a field of 2 GiB or more takes the wide kernel
+  bool faults_fast[kClasses][2][2] = {};  // a launch with a field whose plan it applies
   for (uint32_t j = 0; j < nj; j++)
     if (fp[j].fast) {
-      wide_fast[fp[j].cls][jobs[j].dtype][jobs[j].abft ? 1 : 0] |= wide_field(fp[j].g, vbytes(jobs[j].dtype));
+      faults_fast[fp[j].cls][jobs[j].dtype][jobs[j].abft ? 1 : 0] |= fp[j].faults;
       uint32_t &hw = hw_fast[fp[j].cls][jobs[j].dtype][jobs[j].abft ? 1 : 0];
       hw = std::max(hw, jobs[j].hist_win);
       nb_fast[fp[j].cls][jobs[j].dtype][jobs[j].abft ? 1 : 0] += fp[j].g.n_blocks;
@@ -861,7 +948,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     if (f.fast) {
       const int a = J.abft ? 1 : 0;
       t_fast[f.cls][J.dtype][a].add(j, fast_launch(f.g, &J.L, ln_fast[f.cls][J.dtype][a]));
-      t_redo[J.dtype].add(j, 1);
+      if (J.abft) t_redo[f.cls][J.dtype].add(j, kRedoWgs);
     } else if (f.g.n_blocks) {
       t_gen[J.dtype].add(j, grid_for(f.g.n_blocks, 64));
     }
@@ -869,10 +956,12 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     t_hchunk.add(j, kHistChunks);
   }
   Upload up;
-  up.tabs = {&t_zero, &t_range[0], &t_range[1], &t_gen[0], &t_gen[1], &t_redo[0], &t_redo[1], &t_hist, &t_hchunk};
+  up.tabs = {&t_zero, &t_range[0], &t_range[1], &t_gen[0], &t_gen[1], &t_hist, &t_hchunk};
   for (int c = 0; c < kClasses; c++)
     for (int d = 0; d < 2; d++)
       for (int a = 0; a < 2; a++) up.tabs.push_back(&t_fast[c][d][a]);
+  for (int c = 0; c < kClasses; c++)
+    for (int d = 0; d < 2; d++) up.tabs.push_back(&t_redo[c][d]);
   uint8_t *hs = t_stage.get(std::max<size_t>(up.bytes(nj), 4 * nj + 8 + 8 * t_pair_guess + 64));
   if (!hs) return SDCSZ_EHIP;
   up.place(jobs, hs, ws + B.jobs);
@@ -880,10 +969,10 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   const JobTab &d_zero = up.dev[0];
   const JobTab *d_range = &up.dev[1];
   const JobTab *d_gen = &up.dev[3];
-  const JobTab *d_redo = &up.dev[5];
-  const JobTab &d_hist = up.dev[7];
-  const JobTab &d_hchunk = up.dev[8];
-  const JobTab *d_fast = &up.dev[9];  // [class][dtype][abft] in that order
+  const JobTab &d_hist = up.dev[5];
+  const JobTab &d_hchunk = up.dev[6];
+  const JobTab *d_fast = &up.dev[7];                     // [class][dtype][abft] in that order
+  const JobTab *d_redo = &up.dev[7 + kClasses * 2 * 2];  // [class][dtype]
   auto grid = [](const Tab &t) { return dim3(t.total()); };
   launch(PH_NONE, false, false, k_zero_jobs, grid(t_zero), dim3(256), st, d_zero);
   {
@@ -895,7 +984,8 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     pl.run();
   }
   launch(PH_NONE, false, false, k_consts, grid(t_hist), dim3(kRangeThreads), st, d_hist);
-  // blocks a fault plan names run first through the paper-order routine
+  // plan blocks the specialised kernels leave run first through the
+  // paper-order routine
   for (uint32_t j = 0; j < nj; j++) {
     const CompPlan &f = fp[j];
     const Job &J = jobs[j];
@@ -916,7 +1006,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
           const Tab &t = t_fast[c][d][a];
           if (!t.total()) continue;
           const JobTab jt = d_fast[(c * 2 + d) * 2 + a];
-          const JobKernel k = kCompFast[c][d][a][wide_fast[c][d][a] ? 1 : 0];
+          const JobKernel k = kCompFast[c][d][a][wide_fast[c][d][a] ? 1 : faults_fast[c][d][a] ? 2 : 0];
           const uint32_t ln = ln_fast[c][d][a], shm = 4 * hw_fast[c][d][a];
           pl.fs.push_back([&t, jt, k, ln, shm, st, &grid](bool x, bool y) {
             launch_shm(PH_PREDICT, x, y, k, grid(t), dim3(ln), shm, st, jt);
@@ -928,8 +1018,10 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
       pl.fs.push_back([&](bool a, bool b) { launch(PH_PREDICT, a, b, k_compress_generic<double>, grid(t_gen[1]), dim3(64), st, d_gen[1]); });
     pl.run();
   }
-  if (t_redo[0].total()) launch(PH_NONE, false, false, k_redo<float>, grid(t_redo[0]), dim3(64), st, d_redo[0]);
-  if (t_redo[1].total()) launch(PH_NONE, false, false, k_redo<double>, grid(t_redo[1]), dim3(64), st, d_redo[1]);
+  for (int c = 0; c < kClasses; c++)
+    for (int d = 0; d < 2; d++)
+      if (t_redo[c][d].total())
+        launch(PH_NONE, false, false, kRedoFast[c][d], grid(t_redo[c][d]), dim3(64), st, d_redo[c * 2 + d]);
   for (uint32_t j = 0; j < nj; j++)
     if (fp[j].any_code)
       launch(PH_CODEFAULT, true, true, k_code_faults, dim3(1), dim3(64), st, jobs[j].plan, jobs[j].g,
@@ -1070,8 +1162,11 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     const uint64_t *cnt = hres + (uint64_t)j * kResWords, *res = cnt + C_N;
     fill_report(&c.rep, cnt, fp[j].g.n_blocks);
     std::memcpy(&c.rep.eb_abs, &res[R_EB], 8);
+    // more blocks queued for re-execution than the queue holds: the others
+    // keep the results of their disagreeing pass
+    const bool overflow = (uint32_t)res[R_N] > kMaxRedo;
     const bool unc = cnt[C_UNC + SDCSZ_T_INPUT] || cnt[C_UNC + SDCSZ_T_COEF] || cnt[C_UNC + SDCSZ_T_CODE] ||
-                     cnt[C_UNC + SDCSZ_T_PREP_INPUT] || cnt[C_MISSING];
+                     cnt[C_UNC + SDCSZ_T_PREP_INPUT] || cnt[C_MISSING] || overflow;
     if (unc) {
       c.out_size = 0;
       c.rc = SDCSZ_ESDC;
@@ -1104,7 +1199,7 @@ struct DecItem {  // one stream of a decompression call
   const sdcsz_fault *faults;
   uint32_t n_faults;
   const uint8_t *h_header;  // the caller's copy of the header, or null
-  bool small_recon;  // the no-allocation call: a recon scratch of queue slots only
+  bool small_recon;  // the no-allocation call: no recon scratch for the specialised decoder
   int rc;
   sdcsz_report rep;
   Header h;
@@ -1115,17 +1210,13 @@ struct DecPlan {
   DecLayout L;
   uint8_t *ws;
   bool fast;
-  bool small;  // recon scratch of queue slots only (see dec_layout)
+  bool small;  // no recon scratch (see dec_layout)
+  bool faults;  // the fault-applying instantiation serves the plan blocks not in pb
   int cls;
   std::vector<sdcsz_fault> plan;
-  std::vector<uint32_t> bits;
-  std::vector<uint64_t> pb;
+  std::vector<uint32_t> bits, gen;
+  std::vector<uint64_t> pb;  // blocks the generic routine takes (k_decode_list)
 };
-
-// work-groups (of 64 threads) per job of the decoder's re-execution kernel:
-// its queue is almost always empty, and on a large batch thousands of
-// work-groups that only find it empty cost tens of microseconds
-constexpr uint32_t kRedoWgs = 8;
 
 uint64_t dec_batch_area(uint64_t njobs) {
   return a256(sizeof(Job) * njobs) + 32 * a256(4 * (2 * njobs + 1)) + a256(8ull * (C_N + 1) * njobs) +
@@ -1214,15 +1305,30 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     // block shape has one; verification the generic kernel
     f.cls = d.mode != 1 ? fast_class(d.g, vbytes(d.h.dtype)) : -1;
     f.fast = f.cls >= 0;
-    f.pb = f.fast ? plan_block_list(f.plan) : std::vector<uint64_t>();
-    f.small = d.small_recon && f.fast && f.pb.empty();
-    f.L = dec_layout(d.g, d.h.dtype, d.n_faults, f.small);
-    per += f.L.total;
+    f.faults = false;
     fp.push_back(std::move(f));
     item_of.push_back(i);
   }
   const uint32_t nj = (uint32_t)fp.size();
   if (nj == 0) return SDCSZ_OK;
+  // a launch with a field of 2 GiB or more takes the wide kernel, which
+  // applies no fault plan: its fields' plan blocks take the generic routine
+  bool wide_dec[kClasses][2] = {};
+  for (uint32_t j = 0; j < nj; j++) {
+    const DecItem &d = it[item_of[j]];
+    if (fp[j].fast) wide_dec[fp[j].cls][d.h.dtype] |= wide_field(d.g, vbytes(d.h.dtype));
+  }
+  for (uint32_t j = 0; j < nj; j++) {
+    DecPlan &f = fp[j];
+    const DecItem &d = it[item_of[j]];
+    if (f.fast && !f.plan.empty()) {
+      f.pb = generic_blocks(f.plan, !wide_dec[f.cls][d.h.dtype], true);
+      f.faults = f.pb.size() < plan_blocks(f.plan);
+    }
+    f.small = d.small_recon && f.fast && f.pb.empty();
+    f.L = dec_layout(d.g, d.h.dtype, d.n_faults, f.small);
+    per += f.L.total;
+  }
   const uint64_t area = dec_batch_area(nj);
   if (!ws || ws_size < area + per) {
     for (uint32_t j = 0; j < nj; j++) it[item_of[j]].rc = SDCSZ_ENOSPC;
@@ -1257,6 +1363,7 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     J.plan.n = (uint32_t)f.plan.size();
     J.plan.f = (const sdcsz_fault *)(w + f.L.plan);
     J.plan.bits = (const uint32_t *)(w + f.L.bits);
+    J.plan.gen = nullptr;
     J.reg = d.reg;
     J.mode = d.mode;
     const uint32_t *table = (const uint32_t *)(d.d_stream + d.h.off_table);
@@ -1281,17 +1388,26 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
       HIPCHK(hipMemcpyAsync(w + f.L.plan, f.plan.data(), f.plan.size() * sizeof(sdcsz_fault), hipMemcpyHostToDevice,
                             st));
       HIPCHK(hipMemcpyAsync(w + f.L.bits, f.bits.data(), f.bits.size() * 4, hipMemcpyHostToDevice, st));
-      if (!f.pb.empty())
+      if (!f.pb.empty()) {
         HIPCHK(hipMemcpyAsync(w + f.L.plan_blocks, f.pb.data(), 8 * f.pb.size(), hipMemcpyHostToDevice, st));
+        if (!f.faults) {
+          J.plan.gen = J.plan.bits;  // every plan block
+        } else {
+          f.gen.assign(d.g.n_blocks / 32 + 1, 0);
+          for (uint64_t b : f.pb) f.gen[b >> 5] |= 1u << (b & 31);
+          HIPCHK(hipMemcpyAsync(w + f.L.gen, f.gen.data(), f.gen.size() * 4, hipMemcpyHostToDevice, st));
+          J.plan.gen = (const uint32_t *)(w + f.L.gen);
+        }
+      }
     }
   }
-  Tab t_zero, t_one, t_s1, t_fast[kClasses][2], t_gen[2], t_redo[2];
+  Tab t_zero, t_one, t_s1, t_fast[kClasses][2], t_gen[2], t_redo[kClasses][2][2];
   uint64_t nb_dec[kClasses][2] = {};
-  bool wide_dec[kClasses][2] = {};  // a launch with a field of 2 GiB or more takes the wide kernel
+  bool faults_dec[kClasses][2] = {};  // a launch with a field whose plan it applies
   for (uint32_t j = 0; j < nj; j++)
     if (fp[j].fast) {
       nb_dec[fp[j].cls][jobs[j].dtype] += jobs[j].g.n_blocks;
-      wide_dec[fp[j].cls][jobs[j].dtype] |= wide_field(jobs[j].g, vbytes(jobs[j].dtype));
+      faults_dec[fp[j].cls][jobs[j].dtype] |= fp[j].faults;
     }
   uint32_t ln_dec[kClasses][2];
   for (int c = 0; c < kClasses; c++)
@@ -1313,18 +1429,21 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
       J.L.shell_count = nbox;
       const uint32_t ln = ln_dec[fp[j].cls][J.dtype];
       t_fast[fp[j].cls][J.dtype].add(j, grid_for(nbox, ln));
-      t_redo[J.dtype].add(j, kRedoWgs);
+      t_redo[fp[j].cls][J.dtype][1].add(j, kRedoWgs);
     } else if (fp[j].fast) {
       t_fast[fp[j].cls][J.dtype].add(j, fast_launch(J.g, &J.L, ln_dec[fp[j].cls][J.dtype]));
-      t_redo[J.dtype].add(j, kRedoWgs);
+      t_redo[fp[j].cls][J.dtype][0].add(j, kRedoWgs);
     } else if (J.g.n_blocks) {
       t_gen[J.dtype].add(j, grid_for(J.g.n_blocks, 64));
     }
   }
   Upload up;
-  up.tabs = {&t_zero, &t_one, &t_s1, &t_gen[0], &t_gen[1], &t_redo[0], &t_redo[1]};
+  up.tabs = {&t_zero, &t_one, &t_s1, &t_gen[0], &t_gen[1]};
   for (int c = 0; c < kClasses; c++)
     for (int d = 0; d < 2; d++) up.tabs.push_back(&t_fast[c][d]);
+  for (int c = 0; c < kClasses; c++)
+    for (int d = 0; d < 2; d++)
+      for (int r = 0; r < 2; r++) up.tabs.push_back(&t_redo[c][d][r]);
   const size_t res_bytes = 8ull * (C_N + 1) * nj;
   // caller-given headers go to the end of the batch area (uploaded with the
   // jobs) for k_dectab to check against the streams
@@ -1354,7 +1473,8 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     launch(PH_SCAN_D, false, true, k_scan3, grid(t_s1), dim3(kScanThreads), st, D[2]);
   }
   launch(PH_NONE, false, false, k_dec_check, grid(t_one), dim3(64), st, D[1]);
-  // blocks a fault plan names (full decompression) run through the generic routine first
+  // plan blocks the specialised decoder leaves (full decompression) run
+  // through the generic routine first
   for (uint32_t j = 0; j < nj; j++) {
     const DecPlan &f = fp[j];
     const Job &J = jobs[j];
@@ -1373,8 +1493,8 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
       for (int d = 0; d < 2; d++) {
         const Tab &t = t_fast[c][d];
         if (!t.total()) continue;
-        const JobTab jt = D[7 + 2 * c + d];
-        const JobKernel k = kDecFast[c][d][wide_dec[c][d] ? 1 : 0];
+        const JobTab jt = D[5 + 2 * c + d];
+        const JobKernel k = kDecFast[c][d][wide_dec[c][d] ? 1 : faults_dec[c][d] ? 2 : 0];
         const uint32_t ln = ln_dec[c][d];
         pl.fs.push_back([&t, jt, k, ln, st, &grid](bool x, bool y) { launch(PH_DECODE, x, y, k, grid(t), dim3(ln), st, jt); });
       }
@@ -1384,8 +1504,12 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
       pl.fs.push_back([&](bool a, bool b) { launch(PH_DECODE, a, b, k_decode_generic<double>, grid(t_gen[1]), dim3(64), st, D[4]); });
     pl.run();
   }
-  if (t_redo[0].total()) launch(PH_NONE, false, false, k_decode_redo<float>, grid(t_redo[0]), dim3(64), st, D[5]);
-  if (t_redo[1].total()) launch(PH_NONE, false, false, k_decode_redo<double>, grid(t_redo[1]), dim3(64), st, D[6]);
+  for (int c = 0; c < kClasses; c++)
+    for (int d = 0; d < 2; d++)
+      for (int r = 0; r < 2; r++)
+        if (t_redo[c][d][r].total())
+          launch(PH_NONE, false, false, kDecRedo[c][d][r], grid(t_redo[c][d][r]), dim3(64), st,
+                 D[5 + 2 * kClasses + (c * 2 + d) * 2 + r]);
   const uint64_t *d_res = (const uint64_t *)(ws + a256(up.bytes(nj)));
   if (nj == 1) d_res = jobs[0].stat;  // one stream: no gather needed
   else launch(PH_NONE, false, false, k_results, grid(t_one), dim3(64), st, D[1], (uint64_t *)d_res,
@@ -1397,8 +1521,8 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
   std::vector<uint64_t> resv((const uint64_t *)(hs + up.bytes(nj)), (const uint64_t *)(hs + up.bytes(nj)) + (C_N + 1) * nj);
   // more blocks to re-execute than the queue holds: decode those fields again
   // in full with the generic kernel
-  // (a call with queue-sized recon scratch cannot: the blocks beyond the
-  // queue stay uncorrected and the item ends in ESDC)
+  // (a call without recon scratch cannot: the blocks beyond the queue stay
+  // uncorrected and the item ends in ESDC)
   std::vector<uint32_t> again;
   std::vector<uint64_t> overflow(nj, 0);
   for (uint32_t j = 0; j < nj; j++) {

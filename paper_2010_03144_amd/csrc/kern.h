@@ -128,17 +128,18 @@ __global__ void k_headers(JobTab t, uint8_t *dst);
 __global__ void k_dectab(JobTab t);
 __global__ void k_dec_check(JobTab t);
 
-template <typename T, int ND, int B0, int B1, int B2, bool ABFT, bool WIDE> __global__ void k_compress_fast(JobTab t);
+template <typename T, int ND, int B0, int B1, int B2, bool ABFT, bool WIDE, bool FAULTS>
+__global__ void k_compress_fast(JobTab t);
 template <typename T>
 __global__ void k_compress_list(const T *in, Geo g, RegTab<T> rt, PlanDev plan, CompWork w, uint32_t abft,
                                 uint32_t predictor, const uint64_t *list, uint32_t n);
-template <typename T> __global__ void k_redo(JobTab t);
+template <typename T, int ND, int B0, int B1, int B2> __global__ void k_redo(JobTab t);
 
-template <typename T, int ND, int B0, int B1, int B2, bool WIDE> __global__ void k_decode_fast(JobTab t);
+template <typename T, int ND, int B0, int B1, int B2, bool WIDE, bool FAULTS> __global__ void k_decode_fast(JobTab t);
 template <typename T>
 __global__ void k_decode_list(const uint8_t *s, Header h, Geo g, DecWork w, PlanDev plan, T *out,
                               const uint64_t *list, uint32_t n);
-template <typename T> __global__ void k_decode_redo(JobTab t);
+template <typename T, int ND, int B0, int B1, int B2, bool REG> __global__ void k_decode_redo(JobTab t);
 
 template <int ND, int B0, int B1, int B2> __global__ void k_check_fast(JobTab t);
 template <typename T, int ND, int B0, int B1, int B2> __global__ void k_encode_fast(JobTab t);

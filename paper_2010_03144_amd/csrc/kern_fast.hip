@@ -5,11 +5,23 @@
 // checksums, regression sums, costs at the diagonal samples) and a plane loop
 // that keeps the previous reconstructed plane in registers for the Lorenzo
 // recursion.  The input is read twice (first pass, prediction pass); the
-// prediction pass recomputes the input checksums over exactly the words it
-// predicts from, which is Algorithm 1's detection step at the point of use.
-// Blocks named in a fault plan take the generic per-block routine.  A block
-// whose checksums or duplicated computations disagree (a real corruption) is
-// queued and recomputed by k_redo after the launch.
+// first pass takes the exact 64-bit input checksums of Algorithm 1, the
+// prediction pass recomputes them (modulo 2^32) over exactly the words it
+// predicts from, which detects a word changed in between.  The coefficient
+// checksums are taken when the coefficients are computed and verified (a
+// corrupted word located and repaired in place) before the prediction pass.
+// A block whose input checksums or duplicated computations disagree is
+// queued with its first-pass checksums; k_redo locates and repairs the input
+// word against them and runs the block again.
+//
+// Three instantiations of the per-lane routine share this source: the
+// production one, one that applies a fault plan's flips at the program
+// points of evaluation mode A (input and coefficient memory errors after
+// their checksums, flips of the first copy of a duplicated prediction or
+// reconstruction), and the re-execution of k_redo (one repaired input word,
+// histogram counted in global memory).  Blocks whose plan holds more than one
+// flip of a kind, or errors of the prediction preparation, take the generic
+// per-block routine (k_compress_list).
 #include "block_generic.h"
 #include "kern.h"
 
@@ -18,7 +30,7 @@ namespace sdcsz {
 namespace {
 
 // reasons a block is queued for a re-run (high byte of the queue entry)
-constexpr uint64_t kWhyInput = 1, kWhyCoef = 2, kWhyPred = 4, kWhyRecon = 8;
+constexpr uint64_t kWhyInput = 1, kWhyPred = 4, kWhyRecon = 8;
 
 __device__ inline uint64_t map_block(const Geo &g, const Launch &L, uint32_t mode, uint64_t idx) {
   uint64_t c0, c1, c2;
@@ -85,12 +97,12 @@ template <int ND, int B0, int B1, int B2> constexpr int sample_slot(int i0, int 
   return n;
 }
 
-// Checksum-word accumulation: S = sum of the words, Q = sum of the running
-// sums; the paper's isum = sum_j j * w_j (0-based j) is then n_words*S - Q.
-// Here the pair only detects (the block is then redone by the generic
-// routine, which locates and repairs with the exact 64-bit checksums), so
-// it is kept modulo 2^32: a corrupted word changes S by a non-zero amount
-// below 2^32 in magnitude, which no 32-bit wrap can hide.
+// Checksum-word accumulation of the prediction pass: S = sum of the words,
+// Q = sum of the running sums (the paper's isum = sum_j j * w_j, 0-based j,
+// is n_words*S - Q).  This pair only detects, so it is kept modulo 2^32: a
+// corrupted word changes S by a non-zero amount below 2^32 in magnitude,
+// which no 32-bit wrap can hide.  Locating the word takes the exact
+// first-pass pair (Ck64), which k_redo compares with the memory as it is.
 template <typename T> struct Ck;
 template <> struct Ck<float> {
   __device__ static inline void add(float v, uint32_t &S, uint32_t &Q) {
@@ -127,26 +139,153 @@ template <> struct Bound<double> {
   __device__ static inline bool ok(double x, double r, const EbDev &e) { return fabs(x - r) <= e.eb_abs; }
 };
 
-}  // namespace
+// Exact (64-bit) input checksums of the first pass: S = sum of the words,
+// Q = sum of the running sums, so isum = n_words * S - Q (mod 2^64).  The
+// low 32 bits equal the prediction pass's Ck pair over the same words.
+template <typename T> struct Ck64;
+template <> struct Ck64<float> {
+  __device__ static inline void add(float v, uint64_t &S, uint64_t &Q) {
+    S += __float_as_uint(v);
+    Q += S;
+  }
+};
+template <> struct Ck64<double> {
+  __device__ static inline void add(double v, uint64_t &S, uint64_t &Q) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    S += (uint32_t)u;
+    Q += S;
+    S += u >> 32;
+    Q += S;
+  }
+};
 
-// One lane's block: full blocks (FULL) have compile-time extents, blocks of
-// the partial shell mask every point by their actual extents.
-template <typename T, int ND, int B0, int B1, int B2, bool FULL, bool ABFT, bool WIDE>
-__device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const Geo &g, const RegTab<T> &rt,
-                                               const PlanDev &plan, const CompWork &w, uint32_t predictor,
-                                               const Launch &L, uint32_t *hist, uint32_t hlo, uint32_t hw,
-                                               uint32_t &hot, uint64_t idx,
-                                               uint64_t nlanes) {
-  constexpr int PL = B1 * B2;  // points per plane
-  static_assert(PL % 4 == 0, "a plane must fill whole 4-code groups");
-  constexpr int NS = sample_slot<ND, B0, B1, B2>(B0, 0, 0);
-  bool active = idx < nlanes;
-  const uint64_t blk = map_block(g, L, FULL ? 0u : 1u, active ? idx : nlanes - 1);
-  // wave-uniform base of the input (the wave's lowest block origin); lanes
-  // address it with 32-bit byte offsets (fields below 2 GiB, so every offset
-  // fits; wider fields take the WIDE instantiation)
-  const Box bx = box_of(g, blk);
-  const uint64_t org = fidx(g, bx, 0, 0, 0);
+// value v with word `half` (0 low, 1 high for FP64) xor-ed with m / set to x
+template <typename T> __device__ inline T word_xor(T v, uint32_t half, uint32_t m) {
+  uint32_t wv[2] = {0, 0};
+  Wd<T>::split(v, wv);
+  wv[0] ^= half == 0 ? m : 0u;
+  if (Wd<T>::per == 2) wv[1] ^= half == 1 ? m : 0u;
+  return Wd<T>::join(wv);
+}
+template <typename T> __device__ inline T word_set(T v, uint32_t half, uint32_t x) {
+  uint32_t wv[2] = {0, 0};
+  Wd<T>::split(v, wv);
+  wv[0] = half == 0 ? x : wv[0];
+  if (Wd<T>::per == 2) wv[1] = half == 1 ? x : wv[1];
+  return Wd<T>::join(wv);
+}
+
+// Checksums of the coefficient words (Sec. 3.2 algebra: sum, and sum of
+// index times word, 0-based).
+template <typename T> __device__ inline void coef_sums(T b0, T b1, T b2, T m, uint64_t &s, uint64_t &is) {
+  constexpr uint32_t per = Wd<T>::per;
+  uint32_t cw[4 * per];
+  Wd<T>::split(b0, cw);
+  Wd<T>::split(b1, cw + per);
+  Wd<T>::split(b2, cw + 2 * per);
+  Wd<T>::split(m, cw + 3 * per);
+  s = 0;
+  is = 0;
+#pragma unroll
+  for (uint32_t a = 0; a < 4 * per; a++) {
+    s += cw[a];
+    is += (uint64_t)a * cw[a];
+  }
+}
+
+// Verify the coefficients against their checksums; a single corrupted word
+// is located and repaired in place (Algorithm 1, third loop).  Returns 0
+// clean, 1 repaired, -1 uncorrectable.
+template <typename T> __device__ inline int coef_check(T &b0, T &b1, T &b2, T &m, uint64_t s, uint64_t is) {
+  constexpr uint32_t per = Wd<T>::per;
+  uint64_t s2, i2;
+  coef_sums<T>(b0, b1, b2, m, s2, i2);
+  if (s2 == s && i2 == is) return 0;
+  uint32_t cw[4 * per];
+  Wd<T>::split(b0, cw);
+  Wd<T>::split(b1, cw + per);
+  Wd<T>::split(b2, cw + 2 * per);
+  Wd<T>::split(m, cw + 3 * per);
+  uint64_t jf = 0;
+  uint32_t vf = 0;
+  const int st = locate_repair(s2, i2, s, is, 4 * per, 32, [&](uint64_t j) {
+    uint32_t x = 0;
+#pragma unroll
+    for (uint32_t a = 0; a < 4 * per; a++) x = a == j ? cw[a] : x;
+    return x;
+  }, &jf, &vf);
+  if (st != 1) return st;
+#pragma unroll
+  for (uint32_t a = 0; a < 4 * per; a++) cw[a] = a == jf ? vf : cw[a];
+  b0 = Wd<T>::join(cw);
+  b1 = Wd<T>::join(cw + per);
+  b2 = Wd<T>::join(cw + 2 * per);
+  m = Wd<T>::join(cw + 3 * per);
+  return 1;
+}
+
+// per-lane routine instantiations
+enum { kProd = 0, kFaults = 1, kRedo = 2 };
+
+// A lane's flips of a fault plan (at most one of each kind: the host sends
+// blocks with more to the generic routine).  Words and points index the
+// block in C order over its actual extents.  The wave flags are uniform:
+// some lane of the wave has a flip of that kind.
+struct LaneFaults {
+  uint32_t in = ~0u;            // INPUT: 32-bit word | bit << 16
+  uint32_t cf = ~0u;            // COEF: coefficient word | bit << 16
+  uint32_t dp = ~0u, dr = ~0u;  // DUP_PRED / DUP_RECON: point | bit << 16
+  bool wave_in = false, wave_dp = false, wave_dr = false;
+  __device__ uint32_t in_w() const { return in & 0xFFFFu; }
+  __device__ uint32_t in_m() const { return 1u << ((in >> 16) & 31); }
+};
+
+// All lanes of the wave call this (the flags are ballots).
+__device__ inline LaneFaults lane_faults(const PlanDev &plan, uint64_t blk, bool active) {
+  LaneFaults f;
+  if (active && plan_hit(plan, blk)) {
+    for (uint32_t t = plan_first(plan, blk); t < plan.n && plan.f[t].block == blk; t++) {
+      const sdcsz_fault e = plan.f[t];
+      if (e.target == SDCSZ_T_INPUT) {
+        f.in = (uint32_t)e.word | (e.bit << 16);
+      } else if (e.target == SDCSZ_T_COEF) {
+        f.cf = (uint32_t)e.word | (e.bit << 16);
+      } else if (e.target == SDCSZ_T_DUP_PRED) {
+        f.dp = (uint32_t)e.word | (e.bit << 16);
+      } else if (e.target == SDCSZ_T_DUP_RECON) {
+        f.dr = (uint32_t)e.word | (e.bit << 16);
+      }
+    }
+  }
+  f.wave_in = __ballot(f.in != ~0u) != 0;
+  f.wave_dp = __ballot(f.dp != ~0u) != 0;
+  f.wave_dr = __ballot(f.dr != ~0u) != 0;
+  return f;
+}
+
+// Flip the coefficient word w of (b0, b1, b2, m) by mask mk.
+template <typename T> __device__ inline void coef_flip(T &b0, T &b1, T &b2, T &m, uint32_t w, uint32_t mk) {
+  constexpr uint32_t per = Wd<T>::per;
+  const uint32_t a = w / per, half = w % per;
+  if (a == 0) b0 = word_xor(b0, half, mk);
+  else if (a == 1) b1 = word_xor(b1, half, mk);
+  else if (a == 2) b2 = word_xor(b2, half, mk);
+  else m = word_xor(m, half, mk);
+}
+
+// The re-execution's repaired input word (~0u: none).
+struct Patch {
+  uint32_t w = ~0u, v = 0;
+};
+
+// What a lane's pass found: mismatch reasons and the first-pass checksums.
+struct LaneOut {
+  uint64_t why, S1, Q1;
+};
+
+// The wave's lowest block origin (every lane takes part; inactive lanes pass
+// a valid block's origin).
+__device__ inline uint64_t wave_min(uint64_t org) {
   uint64_t omin = org;
   for (int off = 32; off > 0; off >>= 1) {
     const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)omin, off);
@@ -154,13 +293,42 @@ __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const G
     const uint64_t o = ((uint64_t)hi << 32) | lo;
     omin = o < omin ? o : omin;
   }
-  const uint64_t org0 = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(omin >> 32)) << 32) |
-                        (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)omin);
+  return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(omin >> 32)) << 32) |
+         (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)omin);
+}
+
+}  // namespace
+
+// One lane's block: full blocks (FULL) have compile-time extents, blocks of
+// the partial shell mask every point by their actual extents.  MODE selects
+// the instantiation (kProd, kFaults, kRedo).  Every lane of the wave calls it
+// (inactive lanes with a valid block id).  Returns the lane's mismatch
+// reasons and first-pass checksums; the checksums wait in `stash` (two
+// words of LDS per lane) through the prediction pass, which keeps only
+// their low halves in registers (kRedo needs neither).
+template <typename T, int ND, int B0, int B1, int B2, bool FULL, bool ABFT, bool WIDE, int MODE>
+__device__ __forceinline__ LaneOut compress_lanes(const T *__restrict__ in, const Geo &g, const RegTab<T> &rt,
+                                                  const PlanDev &plan, const CompWork &w, uint32_t predictor,
+                                                  uint32_t *hist, uint32_t hlo, uint32_t hw, uint32_t &hot,
+                                                  uint64_t blk, bool active, const Patch &pt, uint64_t *stash) {
+  constexpr int PL = B1 * B2;  // points per plane
+  static_assert(PL % 4 == 0, "a plane must fill whole 4-code groups");
+  static_assert(!(FULL && MODE == kRedo), "re-execution takes the masked path");
+  constexpr int NS = sample_slot<ND, B0, B1, B2>(B0, 0, 0);
+  constexpr uint32_t per = Wd<T>::per;
+  // wave-uniform base of the input (the wave's lowest block origin); lanes
+  // address it with 32-bit byte offsets (fields below 2 GiB, so every offset
+  // fits; wider fields take the WIDE instantiation)
+  const Box bx = box_of(g, blk);
+  const uint64_t org = fidx(g, bx, 0, 0, 0);
+  const uint64_t org0 = WIDE ? 0 : wave_min(org);
   // below 2 GiB: a wave-uniform base and 32-bit per-lane offsets; wider
   // fields: a per-lane base at the block's origin (32-bit offsets inside it)
   const char *wbase = WIDE ? (const char *)(in + org) : (const char *)(in + org0);
   const uint32_t loff = WIDE ? 0u : (uint32_t)((org - org0) * sizeof(T));
-  if (active && plan_hit(plan, blk)) active = false;  // done by k_compress_list
+  if (MODE != kRedo && active && plan_gen(plan, blk)) active = false;  // done by k_compress_list
+  const LaneFaults lf = MODE == kFaults ? lane_faults(plan, blk, active) : LaneFaults{};
+  LaneOut out{0, 0, 0};
   if (active) {
     const EbDev eb = *w.eb;
     const T q = EbSel<T>::q(eb), inv = EbSel<T>::inv(eb), inv_e = EbSel<T>::inv_e(eb);
@@ -174,14 +342,16 @@ __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const G
     auto ld = [&](int i, int j, int k) -> T {
       if (FULL) return *(const T *)(wbase + (loff + (uint32_t)i * PSB + (uint32_t)j * RSB) + k * sizeof(T));
       const uint32_t ii = min((uint32_t)i, n0 - 1), jj = min((uint32_t)j, n1 - 1), kk = min((uint32_t)k, n2 - 1);
-      const T v = *(const T *)(wbase + (loff + ii * PSB + jj * RSB + kk * (uint32_t)sizeof(T)));
+      T v = *(const T *)(wbase + (loff + ii * PSB + jj * RSB + kk * (uint32_t)sizeof(T)));
+      if (MODE == kRedo && pt.w / per == ((uint32_t)i * n1 + (uint32_t)j) * n2 + (uint32_t)k)
+        v = word_set(v, pt.w % per, pt.v);  // the repaired word
       return valid(i, j, k) ? v : (T)0;
     };
 
     // ---- first pass: input checksums, regression sums, Lorenzo costs ------
     T x[B0][B1][B2];
     T sx[NS > 0 ? NS : 1];
-    uint32_t S1 = 0, Q1 = 0;
+    uint64_t S1 = 0, Q1 = 0;
     uint32_t e_lor = 0;
     T S0 = 0, Sa0 = 0, Sa1 = 0, Sa2 = 0;
 #pragma unroll
@@ -208,7 +378,7 @@ __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const G
 #pragma unroll
         for (int k = 0; k < B2; k++) {
           if (valid(i, j, k)) {
-            if (ABFT) Ck<T>::add(x[i][j][k], S1, Q1);
+            if (ABFT) Ck64<T>::add(x[i][j][k], S1, Q1);
             R = R + x[i][j][k];
             D[k] = D[k] + x[i][j][k];
           }
@@ -245,10 +415,21 @@ __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const G
         Sa2 = Sa2 + Bv;
       }
     }
+    uint32_t S1l = 0, Q1l = 0;  // what the prediction pass compares with
+    if (ABFT) {
+      if (MODE != kRedo) {
+        stash[0] = S1;
+        stash[1] = Q1;
+      }
+      S1l = (uint32_t)S1;
+      Q1l = (uint32_t)Q1;
+    }
     T beta0 = n0 > 1 ? Sa0 * rt.K[pat][0] : (T)0;
     T beta1 = n1 > 1 ? Sa1 * rt.K[pat][1] : (T)0;
     T beta2 = n2 > 1 ? Sa2 * rt.K[pat][2] : (T)0;
     T mu = S0 * rt.inv_pts[pat];
+    uint64_t s_c = 0, i_c = 0;  // coefficient checksums, taken as they are computed
+    if (ABFT) coef_sums<T>(beta0, beta1, beta2, mu, s_c, i_c);
 
     bool is_reg;
     if (predictor == SDCSZ_PRED_LORENZO) is_reg = false;
@@ -269,21 +450,20 @@ __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const G
     }
 
     uint64_t why = 0;
-    if (ABFT) {  // coefficient checksums, taken again where the coefficients are used
-      uint32_t sc = 0, qc = 0, sc2 = 0, qc2 = 0;
-      Ck<T>::add(beta0, sc, qc);
-      Ck<T>::add(beta1, sc, qc);
-      Ck<T>::add(beta2, sc, qc);
-      Ck<T>::add(mu, sc, qc);
+    if (MODE == kFaults && lf.cf != ~0u) {  // memory error in a coefficient after its checksums
+      coef_flip<T>(beta0, beta1, beta2, mu, lf.cf & 0xFFFFu, 1u << ((lf.cf >> 16) & 31));
+      count(w.cnt, C_INJ + SDCSZ_T_COEF);
+    }
+    if (ABFT) {  // verify (and repair) the coefficients as they are held now
       beta0 = launder(beta0);
       beta1 = launder(beta1);
       beta2 = launder(beta2);
       mu = launder(mu);
-      Ck<T>::add(beta0, sc2, qc2);
-      Ck<T>::add(beta1, sc2, qc2);
-      Ck<T>::add(beta2, sc2, qc2);
-      Ck<T>::add(mu, sc2, qc2);
-      if (sc != sc2 || qc != qc2) why |= kWhyCoef;
+      const int st = coef_check<T>(beta0, beta1, beta2, mu, s_c, i_c);
+      if (__builtin_expect(st != 0, 0)) {
+        count(w.cnt, C_DET + SDCSZ_T_COEF);
+        count(w.cnt, (st > 0 ? C_COR : C_UNC) + SDCSZ_T_COEF);
+      }
     }
 
     // ---- prediction pass ------------------------------------------------
@@ -341,10 +521,17 @@ __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const G
         T rowold[B2];
         T cprev = 0, Up = 0, Up2 = 0;
         uint32_t rs = 0, rk = 0;
+        const uint32_t prow = ((uint32_t)i * n1 + (uint32_t)j) * n2;  // point index of the row's start
 #pragma unroll
         for (int k = 0; k < B2; k++) {
           const bool v = valid(i, j, k);
-          const T xv = xr[k];
+          T xv = xr[k];
+          if (MODE == kFaults && lf.wave_in) {  // the memory error the first pass did not see
+            if (v && lf.in_w() / per == prow + k) {
+              xv = word_xor(xv, lf.in_w() % per, lf.in_m());
+              count(w.cnt, C_INJ + SDCSZ_T_INPUT);
+            }
+          }
           if (ABFT && v) Ck<T>::add(xv, S2, Q2);
           const T a = Pw[j][k];
           rowold[k] = a;
@@ -359,7 +546,13 @@ __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const G
             lor = cprev + (U1 - Up);
           }
           const T reg = (Aj + Bk[k]) + mu;
-          const T pred = is_reg ? reg : lor;
+          T pred = is_reg ? reg : lor;
+          if (MODE == kFaults && lf.wave_dp) {  // flip of the first copy
+            if (v && (lf.dp & 0xFFFFu) == prow + k) {
+              pred = Wd<T>::flip(pred, lf.dp >> 16);
+              count(w.cnt, C_INJ + SDCSZ_T_DUP_PRED);
+            }
+          }
           if (ABFT) {  // pred' <- f_dup()
             const T bl = launder(b);
             T lor2, U2 = 0;
@@ -380,7 +573,13 @@ __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const G
           // m = trunc(t) with the sign of the difference; truncating the
           // signed value gives the same integer (-0.0 gives 0 either way)
           const int sm = (int)copysign(t, diff);
-          const T r1 = pred + (T)sm * q;
+          T r1 = pred + (T)sm * q;
+          if (MODE == kFaults && lf.wave_dr) {  // flip of the first copy (codes in range only)
+            if (v && inr && (lf.dr & 0xFFFFu) == prow + k) {
+              r1 = Wd<T>::flip(r1, lf.dr >> 16);
+              count(w.cnt, C_INJ + SDCSZ_T_DUP_RECON);
+            }
+          }
           if (ABFT) mis_r |= Wd<T>::diff(r1, pred + (T)launder(sm) * q);  // dec_dup()
           const bool bok = Bound<T>::ok(xv, r1, eb);
           const bool ok = inr && bok;
@@ -395,14 +594,16 @@ __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const G
             nout += is_out ? 1u : 0u;
           }
           const bool z = v && code == kRadius;
-          hot += (uint32_t)__popcll(__ballot(z));  // the same in every lane running the pass
+          if (MODE != kRedo) hot += (uint32_t)__popcll(__ballot(z));  // the same in every lane running the pass
           if (v) {
             if (ABFT) {
               s_dc += Wd<T>::sum(r_out);
               rs += code;
               rk += (uint32_t)k * code;
             }
-            if (!z) {
+            if (MODE == kRedo) {
+              atomicAdd(w.hist + code, 1u);
+            } else if (!z) {
               const uint32_t cb = code - hlo;
               if (cb < hw) atomicAdd(&hist[cb], 1u);
               else atomicAdd(w.hist + code, 1u);
@@ -441,19 +642,17 @@ __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const G
       w.sum_dc[blk] = s_dc;
       w.sum_q[blk] = s_q;
       w.isum_q[blk] = is_q;
-      if (S1 != S2 || Q1 != Q2) why |= kWhyInput;
+      if (S1l != S2 || Q1l != Q2) why |= kWhyInput;
       if (mis_p) why |= kWhyPred;
       if (mis_r) why |= kWhyRecon;
-      if (__builtin_expect(why != 0, 0)) {
-        if (why & kWhyInput) count(w.cnt, C_DET + SDCSZ_T_INPUT);
-        if (why & kWhyCoef) count(w.cnt, C_DET + SDCSZ_T_COEF);
-        if (why & kWhyPred) count(w.cnt, C_DET + SDCSZ_T_DUP_PRED);
-        if (why & kWhyRecon) count(w.cnt, C_DET + SDCSZ_T_DUP_RECON);
-        const uint32_t slot = atomicAdd(w.redo_n, 1u);
-        if (slot < kMaxRedo) w.redo[slot] = blk | (why << 56);
+      out.why = why;
+      if (MODE != kRedo && why) {
+        out.S1 = stash[0];
+        out.Q1 = stash[1];
       }
     }
   }
+  return out;
 }
 
 // One lane's 2D block of B1 rows by B2 columns (the geometry's slowest axis
@@ -462,35 +661,28 @@ __device__ __forceinline__ void compress_lanes(const T *__restrict__ in, const G
 // in the first pass and two ahead in the prediction pass, which keeps the
 // previous reconstructed row only, so a 16x16 block needs no more registers
 // than a 6x6x6 one.
-template <typename T, int B1, int B2, bool FULL, bool ABFT, bool WIDE>
-__device__ __forceinline__ void compress_rows(const T *__restrict__ in, const Geo &g, const RegTab<T> &rt,
-                                              const PlanDev &plan, const CompWork &w, uint32_t predictor,
-                                              const Launch &L, uint32_t *hist, uint32_t hlo, uint32_t hw,
-                                              uint32_t &hot, uint64_t idx,
-                                              uint64_t nlanes) {
+template <typename T, int B1, int B2, bool FULL, bool ABFT, bool WIDE, int MODE>
+__device__ __forceinline__ LaneOut compress_rows(const T *__restrict__ in, const Geo &g, const RegTab<T> &rt,
+                                                 const PlanDev &plan, const CompWork &w, uint32_t predictor,
+                                                 uint32_t *hist, uint32_t hlo, uint32_t hw, uint32_t &hot,
+                                                 uint64_t blk, bool active, const Patch &pt, uint64_t *stash) {
   static_assert(B2 % 4 == 0, "a row must fill whole 4-code groups");
+  static_assert(!(FULL && MODE == kRedo), "re-execution takes the masked path");
   // FP32 keeps the sampled values in registers; FP64 reads them again
   // (from cache) for the regression cost
   constexpr int NS = sizeof(T) == 4 ? sample_slot<2, 1, B1, B2>(1, 0, 0) : 0;
-  bool active = idx < nlanes;
-  const uint64_t blk = map_block(g, L, FULL ? 0u : 1u, active ? idx : nlanes - 1);
+  constexpr uint32_t per = Wd<T>::per;
   const Box bx = box_of(g, blk);
   const uint64_t org = fidx(g, bx, 0, 0, 0);
-  uint64_t omin = org;
-  for (int off = 32; off > 0; off >>= 1) {
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)omin, off);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(omin >> 32), off);
-    const uint64_t o = ((uint64_t)hi << 32) | lo;
-    omin = o < omin ? o : omin;
-  }
-  const uint64_t org0 = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(omin >> 32)) << 32) |
-                        (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)omin);
+  const uint64_t org0 = WIDE ? 0 : wave_min(org);
   // below 2 GiB: a wave-uniform base and 32-bit per-lane offsets; wider
   // fields: a per-lane base at the block's origin (32-bit offsets inside it)
   const char *wbase = WIDE ? (const char *)(in + org) : (const char *)(in + org0);
   const uint32_t loff = WIDE ? 0u : (uint32_t)((org - org0) * sizeof(T));
-  if (active && plan_hit(plan, blk)) active = false;  // done by k_compress_list
-  if (!active) return;
+  if (MODE != kRedo && active && plan_gen(plan, blk)) active = false;  // done by k_compress_list
+  const LaneFaults lf = MODE == kFaults ? lane_faults(plan, blk, active) : LaneFaults{};
+  LaneOut out{0, 0, 0};
+  if (!active) return out;
   const EbDev eb = *w.eb;
   const T q = EbSel<T>::q(eb), inv = EbSel<T>::inv(eb), inv_e = EbSel<T>::inv_e(eb);
   const uint32_t n1 = FULL ? B1 : bx.n[1], n2 = FULL ? B2 : bx.n[2];
@@ -501,7 +693,9 @@ __device__ __forceinline__ void compress_rows(const T *__restrict__ in, const Ge
   auto ld = [&](int j, int k) -> T {
     if (FULL) return *(const T *)(wbase + (loff + (uint32_t)j * RSB) + k * sizeof(T));
     const uint32_t jj = min((uint32_t)j, n1 - 1), kk = min((uint32_t)k, n2 - 1);
-    const T v = *(const T *)(wbase + (loff + jj * RSB + kk * (uint32_t)sizeof(T)));
+    T v = *(const T *)(wbase + (loff + jj * RSB + kk * (uint32_t)sizeof(T)));
+    if (MODE == kRedo && pt.w / per == (uint32_t)j * n2 + (uint32_t)k)
+      v = word_set(v, pt.w % per, pt.v);  // the repaired word
     return valid(j, k) ? v : (T)0;
   };
 
@@ -509,7 +703,8 @@ __device__ __forceinline__ void compress_rows(const T *__restrict__ in, const Ge
   T xc[B2], xn[B2], xp[B2];  // rows j, j + 1 (in flight) and j - 1
   T sx[NS > 0 ? NS : 1];
   T D[B2];
-  uint32_t S1 = 0, Q1 = 0, e_lor = 0;
+  uint64_t S1 = 0, Q1 = 0;
+  uint32_t e_lor = 0;
   T P = 0, A = 0;
 #pragma unroll
   for (int k = 0; k < B2; k++) {
@@ -527,7 +722,7 @@ __device__ __forceinline__ void compress_rows(const T *__restrict__ in, const Ge
 #pragma unroll
     for (int k = 0; k < B2; k++) {
       if (valid(j, k)) {
-        if (ABFT) Ck<T>::add(xc[k], S1, Q1);
+        if (ABFT) Ck64<T>::add(xc[k], S1, Q1);
         R = R + xc[k];
         D[k] = D[k] + xc[k];
       }
@@ -559,10 +754,21 @@ __device__ __forceinline__ void compress_rows(const T *__restrict__ in, const Ge
   // the slowest axis has one plane: its sums start from zero like the
   // paper-order routine's
   const T S0 = (T)0 + P, Sa1 = (T)0 + A, Sa2 = (T)0 + Bv;
+  uint32_t S1l = 0, Q1l = 0;  // what the prediction pass compares with
+  if (ABFT) {
+    if (MODE != kRedo) {
+      stash[0] = S1;
+      stash[1] = Q1;
+    }
+    S1l = (uint32_t)S1;
+    Q1l = (uint32_t)Q1;
+  }
   T beta0 = 0;
   T beta1 = n1 > 1 ? Sa1 * rt.K[pat][1] : (T)0;
   T beta2 = n2 > 1 ? Sa2 * rt.K[pat][2] : (T)0;
   T mu = S0 * rt.inv_pts[pat];
+  uint64_t s_c = 0, i_c = 0;  // coefficient checksums, taken as they are computed
+  if (ABFT) coef_sums<T>(beta0, beta1, beta2, mu, s_c, i_c);
 
   bool is_reg;
   if (predictor == SDCSZ_PRED_LORENZO) is_reg = false;
@@ -582,21 +788,20 @@ __device__ __forceinline__ void compress_rows(const T *__restrict__ in, const Ge
   }
 
   uint64_t why = 0;
-  if (ABFT) {  // coefficient checksums, taken again where the coefficients are used
-    uint32_t sc = 0, qc = 0, sc2 = 0, qc2 = 0;
-    Ck<T>::add(beta0, sc, qc);
-    Ck<T>::add(beta1, sc, qc);
-    Ck<T>::add(beta2, sc, qc);
-    Ck<T>::add(mu, sc, qc);
+  if (MODE == kFaults && lf.cf != ~0u) {  // memory error in a coefficient after its checksums
+    coef_flip<T>(beta0, beta1, beta2, mu, lf.cf & 0xFFFFu, 1u << ((lf.cf >> 16) & 31));
+    count(w.cnt, C_INJ + SDCSZ_T_COEF);
+  }
+  if (ABFT) {  // verify (and repair) the coefficients as they are held now
     beta0 = launder(beta0);
     beta1 = launder(beta1);
     beta2 = launder(beta2);
     mu = launder(mu);
-    Ck<T>::add(beta0, sc2, qc2);
-    Ck<T>::add(beta1, sc2, qc2);
-    Ck<T>::add(beta2, sc2, qc2);
-    Ck<T>::add(mu, sc2, qc2);
-    if (sc != sc2 || qc != qc2) why |= kWhyCoef;
+    const int st = coef_check<T>(beta0, beta1, beta2, mu, s_c, i_c);
+    if (__builtin_expect(st != 0, 0)) {
+      count(w.cnt, C_DET + SDCSZ_T_COEF);
+      count(w.cnt, (st > 0 ? C_COR : C_UNC) + SDCSZ_T_COEF);
+    }
   }
 
   // ---- prediction pass, a row per iteration --------------------------------
@@ -640,16 +845,29 @@ __device__ __forceinline__ void compress_rows(const T *__restrict__ in, const Ge
     }
     T cprev = 0, fold = 0;
     uint32_t rs = 0, rk = 0, pk0 = 0, pk1 = 0;
+    const uint32_t prow = (uint32_t)j * n2;  // point index of the row's start
 #pragma unroll
     for (int k = 0; k < B2; k++) {
       const bool v = valid(j, k);
-      const T xv = xr[k];
+      T xv = xr[k];
+      if (MODE == kFaults && lf.wave_in) {  // the memory error the first pass did not see
+        if (v && lf.in_w() / per == prow + k) {
+          xv = word_xor(xv, lf.in_w() % per, lf.in_m());
+          count(w.cnt, C_INJ + SDCSZ_T_INPUT);
+        }
+      }
       if (ABFT && v) Ck<T>::add(xv, S2, Q2);
       const T b = Pr[k], f = fold;  // r(j-1,k), r(j-1,k-1)
       fold = b;
       const T lor = (b + cprev) - f;
       const T reg = (Aj + Bk[k]) + mu;
-      const T pred = is_reg ? reg : lor;
+      T pred = is_reg ? reg : lor;
+      if (MODE == kFaults && lf.wave_dp) {  // flip of the first copy
+        if (v && (lf.dp & 0xFFFFu) == prow + k) {
+          pred = Wd<T>::flip(pred, lf.dp >> 16);
+          count(w.cnt, C_INJ + SDCSZ_T_DUP_PRED);
+        }
+      }
       if (ABFT) {  // pred' <- f_dup()
         const T lor2 = (launder(b) + cprev) - f;
         const T reg2 = (Ajd + Bk2[k]) + mu;
@@ -659,7 +877,13 @@ __device__ __forceinline__ void compress_rows(const T *__restrict__ in, const Ge
       const T t = fabs(diff) * inv + (T)0.5;
       const bool inr = t < (T)32768;
       const int sm = (int)copysign(t, diff);
-      const T r1 = pred + (T)sm * q;
+      T r1 = pred + (T)sm * q;
+      if (MODE == kFaults && lf.wave_dr) {  // flip of the first copy (codes in range only)
+        if (v && inr && (lf.dr & 0xFFFFu) == prow + k) {
+          r1 = Wd<T>::flip(r1, lf.dr >> 16);
+          count(w.cnt, C_INJ + SDCSZ_T_DUP_RECON);
+        }
+      }
       if (ABFT) mis_r |= Wd<T>::diff(r1, pred + (T)launder(sm) * q);  // dec_dup()
       const bool bok = Bound<T>::ok(xv, r1, eb);
       const bool ok = inr && bok;
@@ -673,14 +897,16 @@ __device__ __forceinline__ void compress_rows(const T *__restrict__ in, const Ge
         nout += is_out ? 1u : 0u;
       }
       const bool z = v && code == kRadius;
-      hot += (uint32_t)__popcll(__ballot(z));
+      if (MODE != kRedo) hot += (uint32_t)__popcll(__ballot(z));
       if (v) {
         if (ABFT) {
           s_dc += Wd<T>::sum(r_out);
           rs += code;
           rk += (uint32_t)k * code;
         }
-        if (!z) {
+        if (MODE == kRedo) {
+          atomicAdd(w.hist + code, 1u);
+        } else if (!z) {
           const uint32_t cb = code - hlo;
           if (cb < hw) atomicAdd(&hist[cb], 1u);
           else atomicAdd(w.hist + code, 1u);
@@ -714,23 +940,36 @@ __device__ __forceinline__ void compress_rows(const T *__restrict__ in, const Ge
     w.sum_dc[blk] = s_dc;
     w.sum_q[blk] = s_q;
     w.isum_q[blk] = is_q;
-    if (S1 != S2 || Q1 != Q2) why |= kWhyInput;
+    if (S1l != S2 || Q1l != Q2) why |= kWhyInput;
     if (mis_p) why |= kWhyPred;
     if (mis_r) why |= kWhyRecon;
-    if (__builtin_expect(why != 0, 0)) {
-      if (why & kWhyInput) count(w.cnt, C_DET + SDCSZ_T_INPUT);
-      if (why & kWhyCoef) count(w.cnt, C_DET + SDCSZ_T_COEF);
-      if (why & kWhyPred) count(w.cnt, C_DET + SDCSZ_T_DUP_PRED);
-      if (why & kWhyRecon) count(w.cnt, C_DET + SDCSZ_T_DUP_RECON);
-      const uint32_t slot = atomicAdd(w.redo_n, 1u);
-      if (slot < kMaxRedo) w.redo[slot] = blk | (why << 56);
+    out.why = why;
+    if (MODE != kRedo && why) {
+      out.S1 = stash[0];
+      out.Q1 = stash[1];
     }
+  }
+  return out;
+}
+
+// Queue a block whose checks disagreed, with its first-pass checksums.
+__device__ inline void queue_redo(const CompWork &w, uint64_t blk, const LaneOut &o) {
+  if (o.why & kWhyInput) count(w.cnt, C_DET + SDCSZ_T_INPUT);
+  if (o.why & kWhyPred) count(w.cnt, C_DET + SDCSZ_T_DUP_PRED);
+  if (o.why & kWhyRecon) count(w.cnt, C_DET + SDCSZ_T_DUP_RECON);
+  const uint32_t slot = atomicAdd(w.redo_n, 1u);
+  if (slot < kMaxRedo) {
+    w.redo[3 * slot] = blk | (o.why << 56);
+    w.redo[3 * slot + 1] = o.S1;
+    w.redo[3 * slot + 2] = o.Q1;
   }
 }
 
 // Work-groups [0, L.full_wgs) take full blocks, the rest the partial shell.
-template <typename T, int ND, int B0, int B1, int B2, bool ABFT, bool WIDE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ND == 3 && sizeof(T) == 4 ? 3 : 1)))
+// FAULTS: the instantiation that applies the fault plan's flips.
+template <typename T, int ND, int B0, int B1, int B2, bool ABFT, bool WIDE, bool FAULTS>
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(ND == 3 && sizeof(T) == 4 ? (FAULTS ? 2 : 3) : 1)))
 k_compress_fast(JobTab tab) {
   const JobWg jw = job_of(tab);
   const T *__restrict__ in = (const T *)jw.J->src;
@@ -746,26 +985,36 @@ k_compress_fast(JobTab tab) {
   // global histogram
   const uint32_t hw = jw.J->hist_win, hlo = kRadius - hw / 2;
   extern __shared__ uint32_t hist[];
+  __shared__ uint64_t stash[2 * 256];  // first-pass input checksums, per lane
   for (uint32_t t = threadIdx.x; t < hw; t += blockDim.x) hist[t] = 0;
   __syncthreads();
   uint32_t hot = 0;
+  uint64_t *st = ABFT ? stash + 2 * threadIdx.x : nullptr;
   const bool full = jw.b < L.full_wgs;
   const uint64_t idx = (uint64_t)(full ? jw.b : jw.b - L.full_wgs) * blockDim.x + threadIdx.x;
+  const uint64_t nl = full ? L.full_count : L.shell_count;
+  const bool act = idx < nl;
+  const uint64_t blk = map_block(g, L, full ? 0u : 1u, act ? idx : nl - 1);
+  constexpr int M = FAULTS ? kFaults : kProd;
+  const Patch none;
+  LaneOut o;
   if constexpr (ND == 2) {
     static_assert(B0 == 1, "2D blocks have one plane");
     if (full)
-      compress_rows<T, B1, B2, true, ABFT, WIDE>(in, g, rt, plan, w, predictor, L, hist, hlo, hw, hot, idx, L.full_count);
+      o = compress_rows<T, B1, B2, true, ABFT, WIDE, M>(in, g, rt, plan, w, predictor, hist, hlo, hw, hot, blk, act,
+                                                        none, st);
     else
-      compress_rows<T, B1, B2, false, ABFT, WIDE>(in, g, rt, plan, w, predictor, L, hist, hlo, hw, hot, idx,
-                                                  L.shell_count);
+      o = compress_rows<T, B1, B2, false, ABFT, WIDE, M>(in, g, rt, plan, w, predictor, hist, hlo, hw, hot, blk, act,
+                                                         none, st);
   } else {
     if (full)
-      compress_lanes<T, ND, B0, B1, B2, true, ABFT, WIDE>(in, g, rt, plan, w, predictor, L, hist, hlo, hw, hot, idx,
-                                                          L.full_count);
+      o = compress_lanes<T, ND, B0, B1, B2, true, ABFT, WIDE, M>(in, g, rt, plan, w, predictor, hist, hlo, hw, hot,
+                                                                 blk, act, none, st);
     else
-      compress_lanes<T, ND, B0, B1, B2, false, ABFT, WIDE>(in, g, rt, plan, w, predictor, L, hist, hlo, hw, hot,
-                                                           idx, L.shell_count);
+      o = compress_lanes<T, ND, B0, B1, B2, false, ABFT, WIDE, M>(in, g, rt, plan, w, predictor, hist, hlo, hw, hot,
+                                                                  blk, act, none, st);
   }
+  if (ABFT && __builtin_expect(o.why != 0, 0)) queue_redo(w, blk, o);
   // wave total of the zero-residual bin (lanes that ran the pass agree; the
   // others hold 0), then flush the window
   for (int off = 32; off > 0; off >>= 1) hot = max(hot, (uint32_t)__shfl_xor((int)hot, off));
@@ -775,51 +1024,111 @@ k_compress_fast(JobTab tab) {
     if (hist[t]) atomicAdd(w.hist + hlo + t, hist[t]);
 }
 
-// The blocks a fault plan names, in the paper's order with the plan applied
-// (one thread per listed block).
+// The blocks the host sends to the paper-order routine (fault plans the
+// specialised kernels do not apply), one thread per listed block.
 template <typename T>
 __global__ void __launch_bounds__(64) k_compress_list(const T *__restrict__ in, Geo g, RegTab<T> rt, PlanDev plan,
                                                        CompWork w, uint32_t abft, uint32_t predictor,
                                                        const uint64_t *list, uint32_t n) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n) compress_block_generic<T>(in, g, rt, plan, w, abft, predictor, list[t]);
+  if (t < n) {
+    compress_block_generic<T>(in, g, rt, plan, w, abft, predictor, list[t]);
+    count(w.cnt, C_LIST);
+  }
 }
 
-// Blocks whose checks disagreed in the specialised pass: take the block's
-// codes back out of the histogram and run the block again from the input
-// with the generic routine.
-template <typename T> __global__ void __launch_bounds__(64) k_redo(JobTab tab) {
-  const Job &J = *job_of(tab).J;
+// Re-execution of the queued blocks (Algorithm 1's correction at block
+// granularity), one lane per queue entry.  An input mismatch first locates
+// the corrupted word: the exact checksums of the memory as it is now (with a
+// plan's INPUT flip, which persists) against the first-pass checksums give
+// the word and its value before the error; an error that cannot be located
+// is uncorrectable.  Then the block's codes leave the histogram and the
+// block runs again with the repaired word.  A re-run whose own checks
+// disagree is uncorrectable.  Lanes address their blocks from per-lane
+// bases (the wide form), which serves every field size.
+template <typename T, int ND, int B0, int B1, int B2> __global__ void __launch_bounds__(64) k_redo(JobTab tab) {
+  const JobWg jw = job_of(tab);
+  const Job &J = *jw.J;
   const T *__restrict__ in = (const T *)J.src;
   const Geo g = J.g;
   const RegTab<T> &rt = rt_of<T>(J);
   const PlanDev plan = J.plan;
   const CompWork w = J.cw;
-  const uint32_t abft = J.abft, predictor = J.predictor;
+  const uint32_t predictor = J.predictor;
+  constexpr uint32_t per = Wd<T>::per;
+  if (!J.abft) return;
   const uint32_t n = min(*w.redo_n, kMaxRedo);
-  for (uint32_t s = threadIdx.x; s < n; s += blockDim.x) {
-    const uint64_t e = w.redo[s];
-    const uint64_t blk = e & ((1ull << 56) - 1), why = e >> 56;
-    const Box b = box_of(g, blk);
-    for (uint32_t i = 0; i < b.n[0]; i++)
-      for (uint32_t j = 0; j < b.n[1]; j++)
-        for (uint32_t k = 0; k < b.n[2]; k++)
-          atomicSub(w.hist + w.codes[code_index(blk, padded_index(g, i, j, k), g.groups)], 1u);
-    compress_block_generic<T>(in, g, rt, plan, w, abft, predictor, blk);
-    if (why & kWhyInput) count(w.cnt, C_COR + SDCSZ_T_INPUT);
-    if (why & kWhyCoef) count(w.cnt, C_COR + SDCSZ_T_COEF);
-    if (why & kWhyPred) count(w.cnt, C_COR + SDCSZ_T_DUP_PRED);
-    if (why & kWhyRecon) count(w.cnt, C_COR + SDCSZ_T_DUP_RECON);
+  uint32_t hot = 0;
+  for (uint32_t base = jw.b * blockDim.x; base < n; base += jw.nb * blockDim.x) {
+    const uint32_t e = base + threadIdx.x;
+    const bool act = e < n;
+    const uint32_t ec = act ? e : n - 1;
+    const uint64_t blk = w.redo[3 * ec] & ((1ull << 56) - 1), why = w.redo[3 * ec] >> 56;
+    const LaneFaults lf = lane_faults(plan, blk, act);
+    Patch pt;
+    bool run = act;
+    if (act && (why & kWhyInput)) {
+      const Box b = box_of(g, blk);
+      const uint32_t nw = b.pts * per;
+      auto word_at = [&](uint64_t jw_) -> uint32_t {
+        const uint32_t p = (uint32_t)(jw_ / per);
+        const uint32_t k = p % b.n[2], j = (p / b.n[2]) % b.n[1], i = p / (b.n[2] * b.n[1]);
+        T v = in[fidx(g, b, i, j, k)];
+        if (lf.in != ~0u && lf.in_w() / per == p) v = word_xor(v, lf.in_w() % per, lf.in_m());
+        uint32_t wv[2] = {0, 0};
+        Wd<T>::split(v, wv);
+        return wv[jw_ % per];
+      };
+      uint64_t S = 0, Q = 0;
+      for (uint32_t jw_ = 0; jw_ < nw; jw_++) {
+        S += word_at(jw_);
+        Q += S;
+      }
+      const uint64_t S1 = w.redo[3 * e + 1], Q1 = w.redo[3 * e + 2];
+      uint64_t jf = 0;
+      uint32_t vf = 0;
+      const int st = locate_repair(S, (uint64_t)nw * S - Q, S1, (uint64_t)nw * S1 - Q1, nw, 32, word_at, &jf, &vf);
+      if (st < 0) {
+        count(w.cnt, C_UNC + SDCSZ_T_INPUT);
+        run = false;
+      } else if (st == 1) {
+        pt.w = (uint32_t)jf;
+        pt.v = vf;
+      }
+    }
+    if (run) {
+      const Box b = box_of(g, blk);
+      for (uint32_t i = 0; i < b.n[0]; i++)
+        for (uint32_t j = 0; j < b.n[1]; j++)
+          for (uint32_t k = 0; k < b.n[2]; k++)
+            atomicSub(w.hist + w.codes[code_index(blk, padded_index(g, i, j, k), g.groups)], 1u);
+    }
+    LaneOut o;
+    if constexpr (ND == 2)
+      o = compress_rows<T, B1, B2, false, true, true, kRedo>(in, g, rt, plan, w, predictor, nullptr, 0, 0, hot, blk,
+                                                             run, pt, nullptr);
+    else
+      o = compress_lanes<T, ND, B0, B1, B2, false, true, true, kRedo>(in, g, rt, plan, w, predictor, nullptr, 0, 0,
+                                                                      hot, blk, run, pt, nullptr);
+    if (run) {
+      const int slot = o.why ? C_UNC : C_COR;
+      if (why & kWhyInput) count(w.cnt, slot + SDCSZ_T_INPUT);
+      if (why & kWhyPred) count(w.cnt, slot + SDCSZ_T_DUP_PRED);
+      if (why & kWhyRecon) count(w.cnt, slot + SDCSZ_T_DUP_RECON);
+    }
   }
 }
 
-#define SDCSZ_INST_FAST(T, ND, B0, B1, B2, ABFT, WIDE) \
-  template __global__ void k_compress_fast<T, ND, B0, B1, B2, ABFT, WIDE>(JobTab);
-#define SDCSZ_INST_SHAPE(T, ND, B0, B1, B2)         \
-  SDCSZ_INST_FAST(T, ND, B0, B1, B2, true, false)  \
-  SDCSZ_INST_FAST(T, ND, B0, B1, B2, false, false) \
-  SDCSZ_INST_FAST(T, ND, B0, B1, B2, true, true)   \
-  SDCSZ_INST_FAST(T, ND, B0, B1, B2, false, true)
+#define SDCSZ_INST_FAST(T, ND, B0, B1, B2, ABFT, WIDE, FAULTS) \
+  template __global__ void k_compress_fast<T, ND, B0, B1, B2, ABFT, WIDE, FAULTS>(JobTab);
+#define SDCSZ_INST_SHAPE(T, ND, B0, B1, B2)                \
+  SDCSZ_INST_FAST(T, ND, B0, B1, B2, true, false, false)  \
+  SDCSZ_INST_FAST(T, ND, B0, B1, B2, false, false, false) \
+  SDCSZ_INST_FAST(T, ND, B0, B1, B2, true, true, false)   \
+  SDCSZ_INST_FAST(T, ND, B0, B1, B2, false, true, false)  \
+  SDCSZ_INST_FAST(T, ND, B0, B1, B2, true, false, true)   \
+  SDCSZ_INST_FAST(T, ND, B0, B1, B2, false, false, true)  \
+  template __global__ void k_redo<T, ND, B0, B1, B2>(JobTab);
 SDCSZ_INST_SHAPE(float, 3, 6, 6, 6)
 SDCSZ_INST_SHAPE(double, 3, 6, 6, 6)
 SDCSZ_INST_SHAPE(float, 2, 1, 16, 16)
@@ -828,7 +1137,5 @@ template __global__ void k_compress_list<float>(const float *, Geo, RegTab<float
                                                 uint32_t, const uint64_t *, uint32_t);
 template __global__ void k_compress_list<double>(const double *, Geo, RegTab<double>, PlanDev, CompWork, uint32_t,
                                                  uint32_t, const uint64_t *, uint32_t);
-template __global__ void k_redo<float>(JobTab);
-template __global__ void k_redo<double>(JobTab);
 
 }  // namespace sdcsz

@@ -7,8 +7,10 @@
 // with the arithmetic of compression (previous reconstructed plane in
 // registers), the checksum of the block against sum_dc, and coalesced row
 // stores.  A checksum mismatch or an undecodable block queues the block for
-// k_decode_redo (re-execution from the compressed bytes); blocks named in a
-// fault plan run in k_decode_list.
+// k_decode_redo, which re-executes it from the compressed bytes with the
+// same per-lane routine (one lane per queued block).  A fault plan's RECON
+// flips strike the decompressed words in the instantiation that applies
+// them (FAULTS); blocks with more than one flip run in k_decode_list.
 #include "dev.h"
 #include "kern.h"
 
@@ -166,19 +168,39 @@ __device__ inline uint32_t decode_sym(Window &br, const DecLds &t, const uint16_
   return sym;
 }
 
-}  // namespace
+// per-lane routine instantiations
+enum { kDProd = 0, kDFaults = 1, kDRedo = 2 };
 
-template <typename T, int ND, int B0, int B1, int B2, bool FULL, bool REG, bool WIDE>
-__device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, const Header &h, const Geo &g,
-                                             const DecWork &w, const PlanDev &plan, T *out, const Launch &L,
-                                             const DecLds &tl, uint32_t *win, uint64_t idx, uint64_t nlanes,
-                                             const Region &reg, const Region &rb) {
-  static_assert(!(REG && FULL), "a region launch takes the masked path");
-  bool active = idx < nlanes;
-  const uint64_t blk = REG ? rmap_block(g, rb, active ? idx : nlanes - 1)
-                           : dmap_block(g, L, FULL ? 0u : 1u, active ? idx : nlanes - 1);
-  const Box bx = box_of(g, blk);
-  const uint64_t org = fidx(g, bx, 0, 0, 0);
+// A lane's RECON flip (at most one: the host sends blocks with more to the
+// generic routine): point index in C order over the block's extents, word
+// half, xor mask; the wave flag is uniform.
+struct LaneRecon {
+  uint32_t p = ~0u, half = 0, m = 0;
+  bool wave = false;
+};
+__device__ inline LaneRecon lane_recon(const PlanDev &plan, uint64_t blk, bool active, uint32_t per) {
+  LaneRecon f;
+  if (active && plan_hit(plan, blk))
+    for (uint32_t t = plan_first(plan, blk); t < plan.n && plan.f[t].block == blk; t++)
+      if (plan.f[t].target == SDCSZ_T_RECON) {
+        f.p = (uint32_t)(plan.f[t].word / per);
+        f.half = (uint32_t)(plan.f[t].word % per);
+        f.m = 1u << (plan.f[t].bit & 31);
+      }
+  f.wave = __ballot(f.p != ~0u) != 0;
+  return f;
+}
+
+template <typename T> __device__ inline T word_xor(T v, uint32_t half, uint32_t m) {
+  uint32_t wv[2] = {0, 0};
+  Wd<T>::split(v, wv);
+  wv[0] ^= half == 0 ? m : 0u;
+  if (Wd<T>::per == 2) wv[1] ^= half == 1 ? m : 0u;
+  return Wd<T>::join(wv);
+}
+
+// The wave's lowest block origin (every lane takes part).
+__device__ inline uint64_t dwave_min(uint64_t org) {
   uint64_t omin = org;
   for (int off = 32; off > 0; off >>= 1) {
     const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)omin, off);
@@ -186,14 +208,38 @@ __device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, cons
     const uint64_t o = ((uint64_t)hi << 32) | lo;
     omin = o < omin ? o : omin;
   }
-  const uint64_t org0 = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(omin >> 32)) << 32) |
-                        (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)omin);
+  return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(omin >> 32)) << 32) |
+         (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)omin);
+}
+
+// What a lane's decoding found.
+struct DecOut {
+  bool bad;      // no codeword matched, the payload overran, or the outliers disagree
+  uint64_t sum;  // checksum of the decompressed words
+};
+
+}  // namespace
+
+// One lane's block (every lane of the wave calls it; inactive lanes with a
+// valid block id).  MODE: kDProd, kDFaults (the plan's RECON flips), kDRedo
+// (re-execution: nothing queued, the caller judges the result).
+template <typename T, int ND, int B0, int B1, int B2, bool FULL, bool REG, bool WIDE, int MODE>
+__device__ __forceinline__ DecOut decode_lanes(const uint8_t *__restrict__ s, const Header &h, const Geo &g,
+                                               const DecWork &w, const PlanDev &plan, T *out, const DecLds &tl,
+                                               uint32_t *win, uint64_t blk, bool active, const Region &reg) {
+  static_assert(!(REG && FULL), "a region launch takes the masked path");
+  static_assert(!(FULL && MODE == kDRedo), "re-execution takes the masked path");
+  const Box bx = box_of(g, blk);
+  const uint64_t org = fidx(g, bx, 0, 0, 0);
+  const uint64_t org0 = WIDE ? 0 : dwave_min(org);
   // below 2 GiB: a wave-uniform base and 32-bit per-lane offsets; wider
   // fields: a per-lane base at the block's origin (32-bit offsets inside it)
   char *wbase = WIDE ? (char *)(out + org) : (char *)(out + org0);
   const uint32_t loff = WIDE ? 0u : (uint32_t)((org - org0) * sizeof(T));
-  if (active && plan_hit(plan, blk)) active = false;  // done by k_decode_list
-  if (!active) return;
+  if (MODE != kDRedo && active && plan_gen(plan, blk)) active = false;  // done by k_decode_list
+  const LaneRecon lf = MODE == kDFaults ? lane_recon(plan, blk, active, Wd<T>::per) : LaneRecon{};
+  DecOut res{false, 0};
+  if (!active) return res;
 
   const uint32_t n0 = FULL ? B0 : bx.n[0], n1 = FULL ? B1 : bx.n[1], n2 = FULL ? B2 : bx.n[2];
   const uint32_t PSB = (uint32_t)(g.d[1] * g.d[2] * sizeof(T)), RSB = (uint32_t)(g.d[2] * sizeof(T));
@@ -245,6 +291,7 @@ __device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, cons
       dpin(Aj);
       T rowold[B2], rv[B2];
       T cprev = 0, Up = 0;
+      const uint32_t prow = ((uint32_t)i * n1 + (uint32_t)j) * n2;  // point index of the row's start
 #pragma unroll
       for (int k = 0; k < B2; k++) {
         const bool v = FULL || (uint32_t)k < n2;
@@ -278,10 +325,17 @@ __device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, cons
           }
         }
         Pw[j][k] = r;
-        rv[k] = r;
+        T rs = r;  // the decompressed word as stored and checked
+        if (MODE == kDFaults && lf.wave) {
+          if (v && lf.p == prow + k) {
+            rs = word_xor(r, lf.half, lf.m);
+            count(w.cnt, C_INJ + SDCSZ_T_RECON);
+          }
+        }
+        rv[k] = rs;
         cprev = r;
         Up = U1;
-        if (v) sum += Wd<T>::sum(r);
+        if (v) sum += Wd<T>::sum(rs);
       }
       if constexpr (REG) {
         // the part of the row inside the region
@@ -307,50 +361,46 @@ __device__ __forceinline__ void decode_lanes(const uint8_t *__restrict__ s, cons
     }
   }
   if (used_out != nout || br.pos > nw * 32u) bad = true;
-  const uint64_t *sumdc = (const uint64_t *)(s + h.off_sumdc);
-  uint64_t why = 0;
-  if (bad) why = 2;
-  else if (h.abft && sum != sumdc[blk]) {
-    why = 1;
-    count(w.cnt, C_DET + SDCSZ_T_RECON);
+  res.bad = bad;
+  res.sum = sum;
+  if (MODE != kDRedo) {
+    const uint64_t *sumdc = (const uint64_t *)(s + h.off_sumdc);
+    uint64_t why = 0;
+    if (bad) why = 2;
+    else if (h.abft && sum != sumdc[blk]) {
+      why = 1;
+      count(w.cnt, C_DET + SDCSZ_T_RECON);
+    }
+    if (__builtin_expect(why != 0, 0)) {
+      const uint32_t slot = atomicAdd(w.redo_n, 1u);
+      if (slot < kMaxRedo) w.redo[slot] = blk | (why << 56);
+    }
   }
-  if (__builtin_expect(why != 0, 0)) {
-    const uint32_t slot = atomicAdd(w.redo_n, 1u);
-    if (slot < kMaxRedo) w.redo[slot] = blk | (why << 56);
-  }
+  return res;
 }
 
 // One lane's 2D block of B1 rows by B2 columns, a row per iteration with the
 // previous reconstructed row in registers; the window is staged once per row
 // (B2 codewords of <= 24 bits plus the <= 127-bit skew fit in kWin words for
 // B2 <= 16).
-template <typename T, int B1, int B2, bool FULL, bool REG, bool WIDE>
-__device__ __forceinline__ void decode_rows(const uint8_t *__restrict__ s, const Header &h, const Geo &g,
-                                            const DecWork &w, const PlanDev &plan, T *out, const Launch &L,
-                                            const DecLds &tl, uint32_t *win, uint64_t idx, uint64_t nlanes,
-                                            const Region &reg, const Region &rb) {
+template <typename T, int B1, int B2, bool FULL, bool REG, bool WIDE, int MODE>
+__device__ __forceinline__ DecOut decode_rows(const uint8_t *__restrict__ s, const Header &h, const Geo &g,
+                                              const DecWork &w, const PlanDev &plan, T *out, const DecLds &tl,
+                                              uint32_t *win, uint64_t blk, bool active, const Region &reg) {
   static_assert(B2 * kMaxLen + 127 + 32 <= 32 * (int)kWin, "a row's codewords fit the window");
   static_assert(!(REG && FULL), "a region launch takes the masked path");
-  bool active = idx < nlanes;
-  const uint64_t blk = REG ? rmap_block(g, rb, active ? idx : nlanes - 1)
-                           : dmap_block(g, L, FULL ? 0u : 1u, active ? idx : nlanes - 1);
+  static_assert(!(FULL && MODE == kDRedo), "re-execution takes the masked path");
   const Box bx = box_of(g, blk);
   const uint64_t org = fidx(g, bx, 0, 0, 0);
-  uint64_t omin = org;
-  for (int off = 32; off > 0; off >>= 1) {
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)omin, off);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(omin >> 32), off);
-    const uint64_t o = ((uint64_t)hi << 32) | lo;
-    omin = o < omin ? o : omin;
-  }
-  const uint64_t org0 = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(omin >> 32)) << 32) |
-                        (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)omin);
+  const uint64_t org0 = WIDE ? 0 : dwave_min(org);
   // below 2 GiB: a wave-uniform base and 32-bit per-lane offsets; wider
   // fields: a per-lane base at the block's origin (32-bit offsets inside it)
   char *wbase = WIDE ? (char *)(out + org) : (char *)(out + org0);
   const uint32_t loff = WIDE ? 0u : (uint32_t)((org - org0) * sizeof(T));
-  if (active && plan_hit(plan, blk)) active = false;  // done by k_decode_list
-  if (!active) return;
+  if (MODE != kDRedo && active && plan_gen(plan, blk)) active = false;  // done by k_decode_list
+  const LaneRecon lf = MODE == kDFaults ? lane_recon(plan, blk, active, Wd<T>::per) : LaneRecon{};
+  DecOut res{false, 0};
+  if (!active) return res;
 
   const uint32_t n0 = bx.n[0], n1 = FULL ? B1 : bx.n[1], n2 = FULL ? B2 : bx.n[2];
   const uint32_t RSB = (uint32_t)(g.d[2] * sizeof(T));
@@ -391,6 +441,8 @@ __device__ __forceinline__ void decode_rows(const uint8_t *__restrict__ s, const
     T Aj = A0 + beta1 * ((T)j - c1);
     dpin(Aj);
     T cprev = 0, fold = 0;
+    T rv[B2];
+    const uint32_t prow = (uint32_t)j * n2;  // point index of the row's start
 #pragma unroll
     for (int k = 0; k < B2; k++) {
       const bool v = FULL || (uint32_t)k < n2;
@@ -415,8 +467,16 @@ __device__ __forceinline__ void decode_rows(const uint8_t *__restrict__ s, const
         }
       }
       Pr[k] = r;
+      T rs = r;  // the decompressed word as stored and checked
+      if (MODE == kDFaults && lf.wave) {
+        if (v && lf.p == prow + k) {
+          rs = word_xor(r, lf.half, lf.m);
+          count(w.cnt, C_INJ + SDCSZ_T_RECON);
+        }
+      }
+      rv[k] = rs;
       cprev = r;
-      if (v) sum += Wd<T>::sum(r);
+      if (v) sum += Wd<T>::sum(rs);
     }
     if constexpr (REG) {
       T *row = region_row(out, reg, bx.o[0], bx.o[1] + (uint64_t)j);
@@ -424,7 +484,7 @@ __device__ __forceinline__ void decode_rows(const uint8_t *__restrict__ s, const
 #pragma unroll
         for (int k = 0; k < B2; k++) {
           const uint64_t x = bx.o[2] + (uint64_t)k;
-          if ((uint32_t)k < n2 && x >= reg.lo[2] && x < reg.hi[2]) row[x - reg.lo[2]] = Pr[k];
+          if ((uint32_t)k < n2 && x >= reg.lo[2] && x < reg.hi[2]) row[x - reg.lo[2]] = rv[k];
         }
       }
     } else {
@@ -433,39 +493,31 @@ __device__ __forceinline__ void decode_rows(const uint8_t *__restrict__ s, const
       char *dst = wbase + (loff + (uint32_t)j * RSB);
 #pragma unroll
       for (int k = 0; k < B2; k++)
-        if (FULL || (uint32_t)k < n2) *(T *)(dst + k * sizeof(T)) = Pr[k];
+        if (FULL || (uint32_t)k < n2) *(T *)(dst + k * sizeof(T)) = rv[k];
     }
     drow_fence(sum, br.lp);
   }
   if (used_out != nout || br.pos > nw * 32u) bad = true;
-  const uint64_t *sumdc = (const uint64_t *)(s + h.off_sumdc);
-  uint64_t why = 0;
-  if (bad) why = 2;
-  else if (h.abft && sum != sumdc[blk]) {
-    why = 1;
-    count(w.cnt, C_DET + SDCSZ_T_RECON);
+  res.bad = bad;
+  res.sum = sum;
+  if (MODE != kDRedo) {
+    const uint64_t *sumdc = (const uint64_t *)(s + h.off_sumdc);
+    uint64_t why = 0;
+    if (bad) why = 2;
+    else if (h.abft && sum != sumdc[blk]) {
+      why = 1;
+      count(w.cnt, C_DET + SDCSZ_T_RECON);
+    }
+    if (__builtin_expect(why != 0, 0)) {
+      const uint32_t slot = atomicAdd(w.redo_n, 1u);
+      if (slot < kMaxRedo) w.redo[slot] = blk | (why << 56);
+    }
   }
-  if (__builtin_expect(why != 0, 0)) {
-    const uint32_t slot = atomicAdd(w.redo_n, 1u);
-    if (slot < kMaxRedo) w.redo[slot] = blk | (why << 56);
-  }
+  return res;
 }
 
-// Work-groups [0, L.full_wgs) take full blocks, the rest the partial shell.
-template <typename T, int ND, int B0, int B1, int B2, bool WIDE>
-__global__ void __launch_bounds__(kDecThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
-k_decode_fast(JobTab tab) {
-  const JobWg jw = job_of(tab);
-  const uint8_t *__restrict__ s = jw.J->src;
-  const Header h = jw.J->h;
-  const Geo g = jw.J->g;
-  const DecWork w = jw.J->dw;
-  const PlanDev plan = jw.J->plan;
-  T *out = (T *)jw.J->dst;
-  const Launch L = jw.J->L;
-  if (*w.err) return;  // invalid codebook or block table: nothing is read
-  __shared__ DecLds tl;
-  __shared__ uint32_t win[kWin * kDecThreads];
+// The decoding tables in LDS (every thread of the work-group takes part).
+__device__ inline void load_tables(DecLds &tl, const DecWork &w, const Header &h) {
   for (uint32_t t = threadIdx.x; t < (1u << kLutBits); t += blockDim.x) tl.lut[t] = w.lut[t];
   if (threadIdx.x < kMaxLen + 2) {
     tl.first[threadIdx.x] = w.tab->first[threadIdx.x];
@@ -481,41 +533,132 @@ k_decode_fast(JobTab tab) {
     tl.long_n = ln;
   }
   __syncthreads();
+}
+
+// Work-groups [0, L.full_wgs) take full blocks, the rest the partial shell.
+// FAULTS: the instantiation that applies the plan's RECON flips.
+template <typename T, int ND, int B0, int B1, int B2, bool WIDE, bool FAULTS>
+__global__ void __launch_bounds__(kDecThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
+k_decode_fast(JobTab tab) {
+  const JobWg jw = job_of(tab);
+  const uint8_t *__restrict__ s = jw.J->src;
+  const Header h = jw.J->h;
+  const Geo g = jw.J->g;
+  const DecWork w = jw.J->dw;
+  const PlanDev plan = jw.J->plan;
+  T *out = (T *)jw.J->dst;
+  const Launch L = jw.J->L;
+  if (*w.err) return;  // invalid codebook or block table: nothing is read
+  __shared__ DecLds tl;
+  __shared__ uint32_t win[kWin * kDecThreads];
+  load_tables(tl, w, h);
+  constexpr int M = FAULTS ? kDFaults : kDProd;
   const Region &reg = jw.J->reg, &rb = jw.J->rblk;
   if (jw.J->mode == 2) {
     // region decompression: one lane per block of the box of blocks the
     // region touches (L.shell_count of them), each storing only its part of
     // the region, at region-relative offsets
     const uint64_t idx = (uint64_t)jw.b * blockDim.x + threadIdx.x;
+    const bool act = idx < L.shell_count;
+    const uint64_t blk = rmap_block(g, rb, act ? idx : L.shell_count - 1);
     if constexpr (ND == 2)
-      decode_rows<T, B1, B2, false, true, WIDE>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx, L.shell_count, reg, rb);
+      decode_rows<T, B1, B2, false, true, WIDE, M>(s, h, g, w, plan, out, tl, win + threadIdx.x, blk, act, reg);
     else
-      decode_lanes<T, ND, B0, B1, B2, false, true, WIDE>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx,
-                                                   L.shell_count, reg, rb);
+      decode_lanes<T, ND, B0, B1, B2, false, true, WIDE, M>(s, h, g, w, plan, out, tl, win + threadIdx.x, blk, act,
+                                                            reg);
     return;
   }
   const bool full = jw.b < L.full_wgs;
   const uint64_t idx = (uint64_t)(full ? jw.b : jw.b - L.full_wgs) * blockDim.x + threadIdx.x;
+  const uint64_t nl = full ? L.full_count : L.shell_count;
+  const bool act = idx < nl;
+  const uint64_t blk = dmap_block(g, L, full ? 0u : 1u, act ? idx : nl - 1);
   if constexpr (ND == 2) {
     static_assert(B0 == 1, "2D blocks have one plane");
     if (full)
-      decode_rows<T, B1, B2, true, false, WIDE>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx, L.full_count, reg, rb);
+      decode_rows<T, B1, B2, true, false, WIDE, M>(s, h, g, w, plan, out, tl, win + threadIdx.x, blk, act, reg);
     else
-      decode_rows<T, B1, B2, false, false, WIDE>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx, L.shell_count, reg,
-                                           rb);
+      decode_rows<T, B1, B2, false, false, WIDE, M>(s, h, g, w, plan, out, tl, win + threadIdx.x, blk, act, reg);
   } else {
     if (full)
-      decode_lanes<T, ND, B0, B1, B2, true, false, WIDE>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx, L.full_count,
-                                                   reg, rb);
+      decode_lanes<T, ND, B0, B1, B2, true, false, WIDE, M>(s, h, g, w, plan, out, tl, win + threadIdx.x, blk, act,
+                                                            reg);
     else
-      decode_lanes<T, ND, B0, B1, B2, false, false, WIDE>(s, h, g, w, plan, out, L, tl, win + threadIdx.x, idx,
-                                                    L.shell_count, reg, rb);
+      decode_lanes<T, ND, B0, B1, B2, false, false, WIDE, M>(s, h, g, w, plan, out, tl, win + threadIdx.x, blk, act,
+                                                             reg);
   }
 }
 
-#define SDCSZ_INST_DEC(T, ND, B0, B1, B2)                                    \
-  template __global__ void k_decode_fast<T, ND, B0, B1, B2, false>(JobTab); \
-  template __global__ void k_decode_fast<T, ND, B0, B1, B2, true>(JobTab);
+// Zeros over a block (the part inside the region for region decompression).
+template <typename T>
+__device__ void zero_block(const Geo &g, const Box &b, T *out, bool region, const Region &reg) {
+  for (uint32_t i = 0; i < b.n[0]; i++)
+    for (uint32_t j = 0; j < b.n[1]; j++)
+      for (uint32_t k = 0; k < b.n[2]; k++) {
+        if (region) {
+          const uint64_t z = b.o[0] + i, y = b.o[1] + j, x = b.o[2] + k;
+          if (z < reg.lo[0] || z >= reg.hi[0] || y < reg.lo[1] || y >= reg.hi[1] || x < reg.lo[2] || x >= reg.hi[2])
+            continue;
+          out[((z - reg.lo[0]) * (reg.hi[1] - reg.lo[1]) + (y - reg.lo[1])) * (reg.hi[2] - reg.lo[2]) +
+              (x - reg.lo[2])] = (T)0;
+        } else {
+          out[fidx(g, b, i, j, k)] = (T)0;
+        }
+      }
+}
+
+// Re-execution of the blocks the decoder queued (Algorithm 2's second
+// attempt), one lane per queue entry with the same per-lane routine: a
+// checksum mismatch is decoded again from the compressed bytes and stored;
+// the block is corrected when the new checksum equals sum_dc, else
+// uncorrectable.  A block that could not be decoded is zeroed and counted
+// uncorrectable without a second attempt (decoding is deterministic).
+// Lanes address their blocks from per-lane bases (the wide form), which
+// serves every field size.  REG: region decompression.
+template <typename T, int ND, int B0, int B1, int B2, bool REG>
+__global__ void __launch_bounds__(64) k_decode_redo(JobTab tab) {
+  const JobWg jw = job_of(tab);
+  const uint8_t *__restrict__ s = jw.J->src;
+  const Header h = jw.J->h;
+  const Geo g = jw.J->g;
+  const DecWork w = jw.J->dw;
+  const PlanDev plan = jw.J->plan;
+  T *out = (T *)jw.J->dst;
+  if (*w.err) return;
+  const uint32_t n = min(*w.redo_n, kMaxRedo);
+  if (jw.b * blockDim.x >= n) return;  // the whole work-group has no entry
+  __shared__ DecLds tl;
+  __shared__ uint32_t win[kWin * kDecThreads];
+  load_tables(tl, w, h);
+  const Region &reg = jw.J->reg;
+  const uint64_t *sumdc = (const uint64_t *)(s + h.off_sumdc);
+  for (uint32_t base = jw.b * blockDim.x; base < n; base += jw.nb * blockDim.x) {
+    const uint32_t e = base + threadIdx.x;
+    const bool act = e < n;
+    const uint64_t ent = w.redo[act ? e : n - 1];
+    const uint64_t blk = ent & ((1ull << 56) - 1), why = ent >> 56;
+    const bool run = act && why == 1;
+    if (act && why != 1) {
+      zero_block<T>(g, box_of(g, blk), out, REG, reg);
+      count(w.cnt, C_UNC + SDCSZ_T_RECON);
+    }
+    DecOut o;
+    if constexpr (ND == 2)
+      o = decode_rows<T, B1, B2, false, REG, true, kDRedo>(s, h, g, w, plan, out, tl, win + threadIdx.x, blk, run,
+                                                           reg);
+    else
+      o = decode_lanes<T, ND, B0, B1, B2, false, REG, true, kDRedo>(s, h, g, w, plan, out, tl, win + threadIdx.x, blk,
+                                                                    run, reg);
+    if (run) count(w.cnt, (!o.bad && o.sum == sumdc[blk] ? C_COR : C_UNC) + SDCSZ_T_RECON);
+  }
+}
+
+#define SDCSZ_INST_DEC(T, ND, B0, B1, B2)                                           \
+  template __global__ void k_decode_fast<T, ND, B0, B1, B2, false, false>(JobTab); \
+  template __global__ void k_decode_fast<T, ND, B0, B1, B2, true, false>(JobTab);  \
+  template __global__ void k_decode_fast<T, ND, B0, B1, B2, false, true>(JobTab);  \
+  template __global__ void k_decode_redo<T, ND, B0, B1, B2, false>(JobTab);        \
+  template __global__ void k_decode_redo<T, ND, B0, B1, B2, true>(JobTab);
 SDCSZ_INST_DEC(float, 3, 6, 6, 6)
 SDCSZ_INST_DEC(double, 3, 6, 6, 6)
 SDCSZ_INST_DEC(float, 2, 1, 16, 16)

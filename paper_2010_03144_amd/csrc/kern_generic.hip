@@ -83,13 +83,11 @@ __device__ bool decode_block_generic(const uint8_t *__restrict__ s, const Header
 // One thread per block: decode, store, then the checksum half of Algorithm 2
 // with re-execution.  mode 0: full decompression into `out` (field layout);
 // mode 1: verify the caller's `out` (decode only on mismatch); mode 2: region
-// [lo, hi) into `out` laid out over the region.  The block's values are
-// staged in slot `slot` of the recon scratch (the block id for kernels over
-// the whole field, the queue entry for re-execution).
+// [lo, hi) into `out` laid out over the region.
 template <typename T>
 __device__ __noinline__ void decode_one(const uint8_t *__restrict__ s, const Header &h, const Geo &g,
                                         const DecWork &w, const PlanDev &plan, T *out, uint32_t mode,
-                                        const Region &reg, uint64_t blk, uint64_t slot) {
+                                        const Region &reg, uint64_t blk) {
   const Box b = box_of(g, blk);
   if (mode == 2) {
     for (int a = 0; a < 3; a++)
@@ -97,7 +95,7 @@ __device__ __noinline__ void decode_one(const uint8_t *__restrict__ s, const Hea
   }
   const DecTab tab = *w.tab;
   const T q = (T)(2.0 * h.eb_abs);
-  const Slot<T> rec = slot_of<T>(w.recon, slot, g.bpts);
+  const Slot<T> rec = slot_of<T>(w.recon, blk, g.bpts);
   auto store = [&]() {
     for (uint32_t i = 0, p = 0; i < b.n[0]; i++)
       for (uint32_t j = 0; j < b.n[1]; j++)
@@ -191,7 +189,7 @@ template <typename T> __global__ void __launch_bounds__(64) k_decode_generic(Job
   const Job &J = *jw.J;
   if (*J.dw.err) return;  // invalid codebook or block table: nothing is read
   const uint64_t blk = (uint64_t)jw.b * blockDim.x + threadIdx.x;
-  if (blk < J.g.n_blocks) decode_one<T>(J.src, J.h, J.g, J.dw, J.plan, (T *)J.dst, J.mode, J.reg, blk, blk);
+  if (blk < J.g.n_blocks) decode_one<T>(J.src, J.h, J.g, J.dw, J.plan, (T *)J.dst, J.mode, J.reg, blk);
 }
 
 // full decompression of listed blocks (the blocks a fault plan names)
@@ -202,63 +200,9 @@ k_decode_list(const uint8_t *__restrict__ s, Header h, Geo g, DecWork w, PlanDev
   if (*w.err) return;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   Region reg{};
-  if (t < n) decode_one<T>(s, h, g, w, plan, out, 0, reg, list[t], list[t]);
-}
-
-// Blocks the specialised decoder queued: a checksum mismatch (already counted
-// as detected) is re-executed from the compressed bytes; a block that could
-// not be decoded is decoded once more and, failing again, zeroed; a block
-// with a symbol beyond the specialised decoder's tables runs the whole
-// per-block procedure here.  One thread per queue entry.
-template <typename T> __global__ void __launch_bounds__(64) k_decode_redo(JobTab jt) {
-  const JobWg jw = job_of(jt);
-  const uint8_t *__restrict__ s = jw.J->src;
-  const Header h = jw.J->h;
-  const Geo g = jw.J->g;
-  const DecWork w = jw.J->dw;
-  T *out = (T *)jw.J->dst;
-  if (*w.err) return;
-  const uint32_t n = min(*w.redo_n, kMaxRedo);
-  const uint32_t mode = jw.J->mode == 2 ? 2u : 0u;  // the fast decoder runs full (0) or region (2) decompression
-  const DecTab tab = *w.tab;
-  const T q = (T)(2.0 * h.eb_abs);
-  const uint64_t *sumdc = (const uint64_t *)(s + h.off_sumdc);
-  for (uint32_t e = jw.b * blockDim.x + threadIdx.x; e < n; e += jw.nb * blockDim.x) {
-    const uint64_t blk = w.redo[e] & ((1ull << 56) - 1), why = w.redo[e] >> 56;
-    if (why == 3) {
-      const PlanDev none{nullptr, 0, nullptr};
-      decode_one<T>(s, h, g, w, none, out, mode, jw.J->reg, blk, e);
-      continue;
-    }
-    const Box b = box_of(g, blk);
-    const Slot<T> rec = slot_of<T>(w.recon, e, g.bpts);  // one slot per queue entry
-    bool ok = decode_block_generic<T>(s, h, g, b, blk, w, tab, q, rec);
-    if (ok && h.abft) {
-      uint64_t sum = 0;
-      for (uint32_t p = 0; p < b.pts; p++) sum += Wd<T>::sum(rec[p]);
-      ok = sum == sumdc[blk];
-    }
-    if (!ok)
-      for (uint32_t p = 0; p < b.pts; p++) rec[p] = (T)0;
-    if (ok || why == 2) {
-      const Region &reg = jw.J->reg;
-      for (uint32_t i = 0, p = 0; i < b.n[0]; i++)
-        for (uint32_t j = 0; j < b.n[1]; j++)
-          for (uint32_t k = 0; k < b.n[2]; k++, p++) {
-            if (mode == 2) {  // region decompression: region-relative, inside the region only
-              const uint64_t z = b.o[0] + i, y = b.o[1] + j, x = b.o[2] + k;
-              if (z < reg.lo[0] || z >= reg.hi[0] || y < reg.lo[1] || y >= reg.hi[1] || x < reg.lo[2] ||
-                  x >= reg.hi[2])
-                continue;
-              out[((z - reg.lo[0]) * (reg.hi[1] - reg.lo[1]) + (y - reg.lo[1])) * (reg.hi[2] - reg.lo[2]) +
-                  (x - reg.lo[2])] = rec[p];
-            } else {
-              out[fidx(g, b, i, j, k)] = rec[p];
-            }
-          }
-    }
-    if (ok) count(w.cnt, C_COR + SDCSZ_T_RECON);
-    else count(w.cnt, C_UNC + SDCSZ_T_RECON);
+  if (t < n) {
+    decode_one<T>(s, h, g, w, plan, out, 0, reg, list[t]);
+    count(w.cnt, C_LIST);
   }
 }
 
@@ -266,7 +210,5 @@ template __global__ void k_decode_generic<float>(JobTab);
 template __global__ void k_decode_generic<double>(JobTab);
 template __global__ void k_decode_list<float>(const uint8_t *, Header, Geo, DecWork, PlanDev, float *, const uint64_t *, uint32_t);
 template __global__ void k_decode_list<double>(const uint8_t *, Header, Geo, DecWork, PlanDev, double *, const uint64_t *, uint32_t);
-template __global__ void k_decode_redo<float>(JobTab);
-template __global__ void k_decode_redo<double>(JobTab);
 
 }  // namespace sdcsz

@@ -59,7 +59,8 @@ class Report(C.Structure):
                 ("detected", C.c_uint64 * len(TARGETS)), ("corrected", C.c_uint64 * len(TARGETS)),
                 ("uncorrectable", C.c_uint64 * len(TARGETS)), ("n_outliers", C.c_uint64),
                 ("n_regression", C.c_uint64), ("payload_words", C.c_uint64),
-                ("stream_size", C.c_uint64), ("eb_abs", C.c_double)]
+                ("stream_size", C.c_uint64), ("eb_abs", C.c_double),
+                ("generic_plan_blocks", C.c_uint64)]
 
 
 class CompItem(C.Structure):
@@ -126,7 +127,8 @@ def lib():
 def report_dict(r):
     inj, det, cor, unc = r.injected[:], r.detected[:], r.corrected[:], r.uncorrectable[:]
     d = {"n_blocks": r.n_blocks, "n_outliers": r.n_outliers, "n_regression": r.n_regression,
-         "payload_words": r.payload_words, "stream_size": r.stream_size, "eb_abs": r.eb_abs}
+         "payload_words": r.payload_words, "stream_size": r.stream_size, "eb_abs": r.eb_abs,
+         "generic_plan_blocks": r.generic_plan_blocks}
     for i, t in enumerate(TARGETS):
         d[t] = {"injected": inj[i], "detected": det[i], "corrected": cor[i], "uncorrectable": unc[i]}
     return d

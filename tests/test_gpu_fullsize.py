@@ -68,6 +68,7 @@ def test_full_field_fault_injection_matches_oracle(codec, field):
     rc_r, s_r, rep_r = ref.compress(x, BLOCK, 1e-4, faults=plan)
     assert rc_r == rc_g == 0
     counts_equal(rep_r, rep_g)
+    assert rep_g["generic_plan_blocks"] == 0  # the specialised kernels apply every flip
     for t in ("input", "coef", "code"):
         assert rep_g[t]["injected"] == rep_g[t]["corrected"] == 6, (t, rep_g[t])
     s_g_host = s_g.cpu().numpy()
@@ -85,6 +86,7 @@ def test_full_field_fault_injection_matches_oracle(codec, field):
     assert rc_r == rc_g == 0
     counts_equal(rep_dr, rep_dg)
     assert rep_dg["recon"]["detected"] == rep_dg["recon"]["corrected"] == 6
+    assert rep_dg["generic_plan_blocks"] == 0
     assert np.array_equal(y_r.view(np.uint32), y_g.cpu().numpy().view(np.uint32))
 
 

@@ -90,12 +90,14 @@ def test_2d_fault_counts_match_oracle(codec, dtype):
     (rc_r, s_r, rep_r), (rc_g, s_g, rep_g) = both(codec, x, block, 1e-4, faults=plan)
     assert rc_r == rc_g == 0, (rc_r, rc_g)
     same_counts(rep_r, rep_g)
+    assert rep_g["generic_plan_blocks"] == 0  # every flip applied by the specialised kernels
     assert np.array_equal(s_r, s_g), first_difference(s_r, s_g)
     rplan = synth.fault_plan(shape, block, dtype, {"recon": 9}, seed=42)
     rc_r, y_r, rep_dr = ref.decompress(s_r, faults=rplan)
     rc_g, y_g, rep_dg = codec.decompress(torch.from_numpy(s_g).cuda(), faults=rplan)
     assert rc_r == rc_g == 0
     same_counts(rep_dr, rep_dg)
+    assert rep_dg["generic_plan_blocks"] == 0
     assert rep_dg["recon"]["detected"] == rep_dg["recon"]["corrected"] == 9
     assert np.array_equal(y_r.view(np.uint8), y_g.cpu().numpy().view(np.uint8))
 
@@ -158,8 +160,50 @@ def test_compression_fault_counts_match_oracle(codec, dtype):
         (rc_r, s_r, rep_r), (rc_g, s_g, rep_g) = both(codec, x, block, 1e-4, abft=abft, faults=plan)
         assert rc_r == rc_g, (rc_r, rc_g)
         same_counts(rep_r, rep_g)
+        assert rep_g["generic_plan_blocks"] == 0  # every flip applied by the specialised kernels
         if rc_r == 0:
             assert np.array_equal(s_r, s_g), first_difference(s_r, s_g)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("shape,block", [((48, 42, 36), (6, 6, 6)), ((400, 390), (16, 16))])
+def test_several_flips_in_one_block_match_oracle(codec, dtype, shape, block):
+    # input, coefficient and prediction flips together, or coefficient and
+    # reconstruction flips together, stay on the specialised kernels; two of
+    # a kind, or a reconstruction flip after an input flip, send the block to
+    # the generic routine
+    x = synth.grf_field(shape, seed=16, dtype=dtype)
+    per = 1 if dtype == np.float32 else 2
+    bits = 32 * per
+    rows = [(0, 30, 3, 7), (1, 29, 3, 2), (4, bits - 2, 3, 11),  # block 3: INPUT, COEF, DUP_PRED
+            (1, 31, 5, 3), (5, 20, 5, 40),                      # block 5: COEF, DUP_RECON
+            (0, 31, 9, 5), (0, 4, 9, 60),                       # block 9: two INPUT
+            (4, 3, 12, 0), (4, bits - 1, 12, 1),                # block 12: two DUP_PRED
+            (0, 27, 14, 9), (5, 6, 14, 30),                     # block 14: INPUT, DUP_RECON
+            (2, 9, 20, 4), (2, 3, 20, 5)]                       # block 20: two CODE
+    plan = np.array(sorted(rows, key=lambda r: r[2]), dtype=np.int64)
+    for abft in (True, False):
+        (rc_r, s_r, rep_r), (rc_g, s_g, rep_g) = both(codec, x, block, 1e-3, abft=abft, faults=plan)
+        assert rc_r == rc_g, (rc_r, rc_g)
+        same_counts(rep_r, rep_g)
+        assert rep_g["generic_plan_blocks"] == 3
+        if rc_r == 0:
+            assert np.array_equal(s_r, s_g), first_difference(s_r, s_g)
+
+
+def test_reexecution_queue_overflow_is_an_error(codec):
+    # 5,000 blocks whose duplicated predictions disagree: the oracle corrects
+    # them all, the library queues at most 4,096 re-executions and reports
+    # the call as uncorrectable instead of keeping the others' results
+    shape, block = (108, 108, 108), (6, 6, 6)
+    x = synth.grf_field(shape, seed=17)
+    plan = synth.fault_plan(shape, block, np.float32, {"dup_pred": 5000}, seed=18)
+    rc, _, rep = codec.compress(torch.from_numpy(x).cuda(), block, 1e-3, faults=plan)
+    assert rc == sdcsz.ESDC
+    assert rep["dup_pred"]["detected"] == 5000
+    rc, _, _ = codec.compress(torch.from_numpy(x).cuda(), block, 1e-3,
+                              faults=synth.fault_plan(shape, block, np.float32, {"dup_pred": 4000}, seed=18))
+    assert rc == sdcsz.OK
 
 
 def test_decompression_faults_and_verify(codec):
@@ -172,6 +216,7 @@ def test_decompression_faults_and_verify(codec):
     rc_g, y_g, rep_g = codec.decompress(sd, faults=plan)
     assert rc_r == rc_g == 0
     same_counts(rep_r, rep_g)
+    assert rep_g["generic_plan_blocks"] == 0
     assert np.array_equal(y_r.view(np.uint32), y_g.cpu().numpy().view(np.uint32))
     z = y_g.clone()
     rc_v, rep_v = codec.verify(sd, z, faults=plan)
@@ -481,6 +526,7 @@ def test_preparation_fault_counts_and_streams_match_oracle(codec, dtype, shape, 
         (rc_r, s_r, rep_r), (rc_g, s_g, rep_g) = both(codec, x, block, 1e-3, abft=abft, faults=plan)
         assert rc_r == rc_g, (rc_r, rc_g)
         same_counts(rep_r, rep_g)
+        assert rep_g["generic_plan_blocks"] == 18  # the preparation errors; INPUT and COEF stay specialised
         if rc_r == 0:
             assert np.array_equal(s_r, s_g), first_difference(s_r, s_g)
 
