@@ -208,6 +208,44 @@ def block_size_report(codec, xd, ebs=(1e-2, 1e-3, 1e-4)):
             "autotuned_block": picks}
 
 
+def shape_speed_report(codec, torch, xd, eb=1e-3, blocks=((4, 4, 4), (8, 8, 8), (10, 10, 10), (16, 16, 16)),
+                       reps=3):
+    """Speed of the whole field at block shapes without a lane-per-block
+    kernel (Sec. 6.2 settles on 10x10x10): compress and decompress ms (median
+    of reps after a warm-up), CR, and the device time of the prediction and
+    decoding phases."""
+    from paper_2010_03144_amd import sdcsz
+    sync = torch.cuda.synchronize
+    out = {}
+    for blk in blocks:
+        rc, s, _ = codec.compress(xd, blk, eb)
+        assert rc == 0, rc
+        s = s.clone()
+        rc, y, _ = codec.decompress(s)
+        assert rc == 0, rc
+        tc, td = [], []
+        sdcsz.timing_enable(True)
+        for _ in range(reps):
+            sync()
+            t0 = time.perf_counter()
+            rc, s2, _ = codec.compress(xd, blk, eb)
+            sync()
+            tc.append(time.perf_counter() - t0)
+            assert rc == 0 and torch.equal(s2, s)
+            t0 = time.perf_counter()
+            rc, y2, _ = codec.decompress(s)
+            sync()
+            td.append(time.perf_counter() - t0)
+        ph = sdcsz.timing_read()
+        sdcsz.timing_enable(False)
+        out["x".join(map(str, blk))] = {
+            "compress_ms": round(float(np.median(tc)) * 1e3, 3), "decompress_ms": round(float(np.median(td)) * 1e3, 3),
+            "cr": round(xd.numel() * xd.element_size() / s.numel(), 4),
+            "predict_quantize_device_ms": round(ph["predict_quantize"][0] / reps, 3),
+            "decode_device_ms": round(ph["decode"][0] / reps, 3)}
+    return {"workload": f"512^3 FP32 field, eb {eb:g} REL, ABFT on", "blocks": out}
+
+
 def region_report(codec, torch, xd, block, eb=1e-3, edges=(32, 64, 128, 256, 512), reps=5):
     """Random-access decompression (Sec. 5.1): time to decompress a centred
     cube of each edge out of the stream of the whole field, against full
@@ -501,7 +539,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed 192-field batch")
-    ap.add_argument("--only", choices=["batch", "serve", "region", "faults"], help="run one part alone and print its JSON")
+    ap.add_argument("--only", choices=["batch", "serve", "region", "faults", "shapes"],
+                    help="run one part alone and print its JSON")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--tune-file", help="load launch shapes from this JSON file instead of autotuning")
     ap.add_argument("--save-tune", help="write the autotuned launch shapes to this JSON file")
@@ -541,7 +580,7 @@ def main():
         print(json.dumps(batch_bench(sdcsz.Codec("cuda:0"), torch, plain_loop=not args.batch_only_batched)),
               flush=True)
         return
-    if args.only in ("serve", "region", "faults"):
+    if args.only in ("serve", "region", "faults", "shapes"):
         log("generating 512^3 FP32 field")
         x = synth.grf_field((512, 512, 512), seed=2)
         xd = torch.from_numpy(x).cuda()
@@ -549,6 +588,8 @@ def main():
             print(json.dumps(serve_bench(torch, xd, args.serve_seconds)), flush=True)
         elif args.only == "region":
             print(json.dumps(region_report(sdcsz.Codec("cuda:0"), torch, xd, (6, 6, 6))), flush=True)
+        elif args.only == "shapes":
+            print(json.dumps(shape_speed_report(sdcsz.Codec("cuda:0"), torch, xd)), flush=True)
         else:
             print(json.dumps(fault_report(sdcsz.Codec("cuda:0"), torch, x, xd, (6, 6, 6))), flush=True)
         return
@@ -653,6 +694,8 @@ def main():
         result["region"] = region_report(codec, torch, xd, block)
         log("block-size rate-distortion")
         result["block_size"] = block_size_report(codec, xd)
+        log("block shapes without a lane-per-block kernel")
+        result["block_shape_speed"] = shape_speed_report(codec, torch, xd)
 
     if not args.no_batch and not args.copy_probe:
         result["batch"] = batch_bench(codec, torch)

@@ -64,14 +64,17 @@ template <typename T> struct RegTab {
   T c[8][3];     // (n_a - 1) / 2
 };
 
-// Fault plan on the device: entries sorted by block, one bit per block with
-// entries (bits), and one per block that the generic per-block routine takes
-// instead of the specialised kernels (gen; null when there is none).
+// Fault plan on the device: entries sorted by block and one bit per block
+// with entries (bits).  On a field of the lane-per-block kernels, list holds
+// the plan blocks the wave-per-block routine takes and flist those the
+// lane-per-block kernels' fault-applying instantiation takes (both
+// ascending); the production instantiation leaves every plan block.
 struct PlanDev {
   const sdcsz_fault *f;
   uint32_t n;
   const uint32_t *bits;
-  const uint32_t *gen;
+  const uint64_t *list, *flist;
+  uint32_t nlist, nflist;
 };
 
 // Per-call device areas of compression (inside the caller's workspace).

@@ -94,10 +94,6 @@ __device__ inline bool plan_hit(const PlanDev &P, uint64_t blk) {
   return P.n != 0 && ((P.bits[blk >> 5] >> (blk & 31)) & 1u);
 }
 
-__device__ inline bool plan_gen(const PlanDev &P, uint64_t blk) {
-  return P.gen != nullptr && ((P.gen[blk >> 5] >> (blk & 31)) & 1u);
-}
-
 // index of the first plan entry of block blk (entries sorted by block)
 __device__ inline uint32_t plan_first(const PlanDev &P, uint64_t blk) {
   uint32_t lo = 0, hi = P.n;

@@ -234,10 +234,14 @@ template <typename T> RegTab<T> reg_table(const Geo &g) {
 // per-field workspace layouts
 // ---------------------------------------------------------------------------
 struct CompLayout {
-  uint64_t cnt, res, redo_n, hist, enc, zero_end;
+  uint64_t cnt, res, redo_n, hist, enc, zero_end, bits, bits_end;
   uint64_t eb, range, codes, vals, recon, meta, words, coef, sum_dc, sum_q, isum_q;
-  uint64_t off_pay, off_out, off_coef, scan, tot, plan, bits, gen, redo, plan_blocks, hdr, total;
+  uint64_t off_pay, off_out, off_coef, scan, tot, plan, redo, hdr, total;
 };
+
+// A fault plan's device area: the entries, then the blocks of the wave
+// routine's list and of the fault-applying instantiation's list (one copy).
+uint64_t plan_bytes(uint32_t nfaults) { return (sizeof(sdcsz_fault) + 16ull) * std::max<uint32_t>(nfaults, 1); }
 
 CompLayout comp_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
   CompLayout L;
@@ -259,6 +263,8 @@ CompLayout comp_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
   L.hist = take(4 * 65536);
   L.enc = take(4 * 65536);
   L.zero_end = at;
+  L.bits = take(4 * (nb / 32 + 1));  // a plan's blocks: cleared too when there is a plan
+  L.bits_end = at;
   L.eb = take(sizeof(EbDev));
   L.range = take(16ull * kRangeBlocks);
   L.codes = take(2ull * 256 * g.groups * ((nb + 63) / 64));
@@ -275,19 +281,16 @@ CompLayout comp_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
   L.off_coef = take(4 * (nb + 1));
   L.scan = take(24 * chunks);
   L.tot = take(24);
-  L.plan = take(sizeof(sdcsz_fault) * (uint64_t)std::max<uint32_t>(nfaults, 1));
-  L.bits = take(4 * (nb / 32 + 1));
-  L.gen = take(4 * (nb / 32 + 1));
+  L.plan = take(plan_bytes(nfaults));
   L.redo = take(24ull * kMaxRedo);  // block | reason, first-pass checksums
-  L.plan_blocks = take(8ull * std::max<uint32_t>(nfaults, 1));
   L.hdr = take(sizeof(Header));
   L.total = at;
   return L;
 }
 
 struct DecLayout {
-  uint64_t cnt, redo_n, err, zero_end;
-  uint64_t symbols, tab, recon, off_pay, off_out, off_coef, scan, tot, plan, bits, gen, lut, redo, plan_blocks;
+  uint64_t cnt, redo_n, err, zero_end, bits, bits_end;
+  uint64_t symbols, tab, recon, off_pay, off_out, off_coef, scan, tot, plan, lut, redo;
   uint64_t total;
 };
 
@@ -311,6 +314,8 @@ DecLayout dec_layout(const Geo &g, uint32_t dtype, uint32_t nfaults, bool small_
   L.redo_n = L.cnt + 8 * C_N;
   L.err = L.redo_n + 4;
   L.zero_end = at;
+  L.bits = take(4 * (nb / 32 + 1));  // a plan's blocks: cleared too when there is a plan
+  L.bits_end = at;
   L.symbols = take(2 * 65536);
   L.tab = take(sizeof(DecTab));
   L.recon = take(vb * slots * g.bpts);  // interleaved across 64 slots
@@ -319,12 +324,9 @@ DecLayout dec_layout(const Geo &g, uint32_t dtype, uint32_t nfaults, bool small_
   L.off_coef = take(4 * (nb + 1));
   L.scan = take(24 * chunks);
   L.tot = take(24);
-  L.plan = take(sizeof(sdcsz_fault) * (uint64_t)std::max<uint32_t>(nfaults, 1));
-  L.bits = take(4 * (nb / 32 + 1));
-  L.gen = take(4 * (nb / 32 + 1));
+  L.plan = take(plan_bytes(nfaults));
   L.lut = take(4ull << kLutBits);
   L.redo = take(8ull * kMaxRedo);
-  L.plan_blocks = take(8ull * std::max<uint32_t>(nfaults, 1));
   L.total = at;
   return L;
 }
@@ -363,9 +365,6 @@ const JobKernel kCompFast[kClasses][2][2][3] = {
     {{SDCSZ_CF(float, 2, 1, 16, 16, false), SDCSZ_CF(float, 2, 1, 16, 16, true)},
      {SDCSZ_CF(double, 2, 1, 16, 16, false), SDCSZ_CF(double, 2, 1, 16, 16, true)}}};
 #undef SDCSZ_CF
-// [class][dtype]
-const JobKernel kRedoFast[kClasses][2] = {{k_redo<float, 3, 6, 6, 6>, k_redo<double, 3, 6, 6, 6>},
-                                          {k_redo<float, 2, 1, 16, 16>, k_redo<double, 2, 1, 16, 16>}};
 const JobKernel kCheckFast[kClasses] = {k_check_fast<3, 6, 6, 6>, k_check_fast<2, 1, 16, 16>};
 // [class][dtype]
 const JobKernel kEncFast[kClasses][2] = {{k_encode_fast<float, 3, 6, 6, 6>, k_encode_fast<double, 3, 6, 6, 6>},
@@ -380,12 +379,6 @@ const JobKernel kDecFast[kClasses][2][3] = {
       k_decode_fast<float, 2, 1, 16, 16, false, true>},
      {k_decode_fast<double, 2, 1, 16, 16, false, false>, k_decode_fast<double, 2, 1, 16, 16, true, false>,
       k_decode_fast<double, 2, 1, 16, 16, false, true>}}};
-// [class][dtype][region]
-const JobKernel kDecRedo[kClasses][2][2] = {
-    {{k_decode_redo<float, 3, 6, 6, 6, false>, k_decode_redo<float, 3, 6, 6, 6, true>},
-     {k_decode_redo<double, 3, 6, 6, 6, false>, k_decode_redo<double, 3, 6, 6, 6, true>}},
-    {{k_decode_redo<float, 2, 1, 16, 16, false>, k_decode_redo<float, 2, 1, 16, 16, true>},
-     {k_decode_redo<double, 2, 1, 16, 16, false>, k_decode_redo<double, 2, 1, 16, 16, true>}}};
 
 // Lanes per work-group (one block per lane) of the specialised kernels, by
 // stage, shape class and data type: the first entry whose max_blocks holds
@@ -457,6 +450,49 @@ struct Staging {
   }
 };
 thread_local Staging t_stage;
+
+// A second stream of the calling thread (default priority, made on first use
+// on a device and kept until the thread exits): a call's fault-plan work
+// runs there beside the main launch, between a fork and a join event.
+struct SideStream {
+  int dev = -1;
+  hipStream_t s = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  void drop() {
+    if (s) (void)hipStreamDestroy(s);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    if (join_ev) (void)hipEventDestroy(join_ev);
+    s = nullptr;
+    fork_ev = join_ev = nullptr;
+    dev = -1;
+  }
+  // the side stream, after the work queued so far on `main`; null on error
+  hipStream_t fork(hipStream_t main) {
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess) return nullptr;
+    if (d != dev) {
+      drop();
+      if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&join_ev, hipEventDisableTiming) != hipSuccess) {
+        drop();
+        return nullptr;
+      }
+      dev = d;
+    }
+    if (hipEventRecord(fork_ev, main) != hipSuccess || hipStreamWaitEvent(s, fork_ev, 0) != hipSuccess) return nullptr;
+    return s;
+  }
+  // `main` waits for the side stream's work
+  hipError_t join(hipStream_t main) {
+    hipError_t e = hipEventRecord(join_ev, s);
+    return e != hipSuccess ? e : hipStreamWaitEvent(main, join_ev, 0);
+  }
+  ~SideStream() { drop(); }
+};
+thread_local SideStream t_side;
+// calls that must not create resources run their plan work on the main stream
+thread_local bool t_no_side = false;
 // the staging of decompression calls: the thread's own, unless a call that
 // must not allocate has put a fixed buffer in its place
 thread_local Staging *t_stage_over = nullptr;
@@ -525,18 +561,22 @@ void fill_report(sdcsz_report *r, const uint64_t *cnt, uint64_t nb) {
   r->generic_plan_blocks = cnt[C_LIST];
 }
 
-// The blocks of a sorted plan that the generic per-block routine takes on a
-// field of the specialised kernels: all of them when the launch cannot apply
-// plans (faults_ok false: the wide instantiation), else those whose entries
-// the fault-applying instantiation does not model: errors of the prediction
+// The blocks of a sorted plan on a field of the lane-per-block kernels,
+// split between the wave-per-block routine (out) and the lane-per-block
+// kernels' fault-applying instantiation (fast).  The wave routine takes all
+// of them when the launch cannot apply plans (faults_ok false: the wide
+// instantiation), else those whose entries the fault-applying instantiation
+// does not model: errors of the prediction
 // preparation, more than one flip of a kind, or a flip of the duplicated
 // reconstruction together with an input or prediction flip (compression:
 // the specialised pass meets the reconstruction flip with the earlier error
 // still in its values, where the paper-order routine has corrected it, and
 // whether a reconstruction is computed at all depends on those values), more
 // than one RECON flip (decompression).
-std::vector<uint64_t> generic_blocks(const std::vector<sdcsz_fault> &plan, bool faults_ok, bool decomp) {
-  std::vector<uint64_t> out;
+void split_plan(const std::vector<sdcsz_fault> &plan, bool faults_ok, bool decomp, std::vector<uint64_t> &out,
+                std::vector<uint64_t> &fast) {
+  out.clear();
+  fast.clear();
   for (size_t i = 0; i < plan.size();) {
     size_t j = i;
     uint32_t cnt[SDCSZ_N_TARGETS] = {};
@@ -547,19 +587,28 @@ std::vector<uint64_t> generic_blocks(const std::vector<sdcsz_fault> &plan, bool 
       gen = gen || cnt[SDCSZ_T_PREP_INPUT] || cnt[SDCSZ_T_PREP_COEF] || cnt[SDCSZ_T_PREP_SAMPLE] ||
             cnt[SDCSZ_T_INPUT] > 1 || cnt[SDCSZ_T_COEF] > 1 || cnt[SDCSZ_T_DUP_PRED] > 1 ||
             cnt[SDCSZ_T_DUP_RECON] > 1 || (cnt[SDCSZ_T_DUP_RECON] && (cnt[SDCSZ_T_INPUT] || cnt[SDCSZ_T_DUP_PRED]));
-    if (gen) out.push_back(plan[i].block);
+    (gen ? out : fast).push_back(plan[i].block);
     i = j;
   }
-  return out;
 }
 
-// distinct blocks of a sorted plan
-std::vector<uint64_t> plan_block_list(const std::vector<sdcsz_fault> &plan) {
-  std::vector<uint64_t> pb;
-  for (auto &f : plan)
-    if (pb.empty() || pb.back() != f.block) pb.push_back(f.block);
-  return pb;
+// One pageable copy of a plan's entries and block lists to its device area;
+// fills the job's PlanDev (its bitmap is set on the device by k_plan_bits).
+hipError_t upload_plan(const std::vector<sdcsz_fault> &plan, const std::vector<uint64_t> &pb,
+                       const std::vector<uint64_t> &fl, std::vector<uint8_t> &buf, uint8_t *dev, PlanDev &P,
+                       hipStream_t st) {
+  const size_t eb = plan.size() * sizeof(sdcsz_fault);
+  buf.resize(eb + 8 * (pb.size() + fl.size()));
+  std::memcpy(buf.data(), plan.data(), eb);
+  if (!pb.empty()) std::memcpy(buf.data() + eb, pb.data(), 8 * pb.size());
+  if (!fl.empty()) std::memcpy(buf.data() + eb + 8 * pb.size(), fl.data(), 8 * fl.size());
+  P.list = (const uint64_t *)(dev + eb);
+  P.nlist = (uint32_t)pb.size();
+  P.flist = (const uint64_t *)(dev + eb) + pb.size();
+  P.nflist = (uint32_t)fl.size();
+  return hipMemcpyAsync(dev, buf.data(), buf.size(), hipMemcpyHostToDevice, st);
 }
+
 
 // ---------------------------------------------------------------------------
 // launch tables: the jobs of one launch and the work-groups each owns
@@ -698,19 +747,13 @@ struct CompPlan {  // host state of one field
   bool fast;
   int cls;  // shape class of the specialised kernels, -1 for generic
   std::vector<sdcsz_fault> plan;
-  std::vector<uint32_t> bits, gen;
-  std::vector<uint64_t> pb;  // blocks the generic routine takes (k_compress_list)
-  bool faults;               // the fault-applying instantiation serves the others
+  std::vector<uint64_t> pb;  // blocks the wave-per-block routine takes (k_compress_wave_list)
+  std::vector<uint64_t> fl;  // blocks the fault-applying instantiation takes
+  std::vector<uint8_t> up;   // plan area as uploaded (entries, pb, fl)
   bool any_code;
   uint64_t pair_off;  // first entry of the field's histogram / codebook list
 };
 
-// distinct blocks of a sorted plan
-size_t plan_blocks(const std::vector<sdcsz_fault> &plan) {
-  size_t n = 0;
-  for (size_t i = 0; i < plan.size(); i++) n += i == 0 || plan[i].block != plan[i - 1].block;
-  return n;
-}
 
 // work-groups per field of the re-execution kernels: the queue is almost
 // always empty, and on a large batch thousands of work-groups that only
@@ -784,7 +827,6 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     f.L = comp_layout(f.g, c.p->dtype, c.p->n_faults);
     f.cls = fast_class(f.g, vbytes(c.p->dtype));
     f.fast = f.cls >= 0;
-    f.faults = false;
     f.any_code = false;
     for (auto &e : f.plan) f.any_code |= e.target == SDCSZ_T_CODE;
     f.pair_off = cap;
@@ -812,8 +854,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     const sdcsz_params *p = it[item_of[j]].p;
     if (!f.fast || f.plan.empty()) continue;
     const bool wide = wide_fast[f.cls][p->dtype][p->abft ? 1 : 0];
-    f.pb = generic_blocks(f.plan, !wide, false);
-    f.faults = f.pb.size() < plan_blocks(f.plan);
+    split_plan(f.plan, !wide, false, f.pb, f.fl);
   }
   // ---- jobs
   std::vector<Job> jobs(nj);
@@ -856,7 +897,8 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     J.plan.n = (uint32_t)f.plan.size();
     J.plan.f = (const sdcsz_fault *)(w + f.L.plan);
     J.plan.bits = (const uint32_t *)(w + f.L.bits);
-    J.plan.gen = nullptr;
+    J.plan.list = J.plan.flist = nullptr;
+    J.plan.nlist = J.plan.nflist = 0;
     Header &h = J.h;
     h.dtype = c.p->dtype;
     h.ndim = c.p->ndim;
@@ -879,7 +921,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     J.dst = c.d_out;
     J.dst_cap = c.d_out ? c.out_cap : 0;
     J.zero = (uint32_t *)(w + f.L.cnt);
-    J.zero_words = (f.L.zero_end - f.L.cnt) / 4;
+    J.zero_words = ((f.plan.empty() ? f.L.zero_end : f.L.bits_end) - f.L.cnt) / 4;
     J.stat = (const uint64_t *)(w + f.L.cnt);
     J.stat_words = kResWords;
     J.eb = c.p->eb;
@@ -897,35 +939,25 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     J.hist_win = c.p->eb_mode != SDCSZ_REL ? 8192u : c.p->eb >= 5e-4 ? 2048u : c.p->eb >= 5e-5 ? 8192u : kHistWin;
     if (J.dtype == SDCSZ_F32) fill_rt<float>(J);
     else fill_rt<double>(J);
-    // fault plans (pageable sources live in fp until the first synchronisation)
+    // fault plans: entries and block lists in one copy (the pageable source
+    // lives in fp until the first synchronisation); the block bitmap is set
+    // on the device
     if (!f.plan.empty()) {
-      f.bits.assign(f.g.n_blocks / 32 + 1, 0);
-      for (auto &e : f.plan) f.bits[e.block >> 5] |= 1u << (e.block & 31);
-      HIPCHK(hipMemcpyAsync(w + f.L.plan, f.plan.data(), f.plan.size() * sizeof(sdcsz_fault), hipMemcpyHostToDevice,
-                            st));
-      HIPCHK(hipMemcpyAsync(w + f.L.bits, f.bits.data(), f.bits.size() * 4, hipMemcpyHostToDevice, st));
-      if (!f.pb.empty()) {
-        HIPCHK(hipMemcpyAsync(w + f.L.plan_blocks, f.pb.data(), 8 * f.pb.size(), hipMemcpyHostToDevice, st));
-        if (!f.faults) {
-          J.plan.gen = J.plan.bits;  // every plan block
-        } else {
-          f.gen.assign(f.g.n_blocks / 32 + 1, 0);
-          for (uint64_t b : f.pb) f.gen[b >> 5] |= 1u << (b & 31);
-          HIPCHK(hipMemcpyAsync(w + f.L.gen, f.gen.data(), f.gen.size() * 4, hipMemcpyHostToDevice, st));
-          J.plan.gen = (const uint32_t *)(w + f.L.gen);
-        }
-      }
+      HIPCHK(upload_plan(f.plan, f.pb, f.fl, f.up, w + f.L.plan, J.plan, st));
     }
   }
   // ---- stage A tables: zero, range + constants, prediction/quantization,
   // re-runs, histogram compaction
-  Tab t_zero, t_range[2], t_fast[kClasses][2][2], t_gen[2], t_redo[kClasses][2], t_hist, t_hchunk;  // t_hist: one work-group per job
+  // t_gen: one thread per block; t_wave, t_wlist, t_redo: a wave per block;
+  // t_flist: the fault-applying instantiation over the plans' lists
+  Tab t_zero, t_plan, t_range[2], t_fast[kClasses][2][2], t_flist[kClasses][2][2], t_gen[2], t_wave[2], t_wlist[2],
+      t_redo[2], t_hist, t_hchunk;
+  uint32_t lds_wlist[2] = {}, lds_redo[2] = {};  // dynamic LDS of the wave launches
+  uint32_t slice_wave[2] = {}, hw_wave[2] = {};  // k_compress_wave: widest block slice and histogram window
   uint64_t nb_fast[kClasses][2][2] = {}, nb_cls[kClasses] = {}, nb_enc[kClasses][2] = {};
   uint32_t hw_fast[kClasses][2][2] = {};  // widest histogram window of each launch
-  bool faults_fast[kClasses][2][2] = {};  // a launch with a field whose plan it applies
   for (uint32_t j = 0; j < nj; j++)
     if (fp[j].fast) {
-      faults_fast[fp[j].cls][jobs[j].dtype][jobs[j].abft ? 1 : 0] |= fp[j].faults;
       uint32_t &hw = hw_fast[fp[j].cls][jobs[j].dtype][jobs[j].abft ? 1 : 0];
       hw = std::max(hw, jobs[j].hist_win);
       nb_fast[fp[j].cls][jobs[j].dtype][jobs[j].abft ? 1 : 0] += fp[j].g.n_blocks;
@@ -944,24 +976,43 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     Job &J = jobs[j];
     const CompPlan &f = fp[j];
     t_zero.add(j, std::min<uint64_t>(64, grid_for(J.zero_words, 256)));
+    if (!f.plan.empty()) t_plan.add(j, grid_for(f.plan.size(), 256));
     if (J.eb_mode == SDCSZ_REL && f.g.n_values) t_range[J.dtype].add(j, J.nparts);
     if (f.fast) {
       const int a = J.abft ? 1 : 0;
       t_fast[f.cls][J.dtype][a].add(j, fast_launch(f.g, &J.L, ln_fast[f.cls][J.dtype][a]));
-      if (J.abft) t_redo[f.cls][J.dtype].add(j, kRedoWgs);
+      if (!f.fl.empty()) t_flist[f.cls][J.dtype][a].add(j, grid_for(f.fl.size(), 64));
+      const uint32_t lb = wave_lds_bytes(f.g, vbytes(J.dtype));
+      if (J.abft) {
+        t_redo[J.dtype].add(j, kRedoWgs);
+        lds_redo[J.dtype] = std::max(lds_redo[J.dtype], lb);
+      }
+      if (!f.pb.empty()) {
+        t_wlist[J.dtype].add(j, f.pb.size());
+        lds_wlist[J.dtype] = std::max(lds_wlist[J.dtype], lb);
+      }
     } else if (f.g.n_blocks) {
-      t_gen[J.dtype].add(j, grid_for(f.g.n_blocks, 64));
+      const uint32_t lb = wave_slice_bytes(f.g, vbytes(J.dtype));
+      if (lb <= kWaveLdsMax) {
+        t_wave[J.dtype].add(j, std::min<uint64_t>(kWaveWgMax, (f.g.n_blocks + kWaveWgWaves - 1) / kWaveWgWaves));
+        slice_wave[J.dtype] = std::max(slice_wave[J.dtype], lb);
+        hw_wave[J.dtype] = std::max(hw_wave[J.dtype], J.hist_win);
+      } else {
+        t_gen[J.dtype].add(j, grid_for(f.g.n_blocks, 64));
+      }
     }
     t_hist.add(j, 1);
     t_hchunk.add(j, kHistChunks);
   }
   Upload up;
-  up.tabs = {&t_zero, &t_range[0], &t_range[1], &t_gen[0], &t_gen[1], &t_hist, &t_hchunk};
+  up.tabs = {&t_zero,     &t_range[0], &t_range[1], &t_gen[0],  &t_gen[1],  &t_hist,    &t_hchunk,
+             &t_wave[0],  &t_wave[1],  &t_wlist[0], &t_wlist[1], &t_redo[0], &t_redo[1], &t_plan};
   for (int c = 0; c < kClasses; c++)
     for (int d = 0; d < 2; d++)
       for (int a = 0; a < 2; a++) up.tabs.push_back(&t_fast[c][d][a]);
   for (int c = 0; c < kClasses; c++)
-    for (int d = 0; d < 2; d++) up.tabs.push_back(&t_redo[c][d]);
+    for (int d = 0; d < 2; d++)
+      for (int a = 0; a < 2; a++) up.tabs.push_back(&t_flist[c][d][a]);
   uint8_t *hs = t_stage.get(std::max<size_t>(up.bytes(nj), 4 * nj + 8 + 8 * t_pair_guess + 64));
   if (!hs) return SDCSZ_EHIP;
   up.place(jobs, hs, ws + B.jobs);
@@ -971,10 +1022,13 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   const JobTab *d_gen = &up.dev[3];
   const JobTab &d_hist = up.dev[5];
   const JobTab &d_hchunk = up.dev[6];
-  const JobTab *d_fast = &up.dev[7];                     // [class][dtype][abft] in that order
-  const JobTab *d_redo = &up.dev[7 + kClasses * 2 * 2];  // [class][dtype]
+  const JobTab *d_wave = &up.dev[7], *d_wlist = &up.dev[9], *d_redo = &up.dev[11];  // [dtype]
+  const JobTab &d_plan = up.dev[13];
+  const JobTab *d_fast = &up.dev[14];                       // [class][dtype][abft] in that order
+  const JobTab *d_flist = &up.dev[14 + kClasses * 2 * 2];  // the same
   auto grid = [](const Tab &t) { return dim3(t.total()); };
   launch(PH_NONE, false, false, k_zero_jobs, grid(t_zero), dim3(256), st, d_zero);
+  if (t_plan.total()) launch(PH_NONE, false, false, k_plan_bits, grid(t_plan), dim3(256), st, d_plan);
   {
     PhaseLaunch pl{PH_RANGE, {}};
     if (t_range[0].total())
@@ -984,19 +1038,31 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     pl.run();
   }
   launch(PH_NONE, false, false, k_consts, grid(t_hist), dim3(kRangeThreads), st, d_hist);
-  // plan blocks the specialised kernels leave run first through the
-  // paper-order routine
-  for (uint32_t j = 0; j < nj; j++) {
-    const CompPlan &f = fp[j];
-    const Job &J = jobs[j];
-    if (!f.fast || f.pb.empty()) continue;
-    const uint64_t *d_pb = (const uint64_t *)(f.ws + f.L.plan_blocks);
-    if (J.dtype == SDCSZ_F32)
-      launch(PH_NONE, false, false, k_compress_list<float>, dim3(grid_for(f.pb.size(), 64)), dim3(64), st,
-             (const float *)J.src, J.g, J.rtf, J.plan, J.cw, J.abft, J.predictor, d_pb, (uint32_t)f.pb.size());
-    else
-      launch(PH_NONE, false, false, k_compress_list<double>, dim3(grid_for(f.pb.size(), 64)), dim3(64), st,
-             (const double *)J.src, J.g, J.rtd, J.plan, J.cw, J.abft, J.predictor, d_pb, (uint32_t)f.pb.size());
+  // plan blocks, which the production kernels leave, beside them on a second
+  // stream: the fault-applying instantiation over its lists, a wave per
+  // block for the others
+  bool any_plan_work = t_wlist[0].total() || t_wlist[1].total();
+  for (int c = 0; c < kClasses; c++)
+    for (int d = 0; d < 2; d++)
+      for (int a = 0; a < 2; a++) any_plan_work |= t_flist[c][d][a].total() != 0;
+  hipStream_t side = st;
+  if (any_plan_work) {
+    if (!t_no_side) {
+      side = t_side.fork(st);
+      if (!side) return SDCSZ_EHIP;
+    }
+    for (int c = 0; c < kClasses; c++)
+      for (int d = 0; d < 2; d++)
+        for (int a = 0; a < 2; a++)
+          if (t_flist[c][d][a].total())
+            launch_shm(PH_NONE, false, false, kCompFast[c][d][a][2], grid(t_flist[c][d][a]), dim3(64),
+                       4 * hw_fast[c][d][a], side, d_flist[(c * 2 + d) * 2 + a]);
+    if (t_wlist[0].total())
+      launch_shm(PH_NONE, false, false, k_compress_wave_list<float>, grid(t_wlist[0]), dim3(64), lds_wlist[0], side,
+                 d_wlist[0]);
+    if (t_wlist[1].total())
+      launch_shm(PH_NONE, false, false, k_compress_wave_list<double>, grid(t_wlist[1]), dim3(64), lds_wlist[1], side,
+                 d_wlist[1]);
   }
   {
     PhaseLaunch pl{PH_PREDICT, {}};
@@ -1006,22 +1072,36 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
           const Tab &t = t_fast[c][d][a];
           if (!t.total()) continue;
           const JobTab jt = d_fast[(c * 2 + d) * 2 + a];
-          const JobKernel k = kCompFast[c][d][a][wide_fast[c][d][a] ? 1 : faults_fast[c][d][a] ? 2 : 0];
+          const JobKernel k = kCompFast[c][d][a][wide_fast[c][d][a] ? 1 : 0];
           const uint32_t ln = ln_fast[c][d][a], shm = 4 * hw_fast[c][d][a];
           pl.fs.push_back([&t, jt, k, ln, shm, st, &grid](bool x, bool y) {
             launch_shm(PH_PREDICT, x, y, k, grid(t), dim3(ln), shm, st, jt);
           });
         }
+    for (int d = 0; d < 2; d++) {
+      if (!t_wave[d].total()) continue;
+      // as many waves per work-group (up to 4) as the LDS holds
+      uint32_t nwv = kWaveWgWaves;
+      while (nwv > 1 && nwv * slice_wave[d] + 4 * hw_wave[d] > kWaveWgLds) nwv--;
+      const uint32_t shm = nwv * slice_wave[d] + 4 * hw_wave[d], slice = slice_wave[d];
+      const JobTab jt = d_wave[d];
+      const Tab &t = t_wave[d];
+      const auto k = d == 0 ? k_compress_wave<float> : k_compress_wave<double>;
+      pl.fs.push_back([&t, jt, k, nwv, shm, slice, st, &grid](bool a, bool b) {
+        launch_shm(PH_PREDICT, a, b, k, grid(t), dim3(64 * nwv), shm, st, jt, slice);
+      });
+    }
     if (t_gen[0].total())
       pl.fs.push_back([&](bool a, bool b) { launch(PH_PREDICT, a, b, k_compress_generic<float>, grid(t_gen[0]), dim3(64), st, d_gen[0]); });
     if (t_gen[1].total())
       pl.fs.push_back([&](bool a, bool b) { launch(PH_PREDICT, a, b, k_compress_generic<double>, grid(t_gen[1]), dim3(64), st, d_gen[1]); });
     pl.run();
   }
-  for (int c = 0; c < kClasses; c++)
-    for (int d = 0; d < 2; d++)
-      if (t_redo[c][d].total())
-        launch(PH_NONE, false, false, kRedoFast[c][d], grid(t_redo[c][d]), dim3(64), st, d_redo[c * 2 + d]);
+  if (any_plan_work && !t_no_side) HIPCHK(t_side.join(st));
+  if (t_redo[0].total())
+    launch_shm(PH_NONE, false, false, k_redo_wave<float>, grid(t_redo[0]), dim3(64), lds_redo[0], st, d_redo[0]);
+  if (t_redo[1].total())
+    launch_shm(PH_NONE, false, false, k_redo_wave<double>, grid(t_redo[1]), dim3(64), lds_redo[1], st, d_redo[1]);
   for (uint32_t j = 0; j < nj; j++)
     if (fp[j].any_code)
       launch(PH_CODEFAULT, true, true, k_code_faults, dim3(1), dim3(64), st, jobs[j].plan, jobs[j].g,
@@ -1211,11 +1291,11 @@ struct DecPlan {
   uint8_t *ws;
   bool fast;
   bool small;  // no recon scratch (see dec_layout)
-  bool faults;  // the fault-applying instantiation serves the plan blocks not in pb
   int cls;
   std::vector<sdcsz_fault> plan;
-  std::vector<uint32_t> bits, gen;
-  std::vector<uint64_t> pb;  // blocks the generic routine takes (k_decode_list)
+  std::vector<uint64_t> pb;  // blocks the wave-per-block routine takes (k_decode_wave_list)
+  std::vector<uint64_t> fl;  // blocks the fault-applying instantiation takes
+  std::vector<uint8_t> up;   // plan area as uploaded (entries, pb, fl)
 };
 
 uint64_t dec_batch_area(uint64_t njobs) {
@@ -1305,7 +1385,6 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     // block shape has one; verification the generic kernel
     f.cls = d.mode != 1 ? fast_class(d.g, vbytes(d.h.dtype)) : -1;
     f.fast = f.cls >= 0;
-    f.faults = false;
     fp.push_back(std::move(f));
     item_of.push_back(i);
   }
@@ -1321,10 +1400,7 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
   for (uint32_t j = 0; j < nj; j++) {
     DecPlan &f = fp[j];
     const DecItem &d = it[item_of[j]];
-    if (f.fast && !f.plan.empty()) {
-      f.pb = generic_blocks(f.plan, !wide_dec[f.cls][d.h.dtype], true);
-      f.faults = f.pb.size() < plan_blocks(f.plan);
-    }
+    if (f.fast && !f.plan.empty()) split_plan(f.plan, !wide_dec[f.cls][d.h.dtype], true, f.pb, f.fl);
     f.small = d.small_recon && f.fast && f.pb.empty();
     f.L = dec_layout(d.g, d.h.dtype, d.n_faults, f.small);
     per += f.L.total;
@@ -1363,7 +1439,8 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     J.plan.n = (uint32_t)f.plan.size();
     J.plan.f = (const sdcsz_fault *)(w + f.L.plan);
     J.plan.bits = (const uint32_t *)(w + f.L.bits);
-    J.plan.gen = nullptr;
+    J.plan.list = J.plan.flist = nullptr;
+    J.plan.nlist = J.plan.nflist = 0;
     J.reg = d.reg;
     J.mode = d.mode;
     const uint32_t *table = (const uint32_t *)(d.d_stream + d.h.off_table);
@@ -1377,44 +1454,28 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     J.dst = d.d_out;
     J.dst_cap = d.out_cap;
     J.zero = (uint32_t *)(w + f.L.cnt);
-    J.zero_words = (f.L.zero_end - f.L.cnt) / 4;
+    J.zero_words = ((f.plan.empty() ? f.L.zero_end : f.L.bits_end) - f.L.cnt) / 4;
     J.stat = (const uint64_t *)(w + f.L.cnt);
     J.stat_words = C_N + 1;
     J.dtype = d.h.dtype;
     J.abft = d.h.abft;
-    if (!f.plan.empty()) {
-      f.bits.assign(d.g.n_blocks / 32 + 1, 0);
-      for (auto &e : f.plan) f.bits[e.block >> 5] |= 1u << (e.block & 31);
-      HIPCHK(hipMemcpyAsync(w + f.L.plan, f.plan.data(), f.plan.size() * sizeof(sdcsz_fault), hipMemcpyHostToDevice,
-                            st));
-      HIPCHK(hipMemcpyAsync(w + f.L.bits, f.bits.data(), f.bits.size() * 4, hipMemcpyHostToDevice, st));
-      if (!f.pb.empty()) {
-        HIPCHK(hipMemcpyAsync(w + f.L.plan_blocks, f.pb.data(), 8 * f.pb.size(), hipMemcpyHostToDevice, st));
-        if (!f.faults) {
-          J.plan.gen = J.plan.bits;  // every plan block
-        } else {
-          f.gen.assign(d.g.n_blocks / 32 + 1, 0);
-          for (uint64_t b : f.pb) f.gen[b >> 5] |= 1u << (b & 31);
-          HIPCHK(hipMemcpyAsync(w + f.L.gen, f.gen.data(), f.gen.size() * 4, hipMemcpyHostToDevice, st));
-          J.plan.gen = (const uint32_t *)(w + f.L.gen);
-        }
-      }
-    }
+    if (!f.plan.empty()) HIPCHK(upload_plan(f.plan, f.pb, f.fl, f.up, w + f.L.plan, J.plan, st));
   }
-  Tab t_zero, t_one, t_s1, t_fast[kClasses][2], t_gen[2], t_redo[kClasses][2][2];
+  // t_list, t_redo: a wave per block; t_flist: the fault-applying
+  // instantiation over the plans' lists
+  Tab t_zero, t_plan, t_one, t_s1, t_fast[kClasses][2], t_flist[kClasses][2], t_gen[2], t_list[2], t_redo[2];
+  uint32_t lds_list[2] = {}, lds_redo[2] = {};
   uint64_t nb_dec[kClasses][2] = {};
-  bool faults_dec[kClasses][2] = {};  // a launch with a field whose plan it applies
   for (uint32_t j = 0; j < nj; j++)
-    if (fp[j].fast) {
-      nb_dec[fp[j].cls][jobs[j].dtype] += jobs[j].g.n_blocks;
-      faults_dec[fp[j].cls][jobs[j].dtype] |= fp[j].faults;
-    }
+    if (fp[j].fast) nb_dec[fp[j].cls][jobs[j].dtype] += jobs[j].g.n_blocks;
   uint32_t ln_dec[kClasses][2];
   for (int c = 0; c < kClasses; c++)
     for (int d = 0; d < 2; d++) ln_dec[c][d] = tuned_lanes(TS_DECODE, c, d, nb_dec[c][d]);
   for (uint32_t j = 0; j < nj; j++) {
     Job &J = jobs[j];
     t_zero.add(j, 1);
+    if (!fp[j].plan.empty()) t_plan.add(j, grid_for(fp[j].plan.size(), 256));
+    if (!fp[j].fl.empty()) t_flist[fp[j].cls][J.dtype].add(j, grid_for(fp[j].fl.size(), 64));
     t_one.add(j, 1);
     t_s1.add(j, scan_chunks(J.g.n_blocks));
     if (fp[j].fast && J.mode == 2) {
@@ -1429,21 +1490,29 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
       J.L.shell_count = nbox;
       const uint32_t ln = ln_dec[fp[j].cls][J.dtype];
       t_fast[fp[j].cls][J.dtype].add(j, grid_for(nbox, ln));
-      t_redo[fp[j].cls][J.dtype][1].add(j, kRedoWgs);
     } else if (fp[j].fast) {
       t_fast[fp[j].cls][J.dtype].add(j, fast_launch(J.g, &J.L, ln_dec[fp[j].cls][J.dtype]));
-      t_redo[fp[j].cls][J.dtype][0].add(j, kRedoWgs);
     } else if (J.g.n_blocks) {
       t_gen[J.dtype].add(j, grid_for(J.g.n_blocks, 64));
     }
   }
+  for (uint32_t j = 0; j < nj; j++) {
+    const Job &J = jobs[j];
+    if (!fp[j].fast) continue;
+    const uint32_t lb = wave_lds_bytes(J.g, vbytes(J.dtype));
+    t_redo[J.dtype].add(j, kRedoWgs);
+    lds_redo[J.dtype] = std::max(lds_redo[J.dtype], lb);
+    if (!fp[j].pb.empty()) {
+      t_list[J.dtype].add(j, fp[j].pb.size());
+      lds_list[J.dtype] = std::max(lds_list[J.dtype], lb);
+    }
+  }
   Upload up;
-  up.tabs = {&t_zero, &t_one, &t_s1, &t_gen[0], &t_gen[1]};
+  up.tabs = {&t_zero, &t_one, &t_s1, &t_gen[0], &t_gen[1], &t_list[0], &t_list[1], &t_redo[0], &t_redo[1], &t_plan};
   for (int c = 0; c < kClasses; c++)
     for (int d = 0; d < 2; d++) up.tabs.push_back(&t_fast[c][d]);
   for (int c = 0; c < kClasses; c++)
-    for (int d = 0; d < 2; d++)
-      for (int r = 0; r < 2; r++) up.tabs.push_back(&t_redo[c][d][r]);
+    for (int d = 0; d < 2; d++) up.tabs.push_back(&t_flist[c][d]);
   const size_t res_bytes = 8ull * (C_N + 1) * nj;
   // caller-given headers go to the end of the batch area (uploaded with the
   // jobs) for k_dectab to check against the streams
@@ -1464,6 +1533,7 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
   const std::vector<JobTab> &D = up.dev;
   auto grid = [](const Tab &t) { return dim3(t.total()); };
   launch(PH_NONE, false, false, k_zero_jobs, grid(t_zero), dim3(256), st, D[0]);
+  if (t_plan.total()) launch(PH_NONE, false, false, k_plan_bits, grid(t_plan), dim3(256), st, D[9]);
   launch(PH_NONE, false, false, k_dectab, grid(t_one), dim3(kDecTabThreads), st, D[1]);
   bool any_empty = false;
   for (uint32_t j = 0; j < nj; j++) any_empty |= jobs[j].g.n_blocks == 0;
@@ -1473,19 +1543,27 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     launch(PH_SCAN_D, false, true, k_scan3, grid(t_s1), dim3(kScanThreads), st, D[2]);
   }
   launch(PH_NONE, false, false, k_dec_check, grid(t_one), dim3(64), st, D[1]);
-  // plan blocks the specialised decoder leaves (full decompression) run
-  // through the generic routine first
-  for (uint32_t j = 0; j < nj; j++) {
-    const DecPlan &f = fp[j];
-    const Job &J = jobs[j];
-    if (f.pb.empty()) continue;
-    const uint64_t *d_pb = (const uint64_t *)(f.ws + f.L.plan_blocks);
-    if (J.dtype == SDCSZ_F32)
-      launch(PH_NONE, false, false, k_decode_list<float>, dim3(grid_for(f.pb.size(), 64)), dim3(64), st, J.src, J.h,
-             J.g, J.dw, J.plan, (float *)J.dst, d_pb, (uint32_t)f.pb.size());
-    else
-      launch(PH_NONE, false, false, k_decode_list<double>, dim3(grid_for(f.pb.size(), 64)), dim3(64), st, J.src, J.h,
-             J.g, J.dw, J.plan, (double *)J.dst, d_pb, (uint32_t)f.pb.size());
+  // plan blocks (full decompression), which the production decoder leaves,
+  // beside it on a second stream: the fault-applying instantiation over its
+  // lists, a wave per block for the others
+  bool any_plan_work = t_list[0].total() || t_list[1].total();
+  for (int c = 0; c < kClasses; c++)
+    for (int d = 0; d < 2; d++) any_plan_work |= t_flist[c][d].total() != 0;
+  hipStream_t side = st;
+  if (any_plan_work) {
+    if (!t_no_side) {
+      side = t_side.fork(st);
+      if (!side) return SDCSZ_EHIP;
+    }
+    for (int c = 0; c < kClasses; c++)
+      for (int d = 0; d < 2; d++)
+        if (t_flist[c][d].total())
+          launch(PH_NONE, false, false, kDecFast[c][d][2], grid(t_flist[c][d]), dim3(64), side,
+                 D[10 + 2 * kClasses + 2 * c + d]);
+    if (t_list[0].total())
+      launch_shm(PH_NONE, false, false, k_decode_wave_list<float>, grid(t_list[0]), dim3(64), lds_list[0], side, D[5]);
+    if (t_list[1].total())
+      launch_shm(PH_NONE, false, false, k_decode_wave_list<double>, grid(t_list[1]), dim3(64), lds_list[1], side, D[6]);
   }
   {
     PhaseLaunch pl{PH_DECODE, {}};
@@ -1493,8 +1571,8 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
       for (int d = 0; d < 2; d++) {
         const Tab &t = t_fast[c][d];
         if (!t.total()) continue;
-        const JobTab jt = D[5 + 2 * c + d];
-        const JobKernel k = kDecFast[c][d][wide_dec[c][d] ? 1 : faults_dec[c][d] ? 2 : 0];
+        const JobTab jt = D[10 + 2 * c + d];
+        const JobKernel k = kDecFast[c][d][wide_dec[c][d] ? 1 : 0];
         const uint32_t ln = ln_dec[c][d];
         pl.fs.push_back([&t, jt, k, ln, st, &grid](bool x, bool y) { launch(PH_DECODE, x, y, k, grid(t), dim3(ln), st, jt); });
       }
@@ -1504,12 +1582,11 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
       pl.fs.push_back([&](bool a, bool b) { launch(PH_DECODE, a, b, k_decode_generic<double>, grid(t_gen[1]), dim3(64), st, D[4]); });
     pl.run();
   }
-  for (int c = 0; c < kClasses; c++)
-    for (int d = 0; d < 2; d++)
-      for (int r = 0; r < 2; r++)
-        if (t_redo[c][d][r].total())
-          launch(PH_NONE, false, false, kDecRedo[c][d][r], grid(t_redo[c][d][r]), dim3(64), st,
-                 D[5 + 2 * kClasses + (c * 2 + d) * 2 + r]);
+  if (any_plan_work && !t_no_side) HIPCHK(t_side.join(st));
+  if (t_redo[0].total())
+    launch_shm(PH_NONE, false, false, k_decode_wave_redo<float>, grid(t_redo[0]), dim3(64), lds_redo[0], st, D[7]);
+  if (t_redo[1].total())
+    launch_shm(PH_NONE, false, false, k_decode_wave_redo<double>, grid(t_redo[1]), dim3(64), lds_redo[1], st, D[8]);
   const uint64_t *d_res = (const uint64_t *)(ws + a256(up.bytes(nj)));
   if (nj == 1) d_res = jobs[0].stat;  // one stream: no gather needed
   else launch(PH_NONE, false, false, k_results, grid(t_one), dim3(64), st, D[1], (uint64_t *)d_res,
@@ -1815,6 +1892,7 @@ int sdcsz_decompress_noalloc(const void *d_stream, uint64_t stream_size, void *d
   fixed.cap = sizeof(g_noalloc_host);
   fixed.fixed = true;
   t_stage_over = &fixed;
+  t_no_side = true;  // no second stream to create
   DecItem d{};
   d.d_stream = (const uint8_t *)d_stream;
   d.stream_size = stream_size;
@@ -1826,6 +1904,7 @@ int sdcsz_decompress_noalloc(const void *d_stream, uint64_t stream_size, void *d
   const int rc = decode_one_call(d, (uint8_t *)g_scratch_ptr[dev], SDCSZ_NOALLOC_SCRATCH_BYTES,
                                  (hipStream_t)stream, h_rep);
   t_stage_over = nullptr;
+  t_no_side = false;
   return rc;
 }
 

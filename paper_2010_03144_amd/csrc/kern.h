@@ -110,6 +110,7 @@ __device__ inline JobWg job_of(const JobTab &t) {
 __global__ void k_zero_u64(unsigned long long *p, uint64_t n);
 __global__ void k_zero_u32(uint32_t *p, uint64_t n);
 __global__ void k_zero_jobs(JobTab t);
+__global__ void k_plan_bits(JobTab t);
 template <typename T> __global__ void k_range(JobTab t);
 __global__ void k_consts(JobTab t);
 __global__ void k_code_faults(PlanDev plan, Geo g, uint16_t *codes, unsigned long long *cnt);
@@ -130,19 +131,35 @@ __global__ void k_dec_check(JobTab t);
 
 template <typename T, int ND, int B0, int B1, int B2, bool ABFT, bool WIDE, bool FAULTS>
 __global__ void k_compress_fast(JobTab t);
-template <typename T>
-__global__ void k_compress_list(const T *in, Geo g, RegTab<T> rt, PlanDev plan, CompWork w, uint32_t abft,
-                                uint32_t predictor, const uint64_t *list, uint32_t n);
-template <typename T, int ND, int B0, int B1, int B2> __global__ void k_redo(JobTab t);
-
 template <typename T, int ND, int B0, int B1, int B2, bool WIDE, bool FAULTS> __global__ void k_decode_fast(JobTab t);
-template <typename T>
-__global__ void k_decode_list(const uint8_t *s, Header h, Geo g, DecWork w, PlanDev plan, T *out,
-                              const uint64_t *list, uint32_t n);
-template <typename T, int ND, int B0, int B1, int B2, bool REG> __global__ void k_decode_redo(JobTab t);
 
 template <int ND, int B0, int B1, int B2> __global__ void k_check_fast(JobTab t);
 template <typename T, int ND, int B0, int B1, int B2> __global__ void k_encode_fast(JobTab t);
+
+// Wave-per-block kernels (kern_wave.hip): one block per work-group of 64
+// lanes, staged in dynamic LDS of wave_lds_bytes().
+constexpr uint32_t kWaveDupBytes = 12;            // LDS per plan entry of the duplicated computations
+constexpr uint32_t kWaveLdsMax = 64 * 1024;       // blocks needing more take the one-thread kernels
+__host__ __device__ inline uint32_t wave_rsz(const Geo &g) {
+  const uint32_t parts = g.b[0] * g.b[1] + g.b[0] * g.b[2] + 3 * g.b[0];
+  return g.bpts > parts ? g.bpts : parts;
+}
+__host__ __device__ inline uint32_t wave_lds_bytes(const Geo &g, uint32_t vbytes) {
+  const uint32_t rsz = wave_rsz(g);
+  return 2 * rsz * vbytes + 4 * ((rsz + 31) / 32) + kMaxPatches * kWaveDupBytes;
+}
+// one wave's slice of a multi-wave work-group (16-byte aligned)
+__host__ __device__ inline uint32_t wave_slice_bytes(const Geo &g, uint32_t vbytes) {
+  return (wave_lds_bytes(g, vbytes) + 15) & ~15u;
+}
+constexpr uint32_t kWaveWgWaves = 4;          // most waves per work-group of k_compress_wave
+constexpr uint32_t kWaveWgMax = 2048;          // work-groups per field of k_compress_wave
+constexpr uint32_t kWaveWgLds = 150 * 1024;    // dynamic LDS of one of its work-groups at most
+template <typename T> __global__ void k_compress_wave(JobTab t, uint32_t slice);
+template <typename T> __global__ void k_compress_wave_list(JobTab t);
+template <typename T> __global__ void k_redo_wave(JobTab t);
+template <typename T> __global__ void k_decode_wave_list(JobTab t);
+template <typename T> __global__ void k_decode_wave_redo(JobTab t);
 
 template <typename T> __global__ void k_compress_generic(JobTab t);
 template <typename T> __global__ void k_decode_generic(JobTab t);

@@ -11,17 +11,17 @@
 // checksums are taken when the coefficients are computed and verified (a
 // corrupted word located and repaired in place) before the prediction pass.
 // A block whose input checksums or duplicated computations disagree is
-// queued with its first-pass checksums; k_redo locates and repairs the input
-// word against them and runs the block again.
+// queued with its first-pass checksums; k_redo_wave (kern_wave.hip) locates
+// and repairs the input word against them and runs the block again.
 //
-// Three instantiations of the per-lane routine share this source: the
-// production one, one that applies a fault plan's flips at the program
-// points of evaluation mode A (input and coefficient memory errors after
-// their checksums, flips of the first copy of a duplicated prediction or
-// reconstruction), and the re-execution of k_redo (one repaired input word,
-// histogram counted in global memory).  Blocks whose plan holds more than one
-// flip of a kind, or errors of the prediction preparation, take the generic
-// per-block routine (k_compress_list).
+// Two instantiations of the per-lane routine share this source: the
+// production one, which leaves the blocks a fault plan names, and one that
+// runs those blocks (a launch over the plan's list of blocks) and applies the
+// flips at the program points of evaluation mode A (input and coefficient
+// memory errors after their checksums, flips of the first copy of a
+// duplicated prediction or reconstruction).  Blocks whose plan that
+// instantiation does not model take the wave-per-block routine
+// (k_compress_wave_list).
 #include "block_generic.h"
 #include "kern.h"
 
@@ -102,7 +102,8 @@ template <int ND, int B0, int B1, int B2> constexpr int sample_slot(int i0, int 
 // is n_words*S - Q).  This pair only detects, so it is kept modulo 2^32: a
 // corrupted word changes S by a non-zero amount below 2^32 in magnitude,
 // which no 32-bit wrap can hide.  Locating the word takes the exact
-// first-pass pair (Ck64), which k_redo compares with the memory as it is.
+// first-pass pair (Ck64), which k_redo_wave compares with the memory as it
+// is.
 template <typename T> struct Ck;
 template <> struct Ck<float> {
   __device__ static inline void add(float v, uint32_t &S, uint32_t &Q) {
@@ -159,19 +160,12 @@ template <> struct Ck64<double> {
   }
 };
 
-// value v with word `half` (0 low, 1 high for FP64) xor-ed with m / set to x
+// value v with word `half` (0 low, 1 high for FP64) xor-ed with m
 template <typename T> __device__ inline T word_xor(T v, uint32_t half, uint32_t m) {
   uint32_t wv[2] = {0, 0};
   Wd<T>::split(v, wv);
   wv[0] ^= half == 0 ? m : 0u;
   if (Wd<T>::per == 2) wv[1] ^= half == 1 ? m : 0u;
-  return Wd<T>::join(wv);
-}
-template <typename T> __device__ inline T word_set(T v, uint32_t half, uint32_t x) {
-  uint32_t wv[2] = {0, 0};
-  Wd<T>::split(v, wv);
-  wv[0] = half == 0 ? x : wv[0];
-  if (Wd<T>::per == 2) wv[1] = half == 1 ? x : wv[1];
   return Wd<T>::join(wv);
 }
 
@@ -225,7 +219,7 @@ template <typename T> __device__ inline int coef_check(T &b0, T &b1, T &b2, T &m
 }
 
 // per-lane routine instantiations
-enum { kProd = 0, kFaults = 1, kRedo = 2 };
+enum { kProd = 0, kFaults = 1 };
 
 // A lane's flips of a fault plan (at most one of each kind: the host sends
 // blocks with more to the generic routine).  Words and points index the
@@ -273,11 +267,6 @@ template <typename T> __device__ inline void coef_flip(T &b0, T &b1, T &b2, T &m
   else m = word_xor(m, half, mk);
 }
 
-// The re-execution's repaired input word (~0u: none).
-struct Patch {
-  uint32_t w = ~0u, v = 0;
-};
-
 // What a lane's pass found: mismatch reasons and the first-pass checksums.
 struct LaneOut {
   uint64_t why, S1, Q1;
@@ -301,19 +290,18 @@ __device__ inline uint64_t wave_min(uint64_t org) {
 
 // One lane's block: full blocks (FULL) have compile-time extents, blocks of
 // the partial shell mask every point by their actual extents.  MODE selects
-// the instantiation (kProd, kFaults, kRedo).  Every lane of the wave calls it
+// the instantiation (kProd, kFaults).  Every lane of the wave calls it
 // (inactive lanes with a valid block id).  Returns the lane's mismatch
 // reasons and first-pass checksums; the checksums wait in `stash` (two
 // words of LDS per lane) through the prediction pass, which keeps only
-// their low halves in registers (kRedo needs neither).
+// their low halves in registers.
 template <typename T, int ND, int B0, int B1, int B2, bool FULL, bool ABFT, bool WIDE, int MODE>
 __device__ __forceinline__ LaneOut compress_lanes(const T *__restrict__ in, const Geo &g, const RegTab<T> &rt,
                                                   const PlanDev &plan, const CompWork &w, uint32_t predictor,
                                                   uint32_t *hist, uint32_t hlo, uint32_t hw, uint32_t &hot,
-                                                  uint64_t blk, bool active, const Patch &pt, uint64_t *stash) {
+                                                  uint64_t blk, bool active, uint64_t *stash) {
   constexpr int PL = B1 * B2;  // points per plane
   static_assert(PL % 4 == 0, "a plane must fill whole 4-code groups");
-  static_assert(!(FULL && MODE == kRedo), "re-execution takes the masked path");
   constexpr int NS = sample_slot<ND, B0, B1, B2>(B0, 0, 0);
   constexpr uint32_t per = Wd<T>::per;
   // wave-uniform base of the input (the wave's lowest block origin); lanes
@@ -326,7 +314,8 @@ __device__ __forceinline__ LaneOut compress_lanes(const T *__restrict__ in, cons
   // fields: a per-lane base at the block's origin (32-bit offsets inside it)
   const char *wbase = WIDE ? (const char *)(in + org) : (const char *)(in + org0);
   const uint32_t loff = WIDE ? 0u : (uint32_t)((org - org0) * sizeof(T));
-  if (MODE != kRedo && active && plan_gen(plan, blk)) active = false;  // done by k_compress_list
+  // plan blocks: the fault-applying launch over the plan's list, or k_compress_wave_list
+  if (MODE == kProd && active && plan_hit(plan, blk)) active = false;
   const LaneFaults lf = MODE == kFaults ? lane_faults(plan, blk, active) : LaneFaults{};
   LaneOut out{0, 0, 0};
   if (active) {
@@ -342,9 +331,7 @@ __device__ __forceinline__ LaneOut compress_lanes(const T *__restrict__ in, cons
     auto ld = [&](int i, int j, int k) -> T {
       if (FULL) return *(const T *)(wbase + (loff + (uint32_t)i * PSB + (uint32_t)j * RSB) + k * sizeof(T));
       const uint32_t ii = min((uint32_t)i, n0 - 1), jj = min((uint32_t)j, n1 - 1), kk = min((uint32_t)k, n2 - 1);
-      T v = *(const T *)(wbase + (loff + ii * PSB + jj * RSB + kk * (uint32_t)sizeof(T)));
-      if (MODE == kRedo && pt.w / per == ((uint32_t)i * n1 + (uint32_t)j) * n2 + (uint32_t)k)
-        v = word_set(v, pt.w % per, pt.v);  // the repaired word
+      const T v = *(const T *)(wbase + (loff + ii * PSB + jj * RSB + kk * (uint32_t)sizeof(T)));
       return valid(i, j, k) ? v : (T)0;
     };
 
@@ -417,10 +404,8 @@ __device__ __forceinline__ LaneOut compress_lanes(const T *__restrict__ in, cons
     }
     uint32_t S1l = 0, Q1l = 0;  // what the prediction pass compares with
     if (ABFT) {
-      if (MODE != kRedo) {
-        stash[0] = S1;
-        stash[1] = Q1;
-      }
+      stash[0] = S1;
+      stash[1] = Q1;
       S1l = (uint32_t)S1;
       Q1l = (uint32_t)Q1;
     }
@@ -594,16 +579,14 @@ __device__ __forceinline__ LaneOut compress_lanes(const T *__restrict__ in, cons
             nout += is_out ? 1u : 0u;
           }
           const bool z = v && code == kRadius;
-          if (MODE != kRedo) hot += (uint32_t)__popcll(__ballot(z));  // the same in every lane running the pass
+          hot += (uint32_t)__popcll(__ballot(z));  // the same in every lane running the pass
           if (v) {
             if (ABFT) {
               s_dc += Wd<T>::sum(r_out);
               rs += code;
               rk += (uint32_t)k * code;
             }
-            if (MODE == kRedo) {
-              atomicAdd(w.hist + code, 1u);
-            } else if (!z) {
+            if (!z) {
               const uint32_t cb = code - hlo;
               if (cb < hw) atomicAdd(&hist[cb], 1u);
               else atomicAdd(w.hist + code, 1u);
@@ -646,7 +629,7 @@ __device__ __forceinline__ LaneOut compress_lanes(const T *__restrict__ in, cons
       if (mis_p) why |= kWhyPred;
       if (mis_r) why |= kWhyRecon;
       out.why = why;
-      if (MODE != kRedo && why) {
+      if (why) {
         out.S1 = stash[0];
         out.Q1 = stash[1];
       }
@@ -665,9 +648,8 @@ template <typename T, int B1, int B2, bool FULL, bool ABFT, bool WIDE, int MODE>
 __device__ __forceinline__ LaneOut compress_rows(const T *__restrict__ in, const Geo &g, const RegTab<T> &rt,
                                                  const PlanDev &plan, const CompWork &w, uint32_t predictor,
                                                  uint32_t *hist, uint32_t hlo, uint32_t hw, uint32_t &hot,
-                                                 uint64_t blk, bool active, const Patch &pt, uint64_t *stash) {
+                                                 uint64_t blk, bool active, uint64_t *stash) {
   static_assert(B2 % 4 == 0, "a row must fill whole 4-code groups");
-  static_assert(!(FULL && MODE == kRedo), "re-execution takes the masked path");
   // FP32 keeps the sampled values in registers; FP64 reads them again
   // (from cache) for the regression cost
   constexpr int NS = sizeof(T) == 4 ? sample_slot<2, 1, B1, B2>(1, 0, 0) : 0;
@@ -679,7 +661,8 @@ __device__ __forceinline__ LaneOut compress_rows(const T *__restrict__ in, const
   // fields: a per-lane base at the block's origin (32-bit offsets inside it)
   const char *wbase = WIDE ? (const char *)(in + org) : (const char *)(in + org0);
   const uint32_t loff = WIDE ? 0u : (uint32_t)((org - org0) * sizeof(T));
-  if (MODE != kRedo && active && plan_gen(plan, blk)) active = false;  // done by k_compress_list
+  // plan blocks: the fault-applying launch over the plan's list, or k_compress_wave_list
+  if (MODE == kProd && active && plan_hit(plan, blk)) active = false;
   const LaneFaults lf = MODE == kFaults ? lane_faults(plan, blk, active) : LaneFaults{};
   LaneOut out{0, 0, 0};
   if (!active) return out;
@@ -693,9 +676,7 @@ __device__ __forceinline__ LaneOut compress_rows(const T *__restrict__ in, const
   auto ld = [&](int j, int k) -> T {
     if (FULL) return *(const T *)(wbase + (loff + (uint32_t)j * RSB) + k * sizeof(T));
     const uint32_t jj = min((uint32_t)j, n1 - 1), kk = min((uint32_t)k, n2 - 1);
-    T v = *(const T *)(wbase + (loff + jj * RSB + kk * (uint32_t)sizeof(T)));
-    if (MODE == kRedo && pt.w / per == (uint32_t)j * n2 + (uint32_t)k)
-      v = word_set(v, pt.w % per, pt.v);  // the repaired word
+    const T v = *(const T *)(wbase + (loff + jj * RSB + kk * (uint32_t)sizeof(T)));
     return valid(j, k) ? v : (T)0;
   };
 
@@ -756,10 +737,8 @@ __device__ __forceinline__ LaneOut compress_rows(const T *__restrict__ in, const
   const T S0 = (T)0 + P, Sa1 = (T)0 + A, Sa2 = (T)0 + Bv;
   uint32_t S1l = 0, Q1l = 0;  // what the prediction pass compares with
   if (ABFT) {
-    if (MODE != kRedo) {
-      stash[0] = S1;
-      stash[1] = Q1;
-    }
+    stash[0] = S1;
+    stash[1] = Q1;
     S1l = (uint32_t)S1;
     Q1l = (uint32_t)Q1;
   }
@@ -897,16 +876,14 @@ __device__ __forceinline__ LaneOut compress_rows(const T *__restrict__ in, const
         nout += is_out ? 1u : 0u;
       }
       const bool z = v && code == kRadius;
-      if (MODE != kRedo) hot += (uint32_t)__popcll(__ballot(z));
+      hot += (uint32_t)__popcll(__ballot(z));
       if (v) {
         if (ABFT) {
           s_dc += Wd<T>::sum(r_out);
           rs += code;
           rk += (uint32_t)k * code;
         }
-        if (MODE == kRedo) {
-          atomicAdd(w.hist + code, 1u);
-        } else if (!z) {
+        if (!z) {
           const uint32_t cb = code - hlo;
           if (cb < hw) atomicAdd(&hist[cb], 1u);
           else atomicAdd(w.hist + code, 1u);
@@ -944,7 +921,7 @@ __device__ __forceinline__ LaneOut compress_rows(const T *__restrict__ in, const
     if (mis_p) why |= kWhyPred;
     if (mis_r) why |= kWhyRecon;
     out.why = why;
-    if (MODE != kRedo && why) {
+    if (why) {
       out.S1 = stash[0];
       out.Q1 = stash[1];
     }
@@ -966,7 +943,8 @@ __device__ inline void queue_redo(const CompWork &w, uint64_t blk, const LaneOut
 }
 
 // Work-groups [0, L.full_wgs) take full blocks, the rest the partial shell.
-// FAULTS: the instantiation that applies the fault plan's flips.
+// FAULTS: the instantiation that applies the fault plan's flips, one lane
+// per block of the plan's list (plan.flist) on the masked path.
 template <typename T, int ND, int B0, int B1, int B2, bool ABFT, bool WIDE, bool FAULTS>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(ND == 3 && sizeof(T) == 4 ? (FAULTS ? 2 : 3) : 1)))
@@ -990,29 +968,41 @@ k_compress_fast(JobTab tab) {
   __syncthreads();
   uint32_t hot = 0;
   uint64_t *st = ABFT ? stash + 2 * threadIdx.x : nullptr;
+  LaneOut o;
+  uint64_t blk;
+  if constexpr (FAULTS) {
+    const uint32_t idx = jw.b * blockDim.x + threadIdx.x, nl = plan.nflist;
+    const bool act = idx < nl;
+    blk = plan.flist[act ? idx : nl - 1];
+    if constexpr (ND == 2)
+      o = compress_rows<T, B1, B2, false, ABFT, WIDE, kFaults>(in, g, rt, plan, w, predictor, hist, hlo, hw, hot, blk,
+                                                               act, st);
+    else
+      o = compress_lanes<T, ND, B0, B1, B2, false, ABFT, WIDE, kFaults>(in, g, rt, plan, w, predictor, hist, hlo, hw,
+                                                                        hot, blk, act, st);
+  } else {
   const bool full = jw.b < L.full_wgs;
   const uint64_t idx = (uint64_t)(full ? jw.b : jw.b - L.full_wgs) * blockDim.x + threadIdx.x;
   const uint64_t nl = full ? L.full_count : L.shell_count;
   const bool act = idx < nl;
-  const uint64_t blk = map_block(g, L, full ? 0u : 1u, act ? idx : nl - 1);
-  constexpr int M = FAULTS ? kFaults : kProd;
-  const Patch none;
-  LaneOut o;
+  blk = map_block(g, L, full ? 0u : 1u, act ? idx : nl - 1);
+  constexpr int M = kProd;
   if constexpr (ND == 2) {
     static_assert(B0 == 1, "2D blocks have one plane");
     if (full)
       o = compress_rows<T, B1, B2, true, ABFT, WIDE, M>(in, g, rt, plan, w, predictor, hist, hlo, hw, hot, blk, act,
-                                                        none, st);
+                                                        st);
     else
       o = compress_rows<T, B1, B2, false, ABFT, WIDE, M>(in, g, rt, plan, w, predictor, hist, hlo, hw, hot, blk, act,
-                                                         none, st);
+                                                         st);
   } else {
     if (full)
       o = compress_lanes<T, ND, B0, B1, B2, true, ABFT, WIDE, M>(in, g, rt, plan, w, predictor, hist, hlo, hw, hot,
-                                                                 blk, act, none, st);
+                                                                 blk, act, st);
     else
       o = compress_lanes<T, ND, B0, B1, B2, false, ABFT, WIDE, M>(in, g, rt, plan, w, predictor, hist, hlo, hw, hot,
-                                                                  blk, act, none, st);
+                                                                  blk, act, st);
+  }
   }
   if (ABFT && __builtin_expect(o.why != 0, 0)) queue_redo(w, blk, o);
   // wave total of the zero-residual bin (lanes that ran the pass agree; the
@@ -1024,101 +1014,6 @@ k_compress_fast(JobTab tab) {
     if (hist[t]) atomicAdd(w.hist + hlo + t, hist[t]);
 }
 
-// The blocks the host sends to the paper-order routine (fault plans the
-// specialised kernels do not apply), one thread per listed block.
-template <typename T>
-__global__ void __launch_bounds__(64) k_compress_list(const T *__restrict__ in, Geo g, RegTab<T> rt, PlanDev plan,
-                                                       CompWork w, uint32_t abft, uint32_t predictor,
-                                                       const uint64_t *list, uint32_t n) {
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n) {
-    compress_block_generic<T>(in, g, rt, plan, w, abft, predictor, list[t]);
-    count(w.cnt, C_LIST);
-  }
-}
-
-// Re-execution of the queued blocks (Algorithm 1's correction at block
-// granularity), one lane per queue entry.  An input mismatch first locates
-// the corrupted word: the exact checksums of the memory as it is now (with a
-// plan's INPUT flip, which persists) against the first-pass checksums give
-// the word and its value before the error; an error that cannot be located
-// is uncorrectable.  Then the block's codes leave the histogram and the
-// block runs again with the repaired word.  A re-run whose own checks
-// disagree is uncorrectable.  Lanes address their blocks from per-lane
-// bases (the wide form), which serves every field size.
-template <typename T, int ND, int B0, int B1, int B2> __global__ void __launch_bounds__(64) k_redo(JobTab tab) {
-  const JobWg jw = job_of(tab);
-  const Job &J = *jw.J;
-  const T *__restrict__ in = (const T *)J.src;
-  const Geo g = J.g;
-  const RegTab<T> &rt = rt_of<T>(J);
-  const PlanDev plan = J.plan;
-  const CompWork w = J.cw;
-  const uint32_t predictor = J.predictor;
-  constexpr uint32_t per = Wd<T>::per;
-  if (!J.abft) return;
-  const uint32_t n = min(*w.redo_n, kMaxRedo);
-  uint32_t hot = 0;
-  for (uint32_t base = jw.b * blockDim.x; base < n; base += jw.nb * blockDim.x) {
-    const uint32_t e = base + threadIdx.x;
-    const bool act = e < n;
-    const uint32_t ec = act ? e : n - 1;
-    const uint64_t blk = w.redo[3 * ec] & ((1ull << 56) - 1), why = w.redo[3 * ec] >> 56;
-    const LaneFaults lf = lane_faults(plan, blk, act);
-    Patch pt;
-    bool run = act;
-    if (act && (why & kWhyInput)) {
-      const Box b = box_of(g, blk);
-      const uint32_t nw = b.pts * per;
-      auto word_at = [&](uint64_t jw_) -> uint32_t {
-        const uint32_t p = (uint32_t)(jw_ / per);
-        const uint32_t k = p % b.n[2], j = (p / b.n[2]) % b.n[1], i = p / (b.n[2] * b.n[1]);
-        T v = in[fidx(g, b, i, j, k)];
-        if (lf.in != ~0u && lf.in_w() / per == p) v = word_xor(v, lf.in_w() % per, lf.in_m());
-        uint32_t wv[2] = {0, 0};
-        Wd<T>::split(v, wv);
-        return wv[jw_ % per];
-      };
-      uint64_t S = 0, Q = 0;
-      for (uint32_t jw_ = 0; jw_ < nw; jw_++) {
-        S += word_at(jw_);
-        Q += S;
-      }
-      const uint64_t S1 = w.redo[3 * e + 1], Q1 = w.redo[3 * e + 2];
-      uint64_t jf = 0;
-      uint32_t vf = 0;
-      const int st = locate_repair(S, (uint64_t)nw * S - Q, S1, (uint64_t)nw * S1 - Q1, nw, 32, word_at, &jf, &vf);
-      if (st < 0) {
-        count(w.cnt, C_UNC + SDCSZ_T_INPUT);
-        run = false;
-      } else if (st == 1) {
-        pt.w = (uint32_t)jf;
-        pt.v = vf;
-      }
-    }
-    if (run) {
-      const Box b = box_of(g, blk);
-      for (uint32_t i = 0; i < b.n[0]; i++)
-        for (uint32_t j = 0; j < b.n[1]; j++)
-          for (uint32_t k = 0; k < b.n[2]; k++)
-            atomicSub(w.hist + w.codes[code_index(blk, padded_index(g, i, j, k), g.groups)], 1u);
-    }
-    LaneOut o;
-    if constexpr (ND == 2)
-      o = compress_rows<T, B1, B2, false, true, true, kRedo>(in, g, rt, plan, w, predictor, nullptr, 0, 0, hot, blk,
-                                                             run, pt, nullptr);
-    else
-      o = compress_lanes<T, ND, B0, B1, B2, false, true, true, kRedo>(in, g, rt, plan, w, predictor, nullptr, 0, 0,
-                                                                      hot, blk, run, pt, nullptr);
-    if (run) {
-      const int slot = o.why ? C_UNC : C_COR;
-      if (why & kWhyInput) count(w.cnt, slot + SDCSZ_T_INPUT);
-      if (why & kWhyPred) count(w.cnt, slot + SDCSZ_T_DUP_PRED);
-      if (why & kWhyRecon) count(w.cnt, slot + SDCSZ_T_DUP_RECON);
-    }
-  }
-}
-
 #define SDCSZ_INST_FAST(T, ND, B0, B1, B2, ABFT, WIDE, FAULTS) \
   template __global__ void k_compress_fast<T, ND, B0, B1, B2, ABFT, WIDE, FAULTS>(JobTab);
 #define SDCSZ_INST_SHAPE(T, ND, B0, B1, B2)                \
@@ -1127,15 +1022,10 @@ template <typename T, int ND, int B0, int B1, int B2> __global__ void __launch_b
   SDCSZ_INST_FAST(T, ND, B0, B1, B2, true, true, false)   \
   SDCSZ_INST_FAST(T, ND, B0, B1, B2, false, true, false)  \
   SDCSZ_INST_FAST(T, ND, B0, B1, B2, true, false, true)   \
-  SDCSZ_INST_FAST(T, ND, B0, B1, B2, false, false, true)  \
-  template __global__ void k_redo<T, ND, B0, B1, B2>(JobTab);
+  SDCSZ_INST_FAST(T, ND, B0, B1, B2, false, false, true)
 SDCSZ_INST_SHAPE(float, 3, 6, 6, 6)
 SDCSZ_INST_SHAPE(double, 3, 6, 6, 6)
 SDCSZ_INST_SHAPE(float, 2, 1, 16, 16)
 SDCSZ_INST_SHAPE(double, 2, 1, 16, 16)
-template __global__ void k_compress_list<float>(const float *, Geo, RegTab<float>, PlanDev, CompWork, uint32_t,
-                                                uint32_t, const uint64_t *, uint32_t);
-template __global__ void k_compress_list<double>(const double *, Geo, RegTab<double>, PlanDev, CompWork, uint32_t,
-                                                 uint32_t, const uint64_t *, uint32_t);
 
 }  // namespace sdcsz

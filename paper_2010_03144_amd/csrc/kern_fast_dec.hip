@@ -7,10 +7,11 @@
 // with the arithmetic of compression (previous reconstructed plane in
 // registers), the checksum of the block against sum_dc, and coalesced row
 // stores.  A checksum mismatch or an undecodable block queues the block for
-// k_decode_redo, which re-executes it from the compressed bytes with the
-// same per-lane routine (one lane per queued block).  A fault plan's RECON
-// flips strike the decompressed words in the instantiation that applies
-// them (FAULTS); blocks with more than one flip run in k_decode_list.
+// k_decode_wave_redo (kern_wave.hip), which re-executes it from the
+// compressed bytes.  The production instantiation leaves the blocks a fault
+// plan names; the one that applies the plan's RECON flips to the
+// decompressed words (FAULTS) runs them, a lane per block of the plan's list,
+// and blocks with more than one flip run in k_decode_wave_list.
 #include "dev.h"
 #include "kern.h"
 
@@ -169,7 +170,7 @@ __device__ inline uint32_t decode_sym(Window &br, const DecLds &t, const uint16_
 }
 
 // per-lane routine instantiations
-enum { kDProd = 0, kDFaults = 1, kDRedo = 2 };
+enum { kDProd = 0, kDFaults = 1 };
 
 // A lane's RECON flip (at most one: the host sends blocks with more to the
 // generic routine): point index in C order over the block's extents, word
@@ -221,14 +222,12 @@ struct DecOut {
 }  // namespace
 
 // One lane's block (every lane of the wave calls it; inactive lanes with a
-// valid block id).  MODE: kDProd, kDFaults (the plan's RECON flips), kDRedo
-// (re-execution: nothing queued, the caller judges the result).
+// valid block id).  MODE: kDProd, or kDFaults (the plan's RECON flips).
 template <typename T, int ND, int B0, int B1, int B2, bool FULL, bool REG, bool WIDE, int MODE>
 __device__ __forceinline__ DecOut decode_lanes(const uint8_t *__restrict__ s, const Header &h, const Geo &g,
                                                const DecWork &w, const PlanDev &plan, T *out, const DecLds &tl,
                                                uint32_t *win, uint64_t blk, bool active, const Region &reg) {
   static_assert(!(REG && FULL), "a region launch takes the masked path");
-  static_assert(!(FULL && MODE == kDRedo), "re-execution takes the masked path");
   const Box bx = box_of(g, blk);
   const uint64_t org = fidx(g, bx, 0, 0, 0);
   const uint64_t org0 = WIDE ? 0 : dwave_min(org);
@@ -236,7 +235,8 @@ __device__ __forceinline__ DecOut decode_lanes(const uint8_t *__restrict__ s, co
   // fields: a per-lane base at the block's origin (32-bit offsets inside it)
   char *wbase = WIDE ? (char *)(out + org) : (char *)(out + org0);
   const uint32_t loff = WIDE ? 0u : (uint32_t)((org - org0) * sizeof(T));
-  if (MODE != kDRedo && active && plan_gen(plan, blk)) active = false;  // done by k_decode_list
+  // plan blocks: the fault-applying launch over the plan's list, or k_decode_wave_list
+  if (MODE == kDProd && active && plan_hit(plan, blk)) active = false;
   const LaneRecon lf = MODE == kDFaults ? lane_recon(plan, blk, active, Wd<T>::per) : LaneRecon{};
   DecOut res{false, 0};
   if (!active) return res;
@@ -363,18 +363,16 @@ __device__ __forceinline__ DecOut decode_lanes(const uint8_t *__restrict__ s, co
   if (used_out != nout || br.pos > nw * 32u) bad = true;
   res.bad = bad;
   res.sum = sum;
-  if (MODE != kDRedo) {
-    const uint64_t *sumdc = (const uint64_t *)(s + h.off_sumdc);
-    uint64_t why = 0;
-    if (bad) why = 2;
-    else if (h.abft && sum != sumdc[blk]) {
-      why = 1;
-      count(w.cnt, C_DET + SDCSZ_T_RECON);
-    }
-    if (__builtin_expect(why != 0, 0)) {
-      const uint32_t slot = atomicAdd(w.redo_n, 1u);
-      if (slot < kMaxRedo) w.redo[slot] = blk | (why << 56);
-    }
+  const uint64_t *sumdc = (const uint64_t *)(s + h.off_sumdc);
+  uint64_t why = 0;
+  if (bad) why = 2;
+  else if (h.abft && sum != sumdc[blk]) {
+    why = 1;
+    count(w.cnt, C_DET + SDCSZ_T_RECON);
+  }
+  if (__builtin_expect(why != 0, 0)) {
+    const uint32_t slot = atomicAdd(w.redo_n, 1u);
+    if (slot < kMaxRedo) w.redo[slot] = blk | (why << 56);
   }
   return res;
 }
@@ -389,7 +387,6 @@ __device__ __forceinline__ DecOut decode_rows(const uint8_t *__restrict__ s, con
                                               uint32_t *win, uint64_t blk, bool active, const Region &reg) {
   static_assert(B2 * kMaxLen + 127 + 32 <= 32 * (int)kWin, "a row's codewords fit the window");
   static_assert(!(REG && FULL), "a region launch takes the masked path");
-  static_assert(!(FULL && MODE == kDRedo), "re-execution takes the masked path");
   const Box bx = box_of(g, blk);
   const uint64_t org = fidx(g, bx, 0, 0, 0);
   const uint64_t org0 = WIDE ? 0 : dwave_min(org);
@@ -397,7 +394,8 @@ __device__ __forceinline__ DecOut decode_rows(const uint8_t *__restrict__ s, con
   // fields: a per-lane base at the block's origin (32-bit offsets inside it)
   char *wbase = WIDE ? (char *)(out + org) : (char *)(out + org0);
   const uint32_t loff = WIDE ? 0u : (uint32_t)((org - org0) * sizeof(T));
-  if (MODE != kDRedo && active && plan_gen(plan, blk)) active = false;  // done by k_decode_list
+  // plan blocks: the fault-applying launch over the plan's list, or k_decode_wave_list
+  if (MODE == kDProd && active && plan_hit(plan, blk)) active = false;
   const LaneRecon lf = MODE == kDFaults ? lane_recon(plan, blk, active, Wd<T>::per) : LaneRecon{};
   DecOut res{false, 0};
   if (!active) return res;
@@ -500,18 +498,16 @@ __device__ __forceinline__ DecOut decode_rows(const uint8_t *__restrict__ s, con
   if (used_out != nout || br.pos > nw * 32u) bad = true;
   res.bad = bad;
   res.sum = sum;
-  if (MODE != kDRedo) {
-    const uint64_t *sumdc = (const uint64_t *)(s + h.off_sumdc);
-    uint64_t why = 0;
-    if (bad) why = 2;
-    else if (h.abft && sum != sumdc[blk]) {
-      why = 1;
-      count(w.cnt, C_DET + SDCSZ_T_RECON);
-    }
-    if (__builtin_expect(why != 0, 0)) {
-      const uint32_t slot = atomicAdd(w.redo_n, 1u);
-      if (slot < kMaxRedo) w.redo[slot] = blk | (why << 56);
-    }
+  const uint64_t *sumdc = (const uint64_t *)(s + h.off_sumdc);
+  uint64_t why = 0;
+  if (bad) why = 2;
+  else if (h.abft && sum != sumdc[blk]) {
+    why = 1;
+    count(w.cnt, C_DET + SDCSZ_T_RECON);
+  }
+  if (__builtin_expect(why != 0, 0)) {
+    const uint32_t slot = atomicAdd(w.redo_n, 1u);
+    if (slot < kMaxRedo) w.redo[slot] = blk | (why << 56);
   }
   return res;
 }
@@ -536,7 +532,8 @@ __device__ inline void load_tables(DecLds &tl, const DecWork &w, const Header &h
 }
 
 // Work-groups [0, L.full_wgs) take full blocks, the rest the partial shell.
-// FAULTS: the instantiation that applies the plan's RECON flips.
+// FAULTS: the instantiation that applies the plan's RECON flips, one lane
+// per block of the plan's list (plan.flist) on the masked path.
 template <typename T, int ND, int B0, int B1, int B2, bool WIDE, bool FAULTS>
 __global__ void __launch_bounds__(kDecThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
 k_decode_fast(JobTab tab) {
@@ -554,6 +551,16 @@ k_decode_fast(JobTab tab) {
   load_tables(tl, w, h);
   constexpr int M = FAULTS ? kDFaults : kDProd;
   const Region &reg = jw.J->reg, &rb = jw.J->rblk;
+  if constexpr (FAULTS) {
+    const uint32_t idx = jw.b * blockDim.x + threadIdx.x, nl = plan.nflist;
+    const bool act = idx < nl;
+    const uint64_t blk = plan.flist[act ? idx : nl - 1];
+    if constexpr (ND == 2)
+      decode_rows<T, B1, B2, false, false, WIDE, M>(s, h, g, w, plan, out, tl, win + threadIdx.x, blk, act, reg);
+    else
+      decode_lanes<T, ND, B0, B1, B2, false, false, WIDE, M>(s, h, g, w, plan, out, tl, win + threadIdx.x, blk, act,
+                                                             reg);
+  } else {
   if (jw.J->mode == 2) {
     // region decompression: one lane per block of the box of blocks the
     // region touches (L.shell_count of them), each storing only its part of
@@ -588,77 +595,12 @@ k_decode_fast(JobTab tab) {
                                                              reg);
   }
 }
-
-// Zeros over a block (the part inside the region for region decompression).
-template <typename T>
-__device__ void zero_block(const Geo &g, const Box &b, T *out, bool region, const Region &reg) {
-  for (uint32_t i = 0; i < b.n[0]; i++)
-    for (uint32_t j = 0; j < b.n[1]; j++)
-      for (uint32_t k = 0; k < b.n[2]; k++) {
-        if (region) {
-          const uint64_t z = b.o[0] + i, y = b.o[1] + j, x = b.o[2] + k;
-          if (z < reg.lo[0] || z >= reg.hi[0] || y < reg.lo[1] || y >= reg.hi[1] || x < reg.lo[2] || x >= reg.hi[2])
-            continue;
-          out[((z - reg.lo[0]) * (reg.hi[1] - reg.lo[1]) + (y - reg.lo[1])) * (reg.hi[2] - reg.lo[2]) +
-              (x - reg.lo[2])] = (T)0;
-        } else {
-          out[fidx(g, b, i, j, k)] = (T)0;
-        }
-      }
-}
-
-// Re-execution of the blocks the decoder queued (Algorithm 2's second
-// attempt), one lane per queue entry with the same per-lane routine: a
-// checksum mismatch is decoded again from the compressed bytes and stored;
-// the block is corrected when the new checksum equals sum_dc, else
-// uncorrectable.  A block that could not be decoded is zeroed and counted
-// uncorrectable without a second attempt (decoding is deterministic).
-// Lanes address their blocks from per-lane bases (the wide form), which
-// serves every field size.  REG: region decompression.
-template <typename T, int ND, int B0, int B1, int B2, bool REG>
-__global__ void __launch_bounds__(64) k_decode_redo(JobTab tab) {
-  const JobWg jw = job_of(tab);
-  const uint8_t *__restrict__ s = jw.J->src;
-  const Header h = jw.J->h;
-  const Geo g = jw.J->g;
-  const DecWork w = jw.J->dw;
-  const PlanDev plan = jw.J->plan;
-  T *out = (T *)jw.J->dst;
-  if (*w.err) return;
-  const uint32_t n = min(*w.redo_n, kMaxRedo);
-  if (jw.b * blockDim.x >= n) return;  // the whole work-group has no entry
-  __shared__ DecLds tl;
-  __shared__ uint32_t win[kWin * kDecThreads];
-  load_tables(tl, w, h);
-  const Region &reg = jw.J->reg;
-  const uint64_t *sumdc = (const uint64_t *)(s + h.off_sumdc);
-  for (uint32_t base = jw.b * blockDim.x; base < n; base += jw.nb * blockDim.x) {
-    const uint32_t e = base + threadIdx.x;
-    const bool act = e < n;
-    const uint64_t ent = w.redo[act ? e : n - 1];
-    const uint64_t blk = ent & ((1ull << 56) - 1), why = ent >> 56;
-    const bool run = act && why == 1;
-    if (act && why != 1) {
-      zero_block<T>(g, box_of(g, blk), out, REG, reg);
-      count(w.cnt, C_UNC + SDCSZ_T_RECON);
-    }
-    DecOut o;
-    if constexpr (ND == 2)
-      o = decode_rows<T, B1, B2, false, REG, true, kDRedo>(s, h, g, w, plan, out, tl, win + threadIdx.x, blk, run,
-                                                           reg);
-    else
-      o = decode_lanes<T, ND, B0, B1, B2, false, REG, true, kDRedo>(s, h, g, w, plan, out, tl, win + threadIdx.x, blk,
-                                                                    run, reg);
-    if (run) count(w.cnt, (!o.bad && o.sum == sumdc[blk] ? C_COR : C_UNC) + SDCSZ_T_RECON);
-  }
 }
 
 #define SDCSZ_INST_DEC(T, ND, B0, B1, B2)                                           \
   template __global__ void k_decode_fast<T, ND, B0, B1, B2, false, false>(JobTab); \
   template __global__ void k_decode_fast<T, ND, B0, B1, B2, true, false>(JobTab);  \
-  template __global__ void k_decode_fast<T, ND, B0, B1, B2, false, true>(JobTab);  \
-  template __global__ void k_decode_redo<T, ND, B0, B1, B2, false>(JobTab);        \
-  template __global__ void k_decode_redo<T, ND, B0, B1, B2, true>(JobTab);
+  template __global__ void k_decode_fast<T, ND, B0, B1, B2, false, true>(JobTab);
 SDCSZ_INST_DEC(float, 3, 6, 6, 6)
 SDCSZ_INST_DEC(double, 3, 6, 6, 6)
 SDCSZ_INST_DEC(float, 2, 1, 16, 16)

@@ -192,23 +192,7 @@ template <typename T> __global__ void __launch_bounds__(64) k_decode_generic(Job
   if (blk < J.g.n_blocks) decode_one<T>(J.src, J.h, J.g, J.dw, J.plan, (T *)J.dst, J.mode, J.reg, blk);
 }
 
-// full decompression of listed blocks (the blocks a fault plan names)
-template <typename T>
-__global__ void __launch_bounds__(64)
-k_decode_list(const uint8_t *__restrict__ s, Header h, Geo g, DecWork w, PlanDev plan, T *out,
-              const uint64_t *list, uint32_t n) {
-  if (*w.err) return;
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  Region reg{};
-  if (t < n) {
-    decode_one<T>(s, h, g, w, plan, out, 0, reg, list[t]);
-    count(w.cnt, C_LIST);
-  }
-}
-
 template __global__ void k_decode_generic<float>(JobTab);
 template __global__ void k_decode_generic<double>(JobTab);
-template __global__ void k_decode_list<float>(const uint8_t *, Header, Geo, DecWork, PlanDev, float *, const uint64_t *, uint32_t);
-template __global__ void k_decode_list<double>(const uint8_t *, Header, Geo, DecWork, PlanDev, double *, const uint64_t *, uint32_t);
 
 }  // namespace sdcsz

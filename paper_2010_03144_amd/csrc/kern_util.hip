@@ -23,6 +23,18 @@ __global__ void __launch_bounds__(256) k_zero_jobs(JobTab t) {
     J.zero[i] = 0;
 }
 
+// each job's fault-plan bitmap (cleared by k_zero_jobs): one bit per block
+// with entries
+__global__ void __launch_bounds__(256) k_plan_bits(JobTab t) {
+  const JobWg jw = job_of(t);
+  const PlanDev &P = jw.J->plan;
+  const uint32_t i = jw.b * blockDim.x + threadIdx.x;
+  if (i < P.n) {
+    const uint64_t b = P.f[i].block;
+    atomicOr((uint32_t *)P.bits + (b >> 5), 1u << (b & 31));
+  }
+}
+
 // ---- value range of the finite values (value-range relative bound) ----------
 template <typename T> __device__ inline void minmax_finite(T v, T &lo, T &hi) {
   const bool f = isfinite(v);
