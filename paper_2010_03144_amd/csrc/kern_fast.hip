@@ -971,6 +971,9 @@ k_compress_fast(JobTab tab) {
   LaneOut o;
   uint64_t blk;
   if constexpr (FAULTS) {
+    // a few blocks beside the production launch: their waves go first on
+    // the SIMDs they share, so the launch ends with the production one
+    __builtin_amdgcn_s_setprio(3);
     const uint32_t idx = jw.b * blockDim.x + threadIdx.x, nl = plan.nflist;
     const bool act = idx < nl;
     blk = plan.flist[act ? idx : nl - 1];

@@ -552,6 +552,7 @@ k_decode_fast(JobTab tab) {
   constexpr int M = FAULTS ? kDFaults : kDProd;
   const Region &reg = jw.J->reg, &rb = jw.J->rblk;
   if constexpr (FAULTS) {
+    __builtin_amdgcn_s_setprio(3);  // a few blocks beside the production launch
     const uint32_t idx = jw.b * blockDim.x + threadIdx.x, nl = plan.nflist;
     const bool act = idx < nl;
     const uint64_t blk = plan.flist[act ? idx : nl - 1];

@@ -120,7 +120,7 @@ template <int ND, int B0, int B1, int B2> __global__ void __launch_bounds__(256)
 #pragma unroll
   for (int t = 0; t < PG; t++) cur[t] = cb[(uint64_t)t * 64];
   uint64_t s = 0, is = 0, bits = 0;
-  bool missing = false;
+  uint32_t missing = 0;  // codes without a codeword
 #pragma unroll 1
   for (int i = 0; i < U::U0; i++) {
     if (i + 1 < U::U0) {
@@ -142,7 +142,7 @@ template <int ND, int B0, int B1, int B2> __global__ void __launch_bounds__(256)
           rs += c;
           rk += (uint32_t)k * c;
           bits += len;
-          missing |= len == 0;
+          missing += len == 0 ? 1u : 0u;
         }
       }
       s += rs;
@@ -164,15 +164,12 @@ template <int ND, int B0, int B1, int B2> __global__ void __launch_bounds__(256)
                                  [&](uint64_t jj) { return (uint32_t)w.codes[pos(jj)]; }, &jf, &vf);
     count(w.cnt, C_DET + SDCSZ_T_CODE);
     if (st == 1) {
+      // one code changed: the block's size changes by its lengths' difference
+      const uint32_t l_old = len_of(w.codes[pos(jf)], lenw, w.enc), l_new = len_of(vf, lenw, w.enc);
       w.codes[pos(jf)] = (uint16_t)vf;
       count(w.cnt, C_COR + SDCSZ_T_CODE);
-      bits = 0;
-      missing = false;
-      for (uint32_t p = 0; p < b.pts; p++) {
-        const uint32_t len = len_of(w.codes[pos(p)], lenw, w.enc);
-        bits += len;
-        missing |= len == 0;
-      }
+      bits = bits - l_old + l_new;
+      missing = missing - (l_old == 0 ? 1u : 0u) + (l_new == 0 ? 1u : 0u);
     } else {
       count(w.cnt, C_UNC + SDCSZ_T_CODE);
     }

@@ -601,13 +601,13 @@ __device__ bool decode_block_wave(const uint8_t *__restrict__ s, const Header &h
     uint64_t pos = 0;
     uint32_t used = 0;
     bool ok = true;
+    // 64 bits of the payload in a register, refilled a word at a time (zeros
+    // past the block's words): the next 32 bits are buf's top after `sh`
+    auto wd = [&](uint64_t i) -> uint64_t { return i < nwords ? word(i) : 0u; };
+    uint64_t buf = (wd(0) << 32) | wd(1), nextw = 2;
+    uint32_t sh = 0;
     for (uint32_t p = 0; p < pts && ok; p++) {
-      // 32-bit window at bit `pos` (zeros past the block's words)
-      const uint64_t wi = pos >> 5;
-      const uint32_t sh = (uint32_t)(pos & 31);
-      const uint64_t hi = wi * 32 < nbits ? word(wi) : 0u;
-      const uint64_t lo = (wi + 1) * 32 < nbits ? word(wi + 1) : 0u;
-      const uint32_t win = (uint32_t)((((hi << 32) | lo) << sh) >> 32);
+      const uint32_t win = (uint32_t)((buf << sh) >> 32);
       const uint32_t e = tab.lut[win >> (32 - kLutBits)];
       int sy = -1;
       uint32_t len = e & 0xFFu;
@@ -629,6 +629,11 @@ __device__ bool decode_block_wave(const uint8_t *__restrict__ s, const Header &h
         break;
       }
       pos += len;
+      sh += len;
+      if (sh >= 32) {
+        buf = (buf << 32) | wd(nextw++);
+        sh -= 32;
+      }
       sym[p] = (uint16_t)sy;
       if (sy == 0) {
         if (used >= nout) {
