@@ -57,6 +57,10 @@ def lib():
                                          P(C.c_uint64), P(Report), P(Debug)]
         L.sdcsz_ref_decompress.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64,
                                            P(Fault), C.c_uint32, P(Report)]
+        L.sdcsz_ref_pack.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, P(C.c_uint64)]
+        L.sdcsz_ref_unpack.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, P(C.c_uint64)]
+        L.sdcsz_ref_pack_column.restype = C.c_uint64
+        L.sdcsz_ref_pack_column.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p]
         L.sdcsz_ref_decompress_region.argtypes = [C.c_void_p, C.c_uint64, P(C.c_uint64),
                                                   P(C.c_uint64), C.c_void_p, C.c_uint64,
                                                   P(Report)]
@@ -240,3 +244,36 @@ def huffman_lengths(hist):
     lens = np.zeros(65536, np.uint8)
     L.sdcsz_ref_huffman_lengths(h.ctypes.data, lens.ctypes.data)
     return lens
+
+
+def _transform(fn, src):
+    """Run pack or unpack on a uint8 stream: (rc, output array or None)."""
+    src = np.ascontiguousarray(src, dtype=np.uint8)
+    need = C.c_uint64(0)
+    rc = fn(src.ctypes.data, src.size, None, 0, C.byref(need))
+    if rc not in (OK, ENOSPC):
+        return rc, None
+    out = np.zeros(max(int(need.value), 1), np.uint8)
+    rc = fn(src.ctypes.data, src.size, out.ctypes.data, out.size, C.byref(need))
+    return rc, (out[: int(need.value)] if rc == OK else None)
+
+
+def pack(stream):
+    """Lossless stage: the plain stream's block table and sum_dc packed per
+    chunk of 256 blocks (frame of reference); (rc, packed stream)."""
+    return _transform(lib().sdcsz_ref_pack, stream)
+
+
+def unpack(packed):
+    """The plain stream of a packed one: (rc, stream)."""
+    return _transform(lib().sdcsz_ref_unpack, packed)
+
+
+def pack_column(values):
+    """Frame-of-reference words of a column of unsigned 64-bit values."""
+    v = np.ascontiguousarray(values, dtype=np.uint64)
+    n = int(lib().sdcsz_ref_pack_column(v.ctypes.data if v.size else None, v.size, None))
+    out = np.zeros(max(n, 1), np.uint32)
+    lib().sdcsz_ref_pack_column(v.ctypes.data if v.size else None, v.size, out.ctypes.data)
+    return out[:n]
+

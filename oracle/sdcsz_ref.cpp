@@ -416,8 +416,8 @@ void write_header(uint8_t *o, const Header &h) {
   put32(o + 168, h.predictor);
 }
 
-bool read_header(const uint8_t *s, uint64_t size, Header &h) {
-  if (size < kHeaderBytes || std::memcmp(s, kMagic, 8) != 0) return false;
+/* The header's fields, whatever the stream version (magic not checked). */
+void read_fields(const uint8_t *s, Header &h) {
   h.dtype = get32(s + 8);
   h.ndim = get32(s + 12);
   for (int a = 0; a < 3; a++) h.d[a] = get64(s + 16 + 8 * a);
@@ -439,6 +439,11 @@ bool read_header(const uint8_t *s, uint64_t size, Header &h) {
   h.off_payload = get64(s + 152);
   h.total = get64(s + 160);
   h.predictor = get32(s + 168);
+}
+
+bool read_header(const uint8_t *s, uint64_t size, Header &h) {
+  if (size < kHeaderBytes || std::memcmp(s, kMagic, 8) != 0) return false;
+  read_fields(s, h);
   if (h.dtype > 1 || h.abft > 1 || h.n_sym > 65536) return false;
   Header chk = h;
   layout(chk, h.dtype == 0 ? 4 : 8);
@@ -891,6 +896,128 @@ int compress_impl(const T *in, const ref_params *p, const Geometry &g, uint8_t *
 }
 
 /* ------------------------------------------------------------------------ */
+/* Lossless stage after Huffman coding (the place of Algorithm 1's final      */
+/* lossless pass and Algorithm 2's first one).  The Huffman payload is close  */
+/* to its entropy; the per-block metadata is not: neighbouring blocks have    */
+/* similar payload sizes, outlier counts and checksums.  The packed stream    */
+/* ("SDCSZ\0v2") keeps the header, codebook, coefficients, outliers and       */
+/* payload of the plain one ("v1") verbatim and moves the block table and     */
+/* sum_dc to the end, each cut into chunks of 256 blocks, every column of a   */
+/* chunk coded by frame of reference: its minimum, then each value minus the  */
+/* minimum in as many bits as the largest difference needs, packed LSB first. */
+/*   section: u32 off[n_chunks + 1] (word offsets of the chunks after the     */
+/*            array, off[0] = 0), then the chunks' words                      */
+/*   column:  u32 base low, u32 base high, u32 width (0..64), then            */
+/*            ceil(n * width / 32) words: bit t of the column's bit string is */
+/*            bit t % 32 of word t / 32; value i holds bits [i*w, (i+1)*w)    */
+/*   table chunk: column of payload words, column of outliers<<1|regression; */
+/*   sum_dc chunk (ABFT streams only): column of sum_dc                       */
+/* Header offsets of a packed stream: codebook, coefficients, outliers,      */
+/* payload, table, sum_dc, in that order, each 8-byte aligned.                */
+/* ------------------------------------------------------------------------ */
+const uint8_t kMagicPacked[8] = {'S', 'D', 'C', 'S', 'Z', 0, 'v', '2'};
+const uint64_t kPackChunk = 256;
+
+uint32_t bit_width(uint64_t v) {
+  uint32_t w = 0;
+  while (v) { w++; v >>= 1; }
+  return w;
+}
+
+/* Frame-of-reference column: appends its words to out. */
+void pack_column(const std::vector<uint64_t> &v, std::vector<uint32_t> &out) {
+  uint64_t lo = v.empty() ? 0 : v[0], hi = lo;
+  for (uint64_t x : v) { lo = std::min(lo, x); hi = std::max(hi, x); }
+  const uint32_t w = bit_width(hi - lo);
+  out.push_back((uint32_t)lo);
+  out.push_back((uint32_t)(lo >> 32));
+  out.push_back(w);
+  const uint64_t nbits = (uint64_t)v.size() * w, first = out.size();
+  out.resize(first + (nbits + 31) / 32, 0u);
+  for (uint64_t i = 0; i < v.size(); i++) {
+    const uint64_t d = v[i] - lo;
+    for (uint32_t t = 0; t < w; t++)
+      if ((d >> t) & 1) {
+        const uint64_t bit = i * w + t;
+        out[first + bit / 32] |= 1u << (bit % 32);
+      }
+  }
+}
+
+/* Reads n values of a column at words[at..end); false when it does not fit
+ * or its width exceeds maxw.  at advances past the column. */
+bool unpack_column(const uint32_t *words, uint64_t &at, uint64_t end, uint64_t n, uint32_t maxw,
+                   std::vector<uint64_t> &v) {
+  if (at + 3 > end) return false;
+  const uint64_t lo = (uint64_t)words[at] | ((uint64_t)words[at + 1] << 32);
+  const uint32_t w = words[at + 2];
+  if (w > maxw) return false;
+  at += 3;
+  const uint64_t nwords = (n * w + 31) / 32;
+  if (at + nwords > end) return false;
+  v.assign(n, 0);
+  for (uint64_t i = 0; i < n; i++) {
+    uint64_t d = 0;
+    for (uint32_t t = 0; t < w; t++) {
+      const uint64_t bit = i * w + t;
+      d |= (uint64_t)((words[at + bit / 32] >> (bit % 32)) & 1u) << t;
+    }
+    v[i] = lo + d;
+  }
+  at += nwords;
+  return true;
+}
+
+/* One packed section: chunk word offsets then the chunks' columns. */
+std::vector<uint32_t> pack_section(const std::vector<std::vector<uint64_t>> &cols, uint64_t nb) {
+  const uint64_t nch = (nb + kPackChunk - 1) / kPackChunk;
+  std::vector<uint32_t> data, off(nch + 1, 0);
+  for (uint64_t c = 0; c < nch; c++) {
+    const uint64_t b0 = c * kPackChunk, b1 = std::min(nb, b0 + kPackChunk);
+    for (const auto &col : cols) {
+      std::vector<uint64_t> v(col.begin() + b0, col.begin() + b1);
+      pack_column(v, data);
+    }
+    off[c + 1] = (uint32_t)data.size();
+  }
+  off.insert(off.end(), data.begin(), data.end());
+  return off;
+}
+
+bool unpack_section(const uint8_t *s, uint64_t off, uint64_t bytes, uint64_t nb, const uint32_t *maxw, int ncols,
+                    std::vector<std::vector<uint64_t>> &cols) {
+  const uint64_t nch = (nb + kPackChunk - 1) / kPackChunk;
+  if (bytes % 4 != 0 || bytes / 4 < nch + 1) return false;
+  std::vector<uint32_t> w(bytes / 4);
+  std::memcpy(w.data(), s + off, bytes);
+  const uint64_t data = nch + 1, nwords = w.size() - data;
+  if (w[0] != 0) return false;
+  cols.assign(ncols, std::vector<uint64_t>());
+  std::vector<uint64_t> v;
+  for (uint64_t c = 0; c < nch; c++) {
+    if (w[c + 1] < w[c] || w[c + 1] > nwords) return false;
+    uint64_t at = data + w[c];
+    const uint64_t end = data + w[c + 1];
+    const uint64_t n = std::min(nb, (c + 1) * kPackChunk) - c * kPackChunk;
+    for (int k = 0; k < ncols; k++) {
+      if (!unpack_column(w.data(), at, end, n, maxw[k], v)) return false;
+      cols[k].insert(cols[k].end(), v.begin(), v.end());
+    }
+    if (at != end) return false;
+  }
+  return true;
+}
+
+/* The v2 offsets of the verbatim sections (everything but table and sum_dc). */
+void layout_packed_front(Header &h, uint64_t vb) {
+  h.off_codebook = kHeaderBytes;
+  h.off_coef = align8(h.off_codebook + 4ull * h.n_sym);
+  h.off_outliers = align8(h.off_coef + 4ull * vb * h.n_regression);
+  h.off_payload = align8(h.off_outliers + vb * h.n_outliers);
+  h.off_table = align8(h.off_payload + 4ull * h.payload_words);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Decompression, Algorithm 2.                                                */
 /* ------------------------------------------------------------------------ */
 struct Parsed {
@@ -1286,4 +1413,101 @@ extern "C" int sdcsz_ref_verify(const void *stream, uint64_t stream_size, void *
   rep->eb_abs = P.h.eb_abs;
   if (P.h.dtype == 0) return verify_impl<float>((const uint8_t *)stream, P, (float *)data, faults, n_faults, rep);
   return verify_impl<double>((const uint8_t *)stream, P, (double *)data, faults, n_faults, rep);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Lossless stage: entry points.                                              */
+/* ------------------------------------------------------------------------ */
+extern "C" uint64_t sdcsz_ref_pack_column(const uint64_t *v, uint64_t n, uint32_t *out) {
+  std::vector<uint32_t> w;
+  pack_column(std::vector<uint64_t>(v, v + n), w);
+  if (out) std::memcpy(out, w.data(), 4 * w.size());
+  return w.size();
+}
+
+extern "C" int sdcsz_ref_pack(const void *stream, uint64_t size, void *out, uint64_t cap, uint64_t *out_size) {
+  const uint8_t *s = (const uint8_t *)stream;
+  Header h;
+  if (!read_header(s, size, h) || h.total > size) return REF_EFORMAT;
+  const uint64_t vb = h.dtype == REF_F32 ? 4 : 8, nb = h.n_blocks;
+  Header v1 = h;
+  std::vector<std::vector<uint64_t>> tcols(2, std::vector<uint64_t>(nb)), scols(1, std::vector<uint64_t>(nb));
+  for (uint64_t b = 0; b < nb; b++) {
+    tcols[0][b] = get32(s + v1.off_table + 8 * b);
+    tcols[1][b] = get32(s + v1.off_table + 8 * b + 4);
+    if (h.abft) scols[0][b] = get64(s + v1.off_sumdc + 8 * b);
+  }
+  const std::vector<uint32_t> tsec = pack_section(tcols, nb);
+  const std::vector<uint32_t> ssec = h.abft ? pack_section(scols, nb) : std::vector<uint32_t>();
+  Header h2 = h;
+  layout_packed_front(h2, vb);
+  h2.off_sumdc = align8(h2.off_table + 4ull * tsec.size());
+  h2.total = align8(h2.off_sumdc + 4ull * ssec.size());
+  *out_size = h2.total;
+  if (h2.total > cap) return REF_ENOSPC;
+  uint8_t *o = (uint8_t *)out;
+  std::memset(o, 0, h2.total);
+  write_header(o, h2);
+  std::memcpy(o, kMagicPacked, 8);
+  std::memcpy(o + h2.off_codebook, s + v1.off_codebook, 4ull * h.n_sym);
+  std::memcpy(o + h2.off_coef, s + v1.off_coef, 4ull * vb * h.n_regression);
+  std::memcpy(o + h2.off_outliers, s + v1.off_outliers, vb * h.n_outliers);
+  std::memcpy(o + h2.off_payload, s + v1.off_payload, 4ull * h.payload_words);
+  std::memcpy(o + h2.off_table, tsec.data(), 4 * tsec.size());
+  if (!ssec.empty()) std::memcpy(o + h2.off_sumdc, ssec.data(), 4 * ssec.size());
+  return REF_OK;
+}
+
+extern "C" int sdcsz_ref_unpack(const void *packed, uint64_t size, void *out, uint64_t cap, uint64_t *out_size) {
+  const uint8_t *s = (const uint8_t *)packed;
+  if (size < kHeaderBytes || std::memcmp(s, kMagicPacked, 8) != 0) return REF_EFORMAT;
+  Header h2;
+  read_fields(s, h2);
+  if (h2.dtype > 1 || h2.abft > 1 || h2.n_sym > 65536 || h2.total > size) return REF_EFORMAT;
+  const uint64_t vb = h2.dtype == REF_F32 ? 4 : 8, nb = h2.n_blocks;
+  Header chk = h2;
+  layout_packed_front(chk, vb);
+  if (chk.off_codebook != h2.off_codebook || chk.off_coef != h2.off_coef || chk.off_outliers != h2.off_outliers ||
+      chk.off_payload != h2.off_payload || chk.off_table != h2.off_table || h2.off_sumdc < h2.off_table ||
+      h2.total < h2.off_sumdc || h2.off_sumdc % 8 != 0)
+    return REF_EFORMAT;
+  const uint32_t tmax[2] = {32, 32}, smax[1] = {64};
+  std::vector<std::vector<uint64_t>> tcols, scols;
+  const uint64_t tbytes = h2.off_sumdc - h2.off_table;
+  /* the table section ends at the last chunk's word, then pads to 8 bytes */
+  const uint64_t nch = (nb + kPackChunk - 1) / kPackChunk;
+  if (tbytes < 4 * (nch + 1)) return REF_EFORMAT;
+  const uint32_t tlast = get32(s + h2.off_table + 4 * nch);
+  const uint64_t tused = 4 * (nch + 1 + (uint64_t)tlast);
+  if (tused > tbytes || align8(h2.off_table + tused) != h2.off_sumdc) return REF_EFORMAT;
+  if (!unpack_section(s, h2.off_table, tused, nb, tmax, 2, tcols)) return REF_EFORMAT;
+  if (h2.abft) {
+    const uint64_t sbytes = h2.total - h2.off_sumdc;
+    if (sbytes < 4 * (nch + 1)) return REF_EFORMAT;
+    const uint32_t slast = get32(s + h2.off_sumdc + 4 * nch);
+    const uint64_t sused = 4 * (nch + 1 + (uint64_t)slast);
+    if (sused > sbytes || align8(h2.off_sumdc + sused) != h2.total) return REF_EFORMAT;
+    if (!unpack_section(s, h2.off_sumdc, sused, nb, smax, 1, scols)) return REF_EFORMAT;
+  } else if (h2.total != h2.off_sumdc) {
+    return REF_EFORMAT;
+  }
+  for (uint64_t b = 0; b < nb; b++)
+    if (tcols[0][b] > 0xFFFFFFFFull || tcols[1][b] > 0xFFFFFFFFull) return REF_EFORMAT;
+  Header h = h2;
+  layout(h, vb);
+  *out_size = h.total;
+  if (h.total > cap) return REF_ENOSPC;
+  uint8_t *o = (uint8_t *)out;
+  std::memset(o, 0, h.total);
+  write_header(o, h);
+  std::memcpy(o + h.off_codebook, s + h2.off_codebook, 4ull * h.n_sym);
+  for (uint64_t b = 0; b < nb; b++) {
+    put32(o + h.off_table + 8 * b, (uint32_t)tcols[0][b]);
+    put32(o + h.off_table + 8 * b + 4, (uint32_t)tcols[1][b]);
+    if (h.abft) put64(o + h.off_sumdc + 8 * b, scols[0][b]);
+  }
+  std::memcpy(o + h.off_coef, s + h2.off_coef, 4ull * vb * h.n_regression);
+  std::memcpy(o + h.off_outliers, s + h2.off_outliers, vb * h.n_outliers);
+  std::memcpy(o + h.off_payload, s + h2.off_payload, 4ull * h.payload_words);
+  return REF_OK;
 }

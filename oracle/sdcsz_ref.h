@@ -100,6 +100,16 @@ int sdcsz_ref_decompress_region(const void *stream, uint64_t stream_size, const 
 int sdcsz_ref_verify(const void *stream, uint64_t stream_size, void *data, uint64_t data_size,
                      const ref_fault *faults, uint32_t n_faults, ref_report *rep);
 
+/* Lossless stage after Huffman coding: the block table and sum_dc of a plain
+ * stream ("v1") packed per chunk of 256 blocks by frame of reference into a
+ * packed stream ("v2"), and back.  *out_size receives the size (also the
+ * required size on REF_ENOSPC).  REF_EFORMAT: not a stream of the input
+ * version, or inconsistent sections. */
+int sdcsz_ref_pack(const void *stream, uint64_t size, void *out, uint64_t cap, uint64_t *out_size);
+int sdcsz_ref_unpack(const void *packed, uint64_t size, void *out, uint64_t cap, uint64_t *out_size);
+/* One frame-of-reference column of n values: base low, base high, width,
+ * packed words; returns the word count (out may be NULL to size it). */
+uint64_t sdcsz_ref_pack_column(const uint64_t *v, uint64_t n, uint32_t *out);
 /* Building blocks exposed so that tests can pin them one by one. */
 void sdcsz_ref_checksums(const uint32_t *w, uint64_t n, uint64_t *sum, uint64_t *isum);
 /* 0 = clean, 1 = corrected, -1 = uncorrectable; width = 32 or 16 bits. */
