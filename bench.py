@@ -246,6 +246,52 @@ def shape_speed_report(codec, torch, xd, eb=1e-3, blocks=((4, 4, 4), (8, 8, 8), 
     return {"workload": f"512^3 FP32 field, eb {eb:g} REL, ABFT on", "blocks": out}
 
 
+def lossless_report(codec, torch, xd, block, ebs=(1e-2, 1e-3, 1e-4), reps=10):
+    """The lossless stage (block table and sum_dc packed by frame of
+    reference per chunk of 256 blocks) on the field's ABFT streams: sizes
+    and CR gain, and the wall time of sdcsz_pack / sdcsz_unpack (median of
+    reps, each call's own synchronisations included) against compression and
+    decompression of the same field.  unpack(pack(s)) must give s back."""
+    sync = torch.cuda.synchronize
+    n_bytes = xd.numel() * xd.element_size()
+
+    def med(fn):
+        fn()
+        sync()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            r = fn()
+            sync()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), r
+
+    rows = {}
+    for eb in ebs:
+        t_c, (rc, s, _) = med(lambda: codec.compress(xd, block, eb))
+        assert rc == 0, rc
+        s = s.clone()
+        t_d, (rc, _, _) = med(lambda: codec.decompress(s))
+        assert rc == 0, rc
+        rc, p = codec.pack(s)
+        assert rc == 0, rc
+        pbuf = torch.empty_like(p)
+        sbuf = torch.empty_like(s)
+        t_p, (rc, p2) = med(lambda: codec.pack(s, out=pbuf))
+        assert rc == 0 and torch.equal(p2, p)
+        t_u, (rc, s2) = med(lambda: codec.unpack(p, out=sbuf))
+        assert rc == 0 and torch.equal(s2, s)
+        rows[f"{eb:g}"] = {
+            "plain_bytes": int(s.numel()), "packed_bytes": int(p.numel()),
+            "cr_plain": round(n_bytes / s.numel(), 4), "cr_packed": round(n_bytes / p.numel(), 4),
+            "size_gain": round(1 - p.numel() / s.numel(), 5),
+            "pack_ms": round(t_p * 1e3, 4), "unpack_ms": round(t_u * 1e3, 4),
+            "compress_ms": round(t_c * 1e3, 4), "decompress_ms": round(t_d * 1e3, 4),
+            "pack_vs_compress": round(t_p / t_c, 4), "unpack_vs_decompress": round(t_u / t_d, 4)}
+    return {"workload": f"{'x'.join(map(str, xd.shape))} FP32 field, block {'x'.join(map(str, block))}, REL eb, "
+                        f"ABFT on; wall-clock medians of {reps}", "ebs": rows}
+
+
 def region_report(codec, torch, xd, block, eb=1e-3, edges=(32, 64, 128, 256, 512), reps=5):
     """Random-access decompression (Sec. 5.1): time to decompress a centred
     cube of each edge out of the stream of the whole field, against full
@@ -539,7 +585,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed 192-field batch")
-    ap.add_argument("--only", choices=["batch", "serve", "region", "faults", "shapes"],
+    ap.add_argument("--only", choices=["batch", "serve", "region", "faults", "shapes", "lossless"],
                     help="run one part alone and print its JSON")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--tune-file", help="load launch shapes from this JSON file instead of autotuning")
@@ -580,7 +626,7 @@ def main():
         print(json.dumps(batch_bench(sdcsz.Codec("cuda:0"), torch, plain_loop=not args.batch_only_batched)),
               flush=True)
         return
-    if args.only in ("serve", "region", "faults", "shapes"):
+    if args.only in ("serve", "region", "faults", "shapes", "lossless"):
         log("generating 512^3 FP32 field")
         x = synth.grf_field((512, 512, 512), seed=2)
         xd = torch.from_numpy(x).cuda()
@@ -590,6 +636,8 @@ def main():
             print(json.dumps(region_report(sdcsz.Codec("cuda:0"), torch, xd, (6, 6, 6))), flush=True)
         elif args.only == "shapes":
             print(json.dumps(shape_speed_report(sdcsz.Codec("cuda:0"), torch, xd)), flush=True)
+        elif args.only == "lossless":
+            print(json.dumps(lossless_report(sdcsz.Codec("cuda:0"), torch, xd, (6, 6, 6))), flush=True)
         else:
             print(json.dumps(fault_report(sdcsz.Codec("cuda:0"), torch, x, xd, (6, 6, 6))), flush=True)
         return
@@ -692,6 +740,8 @@ def main():
         result["prep_faults"] = prep_fault_report(codec, torch, x, xd, block)
         log("region decompression")
         result["region"] = region_report(codec, torch, xd, block)
+        log("lossless stage")
+        result["lossless"] = lossless_report(codec, torch, xd, block)
         log("block-size rate-distortion")
         result["block_size"] = block_size_report(codec, xd)
         log("block shapes without a lane-per-block kernel")

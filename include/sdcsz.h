@@ -226,6 +226,55 @@ int sdcsz_decompress_region(const void *d_stream, uint64_t stream_size, const ui
                             sdcsz_report *h_rep, void *d_ws, uint64_t ws_size, void *stream);
 
 /*
+ * Lossless stage (the last pass of Algorithm 1 and the first of Algorithm 2):
+ * the per-block metadata that Huffman coding leaves redundant -- the block
+ * table (payload words; outliers << 1 | regression flag) and, with ABFT,
+ * sum_dc -- is packed per chunk of 256 blocks by frame of reference (each
+ * chunk column: its minimum, a bit width, the differences in that width), so
+ * a block's entries are still read from its own chunk (random access).
+ * Codebook, coefficients, outliers and payload move unchanged.  A packed
+ * stream has the magic "SDCSZ\0v2"; the other entry points take plain
+ * streams, so a packed one is unpacked first.  Any change to the packed
+ * metadata that still unpacks is caught by the block checksums of
+ * decompression (ABFT streams), like a change to the plain stream.
+ */
+/* Device workspace of sdcsz_pack for a stream of n_blocks blocks (the
+ * header's block count). */
+uint64_t sdcsz_pack_workspace_size(uint64_t n_blocks);
+#define SDCSZ_UNPACK_WORKSPACE_BYTES 256
+
+/*
+ * Pack a plain stream.
+ *   d_stream  device, stream_size bytes, 8-byte aligned; read only
+ *   d_out     device, out_cap bytes, 8-byte aligned, not overlapping d_stream;
+ *             receives the packed stream (nothing is written on an error);
+ *             NULL with out_cap 0 asks for the size (SDCSZ_ENOSPC)
+ *   h_out_size host; the packed size (also on SDCSZ_ENOSPC: the size needed)
+ *   d_ws      device workspace, ws_size >= sdcsz_pack_workspace_size()
+ * Returns SDCSZ_OK, SDCSZ_EINVAL (null or misaligned pointer), SDCSZ_EFORMAT
+ * (not a plain stream), SDCSZ_ENOSPC, SDCSZ_EHIP.  Synchronises `stream`
+ * twice (header, section sizes); the writes of the packed stream are queued
+ * on `stream` when the call returns.
+ */
+int sdcsz_pack(const void *d_stream, uint64_t stream_size, void *d_out, uint64_t out_cap, uint64_t *h_out_size,
+               void *d_ws, uint64_t ws_size, void *stream);
+
+/*
+ * Unpack a packed stream into the plain stream it was made from (byte for
+ * byte).
+ *   d_packed  device, packed_size bytes, 8-byte aligned; read only
+ *   d_out     device, out_cap bytes, 8-byte aligned, not overlapping d_packed;
+ *             NULL with out_cap 0 asks for the size (SDCSZ_ENOSPC)
+ *   h_out_size host; the plain size (also on SDCSZ_ENOSPC)
+ *   d_ws      device workspace of ws_size >= SDCSZ_UNPACK_WORKSPACE_BYTES
+ * Returns SDCSZ_OK, SDCSZ_EINVAL, SDCSZ_EFORMAT (not a packed stream, or its
+ * packed sections are inconsistent: then d_out's contents are undefined),
+ * SDCSZ_ENOSPC (nothing written), SDCSZ_EHIP.  Synchronises `stream` twice.
+ */
+int sdcsz_unpack(const void *d_packed, uint64_t packed_size, void *d_out, uint64_t out_cap, uint64_t *h_out_size,
+                 void *d_ws, uint64_t ws_size, void *stream);
+
+/*
  * Batches: many fields in one call (the independent-block design of Sec. 5.1
  * makes fields, like blocks, independent units of work).  Each phase runs as
  * one launch per kernel class over all fields of the batch (a table on the

@@ -1,4 +1,4 @@
-"""Build step of the HIP library: compiles csrc/*.hip and csrc/host.cpp for
+"""Build step of the HIP library: compiles csrc/*.hip and csrc/*.cpp for
 gfx950 into paper_2010_03144_amd/libsdcsz.so with hipcc.
 
 Floating-point flags keep every operation a single IEEE operation in source
@@ -22,7 +22,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=
 
 
 def sources():
-    return sorted(glob.glob(os.path.join(CSRC, "*.hip"))) + [os.path.join(CSRC, "host.cpp")]
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip"))) + sorted(glob.glob(os.path.join(CSRC, "*.cpp")))
 
 
 def build(verbose=False, jobs=8):

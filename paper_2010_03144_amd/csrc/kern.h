@@ -164,4 +164,44 @@ template <typename T> __global__ void k_decode_wave_redo(JobTab t);
 template <typename T> __global__ void k_compress_generic(JobTab t);
 template <typename T> __global__ void k_decode_generic(JobTab t);
 
+// Lossless stage (kern_pack.hip): the block table and sum_dc packed per chunk
+// of kPackChunk blocks by frame of reference; every other section verbatim.
+constexpr uint32_t kPackChunk = 256;
+constexpr uint32_t kPackColWords = kPackChunk * 64 / 32;  // packed words of a chunk column at most
+struct PackChunk {
+  uint64_t base[3];   // column minima: payload words, outliers << 1 | regression, sum_dc
+  uint32_t width[3];  // bits per packed difference (0..64)
+  uint32_t words_t, words_s;  // words of the chunk in the table and sum_dc sections
+  uint32_t off_t, off_s;      // their word offsets in the sections' data (after the scan)
+};
+struct PackArgs {
+  const uint8_t *src;      // plain stream
+  uint8_t *dst;            // packed stream
+  PackChunk *info;         // nch entries
+  uint64_t *res;           // [0] table section words, [1] sum_dc section words
+  uint64_t nb, nch;
+  uint64_t src_table, src_sumdc;  // plain-stream byte offsets
+  uint64_t dst_table, dst_sumdc;  // packed-stream byte offsets (dst_sumdc set once scanned)
+  uint32_t abft, n_pads;
+  uint64_t pads[6];        // 4-byte words of alignment padding to clear
+  uint32_t hdr[kHeader / 4];
+};
+struct UnpackArgs {
+  const uint8_t *src;      // packed stream
+  uint8_t *dst;            // plain stream
+  uint32_t *err;           // set when the packed sections are not valid
+  uint64_t nb, nch;
+  uint64_t src_table, src_sumdc, src_total;  // packed-stream byte offsets
+  uint64_t dst_table, dst_sumdc;             // plain-stream byte offsets
+  uint32_t abft, n_pads;
+  uint32_t write;          // 0: check the sections only (the output is too small)
+  uint64_t pads[6];
+  uint32_t hdr[kHeader / 4];
+};
+__global__ void k_pack_sizes(PackArgs a);
+__global__ void k_pack_scan(PackArgs a);
+__global__ void k_pack_write(PackArgs a);
+__global__ void k_unpack_check(UnpackArgs a);
+__global__ void k_unpack_chunks(UnpackArgs a);
+
 }  // namespace sdcsz

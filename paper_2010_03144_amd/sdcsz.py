@@ -22,10 +22,12 @@ FUNCTIONS = ["sdcsz_max_compressed_size", "sdcsz_compress_workspace_size", "sdcs
              "sdcsz_compress_batch", "sdcsz_decompress_batch_workspace_size",
              "sdcsz_decompress_batch", "sdcsz_strerror", "sdcsz_timing_enable",
              "sdcsz_timing_read", "sdcsz_phase_name", "sdcsz_tune_set", "sdcsz_tune_get",
-             "sdcsz_decompress_noalloc"]
+             "sdcsz_decompress_noalloc", "sdcsz_pack_workspace_size", "sdcsz_pack", "sdcsz_unpack"]
 N_PHASES = 11
 HEADER_BYTES = 192
 NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024  # device array of sdcsz_decompress_noalloc
+UNPACK_WORKSPACE_BYTES = 256
+PACKED_MAGIC = b"SDCSZ\x00v2"
 TUNE_MAX = 8
 TUNE_STAGES = ["predict", "check", "encode", "decode"]
 SHAPE_CLASSES = [((6, 6, 6), 3), ((16, 16), 2)]  # (block, ndim) of the specialised kernels
@@ -110,6 +112,10 @@ def lib():
         L.sdcsz_decompress_batch_workspace_size.restype = C.c_uint64
         L.sdcsz_decompress_batch_workspace_size.argtypes = [P(Params), C.c_uint32]
         L.sdcsz_decompress_batch.argtypes = [P(DecItem), C.c_uint32, vp, C.c_uint64, vp]
+        L.sdcsz_pack_workspace_size.restype = C.c_uint64
+        L.sdcsz_pack_workspace_size.argtypes = [C.c_uint64]
+        L.sdcsz_pack.argtypes = [vp, C.c_uint64, vp, C.c_uint64, P(C.c_uint64), vp, C.c_uint64, vp]
+        L.sdcsz_unpack.argtypes = [vp, C.c_uint64, vp, C.c_uint64, P(C.c_uint64), vp, C.c_uint64, vp]
         L.sdcsz_strerror.restype = C.c_char_p
         L.sdcsz_strerror.argtypes = [C.c_int]
         L.sdcsz_timing_enable.argtypes = [C.c_int]
@@ -331,6 +337,51 @@ class Codec:
                                 _stream_handle(self.device))
         del keep
         return rc, out, report_dict(rep)
+
+    # ------------------------------------------------------------ lossless stage
+    def pack(self, stream, out=None):
+        """The packed form of a plain stream: (rc, packed uint8 tensor), a
+        view of `out` when given (uint8, on this device, large enough), else
+        of a new tensor.  Sizes are bounded from the stream's size alone (a
+        plain stream holds 8 bytes of block table per block), so no header
+        is read here."""
+        torch = self.torch
+        L = lib()
+        nb_max = stream.numel() // 8
+        ws = self.workspace(L.sdcsz_pack_workspace_size(nb_max), "pack")
+        size = C.c_uint64(0)
+
+        def call(o):
+            return L.sdcsz_pack(C.c_void_p(stream.data_ptr()), stream.numel(), C.c_void_p(o.data_ptr()),
+                                o.numel(), C.byref(size), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                _stream_handle(self.device))
+        if out is None:
+            # a chunk column adds 3 words and at most one partial word
+            out = torch.empty(stream.numel() + 64 * (nb_max // 256 + 2), dtype=torch.uint8, device=self.device)
+        rc = call(out)
+        if rc == ENOSPC:
+            out = torch.empty(int(size.value), dtype=torch.uint8, device=self.device)
+            rc = call(out)
+        return rc, (out[:int(size.value)] if rc == OK else None)
+
+    def unpack(self, packed, out=None):
+        """The plain stream of a packed one: (rc, uint8 tensor), a view of
+        `out` when given and large enough, else of a new tensor."""
+        torch = self.torch
+        L = lib()
+        ws = self.workspace(UNPACK_WORKSPACE_BYTES, "unpack")
+        size = C.c_uint64(0)
+
+        def call(o):
+            ptr, cap = (o.data_ptr(), o.numel()) if o is not None else (None, 0)
+            return L.sdcsz_unpack(C.c_void_p(packed.data_ptr()), packed.numel(), C.c_void_p(ptr), cap,
+                                  C.byref(size), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                  _stream_handle(self.device))
+        rc = call(out)  # out None: a size query
+        if rc == ENOSPC and (out is None or out.numel() < int(size.value)):
+            out = torch.empty(int(size.value), dtype=torch.uint8, device=self.device)
+            rc = call(out)
+        return rc, (out[:int(size.value)] if rc == OK else None)
 
     def decompress_noalloc(self, stream, out, faults=None):
         """sdcsz_decompress_noalloc: decompress `stream` into the caller's
