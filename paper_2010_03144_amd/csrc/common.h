@@ -112,6 +112,7 @@ struct DecTab {
   uint32_t count[kMaxLen + 2];
   uint32_t start[kMaxLen + 2];
   uint32_t min_len, max_len;
+  uint32_t sub_n;  // entries of the second-level table (0: not built, lut2 falls back to the search)
 };
 
 struct DecWork {
@@ -124,6 +125,8 @@ struct DecWork {
   uint64_t *scan_part;
   unsigned long long *cnt;
   uint32_t *lut;       // 2^kLutBits entries: symbol << 8 | length (0: longer code)
+  uint32_t *lut2;      // the same prefixes for the specialised decoder (two-level, see kLut2Sub)
+  uint32_t *sub;       // kSubMax entries: second level of lut2, symbol << 8 | length
   uint32_t *redo_n;    // blocks queued for re-execution
   uint64_t *redo;      // kMaxRedo entries: block | reason << 56
   uint32_t *err;       // non-zero: the codebook or the block table is not valid
@@ -131,6 +134,14 @@ struct DecWork {
 };
 
 constexpr uint32_t kLutBits = 11;  // codeword prefix resolved by one table lookup
+// lut2 entries: symbol << 8 | length for a codeword of at most kLutBits bits;
+// for a prefix that only longer codewords (lengths lmin..lmax) start with,
+// off << 12 | (lmax - kLutBits) << 8 when its second level (2^(lmax -
+// kLutBits) entries from sub[off], indexed by the bits after the prefix) was
+// built, else kLut2Search | lmax << 16 | lmin << 8; 0 if no codeword starts
+// with the prefix.
+constexpr uint32_t kLut2Search = 0x80000000u;
+constexpr uint32_t kSubMax = 65536;  // second-level entries of one codebook at most
 
 // Stream header fields (byte offsets inside the 192-byte header).
 struct Header {

@@ -290,7 +290,7 @@ CompLayout comp_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
 
 struct DecLayout {
   uint64_t cnt, redo_n, err, zero_end, bits, bits_end;
-  uint64_t symbols, tab, recon, off_pay, off_out, off_coef, scan, tot, plan, lut, redo;
+  uint64_t symbols, tab, recon, off_pay, off_out, off_coef, scan, tot, plan, lut, lut2, sub, redo;
   uint64_t total;
 };
 
@@ -326,6 +326,8 @@ DecLayout dec_layout(const Geo &g, uint32_t dtype, uint32_t nfaults, bool small_
   L.tot = take(24);
   L.plan = take(plan_bytes(nfaults));
   L.lut = take(4ull << kLutBits);
+  L.lut2 = take(4ull << kLutBits);
+  L.sub = take(4ull * kSubMax);
   L.redo = take(8ull * kMaxRedo);
   L.total = at;
   return L;
@@ -1432,6 +1434,8 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     dw.off_coef = (uint32_t *)(w + f.L.off_coef);
     dw.scan_part = (uint64_t *)(w + f.L.scan);
     dw.lut = (uint32_t *)(w + f.L.lut);
+    dw.lut2 = (uint32_t *)(w + f.L.lut2);
+    dw.sub = (uint32_t *)(w + f.L.sub);
     dw.redo_n = (uint32_t *)(w + f.L.redo_n);
     dw.redo = (uint64_t *)(w + f.L.redo);
     dw.err = (uint32_t *)(w + f.L.err);

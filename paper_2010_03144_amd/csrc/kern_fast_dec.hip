@@ -68,96 +68,141 @@ template <typename... V> __device__ inline void drow_fence(V &...v) {
 }
 
 constexpr uint32_t kDecThreads = 256;
-constexpr uint32_t kWin = 20;  // payload words staged per lane for half a plane
-constexpr uint32_t kLongSyms = 5120;  // symbols of codes longer than kLutBits kept in LDS
+constexpr uint32_t kRing = 16;                 // payload words per lane in LDS
+constexpr uint32_t kRingGroups = kRing / 4;    // 16-byte groups of the ring
 
-// The payload bits of one lane's block, staged three rows at a time into a
-// window of kWin words in LDS (word w of thread t at win[w * kDecThreads + t],
-// so a wave's accesses to one word index fall in distinct banks).  Three rows
-// of a 6x6x6 block hold at most 18 codewords of <= 24 bits (432 bits); the
-// window starts at the 16-byte group holding the current word (<= 127 bits
-// of skew), so 20 words always cover them, the word after the last bit
-// included.
+// The payload bits of one lane's block, read through a ring of kRing words
+// in LDS (word r of thread t at win[r * kDecThreads + t], so a wave's
+// accesses to one word index fall in distinct banks).  The ring fills with
+// the stream's 16-byte groups as decoding reaches them, each group fetched
+// once: group k, counted from the group that holds the block's first payload
+// bit, sits in slot k % kRingGroups.  stage<N>() makes the ring hold the next
+// N codewords of at most kMaxLen bits and the 64 bits a lookup reads past
+// them; with the current position's offset inside its group (< 128 bits)
+// that is at most kRingGroups groups, the oldest of which it may overwrite
+// (none of their words is read again).  The 64 bits from the current word
+// on sit in a register pair, refilled with one LDS read per 32 bits consumed.
 struct Window {
-  const uint8_t *pay;  // the block's first payload word
+  const uint8_t *g0;   // the 16-byte group holding the block's first payload bit
   const uint8_t *end;  // end of the readable stream bytes
-  uint32_t *win;       // this thread's column of the LDS window
-  uint32_t pos;        // bits of the block consumed
-  uint32_t lp;         // bit position inside the window
+  uint32_t *win;       // this thread's column of the ring
+  uint32_t skew;       // bits from g0 to the block's first payload bit
+  uint32_t ap;         // current bit position, from g0
+  uint32_t ng;         // groups fetched so far
+  uint64_t bb;         // stream bits [32 * (ap >> 5), 32 * (ap >> 5) + 64)
+  uint4 pf;            // group ng, fetched ahead
 
-  __device__ void stage() {
-    const uint8_t *a = pay + 4ull * (pos >> 5);
-    const uint8_t *g = a - ((uintptr_t)a & 15);
-    lp = (uint32_t)(a - g) * 8 + (pos & 31);
-    constexpr uint32_t NG = kWin / 4;
-    if (__builtin_expect(g + 16 * NG <= end, 1)) {
-      uint4 v[NG];
-#pragma unroll
-      for (uint32_t t = 0; t < NG; t++) v[t] = ((const uint4 *)g)[t];
-#pragma unroll
-      for (uint32_t t = 0; t < NG; t++) {
-        win[(4 * t + 0) * kDecThreads] = v[t].x;
-        win[(4 * t + 1) * kDecThreads] = v[t].y;
-        win[(4 * t + 2) * kDecThreads] = v[t].z;
-        win[(4 * t + 3) * kDecThreads] = v[t].w;
-      }
-    } else {  // the window reaches past the stream: word by word, zeros beyond
-#pragma unroll 1
-      for (uint32_t q = 0; q < kWin; q++)
-        win[q * kDecThreads] = g + 4 * (q + 1) <= end ? ((const uint32_t *)g)[q] : 0u;
+  __device__ inline void init(const uint8_t *pay, const uint8_t *e, uint32_t *w) {
+    g0 = pay - ((uintptr_t)pay & 15);
+    skew = (uint32_t)(pay - g0) * 8;
+    ap = skew;
+    ng = 0;
+    end = e;
+    win = w;
+    bb = 0;
+  }
+  __device__ inline uint32_t word(uint32_t i) const { return win[(i % kRing) * kDecThreads]; }
+  __device__ inline uint4 fetch(uint32_t gi) const {
+    const uint8_t *ga = g0 + 16ull * gi;
+    uint4 v;
+    if (__builtin_expect(ga + 16 <= end, 1)) {
+      v = *(const uint4 *)ga;
+    } else {  // the group reaches past the stream: word by word, zeros beyond
+      const uint32_t *gw = (const uint32_t *)ga;
+      v.x = ga + 4 <= end ? gw[0] : 0u;
+      v.y = ga + 8 <= end ? gw[1] : 0u;
+      v.z = ga + 12 <= end ? gw[2] : 0u;
+      v.w = 0u;
     }
+    return v;
+  }
+  __device__ inline void put(uint32_t gi, const uint4 &v) {
+    uint32_t *d = win + (gi % kRingGroups) * 4 * kDecThreads;
+    d[0] = v.x;
+    d[kDecThreads] = v.y;
+    d[2 * kDecThreads] = v.z;
+    d[3 * kDecThreads] = v.w;
+  }
+  // Every stage after the first holds group ng in registers (pf), fetched
+  // one stage earlier so that its latency hides behind that stage's
+  // decoding; a stage that needs more than that group waits for the rest.
+  template <uint32_t N> __device__ inline void stage() {
+    static_assert(((127 + N * kMaxLen + 63) >> 7) + 1 <= kRingGroups, "N codewords fit the ring");
+    const uint32_t last = (ap + N * kMaxLen + 63) >> 7;  // last group the next N codewords may touch
+    const bool first = ng == 0;
+    bool have = !first;
+    if (have && ng <= last) {
+      put(ng, pf);
+      ng++;
+      have = false;
+    }
+#pragma unroll 1
+    for (; ng <= last; ng++) put(ng, fetch(ng));
+    if (!have) pf = fetch(ng);
+    if (first) bb = ((uint64_t)word(ap >> 5) << 32) | word((ap >> 5) + 1);
   }
   // the next 32 bits of the block (most significant first)
-  __device__ inline uint32_t peek() const {
-    const uint32_t w = lp >> 5;
-    const uint64_t two = ((uint64_t)win[w * kDecThreads] << 32) | win[(w + 1) * kDecThreads];
-    return (uint32_t)((two << (lp & 31)) >> 32);
+  __device__ inline uint32_t peek() const { return (uint32_t)((bb << (ap & 31)) >> 32); }
+  __device__ inline void skip(uint32_t n) {  // n < 32
+    const uint32_t na = ap + n;
+    if ((na >> 5) != (ap >> 5)) bb = (bb << 32) | word((na >> 5) + 1);
+    ap = na;
   }
-  __device__ inline void skip(uint32_t n) {
-    lp += n;
-    pos += n;
-  }
+  __device__ inline uint32_t pos() const { return ap - skew; }
 };
 
-// Canonical decoding tables in LDS: the prefix table, first code, count and
-// first position per length, and the symbols of the long codes from
-// position long_base on.
+// Canonical decoding tables in LDS: the two-level prefix table (lut2), the
+// first kSubLds entries of its second level, and first code, count and first
+// position per length for prefixes that keep the search.
+constexpr uint32_t kSubLds = 3840;
 struct DecLds {
   uint32_t lut[1u << kLutBits];
   uint32_t first[kMaxLen + 2], count[kMaxLen + 2], start[kMaxLen + 2];
-  uint32_t long_base, long_n;
-  uint16_t long_sym[kLongSyms];
+  uint32_t sub_lds;  // second-level entries held in sub
+  uint32_t sub[kSubLds];
 };
 
 // Decode one symbol.  The prefix table resolves codewords of up to kLutBits
-// bits; for a longer one it gives the range of lengths whose codes start
-// with that prefix, and the first length whose codes hold the top bits
-// wins.  The symbols of long codes come from LDS, or (the rarest codes of a
-// large codebook, beyond kLongSyms) from the global table, waiting for that
-// load inside its own branch.  Sets *bad when no codeword matches.  Reading
+// bits; a longer one takes one second-level lookup indexed by the bits after
+// the prefix (from LDS, or from the global table past kSubLds entries,
+// waiting for that load inside its own branch).  Prefixes without a second
+// level search the lengths their prefix allows, the first length whose codes
+// hold the top bits winning.  Sets *bad when no codeword matches.  Reading
 // past the block's words is checked once, at the end of the block.
-__device__ inline uint32_t decode_sym(Window &br, const DecLds &t, const uint16_t *gsym, bool *bad) {
+__device__ inline uint32_t decode_sym(Window &br, const DecLds &t, const uint32_t *gsub, const uint16_t *gsym,
+                                      bool *bad) {
   const uint32_t v = br.peek();
   const uint32_t e = t.lut[v >> (32 - kLutBits)];
   uint32_t len = e & 0xFFu, sym = e >> 8;
   if (__builtin_expect(len == 0, 0)) {
-    const uint32_t lmin = (e >> 8) & 0xFFu, lmax = e >> 16;
     sym = 0;
+    if (e == 0) {
+      // no codeword starts with the prefix
+    } else if (!(e & kLut2Search)) {
+      const uint32_t wb = (e >> 8) & 0xFu;  // 1..kMaxLen - kLutBits
+      const uint32_t idx = (e >> 12) + ((v << kLutBits) >> (32 - wb));
+      uint32_t se;
+      if (idx < t.sub_lds) {
+        se = t.sub[idx];
+      } else {
+        se = gsub[idx];
+        __asm__ volatile("" : "+v"(se));
+      }
+      len = se & 0xFFu;
+      sym = se >> 8;
+    } else {
+      const uint32_t lmin = (e >> 8) & 0xFFu, lmax = (e >> 16) & 0xFFu;
 #pragma unroll 1
-    for (uint32_t l = lmin; l <= lmax; l++) {
-      const uint32_t c = v >> (32 - l);
-      const uint32_t f = t.first[l], n = t.count[l];
-      if (c >= f && c - f < n) {
-        const uint32_t idx = t.start[l] + c - f - t.long_base;
-        if (idx < t.long_n) {
-          sym = t.long_sym[idx];
-        } else {
-          uint32_t gs = gsym[t.long_base + idx];
+      for (uint32_t l = lmin; l <= lmax; l++) {
+        const uint32_t c = v >> (32 - l);
+        const uint32_t f = t.first[l], n = t.count[l];
+        if (c >= f && c - f < n) {
+          uint32_t gs = gsym[t.start[l] + c - f];
           __asm__ volatile("" : "+v"(gs));
           sym = gs;
+          len = l;
+          break;
         }
-        len = l;
-        break;
       }
     }
     if (len == 0) {
@@ -259,10 +304,7 @@ __device__ __forceinline__ DecOut decode_lanes(const uint8_t *__restrict__ s, co
   }
   const uint32_t nw = (uint32_t)(w.off_pay[blk + 1] - w.off_pay[blk]);
   Window br;
-  br.pay = s + h.off_payload + 4ull * w.off_pay[blk];
-  br.end = s + h.total;
-  br.win = win;
-  br.pos = 0;
+  br.init(s + h.off_payload + 4ull * w.off_pay[blk], s + h.total, win);
   bool bad = false;
   uint32_t used_out = 0;
   uint64_t sum = 0;
@@ -286,7 +328,7 @@ __device__ __forceinline__ DecOut decode_lanes(const uint8_t *__restrict__ s, co
 #pragma unroll
     for (int j = 0; j < B1; j++) {
       if (!FULL && (uint32_t)j >= n1) break;
-      if (j % 3 == 0) br.stage();
+      if (j % 2 == 0) br.stage<2 * B2>();
       T Aj = A0 + beta1 * ((T)j - c1);
       dpin(Aj);
       T rowold[B2], rv[B2];
@@ -295,7 +337,7 @@ __device__ __forceinline__ DecOut decode_lanes(const uint8_t *__restrict__ s, co
 #pragma unroll
       for (int k = 0; k < B2; k++) {
         const bool v = FULL || (uint32_t)k < n2;
-        const uint32_t sym = v ? decode_sym(br, tl, w.symbols, &bad) : kRadius;
+        const uint32_t sym = v ? decode_sym(br, tl, w.sub, w.symbols, &bad) : kRadius;
         const T a = Pw[j][k];
         rowold[k] = a;
         const T b = j > 0 ? Pw[j - 1][k] : (T)0;
@@ -357,10 +399,10 @@ __device__ __forceinline__ DecOut decode_lanes(const uint8_t *__restrict__ s, co
       }
 #pragma unroll
       for (int k = 0; k < B2; k++) Sv[k] = rowold[k];
-      drow_fence(cprev, sum, br.lp);
+      drow_fence(cprev, sum, br.ap, br.bb);
     }
   }
-  if (used_out != nout || br.pos > nw * 32u) bad = true;
+  if (used_out != nout || br.pos() > nw * 32u) bad = true;
   res.bad = bad;
   res.sum = sum;
   const uint64_t *sumdc = (const uint64_t *)(s + h.off_sumdc);
@@ -378,14 +420,13 @@ __device__ __forceinline__ DecOut decode_lanes(const uint8_t *__restrict__ s, co
 }
 
 // One lane's 2D block of B1 rows by B2 columns, a row per iteration with the
-// previous reconstructed row in registers; the window is staged once per row
-// (B2 codewords of <= 24 bits plus the <= 127-bit skew fit in kWin words for
-// B2 <= 16).
+// previous reconstructed row in registers; the ring is staged every 8
+// codewords (every row when B2 is not a multiple of 8).
 template <typename T, int B1, int B2, bool FULL, bool REG, bool WIDE, int MODE>
 __device__ __forceinline__ DecOut decode_rows(const uint8_t *__restrict__ s, const Header &h, const Geo &g,
                                               const DecWork &w, const PlanDev &plan, T *out, const DecLds &tl,
                                               uint32_t *win, uint64_t blk, bool active, const Region &reg) {
-  static_assert(B2 * kMaxLen + 127 + 32 <= 32 * (int)kWin, "a row's codewords fit the window");
+  constexpr uint32_t kRowStage = B2 % 8 == 0 ? 8 : B2;  // codewords per ring stage
   static_assert(!(REG && FULL), "a region launch takes the masked path");
   const Box bx = box_of(g, blk);
   const uint64_t org = fidx(g, bx, 0, 0, 0);
@@ -418,10 +459,7 @@ __device__ __forceinline__ DecOut decode_rows(const uint8_t *__restrict__ s, con
   }
   const uint32_t nw = (uint32_t)(w.off_pay[blk + 1] - w.off_pay[blk]);
   Window br;
-  br.pay = s + h.off_payload + 4ull * w.off_pay[blk];
-  br.end = s + h.total;
-  br.win = win;
-  br.pos = 0;
+  br.init(s + h.off_payload + 4ull * w.off_pay[blk], s + h.total, win);
   bool bad = false;
   uint32_t used_out = 0;
   uint64_t sum = 0;
@@ -435,7 +473,6 @@ __device__ __forceinline__ DecOut decode_rows(const uint8_t *__restrict__ s, con
 #pragma unroll 1
   for (int j = 0; j < B1; j++) {
     if (!FULL && (uint32_t)j >= n1) break;
-    br.stage();
     T Aj = A0 + beta1 * ((T)j - c1);
     dpin(Aj);
     T cprev = 0, fold = 0;
@@ -443,8 +480,9 @@ __device__ __forceinline__ DecOut decode_rows(const uint8_t *__restrict__ s, con
     const uint32_t prow = (uint32_t)j * n2;  // point index of the row's start
 #pragma unroll
     for (int k = 0; k < B2; k++) {
+      if (k % kRowStage == 0) br.stage<kRowStage>();
       const bool v = FULL || (uint32_t)k < n2;
-      const uint32_t sym = v ? decode_sym(br, tl, w.symbols, &bad) : kRadius;
+      const uint32_t sym = v ? decode_sym(br, tl, w.sub, w.symbols, &bad) : kRadius;
       const T b = Pr[k], f = fold;  // r(j-1,k), r(j-1,k-1)
       fold = b;
       const T lor = (b + cprev) - f;
@@ -493,9 +531,9 @@ __device__ __forceinline__ DecOut decode_rows(const uint8_t *__restrict__ s, con
       for (int k = 0; k < B2; k++)
         if (FULL || (uint32_t)k < n2) *(T *)(dst + k * sizeof(T)) = rv[k];
     }
-    drow_fence(sum, br.lp);
+    drow_fence(sum, br.ap, br.bb);
   }
-  if (used_out != nout || br.pos > nw * 32u) bad = true;
+  if (used_out != nout || br.pos() > nw * 32u) bad = true;
   res.bad = bad;
   res.sum = sum;
   const uint64_t *sumdc = (const uint64_t *)(s + h.off_sumdc);
@@ -513,21 +551,16 @@ __device__ __forceinline__ DecOut decode_rows(const uint8_t *__restrict__ s, con
 }
 
 // The decoding tables in LDS (every thread of the work-group takes part).
-__device__ inline void load_tables(DecLds &tl, const DecWork &w, const Header &h) {
-  for (uint32_t t = threadIdx.x; t < (1u << kLutBits); t += blockDim.x) tl.lut[t] = w.lut[t];
+__device__ inline void load_tables(DecLds &tl, const DecWork &w) {
+  for (uint32_t t = threadIdx.x; t < (1u << kLutBits); t += blockDim.x) tl.lut[t] = w.lut2[t];
   if (threadIdx.x < kMaxLen + 2) {
     tl.first[threadIdx.x] = w.tab->first[threadIdx.x];
     tl.count[threadIdx.x] = w.tab->count[threadIdx.x];
     tl.start[threadIdx.x] = w.tab->start[threadIdx.x];
   }
-  // symbols of the codes longer than kLutBits, as many as fit
-  const uint32_t lb = w.tab->start[kLutBits + 1];
-  const uint32_t ln = h.n_sym > lb ? min(h.n_sym - lb, kLongSyms) : 0u;
-  for (uint32_t t = threadIdx.x; t < ln; t += blockDim.x) tl.long_sym[t] = w.symbols[lb + t];
-  if (threadIdx.x == 0) {
-    tl.long_base = lb;
-    tl.long_n = ln;
-  }
+  const uint32_t n = min(w.tab->sub_n, kSubLds);
+  for (uint32_t t = threadIdx.x; t < n; t += blockDim.x) tl.sub[t] = w.sub[t];
+  if (threadIdx.x == 0) tl.sub_lds = n;
   __syncthreads();
 }
 
@@ -547,8 +580,8 @@ k_decode_fast(JobTab tab) {
   const Launch L = jw.J->L;
   if (*w.err) return;  // invalid codebook or block table: nothing is read
   __shared__ DecLds tl;
-  __shared__ uint32_t win[kWin * kDecThreads];
-  load_tables(tl, w, h);
+  __shared__ uint32_t win[kRing * kDecThreads];
+  load_tables(tl, w);
   constexpr int M = FAULTS ? kDFaults : kDProd;
   const Region &reg = jw.J->reg, &rb = jw.J->rblk;
   if constexpr (FAULTS) {

@@ -231,6 +231,9 @@ __global__ void __launch_bounds__(kDecTabThreads) k_dectab(JobTab tb) {
   __shared__ uint16_t short_sym[1u << kLutBits];  // symbols at positions < 2^kLutBits
   __shared__ uint32_t first[kMaxLen + 2], cnt[kMaxLen + 2], start[kMaxLen + 2];
   __shared__ uint32_t smin, smax, bad, unordered, hmis;
+  __shared__ uint32_t pe[1u << kLutBits];       // lut entry of each prefix
+  __shared__ uint32_t poff[(1u << kLutBits) + 1];  // second-level offset of each prefix
+  __shared__ uint32_t ptot[kDecTabWaves];
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool small = n_sym <= 4096;
   // a header the caller supplied (the host sized everything from it) must be
@@ -471,6 +474,76 @@ __global__ void __launch_bounds__(kDecTabThreads) k_dectab(JobTab tb) {
       if (lmin) e = (lmax << 16) | (lmin << 8);
     }
     w.lut[v] = e;
+    pe[v] = e;
+  }
+  __syncthreads();
+  // The specialised decoder's two-level table (lut2, sub): a prefix that
+  // only codewords longer than kLutBits start with gets 2^(lmax - kLutBits)
+  // second-level entries, one per value of the bits after it, each holding
+  // the first length lmin..lmax whose codes take those bits (the rule of
+  // bit-by-bit decoding again).  Offsets come from an exclusive scan over the
+  // prefixes; beyond kSubMax entries in all the long prefixes keep the search.
+  constexpr uint32_t kNP = 1u << kLutBits, kPer = kNP / kDecTabThreads;
+  static_assert(kPer * kDecTabThreads == kNP, "prefixes per thread");
+  uint32_t np[kPer], mine = 0;
+#pragma unroll
+  for (uint32_t u = 0; u < kPer; u++) {
+    const uint32_t e = pe[tid * kPer + u];
+    np[u] = (e && !(e & 0xFFu)) ? 1u << ((e >> 16) - kLutBits) : 0u;
+    mine += np[u];
+  }
+  uint32_t inc = mine;
+#pragma unroll
+  for (uint32_t d = 1; d < 64; d <<= 1) {
+    const uint32_t u = (uint32_t)__shfl_up((int)inc, d);
+    if (lane >= d) inc += u;
+  }
+  if (lane == 63) ptot[wave] = inc;
+  __syncthreads();
+  uint32_t pre = 0, total = 0;
+  for (uint32_t q = 0; q < kDecTabWaves; q++) {
+    pre += q < wave ? ptot[q] : 0u;
+    total += ptot[q];
+  }
+  uint32_t o = pre + inc - mine;
+#pragma unroll
+  for (uint32_t u = 0; u < kPer; u++) {
+    poff[tid * kPer + u] = o;
+    o += np[u];
+  }
+  if (tid == 0) poff[kNP] = total;
+  __syncthreads();
+  const bool build = total <= kSubMax;
+#pragma unroll
+  for (uint32_t u = 0; u < kPer; u++) {
+    const uint32_t v = tid * kPer + u, e = pe[v];
+    uint32_t e2 = e;
+    if (e && !(e & 0xFFu)) e2 = build ? (poff[v] << 12) | (((e >> 16) - kLutBits) << 8) : (kLut2Search | e);
+    w.lut2[v] = e2;
+  }
+  if (tid == 0) w.tab->sub_n = build ? total : 0u;
+  if (!build) return;
+  for (uint32_t idx = tid; idx < total; idx += kDecTabThreads) {
+    // the prefix whose entries hold idx: the last with poff[p] <= idx
+    uint32_t lo = 0, hi = kNP;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (poff[mid] <= idx) lo = mid;
+      else hi = mid;
+    }
+    const uint32_t e = pe[lo], lmin = (e >> 8) & 0xFFu, lmax = e >> 16, wb = lmax - kLutBits;
+    const uint32_t c = (lo << wb) | (idx - poff[lo]);  // the first lmax bits
+    uint32_t se = 0;
+    for (uint32_t l = lmin; l <= lmax; l++) {
+      const uint32_t cl = c >> (lmax - l);
+      if (cnt[l] && cl >= first[l] && cl - first[l] < cnt[l]) {
+        const uint32_t pos = start[l] + cl - first[l];
+        const uint32_t sy = pos < kNP ? (uint32_t)short_sym[pos] : (uint32_t)w.symbols[pos];
+        se = (sy << 8) | l;
+        break;
+      }
+    }
+    w.sub[idx] = se;
   }
 }
 

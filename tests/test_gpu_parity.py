@@ -392,11 +392,14 @@ def test_output_too_small_writes_nothing(codec):
     assert bool((out[s_r.size:] == 0xA5).all())
 
 
-@pytest.mark.parametrize("shape,eb", [((48, 42, 36), 2e-5), ((102, 102, 102), 1e-5)])
+@pytest.mark.parametrize("shape,eb", [((48, 42, 36), 2e-5), ((102, 102, 102), 1e-5),
+                                      ((102, 102, 102), 1e-6)])
 def test_large_codebooks_decode_like_the_oracle(codec, shape, eb):
-    # tens of thousands of symbols: long codewords beyond the specialised
-    # decoder's LDS tables send blocks to the generic path (and, past the
-    # re-run queue's capacity, the whole field)
+    # tens of thousands of symbols: the specialised decoder's second-level
+    # table outgrows its LDS share (entries past it come from the global
+    # table), and at 1e-6 (65,529 symbols, 65,830 second-level entries) it
+    # exceeds the 65,536 entries built, so the long prefixes take the length
+    # search
     x = synth.grf_field(shape, seed=9)
     s, rep = check_roundtrip(codec, x, (6, 6, 6), eb)
     n_sym = int(np.frombuffer(s[76:80].tobytes(), "<u4")[0])
