@@ -238,7 +238,8 @@ def batch_bench(codec, torch, reps=3, plain_loop=True):
 def block_size_report(codec, xd, ebs=(1e-2, 1e-3, 1e-4)):
     """Rate-distortion of cubic blocks 4..20 on a 256^3 crop of the field
     (Sec. 6.2's exploration), and the block the autotuner picks for the whole
-    field at each bound from four 64^3 samples."""
+    field at each bound from four 64^3 samples (among shapes with specialised
+    kernels; lowest_rate_block is the pick among all)."""
     from paper_2010_03144_amd import blocksize
     crop = xd[:256, :256, :256].contiguous()
     rd = blocksize.rate_distortion(codec, crop, ebs)
@@ -247,7 +248,8 @@ def block_size_report(codec, xd, ebs=(1e-2, 1e-3, 1e-4)):
     picks = {}
     for eb in ebs:
         best, rates = blocksize.best_block(codec, xd, eb)
-        picks[f"{eb:g}"] = {"block": best, "bits_per_value": {str(e): round(r, 4) for e, r in rates.items()}}
+        picks[f"{eb:g}"] = {"block": best, "lowest_rate_block": min(rates, key=rates.get),
+                            "bits_per_value": {str(e): round(r, 4) for e, r in rates.items()}}
     return {"crop": "256^3 corner of the 512^3 field, REL eb, ABFT on", "rate_distortion": table,
             "autotuned_block": picks}
 

@@ -67,10 +67,21 @@ def sample_views(x, side=64, count=4):
     return views
 
 
-def best_block(codec, x, eb, edges=CUBES, side=64, count=4):
+def fast_edges(nd):
+    """Edges of the cubic (square) block shapes with specialised kernels in
+    `nd` dimensions; other shapes run the wave-per-block and one-thread
+    kernels, tens of times slower on a large field."""
+    from .sdcsz import SHAPE_CLASSES
+    return {blk[0] for blk, d in SHAPE_CLASSES if d == nd and len(set(blk)) == 1}
+
+
+def best_block(codec, x, eb, edges=CUBES, side=64, count=4, fast_only=True):
     """The block edge with the lowest bit-rate at the value-range-relative
     bound eb of x (applied to the samples as the same absolute bound) on
-    samples of x, and the measured bits per value per edge."""
+    samples of x, and the measured bits per value per edge (every edge of
+    `edges`).  With fast_only the pick is made among the edges whose shape
+    has specialised kernels (when `edges` holds any), since a slightly lower
+    rate does not pay for a many times slower compressor."""
     views = sample_views(x, side, count)
     nd = x.dim()
     eb_abs = eb * float(x.max().double() - x.min().double())
@@ -83,5 +94,6 @@ def best_block(codec, x, eb, edges=CUBES, side=64, count=4):
                 raise RuntimeError(f"compress failed: {rc}")
             bits += 8.0 * int(s.numel())
         rates[e] = bits / sum(v.numel() for v in views)
-    best = min(rates, key=rates.get)
+    pool = [e for e in rates if e in fast_edges(nd)] if fast_only else []
+    best = min(pool or rates, key=rates.get)
     return best, rates

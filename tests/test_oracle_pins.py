@@ -495,8 +495,14 @@ def test_block_size_tools_on_the_oracle():
     for e, rows in rd.items():
         (eb1, b1, p1, _), (eb2, b2, p2, _) = rows
         assert b2 > b1 and p2 > p1  # a tighter bound costs bits and buys PSNR
-    best, rates = blocksize.best_block(_OracleCodec(), x, 1e-3, edges=(4, 6, 10), side=16, count=2)
+    best, rates = blocksize.best_block(_OracleCodec(), x, 1e-3, edges=(4, 6, 10), side=16, count=2,
+                                       fast_only=False)
     assert best == min(rates, key=rates.get) and set(rates) == {4, 6, 10}
+    # by default the pick stays among shapes with specialised kernels (6^3 in 3D)
+    best, rates2 = blocksize.best_block(_OracleCodec(), x, 1e-3, edges=(4, 6, 10), side=16, count=2)
+    assert best == 6 and rates2 == rates
+    assert blocksize.best_block(_OracleCodec(), x, 1e-3, edges=(4, 10), side=16, count=2)[0] == \
+        min((4, 10), key=rates.get)
     eb_abs = 1e-3 * float(x.max() - x.min())
     v = blocksize.sample_views(x, 16, 2)[0]
     rc, s, _ = ref.compress(v.numpy(), (6, 6, 6), eb_abs, eb_mode="abs")
