@@ -226,6 +226,33 @@ int sdcsz_decompress_region(const void *d_stream, uint64_t stream_size, const ui
                             sdcsz_report *h_rep, void *d_ws, uint64_t ws_size, void *stream);
 
 /*
+ * Repeated random access to one stream (Sec. 5.1): sdcsz_region_prepare
+ * builds the stream's decoding tables and its per-block offsets (a scan of
+ * the whole block table) in d_ws, together with a copy of the header;
+ * sdcsz_decompress_region_prepared then decodes a box [lo, hi) with them,
+ * touching only the blocks that intersect it (a box that is the whole field
+ * takes the full-field decoder).  Each prepared call first checks on the
+ * device that the stream still carries the header the state was built
+ * from, and returns SDCSZ_EFORMAT if not; the stream's other bytes must not
+ * change in between (ABFT streams would report the blocks that then fail
+ * their checksum).
+ *   h_header  host, the stream's 192 header bytes (as compression returned
+ *             them), or NULL to read them from the device (one more
+ *             synchronisation); checked against the stream on the device
+ *   d_ws      device workspace of ws_size >= sdcsz_decompress_workspace_size()
+ *             for the stream's parameters; the same buffer, unchanged by other
+ *             calls, for the prepare call and the calls that use it
+ *   h_lo, h_hi, d_out, out_cap, h_rep: as for sdcsz_decompress_region
+ * Return codes as for sdcsz_decompress_region.  Each call synchronises
+ * `stream` once at its end.
+ */
+int sdcsz_region_prepare(const void *d_stream, uint64_t stream_size, const void *h_header, void *d_ws,
+                         uint64_t ws_size, void *stream);
+int sdcsz_decompress_region_prepared(const void *d_stream, uint64_t stream_size, const void *h_header,
+                                     const uint64_t *h_lo, const uint64_t *h_hi, void *d_out, uint64_t out_cap,
+                                     sdcsz_report *h_rep, void *d_ws, uint64_t ws_size, void *stream);
+
+/*
  * Lossless stage (the last pass of Algorithm 1 and the first of Algorithm 2):
  * the per-block metadata that Huffman coding leaves redundant -- the block
  * table (payload words; outliers << 1 | regression flag) and, with ABFT,

@@ -290,7 +290,7 @@ CompLayout comp_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
 
 struct DecLayout {
   uint64_t cnt, redo_n, err, zero_end, bits, bits_end;
-  uint64_t symbols, tab, recon, off_pay, off_out, off_coef, scan, tot, plan, lut, lut2, sub, redo;
+  uint64_t symbols, tab, recon, off_pay, off_out, off_coef, scan, tot, plan, lut, lut2, sub, redo, hdr;
   uint64_t total;
 };
 
@@ -329,6 +329,7 @@ DecLayout dec_layout(const Geo &g, uint32_t dtype, uint32_t nfaults, bool small_
   L.lut2 = take(4ull << kLutBits);
   L.sub = take(4ull * kSubMax);
   L.redo = take(8ull * kMaxRedo);
+  L.hdr = take(kHeader);
   L.total = at;
   return L;
 }
@@ -1282,6 +1283,7 @@ struct DecItem {  // one stream of a decompression call
   uint32_t n_faults;
   const uint8_t *h_header;  // the caller's copy of the header, or null
   bool small_recon;  // the no-allocation call: no recon scratch for the specialised decoder
+  uint32_t prep;     // region state in the workspace: 0 none, 1 build it (no decoding), 2 reuse it
   int rc;
   sdcsz_report rep;
   Header h;
@@ -1376,7 +1378,7 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
       d.need = d.g.n_values * vbytes(d.h.dtype);
     }
     if (d.rc) continue;
-    if (d.out_cap < d.need || (d.need && !d.d_out)) {
+    if (d.prep != 1 && (d.out_cap < d.need || (d.need && !d.d_out))) {
       d.rc = SDCSZ_ENOSPC;
       continue;
     }
@@ -1463,12 +1465,14 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     J.stat_words = C_N + 1;
     J.dtype = d.h.dtype;
     J.abft = d.h.abft;
+    J.hdr_keep = (uint32_t *)(w + f.L.hdr);
     if (!f.plan.empty()) HIPCHK(upload_plan(f.plan, f.pb, f.fl, f.up, w + f.L.plan, J.plan, st));
   }
   // t_list, t_redo: a wave per block; t_flist: the fault-applying
   // instantiation over the plans' lists
   Tab t_zero, t_plan, t_one, t_s1, t_fast[kClasses][2], t_flist[kClasses][2], t_gen[2], t_list[2], t_redo[2];
-  uint32_t lds_list[2] = {}, lds_redo[2] = {};
+  Tab t_wreg[2];  // regions of few blocks: a wave per block
+  uint32_t lds_list[2] = {}, lds_redo[2] = {}, lds_wreg[2] = {};
   uint64_t nb_dec[kClasses][2] = {};
   for (uint32_t j = 0; j < nj; j++)
     if (fp[j].fast) nb_dec[fp[j].cls][jobs[j].dtype] += jobs[j].g.n_blocks;
@@ -1482,9 +1486,10 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     if (!fp[j].fl.empty()) t_flist[fp[j].cls][J.dtype].add(j, grid_for(fp[j].fl.size(), 64));
     t_one.add(j, 1);
     t_s1.add(j, scan_chunks(J.g.n_blocks));
-    if (fp[j].fast && J.mode == 2) {
-      // the box of blocks the region touches, one lane each (masked path)
-      uint64_t nbox = 1;
+    uint64_t nbox = 0;
+    if (J.mode == 2) {
+      // the box of blocks the region touches
+      nbox = 1;
       for (int a = 0; a < 3; a++) {
         J.rblk.lo[a] = J.reg.lo[a] / J.g.b[a];
         J.rblk.hi[a] = (J.reg.hi[a] - 1) / J.g.b[a] + 1;
@@ -1492,6 +1497,14 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
       }
       std::memset(&J.L, 0, sizeof(J.L));
       J.L.shell_count = nbox;
+    }
+    const uint32_t wlds = wave_lds_bytes(J.g, vbytes(J.dtype));
+    if (J.mode == 2 && nbox <= kWaveRegionBlocks && wlds <= kWaveLdsMax) {
+      // few blocks: a wave each (one block's serial decoding time in all)
+      t_wreg[J.dtype].add(j, nbox);
+      lds_wreg[J.dtype] = std::max(lds_wreg[J.dtype], wlds);
+    } else if (fp[j].fast && J.mode == 2) {
+      // one lane per block of the box (masked path)
       const uint32_t ln = ln_dec[fp[j].cls][J.dtype];
       t_fast[fp[j].cls][J.dtype].add(j, grid_for(nbox, ln));
     } else if (fp[j].fast) {
@@ -1517,6 +1530,8 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
     for (int d = 0; d < 2; d++) up.tabs.push_back(&t_fast[c][d]);
   for (int c = 0; c < kClasses; c++)
     for (int d = 0; d < 2; d++) up.tabs.push_back(&t_flist[c][d]);
+  up.tabs.push_back(&t_wreg[0]);
+  up.tabs.push_back(&t_wreg[1]);
   const size_t res_bytes = 8ull * (C_N + 1) * nj;
   // caller-given headers go to the end of the batch area (uploaded with the
   // jobs) for k_dectab to check against the streams
@@ -1538,15 +1553,28 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
   auto grid = [](const Tab &t) { return dim3(t.total()); };
   launch(PH_NONE, false, false, k_zero_jobs, grid(t_zero), dim3(256), st, D[0]);
   if (t_plan.total()) launch(PH_NONE, false, false, k_plan_bits, grid(t_plan), dim3(256), st, D[9]);
-  launch(PH_NONE, false, false, k_dectab, grid(t_one), dim3(kDecTabThreads), st, D[1]);
-  bool any_empty = false;
-  for (uint32_t j = 0; j < nj; j++) any_empty |= jobs[j].g.n_blocks == 0;
-  if (any_empty) launch(PH_SCAN_D, true, !t_s1.total(), k_scan2, grid(t_one), dim3(kScanThreads), st, D[1]);
-  if (t_s1.total()) {
-    launch(PH_SCAN_D, !any_empty, false, k_scan1, grid(t_s1), dim3(kScanThreads), st, D[2]);
-    launch(PH_SCAN_D, false, true, k_scan3, grid(t_s1), dim3(kScanThreads), st, D[2]);
+  // region state (single-stream calls only): built once, then reused
+  const uint32_t prep = nj == 1 ? it[item_of[0]].prep : 0u;
+  if (prep == 2) {
+    launch(PH_NONE, false, false, k_hdr_keep, grid(t_one), dim3(64), st, D[1], 2u);
+  } else {
+    launch(PH_NONE, false, false, k_dectab, grid(t_one), dim3(kDecTabThreads), st, D[1]);
+    bool any_empty = false;
+    for (uint32_t j = 0; j < nj; j++) any_empty |= jobs[j].g.n_blocks == 0;
+    if (any_empty) launch(PH_SCAN_D, true, !t_s1.total(), k_scan2, grid(t_one), dim3(kScanThreads), st, D[1]);
+    if (t_s1.total()) {
+      launch(PH_SCAN_D, !any_empty, false, k_scan1, grid(t_s1), dim3(kScanThreads), st, D[2]);
+      launch(PH_SCAN_D, false, true, k_scan3, grid(t_s1), dim3(kScanThreads), st, D[2]);
+    }
+    launch(PH_NONE, false, false, k_dec_check, grid(t_one), dim3(64), st, D[1]);
+    if (prep == 1) launch(PH_NONE, false, false, k_hdr_keep, grid(t_one), dim3(64), st, D[1], 1u);
   }
-  launch(PH_NONE, false, false, k_dec_check, grid(t_one), dim3(64), st, D[1]);
+  if (prep == 1) {
+    // tables and offsets only: no decoding
+    for (int c = 0; c < kClasses; c++)
+      for (int d = 0; d < 2; d++) t_fast[c][d] = Tab(), t_flist[c][d] = Tab();
+    for (int d = 0; d < 2; d++) t_gen[d] = Tab(), t_list[d] = Tab(), t_redo[d] = Tab(), t_wreg[d] = Tab();
+  }
   // plan blocks (full decompression), which the production decoder leaves,
   // beside it on a second stream: the fault-applying instantiation over its
   // lists, a wave per block for the others
@@ -1584,6 +1612,16 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
       pl.fs.push_back([&](bool a, bool b) { launch(PH_DECODE, a, b, k_decode_generic<float>, grid(t_gen[0]), dim3(64), st, D[3]); });
     if (t_gen[1].total())
       pl.fs.push_back([&](bool a, bool b) { launch(PH_DECODE, a, b, k_decode_generic<double>, grid(t_gen[1]), dim3(64), st, D[4]); });
+    if (t_wreg[0].total())
+      pl.fs.push_back([&](bool a, bool b) {
+        launch_shm(PH_DECODE, a, b, k_decode_wave_region<float>, grid(t_wreg[0]), dim3(64), lds_wreg[0], st,
+                   D[10 + 4 * kClasses]);
+      });
+    if (t_wreg[1].total())
+      pl.fs.push_back([&](bool a, bool b) {
+        launch_shm(PH_DECODE, a, b, k_decode_wave_region<double>, grid(t_wreg[1]), dim3(64), lds_wreg[1], st,
+                   D[10 + 4 * kClasses + 1]);
+      });
     pl.run();
   }
   if (any_plan_work && !t_no_side) HIPCHK(t_side.join(st));
@@ -1664,6 +1702,44 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
 // ===========================================================================
 // C ABI
 // ===========================================================================
+// Region decompression (prep 0), building the region state of a stream in
+// the workspace (prep 1: the region is the whole field and nothing is
+// decoded), or a region decoded with that state (prep 2; a region that is
+// the whole field takes the full-field launch, whose output is the same).
+static int region_call(const void *d_stream, uint64_t stream_size, const uint8_t *h_header, const uint64_t *h_lo,
+                const uint64_t *h_hi, void *d_out, uint64_t out_cap, sdcsz_report *h_rep, void *d_ws,
+                uint64_t ws_size, hipStream_t st, uint32_t prep) {
+  DecItem d{};
+  d.d_stream = (const uint8_t *)d_stream;
+  d.stream_size = stream_size;
+  d.d_out = (uint8_t *)d_out;
+  d.out_cap = out_cap;
+  d.mode = 2;
+  d.h_header = h_header;
+  d.prep = prep;
+  int rc = read_headers(&d, 1, nullptr, 0, st);
+  if (rc) return rc;
+  if (d.rc) return d.rc;
+  if (prep != 1 && (!h_lo || !h_hi)) return SDCSZ_EINVAL;
+  const uint32_t off = 3 - d.h.ndim;
+  bool whole = true;
+  for (int a = 0; a < 3; a++) {
+    d.reg.lo[a] = 0;
+    d.reg.hi[a] = a < (int)off || prep == 1 ? d.g.d[a] : 1;
+  }
+  if (prep != 1)
+    for (uint32_t a = 0; a < d.h.ndim; a++) {
+      d.reg.lo[off + a] = h_lo[a];
+      d.reg.hi[off + a] = h_hi[a];
+      whole = whole && h_lo[a] == 0 && h_hi[a] == d.g.d[off + a];
+    }
+  if (prep == 2 && whole) d.mode = 0;
+  rc = decode_batch(&d, 1, (uint8_t *)d_ws, ws_size, st);
+  if (rc == SDCSZ_EHIP) return rc;
+  if (h_rep && (d.rc == SDCSZ_OK || d.rc == SDCSZ_ESDC)) *h_rep = d.rep;
+  return d.rc;
+}
+
 extern "C" {
 
 const char *sdcsz_strerror(int code) {
@@ -1929,30 +2005,21 @@ int sdcsz_verify(const void *d_stream, uint64_t stream_size, void *d_data, uint6
 int sdcsz_decompress_region(const void *d_stream, uint64_t stream_size, const uint64_t *h_lo, const uint64_t *h_hi,
                             void *d_out, uint64_t out_cap, sdcsz_report *h_rep, void *d_ws, uint64_t ws_size,
                             void *stream) {
-  DecItem d{};
-  d.d_stream = (const uint8_t *)d_stream;
-  d.stream_size = stream_size;
-  d.d_out = (uint8_t *)d_out;
-  d.out_cap = out_cap;
-  d.mode = 2;
-  hipStream_t st = (hipStream_t)stream;
-  int rc = read_headers(&d, 1, nullptr, 0, st);
-  if (rc) return rc;
-  if (d.rc) return d.rc;
-  if (!h_lo || !h_hi) return SDCSZ_EINVAL;
-  const uint32_t off = 3 - d.h.ndim;
-  for (int a = 0; a < 3; a++) {
-    d.reg.lo[a] = 0;
-    d.reg.hi[a] = 1;
-  }
-  for (uint32_t a = 0; a < d.h.ndim; a++) {
-    d.reg.lo[off + a] = h_lo[a];
-    d.reg.hi[off + a] = h_hi[a];
-  }
-  rc = decode_batch(&d, 1, (uint8_t *)d_ws, ws_size, st);
-  if (rc == SDCSZ_EHIP) return rc;
-  if (h_rep && (d.rc == SDCSZ_OK || d.rc == SDCSZ_ESDC)) *h_rep = d.rep;
-  return d.rc;
+  return region_call(d_stream, stream_size, nullptr, h_lo, h_hi, d_out, out_cap, h_rep, d_ws, ws_size,
+                     (hipStream_t)stream, 0);
+}
+
+int sdcsz_region_prepare(const void *d_stream, uint64_t stream_size, const void *h_header, void *d_ws,
+                         uint64_t ws_size, void *stream) {
+  return region_call(d_stream, stream_size, (const uint8_t *)h_header, nullptr, nullptr, nullptr, 0, nullptr, d_ws,
+                     ws_size, (hipStream_t)stream, 1);
+}
+
+int sdcsz_decompress_region_prepared(const void *d_stream, uint64_t stream_size, const void *h_header,
+                                     const uint64_t *h_lo, const uint64_t *h_hi, void *d_out, uint64_t out_cap,
+                                     sdcsz_report *h_rep, void *d_ws, uint64_t ws_size, void *stream) {
+  return region_call(d_stream, stream_size, (const uint8_t *)h_header, h_lo, h_hi, d_out, out_cap, h_rep, d_ws,
+                     ws_size, (hipStream_t)stream, 2);
 }
 
 int sdcsz_decompress_batch(sdcsz_dec_item *h_items, uint32_t n, void *d_ws, uint64_t ws_size, void *stream) {

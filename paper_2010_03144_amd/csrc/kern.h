@@ -68,6 +68,7 @@ struct Job {
   uint32_t dtype, abft, predictor, eb_mode, mode, nparts, n_sym;
   uint32_t hist_win;  // codes counted in LDS by the compression kernel (<= kHistWin)
   const uint32_t *hdr_expect;  // decompression: the header the caller gave (device copy), or null
+  uint32_t *hdr_keep;          // region decoding state: the header its tables were built from
   RegTab<float> rtf;
   RegTab<double> rtd;
 };
@@ -128,6 +129,7 @@ __global__ void k_results(JobTab t, uint64_t *dst, uint32_t per);
 __global__ void k_headers(JobTab t, uint8_t *dst);
 __global__ void k_dectab(JobTab t);
 __global__ void k_dec_check(JobTab t);
+__global__ void k_hdr_keep(JobTab t, uint32_t mode);
 
 template <typename T, int ND, int B0, int B1, int B2, bool ABFT, bool WIDE, bool FAULTS>
 __global__ void k_compress_fast(JobTab t);
@@ -160,6 +162,8 @@ template <typename T> __global__ void k_compress_wave_list(JobTab t);
 template <typename T> __global__ void k_redo_wave(JobTab t);
 template <typename T> __global__ void k_decode_wave_list(JobTab t);
 template <typename T> __global__ void k_decode_wave_redo(JobTab t);
+template <typename T> __global__ void k_decode_wave_region(JobTab t);
+constexpr uint64_t kWaveRegionBlocks = 4096;  // regions of at most this many blocks take k_decode_wave_region
 
 template <typename T> __global__ void k_compress_generic(JobTab t);
 template <typename T> __global__ void k_decode_generic(JobTab t);

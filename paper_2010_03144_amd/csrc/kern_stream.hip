@@ -547,6 +547,26 @@ __global__ void __launch_bounds__(kDecTabThreads) k_dectab(JobTab tb) {
   }
 }
 
+// Region decoding state kept in a workspace across calls: mode 1 stores the
+// stream's header beside the tables and offsets built from it; mode 2, a
+// later call that reuses them, first checks that the stream still has that
+// header (and the caller's copy, when given): a mismatch sets the error
+// flag, so that no decoder reads the tables.
+__global__ void __launch_bounds__(64) k_hdr_keep(JobTab t, uint32_t mode) {
+  const Job &J = *job_of(t).J;
+  const uint32_t *src = (const uint32_t *)J.src;
+  __shared__ uint32_t mis;
+  if (threadIdx.x == 0) mis = 0;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < kHeader / 4; i += blockDim.x) {
+    const uint32_t v = src[i];
+    if (mode == 1) J.hdr_keep[i] = v;
+    else if (v != J.hdr_keep[i] || (J.hdr_expect && v != J.hdr_expect[i])) atomicOr(&mis, 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && mis) *J.dw.err = 1;
+}
+
 // The block table must add up to the header's counts (u64 totals of the scan).
 __global__ void __launch_bounds__(64) k_dec_check(JobTab t) {
   const Job &J = *job_of(t).J;

@@ -559,12 +559,19 @@ template <typename T> __global__ void __launch_bounds__(64) k_redo_wave(JobTab t
 // points of 24-bit codewords fits; words beyond it are read from memory).
 constexpr uint32_t kWavePayWords = kMaxBlockPts * kMaxLen / 32 + 2;
 struct WaveDecTab {
-  uint32_t lut[1u << kLutBits];
+  alignas(16) uint32_t lut[1u << kLutBits];
   uint32_t first[kMaxLen + 2], count[kMaxLen + 2], start[kMaxLen + 2];
   uint32_t pay[kWavePayWords];
 };
 __device__ inline void load_wave_tab(WaveDecTab &t, const DecWork &w) {
-  for (uint32_t v = threadIdx.x; v < (1u << kLutBits); v += blockDim.x) t.lut[v] = w.lut[v];
+  // the prefix table 16 bytes per load, all of a lane's loads in flight together
+  constexpr uint32_t kQ = (1u << kLutBits) / 4, kPerLane = kQ / kWL;
+  static_assert(kPerLane * kWL == kQ, "prefix table quarter-words per lane");
+  uint4 q[kPerLane];
+#pragma unroll
+  for (uint32_t u = 0; u < kPerLane; u++) q[u] = ((const uint4 *)w.lut)[threadIdx.x + u * kWL];
+#pragma unroll
+  for (uint32_t u = 0; u < kPerLane; u++) ((uint4 *)t.lut)[threadIdx.x + u * kWL] = q[u];
   for (uint32_t v = threadIdx.x; v < kMaxLen + 2; v += blockDim.x) {
     t.first[v] = w.tab->first[v];
     t.count[v] = w.tab->count[v];
@@ -595,7 +602,10 @@ __device__ bool decode_block_wave(const uint8_t *__restrict__ s, const Header &h
   uint32_t *pay = tab.pay;
   for (uint32_t i = l; i < nst; i += kWL) pay[i] = words[i];
   __syncthreads();
-  auto word = [&](uint64_t i) -> uint32_t { return i < nst ? pay[i] : words[i]; };
+  // a block's codewords take at most kMaxBlockPts * kMaxLen bits, so the
+  // staged words hold every bit the decoding can reach; words past them
+  // read as zeros (an LDS read, never a generic one)
+  auto word = [&](uint64_t i) -> uint32_t { return i < nst ? pay[i] : 0u; };
   if (l == 0) {
     const T *outl = (const T *)(s + h.off_outliers) + w.off_out[blk];
     uint64_t pos = 0;
@@ -798,6 +808,33 @@ template <typename T> __global__ void __launch_bounds__(64) k_decode_wave_redo(J
   }
 }
 
+// Region decompression of few blocks: a wave per block of the box of
+// blocks the region touches, each decoded by one lane (the serial part) and
+// reconstructed by the wave, storing its part of the region; the checksum
+// and the re-execution follow at once.  Small regions finish in about one
+// block's decoding time, where a lane per block would take a whole lane's
+// serial chain at one wave per SIMD.
+template <typename T> __global__ void __launch_bounds__(64) k_decode_wave_region(JobTab tab) {
+  const JobWg jw = job_of(tab);
+  const Job &J = *jw.J;
+  if (*J.dw.err) return;
+  extern __shared__ __align__(16) uint8_t lds[];
+  __shared__ WaveDecTab dt;
+  load_wave_tab(dt, J.dw);
+  const WaveLds<T> L = wave_lds<T>(lds, wave_rsz(J.g));
+  const Region &rb = J.rblk;
+  const uint64_t e1 = rb.hi[1] - rb.lo[1], e2 = rb.hi[2] - rb.lo[2];
+  for (uint64_t idx = jw.b; idx < J.L.shell_count; idx += jw.nb) {
+    const uint64_t c2 = rb.lo[2] + idx % e2, t = idx / e2;
+    const uint64_t c1 = rb.lo[1] + t % e1, c0 = rb.lo[0] + t / e1;
+    const uint64_t blk = (c0 * J.g.nb[1] + c1) * J.g.nb[2] + c2;
+    decode_one_wave<T>(J.src, J.h, J.g, J.dw, J.plan, (T *)J.dst, 2, J.reg, blk, L, dt, true, 0);
+    __syncthreads();
+  }
+}
+
+template __global__ void k_decode_wave_region<float>(JobTab);
+template __global__ void k_decode_wave_region<double>(JobTab);
 template __global__ void k_decode_wave_list<float>(JobTab);
 template __global__ void k_decode_wave_list<double>(JobTab);
 template __global__ void k_decode_wave_redo<float>(JobTab);

@@ -22,7 +22,8 @@ FUNCTIONS = ["sdcsz_max_compressed_size", "sdcsz_compress_workspace_size", "sdcs
              "sdcsz_compress_batch", "sdcsz_decompress_batch_workspace_size",
              "sdcsz_decompress_batch", "sdcsz_strerror", "sdcsz_timing_enable",
              "sdcsz_timing_read", "sdcsz_phase_name", "sdcsz_tune_set", "sdcsz_tune_get",
-             "sdcsz_decompress_noalloc", "sdcsz_pack_workspace_size", "sdcsz_pack", "sdcsz_unpack"]
+             "sdcsz_decompress_noalloc", "sdcsz_pack_workspace_size", "sdcsz_pack", "sdcsz_unpack",
+             "sdcsz_region_prepare", "sdcsz_decompress_region_prepared"]
 N_PHASES = 11
 HEADER_BYTES = 192
 NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024  # device array of sdcsz_decompress_noalloc
@@ -106,6 +107,9 @@ def lib():
                                    C.c_uint64, vp]
         L.sdcsz_decompress_region.argtypes = [vp, C.c_uint64, P(C.c_uint64), P(C.c_uint64), vp,
                                               C.c_uint64, P(Report), vp, C.c_uint64, vp]
+        L.sdcsz_region_prepare.argtypes = [vp, C.c_uint64, vp, vp, C.c_uint64, vp]
+        L.sdcsz_decompress_region_prepared.argtypes = [vp, C.c_uint64, vp, P(C.c_uint64), P(C.c_uint64), vp,
+                                                       C.c_uint64, P(Report), vp, C.c_uint64, vp]
         L.sdcsz_compress_batch_workspace_size.restype = C.c_uint64
         L.sdcsz_compress_batch_workspace_size.argtypes = [P(CompItem), C.c_uint32]
         L.sdcsz_compress_batch.argtypes = [P(CompItem), C.c_uint32, vp, C.c_uint64, vp]
@@ -198,6 +202,8 @@ class Codec:
         self._ws = {}
         # streams this codec wrote into its own buffers: pointer -> (size, shape, dtype, block)
         self._meta = {}
+        # region-decoding states of recently used streams: pointer -> RegionState
+        self._regions = {}
 
     def workspace(self, nbytes, tag):
         """A device buffer of at least nbytes kept under `tag`.  It grows by
@@ -250,6 +256,7 @@ class Codec:
         return rc, stream, rep
 
     def _remember(self, buf, rc, size, shape, dtype, block, header=None):
+        self._regions.pop(buf.data_ptr(), None)  # the buffer now holds another stream
         own = any(t.data_ptr() == buf.data_ptr() for t in self._ws.values())
         if rc == OK and own:
             self._meta[buf.data_ptr()] = (size, shape, dtype, tuple(int(b) for b in block), header)
@@ -510,28 +517,91 @@ class Codec:
                                       _stream_handle(self.device))
         return rc, [(items[i].rc, outs[i], report_dict(items[i].rep)) for i in range(n)]
 
-    def decompress_region(self, stream, lo, hi):
-        """Values of the box [lo, hi) of a stream's field: (rc, tensor of the
-        box's shape, report).  Only the blocks the box touches are decoded."""
+    def prepare_region(self, stream, header=None):
+        """(rc, RegionState): the stream's decoding tables and per-block
+        offsets built once in a workspace of their own, for repeated
+        decompress_region calls on the unchanged stream."""
         torch = self.torch
         L = lib()
         rc, p, shape = self._geometry(stream)
         if rc != OK:
-            return rc, None, None
-        dt = torch.float32 if p.dtype == 0 else torch.float64
+            return rc, None
+        if header is None:
+            header = self._header(stream)
+        if header is None:
+            header = bytes(stream[:HEADER_BYTES].cpu().numpy())
+        p.n_faults = 0
+        ws = torch.empty(int(L.sdcsz_decompress_workspace_size(C.byref(p))), dtype=torch.uint8,
+                         device=self.device)
+        hbuf = C.create_string_buffer(bytes(header), HEADER_BYTES)
+        rc = L.sdcsz_region_prepare(C.c_void_p(stream.data_ptr()), stream.numel(), C.cast(hbuf, C.c_void_p),
+                                    C.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(self.device))
+        if rc != OK:
+            return rc, None
+        return rc, RegionState(stream.data_ptr(), stream.numel(), bytes(header), p.dtype, shape, ws)
+
+    def decompress_region(self, stream, lo, hi, state=None, cache=True):
+        """Values of the box [lo, hi) of a stream's field: (rc, tensor of the
+        box's shape, report).  Only the blocks the box touches are decoded.
+        With a RegionState (prepare_region), or with cache (the codec keeps
+        the states of its last few streams, dropped when it writes another
+        stream into that buffer), the tables and block offsets are not
+        rebuilt; cache=False rebuilds them inside the call."""
+        torch = self.torch
+        L = lib()
+        cached = False
+        if state is None and cache:
+            state = self._regions.get(stream.data_ptr())
+            cached = state is not None
+            if state is not None and state.size != stream.numel():
+                state = None
+            if state is None:
+                rc, state = self.prepare_region(stream)
+                if rc != OK:
+                    return rc, None, None
+                if len(self._regions) >= 4:
+                    self._regions.pop(next(iter(self._regions)))
+                self._regions[stream.data_ptr()] = state
+        if state is not None:
+            dtype, shape = state.dtype, state.shape
+        else:
+            rc, p, shape = self._geometry(stream)
+            if rc != OK:
+                return rc, None, None
+            dtype = p.dtype
+        dt = torch.float32 if dtype == 0 else torch.float64
         ext = [int(h) - int(l) for l, h in zip(lo, hi)]
         out = torch.empty([max(e, 0) for e in ext], dtype=dt, device=self.device)
-        ws = self._dec_ws(p, 0)
         lo_a = (C.c_uint64 * 3)(*([int(v) for v in lo] + [0] * (3 - len(lo))))
         hi_a = (C.c_uint64 * 3)(*([int(v) for v in hi] + [0] * (3 - len(hi))))
         rep = Report()
-        rc = L.sdcsz_decompress_region(C.c_void_p(stream.data_ptr()), stream.numel(), lo_a, hi_a,
-                                       C.c_void_p(out.data_ptr()) if out.numel() else None,
-                                       out.numel() * out.element_size(), C.byref(rep),
-                                       C.c_void_p(ws.data_ptr()), ws.numel(),
-                                       _stream_handle(self.device))
+        optr = C.c_void_p(out.data_ptr()) if out.numel() else None
+        obytes = out.numel() * out.element_size()
+        if state is not None:
+            hbuf = C.create_string_buffer(state.header, HEADER_BYTES)
+            rc = L.sdcsz_decompress_region_prepared(C.c_void_p(stream.data_ptr()), stream.numel(),
+                                                    C.cast(hbuf, C.c_void_p), lo_a, hi_a, optr, obytes,
+                                                    C.byref(rep), C.c_void_p(state.ws.data_ptr()),
+                                                    state.ws.numel(), _stream_handle(self.device))
+            if rc == EFORMAT and cached:
+                # another stream now sits at this address: build its state afresh
+                self._regions.pop(stream.data_ptr(), None)
+                return self.decompress_region(stream, lo, hi)
+        else:
+            ws = self._dec_ws(p, 0)
+            rc = L.sdcsz_decompress_region(C.c_void_p(stream.data_ptr()), stream.numel(), lo_a, hi_a, optr,
+                                           obytes, C.byref(rep), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                           _stream_handle(self.device))
         return rc, out, report_dict(rep)
 
+
+class RegionState:
+    """A stream's region-decoding state on the device (Codec.prepare_region):
+    decoding tables, per-block offsets and a copy of the header they were
+    built from, in a workspace of its own."""
+
+    def __init__(self, ptr, size, header, dtype, shape, ws):
+        self.ptr, self.size, self.header, self.dtype, self.shape, self.ws = ptr, size, header, dtype, shape, ws
 
 def timing_enable(on=True):
     lib().sdcsz_timing_enable(1 if on else 0)

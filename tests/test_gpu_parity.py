@@ -281,11 +281,62 @@ def test_regions_match_oracle(codec, dtype, shape, block):
     for lo, hi in _regions(shape, block, np.random.default_rng(3), 12):
         print(f"case region shape={shape} dtype={np.dtype(dtype).name} lo={lo} hi={hi}", flush=True)
         rc_r, part_r, _ = ref.decompress_region(s, lo, hi)
-        rc_g, part_g, _ = codec.decompress_region(sd, lo, hi)
-        assert rc_r == rc_g == 0, (rc_r, rc_g)
+        rc_g, part_g, _ = codec.decompress_region(sd, lo, hi)  # the stream's state, built once
+        rc_1, part_1, _ = codec.decompress_region(sd, lo, hi, cache=False)  # tables rebuilt in the call
+        assert rc_r == rc_g == rc_1 == 0, (rc_r, rc_g, rc_1)
         part_g = part_g.cpu().numpy()
         assert np.array_equal(part_r.view(u), part_g.view(u))
+        assert np.array_equal(part_1.cpu().numpy().view(u), part_g.view(u))
         assert np.array_equal(full[tuple(slice(a, b) for a, b in zip(lo, hi))].view(u), part_g.view(u))
+
+
+def test_region_state_is_checked_against_the_stream(codec):
+    """A region state answers only for the stream it was built from: a
+    different stream in the same buffer, or a wrong header from the caller,
+    is a format error, and the codec's cache rebuilds the state for the new
+    stream."""
+    import ctypes as C
+    xa = synth.grf_field((30, 30, 30), seed=21)
+    xb = synth.grf_field((30, 30, 30), seed=22)
+    rc, sa, _ = ref.compress(xa, (6, 6, 6), 1e-3)
+    rc2, sb, _ = ref.compress(xb, (6, 6, 6), 1e-3)
+    assert rc == rc2 == 0
+    n = max(sa.size, sb.size)
+    buf = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    buf[:sa.size] = torch.from_numpy(sa).cuda()
+    view = buf[:sa.size]
+    lo, hi = (3, 4, 5), (20, 21, 30)
+    rc, state = codec.prepare_region(view)
+    assert rc == 0
+    rc, part, _ = codec.decompress_region(view, lo, hi, state=state)
+    assert rc == 0
+    assert np.array_equal(part.cpu().numpy().view(np.uint32), ref.decompress_region(sa, lo, hi)[1].view(np.uint32))
+    L = sdcsz.lib()
+    lo_a = (C.c_uint64 * 3)(*lo)
+    hi_a = (C.c_uint64 * 3)(*hi)
+    out = torch.empty(part.shape, dtype=torch.float32, device="cuda")
+
+    def prepared(stream, header):
+        hb = C.create_string_buffer(header, sdcsz.HEADER_BYTES)
+        return L.sdcsz_decompress_region_prepared(
+            C.c_void_p(stream.data_ptr()), stream.numel(), C.cast(hb, C.c_void_p), lo_a, hi_a,
+            C.c_void_p(out.data_ptr()), out.numel() * 4, None, C.c_void_p(state.ws.data_ptr()), state.ws.numel(),
+            None)
+    bad_header = bytearray(state.header)
+    bad_header[100] ^= 1
+    assert prepared(view, bytes(bad_header)) == sdcsz.EFORMAT
+    # stream B in the same buffer: its header differs from the state's
+    buf[:sb.size] = torch.from_numpy(sb).cuda()
+    view_b = buf[:sb.size]
+    assert prepared(view_b, bytes(sb[:192])) == sdcsz.EFORMAT
+    # the codec's cache (keyed by address) notices and rebuilds
+    buf[:sa.size] = torch.from_numpy(sa).cuda()
+    rc, _, _ = codec.decompress_region(buf[:sa.size], lo, hi)
+    assert rc == 0
+    buf[:sb.size] = torch.from_numpy(sb).cuda()
+    rc, part_b, _ = codec.decompress_region(buf[:sb.size], lo, hi)
+    assert rc == 0
+    assert np.array_equal(part_b.cpu().numpy().view(np.uint32), ref.decompress_region(sb, lo, hi)[1].view(np.uint32))
 
 
 def test_region_invalid_bounds(codec):
