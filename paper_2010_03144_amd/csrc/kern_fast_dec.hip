@@ -143,9 +143,13 @@ struct Window {
   }
   // the next 32 bits of the block (most significant first)
   __device__ inline uint32_t peek() const { return (uint32_t)((bb << (ap & 31)) >> 32); }
-  __device__ inline void skip(uint32_t n) {  // n < 32
+  // the word that follows bb, read before the codeword's length is known
+  // (the read overlaps the table lookup; it is used only when the codeword
+  // ends past bb's first word, and then it lies inside the staged groups)
+  __device__ inline uint32_t ahead() const { return word((ap >> 5) + 2); }
+  __device__ inline void skip(uint32_t n, uint32_t nx) {  // n < 32; nx: ahead() at the codeword's start
     const uint32_t na = ap + n;
-    if ((na >> 5) != (ap >> 5)) bb = (bb << 32) | word((na >> 5) + 1);
+    if ((na >> 5) != (ap >> 5)) bb = (bb << 32) | nx;
     ap = na;
   }
   __device__ inline uint32_t pos() const { return ap - skew; }
@@ -172,6 +176,7 @@ struct DecLds {
 __device__ inline uint32_t decode_sym(Window &br, const DecLds &t, const uint32_t *gsub, const uint16_t *gsym,
                                       bool *bad) {
   const uint32_t v = br.peek();
+  const uint32_t nx = br.ahead();
   const uint32_t e = t.lut[v >> (32 - kLutBits)];
   uint32_t len = e & 0xFFu, sym = e >> 8;
   if (__builtin_expect(len == 0, 0)) {
@@ -210,7 +215,7 @@ __device__ inline uint32_t decode_sym(Window &br, const DecLds &t, const uint32_
       len = 1;
     }
   }
-  br.skip(len);
+  br.skip(len, nx);
   return sym;
 }
 
