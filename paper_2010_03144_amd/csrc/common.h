@@ -136,11 +136,14 @@ struct DecWork {
 constexpr uint32_t kLutBits = 11;  // codeword prefix resolved by one table lookup
 // lut2 entries: symbol << 8 | length for a codeword of at most kLutBits bits;
 // for a prefix that only longer codewords (lengths lmin..lmax) start with,
-// off << 12 | (lmax - kLutBits) << 8 when its second level (2^(lmax -
-// kLutBits) entries from sub[off], indexed by the bits after the prefix) was
-// built, else kLut2Search | lmax << 16 | lmin << 8; 0 if no codeword starts
-// with the prefix.
+// off << 12 | w << 8 when its second level was built (2^w entries from
+// sub[off], indexed by the next w = min(lmax - kLutBits, kSubBits) bits),
+// else kLut2Search | lmax << 16 | lmin << 8; 0 if no codeword starts with
+// the prefix.  A second-level entry is symbol << 8 | length, or, for bits
+// that only codewords longer than kLutBits + w start with, kLut2Search |
+// lmax << 16 | (kLutBits + w + 1) << 8 (the lengths left to search), or 0.
 constexpr uint32_t kLut2Search = 0x80000000u;
+constexpr uint32_t kSubBits = 8;
 constexpr uint32_t kSubMax = 65536;  // second-level entries of one codebook at most
 
 // Stream header fields (byte offsets inside the 192-byte header).

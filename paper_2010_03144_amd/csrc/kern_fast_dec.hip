@@ -167,11 +167,11 @@ struct DecLds {
 };
 
 // Decode one symbol.  The prefix table resolves codewords of up to kLutBits
-// bits; a longer one takes one second-level lookup indexed by the bits after
-// the prefix (from LDS, or from the global table past kSubLds entries,
-// waiting for that load inside its own branch).  Prefixes without a second
-// level search the lengths their prefix allows, the first length whose codes
-// hold the top bits winning.  Sets *bad when no codeword matches.  Reading
+// bits; a longer one takes one second-level lookup indexed by the next (at
+// most kSubBits) bits (from LDS, or from the global table past kSubLds
+// entries, waiting for that load inside its own branch).  Codewords longer
+// than the second level resolves, and prefixes without one, search the
+// lengths left, the first length whose codes hold the top bits winning.  Sets *bad when no codeword matches.  Reading
 // past the block's words is checked once, at the end of the block.
 __device__ inline uint32_t decode_sym(Window &br, const DecLds &t, const uint32_t *gsub, const uint16_t *gsym,
                                       bool *bad) {
@@ -181,28 +181,27 @@ __device__ inline uint32_t decode_sym(Window &br, const DecLds &t, const uint32_
   uint32_t len = e & 0xFFu, sym = e >> 8;
   if (__builtin_expect(len == 0, 0)) {
     sym = 0;
-    if (e == 0) {
-      // no codeword starts with the prefix
-    } else if (!(e & kLut2Search)) {
-      const uint32_t wb = (e >> 8) & 0xFu;  // 1..kMaxLen - kLutBits
+    uint32_t f = e;  // a second-level entry, or the lengths to search
+    if (e != 0 && !(e & kLut2Search)) {
+      const uint32_t wb = (e >> 8) & 0xFu;  // 1..kSubBits
       const uint32_t idx = (e >> 12) + ((v << kLutBits) >> (32 - wb));
-      uint32_t se;
       if (idx < t.sub_lds) {
-        se = t.sub[idx];
+        f = t.sub[idx];
       } else {
-        se = gsub[idx];
-        __asm__ volatile("" : "+v"(se));
+        f = gsub[idx];
+        __asm__ volatile("" : "+v"(f));
       }
-      len = se & 0xFFu;
-      sym = se >> 8;
-    } else {
-      const uint32_t lmin = (e >> 8) & 0xFFu, lmax = (e >> 16) & 0xFFu;
+      len = f & 0xFFu;
+      sym = f >> 8;
+    }
+    if (len == 0 && (f & kLut2Search)) {
+      const uint32_t lmin = (f >> 8) & 0xFFu, lmax = (f >> 16) & 0xFFu;
 #pragma unroll 1
       for (uint32_t l = lmin; l <= lmax; l++) {
         const uint32_t c = v >> (32 - l);
-        const uint32_t f = t.first[l], n = t.count[l];
-        if (c >= f && c - f < n) {
-          uint32_t gs = gsym[t.start[l] + c - f];
+        const uint32_t fc = t.first[l], n = t.count[l];
+        if (c >= fc && c - fc < n) {
+          uint32_t gs = gsym[t.start[l] + c - fc];
           __asm__ volatile("" : "+v"(gs));
           sym = gs;
           len = l;

@@ -489,7 +489,7 @@ __global__ void __launch_bounds__(kDecTabThreads) k_dectab(JobTab tb) {
 #pragma unroll
   for (uint32_t u = 0; u < kPer; u++) {
     const uint32_t e = pe[tid * kPer + u];
-    np[u] = (e && !(e & 0xFFu)) ? 1u << ((e >> 16) - kLutBits) : 0u;
+    np[u] = (e && !(e & 0xFFu)) ? 1u << min((e >> 16) - kLutBits, kSubBits) : 0u;
     mine += np[u];
   }
   uint32_t inc = mine;
@@ -518,32 +518,57 @@ __global__ void __launch_bounds__(kDecTabThreads) k_dectab(JobTab tb) {
   for (uint32_t u = 0; u < kPer; u++) {
     const uint32_t v = tid * kPer + u, e = pe[v];
     uint32_t e2 = e;
-    if (e && !(e & 0xFFu)) e2 = build ? (poff[v] << 12) | (((e >> 16) - kLutBits) << 8) : (kLut2Search | e);
+    if (e && !(e & 0xFFu))
+      e2 = build ? (poff[v] << 12) | (min((e >> 16) - kLutBits, kSubBits) << 8) : (kLut2Search | e);
     w.lut2[v] = e2;
   }
   if (tid == 0) w.tab->sub_n = build ? total : 0u;
   if (!build) return;
-  for (uint32_t idx = tid; idx < total; idx += kDecTabThreads) {
-    // the prefix whose entries hold idx: the last with poff[p] <= idx
-    uint32_t lo = 0, hi = kNP;
+  // each thread fills a contiguous run of entries: one search for the
+  // prefix of its first entry, then forward; a codeword shorter than lmax
+  // covers consecutive entries, so the last match is tried first
+  const uint32_t per = (total + kDecTabThreads - 1) / kDecTabThreads;
+  const uint32_t i0 = min(total, tid * per), i1 = min(total, i0 + per);
+  if (i0 < i1) {
+    uint32_t lo = 0, hi = kNP;  // the prefix whose entries hold i0: the last with poff[p] <= i0
     while (hi - lo > 1) {
       const uint32_t mid = (lo + hi) >> 1;
-      if (poff[mid] <= idx) lo = mid;
+      if (poff[mid] <= i0) lo = mid;
       else hi = mid;
     }
-    const uint32_t e = pe[lo], lmin = (e >> 8) & 0xFFu, lmax = e >> 16, wb = lmax - kLutBits;
-    const uint32_t c = (lo << wb) | (idx - poff[lo]);  // the first lmax bits
-    uint32_t se = 0;
-    for (uint32_t l = lmin; l <= lmax; l++) {
-      const uint32_t cl = c >> (lmax - l);
-      if (cnt[l] && cl >= first[l] && cl - first[l] < cnt[l]) {
-        const uint32_t pos = start[l] + cl - first[l];
-        const uint32_t sy = pos < kNP ? (uint32_t)short_sym[pos] : (uint32_t)w.symbols[pos];
-        se = (sy << 8) | l;
-        break;
+    uint32_t p = lo;
+    uint32_t hit_l = 0, hit_lo = 0, hit_hi = 0, hit_e = 0;  // last match: length, range of c, entry
+    for (uint32_t idx = i0; idx < i1; idx++) {
+      while (poff[p + 1] <= idx) {
+        p++;
+        hit_l = 0;
       }
+      const uint32_t e = pe[p], lmin = (e >> 8) & 0xFFu, lmax = e >> 16;
+      const uint32_t wb = min(lmax - kLutBits, kSubBits), cb = kLutBits + wb;
+      const uint32_t c = (p << wb) | (idx - poff[p]);  // the first cb bits
+      uint32_t se = 0;
+      if (hit_l && c >= hit_lo && c < hit_hi) {
+        se = hit_e;
+      } else {
+        hit_l = 0;
+        for (uint32_t l = lmin; l <= cb; l++) {
+          const uint32_t cl = c >> (cb - l);
+          if (cnt[l] && cl >= first[l] && cl - first[l] < cnt[l]) {
+            const uint32_t pos = start[l] + cl - first[l];
+            const uint32_t sy = pos < kNP ? (uint32_t)short_sym[pos] : (uint32_t)w.symbols[pos];
+            se = (sy << 8) | l;
+            hit_l = l;
+            hit_lo = cl << (cb - l);
+            hit_hi = (cl + 1) << (cb - l);
+            hit_e = se;
+            break;
+          }
+        }
+        // longer codewords only: the decoder searches lengths cb + 1 .. lmax
+        if (!hit_l && lmax > cb) se = kLut2Search | (lmax << 16) | ((cb + 1) << 8);
+      }
+      w.sub[idx] = se;
     }
-    w.sub[idx] = se;
   }
 }
 
