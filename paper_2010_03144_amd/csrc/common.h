@@ -31,9 +31,10 @@ enum {
   C_MISSING = 4 * SDCSZ_N_TARGETS,  // a code without codeword was met while encoding
   C_HIST_DONE,                       // histogram chunks finished (the call's first job only)
   C_LIST,                            // fault-plan blocks run by the generic per-block routine
+  C_REDO2,                           // decompression: blocks the fault-applying decoder queued
   C_N = 40
 };
-static_assert(C_LIST < C_N, "counter layout");
+static_assert(C_REDO2 < C_N, "counter layout");
 
 // Block grid of a field normalised to three axes (leading axes of extent 1).
 struct Geo {
@@ -128,7 +129,8 @@ struct DecWork {
   uint32_t *lut2;      // the same prefixes for the specialised decoder (two-level, see kLut2Sub)
   uint32_t *sub;       // kSubMax entries: second level of lut2, symbol << 8 | length
   uint32_t *redo_n;    // blocks queued for re-execution
-  uint64_t *redo;      // kMaxRedo entries: block | reason << 56
+  uint64_t *redo;      // 2 kMaxRedo entries, block | reason << 56: the production decoder's
+                       // queue, then the fault-applying decoder's (count cnt[C_REDO2])
   uint32_t *err;       // non-zero: the codebook or the block table is not valid
   uint64_t *tot;       // scanned totals: payload words, outliers, regression blocks
 };

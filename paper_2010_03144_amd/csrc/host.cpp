@@ -328,7 +328,7 @@ DecLayout dec_layout(const Geo &g, uint32_t dtype, uint32_t nfaults, bool small_
   L.lut = take(4ull << kLutBits);
   L.lut2 = take(4ull << kLutBits);
   L.sub = take(4ull * kSubMax);
-  L.redo = take(8ull * kMaxRedo);
+  L.redo = take(16ull * kMaxRedo);  // the production decoder's queue, then the fault-applying one's
   L.hdr = take(kHeader);
   L.total = at;
   return L;
@@ -1596,6 +1596,16 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
       launch_shm(PH_NONE, false, false, k_decode_wave_list<float>, grid(t_list[0]), dim3(64), lds_list[0], side, D[5]);
     if (t_list[1].total())
       launch_shm(PH_NONE, false, false, k_decode_wave_list<double>, grid(t_list[1]), dim3(64), lds_list[1], side, D[6]);
+    // the blocks the fault-applying decoder queued, re-executed on the side
+    // stream as soon as it is done (its own queue: the production decoder
+    // may still be adding to the other)
+    for (int d = 0; d < 2; d++) {
+      bool fl = false;
+      for (int c = 0; c < kClasses; c++) fl |= t_flist[c][d].total() != 0;
+      if (fl && t_redo[d].total())
+        launch_shm(PH_NONE, false, false, d ? k_decode_wave_redo<double> : k_decode_wave_redo<float>, grid(t_redo[d]),
+                   dim3(64), lds_redo[d], side, D[7 + d], 1u);
+    }
   }
   {
     PhaseLaunch pl{PH_DECODE, {}};
@@ -1626,9 +1636,10 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
   }
   if (any_plan_work && !t_no_side) HIPCHK(t_side.join(st));
   if (t_redo[0].total())
-    launch_shm(PH_NONE, false, false, k_decode_wave_redo<float>, grid(t_redo[0]), dim3(64), lds_redo[0], st, D[7]);
+    launch_shm(PH_NONE, false, false, k_decode_wave_redo<float>, grid(t_redo[0]), dim3(64), lds_redo[0], st, D[7], 0u);
   if (t_redo[1].total())
-    launch_shm(PH_NONE, false, false, k_decode_wave_redo<double>, grid(t_redo[1]), dim3(64), lds_redo[1], st, D[8]);
+    launch_shm(PH_NONE, false, false, k_decode_wave_redo<double>, grid(t_redo[1]), dim3(64), lds_redo[1], st, D[8],
+               0u);
   const uint64_t *d_res = (const uint64_t *)(ws + a256(up.bytes(nj)));
   if (nj == 1) d_res = jobs[0].stat;  // one stream: no gather needed
   else launch(PH_NONE, false, false, k_results, grid(t_one), dim3(64), st, D[1], (uint64_t *)d_res,
@@ -1645,9 +1656,12 @@ int decode_batch(DecItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipStre
   std::vector<uint32_t> again;
   std::vector<uint64_t> overflow(nj, 0);
   for (uint32_t j = 0; j < nj; j++) {
-    const uint32_t *tail = (const uint32_t *)(resv.data() + (uint64_t)j * (C_N + 1) + C_N);
-    if (!tail[1] && fp[j].fast && tail[0] > kMaxRedo) {
-      if (fp[j].small) overflow[j] = tail[0] - kMaxRedo;
+    const uint64_t *cj = resv.data() + (uint64_t)j * (C_N + 1);
+    const uint32_t *tail = (const uint32_t *)(cj + C_N);
+    const uint64_t more = (tail[0] > kMaxRedo ? tail[0] - kMaxRedo : 0) +
+                          (cj[C_REDO2] > kMaxRedo ? cj[C_REDO2] - kMaxRedo : 0);
+    if (!tail[1] && fp[j].fast && more) {
+      if (fp[j].small) overflow[j] = more;
       else again.push_back(j);
     }
   }

@@ -161,7 +161,7 @@ template <typename T> __global__ void k_compress_wave(JobTab t, uint32_t slice);
 template <typename T> __global__ void k_compress_wave_list(JobTab t);
 template <typename T> __global__ void k_redo_wave(JobTab t);
 template <typename T> __global__ void k_decode_wave_list(JobTab t);
-template <typename T> __global__ void k_decode_wave_redo(JobTab t);
+template <typename T> __global__ void k_decode_wave_redo(JobTab t, uint32_t queue);
 template <typename T> __global__ void k_decode_wave_region(JobTab t);
 constexpr uint64_t kWaveRegionBlocks = 4096;  // regions of at most this many blocks take k_decode_wave_region
 

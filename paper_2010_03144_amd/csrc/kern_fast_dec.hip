@@ -417,8 +417,13 @@ __device__ __forceinline__ DecOut decode_lanes(const uint8_t *__restrict__ s, co
     count(w.cnt, C_DET + SDCSZ_T_RECON);
   }
   if (__builtin_expect(why != 0, 0)) {
-    const uint32_t slot = atomicAdd(w.redo_n, 1u);
-    if (slot < kMaxRedo) w.redo[slot] = blk | (why << 56);
+    if (MODE == kDFaults) {  // the fault-applying launch: its own queue, re-executed on its stream
+      const uint64_t slot = atomicAdd(w.cnt + C_REDO2, 1ull);
+      if (slot < kMaxRedo) w.redo[kMaxRedo + slot] = blk | (why << 56);
+    } else {
+      const uint32_t slot = atomicAdd(w.redo_n, 1u);
+      if (slot < kMaxRedo) w.redo[slot] = blk | (why << 56);
+    }
   }
   return res;
 }
@@ -548,8 +553,13 @@ __device__ __forceinline__ DecOut decode_rows(const uint8_t *__restrict__ s, con
     count(w.cnt, C_DET + SDCSZ_T_RECON);
   }
   if (__builtin_expect(why != 0, 0)) {
-    const uint32_t slot = atomicAdd(w.redo_n, 1u);
-    if (slot < kMaxRedo) w.redo[slot] = blk | (why << 56);
+    if (MODE == kDFaults) {  // the fault-applying launch: its own queue, re-executed on its stream
+      const uint64_t slot = atomicAdd(w.cnt + C_REDO2, 1ull);
+      if (slot < kMaxRedo) w.redo[kMaxRedo + slot] = blk | (why << 56);
+    } else {
+      const uint32_t slot = atomicAdd(w.redo_n, 1u);
+      if (slot < kMaxRedo) w.redo[slot] = blk | (why << 56);
+    }
   }
   return res;
 }

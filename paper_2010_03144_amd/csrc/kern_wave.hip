@@ -788,12 +788,14 @@ template <typename T> __global__ void __launch_bounds__(64) k_decode_wave_list(J
 // The blocks the lane-per-block decoder queued: a checksum mismatch is
 // decoded again from the stream; an undecodable block is zeroed.  One
 // work-group per entry at a time.
-template <typename T> __global__ void __launch_bounds__(64) k_decode_wave_redo(JobTab tab) {
+template <typename T> __global__ void __launch_bounds__(64) k_decode_wave_redo(JobTab tab, uint32_t queue) {
   const JobWg jw = job_of(tab);
   const Job &J = *jw.J;
   const DecWork &w = J.dw;
   if (*w.err) return;
-  const uint32_t n = min(*w.redo_n, kMaxRedo);
+  // queue 0: the production decoder's entries; 1: the fault-applying decoder's
+  const uint32_t n = queue ? (uint32_t)min((uint64_t)w.cnt[C_REDO2], (uint64_t)kMaxRedo) : min(*w.redo_n, kMaxRedo);
+  const uint64_t *q = w.redo + (queue ? kMaxRedo : 0u);
   if (jw.b >= n) return;
   extern __shared__ __align__(16) uint8_t lds[];
   __shared__ WaveDecTab dt;
@@ -801,7 +803,7 @@ template <typename T> __global__ void __launch_bounds__(64) k_decode_wave_redo(J
   const WaveLds<T> L = wave_lds<T>(lds, wave_rsz(J.g));
   const uint32_t mode = J.mode == 2 ? 2u : 0u;
   for (uint32_t e = jw.b; e < n; e += jw.nb) {
-    const uint64_t ent = w.redo[e];
+    const uint64_t ent = q[e];
     decode_one_wave<T>(J.src, J.h, J.g, w, J.plan, (T *)J.dst, mode, J.reg, ent & ((1ull << 56) - 1), L, dt, false,
                        ent >> 56);
     __syncthreads();
@@ -837,8 +839,8 @@ template __global__ void k_decode_wave_region<float>(JobTab);
 template __global__ void k_decode_wave_region<double>(JobTab);
 template __global__ void k_decode_wave_list<float>(JobTab);
 template __global__ void k_decode_wave_list<double>(JobTab);
-template __global__ void k_decode_wave_redo<float>(JobTab);
-template __global__ void k_decode_wave_redo<double>(JobTab);
+template __global__ void k_decode_wave_redo<float>(JobTab, uint32_t);
+template __global__ void k_decode_wave_redo<double>(JobTab, uint32_t);
 template __global__ void k_compress_wave<float>(JobTab, uint32_t);
 template __global__ void k_compress_wave<double>(JobTab, uint32_t);
 template __global__ void k_compress_wave_list<float>(JobTab);
