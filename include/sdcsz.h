@@ -187,9 +187,9 @@ int sdcsz_decompress(const void *d_stream, uint64_t stream_size, void *d_out, ui
  *   d_stream, d_out, h_faults, h_rep: as for sdcsz_decompress (the caller
  *             passes the stream and the output buffer)
  * Streams of block shapes with a specialised decoder (6x6x6 in 3D, 16x16 in
- * 2D) and no fault plan need about 16 bytes per block plus 8.5 MiB (FP64)
- * of the array, so fields up to about 3.5 million blocks fit; other shapes
- * and fault plans stage every block's values there and fit only when small.
+ * 2D) and no fault plan need about 16 bytes per block plus 0.5 MiB of the
+ * array, so fields up to about 4 million blocks fit; other shapes and
+ * fault plans stage every block's values there and fit only when small.
  * A stream whose workspace exceeds the array returns SDCSZ_ENOSPC and
  * writes nothing.  More than 4096 blocks that fail their checksum cannot
  * all be re-executed here: the others stay uncorrected, are counted

@@ -227,7 +227,10 @@ class Codec:
     # ------------------------------------------------------------------ compress
     def compress(self, x, block, eb, eb_mode="rel", abft=True, predictor="auto", faults=None,
                  out=None):
-        """Returns (rc, stream uint8 tensor on the device, report dict)."""
+        """Returns (rc, stream uint8 tensor on the device, report dict).
+        Without `out`, the stream is a view into a buffer this codec reuses:
+        its next compression overwrites it, so clone the stream to keep it
+        (decompress and region decompression know a stream still there)."""
         torch = self.torch
         L = lib()
         assert x.is_cuda and x.is_contiguous() and x.dtype in (torch.float32, torch.float64)
