@@ -257,14 +257,18 @@ __device__ inline LaneFaults lane_faults(const PlanDev &plan, uint64_t blk, bool
   return f;
 }
 
-// Flip the coefficient word w of (b0, b1, b2, m) by mask mk.
+// Flip the coefficient word w of (b0, b1, b2, m) by mask mk.  Selects, not
+// branches: hipcc laid out an if-else chain over the four coefficients of the
+// FP64 instantiation so that a flip of the last one took the first one's
+// value (the chain's last branch lost its input in the structured control
+// flow), which made such flips uncorrectable.
 template <typename T> __device__ inline void coef_flip(T &b0, T &b1, T &b2, T &m, uint32_t w, uint32_t mk) {
   constexpr uint32_t per = Wd<T>::per;
   const uint32_t a = w / per, half = w % per;
-  if (a == 0) b0 = word_xor(b0, half, mk);
-  else if (a == 1) b1 = word_xor(b1, half, mk);
-  else if (a == 2) b2 = word_xor(b2, half, mk);
-  else m = word_xor(m, half, mk);
+  b0 = a == 0 ? word_xor(b0, half, mk) : b0;
+  b1 = a == 1 ? word_xor(b1, half, mk) : b1;
+  b2 = a == 2 ? word_xor(b2, half, mk) : b2;
+  m = a == 3 ? word_xor(m, half, mk) : m;
 }
 
 // What a lane's pass found: mismatch reasons and the first-pass checksums.

@@ -167,6 +167,28 @@ def test_compression_fault_counts_match_oracle(codec, dtype):
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 @pytest.mark.parametrize("shape,block", [((48, 42, 36), (6, 6, 6)), ((400, 390), (16, 16))])
+def test_every_coefficient_word_is_repaired(codec, dtype, shape, block):
+    # one flip on each coefficient word (the four coefficients' words, low
+    # word first in FP64), on distinct blocks, at low, middle and top bits:
+    # every flip is located and repaired, as in the oracle (a flip of the
+    # FP64 mean's words was once left uncorrectable by the compiled kernel)
+    x = synth.grf_field(shape, seed=41, dtype=dtype)
+    per = 1 if dtype == np.float32 else 2
+    rows = []
+    for wd in range(4 * per):
+        for t, bit in enumerate((0, 17, 31)):
+            rows.append((1, bit, 3 + 7 * wd + 2 * t, wd))
+    plan = np.array(sorted(rows, key=lambda r: r[2]), dtype=np.int64)
+    (rc_r, s_r, rep_r), (rc_g, s_g, rep_g) = both(codec, x, block, 1e-4, faults=plan)
+    assert rc_r == rc_g == 0, (rc_r, rc_g)
+    same_counts(rep_r, rep_g)
+    assert rep_g["coef"]["corrected"] == len(rows), rep_g["coef"]
+    assert rep_g["generic_plan_blocks"] == 0
+    assert np.array_equal(s_r, s_g), first_difference(s_r, s_g)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("shape,block", [((48, 42, 36), (6, 6, 6)), ((400, 390), (16, 16))])
 def test_several_flips_in_one_block_match_oracle(codec, dtype, shape, block):
     # input, coefficient and prediction flips together, or coefficient and
     # reconstruction flips together, stay on the specialised kernels; two of
