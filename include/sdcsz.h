@@ -128,7 +128,11 @@ uint64_t sdcsz_compress_workspace_size(const sdcsz_params *p);
  * per-block encoding.
  *   d_in      device, dims[0]*dims[1]*dims[2] values of dtype, C order; read only
  *   d_out     device, out_cap bytes, 8-byte aligned; receives the stream.
- *             Nothing is written to it on SDCSZ_ENOSPC or SDCSZ_ESDC.
+ *             Nothing is written to it on SDCSZ_ENOSPC.  On SDCSZ_ESDC its
+ *             contents are undefined when out_cap >= sdcsz_max_compressed_size
+ *             (6x6x6 fields then check and encode their codes in one pass,
+ *             which writes the stream before the call knows that a block
+ *             stays uncorrectable), else nothing is written.
  *   h_out_size host; receives the stream size (also on SDCSZ_ENOSPC: the
  *             required size)
  *   h_rep     host, may be NULL; fault counters and stream statistics

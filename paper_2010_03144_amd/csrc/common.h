@@ -32,9 +32,10 @@ enum {
   C_HIST_DONE,                       // histogram chunks finished (the call's first job only)
   C_LIST,                            // fault-plan blocks run by the generic per-block routine
   C_REDO2,                           // decompression: blocks the fault-applying decoder queued
-  C_N = 40
+  C_SPIN,                            // compression: a look-back that gave up waiting (never expected)
+  C_N = 42
 };
-static_assert(C_REDO2 < C_N, "counter layout");
+static_assert(C_SPIN < C_N, "counter layout");
 
 // Block grid of a field normalised to three axes (leading axes of extent 1).
 struct Geo {
@@ -100,6 +101,8 @@ struct CompWork {
   EbDev *eb;
   uint32_t *redo_n;    // blocks queued for a re-run
   uint64_t *redo;      // kMaxRedo entries of 3 words: block | reason << 56, first-pass S and Q
+  uint64_t *tiles;     // one-pass code check and encoding: a status word per tile of 256 blocks
+  uint32_t *ticket;    // and the next tile to hand out (both cleared at the start of a call)
   struct Header *hdr;  // stream header, filled on the device
   uint64_t *res;       // R_* results of the call, read back once at its end
   uint8_t *hdr_bytes;  // the stream's kHeader header bytes, read back with the results

@@ -234,7 +234,7 @@ template <typename T> RegTab<T> reg_table(const Geo &g) {
 // per-field workspace layouts
 // ---------------------------------------------------------------------------
 struct CompLayout {
-  uint64_t cnt, res, redo_n, hist, enc, zero_end, bits, bits_end;
+  uint64_t cnt, res, redo_n, hist, enc, tiles, zero_end, bits, bits_end;
   uint64_t eb, range, codes, vals, recon, meta, words, coef, sum_dc, sum_q, isum_q;
   uint64_t off_pay, off_out, off_coef, scan, tot, plan, redo, hdr, total;
 };
@@ -242,6 +242,24 @@ struct CompLayout {
 // A fault plan's device area: the entries, then the blocks of the wave
 // routine's list and of the fault-applying instantiation's list (one copy).
 uint64_t plan_bytes(uint32_t nfaults) { return (sizeof(sdcsz_fault) + 16ull) * std::max<uint32_t>(nfaults, 1); }
+
+uint64_t tiles_of(uint64_t nb) { return (nb + kEncTile - 1) / kEncTile; }
+
+// The largest stream of a field: every value an outlier and a codeword of
+// the longest length, every block a regression block, all 65,536 symbols.
+uint64_t max_stream_size(const Geo &g, uint32_t dtype) {
+  Header h;
+  std::memset(&h, 0, sizeof(h));
+  h.dtype = dtype;
+  h.abft = 1;
+  h.n_sym = 65536;
+  h.n_blocks = g.n_blocks;
+  h.n_regression = g.n_blocks;
+  h.n_outliers = g.n_values;
+  h.payload_words = (g.n_values * kMaxLen + 31) / 32 + g.n_blocks;
+  section_offsets(h);
+  return h.total;
+}
 
 CompLayout comp_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
   CompLayout L;
@@ -262,6 +280,7 @@ CompLayout comp_layout(const Geo &g, uint32_t dtype, uint32_t nfaults) {
   L.redo_n = L.res + 8 * R_N;
   L.hist = take(4 * 65536);
   L.enc = take(4 * 65536);
+  L.tiles = take(8 * (tiles_of(nb) + 1));  // one-pass check and encoding: tile states, then the ticket
   L.zero_end = at;
   L.bits = take(4 * (nb / 32 + 1));  // a plan's blocks: cleared too when there is a plan
   L.bits_end = at;
@@ -754,6 +773,7 @@ struct CompPlan {  // host state of one field
   std::vector<uint64_t> fl;  // blocks the fault-applying instantiation takes
   std::vector<uint8_t> up;   // plan area as uploaded (entries, pb, fl)
   bool any_code;
+  bool fused;         // code check and encoding in one pass (k_checkenc_fast)
   uint64_t pair_off;  // first entry of the field's histogram / codebook list
 };
 
@@ -830,6 +850,9 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     f.L = comp_layout(f.g, c.p->dtype, c.p->n_faults);
     f.cls = fast_class(f.g, vbytes(c.p->dtype));
     f.fast = f.cls >= 0;
+    // the one-pass check and encoding writes the stream before it knows the
+    // stream's size: only into an output that holds the largest one
+    f.fused = f.cls == 0 && f.g.n_blocks > 0 && c.d_out && c.out_cap >= max_stream_size(f.g, c.p->dtype);
     f.any_code = false;
     for (auto &e : f.plan) f.any_code |= e.target == SDCSZ_T_CODE;
     f.pair_off = cap;
@@ -897,6 +920,8 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     cw.res = (uint64_t *)(w + f.L.res);
     cw.cb = (uint32_t *)(ws + B.cb) + 2 * f.pair_off;
     cw.tot = (uint64_t *)(w + f.L.tot);
+    cw.tiles = (uint64_t *)(w + f.L.tiles);
+    cw.ticket = (uint32_t *)(cw.tiles + tiles_of(f.g.n_blocks));
     J.plan.n = (uint32_t)f.plan.size();
     J.plan.f = (const sdcsz_fault *)(w + f.L.plan);
     J.plan.bits = (const uint32_t *)(w + f.L.bits);
@@ -914,7 +939,9 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     h.abft = c.p->abft;
     h.n_blocks = f.g.n_blocks;
     h.predictor = c.p->predictor;
-    J.ss = ScanSrc{cw.words, cw.meta, 1};
+    // a one-pass field scans its outliers and regression blocks in stage A
+    // (no payload words yet); the others scan all three after the check
+    J.ss = ScanSrc{f.fused ? nullptr : cw.words, cw.meta, 1};
     J.sc_part = cw.scan_part;
     J.sc_off_pay = cw.off_pay;
     J.sc_off_out = cw.off_out;
@@ -954,7 +981,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   // t_gen: one thread per block; t_wave, t_wlist, t_redo: a wave per block;
   // t_flist: the fault-applying instantiation over the plans' lists
   Tab t_zero, t_plan, t_range[2], t_fast[kClasses][2][2], t_flist[kClasses][2][2], t_gen[2], t_wave[2], t_wlist[2],
-      t_redo[2], t_hist, t_hchunk;
+      t_redo[2], t_hist, t_hchunk, t_sa;  // t_sa: the stage-A scans of one-pass fields
   uint32_t lds_wlist[2] = {}, lds_redo[2] = {};  // dynamic LDS of the wave launches
   uint32_t slice_wave[2] = {}, hw_wave[2] = {};  // k_compress_wave: widest block slice and histogram window
   uint64_t nb_fast[kClasses][2][2] = {}, nb_cls[kClasses] = {}, nb_enc[kClasses][2] = {};
@@ -1006,6 +1033,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     }
     t_hist.add(j, 1);
     t_hchunk.add(j, kHistChunks);
+    if (f.fused) t_sa.add(j, scan_chunks(f.g.n_blocks));
   }
   Upload up;
   up.tabs = {&t_zero,     &t_range[0], &t_range[1], &t_gen[0],  &t_gen[1],  &t_hist,    &t_hchunk,
@@ -1016,6 +1044,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   for (int c = 0; c < kClasses; c++)
     for (int d = 0; d < 2; d++)
       for (int a = 0; a < 2; a++) up.tabs.push_back(&t_flist[c][d][a]);
+  up.tabs.push_back(&t_sa);
   uint8_t *hs = t_stage.get(std::max<size_t>(up.bytes(nj), 4 * nj + 8 + 8 * t_pair_guess + 64));
   if (!hs) return SDCSZ_EHIP;
   up.place(jobs, hs, ws + B.jobs);
@@ -1029,6 +1058,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   const JobTab &d_plan = up.dev[13];
   const JobTab *d_fast = &up.dev[14];                       // [class][dtype][abft] in that order
   const JobTab *d_flist = &up.dev[14 + kClasses * 2 * 2];  // the same
+  const JobTab &d_sa = up.dev[14 + 2 * kClasses * 2 * 2];
   auto grid = [](const Tab &t) { return dim3(t.total()); };
   launch(PH_NONE, false, false, k_zero_jobs, grid(t_zero), dim3(256), st, d_zero);
   if (t_plan.total()) launch(PH_NONE, false, false, k_plan_bits, grid(t_plan), dim3(256), st, d_plan);
@@ -1109,6 +1139,12 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     if (fp[j].any_code)
       launch(PH_CODEFAULT, true, true, k_code_faults, dim3(1), dim3(64), st, jobs[j].plan, jobs[j].g,
              jobs[j].cw.codes, jobs[j].cw.cnt);
+  // one-pass fields: offsets and totals of the outliers and regression
+  // blocks (final once the re-runs are done)
+  if (t_sa.total()) {
+    launch(PH_NONE, false, false, k_scan1, grid(t_sa), dim3(kScanThreads), st, d_sa);
+    launch(PH_NONE, false, false, k_scan3, grid(t_sa), dim3(kScanThreads), st, d_sa);
+  }
   uint32_t *d_counts = (uint32_t *)(ws + B.counts);
   uint64_t *d_pairs = (uint64_t *)(ws + B.pairs);
   uint32_t *d_chunks = (uint32_t *)(ws + B.chunks);
@@ -1163,11 +1199,18 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     build_codebooks(cj);
   }
   Tab t_put, t_chk_fast[kClasses], t_chk_gen, t_s1, t_s2, t_hdr, t_enc_fast[kClasses][2], t_enc_gen[2], t_res;
+  Tab t_fuse[2];  // one-pass check and encoding, a tile of blocks per work-group
   bool any_empty = false;
   for (uint32_t j = 0; j < nj; j++) {
     const Job &J = jobs[j];
     const CompPlan &f = fp[j];
     if (J.n_sym) t_put.add(j, grid_for(J.n_sym, 256));
+    t_hdr.add(j, grid_for(J.n_sym, 256));
+    t_res.add(j, 1);
+    if (f.fused) {
+      t_fuse[J.dtype].add(j, tiles_of(f.g.n_blocks));
+      continue;
+    }
     if (f.fast) {
       t_chk_fast[f.cls].add(j, grid_for(f.g.n_blocks, ln_chk[f.cls]));
       t_enc_fast[f.cls][J.dtype].add(j, grid_for(f.g.n_blocks, ln_enc[f.cls][J.dtype]));
@@ -1178,8 +1221,6 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     t_s1.add(j, scan_chunks(f.g.n_blocks));
     t_s2.add(j, 1);
     any_empty |= f.g.n_blocks == 0;
-    t_hdr.add(j, grid_for(J.n_sym, 256));
-    t_res.add(j, 1);
   }
   Upload ub;
   ub.tabs = {&t_put, &t_chk_gen, &t_s1, &t_s2, &t_hdr, &t_enc_gen[0], &t_enc_gen[1], &t_res};
@@ -1187,6 +1228,8 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     ub.tabs.push_back(&t_chk_fast[c]);
     for (int d = 0; d < 2; d++) ub.tabs.push_back(&t_enc_fast[c][d]);
   }
+  ub.tabs.push_back(&t_fuse[0]);
+  ub.tabs.push_back(&t_fuse[1]);
   ub.place(jobs, hs, ws + B.jobs);
   HIPCHK(hipMemcpyAsync(ws + B.jobs, hs, JR + 8 * total_pairs, hipMemcpyHostToDevice, st));
   const std::vector<JobTab> &D = ub.dev;
@@ -1203,6 +1246,16 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     }
     if (t_chk_gen.total())
       pl.fs.push_back([&](bool a, bool b) { launch(PH_CHECK, a, b, k_codes_check, grid(t_chk_gen), dim3(256), st, D[1]); });
+    if (t_fuse[0].total())
+      pl.fs.push_back([&](bool a, bool b) {
+        launch(PH_CHECK, a, b, k_checkenc_fast<float, 6, 6, 6>, grid(t_fuse[0]), dim3(kEncTile), st,
+               D[8 + 3 * kClasses]);
+      });
+    if (t_fuse[1].total())
+      pl.fs.push_back([&](bool a, bool b) {
+        launch(PH_CHECK, a, b, k_checkenc_fast<double, 6, 6, 6>, grid(t_fuse[1]), dim3(kEncTile), st,
+               D[8 + 3 * kClasses + 1]);
+      });
     pl.run();
   }
   if (any_empty) launch(PH_SCAN_C, true, !t_s1.total(), k_scan2, grid(t_s2), dim3(kScanThreads), st, D[3]);
@@ -1250,7 +1303,10 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     const bool overflow = (uint32_t)res[R_N] > kMaxRedo;
     const bool unc = cnt[C_UNC + SDCSZ_T_INPUT] || cnt[C_UNC + SDCSZ_T_COEF] || cnt[C_UNC + SDCSZ_T_CODE] ||
                      cnt[C_UNC + SDCSZ_T_PREP_INPUT] || cnt[C_MISSING] || overflow;
-    if (unc) {
+    if (cnt[C_SPIN]) {  // a one-pass tile gave up waiting for its predecessor
+      c.out_size = 0;
+      c.rc = SDCSZ_EHIP;
+    } else if (unc) {
       c.out_size = 0;
       c.rc = SDCSZ_ESDC;
     } else {
@@ -1824,17 +1880,7 @@ const char *sdcsz_phase_name(int phase) {
 uint64_t sdcsz_max_compressed_size(const sdcsz_params *p) {
   Geo g;
   if (check_params(p, &g)) return 0;
-  Header h;
-  std::memset(&h, 0, sizeof(h));
-  h.dtype = p->dtype;
-  h.abft = 1;
-  h.n_sym = 65536;
-  h.n_blocks = g.n_blocks;
-  h.n_regression = g.n_blocks;
-  h.n_outliers = g.n_values;
-  h.payload_words = (g.n_values * kMaxLen + 31) / 32 + g.n_blocks;
-  section_offsets(h);
-  return h.total;
+  return max_stream_size(g, p->dtype);
 }
 
 uint64_t sdcsz_compress_workspace_size(const sdcsz_params *p) {

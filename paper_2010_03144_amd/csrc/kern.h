@@ -137,6 +137,8 @@ template <typename T, int ND, int B0, int B1, int B2, bool WIDE, bool FAULTS> __
 
 template <int ND, int B0, int B1, int B2> __global__ void k_check_fast(JobTab t);
 template <typename T, int ND, int B0, int B1, int B2> __global__ void k_encode_fast(JobTab t);
+template <typename T, int B0, int B1, int B2> __global__ void k_checkenc_fast(JobTab t);
+constexpr uint32_t kEncTile = 256;  // blocks per tile of k_checkenc_fast (its work-group)
 
 // Wave-per-block kernels (kern_wave.hip): one block per work-group of 64
 // lanes, staged in dynamic LDS of wave_lds_bytes().

@@ -60,7 +60,7 @@ __device__ inline void load_window(uint32_t *encw, const uint32_t *enc) {
 // The codes of one lane's block, one plane at a time: plane i sits in
 // buffer i & 1 while plane i + 1 loads into the other (8 bytes per lane per
 // access, coalesced across the wave in the interleaved staging layout).
-template <int B0, int B1, int B2> struct PlaneCodes {
+template <int B0, int B1, int B2, bool LAST = true> struct PlaneCodes {
   static constexpr int PG = B1 * B2 / 4;  // 4-code groups per plane
   static_assert((B1 * B2) % 4 == 0, "a plane fills whole groups");
   const uint2 *cb;
@@ -71,9 +71,10 @@ template <int B0, int B1, int B2> struct PlaneCodes {
   __device__ void load(int i) {
 #pragma unroll
     for (int gi = 0; gi < PG; gi++) {
-      // last read of the codes: non-temporal, so they do not displace the
-      // output in the caches
-      const uint64_t u64 = __builtin_nontemporal_load((const uint64_t *)(cb + (uint64_t)(i * PG + gi) * 64));
+      // the last read of the codes is non-temporal, so they do not displace
+      // the output in the caches; an earlier one keeps them there
+      const uint64_t *a = (const uint64_t *)(cb + (uint64_t)(i * PG + gi) * 64);
+      const uint64_t u64 = LAST ? __builtin_nontemporal_load(a) : *a;
       const uint2 u = make_uint2((uint32_t)u64, (uint32_t)(u64 >> 32));
       v[i & 1][2 * gi] = u.x;
       v[i & 1][2 * gi + 1] = u.y;
@@ -280,6 +281,256 @@ template <typename T, int ND, int B0, int B1, int B2> __global__ void __launch_b
   if (h.abft) ((uint64_t *)(out + h.off_sumdc))[blk] = w.sum_dc[blk];
 }
 
+// Code check and encoding in one pass (Algorithm 1 before and at the
+// encoding) for 3D blocks, one lane per block: a lane reads its block's codes
+// once and keeps them in registers while the payload offsets are found, then
+// encodes them.  The offsets come from a scan across work-groups with a
+// decoupled look-back: a work-group takes the next tile of 256 blocks of its
+// field from a ticket counter (so every tile it waits for belongs to a
+// work-group already running), publishes its tile's payload words, and adds
+// the published counts of the tiles before it until it meets a published
+// prefix, which it then extends.  The outlier and coefficient offsets and
+// their totals were scanned before (they depend on the prediction pass
+// only); the last tile leaves the field's payload total for k_header.  The
+// payload, table, coefficients, sum_dc and outliers are written before the
+// call knows whether another block ends uncorrectable (the caller is told
+// by the return code; the host takes this path only when the output holds
+// the largest stream).
+constexpr uint32_t kTileSpin = 1u << 24;  // polls of an unpublished tile before giving up
+
+template <typename T, int B0, int B1, int B2>
+__global__ void __launch_bounds__(256) k_checkenc_fast(JobTab jt) {
+  static_assert((B1 * B2) % 4 == 0, "a plane fills whole groups");
+  const JobWg jw = job_of(jt);
+  const Geo g = jw.J->g;
+  const CompWork w = jw.J->cw;
+  const uint32_t abft = jw.J->abft;
+  uint8_t *out = jw.J->dst;
+  __shared__ uint32_t encw[kEncWin];
+  __shared__ uint32_t ring_all[16 * 256];
+  __shared__ uint32_t s_tile, s_wsum[4];
+  __shared__ uint64_t s_excl;
+  if (threadIdx.x == 0) s_tile = atomicAdd(w.ticket, 1u);
+  load_window(encw, w.enc);  // synchronises the work-group
+  const uint32_t tile = s_tile;
+  // tickets past the field's tiles would mean a counter not cleared for this
+  // call: touch nothing then (the tile states hold one word per tile)
+  if ((uint64_t)tile * 256 >= g.n_blocks) return;
+  const uint64_t blk = (uint64_t)tile * 256 + threadIdx.x;
+  const bool active = blk < g.n_blocks;
+  // section offsets of the stream (the payload offset does not depend on the payload's size)
+  Header h = jw.J->h;
+  h.payload_words = 0;
+  h.n_outliers = w.tot[1];
+  h.n_regression = w.tot[2];
+  section_offsets(h);
+
+  // ---- check: the codes into registers, sums, sizes, repair ----------------
+  uint64_t bits = 0;
+  uint32_t e0 = 0, n1 = 0, n2 = 0;
+  Box b;
+  if (active) {
+    b = box_of(g, blk);
+    e0 = b.n[0];
+    n1 = b.n[1];
+    n2 = b.n[2];
+    // one plane of codes in registers, the next in flight (kept in the
+    // caches for the encoding's second read)
+    PlaneCodes<B0, B1, B2, false> pc;
+    pc.init(w.codes, blk, g.groups);
+    pc.load(0);
+    uint64_t s = 0, is = 0;
+    uint32_t missing = 0;
+#pragma unroll
+    for (int i = 0; i < B0; i++) {
+      if (i + 1 < B0) pc.load(i + 1);
+#pragma unroll
+      for (int j = 0; j < B1; j++) {
+        const uint32_t rowbase = ((uint32_t)i * n1 + (uint32_t)j) * n2;
+        uint32_t rs = 0, rk = 0;
+#pragma unroll
+        for (int k = 0; k < B2; k++) {
+          const int q = j * B2 + k;
+          const bool v = (uint32_t)i < e0 && (uint32_t)j < n1 && (uint32_t)k < n2;
+          const uint32_t c = v ? pc.at(i, q) : kRadius;
+          const uint32_t len = enc_of(c, encw, w.enc) & 0xFFu;
+          if (v) {
+            rs += c;
+            rk += (uint32_t)k * c;
+            bits += len;
+            missing += len == 0 ? 1u : 0u;
+          }
+        }
+        s += rs;
+        is += (uint64_t)rowbase * rs + rk;
+      }
+      // one plane's lookups at a time (the compiler would otherwise hold
+      // the whole block's table entries at once)
+      __asm__ volatile("" : "+v"(bits), "+v"(s), "+v"(is), "+v"(missing)::"memory");
+    }
+    if (abft && (s != w.sum_q[blk] || is != w.isum_q[blk])) {
+      // detected: locate and repair one code (the encoding reads it back)
+      // and size the block again
+      auto pos = [&](uint64_t p) -> uint64_t {
+        const uint32_t m1 = b.n[1], m2 = b.n[2];
+        const uint32_t k = (uint32_t)(p % m2), j = (uint32_t)((p / m2) % m1), i = (uint32_t)(p / ((uint64_t)m2 * m1));
+        return code_index(blk, padded_index(g, i, j, k), g.groups);
+      };
+      uint64_t jf;
+      uint32_t vf;
+      const int st = locate_repair(s, is, w.sum_q[blk], w.isum_q[blk], b.pts, 16,
+                                   [&](uint64_t jj) { return (uint32_t)w.codes[pos(jj)]; }, &jf, &vf);
+      count(w.cnt, C_DET + SDCSZ_T_CODE);
+      if (st == 1) {
+        const uint32_t l_old = enc_of(w.codes[pos(jf)], encw, w.enc) & 0xFFu;
+        const uint32_t l_new = enc_of(vf, encw, w.enc) & 0xFFu;
+        w.codes[pos(jf)] = (uint16_t)vf;
+        count(w.cnt, C_COR + SDCSZ_T_CODE);
+        bits = bits - l_old + l_new;
+        missing = missing - (l_old == 0 ? 1u : 0u) + (l_new == 0 ? 1u : 0u);
+      } else {
+        count(w.cnt, C_UNC + SDCSZ_T_CODE);
+      }
+    }
+    if (missing) count(w.cnt, C_MISSING);
+  }
+  const uint32_t words = active ? (uint32_t)((bits + 31) / 32) : 0u;
+
+  // ---- offsets: scan inside the tile, look-back across tiles ---------------
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t incl = words;
+#pragma unroll
+  for (uint32_t d = 1; d < 64; d <<= 1) {
+    const uint32_t u = (uint32_t)__shfl_up((int)incl, d);
+    if (lane >= d) incl += u;
+  }
+  if (lane == 63) s_wsum[wave] = incl;
+  __syncthreads();
+  uint32_t before = 0, agg = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < 4; q++) {
+    before += q < wave ? s_wsum[q] : 0u;
+    agg += s_wsum[q];
+  }
+  // A tile's state is one 64-bit word (count << 2 | flag), written and read
+  // with relaxed device-scope atomics: nothing else is ordered by it, and
+  // release/acquire at that scope would write back and invalidate the L2 of
+  // the work-group's XCD at every step.
+  if (threadIdx.x == 0) {
+    uint64_t *st = w.tiles;
+    uint64_t excl = 0;
+    if (tile == 0) {
+      __hip_atomic_store(st, ((uint64_t)agg << 2) | 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      __hip_atomic_store(st + tile, ((uint64_t)agg << 2) | 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int64_t p = (int64_t)tile - 1;
+      uint32_t spins = 0;
+      while (p >= 0) {
+        const uint64_t v = __hip_atomic_load(st + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t f = (uint32_t)(v & 3u);
+        if (f == 0) {
+          if (++spins > kTileSpin) {  // never expected: report it and go on
+            count(w.cnt, C_SPIN);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        excl += v >> 2;
+        if (f == 2) break;
+        p--;
+      }
+      __hip_atomic_store(st + tile, ((excl + agg) << 2) | 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    s_excl = excl;
+    if ((uint64_t)(tile + 1) * 256 >= g.n_blocks) w.tot[0] = excl + agg;  // the field's payload words
+  }
+  __syncthreads();
+  if (!active) return;
+
+  // ---- encoding: the codes again, a plane at a time --------------------------
+  PlaneCodes<B0, B1, B2> bc;
+  bc.init(w.codes, blk, g.groups);
+  bc.load(0);
+  uint32_t *ring = ring_all + threadIdx.x;  // word with absolute index a at ring[(a & 15) * 256]
+  uint32_t *pay = (uint32_t *)(out + h.off_payload);
+  uint64_t wabs = s_excl + before + (incl - words);  // absolute index of the next word produced
+  uint64_t fl = wabs;                       // first word not yet written out
+  auto flush = [&]() {
+    if (fl & 7) {  // block head: single words up to the first chunk boundary
+      const uint64_t hb = (fl + 7) & ~7ull;
+      if (wabs >= hb)
+        for (; fl < hb; fl++) pay[fl] = ring[(fl & 15) * 256];
+    }
+    if (!(fl & 7) && fl + 8 <= wabs) {
+      const uint32_t s0 = (uint32_t)(fl & 8);
+      uint4 u0, u1;
+      u0.x = ring[(s0 + 0) * 256];
+      u0.y = ring[(s0 + 1) * 256];
+      u0.z = ring[(s0 + 2) * 256];
+      u0.w = ring[(s0 + 3) * 256];
+      u1.x = ring[(s0 + 4) * 256];
+      u1.y = ring[(s0 + 5) * 256];
+      u1.z = ring[(s0 + 6) * 256];
+      u1.w = ring[(s0 + 7) * 256];
+      uint4 *d = (uint4 *)(pay + fl);
+      d[0] = u0;
+      d[1] = u1;
+      fl += 8;
+    }
+  };
+  uint64_t acc = 0;
+  uint32_t nacc = 0;
+  constexpr int FE = B2 < 8 ? B2 : 8;  // codes between flushes (<= 6 words), as in k_encode_fast
+#pragma unroll
+  for (int i = 0; i < B0; i++) {
+    if (i + 1 < B0) bc.load(i + 1);
+#pragma unroll
+    for (int j = 0; j < B1; j++) {
+#pragma unroll
+      for (int k = 0; k < B2; k++) {
+        const int q = j * B2 + k;
+        const bool v = (uint32_t)i < e0 && (uint32_t)j < n1 && (uint32_t)k < n2;
+        const uint32_t e = enc_of(v ? bc.at(i, q) : kRadius, encw, w.enc);
+        const uint32_t len = v ? (e & 0xFFu) : 0u;
+        acc = (acc << len) | (e >> 8 & ((1u << len) - 1u));
+        nacc += len;
+        if (nacc >= 32) {
+          nacc -= 32;
+          ring[(wabs & 15) * 256] = (uint32_t)(acc >> nacc);
+          wabs++;
+          acc &= (1ull << nacc) - 1;
+        }
+        if ((k + 1) % FE == 0 || k + 1 == B2) flush();
+      }
+      __asm__ volatile("" : "+v"(acc), "+v"(nacc), "+v"(wabs), "+v"(fl)::"memory");
+    }
+  }
+  if (nacc > 0) {
+    ring[(wabs & 15) * 256] = (uint32_t)(acc << (32 - nacc));
+    wabs++;
+  }
+  flush();
+  for (; fl < wabs; fl++) pay[fl] = ring[(fl & 15) * 256];  // block tail
+  const uint32_t meta = w.meta[blk];
+  uint32_t *tab = (uint32_t *)(out + h.off_table) + 2 * blk;
+  tab[0] = words;
+  tab[1] = meta;
+  if (__builtin_expect((meta >> 1) != 0, 0)) {
+    const T *src = (const T *)w.vals + blk * (uint64_t)g.bpts;
+    T *od = (T *)(out + h.off_outliers) + w.off_out[blk];
+    for (uint32_t t = 0; t < (meta >> 1); t++) od[t] = src[t];
+  }
+  if (meta & 1u) {
+    const T *cf = (const T *)w.coef + 4 * blk;
+    T *cd = (T *)(out + h.off_coef) + 4ull * w.off_coef[blk];
+    for (int a = 0; a < 4; a++) cd[a] = cf[a];
+  }
+  if (h.abft) ((uint64_t *)(out + h.off_sumdc))[blk] = w.sum_dc[blk];
+}
+
+template __global__ void k_checkenc_fast<float, 6, 6, 6>(JobTab);
+template __global__ void k_checkenc_fast<double, 6, 6, 6>(JobTab);
 template __global__ void k_check_fast<3, 6, 6, 6>(JobTab);
 template __global__ void k_check_fast<2, 1, 16, 16>(JobTab);
 template __global__ void k_encode_fast<float, 3, 6, 6, 6>(JobTab);

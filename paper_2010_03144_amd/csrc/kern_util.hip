@@ -206,9 +206,10 @@ struct Tri {
   uint64_t c;
 };
 
+// (no words: a scan of the outliers and regression blocks only)
 __device__ inline Tri item(const ScanSrc &s, uint64_t i) {
   uint32_t m = s.meta[i * s.stride];
-  return Tri{s.words[i * s.stride], m >> 1, m & 1u};
+  return Tri{s.words ? s.words[i * s.stride] : 0u, m >> 1, m & 1u};
 }
 
 __device__ inline uint64_t wave_inclusive(uint64_t v) {

@@ -465,6 +465,38 @@ def test_output_too_small_writes_nothing(codec):
     assert bool((out[s_r.size:] == 0xA5).all())
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("abft", [True, False])
+def test_one_pass_encoding_matches_two_pass(codec, dtype, abft):
+    # an output that holds the largest stream takes the one-pass code check
+    # and encoding (k_checkenc_fast); a smaller one the check, scans and
+    # encoding in three passes: both give the oracle's stream, code flips
+    # (repaired with ABFT) included, over several tiles of 256 blocks
+    import ctypes as C
+    shape = (60, 66, 54)  # 10 x 11 x 9 blocks: 990, four tiles, the last partial
+    x = synth.grf_field(shape, seed=44, dtype=dtype)
+    plan = synth.fault_plan(shape, (6, 6, 6), dtype, {"code": 8}, seed=45) if abft else None
+    rc_r, s_r, rep_r = ref.compress(x, (6, 6, 6), 1e-4, abft=abft, faults=plan)
+    assert rc_r == 0
+    xd = torch.from_numpy(x).cuda()
+    rc, s_one, rep_one = codec.compress(xd, (6, 6, 6), 1e-4, abft=abft, faults=plan)
+    assert rc == 0 and np.array_equal(s_one.cpu().numpy(), s_r), first_difference(s_r, s_one.cpu().numpy())
+    same_counts(rep_r, rep_one)
+    L = sdcsz.lib()
+    p = sdcsz.make_params(x.shape, dtype == np.float32, (6, 6, 6), 1e-4, abft=abft, faults=plan)
+    ws = torch.empty(L.sdcsz_compress_workspace_size(C.byref(p)), dtype=torch.uint8, device="cuda")
+    assert s_r.size < L.sdcsz_max_compressed_size(C.byref(p))
+    out = torch.zeros(s_r.size, dtype=torch.uint8, device="cuda")
+    size = C.c_uint64(0)
+    rep = sdcsz.Report()
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    rc = L.sdcsz_compress(C.c_void_p(xd.data_ptr()), C.byref(p), C.c_void_p(out.data_ptr()), out.numel(),
+                          C.byref(size), C.byref(rep), C.c_void_p(ws.data_ptr()), ws.numel(), st)
+    assert rc == 0 and size.value == s_r.size
+    assert np.array_equal(out.cpu().numpy(), s_r)
+    same_counts(rep_r, sdcsz.report_dict(rep))
+
+
 @pytest.mark.parametrize("shape,eb", [((48, 42, 36), 2e-5), ((102, 102, 102), 1e-5),
                                       ((102, 102, 102), 1e-6)])
 def test_large_codebooks_decode_like_the_oracle(codec, shape, eb):
