@@ -38,11 +38,15 @@ def algorithmic_bytes(phase, n, nb, vb, rep, abft):
         return vb * n
     if phase == "predict_quantize":
         return vb * n + 2 * n + vb * n_out + nb * (4 + 4 * vb) + sums
+    check = 2 * n + 4 * nb + (16 * nb if abft else 0)
+    encode = (2 * n + 4 * pw + 2 * vb * n_out + 2 * 4 * vb * n_reg + 16 * nb
+              + (16 * nb if abft else 0))
     if phase == "code_check":
-        return 2 * n + 4 * nb + (16 * nb if abft else 0)
+        # the benchmark's 6x6x6 field checks and encodes its codes in one
+        # pass (k_checkenc_fast), which reads the codes once more itself
+        return check + encode
     if phase == "encode":
-        return (2 * n + 4 * pw + 2 * vb * n_out + 2 * 4 * vb * n_reg + 16 * nb
-                + (16 * nb if abft else 0))
+        return encode
     if phase == "decode":
         return 4 * pw + 8 * nb + vb * n_out + 4 * vb * n_reg + (8 * nb if abft else 0) + vb * n
     if phase in ("scan_compress", "scan_decompress"):
@@ -51,9 +55,9 @@ def algorithmic_bytes(phase, n, nb, vb, rep, abft):
 
 
 # kernel behind each timed phase (one launch per call)
-PHASE_KERNEL = {"range": "k_range<float>", "predict_quantize": "k_compress_fast<float,3,6,6,6,true,false>",
-                "code_check": "k_check_fast<3,6,6,6>", "encode": "k_encode_fast<float,3,6,6,6>",
-                "decode": "k_decode_fast<float,3,6,6,6,false>", "scan_compress": "k_scan1/3",
+PHASE_KERNEL = {"range": "k_range<float>", "predict_quantize": "k_compress_fast<float,3,6,6,6,true,false,false>",
+                "code_check": "k_checkenc_fast<float,6,6,6>", "encode": "k_encode_fast<float,3,6,6,6>",
+                "decode": "k_decode_fast<float,3,6,6,6,false,false>", "scan_compress": "k_scan1/3",
                 "scan_decompress": "k_scan1/3"}
 
 
