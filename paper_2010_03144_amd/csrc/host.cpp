@@ -373,15 +373,17 @@ int fast_class(const Geo &g, uint32_t vb) {
 }
 
 using JobKernel = void (*)(JobTab);
-// [class][dtype][abft][wide]
 // [class][dtype][abft][variant]: variant 0 narrow, 1 wide (fields of 2 GiB
-// or more), 2 narrow with fault plans applied
-#define SDCSZ_CF(T, ND, B0, B1, B2, A)                                                               \
-  {                                                                                                  \
-    k_compress_fast<T, ND, B0, B1, B2, A, false, false>, k_compress_fast<T, ND, B0, B1, B2, A, true, false>, \
-        k_compress_fast<T, ND, B0, B1, B2, A, false, true>                                          \
+// or more), 2 narrow with fault plans applied; 0 and 1 take the full blocks,
+// 3 (narrow) and 4 (wide) the partial shell
+#define SDCSZ_CF(T, ND, B0, B1, B2, A)                                                                       \
+  {                                                                                                          \
+    k_compress_fast<T, ND, B0, B1, B2, A, false, false, 1>, k_compress_fast<T, ND, B0, B1, B2, A, true, false, 1>, \
+        k_compress_fast<T, ND, B0, B1, B2, A, false, true, 0>,                                               \
+        k_compress_fast<T, ND, B0, B1, B2, A, false, false, 2>,                                              \
+        k_compress_fast<T, ND, B0, B1, B2, A, true, false, 2>                                                \
   }
-const JobKernel kCompFast[kClasses][2][2][3] = {
+const JobKernel kCompFast[kClasses][2][2][5] = {
     {{SDCSZ_CF(float, 3, 6, 6, 6, false), SDCSZ_CF(float, 3, 6, 6, 6, true)},
      {SDCSZ_CF(double, 3, 6, 6, 6, false), SDCSZ_CF(double, 3, 6, 6, 6, true)}},
     {{SDCSZ_CF(float, 2, 1, 16, 16, false), SDCSZ_CF(float, 2, 1, 16, 16, true)},
@@ -982,6 +984,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   // t_flist: the fault-applying instantiation over the plans' lists
   Tab t_zero, t_plan, t_range[2], t_fast[kClasses][2][2], t_flist[kClasses][2][2], t_gen[2], t_wave[2], t_wlist[2],
       t_redo[2], t_hist, t_hchunk, t_sa;  // t_sa: the stage-A scans of one-pass fields
+  Tab t_shell[kClasses][2][2];  // the partial shells of the t_fast launches, beside them
   uint32_t lds_wlist[2] = {}, lds_redo[2] = {};  // dynamic LDS of the wave launches
   uint32_t slice_wave[2] = {}, hw_wave[2] = {};  // k_compress_wave: widest block slice and histogram window
   uint64_t nb_fast[kClasses][2][2] = {}, nb_cls[kClasses] = {}, nb_enc[kClasses][2] = {};
@@ -1010,7 +1013,9 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     if (J.eb_mode == SDCSZ_REL && f.g.n_values) t_range[J.dtype].add(j, J.nparts);
     if (f.fast) {
       const int a = J.abft ? 1 : 0;
-      t_fast[f.cls][J.dtype][a].add(j, fast_launch(f.g, &J.L, ln_fast[f.cls][J.dtype][a]));
+      const uint32_t nwg = fast_launch(f.g, &J.L, ln_fast[f.cls][J.dtype][a]);
+      t_fast[f.cls][J.dtype][a].add(j, J.L.full_wgs);
+      t_shell[f.cls][J.dtype][a].add(j, nwg - J.L.full_wgs);
       if (!f.fl.empty()) t_flist[f.cls][J.dtype][a].add(j, grid_for(f.fl.size(), 64));
       const uint32_t lb = wave_lds_bytes(f.g, vbytes(J.dtype));
       if (J.abft) {
@@ -1045,6 +1050,9 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     for (int d = 0; d < 2; d++)
       for (int a = 0; a < 2; a++) up.tabs.push_back(&t_flist[c][d][a]);
   up.tabs.push_back(&t_sa);
+  for (int c = 0; c < kClasses; c++)
+    for (int d = 0; d < 2; d++)
+      for (int a = 0; a < 2; a++) up.tabs.push_back(&t_shell[c][d][a]);
   uint8_t *hs = t_stage.get(std::max<size_t>(up.bytes(nj), 4 * nj + 8 + 8 * t_pair_guess + 64));
   if (!hs) return SDCSZ_EHIP;
   up.place(jobs, hs, ws + B.jobs);
@@ -1059,6 +1067,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   const JobTab *d_fast = &up.dev[14];                       // [class][dtype][abft] in that order
   const JobTab *d_flist = &up.dev[14 + kClasses * 2 * 2];  // the same
   const JobTab &d_sa = up.dev[14 + 2 * kClasses * 2 * 2];
+  const JobTab *d_shell = &up.dev[15 + 2 * kClasses * 2 * 2];  // [class][dtype][abft]
   auto grid = [](const Tab &t) { return dim3(t.total()); };
   launch(PH_NONE, false, false, k_zero_jobs, grid(t_zero), dim3(256), st, d_zero);
   if (t_plan.total()) launch(PH_NONE, false, false, k_plan_bits, grid(t_plan), dim3(256), st, d_plan);
@@ -1073,17 +1082,24 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   launch(PH_NONE, false, false, k_consts, grid(t_hist), dim3(kRangeThreads), st, d_hist);
   // plan blocks, which the production kernels leave, beside them on a second
   // stream: the fault-applying instantiation over its lists, a wave per
-  // block for the others
-  bool any_plan_work = t_wlist[0].total() || t_wlist[1].total();
+  // block for the others; the partial shell of the specialised launches
+  // there too
+  bool side_work = t_wlist[0].total() || t_wlist[1].total();
   for (int c = 0; c < kClasses; c++)
     for (int d = 0; d < 2; d++)
-      for (int a = 0; a < 2; a++) any_plan_work |= t_flist[c][d][a].total() != 0;
+      for (int a = 0; a < 2; a++) side_work |= t_flist[c][d][a].total() != 0 || t_shell[c][d][a].total() != 0;
   hipStream_t side = st;
-  if (any_plan_work) {
+  if (side_work) {
     if (!t_no_side) {
       side = t_side.fork(st);
       if (!side) return SDCSZ_EHIP;
     }
+    for (int c = 0; c < kClasses; c++)
+      for (int d = 0; d < 2; d++)
+        for (int a = 1; a >= 0; a--)
+          if (t_shell[c][d][a].total())
+            launch_shm(PH_NONE, false, false, kCompFast[c][d][a][wide_fast[c][d][a] ? 4 : 3], grid(t_shell[c][d][a]),
+                       dim3(ln_fast[c][d][a]), 4 * hw_fast[c][d][a], side, d_shell[(c * 2 + d) * 2 + a]);
     for (int c = 0; c < kClasses; c++)
       for (int d = 0; d < 2; d++)
         for (int a = 0; a < 2; a++)
@@ -1130,7 +1146,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
       pl.fs.push_back([&](bool a, bool b) { launch(PH_PREDICT, a, b, k_compress_generic<double>, grid(t_gen[1]), dim3(64), st, d_gen[1]); });
     pl.run();
   }
-  if (any_plan_work && !t_no_side) HIPCHK(t_side.join(st));
+  if (side_work && !t_no_side) HIPCHK(t_side.join(st));
   if (t_redo[0].total())
     launch_shm(PH_NONE, false, false, k_redo_wave<float>, grid(t_redo[0]), dim3(64), lds_redo[0], st, d_redo[0]);
   if (t_redo[1].total())

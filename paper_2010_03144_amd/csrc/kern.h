@@ -131,7 +131,7 @@ __global__ void k_dectab(JobTab t);
 __global__ void k_dec_check(JobTab t);
 __global__ void k_hdr_keep(JobTab t, uint32_t mode);
 
-template <typename T, int ND, int B0, int B1, int B2, bool ABFT, bool WIDE, bool FAULTS>
+template <typename T, int ND, int B0, int B1, int B2, bool ABFT, bool WIDE, bool FAULTS, int PART>
 __global__ void k_compress_fast(JobTab t);
 template <typename T, int ND, int B0, int B1, int B2, bool WIDE, bool FAULTS> __global__ void k_decode_fast(JobTab t);
 

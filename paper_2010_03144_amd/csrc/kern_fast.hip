@@ -946,13 +946,18 @@ __device__ inline void queue_redo(const CompWork &w, uint64_t blk, const LaneOut
   }
 }
 
-// Work-groups [0, L.full_wgs) take full blocks, the rest the partial shell.
+// Work-groups [0, L.full_wgs) of a job take its full blocks, the rest the
+// partial shell.  PART 1 launches the full blocks' work-groups and PART 2 the
+// shell's, numbered from 0 (the host runs them on two streams at once): in
+// one kernel the two paths would share one register allocation, and the
+// masked path's needs made the full-block path spill.
 // FAULTS: the instantiation that applies the fault plan's flips, one lane
 // per block of the plan's list (plan.flist) on the masked path.
-template <typename T, int ND, int B0, int B1, int B2, bool ABFT, bool WIDE, bool FAULTS>
+template <typename T, int ND, int B0, int B1, int B2, bool ABFT, bool WIDE, bool FAULTS, int PART>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(ND == 3 && sizeof(T) == 4 ? (FAULTS ? 2 : 3) : 1)))
 k_compress_fast(JobTab tab) {
+  static_assert(FAULTS ? PART == 0 : (PART == 1 || PART == 2), "production launches take one part");
   const JobWg jw = job_of(tab);
   const T *__restrict__ in = (const T *)jw.J->src;
   const Geo g = jw.J->g;
@@ -988,27 +993,18 @@ k_compress_fast(JobTab tab) {
       o = compress_lanes<T, ND, B0, B1, B2, false, ABFT, WIDE, kFaults>(in, g, rt, plan, w, predictor, hist, hlo, hw,
                                                                         hot, blk, act, st);
   } else {
-  const bool full = jw.b < L.full_wgs;
-  const uint64_t idx = (uint64_t)(full ? jw.b : jw.b - L.full_wgs) * blockDim.x + threadIdx.x;
+  constexpr bool full = PART == 1;
+  const uint64_t idx = (uint64_t)jw.b * blockDim.x + threadIdx.x;
   const uint64_t nl = full ? L.full_count : L.shell_count;
   const bool act = idx < nl;
   blk = map_block(g, L, full ? 0u : 1u, act ? idx : nl - 1);
   constexpr int M = kProd;
   if constexpr (ND == 2) {
     static_assert(B0 == 1, "2D blocks have one plane");
-    if (full)
-      o = compress_rows<T, B1, B2, true, ABFT, WIDE, M>(in, g, rt, plan, w, predictor, hist, hlo, hw, hot, blk, act,
-                                                        st);
-    else
-      o = compress_rows<T, B1, B2, false, ABFT, WIDE, M>(in, g, rt, plan, w, predictor, hist, hlo, hw, hot, blk, act,
-                                                         st);
+    o = compress_rows<T, B1, B2, full, ABFT, WIDE, M>(in, g, rt, plan, w, predictor, hist, hlo, hw, hot, blk, act, st);
   } else {
-    if (full)
-      o = compress_lanes<T, ND, B0, B1, B2, true, ABFT, WIDE, M>(in, g, rt, plan, w, predictor, hist, hlo, hw, hot,
-                                                                 blk, act, st);
-    else
-      o = compress_lanes<T, ND, B0, B1, B2, false, ABFT, WIDE, M>(in, g, rt, plan, w, predictor, hist, hlo, hw, hot,
-                                                                  blk, act, st);
+    o = compress_lanes<T, ND, B0, B1, B2, full, ABFT, WIDE, M>(in, g, rt, plan, w, predictor, hist, hlo, hw, hot, blk,
+                                                               act, st);
   }
   }
   if (ABFT && __builtin_expect(o.why != 0, 0)) queue_redo(w, blk, o);
@@ -1021,15 +1017,18 @@ k_compress_fast(JobTab tab) {
     if (hist[t]) atomicAdd(w.hist + hlo + t, hist[t]);
 }
 
-#define SDCSZ_INST_FAST(T, ND, B0, B1, B2, ABFT, WIDE, FAULTS) \
-  template __global__ void k_compress_fast<T, ND, B0, B1, B2, ABFT, WIDE, FAULTS>(JobTab);
-#define SDCSZ_INST_SHAPE(T, ND, B0, B1, B2)                \
-  SDCSZ_INST_FAST(T, ND, B0, B1, B2, true, false, false)  \
-  SDCSZ_INST_FAST(T, ND, B0, B1, B2, false, false, false) \
-  SDCSZ_INST_FAST(T, ND, B0, B1, B2, true, true, false)   \
-  SDCSZ_INST_FAST(T, ND, B0, B1, B2, false, true, false)  \
-  SDCSZ_INST_FAST(T, ND, B0, B1, B2, true, false, true)   \
-  SDCSZ_INST_FAST(T, ND, B0, B1, B2, false, false, true)
+#define SDCSZ_INST_FAST(T, ND, B0, B1, B2, ABFT, WIDE, FAULTS, PART) \
+  template __global__ void k_compress_fast<T, ND, B0, B1, B2, ABFT, WIDE, FAULTS, PART>(JobTab);
+#define SDCSZ_INST_PROD(T, ND, B0, B1, B2, ABFT, WIDE)        \
+  SDCSZ_INST_FAST(T, ND, B0, B1, B2, ABFT, WIDE, false, 1) \
+  SDCSZ_INST_FAST(T, ND, B0, B1, B2, ABFT, WIDE, false, 2)
+#define SDCSZ_INST_SHAPE(T, ND, B0, B1, B2)          \
+  SDCSZ_INST_PROD(T, ND, B0, B1, B2, true, false)   \
+  SDCSZ_INST_PROD(T, ND, B0, B1, B2, false, false)  \
+  SDCSZ_INST_PROD(T, ND, B0, B1, B2, true, true)    \
+  SDCSZ_INST_PROD(T, ND, B0, B1, B2, false, true)   \
+  SDCSZ_INST_FAST(T, ND, B0, B1, B2, true, false, true, 0) \
+  SDCSZ_INST_FAST(T, ND, B0, B1, B2, false, false, true, 0)
 SDCSZ_INST_SHAPE(float, 3, 6, 6, 6)
 SDCSZ_INST_SHAPE(double, 3, 6, 6, 6)
 SDCSZ_INST_SHAPE(float, 2, 1, 16, 16)

@@ -281,10 +281,11 @@ template <typename T, int ND, int B0, int B1, int B2> __global__ void __launch_b
   if (h.abft) ((uint64_t *)(out + h.off_sumdc))[blk] = w.sum_dc[blk];
 }
 
-// Code check and encoding in one pass (Algorithm 1 before and at the
-// encoding) for 3D blocks, one lane per block: a lane reads its block's codes
-// once and keeps them in registers while the payload offsets are found, then
-// encodes them.  The offsets come from a scan across work-groups with a
+// Code check and encoding in one kernel (Algorithm 1 before and at the
+// encoding) for 3D blocks, one lane per block: a lane checks its block's
+// codes a plane at a time (sums and codeword lengths), takes its payload
+// offset, then reads the codes again, now mostly from the caches, and encodes
+// them.  The offsets come from a scan across work-groups with a
 // decoupled look-back: a work-group takes the next tile of 256 blocks of its
 // field from a ticket counter (so every tile it waits for belongs to a
 // work-group already running), publishes its tile's payload words, and adds
