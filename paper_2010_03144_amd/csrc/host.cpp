@@ -477,7 +477,8 @@ thread_local Staging t_stage;
 
 // A second stream of the calling thread (default priority, made on first use
 // on a device and kept until the thread exits): a call's fault-plan work
-// runs there beside the main launch, between a fork and a join event.
+// (and, on another one, the compressor's partial shells) runs there beside
+// the main launch, between a fork and a join event.
 struct SideStream {
   int dev = -1;
   hipStream_t s = nullptr;
@@ -515,7 +516,8 @@ struct SideStream {
   ~SideStream() { drop(); }
 };
 thread_local SideStream t_side;
-// calls that must not create resources run their plan work on the main stream
+thread_local SideStream t_shell_side;  // compression: the partial shells of the specialised launches
+// calls that must not create resources run their plan and shell work on the main stream
 thread_local bool t_no_side = false;
 // the staging of decompression calls: the thread's own, unless a call that
 // must not allocate has put a fixed buffer in its place
@@ -1082,24 +1084,34 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   launch(PH_NONE, false, false, k_consts, grid(t_hist), dim3(kRangeThreads), st, d_hist);
   // plan blocks, which the production kernels leave, beside them on a second
   // stream: the fault-applying instantiation over its lists, a wave per
-  // block for the others; the partial shell of the specialised launches
-  // there too
-  bool side_work = t_wlist[0].total() || t_wlist[1].total();
+  // block for the others; the partial shell of the specialised launches on
+  // a third stream
+  bool side_work = t_wlist[0].total() || t_wlist[1].total(), shell_work = false;
   for (int c = 0; c < kClasses; c++)
     for (int d = 0; d < 2; d++)
-      for (int a = 0; a < 2; a++) side_work |= t_flist[c][d][a].total() != 0 || t_shell[c][d][a].total() != 0;
-  hipStream_t side = st;
-  if (side_work) {
+      for (int a = 0; a < 2; a++) {
+        side_work |= t_flist[c][d][a].total() != 0;
+        shell_work |= t_shell[c][d][a].total() != 0;
+      }
+  if (shell_work) {
+    hipStream_t s2 = st;
     if (!t_no_side) {
-      side = t_side.fork(st);
-      if (!side) return SDCSZ_EHIP;
+      s2 = t_shell_side.fork(st);
+      if (!s2) return SDCSZ_EHIP;
     }
     for (int c = 0; c < kClasses; c++)
       for (int d = 0; d < 2; d++)
         for (int a = 1; a >= 0; a--)
           if (t_shell[c][d][a].total())
             launch_shm(PH_NONE, false, false, kCompFast[c][d][a][wide_fast[c][d][a] ? 4 : 3], grid(t_shell[c][d][a]),
-                       dim3(ln_fast[c][d][a]), 4 * hw_fast[c][d][a], side, d_shell[(c * 2 + d) * 2 + a]);
+                       dim3(ln_fast[c][d][a]), 4 * hw_fast[c][d][a], s2, d_shell[(c * 2 + d) * 2 + a]);
+  }
+  hipStream_t side = st;
+  if (side_work) {
+    if (!t_no_side) {
+      side = t_side.fork(st);
+      if (!side) return SDCSZ_EHIP;
+    }
     for (int c = 0; c < kClasses; c++)
       for (int d = 0; d < 2; d++)
         for (int a = 0; a < 2; a++)
@@ -1147,6 +1159,7 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
     pl.run();
   }
   if (side_work && !t_no_side) HIPCHK(t_side.join(st));
+  if (shell_work && !t_no_side) HIPCHK(t_shell_side.join(st));
   if (t_redo[0].total())
     launch_shm(PH_NONE, false, false, k_redo_wave<float>, grid(t_redo[0]), dim3(64), lds_redo[0], st, d_redo[0]);
   if (t_redo[1].total())

@@ -36,7 +36,8 @@ constexpr uint32_t kRangeBlocks = 2048;
 // Work of one specialised launch: work-groups [0, full_wgs) take the
 // sub-grid of full blocks, the others the shell of partial blocks at the
 // upper edges (the slab of blocks partial along the fastest axis, then the
-// middle, then the slowest, each excluding the earlier slabs).
+// middle, then the slowest, each excluding the earlier slabs).  The
+// compressor launches the two apart, each numbering its work-groups from 0.
 struct Launch {
   uint32_t nf[3];      // full blocks per axis
   uint32_t full_wgs;   // work-groups of full blocks

@@ -204,6 +204,9 @@ class Codec:
         self._meta = {}
         # region-decoding states of recently used streams: pointer -> RegionState
         self._regions = {}
+        # parameters and sizes of recent call shapes without fault plans
+        self._cp = {}  # compress: (shape, dtype, block, eb, mode, abft, predictor) -> (Params, ws, cap)
+        self._dp = {}  # decompress: (shape, is_f32, block) -> (Params, ws)
 
     def workspace(self, nbytes, tag):
         """A device buffer of at least nbytes kept under `tag`.  It grows by
@@ -234,12 +237,20 @@ class Codec:
         torch = self.torch
         L = lib()
         assert x.is_cuda and x.is_contiguous() and x.dtype in (torch.float32, torch.float64)
-        p = make_params(tuple(x.shape), x.dtype == torch.float32, block, eb, eb_mode, abft,
-                        predictor, faults)
-        ws_n = L.sdcsz_compress_workspace_size(C.byref(p))
+        plain = faults is None or len(faults) == 0
+        key = (tuple(x.shape), x.dtype, tuple(block), float(eb), eb_mode, bool(abft), predictor) if plain else None
+        ent = self._cp.get(key) if key else None
+        if ent is None:
+            p = make_params(tuple(x.shape), x.dtype == torch.float32, block, eb, eb_mode, abft,
+                            predictor, faults)
+            ent = (p, L.sdcsz_compress_workspace_size(C.byref(p)), L.sdcsz_max_compressed_size(C.byref(p)))
+            if key and ent[1]:
+                if len(self._cp) >= 64:
+                    self._cp.clear()
+                self._cp[key] = ent
+        p, ws_n, cap = ent
         if ws_n == 0:
             return EINVAL, None, None
-        cap = L.sdcsz_max_compressed_size(C.byref(p))
         if out is None or out.numel() < cap:
             out = self.workspace(cap, "stream_out")
         ws = self.workspace(ws_n, "compress")
@@ -281,9 +292,21 @@ class Codec:
         else read from the stream's header on the device."""
         m = self._meta.get(stream.data_ptr())
         if m is not None and m[0] == stream.numel():
-            p = make_params(m[1], m[2] == 0, m[3], 1.0)
-            return OK, p, m[1]
+            return OK, self._dec_params(m[1], m[2] == 0, m[3])[0], m[1]
         return self.info(stream)
+
+    def _dec_params(self, shape, is_f32, block):
+        """(Params, workspace bytes without fault plans) of a decompression;
+        the Params are shared: callers must not change them."""
+        key = (tuple(shape), bool(is_f32), tuple(int(b) for b in block))
+        ent = self._dp.get(key)
+        if ent is None:
+            p = make_params(key[0], is_f32, key[2], 1.0)
+            ent = (p, int(lib().sdcsz_decompress_workspace_size(C.byref(p))))
+            if len(self._dp) >= 64:
+                self._dp.clear()
+            self._dp[key] = ent
+        return ent
 
     def info(self, stream):
         L = lib()
@@ -298,9 +321,13 @@ class Codec:
         return rc, p, shape
 
     def _dec_ws(self, p, n_faults):
-        L = lib()
-        p.n_faults = n_faults
-        n = L.sdcsz_decompress_workspace_size(C.byref(p))
+        if n_faults == 0:
+            n = self._dec_params(tuple(p.dims[a] for a in range(p.ndim)), p.dtype == 0,
+                                 tuple(p.block[a] for a in range(p.ndim)))[1]
+        else:
+            q = Params.from_buffer_copy(p)  # p may be shared
+            q.n_faults = n_faults
+            n = lib().sdcsz_decompress_workspace_size(C.byref(q))
         return self.workspace(n, "decompress")
 
     # ---------------------------------------------------------------- decompress
@@ -314,7 +341,7 @@ class Codec:
         torch = self.torch
         L = lib()
         if geom is not None:
-            rc, p, shape = OK, make_params(tuple(geom[0]), geom[1], geom[2], 1.0), tuple(geom[0])
+            rc, p, shape = OK, self._dec_params(geom[0], geom[1], geom[2])[0], tuple(geom[0])
         else:
             rc, p, shape = self._geometry(stream)
         if rc != OK:
@@ -505,8 +532,8 @@ class Codec:
                 hbuf = C.create_string_buffer(bytes(hb), HEADER_BYTES)
                 keep.append(hbuf)
                 items[i].h_header = C.cast(hbuf, C.c_void_p)
-            p.n_faults = nf
-            params[i] = p
+            params[i] = p  # a copy (p may be shared)
+            params[i].n_faults = nf
             dt = torch.float32 if p.dtype == 0 else torch.float64
             if outs[i] is None:
                 outs[i] = torch.empty(shape, dtype=dt, device=self.device)
@@ -533,8 +560,9 @@ class Codec:
             header = self._header(stream)
         if header is None:
             header = bytes(stream[:HEADER_BYTES].cpu().numpy())
-        p.n_faults = 0
-        ws = torch.empty(int(L.sdcsz_decompress_workspace_size(C.byref(p))), dtype=torch.uint8,
+        q = Params.from_buffer_copy(p)  # p may be shared
+        q.n_faults = 0
+        ws = torch.empty(int(L.sdcsz_decompress_workspace_size(C.byref(q))), dtype=torch.uint8,
                          device=self.device)
         hbuf = C.create_string_buffer(bytes(header), HEADER_BYTES)
         rc = L.sdcsz_region_prepare(C.c_void_p(stream.data_ptr()), stream.numel(), C.cast(hbuf, C.c_void_p),
