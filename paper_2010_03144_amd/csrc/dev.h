@@ -5,6 +5,16 @@
 
 namespace sdcsz {
 
+// ---- global-memory views of device pointers -------------------------------
+// A pointer read out of a job table has no known address space, so accesses
+// through it compile to flat instructions, and a flat access counts on the
+// LDS counter too: the wait for the next LDS result then also waits for it
+// (a prefetch, a store).  Accesses through these views are global ones.
+template <typename T> using gptr = __attribute__((address_space(1))) T *;
+template <typename T> __device__ inline gptr<T> gbl(T *p) { return (gptr<T>)p; }
+typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));  // 16- and 8-byte accesses without a class copy
+typedef uint32_t v2u32 __attribute__((ext_vector_type(2)));
+
 // ---- words of a value (integer reinterpretation, Sec. 5.4) ---------------
 template <typename T> struct Wd;
 template <> struct Wd<float> {

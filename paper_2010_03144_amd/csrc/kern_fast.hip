@@ -333,9 +333,9 @@ __device__ __forceinline__ LaneOut compress_lanes(const T *__restrict__ in, cons
       return FULL || ((uint32_t)i < n0 && (uint32_t)j < n1 && (uint32_t)k < n2);
     };
     auto ld = [&](int i, int j, int k) -> T {
-      if (FULL) return *(const T *)(wbase + (loff + (uint32_t)i * PSB + (uint32_t)j * RSB) + k * sizeof(T));
+      if (FULL) return *gbl((const T *)(wbase + (loff + (uint32_t)i * PSB + (uint32_t)j * RSB) + k * sizeof(T)));
       const uint32_t ii = min((uint32_t)i, n0 - 1), jj = min((uint32_t)j, n1 - 1), kk = min((uint32_t)k, n2 - 1);
-      const T v = *(const T *)(wbase + (loff + ii * PSB + jj * RSB + kk * (uint32_t)sizeof(T)));
+      const T v = *gbl((const T *)(wbase + (loff + ii * PSB + jj * RSB + kk * (uint32_t)sizeof(T))));
       return valid(i, j, k) ? v : (T)0;
     };
 
@@ -474,7 +474,7 @@ __device__ __forceinline__ LaneOut compress_lanes(const T *__restrict__ in, cons
     uint32_t s_q = 0, nout = 0;
     uint32_t mis_p = 0, mis_r = 0;  // OR of bit differences between the duplicated results
     T *outl = (T *)w.vals + blk * (uint64_t)g.bpts;
-    uint2 *cbase = (uint2 *)(w.codes + code_index(blk, 0, g.groups));  // next group is 64 vectors on
+    const gptr<v2u32> cbase = gbl((v2u32 *)(w.codes + code_index(blk, 0, g.groups)));  // next group is 64 vectors on
     T xn[B2], xn2[B2];  // the next two rows, loaded two rows ahead of their use
 #pragma unroll
     for (int k = 0; k < B2; k++) {
@@ -579,7 +579,7 @@ __device__ __forceinline__ LaneOut compress_lanes(const T *__restrict__ in, cons
           Up = U1;
           const bool is_out = v && !ok;
           if (__builtin_expect(__ballot(is_out) != 0, 0)) {
-            if (is_out) outl[nout] = xv;
+            if (is_out) gbl(outl)[nout] = xv;
             nout += is_out ? 1u : 0u;
           }
           const bool z = v && code == kRadius;
@@ -607,7 +607,7 @@ __device__ __forceinline__ LaneOut compress_lanes(const T *__restrict__ in, cons
             if ((qp & 2) == 0) pk0 |= code << 16;
             else pk1 |= code << 16;
           }
-          if ((qp & 3) == 3) cbase[(uint64_t)((i * PL + qp) >> 2) * 64] = make_uint2(pk0, pk1);
+          if ((qp & 3) == 3) cbase[(uint64_t)((i * PL + qp) >> 2) * 64] = v2u32{pk0, pk1};
         }
         if (ABFT) {
           const uint32_t rowbase = ((uint32_t)i * n1 + (uint32_t)j) * n2;
@@ -678,9 +678,9 @@ __device__ __forceinline__ LaneOut compress_rows(const T *__restrict__ in, const
   const uint32_t RSB = (uint32_t)(g.d[2] * sizeof(T));
   auto valid = [&](int j, int k) -> bool { return FULL || ((uint32_t)j < n1 && (uint32_t)k < n2); };
   auto ld = [&](int j, int k) -> T {
-    if (FULL) return *(const T *)(wbase + (loff + (uint32_t)j * RSB) + k * sizeof(T));
+    if (FULL) return *gbl((const T *)(wbase + (loff + (uint32_t)j * RSB) + k * sizeof(T)));
     const uint32_t jj = min((uint32_t)j, n1 - 1), kk = min((uint32_t)k, n2 - 1);
-    const T v = *(const T *)(wbase + (loff + jj * RSB + kk * (uint32_t)sizeof(T)));
+    const T v = *gbl((const T *)(wbase + (loff + jj * RSB + kk * (uint32_t)sizeof(T))));
     return valid(j, k) ? v : (T)0;
   };
 
@@ -803,7 +803,7 @@ __device__ __forceinline__ LaneOut compress_rows(const T *__restrict__ in, const
   uint32_t s_q = 0, nout = 0;
   uint32_t mis_p = 0, mis_r = 0;
   T *outl = (T *)w.vals + blk * (uint64_t)g.bpts;
-  uint2 *cbase = (uint2 *)(w.codes + code_index(blk, 0, g.groups));
+  const gptr<v2u32> cbase = gbl((v2u32 *)(w.codes + code_index(blk, 0, g.groups)));
   T xn1[B2], xn2[B2];  // the next two rows, loaded two rows ahead of their use
 #pragma unroll
   for (int k = 0; k < B2; k++) {
@@ -876,7 +876,7 @@ __device__ __forceinline__ LaneOut compress_rows(const T *__restrict__ in, const
       cprev = r_out;
       const bool is_out = v && !ok;
       if (__builtin_expect(__ballot(is_out) != 0, 0)) {
-        if (is_out) outl[nout] = xv;
+        if (is_out) gbl(outl)[nout] = xv;
         nout += is_out ? 1u : 0u;
       }
       const bool z = v && code == kRadius;
@@ -900,7 +900,7 @@ __device__ __forceinline__ LaneOut compress_rows(const T *__restrict__ in, const
         if ((k & 2) == 0) pk0 |= code << 16;
         else pk1 |= code << 16;
       }
-      if ((k & 3) == 3) cbase[(uint64_t)((j * B2 + k) >> 2) * 64] = make_uint2(pk0, pk1);
+      if ((k & 3) == 3) cbase[(uint64_t)((j * B2 + k) >> 2) * 64] = v2u32{pk0, pk1};
       // work in steps of 4 points (the duplicated computations of a whole
       // row at once would need twice the registers)
       if ((k & 3) == 3 && k + 1 < B2) row_fence(cprev, fold, S2, Q2, s_dc, rs, rk, nout, mis_p, mis_r);

@@ -20,7 +20,7 @@ __device__ inline uint32_t enc_of(uint32_t code, const uint32_t *encw, const uin
   const uint32_t c = code - kEncLo;
   uint32_t e = encw[c < kEncWin ? c : 0u];
   if (__builtin_expect(c >= kEncWin, 0)) {
-    uint32_t f = enc[code];
+    uint32_t f = gbl(enc)[code];
     __asm__ volatile("" : "+v"(f));
     e = f;
   }
@@ -73,7 +73,7 @@ template <int B0, int B1, int B2, bool LAST = true> struct PlaneCodes {
     for (int gi = 0; gi < PG; gi++) {
       // the last read of the codes is non-temporal, so they do not displace
       // the output in the caches; an earlier one keeps them there
-      const uint64_t *a = (const uint64_t *)(cb + (uint64_t)(i * PG + gi) * 64);
+      const gptr<const uint64_t> a = gbl((const uint64_t *)(cb + (uint64_t)(i * PG + gi) * 64));
       const uint64_t u64 = LAST ? __builtin_nontemporal_load(a) : *a;
       const uint2 u = make_uint2((uint32_t)u64, (uint32_t)(u64 >> 32));
       v[i & 1][2 * gi] = u.x;
@@ -205,7 +205,7 @@ template <typename T, int ND, int B0, int B1, int B2> __global__ void __launch_b
   bc.init(w.codes, blk, g.groups);
   bc.load(0);
   uint32_t *ring = ring_all + threadIdx.x;  // word with absolute index a at ring[(a & 15) * 256]
-  uint32_t *pay = (uint32_t *)(out + h.off_payload);
+  const gptr<uint32_t> pay = gbl((uint32_t *)(out + h.off_payload));
   uint64_t wabs = w.off_pay[blk];  // absolute index of the next word produced
   uint64_t fl = wabs;              // first word not yet written out
   auto flush = [&]() {
@@ -225,9 +225,9 @@ template <typename T, int ND, int B0, int B1, int B2> __global__ void __launch_b
       u1.y = ring[(s0 + 5) * 256];
       u1.z = ring[(s0 + 6) * 256];
       u1.w = ring[(s0 + 7) * 256];
-      uint4 *d = (uint4 *)(pay + fl);
-      d[0] = u0;
-      d[1] = u1;
+      const gptr<v4u32> d = (gptr<v4u32>)(pay + fl);
+      d[0] = v4u32{u0.x, u0.y, u0.z, u0.w};
+      d[1] = v4u32{u1.x, u1.y, u1.z, u1.w};
       fl += 8;
     }
   };
@@ -454,7 +454,7 @@ __global__ void __launch_bounds__(256) k_checkenc_fast(JobTab jt) {
   bc.init(w.codes, blk, g.groups);
   bc.load(0);
   uint32_t *ring = ring_all + threadIdx.x;  // word with absolute index a at ring[(a & 15) * 256]
-  uint32_t *pay = (uint32_t *)(out + h.off_payload);
+  const gptr<uint32_t> pay = gbl((uint32_t *)(out + h.off_payload));
   uint64_t wabs = s_excl + before + (incl - words);  // absolute index of the next word produced
   uint64_t fl = wabs;                       // first word not yet written out
   auto flush = [&]() {
@@ -474,9 +474,9 @@ __global__ void __launch_bounds__(256) k_checkenc_fast(JobTab jt) {
       u1.y = ring[(s0 + 5) * 256];
       u1.z = ring[(s0 + 6) * 256];
       u1.w = ring[(s0 + 7) * 256];
-      uint4 *d = (uint4 *)(pay + fl);
-      d[0] = u0;
-      d[1] = u1;
+      const gptr<v4u32> d = (gptr<v4u32>)(pay + fl);
+      d[0] = v4u32{u0.x, u0.y, u0.z, u0.w};
+      d[1] = v4u32{u1.x, u1.y, u1.z, u1.w};
       fl += 8;
     }
   };
