@@ -158,7 +158,7 @@ struct Window {
 // Canonical decoding tables in LDS: the two-level prefix table (lut2), the
 // first kSubLds entries of its second level, and first code, count and first
 // position per length for prefixes that keep the search.
-constexpr uint32_t kSubLds = 3840;
+constexpr uint32_t kSubLds = 2048;
 struct DecLds {
   uint32_t lut[1u << kLutBits];
   uint32_t first[kMaxLen + 2], count[kMaxLen + 2], start[kMaxLen + 2];
@@ -275,7 +275,8 @@ struct DecOut {
 template <typename T, int ND, int B0, int B1, int B2, bool FULL, bool REG, bool WIDE, int MODE>
 __device__ __forceinline__ DecOut decode_lanes(const uint8_t *__restrict__ s, const Header &h, const Geo &g,
                                                const DecWork &w, const PlanDev &plan, T *out, const DecLds &tl,
-                                               uint32_t *win, uint64_t blk, bool active, const Region &reg) {
+                                               uint32_t *win, uint64_t blk, bool active, const Region &reg,
+                                               T *stg, uint32_t *lof) {
   static_assert(!(REG && FULL), "a region launch takes the masked path");
   const Box bx = box_of(g, blk);
   const uint64_t org = fidx(g, bx, 0, 0, 0);
@@ -287,6 +288,27 @@ __device__ __forceinline__ DecOut decode_lanes(const uint8_t *__restrict__ s, co
   // plan blocks: the fault-applying launch over the plan's list, or k_decode_wave_list
   if (MODE == kDProd && active && plan_hit(plan, blk)) active = false;
   const LaneRecon lf = MODE == kDFaults ? lane_recon(plan, blk, active, Wd<T>::per) : LaneRecon{};
+  // A wave of full blocks with every lane active stores its rows through
+  // LDS (stg: 64 rows of B2 values; lof: the lanes' offsets): B2 passes of 64
+  // consecutive values, so that each store instruction covers whole cache
+  // lines.  Stored lane by lane, the rows leave partial lines (24 bytes per
+  // lane in FP32), which non-temporal stores write out slowly.
+  constexpr bool CAN_COOP = FULL && !REG && MODE == kDProd && !WIDE;
+  uint32_t soff[CAN_COOP ? B2 : 1];  // byte offset (before the row's) of the value each pass stores
+  bool coop = false;
+  const uint32_t lane = threadIdx.x & 63;
+  if constexpr (CAN_COOP) {
+    coop = __ballot(active) == ~0ull;
+    if (coop) {
+      lof[lane] = loff;
+      __asm__ volatile("" ::: "memory");  // the wave's LDS accesses run in order
+#pragma unroll
+      for (int p = 0; p < B2; p++) {
+        const uint32_t f = lane + 64u * (uint32_t)p;
+        soff[p] = lof[f / B2] + (f % B2) * (uint32_t)sizeof(T);
+      }
+    }
+  }
   DecOut res{false, 0};
   if (!active) return res;
 
@@ -396,10 +418,26 @@ __device__ __forceinline__ DecOut decode_lanes(const uint8_t *__restrict__ s, co
       } else {
         // store the row (non-temporal: the output is not read again here, and
         // keeping it out of the caches leaves them to the payload windows)
-        char *dst = wbase + (loff + (uint32_t)i * PSB + (uint32_t)j * RSB);
+        bool stored = false;
+        if constexpr (CAN_COOP) {
+          if (coop) {  // wave-uniform
+            __asm__ volatile("" ::: "memory");  // the last row's reads of stg come first
 #pragma unroll
-        for (int k = 0; k < B2; k++)
-          if (FULL || (uint32_t)k < n2) __builtin_nontemporal_store(rv[k], (T *)(dst + k * sizeof(T)));
+            for (int k = 0; k < B2; k++) stg[lane * B2 + k] = rv[k];
+            __asm__ volatile("" ::: "memory");
+            const uint32_t rowoff = (uint32_t)i * PSB + (uint32_t)j * RSB;
+#pragma unroll
+            for (int p = 0; p < B2; p++)
+              __builtin_nontemporal_store(stg[lane + 64u * (uint32_t)p], gbl((T *)(wbase + (soff[p] + rowoff))));
+            stored = true;
+          }
+        }
+        if (!stored) {
+          char *dst = wbase + (loff + (uint32_t)i * PSB + (uint32_t)j * RSB);
+#pragma unroll
+          for (int k = 0; k < B2; k++)
+            if (FULL || (uint32_t)k < n2) __builtin_nontemporal_store(rv[k], (T *)(dst + k * sizeof(T)));
+        }
       }
 #pragma unroll
       for (int k = 0; k < B2; k++) Sv[k] = rowold[k];
@@ -595,6 +633,11 @@ k_decode_fast(JobTab tab) {
   if (*w.err) return;  // invalid codebook or block table: nothing is read
   __shared__ DecLds tl;
   __shared__ uint32_t win[kRing * kDecThreads];
+  // 3D full blocks: each wave's rows on their way out, and its lanes' offsets
+  __shared__ T stage[ND == 3 ? B2 * kDecThreads : 1];
+  __shared__ uint32_t lofs[ND == 3 ? kDecThreads : 1];
+  T *stg = stage + (ND == 3 ? (threadIdx.x >> 6) * 64u * B2 : 0u);
+  uint32_t *lof = lofs + (ND == 3 ? (threadIdx.x & ~63u) : 0u);
   load_tables(tl, w);
   constexpr int M = FAULTS ? kDFaults : kDProd;
   const Region &reg = jw.J->reg, &rb = jw.J->rblk;
@@ -607,7 +650,7 @@ k_decode_fast(JobTab tab) {
       decode_rows<T, B1, B2, false, false, WIDE, M>(s, h, g, w, plan, out, tl, win + threadIdx.x, blk, act, reg);
     else
       decode_lanes<T, ND, B0, B1, B2, false, false, WIDE, M>(s, h, g, w, plan, out, tl, win + threadIdx.x, blk, act,
-                                                             reg);
+                                                             reg, stg, lof);
   } else {
   if (jw.J->mode == 2) {
     // region decompression: one lane per block of the box of blocks the
@@ -620,7 +663,7 @@ k_decode_fast(JobTab tab) {
       decode_rows<T, B1, B2, false, true, WIDE, M>(s, h, g, w, plan, out, tl, win + threadIdx.x, blk, act, reg);
     else
       decode_lanes<T, ND, B0, B1, B2, false, true, WIDE, M>(s, h, g, w, plan, out, tl, win + threadIdx.x, blk, act,
-                                                            reg);
+                                                            reg, stg, lof);
     return;
   }
   const bool full = jw.b < L.full_wgs;
@@ -637,10 +680,10 @@ k_decode_fast(JobTab tab) {
   } else {
     if (full)
       decode_lanes<T, ND, B0, B1, B2, true, false, WIDE, M>(s, h, g, w, plan, out, tl, win + threadIdx.x, blk, act,
-                                                            reg);
+                                                            reg, stg, lof);
     else
       decode_lanes<T, ND, B0, B1, B2, false, false, WIDE, M>(s, h, g, w, plan, out, tl, win + threadIdx.x, blk, act,
-                                                             reg);
+                                                             reg, stg, lof);
   }
 }
 }
