@@ -1055,7 +1055,12 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   for (int c = 0; c < kClasses; c++)
     for (int d = 0; d < 2; d++)
       for (int a = 0; a < 2; a++) up.tabs.push_back(&t_shell[c][d][a]);
-  uint8_t *hs = t_stage.get(std::max<size_t>(up.bytes(nj), 4 * nj + 8 + 8 * t_pair_guess + 64));
+  // the histogram kernels also write the counts and the first `pre` pairs
+  // straight into this pinned staging, laid out as the device's counts and
+  // pairs (so no copy is queued after them)
+  const uint64_t head = B.pairs - B.counts;
+  const uint64_t pre = std::min<uint64_t>(t_pair_guess, cap);
+  uint8_t *hs = t_stage.get(std::max<size_t>(up.bytes(nj), head + 8 * pre + 64));
   if (!hs) return SDCSZ_EHIP;
   up.place(jobs, hs, ws + B.jobs);
   HIPCHK(hipMemcpyAsync(ws + B.jobs, hs, up.bytes(nj), hipMemcpyHostToDevice, st));
@@ -1178,15 +1183,13 @@ int compress_batch(CompItem *it, uint32_t n, uint8_t *ws, uint64_t ws_size, hipS
   uint64_t *d_pairs = (uint64_t *)(ws + B.pairs);
   uint32_t *d_chunks = (uint32_t *)(ws + B.chunks);
   launch(PH_NONE, false, false, k_hist_count, grid(t_hchunk), dim3(256), st, d_hchunk, d_chunks);
-  launch(PH_NONE, false, false, k_hist_scan, dim3(1), dim3(256), st, nj, d_chunks, d_counts);
+  launch(PH_NONE, false, false, k_hist_scan, dim3(1), dim3(256), st, nj, d_chunks, d_counts, (uint32_t *)hs);
   launch(PH_NONE, false, false, k_hist_pack, grid(t_hchunk), dim3(256), st, d_hchunk, (const uint32_t *)d_chunks,
-         d_pairs);
+         d_pairs, (uint64_t *)(hs + head), pre);
   HIPCHK(hipGetLastError());
 
-  // ---- histograms back (the first t_pair_guess entries with the counts)
-  const uint64_t head = B.pairs - B.counts;
-  const uint64_t pre = std::min<uint64_t>(t_pair_guess, cap);
-  HIPCHK(hipMemcpyAsync(hs, ws + B.counts, head + 8 * pre, hipMemcpyDeviceToHost, st));
+  // ---- histograms back (the counts and the first t_pair_guess entries,
+  // written into the staging by the kernels)
   HIPCHK(sync_wait(st));
   std::vector<uint32_t> cnt_sym((const uint32_t *)hs, (const uint32_t *)hs + nj);
   uint64_t total_pairs = 0;

@@ -122,8 +122,8 @@ __global__ void k_scan2(JobTab t);
 __global__ void k_scan3(JobTab t);
 template <typename T> __global__ void k_encode(JobTab t);
 __global__ void k_hist_count(JobTab t, uint32_t *chunk_cnt);
-__global__ void k_hist_scan(uint32_t n, uint32_t *chunk_cnt, uint32_t *counts);
-__global__ void k_hist_pack(JobTab t, const uint32_t *chunk_off, uint64_t *dst);
+__global__ void k_hist_scan(uint32_t n, uint32_t *chunk_cnt, uint32_t *counts, uint32_t *hcounts);
+__global__ void k_hist_pack(JobTab t, const uint32_t *chunk_off, uint64_t *dst, uint64_t *hdst, uint64_t hn);
 __global__ void k_put_codes(JobTab t);
 __global__ void k_header(JobTab t);
 __global__ void k_results(JobTab t, uint64_t *dst, uint32_t per);

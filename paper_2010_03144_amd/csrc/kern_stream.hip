@@ -77,7 +77,9 @@ __global__ void __launch_bounds__(256) k_hist_count(JobTab t, uint32_t *chunk_cn
 
 // one work-group: exclusive scan of the n * kHistChunks chunk counts in
 // place, and each job's total into counts[] (a job's chunks are one wave)
-__global__ void __launch_bounds__(256) k_hist_scan(uint32_t n, uint32_t *chunk_cnt, uint32_t *counts) {
+// counts: per job, in device memory and (hcounts) in the caller's pinned staging.
+__global__ void __launch_bounds__(256) k_hist_scan(uint32_t n, uint32_t *chunk_cnt, uint32_t *counts,
+                                                   uint32_t *hcounts) {
   const uint32_t total = n * kHistChunks;
   uint32_t carry = 0;
   for (uint32_t base = 0; base < total; base += 256) {
@@ -86,12 +88,18 @@ __global__ void __launch_bounds__(256) k_hist_scan(uint32_t n, uint32_t *chunk_c
     uint32_t all, job_total;
     const uint32_t ex = wg_exclusive_u32(v, &all, &job_total);
     if (i < total) chunk_cnt[i] = carry + ex;
-    if (i < total && (threadIdx.x & 63) == 63) counts[i / kHistChunks] = job_total;
+    if (i < total && (threadIdx.x & 63) == 63) {
+      counts[i / kHistChunks] = job_total;
+      hcounts[i / kHistChunks] = job_total;
+    }
     carry += all;
   }
 }
 
-__global__ void __launch_bounds__(256) k_hist_pack(JobTab t, const uint32_t *chunk_off, uint64_t *dst) {
+// The pairs go to dst (device memory), and the first hn of them also to hdst
+// (the caller's pinned staging, read after the synchronisation).
+__global__ void __launch_bounds__(256) k_hist_pack(JobTab t, const uint32_t *chunk_off, uint64_t *dst, uint64_t *hdst,
+                                                   uint64_t hn) {
   const JobWg jw = job_of(t);
   const uint32_t s0 = jw.b * kHistChunk;
   const uint32_t *hist = jw.J->cw.hist;
@@ -103,7 +111,12 @@ __global__ void __launch_bounds__(256) k_hist_pack(JobTab t, const uint32_t *chu
   for (uint32_t q = 0; q < per; q++) {
     const uint32_t s = s0 + threadIdx.x * per + q;
     const uint32_t c = hist[s];
-    if (c) dst[at++] = ((uint64_t)s << 32) | c;
+    if (c) {
+      const uint64_t v = ((uint64_t)s << 32) | c;
+      dst[at] = v;
+      if (at < hn) hdst[at] = v;
+      at++;
+    }
   }
 }
 
