@@ -11,8 +11,12 @@
  *  - The caller owns every buffer.  The library allocates no device memory
  *    and frees nothing: each call takes a caller-provided device workspace of
  *    at least the size the matching *_workspace_size() reports.
- *  - All device work is queued on `stream`.  Calls that return host results
- *    (sizes, reports) synchronise that stream before returning.
+ *  - All device work starts after the work queued on `stream` before the
+ *    call, and `stream` waits for all of it: part of it (fault-plan blocks,
+ *    the compressor's partial blocks) runs on streams the library keeps per
+ *    calling thread, forked from `stream` and joined back into it.  Calls
+ *    that return host results (sizes, reports) synchronise that stream
+ *    before returning.
  *  - Errors are negative return codes (SDCSZ_E*); nothing throws or aborts
  *    across the ABI.  sdcsz_strerror() names them.
  */
