@@ -11,11 +11,11 @@ namespace sdcsz {
 
 namespace {
 
-// Codeword entries of the codes around the zero residual held in LDS: 3072
-// (12 KiB) leaves k_checkenc_fast 28 KiB of LDS per work-group, five
-// work-groups per CU (4096 entries allowed four, 2048 sent more codes to
-// the global table)
-constexpr uint32_t kEncWin = 3072;
+// Codeword entries of the codes around the zero residual held in LDS: 3584
+// (14 KiB) leaves k_checkenc_fast 30 KiB of LDS per work-group, five
+// work-groups per CU (4096 entries allowed four; fewer entries send more
+// codes to the global table at small bounds)
+constexpr uint32_t kEncWin = 3584;
 constexpr uint32_t kEncLo = kRadius - kEncWin / 2;
 
 // Codeword table entry of a code: from the LDS window, or (rarely) from the
